@@ -1,0 +1,143 @@
+/*
+ * Plain FP64 CPU oracle of the implicit unsteady unified gas-kinetic scheme
+ * (UGKS) on moving overset structured meshes.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or
+ * call this code; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code with the HIP library.
+ *
+ * Every routine follows the paper (Zhang, Long, Cao, Xu, "Unified Gas-Kinetic
+ * Scheme for Unsteady Multiscale Flows with Moving Boundaries") step by step:
+ *   Sec. 2.1  kinetic model, reduced distributions h and b, Shakhov equilibrium,
+ *             finite-volume update, UGKS interface solution (Eq. fullSolution),
+ *             ghost-cell and isothermal-wall boundaries (Eq. maxWalldes),
+ *   Sec. 2.2  dual time stepping (Eqs. dualTimeStepping_macro/_micro,
+ *             residual_macro_n, residual_micro_n+1,s), LU-SGS, Steps 1-8,
+ *   Sec. 3    overset assembly and inverse-distance interpolation.
+ * Where the paper is silent the reading taken is written next to the code.
+ */
+#ifndef UGKS_ORACLE_H
+#define UGKS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* block side boundary kinds */
+enum { OR_PERIODIC = 0, OR_FARFIELD = 1, OR_COPY = 2, OR_WALL = 3, OR_NONE = 4 };
+/* cell kinds */
+enum { OR_HOLE = 0, OR_FIELD = 1, OR_RECEPTOR = 2 };
+
+typedef struct or_case or_case;
+
+/*
+ * Create a case.
+ *   dim         1 or 2 (monatomic gas: N_xi = 3 - dim internal components).
+ *   gas[4]      Pr, omega, mu_ref, rt_ref.  tau = mu_ref (RT/rt_ref)^omega / p;
+ *               mu_ref <= 0 means collisionless (1/tau = 0).
+ *   nv[2]       nvx, nvy (nvy = 1 in 1D).
+ *   vrange[4]   vx_min, vx_max, vy_min, vy_max of the uniform velocity grid.
+ *   vx, vy      the velocity points (length nvx, nvy).
+ *   winf[4]     far-field conservative state (rho, rho u, [rho v,] rho E).
+ *   cfl[2]      CFL of the explicit flux time step and of the virtual step.
+ *   nblock      number of structured blocks.
+ *   bint        per block 6 ints: ni, nj, bc[i-min,i-max,j-min,j-max].
+ *   bdbl        per block 14 doubles: rtw[4], vwx[4], vwy[4], xc0, yc0
+ *               (wall RT and wall velocity added to the mesh velocity per
+ *               side; reference rotation centre).
+ *   nodes       per block the reference node coordinates: x then y, each
+ *               (ni+1)*(nj+1) values, index i + (ni+1)*j (1D: x only, ni+1).
+ * Returns NULL on bad input.
+ */
+or_case* or_create(int dim, const double* gas, const int* nv, const double* vrange,
+                   const double* vx, const double* vy, const double* winf,
+                   const double* cfl, int nblock, const int* bint,
+                   const double* bdbl, const double* nodes);
+void or_free(or_case* c);
+
+int or_ncell(const or_case* c);
+int or_nface(const or_case* c);
+int or_nv(const or_case* c);
+
+/* rigid pose of a block: translation (dx,dy), rotation th about the moved
+   centre, and the rigid velocity (ux,uy) and angular velocity om. */
+void or_set_pose(or_case* c, int blk, double dx, double dy, double th,
+                 double ux, double uy, double om);
+/* node positions, cell and face geometry, face grid velocity at the current
+   poses. */
+void or_update_geometry(or_case* c);
+
+/* velocity points and quadrature weights V_k (k = ix + nvx*iy) */
+void or_dvs(const or_case* c, double* vx, double* vy, double* wk);
+/* one-axis composite Newton-Cotes weights (reading of the velocity grid) */
+void or_nc_weights(int n, double a, double b, double* w);
+
+/* geometry export: cell centroid [ncell][2], volume, metric [ncell][4];
+   face L,R (cell or -1-side), normal [2], area, centre [2], grid velocity [2] */
+void or_geometry(const or_case* c, double* cx, double* vol, double* g,
+                 int* fl, int* fr, double* fn, double* fs, double* fx, double* fu);
+
+void or_set_types(or_case* c, const int8_t* type);
+void or_get_types(const or_case* c, int8_t* type);
+void or_set_overset(or_case* c, int nrec, const int* rec, const int* ptr,
+                    const int* don, const double* w);
+
+/* discrete reduced Maxwellian (H,B) of W at every cell (no Shakhov part) */
+void or_maxwellian(const or_case* c, const double* W, double* h, double* b);
+/* W = sum_k V_k Psi_k f and q about the velocity of that W, every cell */
+void or_moments(const or_case* c, const double* h, const double* b, double* W, double* q);
+/* heat flux of f about the velocity of a given W (every cell) */
+void or_heatflux(const or_case* c, const double* h, const double* b, const double* W, double* q);
+
+/* explicit flux time step dt_s (global) and virtual steps dtp[ncell] */
+double or_timesteps(const or_case* c, double* dtp);
+
+/* time-integration coefficients q1..q5 of the interface solution */
+void or_time_coeffs(double dts, double tau, double* q);
+/* equilibrium slope and time coefficients: a[d][nw], A[nw] */
+void or_slope_coeffs(int dim, double rho, const double* u, double lam,
+                     const double* uf, const double* dW, double* a, double* A);
+/* reduced Shakhov equilibrium at one velocity */
+void or_shakhov(int dim, double pr, double rho, const double* u, double lam,
+                const double* q, const double* v, double* hp, double* bp);
+
+/* Step 1 / Step 3 flux: divergence D[ncell][nv] (h,b), face macro flux
+   F[nface][nw] along the face normal, wall output [nface][1+nw]
+   (rho_w, then the macro flux into the wall). */
+void or_flux(const or_case* c, double dts, const double* h, const double* b,
+             const double* W, const double* q, double* Dh, double* Db,
+             double* F, double* wall);
+
+/* overset interpolation of f, W, q into receptors */
+void or_interp(const or_case* c, double* h, double* b, double* W, double* q);
+
+/* Steps 1-2: source S = f^n/dt + r^n/2 and the level-n face flux Fn */
+void or_begin_step(const or_case* c, double dt, double dts, double* h, double* b,
+                   double* W, double* q, double* Sh, double* Sb, double* Fn);
+/* Steps 3-7, one inner iteration; resid[nw] = L2 norm of R over field cells */
+void or_pseudo_step(const or_case* c, double dt, double dts, const double* dtp,
+                    double* h, double* b, double* W, const double* Wn, double* q,
+                    const double* Sh, const double* Sb, const double* Fn,
+                    double* resid);
+
+/* exposed pieces of one inner iteration, for tests */
+void or_macro_lusgs(const or_case* c, double dt, const double* dtp, const double* W,
+                    const double* Wn, const double* F, const double* Fn, double* Wp,
+                    double* resid);
+void or_micro_lusgs(const or_case* c, double dt, const double* dtp, const double* Wp,
+                    const double* qp, double* h, double* b, const double* Sh,
+                    const double* Sb, const double* Dh, const double* Db);
+void or_step7(const or_case* c, const double* Wp, const double* h, const double* b, double* W);
+
+/* overset assembly (hole cutting, buffer layer, donors and weights) at the
+   current geometry.  wrule 0 = inverse distance squared, 1 = bilinear.
+   overlap = fringe depth (cell layers) kept beside an overset boundary.
+   Returns 0, or -5 if a receptor has no donor. */
+int or_assemble(or_case* c, int wrule, int overlap, int* nrec_out);
+int or_get_overset(const or_case* c, int* rec, int* ptr, int* don, double* w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
