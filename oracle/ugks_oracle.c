@@ -669,6 +669,19 @@ void or_geometry(const or_case* c, double* cx, double* vol, double* g, int* fl, 
   }
 }
 
+void or_face_ids(const or_case* c, int* blk, int* dir, int* fi, int* fj) {
+  for (int f = 0; f < c->nface; f++) {
+    const face_t* F = &c->face[f];
+    blk[f] = F->blk;
+    dir[f] = F->dir;
+    if (F->R >= 0) { fi[f] = c->ci[F->R]; fj[f] = c->cj[F->R]; }
+    else {
+      fi[f] = c->ci[F->L] + (F->dir == 0 ? 1 : 0);
+      fj[f] = c->cj[F->L] + (F->dir == 1 ? 1 : 0);
+    }
+  }
+}
+
 void or_set_types(or_case* c, const int8_t* type) { memcpy(c->type, type, c->ncell); }
 void or_get_types(const or_case* c, int8_t* type) { memcpy(type, c->type, c->ncell); }
 
@@ -728,7 +741,11 @@ void or_moments(const or_case* c, const double* h, const double* b, double* W, d
     cell_moments(c, hn, bn, W + (size_t)n * c->nw);
     double rho, u[2], lam;
     prim(c, W + (size_t)n * c->nw, &rho, u, &lam);
-    if (q) cell_heatflux(c, hn, bn, u, q + (size_t)n * c->dim);
+    if (q) {
+      double qq[2];
+      cell_heatflux(c, hn, bn, u, qq);
+      for (int i = 0; i < c->dim; i++) q[(size_t)n * c->dim + i] = qq[i];
+    }
   }
 }
 
