@@ -1,0 +1,215 @@
+/*
+ * libugks -- MI355X (gfx950) implementation of one dual-time pseudo-iteration
+ * of the implicit unsteady unified gas-kinetic scheme (UGKS) on moving
+ * overset structured meshes, after Zhang, Long, Cao, Xu, "Unified Gas-Kinetic
+ * Scheme for Unsteady Multiscale Flows with Moving Boundaries".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: UGKS_OK (0) or a negative UGKS_E_* code; ugks_last_error()
+ *    returns a thread-local message for the last failure.  Arguments are
+ *    validated before anything is launched, so on error nothing is written.
+ *    No C++ exception crosses this interface.
+ *  - Device arrays are caller-owned HIP device pointers; the library never
+ *    frees them.  Host arrays are marked "host".  The context owns its own
+ *    device copies of the geometry and its scratch buffers.
+ *  - Every compute call is asynchronous on `stream` (a hipStream_t passed as
+ *    void*, NULL = the null stream).  Calls on one context must not overlap.
+ *  - Layouts.  nv = nvx*nvy discrete velocities, k = ix + nvx*iy.  The reduced
+ *    distributions h, b (Sec. 2.1: h = int f dxi, b = int xi^2 f dxi) and the
+ *    arrays of the same shape (sources, divergences) are [ncell][nv],
+ *    velocity innermost, in the storage type chosen at creation (double for
+ *    UGKS_F64, float for UGKS_F32).  W is [ncell][dim+2] (rho, rho U, rho E)
+ *    and q [ncell][dim], always double.  Face arrays are [nface][...].
+ *  - Cells are numbered block by block, i fastest (cell0(b) + i + ni*j).
+ *    Faces: per block first the i-faces ((ni+1)*nj, index i + (ni+1)*j, face
+ *    i lies on the low-i side of cell i), then the j-faces (ni*(nj+1)).  A
+ *    face's normal points from its low-index side to its high-index side.
+ *  - Monatomic gas (no internal degrees of freedom): b carries the 3-dim
+ *    velocity components that the dim-dimensional grid does not resolve.
+ */
+#ifndef UGKS_H
+#define UGKS_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define UGKS_OK 0
+#define UGKS_E_ARG (-1)         /* null pointer or value out of range */
+#define UGKS_E_SHAPE (-2)       /* inconsistent sizes */
+#define UGKS_E_DEVICE (-3)      /* a HIP call failed */
+#define UGKS_E_NONPHYS (-4)     /* non-positive density or temperature */
+#define UGKS_E_ORPHAN (-5)      /* a receptor cell found no donor */
+#define UGKS_E_UNSUPPORTED (-6) /* feature not available for this input */
+
+/* storage precision of h, b and the arrays of their shape */
+#define UGKS_F64 0 /* double storage, double arithmetic */
+#define UGKS_F32 1 /* float storage and float flux arithmetic; moments,
+                      the equilibrium solve and residual assembly in double */
+
+/* block side kinds (sides: 0 i-min, 1 i-max, 2 j-min, 3 j-max) */
+#define UGKS_BC_PERIODIC 0 /* both sides of a direction */
+#define UGKS_BC_FARFIELD 1 /* ghost = Maxwellian of the far-field state */
+#define UGKS_BC_COPY 2     /* ghost = adjacent cell (zero gradient) */
+#define UGKS_BC_WALL 3     /* diffuse isothermal wall (Eq. maxWalldes) */
+#define UGKS_BC_NONE 4     /* overset fringe: no face */
+
+/* cell kinds */
+#define UGKS_HOLE 0
+#define UGKS_FIELD 1
+#define UGKS_RECEPTOR 2
+
+/*
+ * Problem statement (Sec. 2.1 kinetic model and discretisation; Sec. 3 mesh).
+ * All pointers are host pointers, read during ugks_create only.
+ *   dim            1 or 2.
+ *   pr, omega      Prandtl number of the Shakhov model; viscosity exponent.
+ *   mu_ref, rt_ref collision time tau = mu_ref (RT/rt_ref)^omega / p;
+ *                  mu_ref <= 0 means collisionless (1/tau = 0).
+ *   nvx, nvy, vx, vy, vrange
+ *                  uniform velocity points per axis on [vrange[0], vrange[1]]
+ *                  x [vrange[2], vrange[3]] (nvy = 1, vy = {0} in 1D);
+ *                  weights are composite closed Newton-Cotes per axis.
+ *   winf           far-field conservative state (dim+2 values).
+ *   cfl_s, cfl_p   CFL of the explicit flux step dt_s and of the virtual
+ *                  step dt' (the paper uses 0.5 and 100).
+ *   nblock, bint   per block 6 ints: ni, nj (1 in 1D), bc[4].
+ *   bdbl           per block 14 doubles: wall RT per side (4), wall velocity
+ *                  added to the mesh velocity per side (x: 4, y: 4), and the
+ *                  rotation centre at the reference pose (2).
+ *   nodes          per block the reference node coordinates, x then y, each
+ *                  (ni+1)*(nj+1) values with index i + (ni+1)*j (1D: x only).
+ *   prec           UGKS_F64 or UGKS_F32.
+ */
+typedef struct {
+  int32_t dim;
+  double pr, omega, mu_ref, rt_ref;
+  int32_t nvx, nvy;
+  const double* vx;
+  const double* vy;
+  double vrange[4];
+  double winf[4];
+  double cfl_s, cfl_p;
+  int32_t nblock;
+  const int32_t* bint;
+  const double* bdbl;
+  const double* nodes;
+  int32_t prec;
+} ugks_problem;
+
+typedef struct ugks_ctx ugks_ctx;
+
+/* Create a context on HIP device `device`: copies the problem, builds the
+   geometry at the reference pose, uploads it and allocates scratch.
+   *out receives the context. */
+int ugks_create(const ugks_problem* p, int device, ugks_ctx** out);
+/* Release the context and its device memory.  NULL is accepted. */
+int ugks_destroy(ugks_ctx* ctx);
+/* Sizes: cells, faces, velocities, storage precision (any pointer may be NULL). */
+int ugks_sizes(const ugks_ctx* ctx, int32_t* ncell, int32_t* nface, int32_t* nv, int32_t* prec);
+
+/*
+ * Rigid motion of every block to the poses of the next physical time
+ * (Sec. 3, Step 1): host array poses[nblock][6] = translation (dx, dy),
+ * rotation th about the moved centre, velocity (ux, uy), angular velocity om.
+ * Recomputes node positions, cell and face geometry, the face grid velocity
+ * U_f = u + om x (x_f - centre), the explicit flux step dt_s (written to
+ * *dts, host) and the per-cell virtual steps dt', and uploads them.  The
+ * geometry is frozen until the next call (both flux levels of a physical
+ * step use it).  Synchronous.
+ */
+int ugks_set_poses(ugks_ctx* ctx, const double* poses, double* dts);
+
+/* Host cell kinds [ncell] (UGKS_HOLE / FIELD / RECEPTOR); default all field. */
+int ugks_set_types(ugks_ctx* ctx, const int8_t* types);
+int ugks_get_types(const ugks_ctx* ctx, int8_t* types);
+
+/*
+ * Overset donor table (Sec. 3.2), host CSR: receptor cells rec[nrec], donors
+ * of receptor r are don[ptr[r] .. ptr[r+1]-1] with weights w (sum to 1).
+ * Donors must be field cells.  Copied to the device.
+ */
+int ugks_set_overset(ugks_ctx* ctx, int32_t nrec, const int32_t* rec, const int32_t* ptr,
+                     const int32_t* don, const double* w);
+
+/*
+ * Overset assembly at the current geometry (Sec. 3.1, host): node
+ * classification, cell classification with one buffer layer, fringe layers
+ * beside overset boundaries, donor search and weights (wrule 0: inverse
+ * distance squared over the donor and its field neighbours; 1: bilinear in
+ * the donor grid).  Installs the cell kinds and the donor table.
+ * *nrec receives the receptor count.  UGKS_E_ORPHAN if a receptor has no
+ * donor (nothing is installed then).
+ */
+int overset_assemble(ugks_ctx* ctx, int32_t wrule, int32_t overlap, int32_t* nrec);
+
+/* Discrete reduced Maxwellian h = H(W), b = B(W) at every cell
+   (initialisation). */
+int ugks_maxwellian(ugks_ctx* ctx, const double* W, void* h, void* b, void* stream);
+
+/*
+ * Velocity moments (Sec. 2.1): W = sum_k V_k Psi_k (h, b) and the heat flux
+ * q = 1/2 sum_k V_k c (|c|^2 h + b), c = v_k - U of that W, for every cell.
+ */
+int ugks_moments(ugks_ctx* ctx, const void* h, const void* b, double* W, double* q, void* stream);
+
+/*
+ * Heat flux q = 1/2 sum_k V_k c (|c|^2 h + b) with c = v_k - U, U the
+ * velocity of the given W (Sec. 2.1 moments), for every non-hole cell.
+ * This is the q that the Shakhov equilibrium of (W, q) uses.
+ */
+int ugks_heatflux(ugks_ctx* ctx, const void* h, const void* b, const double* W, double* q, void* stream);
+
+/*
+ * UGKS flux (Sec. 2.1, Eqs. microscopicFlux, macroscopicFlux, fullSolution,
+ * maxWalldes; time-averaged over dt_s as in Sec. 2.2) of the state (h, b, W,
+ * q): divergence Dh, Db [ncell][nv] = -(1/|Omega_i|) sum_f sigma S_f F_f,k
+ * (zero on non-field cells), face macro flux F [nface][dim+2] along the face
+ * normal, and wall output wall [nface][dim+3] = (rho_w, macro flux into the
+ * wall) on wall faces (zero elsewhere).  F and wall may be NULL.
+ */
+int ugks_flux(ugks_ctx* ctx, double dts, const void* h, const void* b, const double* W,
+              const double* q, void* Dh, void* Db, double* F, double* wall, void* stream);
+
+/* Overset interpolation (Sec. 3.2) of h, b, W and q into the receptor rows,
+   in place. */
+int overset_interp(ugks_ctx* ctx, void* h, void* b, double* W, double* q, void* stream);
+
+/*
+ * Steps 1-2 of the dual time stepping (Sec. 2.2): interpolate receptors,
+ * evaluate the level-n flux and store the source S = f^n/dt + r^n/2 with
+ * r^n of Eq. residual_macro_n (Sh, Sb [ncell][nv]) and the level-n face
+ * flux Fn [nface][dim+2].  q [ncell][dim] is the heat flux of f^n about
+ * the velocity of W^n (as ugks_heatflux returns); receptor rows of h, b, W, q
+ * are refreshed by interpolation.
+ */
+int ugks_begin_step(ugks_ctx* ctx, double dt, void* h, void* b, double* W, double* q,
+                    void* Sh, void* Sb, double* Fn, void* stream);
+
+/*
+ * Steps 3-7 of the dual time stepping, n_inner times (Sec. 2.2): per inner
+ * iteration interpolate receptors, evaluate the flux, solve the macro delta
+ * form (Eq. dualTimeStepping_macro) by LU-SGS, solve the micro delta form
+ * (Eq. dualTimeStepping_micro) by LU-SGS per velocity and correct W
+ * (Step 7).  Wn is W at level n.  resid (device, may be NULL) receives
+ * [n_inner][dim+2] L2 norms of the macro residual over field cells.
+ */
+int ugks_step(ugks_ctx* ctx, double dt, int32_t n_inner, void* h, void* b, double* W,
+              const double* Wn, double* q, const void* Sh, const void* Sb, const double* Fn,
+              double* resid, void* stream);
+
+/* Current explicit flux step dt_s and a copy of the virtual steps dt' (host
+   array [ncell], may be NULL). */
+int ugks_timesteps(const ugks_ctx* ctx, double* dts, double* dtp);
+
+/* Thread-local message of the last failure ("" if none). */
+const char* ugks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -37,6 +37,7 @@ def lib():
         L.or_dvs.argtypes = [C.c_void_p, D, D, D]
         L.or_nc_weights.argtypes = [C.c_int, C.c_double, C.c_double, D]
         L.or_geometry.argtypes = [C.c_void_p, D, D, D, I, I, D, D, D, D]
+        L.or_face_ids.argtypes = [C.c_void_p, I, I, I, I]
         L.or_set_types.argtypes = [C.c_void_p, I8]
         L.or_get_types.argtypes = [C.c_void_p, I8]
         L.or_set_overset.argtypes = [C.c_void_p, C.c_int, I, I, I, D]
@@ -159,6 +160,28 @@ class Oracle:
         lib().or_geometry(self.ptr, _d(cx), _d(vol), _d(g), _i(fl), _i(fr), _d(fn), _d(fs),
                           _d(fx), _d(fu))
         return dict(cx=cx, vol=vol, g=g, fl=fl, fr=fr, fn=fn, fs=fs, fx=fx, fu=fu)
+
+    def face_ids(self):
+        a = [np.zeros(self.nface, np.int32) for _ in range(4)]
+        lib().or_face_ids(self.ptr, *[_i(x) for x in a])
+        return a
+
+    def product_face_index(self):
+        """Index of each oracle face in the face numbering of include/ugks.h
+        (per block the (ni+1)*nj i-faces, then the ni*(nj+1) j-faces)."""
+        blk, dr, fi, fj = self.face_ids()
+        offs_i, offs_j, nf = [], [], 0
+        for b in self.case.blocks:
+            offs_i.append(nf); nf += (b.ni + 1) * b.nj
+            offs_j.append(nf)
+            if self.case.dim == 2:
+                nf += b.ni * (b.nj + 1)
+        out = np.zeros(self.nface, np.int64)
+        for f in range(self.nface):
+            B = self.case.blocks[blk[f]]
+            out[f] = (offs_i[blk[f]] + fi[f] + (B.ni + 1) * fj[f]) if dr[f] == 0 else \
+                     (offs_j[blk[f]] + fi[f] + B.ni * fj[f])
+        return out
 
     def set_types(self, t):
         t = np.ascontiguousarray(t, dtype=np.int8)

@@ -78,6 +78,10 @@ void or_nc_weights(int n, double a, double b, double* w);
 void or_geometry(const or_case* c, double* cx, double* vol, double* g,
                  int* fl, int* fr, double* fn, double* fs, double* fx, double* fu);
 
+/* structured position of every face: block, direction (0 i, 1 j) and the
+   (i, j) of the face in its block's face grid */
+void or_face_ids(const or_case* c, int* blk, int* dir, int* fi, int* fj);
+
 void or_set_types(or_case* c, const int8_t* type);
 void or_get_types(const or_case* c, int8_t* type);
 void or_set_overset(or_case* c, int nrec, const int* rec, const int* ptr,

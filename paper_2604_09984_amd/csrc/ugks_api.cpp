@@ -1,0 +1,761 @@
+// libugks host side: the C ABI of include/ugks.h, problem setup, host
+// geometry of the moving structured blocks and the pseudo-iteration driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ugks.h"
+#include "ugks_kernels.h"
+#include "ugks_overset.h"
+
+using namespace ugks;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return fail(UGKS_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Block {
+  int ni, nj, bc[4];
+  double rtw[4], vwx[4], vwy[4], xc0, yc0;
+  std::vector<double> x0, y0;  // reference nodes
+  double pose[6] = {0, 0, 0, 0, 0, 0};
+  int cell0, face_i0, face_j0;
+};
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct ugks_ctx {
+  int device = 0;
+  int dim = 2, nxi = 1, nw = 4, prec = 0;
+  double pr, omega, mu_ref, rt_ref, cfl_s, cfl_p;
+  int nvx, nvy, nv;
+  double vrange[4];
+  double winf[4] = {0, 0, 0, 0};
+  std::vector<double> vx, vy, wk;  // per k
+  std::vector<Block> blk;
+  int ncell = 0, nface = 0;
+  int max_ni = 0, max_nj = 0, any_pj = 0;
+  // host geometry
+  std::vector<double> xn, yn;  // current nodes, per block
+  std::vector<size_t> node0;
+  std::vector<double> vol, G, cdx, dtp, fgeo;
+  std::vector<int> nb, cf, fcell;
+  std::vector<int8_t> type, fact;
+  std::vector<int> cblk, ci, cj;
+  double dts = 0.0;
+  // device copies
+  Dev dev{};
+  void *d_vx = nullptr, *d_vy = nullptr, *d_wk = nullptr, *d_vol = nullptr, *d_G = nullptr, *d_cdx = nullptr,
+       *d_dtp = nullptr, *d_type = nullptr, *d_nb = nullptr, *d_cf = nullptr, *d_fcell = nullptr,
+       *d_fgeo = nullptr, *d_fact = nullptr, *d_finf_h = nullptr, *d_finf_b = nullptr, *d_binfo = nullptr;
+  // scratch
+  void *s_gW = nullptr, *s_rec = nullptr, *s_gam = nullptr, *s_R = nullptr, *s_Dg = nullptr, *s_dWs = nullptr,
+       *s_dW = nullptr, *s_Wp = nullptr, *s_rpart = nullptr, *s_crec = nullptr, *s_mrec = nullptr,
+       *s_Dh = nullptr, *s_Db = nullptr, *s_F = nullptr;
+  // overset
+  int nrec = 0;
+  void *d_rec = nullptr, *d_ptr = nullptr, *d_don = nullptr, *d_w = nullptr;
+  std::vector<int> h_rec, h_ptr, h_don;
+  std::vector<double> h_w;
+};
+
+namespace {
+
+size_t tsize(const ugks_ctx* c) { return c->prec == UGKS_F64 ? sizeof(double) : sizeof(float); }
+
+// composite closed Newton-Cotes weights on n uniform points of [a, b]
+// (Boole if (n-1) % 4 == 0; Simpson for odd n; Simpson | 3/8 | Simpson for
+// n % 4 == 0; Simpson | 3/8 | 3/8 | 3/8 | Simpson for n % 4 == 2, n >= 10)
+std::vector<double> nc_weights(int n, double a, double b) {
+  std::vector<double> w(n, 0.0);
+  if (n == 1) { w[0] = 1.0; return w; }
+  double h = (b - a) / (n - 1);
+  if (n == 2) { w[0] = w[1] = 0.5 * h; return w; }
+  auto simpson = [&](int i0, int m) {
+    for (int p = i0; p < i0 + m; p += 2) { w[p] += h / 3.0; w[p + 1] += 4.0 * h / 3.0; w[p + 2] += h / 3.0; }
+  };
+  auto three8 = [&](int i0) {
+    w[i0] += 3.0 * h / 8.0; w[i0 + 1] += 9.0 * h / 8.0; w[i0 + 2] += 9.0 * h / 8.0; w[i0 + 3] += 3.0 * h / 8.0;
+  };
+  int m = n - 1;
+  if (m % 4 == 0) {
+    for (int p = 0; p < m; p += 4) {
+      w[p] += 14.0 * h / 45.0; w[p + 1] += 64.0 * h / 45.0; w[p + 2] += 24.0 * h / 45.0;
+      w[p + 3] += 64.0 * h / 45.0; w[p + 4] += 14.0 * h / 45.0;
+    }
+  } else if (n % 2 == 1) {
+    simpson(0, m);
+  } else if (n % 4 == 0) {
+    int s = (n - 4) / 2;
+    simpson(0, s); three8(s); simpson(s + 3, s);
+  } else if (n >= 10) {
+    int s = (n - 4) / 2 - 3;
+    simpson(0, s); three8(s); three8(s + 3); three8(s + 6); simpson(s + 9, s);
+  } else {
+    simpson(0, n - 4); three8(n - 4);
+  }
+  return w;
+}
+
+template <class T>
+int upload(void*& d, const std::vector<T>& h) {
+  size_t bytes = std::max<size_t>(1, h.size()) * sizeof(T);
+  if (!d) HIPCHK(hipMalloc(&d, bytes));
+  if (!h.empty()) HIPCHK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return UGKS_OK;
+}
+
+int alloc(void*& d, size_t bytes) {
+  if (d) return UGKS_OK;
+  HIPCHK(hipMalloc(&d, std::max<size_t>(bytes, 256)));
+  return UGKS_OK;
+}
+
+void prim(const ugks_ctx* c, const double* W, double& rho, double& ux, double& uy, double& lam) {
+  rho = W[0];
+  ux = W[1] / rho;
+  uy = (c->dim == 2) ? W[2] / rho : 0.0;
+  double e = W[c->dim + 1] - 0.5 * rho * (ux * ux + uy * uy);
+  lam = 0.25 * (double)(c->dim + c->nxi) * rho / e;
+}
+
+int cell_of(const ugks_ctx* c, int b, int i, int j) { return c->blk[b].cell0 + i + c->blk[b].ni * j; }
+
+// neighbour code of cell (b, i, j) in slot s
+int neighbour(const ugks_ctx* c, int cell, int s) {
+  int b = c->cblk[cell], i = c->ci[cell], j = c->cj[cell];
+  const Block& B = c->blk[b];
+  int dir = s / 2, side = (s & 1) ? 1 : -1;
+  if (c->dim == 1 && dir == 1) return kNbMiss;
+  int ii = i + (dir == 0 ? side : 0), jj = j + (dir == 1 ? side : 0);
+  int n = (dir == 0) ? B.ni : B.nj;
+  int idx = (dir == 0) ? ii : jj;
+  if (idx < 0 || idx >= n) {
+    if (B.bc[2 * dir] == UGKS_BC_PERIODIC) {
+      idx = (idx + n) % n;
+      if (dir == 0) ii = idx; else jj = idx;
+    } else {
+      switch (B.bc[s]) {
+        case UGKS_BC_FARFIELD: return kNbFar;
+        case UGKS_BC_COPY: return kNbCopy;
+        case UGKS_BC_WALL: return kNbWall;
+        default: return kNbMiss;
+      }
+    }
+  }
+  int o = cell_of(c, b, ii, jj);
+  return c->type[o] == UGKS_HOLE ? kNbMiss : o;
+}
+
+// topology tables that depend on the cell kinds
+void build_tables(ugks_ctx* c) {
+  c->nb.assign(4 * (size_t)c->ncell, kNbMiss);
+  for (int n = 0; n < c->ncell; ++n)
+    for (int s = 0; s < 4; ++s) c->nb[4 * n + s] = neighbour(c, n, s);
+  c->fact.assign(c->nface, 0);
+  for (int f = 0; f < c->nface; ++f) {
+    int L = c->fcell[2 * f], R = c->fcell[2 * f + 1];
+    bool a = (L >= 0 && c->type[L] == UGKS_FIELD) || (R >= 0 && c->type[R] == UGKS_FIELD);
+    bool valid = !(L == kNbMiss || R == kNbMiss);
+    c->fact[f] = (a && valid) ? 1 : 0;
+  }
+}
+
+// face numbering and the static face-cell table
+void build_faces(ugks_ctx* c) {
+  int nf = 0;
+  for (auto& B : c->blk) {
+    B.face_i0 = nf;
+    nf += (B.ni + 1) * B.nj;
+    B.face_j0 = nf;
+    if (c->dim == 2) nf += B.ni * (B.nj + 1);
+  }
+  c->nface = nf;
+  c->fcell.assign(2 * (size_t)nf, kNbMiss);
+  c->cf.assign(4 * (size_t)c->ncell, -1);
+  for (int b = 0; b < (int)c->blk.size(); ++b) {
+    const Block& B = c->blk[b];
+    for (int dir = 0; dir < c->dim; ++dir) {
+      bool per = B.bc[2 * dir] == UGKS_BC_PERIODIC;
+      int nI = (dir == 0) ? B.ni + 1 : B.ni, nJ = (dir == 0) ? B.nj : B.nj + 1;
+      for (int j = 0; j < nJ; ++j)
+        for (int i = 0; i < nI; ++i) {
+          int f = (dir == 0) ? B.face_i0 + i + (B.ni + 1) * j : B.face_j0 + i + B.ni * j;
+          int idx = (dir == 0) ? i : j, n = (dir == 0) ? B.ni : B.nj;
+          if (per && idx == n) continue;  // duplicate of face 0 of the row
+          int L, R;
+          int lo_cell = (idx > 0) ? cell_of(c, b, dir == 0 ? i - 1 : i, dir == 0 ? j : j - 1)
+                                  : (per ? cell_of(c, b, dir == 0 ? n - 1 : i, dir == 0 ? j : n - 1) : -1);
+          int hi_cell = (idx < n) ? cell_of(c, b, i, j) : -1;
+          auto code = [&](int side) -> int {
+            switch (B.bc[side]) {
+              case UGKS_BC_FARFIELD: return kNbFar;
+              case UGKS_BC_COPY: return kNbCopy;
+              case UGKS_BC_WALL: return kNbWall;
+              default: return kNbMiss;
+            }
+          };
+          L = (lo_cell >= 0) ? lo_cell : code(2 * dir);
+          R = (hi_cell >= 0) ? hi_cell : code(2 * dir + 1);
+          if (L == kNbMiss || R == kNbMiss) continue;  // fringe side: no face
+          c->fcell[2 * f] = L;
+          c->fcell[2 * f + 1] = R;
+          if (L >= 0) c->cf[4 * L + 2 * dir + 1] = f;
+          if (R >= 0) c->cf[4 * R + 2 * dir] = f;
+        }
+    }
+  }
+}
+
+// node positions, cell and face geometry, time steps at the current poses
+void compute_geometry(ugks_ctx* c) {
+  int d = c->dim;
+  for (int b = 0; b < (int)c->blk.size(); ++b) {
+    Block& B = c->blk[b];
+    double cs = std::cos(B.pose[2]), sn = std::sin(B.pose[2]);
+    size_t nn = B.x0.size();
+    for (size_t n = 0; n < nn; ++n) {
+      double rx = B.x0[n] - B.xc0, ry = (d == 2) ? B.y0[n] - B.yc0 : 0.0;
+      c->xn[c->node0[b] + n] = B.xc0 + B.pose[0] + (cs * rx - sn * ry);
+      c->yn[c->node0[b] + n] = (d == 2) ? B.yc0 + B.pose[1] + (sn * rx + cs * ry) : 0.0;
+    }
+  }
+  auto X = [&](int b, int i, int j) { return c->xn[c->node0[b] + i + (size_t)(c->blk[b].ni + 1) * j]; };
+  auto Y = [&](int b, int i, int j) { return c->yn[c->node0[b] + i + (size_t)(c->blk[b].ni + 1) * j]; };
+  for (int n = 0; n < c->ncell; ++n) {
+    int b = c->cblk[n], i = c->ci[n], j = c->cj[n];
+    double* G = &c->G[4 * (size_t)n];
+    double* D = &c->cdx[8 * (size_t)n];
+    if (d == 1) {
+      double xa = X(b, i, 0), xb = X(b, i + 1, 0);
+      c->vol[n] = xb - xa;
+      double xc = 0.5 * (xa + xb);
+      G[0] = 1.0 / (xb - xa); G[1] = G[2] = G[3] = 0.0;
+      for (int q = 0; q < 8; ++q) D[q] = 0.0;
+      D[0] = xa - xc;
+      D[2] = xb - xc;
+      continue;
+    }
+    double px[4] = {X(b, i, j), X(b, i + 1, j), X(b, i + 1, j + 1), X(b, i, j + 1)};
+    double py[4] = {Y(b, i, j), Y(b, i + 1, j), Y(b, i + 1, j + 1), Y(b, i, j + 1)};
+    double A = 0.0, sx = 0.0, sy = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      int k1 = (k + 1) % 4;
+      double cr = px[k] * py[k1] - px[k1] * py[k];
+      A += cr; sx += (px[k] + px[k1]) * cr; sy += (py[k] + py[k1]) * cr;
+    }
+    A *= 0.5;
+    double xc = sx / (6.0 * A), yc = sy / (6.0 * A);
+    c->vol[n] = A;
+    double xxi = 0.5 * (px[1] + px[2]) - 0.5 * (px[0] + px[3]);
+    double yxi = 0.5 * (py[1] + py[2]) - 0.5 * (py[0] + py[3]);
+    double xet = 0.5 * (px[3] + px[2]) - 0.5 * (px[0] + px[1]);
+    double yet = 0.5 * (py[3] + py[2]) - 0.5 * (py[0] + py[1]);
+    double det = xxi * yet - xet * yxi;
+    G[0] = yet / det; G[1] = -yxi / det; G[2] = -xet / det; G[3] = xxi / det;
+    double fx[4] = {0.5 * (px[0] + px[3]), 0.5 * (px[1] + px[2]), 0.5 * (px[0] + px[1]), 0.5 * (px[3] + px[2])};
+    double fy[4] = {0.5 * (py[0] + py[3]), 0.5 * (py[1] + py[2]), 0.5 * (py[0] + py[1]), 0.5 * (py[3] + py[2])};
+    for (int q = 0; q < 4; ++q) { D[2 * q] = fx[q] - xc; D[2 * q + 1] = fy[q] - yc; }
+  }
+  // faces
+  c->fgeo.assign(8 * (size_t)c->nface, 0.0);
+  for (int b = 0; b < (int)c->blk.size(); ++b) {
+    const Block& B = c->blk[b];
+    double cxm = B.xc0 + B.pose[0], cym = B.yc0 + B.pose[1];
+    for (int dir = 0; dir < d; ++dir) {
+      int nI = (dir == 0) ? B.ni + 1 : B.ni, nJ = (dir == 0) ? B.nj : B.nj + 1;
+      for (int j = 0; j < nJ; ++j)
+        for (int i = 0; i < nI; ++i) {
+          int f = (dir == 0) ? B.face_i0 + i + (B.ni + 1) * j : B.face_j0 + i + B.ni * j;
+          double* g = &c->fgeo[8 * (size_t)f];
+          double xf, yf;
+          if (d == 1) {
+            g[0] = 1.0; g[1] = 0.0; g[2] = 1.0;
+            xf = X(b, i, 0); yf = 0.0;
+          } else {
+            double x0 = X(b, i, j), y0 = Y(b, i, j);
+            double x1 = (dir == 0) ? X(b, i, j + 1) : X(b, i + 1, j);
+            double y1 = (dir == 0) ? Y(b, i, j + 1) : Y(b, i + 1, j);
+            double ex = x1 - x0, ey = y1 - y0;
+            double S = std::sqrt(ex * ex + ey * ey);
+            g[2] = S;
+            if (dir == 0) { g[0] = ey / S; g[1] = -ex / S; }
+            else { g[0] = -ey / S; g[1] = ex / S; }
+            xf = 0.5 * (x0 + x1); yf = 0.5 * (y0 + y1);
+          }
+          double rx = xf - cxm, ry = yf - cym;
+          g[3] = B.pose[3] - B.pose[5] * ry;
+          g[4] = (d == 2) ? B.pose[4] + B.pose[5] * rx : 0.0;
+          int L = c->fcell[2 * f], R = c->fcell[2 * f + 1];
+          int side = -1;
+          if (L == kNbWall) side = 2 * dir;
+          if (R == kNbWall) side = 2 * dir + 1;
+          if (side >= 0) {
+            g[5] = g[3] + B.vwx[side];
+            g[6] = (d == 2) ? g[4] + B.vwy[side] : 0.0;
+            g[7] = B.rtw[side];
+          }
+        }
+    }
+  }
+  // time steps: max_k |(v_k - U_f).n| is reached at a corner of the velocity box
+  std::vector<double> smax(c->nface, 0.0);
+  double vxs[2] = {c->vx[0], c->vx[c->nv - 1]};
+  double vys[2] = {c->vy[0], c->vy[c->nv - 1]};
+  for (int f = 0; f < c->nface; ++f) {
+    const double* g = &c->fgeo[8 * (size_t)f];
+    double m = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int e = 0; e < 2; ++e) {
+        double w = std::fabs((vxs[a] - g[3]) * g[0] + (vys[e] - g[4]) * g[1]);
+        m = std::max(m, w);
+      }
+    smax[f] = m;
+  }
+  double dts = INFINITY;
+  for (int n = 0; n < c->ncell; ++n) {
+    double s = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      int f = c->cf[4 * (size_t)n + q];
+      if (f >= 0) s += 0.5 * c->fgeo[8 * (size_t)f + 2] * smax[f];
+    }
+    c->dtp[n] = c->cfl_p * c->vol[n] / s;
+    if (c->type[n] == UGKS_FIELD) dts = std::min(dts, c->cfl_s * c->vol[n] / s);
+  }
+  c->dts = dts;
+}
+
+int upload_geometry(ugks_ctx* c) {
+  int rc;
+  if ((rc = upload(c->d_vol, c->vol))) return rc;
+  if ((rc = upload(c->d_G, c->G))) return rc;
+  if ((rc = upload(c->d_cdx, c->cdx))) return rc;
+  if ((rc = upload(c->d_dtp, c->dtp))) return rc;
+  if ((rc = upload(c->d_fgeo, c->fgeo))) return rc;
+  return UGKS_OK;
+}
+
+int upload_tables(ugks_ctx* c) {
+  int rc;
+  if ((rc = upload(c->d_type, c->type))) return rc;
+  if ((rc = upload(c->d_nb, c->nb))) return rc;
+  if ((rc = upload(c->d_fact, c->fact))) return rc;
+  return UGKS_OK;
+}
+
+void fill_dev(ugks_ctx* c) {
+  Dev& g = c->dev;
+  g.dim = c->dim; g.nxi = c->nxi; g.nw = c->nw; g.nv = c->nv; g.nvx = c->nvx; g.nvy = c->nvy;
+  g.ncell = c->ncell; g.nface = c->nface; g.nblock = (int)c->blk.size();
+  g.pr = c->pr; g.omega = c->omega; g.mu_ref = c->mu_ref; g.rt_ref = c->rt_ref;
+  for (int m = 0; m < 4; ++m) g.winf[m] = c->winf[m];
+  g.vx = (const double*)c->d_vx; g.vy = (const double*)c->d_vy; g.wk = (const double*)c->d_wk;
+  g.vol = (const double*)c->d_vol; g.G = (const double*)c->d_G; g.cdx = (const double*)c->d_cdx;
+  g.dtp = (const double*)c->d_dtp; g.type = (const int8_t*)c->d_type; g.nb = (const int*)c->d_nb;
+  g.cf = (const int*)c->d_cf; g.fcell = (const int*)c->d_fcell; g.fgeo = (const double*)c->d_fgeo;
+  g.fact = (const int8_t*)c->d_fact; g.finf_h = c->d_finf_h; g.finf_b = c->d_finf_b;
+}
+
+void free_all(ugks_ctx* c) {
+  void* ps[] = {c->d_vx, c->d_vy, c->d_wk, c->d_vol, c->d_G, c->d_cdx, c->d_dtp, c->d_type, c->d_nb, c->d_cf,
+                c->d_fcell, c->d_fgeo, c->d_fact, c->d_finf_h, c->d_finf_b, c->d_binfo, c->s_gW, c->s_rec,
+                c->s_gam, c->s_R, c->s_Dg, c->s_dWs, c->s_dW, c->s_Wp, c->s_rpart, c->s_crec, c->s_mrec,
+                c->s_Dh, c->s_Db, c->s_F, c->d_rec, c->d_ptr, c->d_don, c->d_w};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* ugks_last_error(void) { return g_err.c_str(); }
+
+int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
+  g_err.clear();
+  if (!p || !out) return fail(UGKS_E_ARG, "null argument");
+  *out = nullptr;
+  if (p->dim != 1 && p->dim != 2) return fail(UGKS_E_ARG, "dim must be 1 or 2");
+  if (p->prec != UGKS_F64 && p->prec != UGKS_F32) return fail(UGKS_E_ARG, "prec must be UGKS_F64 or UGKS_F32");
+  if (p->nvx < 2 || (p->dim == 2 && p->nvy < 2) || (p->dim == 1 && p->nvy != 1))
+    return fail(UGKS_E_SHAPE, "bad velocity grid size");
+  if (!p->vx || !p->vy || !p->bint || !p->bdbl || !p->nodes || p->nblock < 1)
+    return fail(UGKS_E_ARG, "null array or no block");
+  if (!(p->cfl_s > 0) || !(p->cfl_p > 0) || !(p->pr > 0)) return fail(UGKS_E_ARG, "bad CFL or Prandtl number");
+  auto* c = new ugks_ctx();
+  c->device = device;
+  c->dim = p->dim; c->nxi = 3 - p->dim; c->nw = p->dim + 2; c->prec = p->prec;
+  c->pr = p->pr; c->omega = p->omega; c->mu_ref = p->mu_ref; c->rt_ref = p->rt_ref;
+  c->cfl_s = p->cfl_s; c->cfl_p = p->cfl_p;
+  c->nvx = p->nvx; c->nvy = p->nvy; c->nv = p->nvx * p->nvy;
+  for (int m = 0; m < 4; ++m) c->vrange[m] = p->vrange[m];
+  for (int m = 0; m < c->nw; ++m) c->winf[m] = p->winf[m];
+  std::vector<double> wx = nc_weights(c->nvx, p->vrange[0], p->vrange[1]);
+  std::vector<double> wy = (c->dim == 2) ? nc_weights(c->nvy, p->vrange[2], p->vrange[3]) : std::vector<double>{1.0};
+  c->vx.resize(c->nv); c->vy.resize(c->nv); c->wk.resize(c->nv);
+  for (int iy = 0; iy < c->nvy; ++iy)
+    for (int ix = 0; ix < c->nvx; ++ix) {
+      int k = ix + c->nvx * iy;
+      c->vx[k] = p->vx[ix];
+      c->vy[k] = (c->dim == 2) ? p->vy[iy] : 0.0;
+      c->wk[k] = wx[ix] * wy[iy];
+    }
+  const double* np = p->nodes;
+  int ncell = 0;
+  size_t nnode = 0;
+  for (int b = 0; b < p->nblock; ++b) {
+    Block B;
+    B.ni = p->bint[6 * b];
+    B.nj = (c->dim == 2) ? p->bint[6 * b + 1] : 1;
+    for (int s = 0; s < 4; ++s) B.bc[s] = p->bint[6 * b + 2 + s];
+    for (int s = 0; s < 4; ++s) {
+      B.rtw[s] = p->bdbl[14 * b + s];
+      B.vwx[s] = p->bdbl[14 * b + 4 + s];
+      B.vwy[s] = p->bdbl[14 * b + 8 + s];
+    }
+    B.xc0 = p->bdbl[14 * b + 12];
+    B.yc0 = p->bdbl[14 * b + 13];
+    bool ok = B.ni >= 2 && B.nj >= 1;
+    for (int dir = 0; dir < 2; ++dir) {
+      bool a = B.bc[2 * dir] == UGKS_BC_PERIODIC, e = B.bc[2 * dir + 1] == UGKS_BC_PERIODIC;
+      if (a != e) ok = false;
+      if (a && ((dir == 0 && B.ni < 3) || (dir == 1 && B.nj < 3))) ok = false;
+    }
+    for (int s = 0; s < 4; ++s) {
+      if (B.bc[s] < 0 || B.bc[s] > 4) ok = false;
+      if (B.bc[s] == UGKS_BC_WALL && !(B.rtw[s] > 0)) ok = false;
+    }
+    if (c->dim == 2 && B.nj < 2) ok = false;
+    if (!ok) { delete c; return fail(UGKS_E_ARG, "bad block " + std::to_string(b)); }
+    size_t nn = (size_t)(B.ni + 1) * ((c->dim == 2) ? (B.nj + 1) : 1);
+    B.x0.assign(np, np + nn); np += nn;
+    if (c->dim == 2) { B.y0.assign(np, np + nn); np += nn; }
+    else B.y0.assign(nn, 0.0);
+    B.cell0 = ncell;
+    c->node0.push_back(nnode);
+    ncell += B.ni * B.nj;
+    nnode += nn;
+    c->max_ni = std::max(c->max_ni, B.ni);
+    c->max_nj = std::max(c->max_nj, B.nj);
+    if (B.bc[2] == UGKS_BC_PERIODIC) c->any_pj = 1;
+    c->blk.push_back(std::move(B));
+  }
+  if (c->dim == 2 && c->max_nj > 64 * kMaxRowsMicroHost) { delete c; return fail(UGKS_E_UNSUPPORTED, "nj above 256"); }
+  if (c->any_pj && c->max_ni > 64) { delete c; return fail(UGKS_E_UNSUPPORTED, "periodic j needs ni <= 64"); }
+  if (c->max_nj > 64 * 8) { delete c; return fail(UGKS_E_UNSUPPORTED, "nj above 512"); }
+  c->ncell = ncell;
+  c->xn.assign(nnode, 0.0);
+  c->yn.assign(nnode, 0.0);
+  c->cblk.resize(ncell); c->ci.resize(ncell); c->cj.resize(ncell);
+  for (int b = 0; b < (int)c->blk.size(); ++b)
+    for (int j = 0; j < c->blk[b].nj; ++j)
+      for (int i = 0; i < c->blk[b].ni; ++i) {
+        int n = cell_of(c, b, i, j);
+        c->cblk[n] = b; c->ci[n] = i; c->cj[n] = j;
+      }
+  c->type.assign(ncell, UGKS_FIELD);
+  c->vol.resize(ncell); c->G.resize(4 * (size_t)ncell); c->cdx.resize(8 * (size_t)ncell); c->dtp.resize(ncell);
+  build_faces(c);
+  build_tables(c);
+  compute_geometry(c);
+  // device
+  if (hipSetDevice(device) != hipSuccess) { delete c; return fail(UGKS_E_DEVICE, "hipSetDevice failed"); }
+  int rc = UGKS_OK;
+  std::vector<int> binfo(8 * c->blk.size(), 0);
+  for (size_t b = 0; b < c->blk.size(); ++b) {
+    const Block& B = c->blk[b];
+    binfo[8 * b] = B.ni; binfo[8 * b + 1] = B.nj; binfo[8 * b + 2] = B.cell0;
+    binfo[8 * b + 3] = B.bc[0] == UGKS_BC_PERIODIC; binfo[8 * b + 4] = B.bc[2] == UGKS_BC_PERIODIC;
+  }
+  // far-field Maxwellian in storage precision
+  std::vector<double> fh(c->nv), fb(c->nv);
+  {
+    double rho, ux, uy, lam;
+    prim(c, c->winf, rho, ux, uy, lam);
+    double nrm = rho * std::pow(lam / kPi, 0.5 * c->dim);
+    for (int k = 0; k < c->nv; ++k) {
+      double cx = c->vx[k] - ux, cy = (c->dim == 2) ? c->vy[k] - uy : 0.0;
+      fh[k] = nrm * std::exp(-lam * (cx * cx + cy * cy));
+      fb[k] = (double)c->nxi * 0.5 / lam * fh[k];
+    }
+  }
+  if (!rc) rc = upload(c->d_vx, c->vx);
+  if (!rc) rc = upload(c->d_vy, c->vy);
+  if (!rc) rc = upload(c->d_wk, c->wk);
+  if (!rc) rc = upload(c->d_cf, c->cf);
+  if (!rc) rc = upload(c->d_fcell, c->fcell);
+  if (!rc) rc = upload(c->d_binfo, binfo);
+  if (!rc) {
+    if (c->prec == UGKS_F64) { rc = upload(c->d_finf_h, fh); if (!rc) rc = upload(c->d_finf_b, fb); }
+    else {
+      std::vector<float> a(fh.begin(), fh.end()), e(fb.begin(), fb.end());
+      rc = upload(c->d_finf_h, a);
+      if (!rc) rc = upload(c->d_finf_b, e);
+    }
+  }
+  if (!rc) rc = upload_geometry(c);
+  if (!rc) rc = upload_tables(c);
+  size_t N = (size_t)c->ncell * c->nv;
+  if (!rc) rc = alloc(c->s_gW, sizeof(double) * 8 * c->ncell);
+  if (!rc) rc = alloc(c->s_rec, sizeof(double) * NREC * (size_t)c->nface);
+  if (!rc) rc = alloc(c->s_gam, sizeof(double) * c->nface);
+  if (!rc) rc = alloc(c->s_R, sizeof(double) * c->nw * (size_t)c->ncell);
+  if (!rc) rc = alloc(c->s_Dg, sizeof(double) * c->ncell);
+  if (!rc) rc = alloc(c->s_dWs, sizeof(double) * c->nw * (size_t)c->ncell);
+  if (!rc) rc = alloc(c->s_dW, sizeof(double) * c->nw * (size_t)c->ncell);
+  if (!rc) rc = alloc(c->s_Wp, sizeof(double) * c->nw * (size_t)c->ncell);
+  if (!rc) rc = alloc(c->s_rpart, sizeof(double) * 4 * c->blk.size());
+  if (!rc) rc = alloc(c->s_crec, sizeof(double) * NCREC * (size_t)c->ncell);
+  if (!rc) rc = alloc(c->s_mrec, sizeof(double) * NMREC * (size_t)c->ncell);
+  if (!rc) rc = alloc(c->s_Dh, tsize(c) * N);
+  if (!rc) rc = alloc(c->s_Db, tsize(c) * N);
+  if (!rc) rc = alloc(c->s_F, sizeof(double) * c->nw * (size_t)c->nface);
+  if (rc) { free_all(c); delete c; return rc; }
+  // scratch that kernels read before writing everywhere starts at zero
+  if (hipMemset(c->s_rec, 0, sizeof(double) * NREC * (size_t)c->nface) != hipSuccess ||
+      hipMemset(c->s_mrec, 0, sizeof(double) * NMREC * (size_t)c->ncell) != hipSuccess ||
+      hipMemset(c->s_crec, 0, sizeof(double) * NCREC * (size_t)c->ncell) != hipSuccess) {
+    free_all(c); delete c; return fail(UGKS_E_DEVICE, "hipMemset failed");
+  }
+  fill_dev(c);
+  *out = c;
+  return UGKS_OK;
+}
+
+int ugks_destroy(ugks_ctx* c) {
+  if (!c) return UGKS_OK;
+  (void)hipDeviceSynchronize();
+  free_all(c);
+  delete c;
+  return UGKS_OK;
+}
+
+int ugks_sizes(const ugks_ctx* c, int32_t* ncell, int32_t* nface, int32_t* nv, int32_t* prec) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  if (ncell) *ncell = c->ncell;
+  if (nface) *nface = c->nface;
+  if (nv) *nv = c->nv;
+  if (prec) *prec = c->prec;
+  return UGKS_OK;
+}
+
+int ugks_set_poses(ugks_ctx* c, const double* poses, double* dts) {
+  if (!c || !poses) return fail(UGKS_E_ARG, "null argument");
+  for (size_t b = 0; b < c->blk.size(); ++b)
+    for (int m = 0; m < 6; ++m) {
+      if (!std::isfinite(poses[6 * b + m])) return fail(UGKS_E_ARG, "non-finite pose");
+    }
+  for (size_t b = 0; b < c->blk.size(); ++b)
+    for (int m = 0; m < 6; ++m) c->blk[b].pose[m] = poses[6 * b + m];
+  compute_geometry(c);
+  int rc = upload_geometry(c);
+  if (rc) return rc;
+  if (dts) *dts = c->dts;
+  return UGKS_OK;
+}
+
+int ugks_timesteps(const ugks_ctx* c, double* dts, double* dtp) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  if (dts) *dts = c->dts;
+  if (dtp) std::memcpy(dtp, c->dtp.data(), sizeof(double) * c->ncell);
+  return UGKS_OK;
+}
+
+int ugks_set_types(ugks_ctx* c, const int8_t* types) {
+  if (!c || !types) return fail(UGKS_E_ARG, "null argument");
+  for (int n = 0; n < c->ncell; ++n)
+    if (types[n] < 0 || types[n] > 2) return fail(UGKS_E_ARG, "bad cell kind");
+  c->type.assign(types, types + c->ncell);
+  build_tables(c);
+  compute_geometry(c);  // dt_s is a minimum over field cells
+  int rc = upload_tables(c);
+  if (!rc) rc = upload_geometry(c);
+  if (!rc) fill_dev(c);
+  return rc;
+}
+
+int ugks_get_types(const ugks_ctx* c, int8_t* types) {
+  if (!c || !types) return fail(UGKS_E_ARG, "null argument");
+  std::memcpy(types, c->type.data(), c->ncell);
+  return UGKS_OK;
+}
+
+int ugks_set_overset(ugks_ctx* c, int32_t nrec, const int32_t* rec, const int32_t* ptr, const int32_t* don,
+                     const double* w) {
+  if (!c || nrec < 0) return fail(UGKS_E_ARG, "bad argument");
+  if (nrec > 0 && (!rec || !ptr || !don || !w)) return fail(UGKS_E_ARG, "null overset array");
+  if (nrec > 0) {
+    if (ptr[0] != 0) return fail(UGKS_E_ARG, "ptr[0] must be 0");
+    for (int r = 0; r < nrec; ++r) {
+      if (rec[r] < 0 || rec[r] >= c->ncell) return fail(UGKS_E_ARG, "receptor out of range");
+      if (ptr[r + 1] < ptr[r]) return fail(UGKS_E_ARG, "ptr not monotone");
+    }
+    for (int p = 0; p < ptr[nrec]; ++p) {
+      if (don[p] < 0 || don[p] >= c->ncell) return fail(UGKS_E_ARG, "donor out of range");
+      if (c->type[don[p]] != UGKS_FIELD) return fail(UGKS_E_ARG, "donor is not a field cell");
+    }
+  }
+  c->nrec = nrec;
+  c->h_rec.assign(rec, rec + nrec);
+  c->h_ptr.assign(ptr, ptr + nrec + 1);
+  int nd = nrec > 0 ? ptr[nrec] : 0;
+  c->h_don.assign(don, don + nd);
+  c->h_w.assign(w, w + nd);
+  for (void** p : {&c->d_rec, &c->d_ptr, &c->d_don, &c->d_w})
+    if (*p) { (void)hipFree(*p); *p = nullptr; }
+  int rc = upload(c->d_rec, c->h_rec);
+  if (!rc) rc = upload(c->d_ptr, c->h_ptr);
+  if (!rc) rc = upload(c->d_don, c->h_don);
+  if (!rc) rc = upload(c->d_w, c->h_w);
+  return rc;
+}
+
+int overset_assemble(ugks_ctx* c, int32_t wrule, int32_t overlap, int32_t* nrec) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  if (wrule != 0 && wrule != 1) return fail(UGKS_E_ARG, "wrule must be 0 or 1");
+  if (overlap < 0) return fail(UGKS_E_ARG, "negative overlap");
+  if (c->dim != 2) return fail(UGKS_E_UNSUPPORTED, "overset assembly is 2D");
+  OversetInput in;
+  in.nblock = (int)c->blk.size();
+  for (const auto& B : c->blk) {
+    in.ni.push_back(B.ni); in.nj.push_back(B.nj); in.cell0.push_back(B.cell0);
+    for (int s = 0; s < 4; ++s) in.bc.push_back(B.bc[s]);
+  }
+  in.xn = &c->xn; in.yn = &c->yn; in.node0 = &c->node0;
+  OversetOutput res;
+  std::string msg;
+  int rc = overset_build(in, wrule, overlap, res, msg);
+  if (rc) return fail(rc, msg);
+  c->type = res.type;
+  build_tables(c);
+  compute_geometry(c);
+  rc = upload_tables(c);
+  if (!rc) rc = upload_geometry(c);
+  if (!rc) fill_dev(c);
+  if (rc) return rc;
+  rc = ugks_set_overset(c, (int)res.rec.size(), res.rec.data(), res.ptr.data(), res.don.data(), res.w.data());
+  if (!rc && nrec) *nrec = (int)res.rec.size();
+  return rc;
+}
+
+static int check_dev(const ugks_ctx* c, std::initializer_list<const void*> ps) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  for (const void* p : ps)
+    if (!p) return fail(UGKS_E_ARG, "null device array");
+  return UGKS_OK;
+}
+
+int ugks_maxwellian(ugks_ctx* c, const double* W, void* h, void* b, void* stream) {
+  if (int rc = check_dev(c, {W, h, b})) return rc;
+  launch_maxwellian(c->dev, c->prec, W, h, b, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+int ugks_moments(ugks_ctx* c, const void* h, const void* b, double* W, double* q, void* stream) {
+  if (int rc = check_dev(c, {h, b, W, q})) return rc;
+  launch_moments(c->dev, c->prec, h, b, W, q, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+int ugks_heatflux(ugks_ctx* c, const void* h, const void* b, const double* W, double* q, void* stream) {
+  if (int rc = check_dev(c, {h, b, W, q})) return rc;
+  launch_step7(c->dev, c->prec, 2, h, b, nullptr, nullptr, const_cast<double*>(W), q, (double*)c->s_mrec,
+               (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+int ugks_flux(ugks_ctx* c, double dts, const void* h, const void* b, const double* W, const double* q,
+              void* Dh, void* Db, double* F, double* wall, void* stream) {
+  if (int rc = check_dev(c, {h, b, W, q, Dh, Db})) return rc;
+  if (!(dts > 0) || !std::isfinite(dts)) return fail(UGKS_E_ARG, "dts must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  if (wall) HIPCHK(hipMemsetAsync(wall, 0, sizeof(double) * (c->nw + 1) * (size_t)c->nface, st));
+  double* Fo = F ? F : (double*)c->s_F;
+  HIPCHK(hipMemsetAsync(Fo, 0, sizeof(double) * c->nw * (size_t)c->nface, st));
+  launch_flux(c->dev, c->prec, dts, h, b, W, q, (double*)c->s_gW, (double*)c->s_rec, Dh, Db, Fo, wall, st);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+int overset_interp(ugks_ctx* c, void* h, void* b, double* W, double* q, void* stream) {
+  if (int rc = check_dev(c, {h, b, W, q})) return rc;
+  launch_interp(c->dev, c->prec, c->nrec, (const int*)c->d_rec, (const int*)c->d_ptr, (const int*)c->d_don,
+                (const double*)c->d_w, h, b, W, q, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+int ugks_begin_step(ugks_ctx* c, double dt, void* h, void* b, double* W, double* q, void* Sh, void* Sb,
+                    double* Fn, void* stream) {
+  if (int rc = check_dev(c, {h, b, W, q, Sh, Sb, Fn})) return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  launch_interp(c->dev, c->prec, c->nrec, (const int*)c->d_rec, (const int*)c->d_ptr, (const int*)c->d_don,
+                (const double*)c->d_w, h, b, W, q, st);
+  HIPCHK(hipMemsetAsync(Fn, 0, sizeof(double) * c->nw * (size_t)c->nface, st));
+  // the level-n divergence is staged in Sh, Sb
+  launch_flux(c->dev, c->prec, c->dts, h, b, W, q, (double*)c->s_gW, (double*)c->s_rec, Sh, Sb, Fn, nullptr, st);
+  launch_cellrec(c->dev, W, q, nullptr, (double*)c->s_crec, st);
+  launch_source(c->dev, c->prec, dt, h, b, (const double*)c->s_crec, Sh, Sb, st);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+int ugks_step(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, double* W, const double* Wn, double* q,
+              const void* Sh, const void* Sb, const double* Fn, double* resid, void* stream) {
+  if (int rc = check_dev(c, {h, b, W, Wn, q, Sh, Sb, Fn})) return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
+  if (n_inner < 0) return fail(UGKS_E_ARG, "n_inner must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  const Dev& g = c->dev;
+  double* F = (double*)c->s_F;
+  // moments of f^s about the velocity of W^s (heat flux source of the first
+  // micro step)
+  launch_step7(g, c->prec, 0, h, b, nullptr, nullptr, W, q, (double*)c->s_mrec, st);
+  for (int s = 0; s < n_inner; ++s) {
+    launch_interp(g, c->prec, c->nrec, (const int*)c->d_rec, (const int*)c->d_ptr, (const int*)c->d_don,
+                  (const double*)c->d_w, h, b, W, q, st);
+    launch_flux(g, c->prec, c->dts, h, b, W, q, (double*)c->s_gW, (double*)c->s_rec, c->s_Dh, c->s_Db, F,
+                nullptr, st);
+    launch_macro(g, (const int*)c->d_binfo, dt, W, Wn, F, Fn, (double*)c->s_gam, (double*)c->s_R,
+                 (double*)c->s_Dg, (double*)c->s_dWs, (double*)c->s_dW, (double*)c->s_Wp, (double*)c->s_rpart,
+                 resid ? resid + (size_t)s * c->nw : nullptr, st);
+    launch_cellrec(g, (const double*)c->s_Wp, nullptr, (const double*)c->s_mrec, (double*)c->s_crec, st);
+    launch_micro(g, c->prec, (const int*)c->d_binfo, c->max_ni, c->max_nj, c->any_pj, dt,
+                 (const double*)c->s_crec, h, b, Sh, Sb, c->s_Dh, c->s_Db, st);
+    launch_step7(g, c->prec, 1, h, b, (const double*)c->s_crec, (const double*)c->s_Wp, W, q,
+                 (double*)c->s_mrec, st);
+  }
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,235 @@
+// Device-side data layout and math of libugks (gfx950).
+//
+// Geometry lives in struct-of-arrays device buffers owned by the context; a
+// Dev value (plain pointers and sizes) is passed to every kernel by value.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ugks {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// neighbour codes in the per-cell table nb[cell][4] (slots: i-low, i-high,
+// j-low, j-high); >= 0 is a non-hole cell of the same block
+constexpr int kNbFar = -1;    // far-field ghost: Maxwellian of W_inf
+constexpr int kNbCopy = -2;   // zero-gradient ghost: the cell itself
+constexpr int kNbWall = -3;   // isothermal wall
+constexpr int kNbMiss = -4;   // hole, overset fringe or no face
+
+// face record (double) written by the face-equilibrium kernels
+enum : int {
+  R_RHO = 0, R_UX, R_UY, R_LAM, R_QX, R_QY,
+  R_HN,        // rho (lam/pi)^(D/2)
+  R_SH,        // 4 (1-Pr) lam^2 / (5 rho)
+  R_AX = 8,    // slope coefficients along x (4)
+  R_AY = 12,   // along y (4)
+  R_AT = 16,   // time coefficients A (4)
+  R_T1 = 20,   // q1..q5 / dt_s (5)
+  R_ACT = 25,  // 1 if the face carries flux
+  R_RHOW,      // wall density
+  R_LAMW,      // 1/(2 RT_w)
+  R_HWN,       // (lam_w/pi)^(D/2)
+  R_VWX, R_VWY,
+  R_SGN,       // +1: face normal points into the wall
+  NREC = 32
+};
+
+// per-cell equilibrium record (double): state used by the Shakhov source
+enum : int {
+  C_RHO = 0, C_UX, C_UY, C_LAM, C_QX, C_QY, C_HN, C_SH, C_ITAU, NCREC = 10
+};
+
+// per-cell moment record about a shift s: s(2), m0, m1(2), m2, P(3), m3(2)
+enum : int {
+  M_SX = 0, M_SY, M_M0, M_M1X, M_M1Y, M_M2, M_PXX, M_PXY, M_PYY, M_M3X, M_M3Y, NMREC = 11
+};
+
+struct Dev {
+  int dim, nxi, nw, nv, nvx, nvy, ncell, nface, nblock;
+  double pr, omega, mu_ref, rt_ref;
+  double winf[4];
+  const double* vx;     // [nv]
+  const double* vy;     // [nv]
+  const double* wk;     // [nv] velocity weights
+  const double* vol;    // [ncell]
+  const double* G;      // [ncell][4] J^{-T}
+  const double* cdx;    // [ncell][8] face centre - centroid per slot
+  const double* dtp;    // [ncell]
+  const int8_t* type;   // [ncell]
+  const int* nb;        // [ncell][4]
+  const int* cf;        // [ncell][4] face per slot or -1
+  const int* fcell;     // [nface][2] L, R (cell or ghost code)
+  const double* fgeo;   // [nface][8] nx, ny, S, ux, uy, vwx, vwy, rtw
+  const int8_t* fact;   // [nface] face adjacent to a field cell
+  const void* finf_h;   // [nv] storage type
+  const void* finf_b;
+};
+
+// ------------------------------------------------------------------------
+// gas relations
+// ------------------------------------------------------------------------
+__device__ __host__ inline void prim_of(const Dev& g, const double* W, double& rho, double& ux,
+                                        double& uy, double& lam) {
+  rho = W[0];
+  ux = W[1] / rho;
+  uy = (g.dim == 2) ? W[2] / rho : 0.0;
+  double e = W[g.dim + 1] - 0.5 * rho * (ux * ux + uy * uy);
+  lam = 0.25 * (double)(g.dim + g.nxi) * rho / e;
+}
+
+__device__ inline double inv_tau_of(const Dev& g, double rho, double lam) {
+  if (g.mu_ref <= 0.0) return 0.0;
+  double rt = 0.5 / lam;
+  double mu = g.mu_ref * pow(rt / g.rt_ref, g.omega);
+  return rho * rt / mu;
+}
+
+// time integrals q1..q5 over [0, dts] of the interface-solution coefficients;
+// Taylor series below x = 1 (m <= 24), closed forms above
+__device__ inline void time_integrals(double dts, double itau, double* q) {
+  double x = dts * itau;
+  if (x < 1.0) {
+    double a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+    double p = 1.0;  // x^(m-1)
+    double pp = 0.0; // x^(m-2)
+    double fac = 1.0;
+    for (int m = 1; m <= 24; ++m) {
+      fac *= (double)m;
+      double s = (m & 1) ? 1.0 : -1.0;  // (-1)^(m+1)
+      a1 += s * p / fac;
+      if (m >= 2) {
+        a3 -= s * p / fac;
+        a2 += s * (double)(m - 1) * pp / fac;
+      }
+      if (m >= 3) {
+        a4 -= s * (double)(m - 2) * pp / fac;
+        a5 += s * pp / fac;
+      }
+      pp = (m == 1) ? 1.0 : pp * x;
+      p *= x;
+    }
+    q[0] = dts * a1;
+    q[1] = dts * dts * a2;
+    q[2] = dts * a3;
+    q[3] = dts * dts * a4;
+    q[4] = dts * dts * a5;
+  } else {
+    double tau = 1.0 / itau;
+    double e = exp(-x);
+    q[0] = tau * (1.0 - e);
+    q[1] = tau * tau * ((1.0 + x) * e - 1.0);
+    q[2] = dts - q[0];
+    q[3] = tau * tau * (2.0 - x - (2.0 + x) * e);
+    q[4] = tau * tau * (0.5 * x * x - x + 1.0 - e);
+  }
+}
+
+// closed-form inverse of the Maxwellian moment matrix: a with <psi psi^T> a = d
+// (gas-kinetic micro-slope formulas; K' = N_xi internal components)
+__device__ inline void slope_inverse(int dim, double U, double V, double lam, const double* d,
+                                     double* a) {
+  if (dim == 2) {
+    const double K = 1.0;
+    double e2 = U * U + V * V + (K + 2.0) / (2.0 * lam);
+    double r4 = 2.0 * d[3] - e2 * d[0];
+    double r3 = d[2] - V * d[0];
+    double r2 = d[1] - U * d[0];
+    a[3] = 4.0 * lam * lam / (K + 2.0) * (r4 - 2.0 * U * r2 - 2.0 * V * r3);
+    a[2] = 2.0 * lam * r3 - V * a[3];
+    a[1] = 2.0 * lam * r2 - U * a[3];
+    a[0] = d[0] - U * a[1] - V * a[2] - 0.5 * a[3] * e2;
+  } else {
+    const double K = 2.0;
+    double e2 = U * U + (K + 1.0) / (2.0 * lam);
+    double r3 = 2.0 * d[2] - e2 * d[0];
+    double r2 = d[1] - U * d[0];
+    a[2] = 4.0 * lam * lam / (K + 1.0) * (r3 - 2.0 * U * r2);
+    a[1] = 2.0 * lam * r2 - U * a[2];
+    a[0] = d[0] - U * a[1] - 0.5 * a[2] * e2;
+  }
+}
+
+// <psi v_dir (a . psi)> under the normalised Maxwellian (mean U, V; 1/(2 lam))
+__device__ inline void psi_v_apsi(int dim, int dir, double U, double V, double lam,
+                                  const double* a, double* out) {
+  double th = 0.5 / lam;
+  double mu[7], mv[7];
+  mu[0] = 1.0; mu[1] = U;
+  mv[0] = 1.0; mv[1] = V;
+  for (int n = 1; n < 6; ++n) {
+    mu[n + 1] = U * mu[n] + n * th * mu[n - 1];
+    mv[n + 1] = V * mv[n] + n * th * mv[n - 1];
+  }
+  if (dim == 1) {
+    double x1 = 2.0 * th, x2 = 8.0 * th * th;  // <xi^2>, <xi^4> for 2 components
+    double uE = 0.5 * (mu[3] + mu[1] * x1);
+    double u2E = 0.5 * (mu[4] + mu[2] * x1);
+    double uE2 = 0.25 * (mu[5] + 2.0 * mu[3] * x1 + mu[1] * x2);
+    out[0] = a[0] * mu[1] + a[1] * mu[2] + a[2] * uE;
+    out[1] = a[0] * mu[2] + a[1] * mu[3] + a[2] * u2E;
+    out[2] = a[0] * uE + a[1] * u2E + a[2] * uE2;
+    return;
+  }
+  double x1 = th, x2 = 3.0 * th * th;  // one internal component
+  if (dir == 1) {  // swap roles of the two axes
+    for (int n = 0; n < 7; ++n) { double t = mu[n]; mu[n] = mv[n]; mv[n] = t; }
+  }
+  // moments with w the chosen axis (mu) and z the other (mv)
+  double wE = 0.5 * (mu[3] + mu[1] * mv[2] + mu[1] * x1);
+  double w2E = 0.5 * (mu[4] + mu[2] * mv[2] + mu[2] * x1);
+  double wzE = 0.5 * (mu[3] * mv[1] + mu[1] * mv[3] + mu[1] * mv[1] * x1);
+  double wE2 = 0.25 * (mu[5] + mu[1] * mv[4] + mu[1] * x2 + 2.0 * mu[3] * mv[2] +
+                       2.0 * mu[3] * x1 + 2.0 * mu[1] * mv[2] * x1);
+  // coefficient along the chosen axis and along the other
+  double aw = (dir == 0) ? a[1] : a[2];
+  double az = (dir == 0) ? a[2] : a[1];
+  double o0 = a[0] * mu[1] + aw * mu[2] + az * mu[1] * mv[1] + a[3] * wE;
+  double ow = a[0] * mu[2] + aw * mu[3] + az * mu[2] * mv[1] + a[3] * w2E;
+  double oz = a[0] * mu[1] * mv[1] + aw * mu[2] * mv[1] + az * mu[1] * mv[2] + a[3] * wzE;
+  double oE = a[0] * wE + aw * w2E + az * wzE + a[3] * wE2;
+  out[0] = o0;
+  out[1] = (dir == 0) ? ow : oz;
+  out[2] = (dir == 0) ? oz : ow;
+  out[3] = oE;
+}
+
+// equilibrium expansion coefficients of a face state: slopes a_d from the
+// gradient dW[d][nw] and time coefficient A from the compatibility condition
+// with the relative velocity w = v - U_f
+__device__ inline void expansion(int dim, double rho, double U, double V, double lam, double ufx,
+                                 double ufy, const double* dW, double* ax, double* ay,
+                                 double* At) {
+  int nw = dim + 2;
+  double d[4];
+  for (int m = 0; m < nw; ++m) d[m] = dW[m] / rho;
+  slope_inverse(dim, U, V, lam, d, ax);
+  double b[4] = {0, 0, 0, 0};
+  double t[4];
+  psi_v_apsi(dim, 0, U, V, lam, ax, t);
+  for (int m = 0; m < nw; ++m) b[m] = -t[m] + ufx * d[m];
+  if (dim == 2) {
+    for (int m = 0; m < nw; ++m) d[m] = dW[nw + m] / rho;
+    slope_inverse(dim, U, V, lam, d, ay);
+    psi_v_apsi(dim, 1, U, V, lam, ay, t);
+    for (int m = 0; m < nw; ++m) b[m] += -t[m] + ufy * d[m];
+  } else {
+    for (int m = 0; m < 4; ++m) ay[m] = 0.0;
+  }
+  slope_inverse(dim, U, V, lam, b, At);
+  if (dim == 1) { ax[3] = 0.0; At[3] = 0.0; }
+}
+
+// ------------------------------------------------------------------------
+// wavefront reduction (64 lanes)
+// ------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <class T>
+__device__ inline double ld(const T* p, size_t i) { return (double)p[i]; }
+
+}  // namespace ugks

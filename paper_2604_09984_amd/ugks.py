@@ -1,0 +1,241 @@
+"""Thin Python binding of libugks (C ABI of include/ugks.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  PyTorch provides device memory and streams.  The binding raises if
+the library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libugks.so")
+
+F64, F32 = 0, 1
+
+_lib = None
+
+
+class _Problem(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("pr", C.c_double), ("omega", C.c_double), ("mu_ref", C.c_double),
+                ("rt_ref", C.c_double), ("nvx", C.c_int32), ("nvy", C.c_int32),
+                ("vx", C.POINTER(C.c_double)), ("vy", C.POINTER(C.c_double)),
+                ("vrange", C.c_double * 4), ("winf", C.c_double * 4), ("cfl_s", C.c_double),
+                ("cfl_p", C.c_double), ("nblock", C.c_int32), ("bint", C.POINTER(C.c_int32)),
+                ("bdbl", C.POINTER(C.c_double)), ("nodes", C.POINTER(C.c_double)), ("prec", C.c_int32)]
+
+
+class UgksError(RuntimeError):
+    pass
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise UgksError(f"libugks.so not built ({LIB_PATH}); run paper_2604_09984_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        d = C.c_double
+        i32 = C.c_int32
+        L.ugks_last_error.restype = C.c_char_p
+        L.ugks_create.argtypes = [C.POINTER(_Problem), C.c_int, C.POINTER(vp)]
+        L.ugks_destroy.argtypes = [vp]
+        L.ugks_sizes.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.ugks_set_poses.argtypes = [vp, C.POINTER(d), C.POINTER(d)]
+        L.ugks_set_types.argtypes = [vp, C.POINTER(C.c_int8)]
+        L.ugks_get_types.argtypes = [vp, C.POINTER(C.c_int8)]
+        L.ugks_set_overset.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(d)]
+        L.overset_assemble.argtypes = [vp, i32, i32, C.POINTER(i32)]
+        L.ugks_maxwellian.argtypes = [vp, vp, vp, vp, vp]
+        L.ugks_moments.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.ugks_heatflux.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.ugks_flux.argtypes = [vp, d, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.overset_interp.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.ugks_begin_step.argtypes = [vp, d, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ugks_step.argtypes = [vp, d, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ugks_timesteps.argtypes = [vp, C.POINTER(d), C.POINTER(d)]
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return ["ugks_create", "ugks_destroy", "ugks_sizes", "ugks_set_poses", "ugks_set_types",
+            "ugks_get_types", "ugks_set_overset", "overset_assemble", "ugks_maxwellian",
+            "ugks_moments", "ugks_heatflux", "ugks_flux", "overset_interp", "ugks_begin_step", "ugks_step",
+            "ugks_timesteps", "ugks_last_error"]
+
+
+def _check(rc):
+    if rc != 0:
+        msg = lib().ugks_last_error().decode()
+        raise UgksError(f"libugks error {rc}: {msg}")
+
+
+def _p(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Solver:
+    """A libugks context for one case (see workloads.Case)."""
+
+    def __init__(self, case, prec: int = F64, device: int = 0):
+        L = lib()
+        self.case = case
+        self.prec = prec
+        self.device = torch.device("cuda", device)
+        self.dtype = torch.float64 if prec == F64 else torch.float32
+        vx = np.ascontiguousarray(case.vx, dtype=np.float64)
+        vy = np.ascontiguousarray(case.vy, dtype=np.float64)
+        bint = case.block_ints()
+        bdbl = case.block_dbls()
+        nodes = case.node_array()
+        self._keep = (vx, vy, bint, bdbl, nodes)
+        p = _Problem()
+        p.dim = case.dim
+        p.pr, p.omega, p.mu_ref, p.rt_ref = case.pr, case.omega, case.mu_ref, case.rt_ref
+        p.nvx, p.nvy = case.nvx, case.nvy
+        p.vx, p.vy = _dp(vx), _dp(vy)
+        for m in range(4):
+            p.vrange[m] = float(case.vrange[m])
+            p.winf[m] = float(case.winf[m]) if m < case.nw else 0.0
+        p.cfl_s, p.cfl_p = case.cfl_s, case.cfl_p
+        p.nblock = len(case.blocks)
+        p.bint = bint.ctypes.data_as(C.POINTER(C.c_int32))
+        p.bdbl = _dp(bdbl)
+        p.nodes = _dp(nodes)
+        p.prec = prec
+        ctx = C.c_void_p()
+        _check(L.ugks_create(C.byref(p), device, C.byref(ctx)))
+        self.ctx = ctx
+        n = [C.c_int32() for _ in range(4)]
+        _check(L.ugks_sizes(ctx, *[C.byref(x) for x in n]))
+        self.ncell, self.nface, self.nv = n[0].value, n[1].value, n[2].value
+        self.dim, self.nw = case.dim, case.nw
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().ugks_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ setup
+    def set_poses(self, poses) -> float:
+        a = np.ascontiguousarray(np.asarray(poses, dtype=np.float64).reshape(-1, 6))
+        dts = C.c_double()
+        _check(lib().ugks_set_poses(self.ctx, _dp(a), C.byref(dts)))
+        return dts.value
+
+    def timesteps(self):
+        dts = C.c_double()
+        dtp = np.zeros(self.ncell)
+        _check(lib().ugks_timesteps(self.ctx, C.byref(dts), _dp(dtp)))
+        return dts.value, dtp
+
+    def set_types(self, t):
+        t = np.ascontiguousarray(t, dtype=np.int8)
+        _check(lib().ugks_set_types(self.ctx, t.ctypes.data_as(C.POINTER(C.c_int8))))
+
+    def types(self):
+        t = np.zeros(self.ncell, np.int8)
+        _check(lib().ugks_get_types(self.ctx, t.ctypes.data_as(C.POINTER(C.c_int8))))
+        return t
+
+    def set_overset(self, rec, ptr, don, w):
+        rec = np.ascontiguousarray(rec, np.int32); ptr = np.ascontiguousarray(ptr, np.int32)
+        don = np.ascontiguousarray(don, np.int32); w = np.ascontiguousarray(w, np.float64)
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        _check(lib().ugks_set_overset(self.ctx, len(rec), ip(rec), ip(ptr), ip(don), _dp(w)))
+
+    def assemble(self, wrule=0, overlap=2) -> int:
+        n = C.c_int32()
+        _check(lib().overset_assemble(self.ctx, int(wrule), int(overlap), C.byref(n)))
+        return n.value
+
+    # -------------------------------------------------------------- tensors
+    def empty_f(self):
+        return torch.empty((self.ncell, self.nv), dtype=self.dtype, device=self.device)
+
+    def zeros_w(self):
+        return torch.zeros((self.ncell, self.nw), dtype=torch.float64, device=self.device)
+
+    def zeros_q(self):
+        return torch.zeros((self.ncell, self.dim), dtype=torch.float64, device=self.device)
+
+    def zeros_face(self, width):
+        return torch.zeros((self.nface, width), dtype=torch.float64, device=self.device)
+
+    def _stream(self, stream):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return C.c_void_p(s.cuda_stream)
+
+    # ------------------------------------------------------------ compute
+    def maxwellian(self, W, stream=None):
+        h, b = self.empty_f(), self.empty_f()
+        _check(lib().ugks_maxwellian(self.ctx, _p(W), _p(h), _p(b), self._stream(stream)))
+        return h, b
+
+    def moments(self, h, b, stream=None):
+        W, q = self.zeros_w(), self.zeros_q()
+        _check(lib().ugks_moments(self.ctx, _p(h), _p(b), _p(W), _p(q), self._stream(stream)))
+        return W, q
+
+    def flux(self, dts, h, b, W, q, stream=None):
+        Dh, Db = self.empty_f(), self.empty_f()
+        F, wall = self.zeros_face(self.nw), self.zeros_face(self.nw + 1)
+        _check(lib().ugks_flux(self.ctx, float(dts), _p(h), _p(b), _p(W), _p(q), _p(Dh), _p(Db), _p(F),
+                               _p(wall), self._stream(stream)))
+        return Dh, Db, F, wall
+
+    def interp(self, h, b, W, q, stream=None):
+        _check(lib().overset_interp(self.ctx, _p(h), _p(b), _p(W), _p(q), self._stream(stream)))
+
+    def begin_step(self, dt, h, b, W, q, Sh=None, Sb=None, Fn=None, stream=None):
+        Sh = self.empty_f() if Sh is None else Sh
+        Sb = self.empty_f() if Sb is None else Sb
+        Fn = self.zeros_face(self.nw) if Fn is None else Fn
+        _check(lib().ugks_begin_step(self.ctx, float(dt), _p(h), _p(b), _p(W), _p(q), _p(Sh), _p(Sb), _p(Fn),
+                                     self._stream(stream)))
+        return Sh, Sb, Fn
+
+    def step(self, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, resid=None, stream=None):
+        _check(lib().ugks_step(self.ctx, float(dt), int(n_inner), _p(h), _p(b), _p(W), _p(Wn), _p(q), _p(Sh),
+                               _p(Sb), _p(Fn), _p(resid), self._stream(stream)))
+        return resid
+
+    # ------------------------------------------------------------- driver
+    def init_state(self):
+        W = torch.tensor(np.asarray(self.case.w_init, dtype=np.float64), device=self.device).contiguous()
+        h, b = self.maxwellian(W)
+        q = self.heatflux(h, b, W)
+        return h, b, W, q
+
+    def heatflux(self, h, b, W, stream=None):
+        """Heat flux of (h, b) about the velocity of W."""
+        q = self.zeros_q()
+        _check(lib().ugks_heatflux(self.ctx, _p(h), _p(b), _p(W), _p(q), self._stream(stream)))
+        return q
+
+    def physical_step(self, dt, h, b, W, q, n_inner=None, resid=None):
+        Wn = W.clone()
+        Sh, Sb, Fn = self.begin_step(dt, h, b, W, q)
+        n = self.case.n_inner if n_inner is None else n_inner
+        self.step(dt, n, h, b, W, Wn, q, Sh, Sb, Fn, resid)
+        return Wn
