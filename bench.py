@@ -1,0 +1,189 @@
+#!/usr/bin/env python
+"""Benchmark of one dual-time pseudo-iteration (Steps 3-7) of the implicit
+unsteady UGKS on MI355X, on the Ma 5 cylinder workload: O-mesh 128 x 64
+cells, 64 x 64 velocity grid on [-15, 15]^2, Kn 0.01, hard-sphere gas,
+isothermal wall, far field, dt = 20 dt_s.
+
+Prints one JSON line: (cell x velocity) updates per second per pseudo-step
+for the FP64 path (`value`), the FP32-storage path beside it, the roofline
+of the dominant kernel (timed live with HIP events on the library's stream)
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+Inputs are resident in HBM before the timed region starts.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+# algorithmic values moved per (cell, velocity) pair by each kernel
+# (storage-precision values: h, b, sources, divergences)
+KERNEL_VALUES = {"face_eq": 2, "flux": 4, "micro_lusgs": 14, "step7": 2}
+KERNEL_NAMES = {"face_eq": "k_face_eq", "flux": "k_flux", "micro_lusgs": "k_micro", "step7": "k_step7"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50, help="timed pseudo-iterations")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed pseudo-iterations")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle pseudo-iterations (0: skip)")
+    ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--nvx", type=int, default=64)
+    return ap.parse_args()
+
+
+def traffic_from_profiles(kernel, prec):
+    """HBM bytes per launch from the committed counter summary, if it still
+    matches the kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        ent = data.get(f"{kernel}:{prec}")
+        if not ent:
+            return None
+        import hashlib
+        src = open(os.path.join(ROOT, "paper_2604_09984_amd", "csrc", "ugks_kernels.hip"), "rb").read()
+        if ent.get("source_sha1") != hashlib.sha1(src).hexdigest():
+            return None
+        return ent["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def run_gpu(case, prec_name, steps, warmup):
+    import torch
+    from paper_2604_09984_amd import ugks
+    prec = ugks.F64 if prec_name == "f64" else ugks.F32
+    s = ugks.Solver(case, prec)
+    dts, _ = s.timesteps()
+    dt = case.dt_over_dts * dts
+    h, b, W, q = s.init_state()
+    Wn = W.clone()
+    Sh, Sb, Fn = s.begin_step(dt, h, b, W, q)
+    if warmup > 0:
+        s.step(dt, warmup, h, b, W, Wn, q, Sh, Sb, Fn)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    left = steps
+    while left > 0:
+        n = min(10, left)  # one physical step's inner loop per call
+        s.step(dt, n, h, b, W, Wn, q, Sh, Sb, Fn)
+        left -= n
+    ev1.record()
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    # stage timing (HIP events on the library's stream), separate short run
+    prof = s.step_profile(dt, 10, h, b, W, Wn, q, Sh, Sb, Fn)
+    torch.cuda.synchronize()
+    pairs = int((s.types() == 1).sum()) * s.nv
+    out = dict(prec=prec_name, pairs=pairs, wall_s=wall_s, ev_ms=ev_ms, steps=steps, stages=prof,
+               finite=bool(torch.isfinite(h).all().item() and torch.isfinite(W).all().item()))
+    out["h"] = h.to(torch.float64).cpu()
+    s.close()
+    return out
+
+
+def cpu_baseline(case, nsteps):
+    """The FP64 oracle, as it stands, on the host cores: Steps 1-2 untimed,
+    then `nsteps` pseudo-iterations timed on the full workload."""
+    import numpy as np
+    from oracle.oracle import Oracle
+    o = Oracle(case)
+    h, b, W, q = o.init_state()
+    dts, dtp = o.timesteps()
+    dt = case.dt_over_dts * dts
+    Wn = W.copy()
+    Sh, Sb, Fn = o.begin_step(dt, dts, h, b, W, q)
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        o.pseudo_step(dt, dts, dtp, h, b, W, Wn, q, Sh, Sb, Fn)
+    sec = time.perf_counter() - t0
+    pairs = o.ncell * o.nv
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pairs * nsteps / sec, "unit": "pair-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nsteps} pseudo-iterations (after Steps 1-2) of the full workload, "
+                      f"{pairs} pairs, {sec:.1f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): the pseudo-iteration "
+              "is measured on a single MI355X; the multi-GPU velocity-sharded design is described "
+              "in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2604_09984_amd import workloads as wl
+    from paper_2604_09984_amd import ugks
+    ugks.lib()  # fail loudly when the HIP library is missing
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(3)
+    case = wl.cylinder(nvx=args.nvx)
+    r64 = run_gpu(case, "f64", args.steps, args.warmup)
+    r32 = None if args.no_f32 else run_gpu(case, "f32", args.steps, args.warmup)
+    ms64 = 1e3 * r64["wall_s"] / args.steps
+    value = r64["pairs"] * args.steps / r64["wall_s"]
+    # dominant kernel of the FP64 path
+    st = r64["stages"]
+    dom = max(KERNEL_VALUES, key=lambda k: st[k])
+    t_launch = st[dom] * 1e-3
+    algo_bytes = KERNEL_VALUES[dom] * 8 * r64["pairs"]
+    achieved = algo_bytes / t_launch / 1e9
+    traffic = traffic_from_profiles(KERNEL_NAMES[dom], "f64")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": KERNEL_NAMES[dom], "kernel_ms": round(st[dom], 4),
+            "algorithmic_bytes_per_launch": algo_bytes}
+    total_algo = sum(KERNEL_VALUES.values()) * 8 * r64["pairs"]
+    line = {
+        "metric": "(cell x velocity) updates/s per pseudo-step",
+        "value": value,
+        "unit": "pair-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"Ma5 cylinder, O-mesh 128x64 cells, {args.nvx}x{args.nvx} velocities on "
+                               f"[-15,15]^2, Kn 0.01 hard sphere, isothermal wall, dt = 20 dt_s",
+                   "pairs": r64["pairs"], "pseudo_steps": args.steps},
+        "roofline": roof,
+        "stages_ms_f64": {k: round(v, 4) for k, v in st.items()},
+        "hbm_algorithmic_GBs_f64": round(total_algo / (ms64 * 1e-3) / 1e9, 1),
+    }
+    if r32 is not None:
+        ms32 = 1e3 * r32["wall_s"] / args.steps
+        import numpy as np
+        h64 = r64["h"].numpy().ravel()
+        h32 = r32["h"].numpy().ravel()
+        rel = float(np.linalg.norm(h32 - h64) / np.linalg.norm(h64))
+        line["f32"] = {"value": r32["pairs"] * args.steps / r32["wall_s"], "ms_per_step": ms32,
+                       "speedup_vs_f64": ms64 / ms32,
+                       "rel_l2_h_vs_f64_after_run": rel,
+                       "stages_ms": {k: round(v, 4) for k, v in r32["stages"].items()}}
+    line["finite"] = r64["finite"] and (r32 is None or r32["finite"])
+    if args.cpu_steps > 0:
+        line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

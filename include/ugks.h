@@ -202,6 +202,20 @@ int ugks_step(ugks_ctx* ctx, double dt, int32_t n_inner, void* h, void* b, doubl
               const double* Wn, double* q, const void* Sh, const void* Sb, const double* Fn,
               double* resid, void* stream);
 
+/*
+ * Instrumented ugks_step for measurement: the same n_inner pseudo-iterations,
+ * with HIP events recorded on `stream` between the stages; waits for the
+ * last event and writes host stage_ms[UGKS_NSTAGE], the mean milliseconds
+ * per pseudo-iteration of: 0 overset interpolation, 1 W gradients and wall
+ * incident states, 2 face equilibrium (k_face_eq), 3 flux (k_flux), 4 macro
+ * LU-SGS, 5 cell equilibrium records, 6 micro LU-SGS sweeps (k_micro),
+ * 7 Step-7 moments (k_step7).
+ */
+#define UGKS_NSTAGE 8
+int ugks_step_profile(ugks_ctx* ctx, double dt, int32_t n_inner, void* h, void* b, double* W,
+                      const double* Wn, double* q, const void* Sh, const void* Sb, const double* Fn,
+                      double* stage_ms, void* stream);
+
 /* Current explicit flux step dt_s and a copy of the virtual steps dt' (host
    array [ncell], may be NULL). */
 int ugks_timesteps(const ugks_ctx* ctx, double* dts, double* dtp);

@@ -729,33 +729,74 @@ int ugks_begin_step(ugks_ctx* c, double dt, void* h, void* b, double* W, double*
   return UGKS_OK;
 }
 
-int ugks_step(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, double* W, const double* Wn, double* q,
-              const void* Sh, const void* Sb, const double* Fn, double* resid, void* stream) {
-  if (int rc = check_dev(c, {h, b, W, Wn, q, Sh, Sb, Fn})) return rc;
-  if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
-  if (n_inner < 0) return fail(UGKS_E_ARG, "n_inner must be >= 0");
-  hipStream_t st = (hipStream_t)stream;
+// the pseudo-iteration loop; with ev (9 events per inner iteration) the
+// stage boundaries are recorded on the stream
+static int run_inner(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, double* W, const double* Wn,
+                     double* q, const void* Sh, const void* Sb, const double* Fn, double* resid, hipStream_t st,
+                     std::vector<hipEvent_t>* ev) {
   const Dev& g = c->dev;
   double* F = (double*)c->s_F;
   // moments of f^s about the velocity of W^s (heat flux source of the first
   // micro step)
   launch_step7(g, c->prec, 0, h, b, nullptr, nullptr, W, q, (double*)c->s_mrec, st);
   for (int s = 0; s < n_inner; ++s) {
+    hipEvent_t* e = ev ? &(*ev)[9 * (size_t)s] : nullptr;
+    if (e) HIPCHK(hipEventRecord(e[0], st));
     launch_interp(g, c->prec, c->nrec, (const int*)c->d_rec, (const int*)c->d_ptr, (const int*)c->d_don,
                   (const double*)c->d_w, h, b, W, q, st);
+    if (e) HIPCHK(hipEventRecord(e[1], st));
     launch_flux(g, c->prec, c->dts, h, b, W, q, (double*)c->s_gW, (double*)c->s_rec, c->s_Dh, c->s_Db, F,
-                nullptr, st);
+                nullptr, st, e ? e + 2 : nullptr);
+    if (e) HIPCHK(hipEventRecord(e[4], st));
     launch_macro(g, (const int*)c->d_binfo, dt, W, Wn, F, Fn, (double*)c->s_gam, (double*)c->s_R,
                  (double*)c->s_Dg, (double*)c->s_dWs, (double*)c->s_dW, (double*)c->s_Wp, (double*)c->s_rpart,
                  resid ? resid + (size_t)s * c->nw : nullptr, st);
+    if (e) HIPCHK(hipEventRecord(e[5], st));
     launch_cellrec(g, (const double*)c->s_Wp, nullptr, (const double*)c->s_mrec, (double*)c->s_crec, st);
+    if (e) HIPCHK(hipEventRecord(e[6], st));
     launch_micro(g, c->prec, (const int*)c->d_binfo, c->max_ni, c->max_nj, c->any_pj, dt,
                  (const double*)c->s_crec, h, b, Sh, Sb, c->s_Dh, c->s_Db, st);
+    if (e) HIPCHK(hipEventRecord(e[7], st));
     launch_step7(g, c->prec, 1, h, b, (const double*)c->s_crec, (const double*)c->s_Wp, W, q,
                  (double*)c->s_mrec, st);
+    if (e) HIPCHK(hipEventRecord(e[8], st));
   }
   HIPCHK(hipGetLastError());
   return UGKS_OK;
+}
+
+int ugks_step(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, double* W, const double* Wn, double* q,
+              const void* Sh, const void* Sb, const double* Fn, double* resid, void* stream) {
+  if (int rc = check_dev(c, {h, b, W, Wn, q, Sh, Sb, Fn})) return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
+  if (n_inner < 0) return fail(UGKS_E_ARG, "n_inner must be >= 0");
+  return run_inner(c, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, resid, (hipStream_t)stream, nullptr);
+}
+
+int ugks_step_profile(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, double* W, const double* Wn,
+                      double* q, const void* Sh, const void* Sb, const double* Fn, double* stage_ms,
+                      void* stream) {
+  if (int rc = check_dev(c, {h, b, W, Wn, q, Sh, Sb, Fn, stage_ms})) return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
+  if (n_inner < 1) return fail(UGKS_E_ARG, "n_inner must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<hipEvent_t> ev(9 * (size_t)n_inner);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  int rc = run_inner(c, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, nullptr, st, &ev);
+  if (!rc) {
+    if (hipEventSynchronize(ev.back()) != hipSuccess) rc = fail(UGKS_E_DEVICE, "event synchronisation failed");
+  }
+  if (!rc) {
+    for (int k = 0; k < UGKS_NSTAGE; ++k) stage_ms[k] = 0.0;
+    for (int s = 0; s < n_inner; ++s)
+      for (int k = 0; k < UGKS_NSTAGE; ++k) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[9 * (size_t)s + k], ev[9 * (size_t)s + k + 1]);
+        stage_ms[k] += ms / n_inner;
+      }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return rc;
 }
 
 }  // extern "C"

@@ -8,7 +8,7 @@ constexpr int kMaxRowsMicroHost = 4;
 
 void launch_flux(const Dev& g, int prec, double dts, const void* h, const void* b, const double* W,
                  const double* q, double* gW, double* rec, void* Dh, void* Db, double* F, double* wall,
-                 hipStream_t st);
+                 hipStream_t st, hipEvent_t* ev = nullptr);
 void launch_moments(const Dev& g, int prec, const void* h, const void* b, double* W, double* q, hipStream_t st);
 void launch_maxwellian(const Dev& g, int prec, const double* W, void* h, void* b, hipStream_t st);
 void launch_interp(const Dev& g, int prec, int nrec, const int* rec, const int* ptr, const int* don,

@@ -1010,18 +1010,21 @@ static inline unsigned nbl(size_t n, int t) { return (unsigned)((n + t - 1) / t)
 
 template <class T, class C>
 void launch_flux_t(const Dev& g, double dts, const void* h, const void* b, const double* W, const double* q,
-                   double* gW, double* rec, void* Dh, void* Db, double* F, double* wall, hipStream_t st) {
+                   double* gW, double* rec, void* Dh, void* Db, double* F, double* wall, hipStream_t st,
+                   hipEvent_t* ev) {
   k_gradW<<<nbl(g.ncell, 256), 256, 0, st>>>(g, W, gW);
   k_wallprep<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, W, q, gW, rec);
+  if (ev) (void)hipEventRecord(ev[0], st);
   k_face_eq<T><<<nb4(g.ncell), 256, 0, st>>>(g, dts, (const T*)h, (const T*)b, W, gW, rec);
+  if (ev) (void)hipEventRecord(ev[1], st);
   k_flux<T, C><<<nb4(g.ncell), 256, 0, st>>>(g, (const T*)h, (const T*)b, rec, (T*)Dh, (T*)Db, F, wall);
 }
 
 void launch_flux(const Dev& g, int prec, double dts, const void* h, const void* b, const double* W,
                  const double* q, double* gW, double* rec, void* Dh, void* Db, double* F, double* wall,
-                 hipStream_t st) {
-  if (prec == 0) launch_flux_t<double, double>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st);
-  else launch_flux_t<float, float>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st);
+                 hipStream_t st, hipEvent_t* ev) {
+  if (prec == 0) launch_flux_t<double, double>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st, ev);
+  else launch_flux_t<float, float>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st, ev);
 }
 
 void launch_moments(const Dev& g, int prec, const void* h, const void* b, double* W, double* q, hipStream_t st) {

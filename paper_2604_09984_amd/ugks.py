@@ -60,6 +60,7 @@ def lib():
         L.ugks_begin_step.argtypes = [vp, d, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ugks_step.argtypes = [vp, d, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ugks_timesteps.argtypes = [vp, C.POINTER(d), C.POINTER(d)]
+        L.ugks_step_profile.argtypes = [vp, d, i32, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(d), vp]
         _lib = L
     return _lib
 
@@ -68,7 +69,7 @@ def exported_symbols():
     return ["ugks_create", "ugks_destroy", "ugks_sizes", "ugks_set_poses", "ugks_set_types",
             "ugks_get_types", "ugks_set_overset", "overset_assemble", "ugks_maxwellian",
             "ugks_moments", "ugks_heatflux", "ugks_flux", "overset_interp", "ugks_begin_step", "ugks_step",
-            "ugks_timesteps", "ugks_last_error"]
+            "ugks_timesteps", "ugks_step_profile", "ugks_last_error"]
 
 
 def _check(rc):
@@ -219,6 +220,16 @@ class Solver:
         _check(lib().ugks_step(self.ctx, float(dt), int(n_inner), _p(h), _p(b), _p(W), _p(Wn), _p(q), _p(Sh),
                                _p(Sb), _p(Fn), _p(resid), self._stream(stream)))
         return resid
+
+    STAGES = ["interp", "gradW_wall", "face_eq", "flux", "macro_lusgs", "cell_rec", "micro_lusgs", "step7"]
+
+    def step_profile(self, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, stream=None):
+        """Run n_inner pseudo-iterations with stage timing; returns
+        {stage: mean ms per pseudo-iteration} (synchronous)."""
+        ms = (C.c_double * 8)()
+        _check(lib().ugks_step_profile(self.ctx, float(dt), int(n_inner), _p(h), _p(b), _p(W), _p(Wn), _p(q),
+                                       _p(Sh), _p(Sb), _p(Fn), ms, self._stream(stream)))
+        return dict(zip(self.STAGES, list(ms)))
 
     # ------------------------------------------------------------- driver
     def init_state(self):

@@ -263,10 +263,14 @@ def sod_1d(ncell: int = 200, nv: int = 101, kn: float = 1e-3, dt: float = 1.5e-3
 
 def cylinder(ni: int = 128, nj: int = 64, nvx: int = 64, vmax: float = 15.0, kn: float = 0.01,
              mach: float = 5.0, r_out: float = 8.0, ratio: float = 1.06,
-             n_inner: int = 10, n_phys: int = 50, dt_over_dts: float = 20.0) -> Case:
+             n_inner: int = 10, n_phys: int = 50, dt_over_dts: float = 20.0,
+             start: str = "potential") -> Case:
     """Ma 5 flow over a stationary cylinder (diameter 1): O-mesh ni x nj
     (periodic around, geometric radial spacing to r_out), isothermal wall at
-    the free-stream temperature, far field outside, hard-sphere gas."""
+    the free-stream temperature, far field outside, hard-sphere gas.
+    start = "potential": the initial velocity is the incompressible potential
+    flow around the cylinder (no flow through the wall) at the free-stream
+    density and temperature; "uniform": an impulsive uniform start."""
     radii = geometric_radii(0.5, r_out, nj, ratio)
     blk = o_block(ni, nj, radii, bc=(PERIODIC, PERIODIC, WALL, FARFIELD),
                   rtw=(0.5, 0.5, 0.5, 0.5), body=True)
@@ -278,6 +282,13 @@ def cylinder(ni: int = 128, nj: int = 64, nvx: int = 64, vmax: float = 15.0, kn:
                 (-vmax, vmax, -vmax, vmax), winf, [blk],
                 np.tile(winf, (ni * nj, 1)), dt_over_dts=dt_over_dts,
                 n_inner=n_inner, n_phys=n_phys)
+    if start == "potential" and mach > 0:
+        xc = case.node_centres()
+        r2 = np.sum(xc ** 2, 1)
+        a2 = 0.25
+        ux = u * (1.0 - a2 * (xc[:, 0] ** 2 - xc[:, 1] ** 2) / r2 ** 2)
+        uy = u * (-a2 * 2.0 * xc[:, 0] * xc[:, 1] / r2 ** 2)
+        case.w_init = cons(2, np.ones(len(xc)), np.stack([ux, uy], 1), np.full(len(xc), rt))
     return case
 
 
