@@ -147,6 +147,16 @@ static void prim(const or_case* c, const double* W, double* rho, double* u, doub
   *lam = (double)(d + c->nxi) * W[0] / (4.0 * e);
 }
 
+/* positive density and internal energy */
+static int physical(const or_case* c, const double* W) {
+  int d = c->dim;
+  if (!(W[0] > 0.0)) return 0;
+  double ke = 0.0;
+  for (int i = 0; i < d; i++) ke += W[1 + i] * W[1 + i];
+  double e = W[d + 1] - 0.5 * ke / W[0];
+  return e > 0.0;
+}
+
 /* collision time tau = mu/p, mu = mu_ref (RT/RT_ref)^omega; 1/tau returned */
 static double inv_tau(const or_case* c, double rho, double lam) {
   if (c->mu_ref <= 0.0) return 0.0;
@@ -941,6 +951,11 @@ static void face_record(const flux_ctx* X, int f) {
     int slot = 2 * F->dir + ((F->L >= 0) ? 1 : 0);
     double Win[4], dx = c->cdx[8 * cell + 2 * slot], dy = c->cdx[8 * cell + 2 * slot + 1];
     for (int m = 0; m < nw; m++) Win[m] = X->W[(size_t)cell * nw + m] + gw[m] * dx + gw[nw + m] * dy;
+    /* Reading (the paper is silent on positivity): an extrapolated state
+       with non-positive density or internal energy is replaced by the cell
+       state. */
+    if (!physical(c, Win))
+      for (int m = 0; m < nw; m++) Win[m] = X->W[(size_t)cell * nw + m];
     prim(c, Win, &R->rho, R->u, &R->lam);
     R->q[0] = X->q[(size_t)cell * d];
     R->q[1] = (d == 2) ? X->q[(size_t)cell * d + 1] : 0.0;
@@ -1322,6 +1337,11 @@ void or_macro_lusgs(const or_case* c, double dt, const double* dtp, const double
       dW[n * nw + m] = dWs[n * nw + m] - acc[m] / (4.0 * c->vol[n] * Dg[n]);
   }
   for (size_t i = 0; i < NW; i++) Wp[i] = W[i] + dW[i];
+  /* Reading (the paper is silent on positivity): a predictor with
+     non-positive density or internal energy keeps the current state. */
+  for (int n = 0; n < c->ncell; n++)
+    if (c->type[n] == OR_FIELD && !physical(c, Wp + (size_t)n * nw))
+      for (int m = 0; m < nw; m++) Wp[(size_t)n * nw + m] = W[(size_t)n * nw + m];
   free(R); free(Dg); free(dWs); free(dW);
 }
 

@@ -60,7 +60,7 @@ struct ugks_ctx {
   // host geometry
   std::vector<double> xn, yn;  // current nodes, per block
   std::vector<size_t> node0;
-  std::vector<double> vol, G, cdx, dtp, fgeo;
+  std::vector<double> vol, G, cdx, dtp, fgeo, mgeo;
   std::vector<int> nb, cf, fcell;
   std::vector<int8_t> type, fact;
   std::vector<int> cblk, ci, cj;
@@ -69,7 +69,8 @@ struct ugks_ctx {
   Dev dev{};
   void *d_vx = nullptr, *d_vy = nullptr, *d_wk = nullptr, *d_vol = nullptr, *d_G = nullptr, *d_cdx = nullptr,
        *d_dtp = nullptr, *d_type = nullptr, *d_nb = nullptr, *d_cf = nullptr, *d_fcell = nullptr,
-       *d_fgeo = nullptr, *d_fact = nullptr, *d_finf_h = nullptr, *d_finf_b = nullptr, *d_binfo = nullptr;
+       *d_fgeo = nullptr, *d_fact = nullptr, *d_finf_h = nullptr, *d_finf_b = nullptr, *d_binfo = nullptr,
+       *d_mgeo = nullptr;
   // scratch
   void *s_gW = nullptr, *s_rec = nullptr, *s_gam = nullptr, *s_R = nullptr, *s_Dg = nullptr, *s_dWs = nullptr,
        *s_dW = nullptr, *s_Wp = nullptr, *s_rpart = nullptr, *s_crec = nullptr, *s_mrec = nullptr,
@@ -345,6 +346,20 @@ void compute_geometry(ugks_ctx* c) {
     if (c->type[n] == UGKS_FIELD) dts = std::min(dts, c->cfl_s * c->vol[n] / s);
   }
   c->dts = dts;
+  // micro sweep face coefficients: S/(2|Omega|) (v - U).n_out = A vx + B vy - C
+  c->mgeo.assign(12 * (size_t)c->ncell, 0.0);
+  for (int n = 0; n < c->ncell; ++n)
+    for (int s = 0; s < 4; ++s) {
+      int f = c->cf[4 * (size_t)n + s];
+      if (f < 0) continue;
+      const double* g = &c->fgeo[8 * (size_t)f];
+      double sg = (s & 1) ? 1.0 : -1.0;
+      double coef = g[2] / (2.0 * c->vol[n]);
+      double* m = &c->mgeo[12 * (size_t)n + 3 * s];
+      m[0] = coef * sg * g[0];
+      m[1] = coef * sg * g[1];
+      m[2] = coef * sg * (g[3] * g[0] + g[4] * g[1]);
+    }
 }
 
 int upload_geometry(ugks_ctx* c) {
@@ -354,6 +369,7 @@ int upload_geometry(ugks_ctx* c) {
   if ((rc = upload(c->d_cdx, c->cdx))) return rc;
   if ((rc = upload(c->d_dtp, c->dtp))) return rc;
   if ((rc = upload(c->d_fgeo, c->fgeo))) return rc;
+  if ((rc = upload(c->d_mgeo, c->mgeo))) return rc;
   return UGKS_OK;
 }
 
@@ -376,11 +392,12 @@ void fill_dev(ugks_ctx* c) {
   g.dtp = (const double*)c->d_dtp; g.type = (const int8_t*)c->d_type; g.nb = (const int*)c->d_nb;
   g.cf = (const int*)c->d_cf; g.fcell = (const int*)c->d_fcell; g.fgeo = (const double*)c->d_fgeo;
   g.fact = (const int8_t*)c->d_fact; g.finf_h = c->d_finf_h; g.finf_b = c->d_finf_b;
+  g.mgeo = (const double*)c->d_mgeo;
 }
 
 void free_all(ugks_ctx* c) {
   void* ps[] = {c->d_vx, c->d_vy, c->d_wk, c->d_vol, c->d_G, c->d_cdx, c->d_dtp, c->d_type, c->d_nb, c->d_cf,
-                c->d_fcell, c->d_fgeo, c->d_fact, c->d_finf_h, c->d_finf_b, c->d_binfo, c->s_gW, c->s_rec,
+                c->d_fcell, c->d_fgeo, c->d_fact, c->d_finf_h, c->d_finf_b, c->d_binfo, c->d_mgeo, c->s_gW, c->s_rec,
                 c->s_gam, c->s_R, c->s_Dg, c->s_dWs, c->s_dW, c->s_Wp, c->s_rpart, c->s_crec, c->s_mrec,
                 c->s_Dh, c->s_Db, c->s_F, c->d_rec, c->d_ptr, c->d_don, c->d_w};
   for (void* p : ps)
@@ -465,9 +482,11 @@ int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
     if (B.bc[2] == UGKS_BC_PERIODIC) c->any_pj = 1;
     c->blk.push_back(std::move(B));
   }
-  if (c->dim == 2 && c->max_nj > 64 * kMaxRowsMicroHost) { delete c; return fail(UGKS_E_UNSUPPORTED, "nj above 256"); }
-  if (c->any_pj && c->max_ni > 64) { delete c; return fail(UGKS_E_UNSUPPORTED, "periodic j needs ni <= 64"); }
-  if (c->max_nj > 64 * 8) { delete c; return fail(UGKS_E_UNSUPPORTED, "nj above 512"); }
+  if (c->dim == 2 && c->max_nj > 512) { delete c; return fail(UGKS_E_UNSUPPORTED, "nj above 512"); }
+  if (c->any_pj && c->max_ni > 256) { delete c; return fail(UGKS_E_UNSUPPORTED, "periodic j needs ni <= 256"); }
+  if (micro_lds(c->dim, c->max_ni, c->max_nj, c->any_pj) > 160 * 1024) {
+    delete c; return fail(UGKS_E_UNSUPPORTED, "micro sweep LDS above 160 KiB");
+  }
   c->ncell = ncell;
   c->xn.assign(nnode, 0.0);
   c->yn.assign(nnode, 0.0);
@@ -723,7 +742,7 @@ int ugks_begin_step(ugks_ctx* c, double dt, void* h, void* b, double* W, double*
   HIPCHK(hipMemsetAsync(Fn, 0, sizeof(double) * c->nw * (size_t)c->nface, st));
   // the level-n divergence is staged in Sh, Sb
   launch_flux(c->dev, c->prec, c->dts, h, b, W, q, (double*)c->s_gW, (double*)c->s_rec, Sh, Sb, Fn, nullptr, st);
-  launch_cellrec(c->dev, W, q, nullptr, (double*)c->s_crec, st);
+  launch_cellrec(c->dev, dt, W, q, nullptr, (double*)c->s_crec, st);
   launch_source(c->dev, c->prec, dt, h, b, (const double*)c->s_crec, Sh, Sb, st);
   HIPCHK(hipGetLastError());
   return UGKS_OK;
@@ -748,11 +767,12 @@ static int run_inner(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, 
     launch_flux(g, c->prec, c->dts, h, b, W, q, (double*)c->s_gW, (double*)c->s_rec, c->s_Dh, c->s_Db, F,
                 nullptr, st, e ? e + 2 : nullptr);
     if (e) HIPCHK(hipEventRecord(e[4], st));
-    launch_macro(g, (const int*)c->d_binfo, dt, W, Wn, F, Fn, (double*)c->s_gam, (double*)c->s_R,
+    launch_macro(g, (const int*)c->d_binfo, c->max_ni, c->max_nj, c->any_pj, dt, W, Wn, F, Fn,
+                 (double*)c->s_gam, (double*)c->s_R,
                  (double*)c->s_Dg, (double*)c->s_dWs, (double*)c->s_dW, (double*)c->s_Wp, (double*)c->s_rpart,
                  resid ? resid + (size_t)s * c->nw : nullptr, st);
     if (e) HIPCHK(hipEventRecord(e[5], st));
-    launch_cellrec(g, (const double*)c->s_Wp, nullptr, (const double*)c->s_mrec, (double*)c->s_crec, st);
+    launch_cellrec(g, dt, (const double*)c->s_Wp, nullptr, (const double*)c->s_mrec, (double*)c->s_crec, st);
     if (e) HIPCHK(hipEventRecord(e[6], st));
     launch_micro(g, c->prec, (const int*)c->d_binfo, c->max_ni, c->max_nj, c->any_pj, dt,
                  (const double*)c->s_crec, h, b, Sh, Sb, c->s_Dh, c->s_Db, st);

@@ -35,9 +35,11 @@ enum : int {
   NREC = 32
 };
 
-// per-cell equilibrium record (double): state used by the Shakhov source
+// per-cell record (double): state of the Shakhov source, the micro LU-SGS
+// diagonal base 1/dt' + 1/dt + 1/(2 tau) and, per slot s, the face
+// coefficients (A, B, C) with S/(2|Omega|) * w.n_out = A vx + B vy - C
 enum : int {
-  C_RHO = 0, C_UX, C_UY, C_LAM, C_QX, C_QY, C_HN, C_SH, C_ITAU, NCREC = 10
+  C_RHO = 0, C_UX, C_UY, C_LAM, C_QX, C_QY, C_HN, C_SH, C_ITAU, C_D0, C_GEO = 10, NCREC = 24
 };
 
 // per-cell moment record about a shift s: s(2), m0, m1(2), m2, P(3), m3(2)
@@ -64,6 +66,7 @@ struct Dev {
   const int8_t* fact;   // [nface] face adjacent to a field cell
   const void* finf_h;   // [nv] storage type
   const void* finf_b;
+  const double* mgeo;   // [ncell][12] per slot (A, B, C) of the micro sweep
 };
 
 // ------------------------------------------------------------------------
@@ -76,6 +79,13 @@ __device__ __host__ inline void prim_of(const Dev& g, const double* W, double& r
   uy = (g.dim == 2) ? W[2] / rho : 0.0;
   double e = W[g.dim + 1] - 0.5 * rho * (ux * ux + uy * uy);
   lam = 0.25 * (double)(g.dim + g.nxi) * rho / e;
+}
+
+// positive density and internal energy
+__device__ __host__ inline bool physical_state(int dim, const double* W) {
+  if (!(W[0] > 0.0)) return false;
+  double ke = W[1] * W[1] + ((dim == 2) ? W[2] * W[2] : 0.0);
+  return W[dim + 1] - 0.5 * ke / W[0] > 0.0;
 }
 
 __device__ inline double inv_tau_of(const Dev& g, double rho, double lam) {

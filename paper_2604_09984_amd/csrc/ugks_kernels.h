@@ -4,7 +4,8 @@
 
 namespace ugks {
 
-constexpr int kMaxRowsMicroHost = 4;
+int micro_kc(int dim, int max_nj);
+size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj);
 
 void launch_flux(const Dev& g, int prec, double dts, const void* h, const void* b, const double* W,
                  const double* q, double* gW, double* rec, void* Dh, void* Db, double* F, double* wall,
@@ -13,15 +14,15 @@ void launch_moments(const Dev& g, int prec, const void* h, const void* b, double
 void launch_maxwellian(const Dev& g, int prec, const double* W, void* h, void* b, hipStream_t st);
 void launch_interp(const Dev& g, int prec, int nrec, const int* rec, const int* ptr, const int* don,
                    const double* w, void* h, void* b, double* W, double* q, hipStream_t st);
-void launch_cellrec(const Dev& g, const double* W, const double* q, const double* mrec, double* crec,
+void launch_cellrec(const Dev& g, double dt, const double* W, const double* q, const double* mrec, double* crec,
                     hipStream_t st);
 void launch_source(const Dev& g, int prec, double dt, const void* h, const void* b, const double* crec,
                    void* Sh, void* Sb, hipStream_t st);
 void launch_step7(const Dev& g, int prec, int mode, const void* h, const void* b, const double* crec,
                   const double* Wp, double* W, double* q, double* mrec, hipStream_t st);
-void launch_macro(const Dev& g, const int* binfo, double dt, const double* W, const double* Wn,
-                  const double* F, const double* Fn, double* gam, double* R, double* Dg, double* dWs,
-                  double* dW, double* Wp, double* rpart, double* resid, hipStream_t st);
+void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
+                  const double* W, const double* Wn, const double* F, const double* Fn, double* gam, double* R,
+                  double* Dg, double* dWs, double* dW, double* Wp, double* rpart, double* resid, hipStream_t st);
 void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
                   const double* crec, void* h, void* b, const void* Sh, const void* Sb, void* Dh, void* Db,
                   hipStream_t st);

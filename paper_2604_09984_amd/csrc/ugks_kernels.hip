@@ -18,51 +18,6 @@ __device__ __attribute__((noinline)) double wnorm(double vx, double vy, double u
   return (vx - ux) * nx + (vy - uy) * ny;
 }
 
-// limited slope per unit index along dir (van Leer; one-sided beside a wall;
-// zero beside a hole / fringe)
-template <class T>
-__device__ inline double index_slope(const Dev& g, const T* __restrict__ f, const T* __restrict__ finf,
-                                     int c, int dir, int k, double v0) {
-  int lo = g.nb[4 * c + 2 * dir], hi = g.nb[4 * c + 2 * dir + 1];
-  if (lo == kNbMiss || hi == kNbMiss) return 0.0;
-  auto val = [&](int code) -> double {
-    if (code >= 0) return (double)f[(size_t)code * g.nv + k];
-    if (code == kNbFar) return (double)finf[k];
-    return v0;  // copy ghost
-  };
-  if (lo == kNbWall && hi == kNbWall) return 0.0;
-  if (lo == kNbWall) return val(hi) - v0;
-  if (hi == kNbWall) return v0 - val(lo);
-  double s1 = v0 - val(lo), s2 = val(hi) - v0;
-  if (s1 * s2 <= 0.0) return 0.0;
-  return (s1 * fabs(s2) + fabs(s1) * s2) / (fabs(s1) + fabs(s2));
-}
-
-// reconstruction of cell c at the face in its slot: face value and gradient
-template <class T>
-__device__ inline void recon(const Dev& g, const T* __restrict__ f, const T* __restrict__ finf, int c,
-                             int slot, int k, double& val, double& gx, double& gy) {
-  double v0 = (double)f[(size_t)c * g.nv + k];
-  double si = index_slope(g, f, finf, c, 0, k, v0);
-  double sj = (g.dim == 2) ? index_slope(g, f, finf, c, 1, k, v0) : 0.0;
-  const double* G = g.G + 4 * c;
-  gx = G[0] * si + G[1] * sj;
-  gy = (g.dim == 2) ? G[2] * si + G[3] * sj : 0.0;
-  val = v0 + gx * g.cdx[8 * c + 2 * slot] + gy * g.cdx[8 * c + 2 * slot + 1];
-}
-
-// side data of face f seen from cell c in slot s: the other side
-template <class T>
-__device__ inline void other_side(const Dev& g, const T* __restrict__ f, const T* __restrict__ finf,
-                                  int c, int s, int o, int k, double& val, double& gx, double& gy) {
-  if (o >= 0) {
-    recon(g, f, finf, o, s ^ 1, k, val, gx, gy);
-  } else {
-    val = (o == kNbFar) ? (double)finf[k] : (double)f[(size_t)c * g.nv + k];
-    gx = gy = 0.0;
-  }
-}
-
 // interface distribution integrated over dt_s and divided by dt_s
 // (Eq. fullSolution with the coefficient integrals) for h (m = 0) and b
 // (m = 1), computed in type C
@@ -164,6 +119,9 @@ __global__ void k_wallprep(Dev g, double dts, const double* __restrict__ W, cons
   const double* gw = gW + (size_t)c * 8;
   double dx = g.cdx[8 * c + 2 * dir], dy = g.cdx[8 * c + 2 * dir + 1];
   for (int m = 0; m < nw; ++m) Win[m] = W[(size_t)c * nw + m] + gw[m] * dx + gw[nw + m] * dy;
+  // a non-physical extrapolation falls back to the cell state
+  if (!physical_state(g.dim, Win))
+    for (int m = 0; m < nw; ++m) Win[m] = W[(size_t)c * nw + m];
   double rho, ux, uy, lam;
   prim_of(g, Win, rho, ux, uy, lam);
   r[R_RHO] = rho; r[R_UX] = ux; r[R_UY] = uy; r[R_LAM] = lam;
@@ -184,125 +142,203 @@ __global__ void k_wallprep(Dev g, double dts, const double* __restrict__ W, cons
 }
 
 // ------------------------------------------------------------------------
-// face equilibrium: one wavefront per cell, lanes over velocities; the cell
-// reduces the faces it owns (its high faces, and low faces on a block
-// boundary) and writes their records
+// face equilibrium and flux: one wavefront per cell, lanes over velocities.
+// The cell index is wave-uniform, so topology, geometry and face records
+// come through scalar loads; each neighbour value is loaded once per
+// velocity and shared by the cell's own reconstruction and the neighbours'.
 // ------------------------------------------------------------------------
-__device__ inline bool owns(const Dev& g, int c, int s, int f) {
+__device__ __forceinline__ double exact_wn(double vx, double vy, double ux, double uy, double nx, double ny) {
+#pragma clang fp contract(off)
+  double a = (vx - ux) * nx;
+  double b = (vy - uy) * ny;
+  return a + b;
+}
+
+__device__ __forceinline__ double lim(int lo, int hi, double vlo, double v0, double vhi) {
+  if (lo == kNbMiss || hi == kNbMiss) return 0.0;
+  if (lo == kNbWall && hi == kNbWall) return 0.0;
+  if (lo == kNbWall) return vhi - v0;
+  if (hi == kNbWall) return v0 - vlo;
+  double s1 = v0 - vlo, s2 = vhi - v0;
+  double vl = (s1 * fabs(s2) + fabs(s1) * s2) / (fabs(s1) + fabs(s2));
+  return (s1 * s2 <= 0.0) ? 0.0 : vl;
+}
+
+template <class T>
+__device__ __forceinline__ double fetch(const T* __restrict__ f, const T* __restrict__ finf, int code, double self,
+                                        int nv, int k) {
+  if (code >= 0) return (double)f[(size_t)code * nv + k];
+  if (code == kNbFar) return (double)finf[k];
+  return self;
+}
+
+__device__ __forceinline__ bool owns(const Dev& g, int c, int s, int f) {
   if (f < 0 || !g.fact[f]) return false;
   int other = g.fcell[2 * f + ((s & 1) ? 1 : 0)];
   return (s & 1) || other < 0;
 }
 
-template <class T>
+// per-velocity data of one distribution component at a cell and its
+// neighbours: own value, neighbour values and own physical gradient
+template <int D>
+struct Local {
+  double v0, nbv[2 * D], gx, gy;
+};
+
+template <int D, class T>
+__device__ __forceinline__ void local_data(const Dev& g, const T* __restrict__ f, const T* __restrict__ finf,
+                                           int c, const int* nbc, const double* G, int k, Local<D>& L) {
+  L.v0 = (double)f[(size_t)c * g.nv + k];
+#pragma unroll
+  for (int s = 0; s < 2 * D; ++s) L.nbv[s] = fetch(f, finf, nbc[s], L.v0, g.nv, k);
+  double si = lim(nbc[0], nbc[1], L.nbv[0], L.v0, L.nbv[1]);
+  double sj = (D == 2) ? lim(nbc[2], nbc[3], L.nbv[2], L.v0, L.nbv[3]) : 0.0;
+  L.gx = G[0] * si + G[1] * sj;
+  L.gy = (D == 2) ? G[2] * si + G[3] * sj : 0.0;
+}
+
+// reconstruction of the neighbour o across slot s of cell c (o's own slot is
+// s ^ 1; its neighbour across that face is c with value vc)
+template <int D, class T>
+__device__ __forceinline__ void neighbour_recon(const Dev& g, const T* __restrict__ f, const T* __restrict__ finf,
+                                                int o, int s, double vo, double vc, int k, double& val,
+                                                double& gx, double& gy) {
+  const int dir = s >> 1;
+  const int* nbo = g.nb + 4 * o;
+  int lo = nbo[2 * dir], hi = nbo[2 * dir + 1];
+  double vlo, vhi;
+  if (s & 1) { vlo = vc; vhi = fetch(f, finf, hi, vo, g.nv, k); }  // o on the high side of c
+  else { vhi = vc; vlo = fetch(f, finf, lo, vo, g.nv, k); }
+  double sd = lim(lo, hi, vlo, vo, vhi);
+  double st = 0.0;
+  if (D == 2) {
+    int t = 1 - dir;
+    int tl = nbo[2 * t], th = nbo[2 * t + 1];
+    st = lim(tl, th, fetch(f, finf, tl, vo, g.nv, k), vo, fetch(f, finf, th, vo, g.nv, k));
+  }
+  double si = (dir == 0) ? sd : st, sj = (dir == 0) ? st : sd;
+  const double* G = g.G + 4 * o;
+  gx = G[0] * si + G[1] * sj;
+  gy = (D == 2) ? G[2] * si + G[3] * sj : 0.0;
+  const double* cd = g.cdx + 8 * o + 2 * (s ^ 1);
+  val = vo + gx * cd[0] + gy * cd[1];
+}
+
+template <int D, class T>
 __global__ __launch_bounds__(256) void k_face_eq(Dev g, double dts, const T* __restrict__ h,
                                                  const T* __restrict__ b, const double* __restrict__ W,
                                                  const double* __restrict__ gW, double* __restrict__ rec) {
-  int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-  int lane = threadIdx.x & 63;
+  const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
   if (c >= g.ncell || g.type[c] == 0) return;
   const T* hinf = (const T*)g.finf_h;
   const T* binf = (const T*)g.finf_b;
-  int nw = g.nw;
-  for (int s = 0; s < 2 * g.dim; ++s) {
-    int f = g.cf[4 * c + s];
+  const int nw = D + 2;
+  int nbc[2 * D];
+#pragma unroll
+  for (int s = 0; s < 2 * D; ++s) nbc[s] = g.nb[4 * c + s];
+  const double* G = g.G + 4 * c;
+#pragma unroll
+  for (int s = 0; s < 2 * D; ++s) {
+    const int f = g.cf[4 * c + s];
     if (!owns(g, c, s, f)) continue;
-    int o = g.fcell[2 * f + ((s & 1) ? 1 : 0)];
+    const int o = g.fcell[2 * f + ((s & 1) ? 1 : 0)];
     const double* fg = g.fgeo + (size_t)f * 8;
-    double nx = fg[0], ny = fg[1], ufx = fg[3], ufy = fg[4];
+    const double nx = fg[0], ny = fg[1], ufx = fg[3], ufy = fg[4];
+    const double cdx = g.cdx[8 * c + 2 * s], cdy = g.cdx[8 * c + 2 * s + 1];
     double* r = rec + (size_t)f * NREC;
     if (o == kNbWall) {
       // wall density from zero net mass flux (Eq. maxWalldes)
       if (g.type[c] != 1) continue;
       FaceEq<double> e;
       e.load(r);
-      double sg = r[R_SGN], nwx = sg * nx, nwy = sg * ny;
-      double lw = r[R_LAMW], hwn = r[R_HWN], vwx = r[R_VWX], vwy = r[R_VWY];
+      const double sg = r[R_SGN], nwx = sg * nx, nwy = sg * ny;
+      const double lw = r[R_LAMW], hwn = r[R_HWN], vwx = r[R_VWX], vwy = r[R_VWY];
       double num = 0.0, den = 0.0;
       for (int k = lane; k < g.nv; k += 64) {
-        double vx = g.vx[k], vy = g.vy[k];
-        double wn = wnorm(vx, vy, ufx, ufy, nwx, nwy);
-        if (wn > 0.0) {
-          double fh, ghx, ghy, fb, gbx, gby;
-          recon(g, h, hinf, c, s, k, fh, ghx, ghy);
-          recon(g, b, binf, c, s, k, fb, gbx, gby);
-          double Ih, Ib;
-          interface_avg<double>(e, g.dim, g.nxi, vx, vy, vx - ufx, vy - ufy, fh, fb, ghx, ghy, gbx, gby, Ih, Ib);
-          num += g.wk[k] * wn * Ih;
-        } else if (wn < 0.0) {
-          double cx = vx - vwx, cy = (g.dim == 2) ? vy - vwy : 0.0;
-          den += g.wk[k] * wn * hwn * exp(-lw * (cx * cx + cy * cy));
-        }
+        const double vx = g.vx[k], vy = g.vy[k];
+        const double wn = exact_wn(vx, vy, ufx, ufy, nwx, nwy);
+        Local<D> Lh, Lb;
+        local_data<D>(g, h, hinf, c, nbc, G, k, Lh);
+        local_data<D>(g, b, binf, c, nbc, G, k, Lb);
+        double Ih, Ib;
+        interface_avg<double>(e, D, 3 - D, vx, vy, vx - ufx, vy - ufy, Lh.v0 + Lh.gx * cdx + Lh.gy * cdy,
+                              Lb.v0 + Lb.gx * cdx + Lb.gy * cdy, Lh.gx, Lh.gy, Lb.gx, Lb.gy, Ih, Ib);
+        const double cx = vx - vwx, cy = (D == 2) ? vy - vwy : 0.0;
+        const double hw = hwn * exp(-lw * (cx * cx + cy * cy));
+        num += (wn > 0.0) ? g.wk[k] * wn * Ih : 0.0;
+        den += (wn < 0.0) ? g.wk[k] * wn * hw : 0.0;
       }
       num = wave_sum(num);
       den = wave_sum(den);
       if (lane == 0) r[R_RHOW] = -num / den;
       continue;
     }
-    // moments of the upwind interface data about the shift s = mean velocity
-    int Lc = (s & 1) ? c : o, Rc = (s & 1) ? o : c;
+    // moments of the upwind interface data about the mean velocity of the sides
+    const int Lc = (s & 1) ? c : o, Rc = (s & 1) ? o : c;
     double sx, sy;
     {
-      double r1, u1, v1, l1, r2, u2, v2, l2;
-      auto Wof = [&](int code, double* out) {
-        if (code >= 0) for (int m = 0; m < nw; ++m) out[m] = W[(size_t)code * nw + m];
-        else if (code == kNbFar) for (int m = 0; m < nw; ++m) out[m] = g.winf[m];
-        else for (int m = 0; m < nw; ++m) out[m] = W[(size_t)c * nw + m];
-      };
       double WL[4], WR[4];
-      Wof(Lc, WL);
-      Wof(Rc, WR);
-      prim_of(g, WL, r1, u1, v1, l1);
-      prim_of(g, WR, r2, u2, v2, l2);
-      sx = 0.5 * (u1 + u2);
-      sy = 0.5 * (v1 + v2);
+      for (int m = 0; m < nw; ++m) {
+        WL[m] = (Lc >= 0) ? W[(size_t)Lc * nw + m] : (Lc == kNbFar ? g.winf[m] : W[(size_t)c * nw + m]);
+        WR[m] = (Rc >= 0) ? W[(size_t)Rc * nw + m] : (Rc == kNbFar ? g.winf[m] : W[(size_t)c * nw + m]);
+      }
+      sx = 0.5 * (WL[1] / WL[0] + WR[1] / WR[0]);
+      sy = (D == 2) ? 0.5 * (WL[2] / WL[0] + WR[2] / WR[0]) : 0.0;
     }
     double m0 = 0, m1x = 0, m1y = 0, m2 = 0, pxx = 0, pxy = 0, pyy = 0, m3x = 0, m3y = 0;
     for (int k = lane; k < g.nv; k += 64) {
-      double vx = g.vx[k], vy = g.vy[k];
-      double wn = wnorm(vx, vy, ufx, ufy, nx, ny);
-      double hc, bc, ho, bo, t0, t1;
-      recon(g, h, hinf, c, s, k, hc, t0, t1);
-      recon(g, b, binf, c, s, k, bc, t0, t1);
-      other_side(g, h, hinf, c, s, o, k, ho, t0, t1);
-      other_side(g, b, binf, c, s, o, k, bo, t0, t1);
-      double hl = (s & 1) ? hc : ho, hr = (s & 1) ? ho : hc;
-      double bl = (s & 1) ? bc : bo, br = (s & 1) ? bo : bc;
-      double fh, fb;
-      if (wn > 0.0) { fh = hl; fb = bl; }
-      else if (wn < 0.0) { fh = hr; fb = br; }
-      else { fh = 0.5 * (hl + hr); fb = 0.5 * (bl + br); }
-      double w = g.wk[k];
-      double cx = vx - sx, cy = (g.dim == 2) ? vy - sy : 0.0;
-      double c2 = cx * cx + cy * cy;
-      double e = c2 * fh + fb;
-      m0 += w * fh;
-      m1x += w * cx * fh;
-      m1y += w * cy * fh;
-      m2 += w * e;
-      pxx += w * cx * cx * fh;
-      pxy += w * cx * cy * fh;
-      pyy += w * cy * cy * fh;
-      m3x += w * cx * e;
-      m3y += w * cy * e;
+      const double vx = g.vx[k], vy = g.vy[k];
+      const double wn = exact_wn(vx, vy, ufx, ufy, nx, ny);
+      Local<D> Lh, Lb;
+      local_data<D>(g, h, hinf, c, nbc, G, k, Lh);
+      local_data<D>(g, b, binf, c, nbc, G, k, Lb);
+      const double hc = Lh.v0 + Lh.gx * cdx + Lh.gy * cdy;
+      const double bc = Lb.v0 + Lb.gx * cdx + Lb.gy * cdy;
+      double ho, bo, t0, t1;
+      if (o >= 0) {
+        neighbour_recon<D>(g, h, hinf, o, s, Lh.nbv[s], Lh.v0, k, ho, t0, t1);
+        neighbour_recon<D>(g, b, binf, o, s, Lb.nbv[s], Lb.v0, k, bo, t0, t1);
+      } else {
+        ho = (o == kNbFar) ? (double)hinf[k] : Lh.v0;
+        bo = (o == kNbFar) ? (double)binf[k] : Lb.v0;
+      }
+      const double hl = (s & 1) ? hc : ho, hr = (s & 1) ? ho : hc;
+      const double bl = (s & 1) ? bc : bo, br = (s & 1) ? bo : bc;
+      double fh = (wn > 0.0) ? hl : ((wn < 0.0) ? hr : 0.5 * (hl + hr));
+      double fb = (wn > 0.0) ? bl : ((wn < 0.0) ? br : 0.5 * (bl + br));
+      const double w = g.wk[k];
+      const double cx = vx - sx, cy = (D == 2) ? vy - sy : 0.0;
+      const double e = (cx * cx + cy * cy) * fh + fb;
+      const double wh = w * fh, we = w * e;
+      m0 += wh;
+      m1x += wh * cx;
+      m2 += we;
+      pxx += wh * cx * cx;
+      m3x += we * cx;
+      if (D == 2) {
+        m1y += wh * cy;
+        pxy += wh * cx * cy;
+        pyy += wh * cy * cy;
+        m3y += we * cy;
+      }
     }
-    m0 = wave_sum(m0); m1x = wave_sum(m1x); m1y = wave_sum(m1y); m2 = wave_sum(m2);
-    pxx = wave_sum(pxx); pxy = wave_sum(pxy); pyy = wave_sum(pyy);
-    m3x = wave_sum(m3x); m3y = wave_sum(m3y);
+    m0 = wave_sum(m0); m1x = wave_sum(m1x); m2 = wave_sum(m2); pxx = wave_sum(pxx); m3x = wave_sum(m3x);
+    if (D == 2) { m1y = wave_sum(m1y); pxy = wave_sum(pxy); pyy = wave_sum(pyy); m3y = wave_sum(m3y); }
     if (lane != 0) continue;
     // face state from the shifted moments
-    double rho = m0;
-    double dx = m1x / m0, dy = m1y / m0;
-    double ux = sx + dx, uy = sy + dy;
-    double eint = 0.5 * (m2 - (m1x * m1x + m1y * m1y) / m0);
-    double lam = 0.25 * (double)(g.dim + g.nxi) * rho / eint;
+    const double rho = m0;
+    const double dx = m1x / m0, dy = m1y / m0;
+    const double ux = sx + dx, uy = sy + dy;
+    const double eint = 0.5 * (m2 - (m1x * m1x + m1y * m1y) / m0);
+    const double lam = 0.25 * (double)(D + 3 - D) * rho / eint;
     // heat flux about the face velocity: 2q = m3 - 2 P d - d m2 + 2 m0 |d|^2 d
-    double dd = dx * dx + dy * dy;
+    const double dd = dx * dx + dy * dy;
     double qx = 0.5 * (m3x - 2.0 * (pxx * dx + pxy * dy) - dx * m2 + 2.0 * m0 * dd * dx);
     double qy = 0.5 * (m3y - 2.0 * (pxy * dx + pyy * dy) - dy * m2 + 2.0 * m0 * dd * dy);
-    if (g.dim == 1) qy = 0.0;
+    if (D == 1) qy = 0.0;
     r[R_RHO] = rho; r[R_UX] = ux; r[R_UY] = uy; r[R_LAM] = lam; r[R_QX] = qx; r[R_QY] = qy;
-    r[R_HN] = rho * pow(lam / kPi, 0.5 * g.dim);
+    r[R_HN] = rho * pow(lam / kPi, 0.5 * D);
     r[R_SH] = 4.0 * (1.0 - g.pr) * lam * lam / (5.0 * rho);
     double dW[8];
     for (int m = 0; m < 2 * nw; ++m) {
@@ -310,7 +346,7 @@ __global__ __launch_bounds__(256) void k_face_eq(Dev g, double dts, const T* __r
       double gr = (Rc >= 0) ? gW[(size_t)Rc * 8 + m] : 0.0;
       dW[m] = 0.5 * (gl + gr);
     }
-    expansion(g.dim, rho, ux, uy, lam, ufx, ufy, dW, r + R_AX, r + R_AY, r + R_AT);
+    expansion(D, rho, ux, uy, lam, ufx, ufy, dW, r + R_AX, r + R_AY, r + R_AT);
     double tq[5];
     time_integrals(dts, inv_tau_of(g, rho, lam), tq);
     for (int m = 0; m < 5; ++m) r[R_T1 + m] = tq[m] / dts;
@@ -318,92 +354,106 @@ __global__ __launch_bounds__(256) void k_face_eq(Dev g, double dts, const T* __r
   }
 }
 
-// ------------------------------------------------------------------------
-// flux: one wavefront per cell; divergence D of field cells, macro flux of
-// the faces the cell owns (wall faces also give the wall output)
-// ------------------------------------------------------------------------
-template <class T, class C>
+// flux: divergence D of field cells, macro flux of the faces the cell owns
+// (wall faces also give the wall output)
+template <int D, class T, class C>
 __global__ __launch_bounds__(256) void k_flux(Dev g, const T* __restrict__ h, const T* __restrict__ b,
                                               const double* __restrict__ rec, T* __restrict__ Dh,
                                               T* __restrict__ Db, double* __restrict__ F,
                                               double* __restrict__ wall) {
-  int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-  int lane = threadIdx.x & 63;
+  const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
   if (c >= g.ncell || g.type[c] == 0) return;
   const T* hinf = (const T*)g.finf_h;
   const T* binf = (const T*)g.finf_b;
-  bool field = (g.type[c] == 1);
-  double ivol = 1.0 / g.vol[c];
-  int nw = g.nw;
-  double acc[4][4];
-  for (int s = 0; s < 4; ++s) for (int m = 0; m < 4; ++m) acc[s][m] = 0.0;
+  const bool field = (g.type[c] == 1);
+  const double ivol = 1.0 / g.vol[c];
+  const int nw = D + 2;
+  int nbc[2 * D], fc[2 * D], oc[2 * D];
+  bool act[2 * D], own[2 * D];
+#pragma unroll
+  for (int s = 0; s < 2 * D; ++s) {
+    nbc[s] = g.nb[4 * c + s];
+    fc[s] = g.cf[4 * c + s];
+    own[s] = owns(g, c, s, fc[s]);
+    act[s] = fc[s] >= 0 && g.fact[fc[s]] && (field || own[s]);
+    oc[s] = act[s] ? g.fcell[2 * fc[s] + ((s & 1) ? 1 : 0)] : kNbMiss;
+  }
+  const double* G = g.G + 4 * c;
+  double acc[2 * D][4];
+#pragma unroll
+  for (int s = 0; s < 2 * D; ++s)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc[s][m] = 0.0;
   for (int k0 = 0; k0 < g.nv; k0 += 64) {
-    int k = k0 + lane;
-    bool kin = k < g.nv;
-    int kk = kin ? k : 0;
-    double vx = g.vx[kk], vy = g.vy[kk], wk = kin ? g.wk[kk] : 0.0;
-    C dh = 0, db = 0;
-    for (int s = 0; s < 2 * g.dim; ++s) {
-      int f = g.cf[4 * c + s];
-      if (f < 0 || !g.fact[f]) continue;
-      bool own = owns(g, c, s, f);
-      if (!field && !own) continue;
+    const int k = k0 + lane;
+    const bool kin = k < g.nv;
+    const int kk = kin ? k : g.nv - 1;
+    const double vx = g.vx[kk], vy = g.vy[kk], wk = kin ? g.wk[kk] : 0.0;
+    Local<D> Lh, Lb;
+    local_data<D>(g, h, hinf, c, nbc, G, kk, Lh);
+    local_data<D>(g, b, binf, c, nbc, G, kk, Lb);
+    double dh = 0.0, db = 0.0;
+#pragma unroll
+    for (int s = 0; s < 2 * D; ++s) {
+      if (!act[s]) continue;
+      const int f = fc[s], o = oc[s];
       const double* r = rec + (size_t)f * NREC;
       const double* fg = g.fgeo + (size_t)f * 8;
-      int o = g.fcell[2 * f + ((s & 1) ? 1 : 0)];
-      double sig = (s & 1) ? 1.0 : -1.0;  // +1 if the face normal points out of c
-      double fh = 0.0, fb = 0.0;           // flux along the face normal
+      const double cdx = g.cdx[8 * c + 2 * s], cdy = g.cdx[8 * c + 2 * s + 1];
+      double fh, fb;  // flux along the face normal
       if (o == kNbWall) {
-        double sg = r[R_SGN];
-        double wn = wnorm(vx, vy, fg[3], fg[4], sg * fg[0], sg * fg[1]);
-        if (wn > 0.0) {
-          double vh, vb, ghx, ghy, gbx, gby;
-          recon(g, h, hinf, c, s, kk, vh, ghx, ghy);
-          recon(g, b, binf, c, s, kk, vb, gbx, gby);
-          FaceEq<C> e;
-          e.load(r);
-          C Ih, Ib;
-          interface_avg<C>(e, g.dim, g.nxi, (C)vx, (C)vy, (C)(vx - fg[3]), (C)(vy - fg[4]), (C)vh, (C)vb,
-                           (C)ghx, (C)ghy, (C)gbx, (C)gby, Ih, Ib);
-          fh = sg * wn * (double)Ih;
-          fb = sg * wn * (double)Ib;
-        } else if (wn < 0.0) {
-          double cx = vx - r[R_VWX], cy = (g.dim == 2) ? vy - r[R_VWY] : 0.0;
-          double Hw = r[R_RHOW] * r[R_HWN] * exp(-r[R_LAMW] * (cx * cx + cy * cy));
-          fh = sg * wn * Hw;
-          fb = sg * wn * (double)g.nxi * 0.5 / r[R_LAMW] * Hw;
-        }
+        const double sg = r[R_SGN];
+        const double wn = exact_wn(vx, vy, fg[3], fg[4], sg * fg[0], sg * fg[1]);
+        FaceEq<C> e;
+        e.load(r);
+        C Ih, Ib;
+        interface_avg<C>(e, D, 3 - D, (C)vx, (C)vy, (C)(vx - fg[3]), (C)(vy - fg[4]),
+                         (C)(Lh.v0 + Lh.gx * cdx + Lh.gy * cdy), (C)(Lb.v0 + Lb.gx * cdx + Lb.gy * cdy),
+                         (C)Lh.gx, (C)Lh.gy, (C)Lb.gx, (C)Lb.gy, Ih, Ib);
+        const double cx = vx - r[R_VWX], cy = (D == 2) ? vy - r[R_VWY] : 0.0;
+        const double hw = r[R_RHOW] * r[R_HWN] * exp(-r[R_LAMW] * (cx * cx + cy * cy));
+        const double rt = (double)(3 - D) * 0.5 / r[R_LAMW];
+        fh = (wn > 0.0) ? sg * wn * (double)Ih : ((wn < 0.0) ? sg * wn * hw : 0.0);
+        fb = (wn > 0.0) ? sg * wn * (double)Ib : ((wn < 0.0) ? sg * wn * rt * hw : 0.0);
       } else {
-        double wn = wnorm(vx, vy, fg[3], fg[4], fg[0], fg[1]);
-        if (wn != 0.0) {
-          bool upc = (wn > 0.0) == ((s & 1) != 0);  // upwind side is c
-          double vh, vb, ghx, ghy, gbx, gby;
-          if (upc) {
-            recon(g, h, hinf, c, s, kk, vh, ghx, ghy);
-            recon(g, b, binf, c, s, kk, vb, gbx, gby);
-          } else {
-            other_side(g, h, hinf, c, s, o, kk, vh, ghx, ghy);
-            other_side(g, b, binf, c, s, o, kk, vb, gbx, gby);
-          }
-          FaceEq<C> e;
-          e.load(r);
-          C Ih, Ib;
-          interface_avg<C>(e, g.dim, g.nxi, (C)vx, (C)vy, (C)(vx - fg[3]), (C)(vy - fg[4]), (C)vh, (C)vb,
-                           (C)ghx, (C)ghy, (C)gbx, (C)gby, Ih, Ib);
-          fh = wn * (double)Ih;
-          fb = wn * (double)Ib;
+        const double wn = exact_wn(vx, vy, fg[3], fg[4], fg[0], fg[1]);
+        const bool upc = (wn > 0.0) == ((s & 1) != 0);  // the upwind side is c
+        double vh, vb, ghx, ghy, gbx, gby;
+        if (o >= 0) {
+          double oh, ob, ohx, ohy, obx, oby;
+          neighbour_recon<D>(g, h, hinf, o, s, Lh.nbv[s], Lh.v0, kk, oh, ohx, ohy);
+          neighbour_recon<D>(g, b, binf, o, s, Lb.nbv[s], Lb.v0, kk, ob, obx, oby);
+          vh = upc ? Lh.v0 + Lh.gx * cdx + Lh.gy * cdy : oh;
+          vb = upc ? Lb.v0 + Lb.gx * cdx + Lb.gy * cdy : ob;
+          ghx = upc ? Lh.gx : ohx; ghy = upc ? Lh.gy : ohy;
+          gbx = upc ? Lb.gx : obx; gby = upc ? Lb.gy : oby;
+        } else {
+          const double gh0 = (o == kNbFar) ? (double)hinf[kk] : Lh.v0;
+          const double gb0 = (o == kNbFar) ? (double)binf[kk] : Lb.v0;
+          vh = upc ? Lh.v0 + Lh.gx * cdx + Lh.gy * cdy : gh0;
+          vb = upc ? Lb.v0 + Lb.gx * cdx + Lb.gy * cdy : gb0;
+          ghx = upc ? Lh.gx : 0.0; ghy = upc ? Lh.gy : 0.0;
+          gbx = upc ? Lb.gx : 0.0; gby = upc ? Lb.gy : 0.0;
         }
+        FaceEq<C> e;
+        e.load(r);
+        C Ih, Ib;
+        interface_avg<C>(e, D, 3 - D, (C)vx, (C)vy, (C)(vx - fg[3]), (C)(vy - fg[4]), (C)vh, (C)vb,
+                         (C)ghx, (C)ghy, (C)gbx, (C)gby, Ih, Ib);
+        fh = (wn != 0.0) ? wn * (double)Ih : 0.0;
+        fb = (wn != 0.0) ? wn * (double)Ib : 0.0;
       }
-      if (!kin) { fh = 0.0; fb = 0.0; }
-      if (field) {
-        dh -= (C)(sig * fg[2] * fh * ivol);
-        db -= (C)(sig * fg[2] * fb * ivol);
-      }
-      if (own) {
+      fh = kin ? fh : 0.0;
+      fb = kin ? fb : 0.0;
+      const double sig = (s & 1) ? 1.0 : -1.0;  // +1 if the face normal points out of c
+      dh -= sig * fg[2] * fh * ivol;
+      db -= sig * fg[2] * fb * ivol;
+      if (own[s]) {
         acc[s][0] += wk * fh;
         acc[s][1] += wk * vx * fh;
-        if (g.dim == 2) acc[s][2] += wk * vy * fh;
-        acc[s][g.dim + 1] += wk * 0.5 * ((vx * vx + vy * vy) * fh + fb);
+        if (D == 2) acc[s][2] += wk * vy * fh;
+        acc[s][D + 1] += wk * 0.5 * ((vx * vx + vy * vy) * fh + fb);
       }
     }
     if (kin) {
@@ -411,14 +461,16 @@ __global__ __launch_bounds__(256) void k_flux(Dev g, const T* __restrict__ h, co
       Db[(size_t)c * g.nv + k] = field ? (T)db : (T)0;
     }
   }
-  for (int s = 0; s < 2 * g.dim; ++s) {
-    int f = g.cf[4 * c + s];
-    if (!owns(g, c, s, f)) continue;
+#pragma unroll
+  for (int s = 0; s < 2 * D; ++s) {
+    if (!own[s] || !act[s]) continue;
+    const int f = fc[s];
     double v[4];
-    for (int m = 0; m < nw; ++m) v[m] = wave_sum(acc[s][m]);
+#pragma unroll
+    for (int m = 0; m < D + 2; ++m) v[m] = wave_sum(acc[s][m]);
     if (lane == 0) {
       if (F) for (int m = 0; m < nw; ++m) F[(size_t)f * nw + m] = v[m];
-      if (wall && g.fcell[2 * f + ((s & 1) ? 1 : 0)] == kNbWall) {
+      if (wall && oc[s] == kNbWall) {
         const double* r = rec + (size_t)f * NREC;
         double* o = wall + (size_t)f * (nw + 1);
         o[0] = r[R_RHOW];
@@ -557,9 +609,10 @@ __global__ __launch_bounds__(256) void k_step7(Dev g, int mode, const T* __restr
   if (g.dim == 2) q[(size_t)c * g.dim + 1] = qy;
 }
 
-// per-cell equilibrium record from W (or W') and the heat flux (given, or
-// from a moment record shifted to the velocity of W)
-__global__ void k_cellrec(Dev g, const double* __restrict__ W, const double* __restrict__ q,
+// per-cell record from W (or W') and the heat flux (given, or from a moment
+// record shifted to the velocity of W), the micro diagonal base for the
+// physical step dt, and the micro face coefficients
+__global__ void k_cellrec(Dev g, double dt, const double* __restrict__ W, const double* __restrict__ q,
                           const double* __restrict__ mrec, double* __restrict__ crec) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.ncell || g.type[c] == 0) return;
@@ -572,7 +625,11 @@ __global__ void k_cellrec(Dev g, const double* __restrict__ W, const double* __r
   r[C_RHO] = rho; r[C_UX] = ux; r[C_UY] = uy; r[C_LAM] = lam; r[C_QX] = qx; r[C_QY] = qy;
   r[C_HN] = rho * pow(lam / kPi, 0.5 * g.dim);
   r[C_SH] = 4.0 * (1.0 - g.pr) * lam * lam / (5.0 * rho);
-  r[C_ITAU] = inv_tau_of(g, rho, lam);
+  double it = inv_tau_of(g, rho, lam);
+  r[C_ITAU] = it;
+  r[C_D0] = 1.0 / g.dtp[c] + 1.0 / dt + 0.5 * it;
+  for (int m = 0; m < 12; ++m) r[C_GEO + m] = g.mgeo[(size_t)c * 12 + m];
+  r[22] = 0.0; r[23] = 0.0;
 }
 
 // Shakhov equilibrium h+, b+ of a cell record at velocity (vx, vy)
@@ -722,22 +779,25 @@ __global__ void k_macro_prep(Dev g, double dt, const double* __restrict__ W, con
 }
 
 // ALE Euler flux difference F_E(W + dW) - F_E(W) along n with mesh velocity U
-__device__ inline void euler_dflux(int dim, int nxi, const double* W, const double* dW, double nx, double ny,
-                                   double ux, double uy, double* out) {
-  auto fe = [&](const double* w, double* o) {
-    double rho = w[0], vx = w[1] / rho, vy = (dim == 2) ? w[2] / rho : 0.0;
-    double e = w[dim + 1] - 0.5 * rho * (vx * vx + vy * vy);
-    double p = 2.0 * e / (double)(dim + nxi);  // rho/(2 lam)
-    double th = (vx - ux) * nx + ((dim == 2) ? (vy - uy) * ny : 0.0);
-    o[0] = rho * th;
-    o[1] = w[1] * th + p * nx;
-    if (dim == 2) o[2] = w[2] * th + p * ny;
-    o[dim + 1] = w[dim + 1] * th + p * (vx * nx + ((dim == 2) ? vy * ny : 0.0));
-  };
-  double w1[4], f1[4], f0[4];
-  for (int m = 0; m < dim + 2; ++m) w1[m] = W[m] + dW[m];
-  fe(w1, f1);
-  fe(W, f0);
+__device__ __forceinline__ void euler_flux4(int dim, int nxi, double w0, double w1, double w2, double w3,
+                                            double nx, double ny, double ux, double uy, double* o) {
+  double rho = w0, vx = w1 / rho, vy = (dim == 2) ? w2 / rho : 0.0;
+  double wE = (dim == 2) ? w3 : w2;
+  double e = wE - 0.5 * rho * (vx * vx + vy * vy);
+  double p = 2.0 * e / (double)(dim + nxi);  // rho/(2 lam)
+  double th = (vx - ux) * nx + ((dim == 2) ? (vy - uy) * ny : 0.0);
+  o[0] = rho * th;
+  o[1] = w1 * th + p * nx;
+  if (dim == 2) { o[2] = w2 * th + p * ny; o[3] = wE * th + p * (vx * nx + vy * ny); }
+  else o[2] = wE * th + p * vx * nx;
+}
+
+__device__ __forceinline__ void euler_dflux(int dim, int nxi, const double* W, const double* dW, double nx,
+                                            double ny, double ux, double uy, double* out) {
+  double f1[4], f0[4];
+  euler_flux4(dim, nxi, W[0] + dW[0], W[1] + dW[1], W[2] + dW[2], (dim == 2) ? W[3] + dW[3] : 0.0, nx, ny,
+              ux, uy, f1);
+  euler_flux4(dim, nxi, W[0], W[1], W[2], (dim == 2) ? W[3] : 0.0, nx, ny, ux, uy, f0);
   for (int m = 0; m < dim + 2; ++m) out[m] = f1[m] - f0[m];
 }
 
@@ -752,109 +812,189 @@ __device__ inline void euler_dflux(int dim, int nxi, const double* W, const doub
 // rows and keeps the latest value of each row in registers; the first row of
 // a thread reads the last row of the previous thread through LDS.
 // ------------------------------------------------------------------------
-constexpr int kMaxRowsMacro = 8;
-constexpr int kMaxRowsMicro = 4;
+// macro sweep: one workgroup per block, one thread per row j.  The next
+// hyperplane's inputs (residual, diagonal, neighbour states and face data)
+// are loaded before the current hyperplane is computed, so their latency
+// overlaps the computation and the barrier.
+struct MacroNb {
+  double W[4], nx, ny, ux, uy, S, G;
+  bool on;
+};
+struct MacroRow {
+  int c;
+  bool ok, fld;
+  double base[4], Dg, ivd;  // forward: R; backward: dW*
+  MacroNb nb[2];
+};
 
-__device__ inline void macro_couple(const Dev& g, const double* __restrict__ W,
-                                    const double* __restrict__ gam, int c, int s, int nbc,
-                                    const double* x, double* acc) {
-  if (g.type[nbc] != 1) return;
+template <int D>
+__device__ __forceinline__ void macro_nb_load(const Dev& g, const double* __restrict__ W,
+                                              const double* __restrict__ gam, int c, int s, int o, MacroNb& N) {
+  N.on = (o >= 0) && g.type[o] == 1;
   int f = g.cf[4 * c + s];
+  if (f < 0) N.on = false;
+  if (!N.on) return;
   const double* fg = g.fgeo + (size_t)f * 8;
   double sg = (s & 1) ? 1.0 : -1.0;
-  double dF[4];
-  euler_dflux(g.dim, g.nxi, W + (size_t)nbc * g.nw, x, sg * fg[0], sg * fg[1], fg[3], fg[4], dF);
-  double G = gam[f], S = fg[2];
-  for (int m = 0; m < g.nw; ++m) acc[m] += S * (dF[m] - G * x[m]);
+  N.nx = sg * fg[0]; N.ny = sg * fg[1]; N.ux = fg[3]; N.uy = fg[4]; N.S = fg[2]; N.G = gam[f];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) N.W[m] = (m < D + 2) ? W[(size_t)o * (D + 2) + m] : 0.0;
 }
 
-__global__ __launch_bounds__(64) void k_macro_sweep(Dev g, const int* __restrict__ binfo,
-                                                    const double* __restrict__ W,
-                                                    const double* __restrict__ R,
-                                                    const double* __restrict__ Dg,
-                                                    const double* __restrict__ gam,
-                                                    double* __restrict__ dWs, double* __restrict__ dW,
-                                                    double* __restrict__ Wp, double* __restrict__ rpart) {
+template <int D>
+__device__ __forceinline__ void macro_apply(const MacroNb& N, const double* x, double* acc) {
+  if (!N.on) return;
+  double dF[4];
+  euler_dflux(D, 3 - D, N.W, x, N.nx, N.ny, N.ux, N.uy, dF);
+#pragma unroll
+  for (int m = 0; m < D + 2; ++m) acc[m] += N.S * (dF[m] - N.G * x[m]);
+}
+
+// inputs of row j on hyperplane h: forward (bwd = 0) reads the residual and
+// the lower neighbours, backward the forward result and the upper neighbours
+template <int D>
+__device__ __forceinline__ void macro_row_load(const Dev& g, const double* __restrict__ W,
+                                               const double* __restrict__ gam, const double* __restrict__ base,
+                                               const double* __restrict__ Dg, int bwd, int ni, int nj, int c0,
+                                               int j, int h, MacroRow& M) {
+  constexpr int nw = D + 2;
+  int i = h - j;
+  M.ok = (j < nj) && (i >= 0) && (i < ni);
+  M.fld = false;
+  M.nb[0].on = false;
+  M.nb[1].on = false;
+  if (!M.ok) return;
+  int c = c0 + i + ni * j;
+  M.c = c;
+  M.fld = g.type[c] == 1;
+  if (!M.fld) return;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) M.base[m] = (m < nw) ? base[(size_t)c * nw + m] : 0.0;
+  M.Dg = Dg[c];
+  M.ivd = bwd ? 0.25 / (g.vol[c] * M.Dg) : 0.25 / g.vol[c];
+  if (!bwd) {
+    macro_nb_load<D>(g, W, gam, c, 0, (i >= 1) ? c - 1 : -1, M.nb[0]);
+    macro_nb_load<D>(g, W, gam, c, 2, (j >= 1) ? c - ni : -1, M.nb[1]);
+  } else {
+    macro_nb_load<D>(g, W, gam, c, 1, (i + 1 < ni) ? c + 1 : -1, M.nb[0]);
+    macro_nb_load<D>(g, W, gam, c, 3, (j + 1 < nj) ? c + ni : -1, M.nb[1]);
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(512) void k_macro_sweep(Dev g, const int* __restrict__ binfo,
+                                                     const double* __restrict__ W,
+                                                     const double* __restrict__ R,
+                                                     const double* __restrict__ Dg,
+                                                     const double* __restrict__ gam,
+                                                     double* __restrict__ dWs, double* __restrict__ dW,
+                                                     double* __restrict__ Wp, double* __restrict__ rpart) {
+  extern __shared__ double msm[];
   const int* bi = binfo + 8 * blockIdx.x;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], pi = bi[3], pj = bi[4];
-  const int t = threadIdx.x, NT = blockDim.x;
-  const int rpt = (nj + NT - 1) / NT;
-  const int j0 = t * rpt;
-  const int nw = g.nw;
-  __shared__ double hand[2][64][4];
-  __shared__ double pjb[64][4];
-  double prev[kMaxRowsMacro][4], cw[kMaxRowsMacro][4];
-  for (int r = 0; r < kMaxRowsMacro; ++r)
-    for (int m = 0; m < 4; ++m) { prev[r][m] = 0.0; cw[r][m] = 0.0; }
+  const int j = threadIdx.x;
+  const int NT = blockDim.x;
+  constexpr int nw = D + 2;
+  double* hand = msm;              // [2][NT][4]
+  double* pjb = msm + 2 * NT * 4;  // [ni][4] (periodic j)
   // residual norm over the block's field cells
   double rs[4] = {0, 0, 0, 0};
-  for (int r = 0; r < rpt; ++r) {
-    int j = j0 + r;
-    if (j >= nj) break;
+  if (j < nj)
     for (int i = 0; i < ni; ++i) {
       int c = c0 + i + ni * j;
       if (g.type[c] != 1) continue;
       for (int m = 0; m < nw; ++m) rs[m] += R[(size_t)c * nw + m] * R[(size_t)c * nw + m];
     }
-  }
   for (int m = 0; m < 4; ++m) rs[m] = wave_sum(rs[m]);
-  if (t == 0) for (int m = 0; m < nw; ++m) rpart[(size_t)blockIdx.x * 4 + m] = rs[m];
+  // deterministic combination of the per-wave sums
+  __shared__ double wsum[8][4];
+  if ((j & 63) == 0) for (int m = 0; m < 4; ++m) wsum[j >> 6][m] = rs[m];
+  __syncthreads();
+  if (j == 0) {
+    for (int m = 0; m < nw; ++m) {
+      double t = 0.0;
+      for (int w = 0; w < (NT + 63) / 64; ++w) t += wsum[w][m];
+      rpart[(size_t)blockIdx.x * 4 + m] = t;
+    }
+  }
   const int H = ni + nj - 1;
+  double prev[4] = {0, 0, 0, 0}, cw[4] = {0, 0, 0, 0};
+  MacroRow cur, nxt;
   // forward sweep: (D + L) dW* = R
+  macro_row_load<D>(g, W, gam, R, Dg, 0, ni, nj, c0, j, 0, cur);
   for (int h = 0; h < H; ++h) {
-    for (int r = rpt - 1; r >= 0; --r) {
-      int j = j0 + r, i = h - j;
-      if (j >= nj || i < 0 || i >= ni) continue;
-      int c = c0 + i + ni * j;
+    if (h + 1 < H) macro_row_load<D>(g, W, gam, R, Dg, 0, ni, nj, c0, j, h + 1, nxt);
+    if (cur.ok) {
+      int i = h - j, c = cur.c;
       double x[4] = {0, 0, 0, 0};
-      if (g.type[c] == 1) {
+      if (cur.fld) {
         double acc[4] = {0, 0, 0, 0};
-        if (i >= 1) macro_couple(g, W, gam, c, 0, c - 1, prev[r], acc);
-        if (j >= 1) macro_couple(g, W, gam, c, 2, c - ni, (r > 0) ? prev[r - 1] : hand[(h - 1) & 1][t - 1], acc);
-        if (pi && i == ni - 1 && ni > 1) macro_couple(g, W, gam, c, 1, c - (ni - 1), cw[r], acc);
-        if (pj && j == nj - 1 && nj > 1) macro_couple(g, W, gam, c, 3, c0 + i, pjb[i], acc);
-        double ivd = 0.25 / g.vol[c];
-        for (int m = 0; m < nw; ++m) x[m] = (R[(size_t)c * nw + m] - ivd * acc[m]) / Dg[c];
+        macro_apply<D>(cur.nb[0], prev, acc);
+        if (j >= 1) macro_apply<D>(cur.nb[1], hand + ((h - 1) & 1) * NT * 4 + (j - 1) * 4, acc);
+        if (pi && i == ni - 1 && ni > 1) {
+          MacroNb N;
+          macro_nb_load<D>(g, W, gam, c, 1, c - (ni - 1), N);
+          macro_apply<D>(N, cw, acc);
+        }
+        if (pj && j == nj - 1 && nj > 1) {
+          MacroNb N;
+          macro_nb_load<D>(g, W, gam, c, 3, c0 + i, N);
+          macro_apply<D>(N, pjb + 4 * i, acc);
+        }
+        for (int m = 0; m < nw; ++m) x[m] = (cur.base[m] - cur.ivd * acc[m]) / cur.Dg;
       }
       for (int m = 0; m < nw; ++m) {
         dWs[(size_t)c * nw + m] = x[m];
-        prev[r][m] = x[m];
-        if (i == 0) cw[r][m] = x[m];
-        if (r == rpt - 1) hand[h & 1][t][m] = x[m];
-        if (pj && j == 0) pjb[i][m] = x[m];
+        prev[m] = x[m];
+        if (i == 0) cw[m] = x[m];
+        hand[(h & 1) * NT * 4 + j * 4 + m] = x[m];
+        if (pj && j == 0) pjb[4 * i + m] = x[m];
       }
     }
     __syncthreads();
+    cur = nxt;
   }
-  for (int r = 0; r < kMaxRowsMacro; ++r)
-    for (int m = 0; m < 4; ++m) { prev[r][m] = 0.0; cw[r][m] = 0.0; }
+  for (int m = 0; m < 4; ++m) { prev[m] = 0.0; cw[m] = 0.0; }
   __syncthreads();
   // backward sweep: (D + U) dW = D dW*
+  macro_row_load<D>(g, W, gam, dWs, Dg, 1, ni, nj, c0, j, H - 1, cur);
   for (int h = H - 1; h >= 0; --h) {
-    for (int r = 0; r < rpt; ++r) {
-      int j = j0 + r, i = h - j;
-      if (j >= nj || i < 0 || i >= ni) continue;
-      int c = c0 + i + ni * j;
+    if (h >= 1) macro_row_load<D>(g, W, gam, dWs, Dg, 1, ni, nj, c0, j, h - 1, nxt);
+    if (cur.ok) {
+      int i = h - j, c = cur.c;
       double x[4] = {0, 0, 0, 0};
-      if (g.type[c] == 1) {
+      if (cur.fld) {
         double acc[4] = {0, 0, 0, 0};
-        if (i + 1 < ni) macro_couple(g, W, gam, c, 1, c + 1, prev[r], acc);
-        if (j + 1 < nj) macro_couple(g, W, gam, c, 3, c + ni, (r + 1 < rpt) ? prev[r + 1] : hand[(h + 1) & 1][t + 1], acc);
-        if (pi && i == 0 && ni > 1) macro_couple(g, W, gam, c, 0, c + ni - 1, cw[r], acc);
-        if (pj && j == 0 && nj > 1) macro_couple(g, W, gam, c, 2, c0 + i + ni * (nj - 1), pjb[i], acc);
-        double ivd = 0.25 / (g.vol[c] * Dg[c]);
-        for (int m = 0; m < nw; ++m) x[m] = dWs[(size_t)c * nw + m] - ivd * acc[m];
+        macro_apply<D>(cur.nb[0], prev, acc);
+        if (j + 1 < nj) macro_apply<D>(cur.nb[1], hand + ((h + 1) & 1) * NT * 4 + (j + 1) * 4, acc);
+        if (pi && i == 0 && ni > 1) {
+          MacroNb N;
+          macro_nb_load<D>(g, W, gam, c, 0, c + ni - 1, N);
+          macro_apply<D>(N, cw, acc);
+        }
+        if (pj && j == 0 && nj > 1) {
+          MacroNb N;
+          macro_nb_load<D>(g, W, gam, c, 2, c0 + i + ni * (nj - 1), N);
+          macro_apply<D>(N, pjb + 4 * i, acc);
+        }
+        for (int m = 0; m < nw; ++m) x[m] = cur.base[m] - cur.ivd * acc[m];
       }
+      // a non-physical predictor keeps the current state
+      double wp[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) wp[m] = (m < nw) ? W[(size_t)c * nw + m] + x[m] : 0.0;
+      const bool okp = physical_state(D, wp);
       for (int m = 0; m < nw; ++m) {
         dW[(size_t)c * nw + m] = x[m];
-        Wp[(size_t)c * nw + m] = W[(size_t)c * nw + m] + x[m];
-        prev[r][m] = x[m];
-        if (i == ni - 1) cw[r][m] = x[m];
-        if (r == 0) hand[h & 1][t][m] = x[m];
-        if (pj && j == nj - 1) pjb[i][m] = x[m];
+        Wp[(size_t)c * nw + m] = okp ? wp[m] : W[(size_t)c * nw + m];
+        prev[m] = x[m];
+        if (i == ni - 1) cw[m] = x[m];
+        hand[(h & 1) * NT * 4 + j * 4 + m] = x[m];
+        if (pj && j == nj - 1) pjb[4 * i + m] = x[m];
       }
     }
     __syncthreads();
+    cur = nxt;
   }
 }
 
@@ -867,11 +1007,13 @@ __global__ void k_resid(int nblock, int nw, const double* __restrict__ rpart, do
   out[m] = sqrt(s);
 }
 
-// micro LU-SGS (Eq. dualTimeStepping_micro), forward and backward sweep of
-// one velocity chunk of one block; Dh/Db hold the flux divergence on entry
-// and dF* afterwards; h, b are updated to f^{s+1}
-template <class T>
-__global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ binfo, int KC, double dt,
+// micro LU-SGS (Eq. dualTimeStepping_micro): forward and backward sweep of
+// one velocity chunk (KC lanes) of one block, one row per thread slot.
+// Dh/Db hold the flux divergence on entry and dF* afterwards; h, b are
+// updated to f^{s+1}.  Per-cell data of the next hyperplane is staged in LDS
+// by the lanes of its slot while the current hyperplane is computed.
+template <int D, class T>
+__global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ binfo, int KC, int nslot, double dt,
                                                 const double* __restrict__ crec, T* __restrict__ h,
                                                 T* __restrict__ b, const T* __restrict__ Sh,
                                                 const T* __restrict__ Sb, T* __restrict__ Dh,
@@ -879,125 +1021,186 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   extern __shared__ double smem[];
   const int* bi = binfo + 8 * blockIdx.y;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], pi = bi[3], pj = bi[4];
-  const int t = threadIdx.x, nslot = blockDim.x / KC;
-  const int lk = t % KC, slot = t / KC;
+  const int t = threadIdx.x;
+  const int lk = t % KC, j = t / KC;
   const int k = blockIdx.x * KC + lk;
   const bool kin = k < g.nv;
   const int kk = kin ? k : g.nv - 1;
-  const int rpt = (nj + nslot - 1) / nslot;
-  const int j0 = slot * rpt;
-  // LDS: hand[2][nslot][KC][2], then pj[ni][KC][2]
+  // LDS: hand[2][nslot][KC][2], cells[2][nslot][NCREC], pj[ni][KC][2]
   double* hand = smem;
-  double* pjb = smem + 2 * nslot * KC * 2;
-  auto H_ = [&](int p, int s) -> double* { return hand + ((size_t)(p * nslot + s) * KC + lk) * 2; };
-  auto P_ = [&](int i) -> double* { return pjb + ((size_t)i * KC + lk) * 2; };
+  double* cells = smem + 4 * nslot * KC;
+  double* pjb = cells + 2 * nslot * NCREC;
+  auto HND = [&](int p, int s) -> double* { return hand + ((size_t)(p * nslot + s) * KC + lk) * 2; };
+  auto CEL = [&](int p) -> double* { return cells + (size_t)(p * nslot + j) * NCREC; };
+  auto PJ = [&](int i) -> double* { return pjb + ((size_t)i * KC + lk) * 2; };
   const double vx = g.vx[kk], vy = g.vy[kk];
-  double ph[kMaxRowsMicro], pb[kMaxRowsMicro], ch[kMaxRowsMicro], cb[kMaxRowsMicro];
-  for (int r = 0; r < kMaxRowsMicro; ++r) { ph[r] = pb[r] = ch[r] = cb[r] = 0.0; }
-  const int HH = ni + nj - 1;
   const double idt = 1.0 / dt;
+  const int HH = ni + nj - 1;
+  const bool row = j < nj;
+  double ph = 0.0, pb = 0.0, chh = 0.0, cbb = 0.0;
 
-  auto diag_and_w = [&](int c, double* wn, double& d) {
-    const double* cr = crec + (size_t)c * NCREC;
-    double ivol = 1.0 / g.vol[c];
-    d = 1.0 / g.dtp[c] + idt + 0.5 * cr[C_ITAU];
-    for (int s = 0; s < 2 * g.dim; ++s) {
-      int f = g.cf[4 * c + s];
-      wn[s] = 0.0;
-      if (f < 0) continue;
-      const double* fg = g.fgeo + (size_t)f * 8;
-      double w = wnorm(vx, vy, fg[3], fg[4], fg[0], fg[1]);
-      w = (s & 1) ? w : -w;
-      wn[s] = w;
-      d += 0.5 * ivol * fg[2] * ((w > 0.0) ? w : 0.0);
-    }
+  // stage the per-cell record of hyperplane hp into LDS buffer p (after the
+  // caller's barrier the buffer is read); loads are issued into registers
+  // first so that they overlap the current hyperplane's work
+  double st0 = 0.0, st1 = 0.0;
+  auto cell_of_hp = [&](int hp) -> int {
+    int i = hp - j;
+    return (row && i >= 0 && i < ni) ? c0 + i + ni * j : -1;
   };
-  // forward sweep
+  auto stage_load = [&](int hp) {
+    int c = cell_of_hp(hp);
+    st0 = 0.0; st1 = 0.0;
+    if (c < 0) return;
+    const double* r = crec + (size_t)c * NCREC;
+    if (lk < NCREC) st0 = r[lk];
+    if (lk + KC < NCREC) st1 = r[lk + KC];
+  };
+  auto stage_store = [&](int p) {
+    if (!row) return;
+    double* d = CEL(p);
+    if (lk < NCREC) d[lk] = st0;
+    if (lk + KC < NCREC) d[lk + KC] = st1;
+  };
+  auto stage_small = [&](int hp, int p) {  // narrow chunks: the remaining entries
+    int c = cell_of_hp(hp);
+    if (c < 0 || 2 * KC >= NCREC) return;
+    double* d = CEL(p);
+    for (int e = lk + 2 * KC; e < NCREC; e += KC) d[e] = crec[(size_t)c * NCREC + e];
+  };
+  // streaming values of the next cell of this row
+  double n0 = 0, n1 = 0, n2 = 0, n3 = 0, n4 = 0, n5 = 0;
+  int ncell_ = -1;
+  auto stream_fwd = [&](int hp) {
+    ncell_ = cell_of_hp(hp);
+    if (ncell_ < 0 || g.type[ncell_] != 1) { ncell_ = -1; return; }
+    size_t o = (size_t)ncell_ * g.nv + kk;
+    n0 = (double)Sh[o]; n1 = (double)Sb[o]; n2 = (double)h[o]; n3 = (double)b[o];
+    n4 = (double)Dh[o]; n5 = (double)Db[o];
+  };
+  auto stream_bwd = [&](int hp) {
+    ncell_ = cell_of_hp(hp);
+    if (ncell_ < 0 || g.type[ncell_] != 1) { ncell_ = -1; return; }
+    size_t o = (size_t)ncell_ * g.nv + kk;
+    n2 = (double)h[o]; n3 = (double)b[o]; n4 = (double)Dh[o]; n5 = (double)Db[o];
+  };
+
+  // ---------------- forward sweep: (D + L) dF* = r ----------------
+  stage_load(0);
+  stage_store(0);
+  stage_small(0, 0);
+  stream_fwd(0);
+  __syncthreads();
   for (int hp = 0; hp < HH; ++hp) {
-    for (int r = rpt - 1; r >= 0; --r) {
-      int j = j0 + r, i = hp - j;
-      if (j >= nj || i < 0 || i >= ni) continue;
-      int c = c0 + i + ni * j;
-      double xh = 0.0, xb = 0.0;
-      if (g.type[c] == 1) {
-        double wn[4], d;
-        diag_and_w(c, wn, d);
-        double oh = 0.0, ob = 0.0;
-        auto couple = [&](int s, double vh, double vb) {
-          int f = g.cf[4 * c + s];
-          double S = g.fgeo[(size_t)f * 8 + 2];
-          double wm = (wn[s] < 0.0) ? wn[s] : 0.0;
-          oh += S * wm * vh;
-          ob += S * wm * vb;
-        };
-        if (i >= 1) couple(0, ph[r], pb[r]);
-        if (j >= 1) {
-          if (r > 0) couple(2, ph[r - 1], pb[r - 1]);
-          else { double* q = H_((hp - 1) & 1, slot - 1); couple(2, q[0], q[1]); }
-        }
-        if (pi && i == ni - 1 && ni > 1) couple(1, ch[r], cb[r]);
-        if (pj && j == nj - 1 && nj > 1) { double* q = P_(i); couple(3, q[0], q[1]); }
-        const double* cr = crec + (size_t)c * NCREC;
-        double hpl, bpl;
-        cell_fplus(cr, g.dim, g.nxi, vx, vy, hpl, bpl);
-        size_t o = (size_t)c * g.nv + kk;
-        double hv = (double)h[o], bv = (double)b[o];
-        double it = cr[C_ITAU];
-        double rh = (double)Sh[o] - hv * idt + 0.5 * ((double)Dh[o] + (hpl - hv) * it);
-        double rb = (double)Sb[o] - bv * idt + 0.5 * ((double)Db[o] + (bpl - bv) * it);
-        double ivol2 = 0.5 / g.vol[c];
-        xh = (rh - ivol2 * oh) / d;
-        xb = (rb - ivol2 * ob) / d;
-        if (kin) { Dh[o] = (T)xh; Db[o] = (T)xb; }
+    const int p = hp & 1;
+    const int c = ncell_;
+    const double s0 = n0, s1 = n1, f0 = n2, f1 = n3, d0v = n4, d1v = n5;
+    // issue the next hyperplane's loads
+    if (hp + 1 < HH) { stage_load(hp + 1); stream_fwd(hp + 1); }
+    const int i = hp - j;
+    const bool has = row && i >= 0 && i < ni;
+    double xh = 0.0, xb = 0.0;
+    if (c >= 0) {
+      const double* r = CEL(p);
+      double ts[2 * D];
+      double d = r[C_D0];
+#pragma unroll
+      for (int s = 0; s < 2 * D; ++s) {
+        ts[s] = r[C_GEO + 3 * s] * vx + r[C_GEO + 3 * s + 1] * vy - r[C_GEO + 3 * s + 2];
+        d += (ts[s] > 0.0) ? ts[s] : 0.0;
       }
-      ph[r] = xh; pb[r] = xb;
-      if (i == 0) { ch[r] = xh; cb[r] = xb; }
-      if (r == rpt - 1) { double* q = H_(hp & 1, slot); q[0] = xh; q[1] = xb; }
-      if (pj && j == 0) { double* q = P_(i); q[0] = xh; q[1] = xb; }
+      double oh = 0.0, ob = 0.0;
+      if (i >= 1) { double w = fmin(ts[0], 0.0); oh += w * ph; ob += w * pb; }
+      if (D == 2 && j >= 1) {
+        const double* q = HND(p ^ 1, j - 1);
+        double w = fmin(ts[2], 0.0); oh += w * q[0]; ob += w * q[1];
+      }
+      if (pi && i == ni - 1 && ni > 1) { double w = fmin(ts[1], 0.0); oh += w * chh; ob += w * cbb; }
+      if (D == 2 && pj && j == nj - 1 && nj > 1) {
+        const double* q = PJ(i);
+        double w = fmin(ts[3], 0.0); oh += w * q[0]; ob += w * q[1];
+      }
+      // Shakhov equilibrium of W' and the residual
+      double cx = vx - r[C_UX], cy = (D == 2) ? vy - r[C_UY] : 0.0;
+      double c2 = cx * cx + cy * cy, lam = r[C_LAM];
+      double H = r[C_HN] * exp(-lam * c2);
+      double rt = 0.5 / lam;
+      double B = (double)(3 - D) * rt * H;
+      double sq = r[C_SH] * (cx * r[C_QX] + cy * r[C_QY]);
+      double tl = 2.0 * lam * c2;
+      double hpl = H + sq * (tl - 2.0 - D) * H;
+      double bpl = B + sq * (tl - D) * (double)(3 - D) * rt * H;
+      double it = r[C_ITAU];
+      double rh = s0 - f0 * idt + 0.5 * (d0v + (hpl - f0) * it);
+      double rb = s1 - f1 * idt + 0.5 * (d1v + (bpl - f1) * it);
+      xh = (rh - oh) / d;
+      xb = (rb - ob) / d;
+      if (kin) {
+        size_t o = (size_t)c * g.nv + k;
+        Dh[o] = (T)xh;
+        Db[o] = (T)xb;
+      }
     }
+    if (has) {
+      ph = xh; pb = xb;
+      if (i == 0) { chh = xh; cbb = xb; }
+      double* q = HND(p, j);
+      q[0] = xh; q[1] = xb;
+      if (D == 2 && pj && j == 0) { double* z = PJ(i); z[0] = xh; z[1] = xb; }
+    }
+    if (hp + 1 < HH) { stage_store(p ^ 1); stage_small(hp + 1, p ^ 1); }
     __syncthreads();
   }
-  for (int r = 0; r < kMaxRowsMicro; ++r) { ph[r] = pb[r] = ch[r] = cb[r] = 0.0; }
+  // ---------------- backward sweep: (D + U) dF = D dF* ----------------
+  ph = pb = chh = cbb = 0.0;
+  stage_load(HH - 1);
+  stage_store((HH - 1) & 1);
+  stage_small(HH - 1, (HH - 1) & 1);
+  stream_bwd(HH - 1);
   __syncthreads();
-  // backward sweep
   for (int hp = HH - 1; hp >= 0; --hp) {
-    for (int r = 0; r < rpt; ++r) {
-      int j = j0 + r, i = hp - j;
-      if (j >= nj || i < 0 || i >= ni) continue;
-      int c = c0 + i + ni * j;
-      double xh = 0.0, xb = 0.0;
-      if (g.type[c] == 1) {
-        double wn[4], d;
-        diag_and_w(c, wn, d);
-        double oh = 0.0, ob = 0.0;
-        auto couple = [&](int s, double vh, double vb) {
-          int f = g.cf[4 * c + s];
-          double S = g.fgeo[(size_t)f * 8 + 2];
-          double wm = (wn[s] < 0.0) ? wn[s] : 0.0;
-          oh += S * wm * vh;
-          ob += S * wm * vb;
-        };
-        if (i + 1 < ni) couple(1, ph[r], pb[r]);
-        if (j + 1 < nj) {
-          if (r + 1 < rpt) couple(3, ph[r + 1], pb[r + 1]);
-          else { double* q = H_((hp + 1) & 1, slot + 1); couple(3, q[0], q[1]); }
-        }
-        if (pi && i == 0 && ni > 1) couple(0, ch[r], cb[r]);
-        if (pj && j == 0 && nj > 1) { double* q = P_(i); couple(2, q[0], q[1]); }
-        size_t o = (size_t)c * g.nv + kk;
-        double ivd = 0.5 / (g.vol[c] * d);
-        xh = (double)Dh[o] - ivd * oh;
-        xb = (double)Db[o] - ivd * ob;
-        if (kin) {
-          h[o] = (T)((double)h[o] + xh);
-          b[o] = (T)((double)b[o] + xb);
-        }
+    const int p = hp & 1;
+    const int c = ncell_;
+    const double f0 = n2, f1 = n3, x0 = n4, x1 = n5;
+    if (hp >= 1) { stage_load(hp - 1); stream_bwd(hp - 1); }
+    const int i = hp - j;
+    const bool has = row && i >= 0 && i < ni;
+    double xh = 0.0, xb = 0.0;
+    if (c >= 0) {
+      const double* r = CEL(p);
+      double ts[2 * D];
+      double d = r[C_D0];
+#pragma unroll
+      for (int s = 0; s < 2 * D; ++s) {
+        ts[s] = r[C_GEO + 3 * s] * vx + r[C_GEO + 3 * s + 1] * vy - r[C_GEO + 3 * s + 2];
+        d += (ts[s] > 0.0) ? ts[s] : 0.0;
       }
-      ph[r] = xh; pb[r] = xb;
-      if (i == ni - 1) { ch[r] = xh; cb[r] = xb; }
-      if (r == 0) { double* q = H_(hp & 1, slot); q[0] = xh; q[1] = xb; }
-      if (pj && j == nj - 1) { double* q = P_(i); q[0] = xh; q[1] = xb; }
+      double oh = 0.0, ob = 0.0;
+      if (i + 1 < ni) { double w = fmin(ts[1], 0.0); oh += w * ph; ob += w * pb; }
+      if (D == 2 && j + 1 < nj) {
+        const double* q = HND(p ^ 1, j + 1);
+        double w = fmin(ts[3], 0.0); oh += w * q[0]; ob += w * q[1];
+      }
+      if (pi && i == 0 && ni > 1) { double w = fmin(ts[0], 0.0); oh += w * chh; ob += w * cbb; }
+      if (D == 2 && pj && j == 0 && nj > 1) {
+        const double* q = PJ(i);
+        double w = fmin(ts[2], 0.0); oh += w * q[0]; ob += w * q[1];
+      }
+      xh = x0 - oh / d;
+      xb = x1 - ob / d;
+      if (kin) {
+        size_t o = (size_t)c * g.nv + k;
+        h[o] = (T)(f0 + xh);
+        b[o] = (T)(f1 + xb);
+      }
     }
+    if (has) {
+      ph = xh; pb = xb;
+      if (i == ni - 1) { chh = xh; cbb = xb; }
+      double* q = HND(p, j);
+      q[0] = xh; q[1] = xb;
+      if (D == 2 && pj && j == nj - 1) { double* z = PJ(i); z[0] = xh; z[1] = xb; }
+    }
+    if (hp >= 1) { stage_store(p ^ 1); stage_small(hp - 1, p ^ 1); }
     __syncthreads();
   }
 }
@@ -1008,23 +1211,28 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
 static inline unsigned nb4(int n) { return (unsigned)((n + 3) / 4); }
 static inline unsigned nbl(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-template <class T, class C>
+template <int D, class T, class C>
 void launch_flux_t(const Dev& g, double dts, const void* h, const void* b, const double* W, const double* q,
                    double* gW, double* rec, void* Dh, void* Db, double* F, double* wall, hipStream_t st,
                    hipEvent_t* ev) {
   k_gradW<<<nbl(g.ncell, 256), 256, 0, st>>>(g, W, gW);
   k_wallprep<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, W, q, gW, rec);
   if (ev) (void)hipEventRecord(ev[0], st);
-  k_face_eq<T><<<nb4(g.ncell), 256, 0, st>>>(g, dts, (const T*)h, (const T*)b, W, gW, rec);
+  k_face_eq<D, T><<<nb4(g.ncell), 256, 0, st>>>(g, dts, (const T*)h, (const T*)b, W, gW, rec);
   if (ev) (void)hipEventRecord(ev[1], st);
-  k_flux<T, C><<<nb4(g.ncell), 256, 0, st>>>(g, (const T*)h, (const T*)b, rec, (T*)Dh, (T*)Db, F, wall);
+  k_flux<D, T, C><<<nb4(g.ncell), 256, 0, st>>>(g, (const T*)h, (const T*)b, rec, (T*)Dh, (T*)Db, F, wall);
 }
 
 void launch_flux(const Dev& g, int prec, double dts, const void* h, const void* b, const double* W,
                  const double* q, double* gW, double* rec, void* Dh, void* Db, double* F, double* wall,
                  hipStream_t st, hipEvent_t* ev) {
-  if (prec == 0) launch_flux_t<double, double>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st, ev);
-  else launch_flux_t<float, float>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st, ev);
+  if (g.dim == 2) {
+    if (prec == 0) launch_flux_t<2, double, double>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st, ev);
+    else launch_flux_t<2, float, float>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st, ev);
+  } else {
+    if (prec == 0) launch_flux_t<1, double, double>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st, ev);
+    else launch_flux_t<1, float, float>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st, ev);
+  }
 }
 
 void launch_moments(const Dev& g, int prec, const void* h, const void* b, double* W, double* q, hipStream_t st) {
@@ -1045,9 +1253,9 @@ void launch_interp(const Dev& g, int prec, int nrec, const int* rec, const int* 
   else k_interp<float><<<nb4(nrec), 256, 0, st>>>(g, nrec, rec, ptr, don, w, (float*)h, (float*)b, W, q);
 }
 
-void launch_cellrec(const Dev& g, const double* W, const double* q, const double* mrec, double* crec,
+void launch_cellrec(const Dev& g, double dt, const double* W, const double* q, const double* mrec, double* crec,
                     hipStream_t st) {
-  k_cellrec<<<nbl(g.ncell, 256), 256, 0, st>>>(g, W, q, mrec, crec);
+  k_cellrec<<<nbl(g.ncell, 256), 256, 0, st>>>(g, dt, W, q, mrec, crec);
 }
 
 void launch_source(const Dev& g, int prec, double dt, const void* h, const void* b, const double* crec,
@@ -1063,32 +1271,59 @@ void launch_step7(const Dev& g, int prec, int mode, const void* h, const void* b
   else k_step7<float><<<nb4(g.ncell), 256, 0, st>>>(g, mode, (const float*)h, (const float*)b, crec, Wp, W, q, mrec);
 }
 
-void launch_macro(const Dev& g, const int* binfo, double dt, const double* W, const double* Wn,
-                  const double* F, const double* Fn, double* gam, double* R, double* Dg, double* dWs,
-                  double* dW, double* Wp, double* rpart, double* resid, hipStream_t st) {
+void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
+                  const double* W, const double* Wn, const double* F, const double* Fn, double* gam, double* R,
+                  double* Dg, double* dWs, double* dW, double* Wp, double* rpart, double* resid, hipStream_t st) {
   k_gamma<<<nbl(g.nface, 256), 256, 0, st>>>(g, W, gam);
   k_macro_prep<<<nbl(g.ncell, 256), 256, 0, st>>>(g, dt, W, Wn, F, Fn, gam, R, Dg);
-  k_macro_sweep<<<g.nblock, 64, 0, st>>>(g, binfo, W, R, Dg, gam, dWs, dW, Wp, rpart);
+  int nt = ((max_nj + 63) / 64) * 64;
+  size_t lds = sizeof(double) * (size_t)(2 * nt * 4 + (any_pj ? 4 * max_ni : 0));
+  if (g.dim == 2) k_macro_sweep<2><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, Dg, gam, dWs, dW, Wp, rpart);
+  else k_macro_sweep<1><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, Dg, gam, dWs, dW, Wp, rpart);
   if (resid) k_resid<<<1, 64, 0, st>>>(g.nblock, g.nw, rpart, resid);
+}
+
+// velocity-chunk width of the micro sweep for a block height
+int micro_kc(int dim, int max_nj) {
+  if (dim == 1) return 64;
+  int kc = 16;
+  while (kc > 1 && kc * max_nj > 1024) kc >>= 1;
+  return kc;
+}
+
+size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj) {
+  int kc = micro_kc(dim, max_nj);
+  int nslot = (dim == 1) ? 1 : max_nj;
+  return sizeof(double) * (size_t)(4 * nslot * kc + 2 * nslot * NCREC + (any_pj ? 2 * max_ni * kc : 0));
+}
+
+template <int D, class T>
+static void micro_t(const Dev& g, const int* binfo, int KC, int nslot, size_t lds, double dt, const double* crec,
+                    void* h, void* b, const void* Sh, const void* Sb, void* Dh, void* Db, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_micro<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  dim3 grid((unsigned)((g.nv + KC - 1) / KC), (unsigned)g.nblock);
+  int threads = ((nslot * KC + 63) / 64) * 64;
+  k_micro<D, T><<<grid, threads, lds, st>>>(g, binfo, KC, nslot, dt, crec, (T*)h, (T*)b, (const T*)Sh,
+                                            (const T*)Sb, (T*)Dh, (T*)Db);
 }
 
 void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
                   const double* crec, void* h, void* b, const void* Sh, const void* Sb, void* Dh, void* Db,
                   hipStream_t st) {
-  int KC, nslot;
-  if (g.dim == 1) { KC = 64; nslot = 1; }
-  else {
-    KC = 16;
-    nslot = max_nj < 64 ? ((max_nj + 3) / 4) * 4 : 64;
+  int KC = micro_kc(g.dim, max_nj);
+  int nslot = (g.dim == 1) ? 1 : max_nj;
+  size_t lds = micro_lds(g.dim, max_ni, max_nj, any_pj);
+  if (g.dim == 2) {
+    if (prec == 0) micro_t<2, double>(g, binfo, KC, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st);
+    else micro_t<2, float>(g, binfo, KC, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st);
+  } else {
+    if (prec == 0) micro_t<1, double>(g, binfo, KC, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st);
+    else micro_t<1, float>(g, binfo, KC, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st);
   }
-  size_t lds = sizeof(double) * (size_t)(2 * nslot * KC * 2 + (any_pj ? max_ni * KC * 2 : 0));
-  dim3 grid((unsigned)((g.nv + KC - 1) / KC), (unsigned)g.nblock);
-  if (prec == 0)
-    k_micro<double><<<grid, nslot * KC, lds, st>>>(g, binfo, KC, dt, crec, (double*)h, (double*)b,
-                                                   (const double*)Sh, (const double*)Sb, (double*)Dh, (double*)Db);
-  else
-    k_micro<float><<<grid, nslot * KC, lds, st>>>(g, binfo, KC, dt, crec, (float*)h, (float*)b,
-                                                  (const float*)Sh, (const float*)Sb, (float*)Dh, (float*)Db);
 }
 
 }  // namespace ugks

@@ -333,6 +333,18 @@ def cavity(n: int = 16, nv: int = 16, kn: float = 0.1, lid: float = 0.5, periodi
                 np.tile(winf, (n * n, 1)), dt_over_dts=10.0)
 
 
+def channel(ni: int = 6, nj: int = 70, nv: int = 8, kn: float = 0.1, lid: float = 0.4) -> Case:
+    """Periodic channel [0, 1] x [0, nj/ni]: diffuse walls below and above, the
+    upper wall moving along +x (a tall block for the sweep variants)."""
+    blk = cartesian_block(ni, nj, 0.0, 1.0, 0.0, nj / ni, (PERIODIC, PERIODIC, WALL, WALL),
+                          vwx=(0.0, 0.0, 0.0, lid))
+    vmax = 5.0 * math.sqrt(0.5)
+    v = uniform_points(nv, -vmax, vmax)
+    winf = cons(2, 1.0, [0.0, 0.0], 0.5)
+    return Case(f"channel{nj}", 2, 2.0 / 3.0, 0.5, mu_ref_from_kn(kn, 0.5), 0.5, v, v.copy(),
+                (-vmax, vmax, -vmax, vmax), winf, [blk], np.tile(winf, (ni * nj, 1)), dt_over_dts=10.0)
+
+
 def moving_body_box(ni_bg: int = 24, nb: int = 16, njb: int = 6, nv: int = 12, kn: float = 0.1,
                     seed: int = SEED) -> Case:
     """Small overset case: a periodic background box and a circular body grid

@@ -27,7 +27,7 @@ def small_cases():
     wallmov.motion = lambda t: [(0.0, 0.03 * t, 0.2 * t, 0.0, 0.03, 0.2)]
     return [wl.sod_1d(ncell=40, nv=33), wl.periodic_box(1, 12, 1, 17), wl.periodic_box(2, 8, 6, 10),
             wl.cylinder(ni=16, nj=8, nvx=16), wl.cavity(8, 12), wl.cavity(6, 10, periodic_x=True),
-            mov, wallmov]
+            mov, wallmov, wl.channel(6, 70, 8), wl.channel(5, 130, 6)]
 
 
 CASES = small_cases()
