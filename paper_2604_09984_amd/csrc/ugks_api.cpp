@@ -74,7 +74,7 @@ struct ugks_ctx {
   // scratch
   void *s_gW = nullptr, *s_rec = nullptr, *s_gam = nullptr, *s_R = nullptr, *s_Dg = nullptr, *s_dWs = nullptr,
        *s_dW = nullptr, *s_Wp = nullptr, *s_rpart = nullptr, *s_crec = nullptr, *s_mrec = nullptr,
-       *s_Dh = nullptr, *s_Db = nullptr, *s_F = nullptr;
+       *s_Dh = nullptr, *s_Db = nullptr, *s_F = nullptr, *s_part = nullptr;
   // overset
   int nrec = 0;
   void *d_rec = nullptr, *d_ptr = nullptr, *d_don = nullptr, *d_w = nullptr;
@@ -399,7 +399,7 @@ void free_all(ugks_ctx* c) {
   void* ps[] = {c->d_vx, c->d_vy, c->d_wk, c->d_vol, c->d_G, c->d_cdx, c->d_dtp, c->d_type, c->d_nb, c->d_cf,
                 c->d_fcell, c->d_fgeo, c->d_fact, c->d_finf_h, c->d_finf_b, c->d_binfo, c->d_mgeo, c->s_gW, c->s_rec,
                 c->s_gam, c->s_R, c->s_Dg, c->s_dWs, c->s_dW, c->s_Wp, c->s_rpart, c->s_crec, c->s_mrec,
-                c->s_Dh, c->s_Db, c->s_F, c->d_rec, c->d_ptr, c->d_don, c->d_w};
+                c->s_Dh, c->s_Db, c->s_F, c->s_part, c->d_rec, c->d_ptr, c->d_don, c->d_w};
   for (void* p : ps)
     if (p) (void)hipFree(p);
 }
@@ -543,7 +543,7 @@ int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
   if (!rc) rc = alloc(c->s_gW, sizeof(double) * 8 * c->ncell);
   if (!rc) rc = alloc(c->s_rec, sizeof(double) * NREC * (size_t)c->nface);
   if (!rc) rc = alloc(c->s_gam, sizeof(double) * c->nface);
-  if (!rc) rc = alloc(c->s_R, sizeof(double) * c->nw * (size_t)c->ncell);
+  if (!rc) rc = alloc(c->s_R, sizeof(double) * 64 * (size_t)c->ncell);  // macro record
   if (!rc) rc = alloc(c->s_Dg, sizeof(double) * c->ncell);
   if (!rc) rc = alloc(c->s_dWs, sizeof(double) * c->nw * (size_t)c->ncell);
   if (!rc) rc = alloc(c->s_dW, sizeof(double) * c->nw * (size_t)c->ncell);
@@ -554,6 +554,7 @@ int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
   if (!rc) rc = alloc(c->s_Dh, tsize(c) * N);
   if (!rc) rc = alloc(c->s_Db, tsize(c) * N);
   if (!rc) rc = alloc(c->s_F, sizeof(double) * c->nw * (size_t)c->nface);
+  if (!rc) rc = alloc(c->s_part, sizeof(double) * flux_part_doubles(c->nv, c->nface));
   if (rc) { free_all(c); delete c; return rc; }
   // scratch that kernels read before writing everywhere starts at zero
   if (hipMemset(c->s_rec, 0, sizeof(double) * NREC * (size_t)c->nface) != hipSuccess ||
@@ -719,7 +720,8 @@ int ugks_flux(ugks_ctx* c, double dts, const void* h, const void* b, const doubl
   if (wall) HIPCHK(hipMemsetAsync(wall, 0, sizeof(double) * (c->nw + 1) * (size_t)c->nface, st));
   double* Fo = F ? F : (double*)c->s_F;
   HIPCHK(hipMemsetAsync(Fo, 0, sizeof(double) * c->nw * (size_t)c->nface, st));
-  launch_flux(c->dev, c->prec, dts, h, b, W, q, (double*)c->s_gW, (double*)c->s_rec, Dh, Db, Fo, wall, st);
+  launch_flux(c->dev, c->prec, (const int*)c->d_binfo, c->max_nj, dts, h, b, W, q, (double*)c->s_gW,
+              (double*)c->s_rec, (double*)c->s_part, Dh, Db, Fo, wall, st);
   HIPCHK(hipGetLastError());
   return UGKS_OK;
 }
@@ -741,7 +743,8 @@ int ugks_begin_step(ugks_ctx* c, double dt, void* h, void* b, double* W, double*
                 (const double*)c->d_w, h, b, W, q, st);
   HIPCHK(hipMemsetAsync(Fn, 0, sizeof(double) * c->nw * (size_t)c->nface, st));
   // the level-n divergence is staged in Sh, Sb
-  launch_flux(c->dev, c->prec, c->dts, h, b, W, q, (double*)c->s_gW, (double*)c->s_rec, Sh, Sb, Fn, nullptr, st);
+  launch_flux(c->dev, c->prec, (const int*)c->d_binfo, c->max_nj, c->dts, h, b, W, q, (double*)c->s_gW,
+              (double*)c->s_rec, (double*)c->s_part, Sh, Sb, Fn, nullptr, st);
   launch_cellrec(c->dev, dt, W, q, nullptr, (double*)c->s_crec, st);
   launch_source(c->dev, c->prec, dt, h, b, (const double*)c->s_crec, Sh, Sb, st);
   HIPCHK(hipGetLastError());
@@ -764,8 +767,8 @@ static int run_inner(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, 
     launch_interp(g, c->prec, c->nrec, (const int*)c->d_rec, (const int*)c->d_ptr, (const int*)c->d_don,
                   (const double*)c->d_w, h, b, W, q, st);
     if (e) HIPCHK(hipEventRecord(e[1], st));
-    launch_flux(g, c->prec, c->dts, h, b, W, q, (double*)c->s_gW, (double*)c->s_rec, c->s_Dh, c->s_Db, F,
-                nullptr, st, e ? e + 2 : nullptr);
+    launch_flux(g, c->prec, (const int*)c->d_binfo, c->max_nj, c->dts, h, b, W, q, (double*)c->s_gW,
+                (double*)c->s_rec, (double*)c->s_part, c->s_Dh, c->s_Db, F, nullptr, st, e ? e + 2 : nullptr);
     if (e) HIPCHK(hipEventRecord(e[4], st));
     launch_macro(g, (const int*)c->d_binfo, c->max_ni, c->max_nj, c->any_pj, dt, W, Wn, F, Fn,
                  (double*)c->s_gam, (double*)c->s_R,

@@ -233,10 +233,29 @@ __device__ inline void expansion(int dim, double rho, double U, double V, double
 // ------------------------------------------------------------------------
 // wavefront reduction (64 lanes)
 // ------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// lane permutation of a double through DPP (both 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_read(double v, int l) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the 64 lanes, returned to every lane: pairs, quads, half rows
+// and rows of 16 through DPP, then the four row sums in a fixed order
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_perm<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_perm<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_perm<0x141>(v);  // row_half_mirror
+  v += dpp_perm<0x140>(v);  // row_mirror
+  return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
 template <class T>

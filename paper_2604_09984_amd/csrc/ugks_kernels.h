@@ -7,9 +7,11 @@ namespace ugks {
 int micro_kc(int dim, int max_nj);
 size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj);
 
-void launch_flux(const Dev& g, int prec, double dts, const void* h, const void* b, const double* W,
-                 const double* q, double* gW, double* rec, void* Dh, void* Db, double* F, double* wall,
-                 hipStream_t st, hipEvent_t* ev = nullptr);
+void launch_flux(const Dev& g, int prec, const int* binfo, int max_nj, double dts, const void* h, const void* b,
+                 const double* W, const double* q, double* gW, double* rec, double* part, void* Dh, void* Db,
+                 double* F, double* wall, hipStream_t st, hipEvent_t* ev = nullptr);
+// doubles of the per-chunk partial-sum scratch of the flux
+inline size_t flux_part_doubles(int nv, int nface) { return (size_t)((nv + 63) / 64) * (size_t)nface * 9; }
 void launch_moments(const Dev& g, int prec, const void* h, const void* b, double* W, double* q, hipStream_t st);
 void launch_maxwellian(const Dev& g, int prec, const double* W, void* h, void* b, hipStream_t st);
 void launch_interp(const Dev& g, int prec, int nrec, const int* rec, const int* ptr, const int* don,

@@ -481,6 +481,407 @@ __global__ __launch_bounds__(256) void k_flux(Dev g, const T* __restrict__ h, co
 }
 
 // ------------------------------------------------------------------------
+// row-group march (2D).  A workgroup holds RG core rows and the rows just
+// below and above them (RG + 2 wavefronts) of one block, for one chunk of 64
+// velocities, and marches along i.  At column x every wavefront reconstructs
+// the next cell of its row once (values and gradients of h and b into LDS);
+// then the core wavefronts evaluate the i-face (x|x+1) of their row and every
+// wavefront below the top halo the j-face above its row at column x; in
+// flux mode the core rows then gather the divergence of cell x.  Face
+// moments (MODE 0) and macro fluxes (MODE 1) are written as per-chunk
+// partial sums, reduced over chunks by the finalize kernels in a fixed order.
+// ------------------------------------------------------------------------
+constexpr int kMomP = 9;   // partial values per face and chunk, MODE 0
+constexpr int kFluxP = 4;  // MODE 1
+
+template <class C>
+struct LD6 {
+  C hv, hx, hy, bv, bx, by;
+};
+
+template <class T, class C>
+__device__ __forceinline__ C cfetch(const T* __restrict__ f, const T* __restrict__ finf, int code, C self, int nv,
+                                    int k) {
+  if (code >= 0) return (C)f[(size_t)code * nv + k];
+  if (code == kNbFar) return (C)finf[k];
+  return self;
+}
+
+template <class C>
+__device__ __forceinline__ C climit(int lo, int hi, C vlo, C v0, C vhi) {
+  if (lo == kNbMiss || hi == kNbMiss) return C(0);
+  if (lo == kNbWall && hi == kNbWall) return C(0);
+  if (lo == kNbWall) return vhi - v0;
+  if (hi == kNbWall) return v0 - vlo;
+  C s1 = v0 - vlo, s2 = vhi - v0;
+  C vl = (s1 * fabs(s2) + fabs(s1) * s2) / (fabs(s1) + fabs(s2));
+  return (s1 * s2 <= C(0)) ? C(0) : vl;
+}
+
+// value and physical gradient of one component at cell c (codes nbc)
+template <class T, class C>
+__device__ __forceinline__ void cell_recon(const Dev& g, const T* __restrict__ f, const T* __restrict__ finf, int c,
+                                           const int* nbc, const double* G, int k, C& v, C& gx, C& gy) {
+  v = (C)f[(size_t)c * g.nv + k];
+  C n0 = cfetch<T, C>(f, finf, nbc[0], v, g.nv, k), n1 = cfetch<T, C>(f, finf, nbc[1], v, g.nv, k);
+  C n2 = cfetch<T, C>(f, finf, nbc[2], v, g.nv, k), n3 = cfetch<T, C>(f, finf, nbc[3], v, g.nv, k);
+  C si = climit<C>(nbc[0], nbc[1], n0, v, n1);
+  C sj = climit<C>(nbc[2], nbc[3], n2, v, n3);
+  gx = (C)G[0] * si + (C)G[1] * sj;
+  gy = (C)G[2] * si + (C)G[3] * sj;
+}
+
+// data of one side of a face: reconstructed value at the face and gradient
+template <class C>
+struct Side {
+  C hv, bv, hx, hy, bx, by;
+};
+
+template <class T, class C>
+__device__ __forceinline__ Side<C> side_from_cell(const Dev& g, const LD6<C>& L, int c, int slot) {
+  Side<C> S;
+  C dx = (C)g.cdx[8 * c + 2 * slot], dy = (C)g.cdx[8 * c + 2 * slot + 1];
+  S.hv = L.hv + L.hx * dx + L.hy * dy;
+  S.bv = L.bv + L.bx * dx + L.by * dy;
+  S.hx = L.hx; S.hy = L.hy; S.bx = L.bx; S.by = L.by;
+  return S;
+}
+
+// ghost side (far field or copy of the interior cell c with data L), zero slope
+template <class T, class C>
+__device__ __forceinline__ Side<C> side_ghost(const Dev& g, const LD6<C>& L, int code, int k) {
+  Side<C> S;
+  const T* hinf = (const T*)g.finf_h;
+  const T* binf = (const T*)g.finf_b;
+  S.hv = (code == kNbFar) ? (C)hinf[k] : L.hv;
+  S.bv = (code == kNbFar) ? (C)binf[k] : L.bv;
+  S.hx = S.hy = S.bx = S.by = C(0);
+  return S;
+}
+
+template <int RG, class T, class C, int MODE>
+__global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __restrict__ binfo, int nchunk,
+                                                         const T* __restrict__ h, const T* __restrict__ b,
+                                                         const double* __restrict__ W,
+                                                         const double* __restrict__ rec,
+                                                         double* __restrict__ part, T* __restrict__ Dh,
+                                                         T* __restrict__ Db) {
+  __shared__ LD6<C> lds[2][RG + 2][64];
+  __shared__ C jfl[RG + 2][2][64];  // j-face flux above each row (h, b)
+  const int* bi = binfo + 8 * blockIdx.z;
+  const int ni = bi[0], nj = bi[1], c0 = bi[2], per_i = bi[3], per_j = bi[4];
+  const int j0 = blockIdx.y * RG;
+  if (j0 >= nj) return;  // whole workgroup
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int chunk = blockIdx.x;
+  const int k = chunk * 64 + lane;
+  const bool kin = k < g.nv;
+  const int kk = kin ? k : g.nv - 1;
+  const double vx = g.vx[kk], vy = g.vy[kk];
+  const double wk = kin ? g.wk[kk] : 0.0;
+  const T* hinf = (const T*)g.finf_h;
+  const T* binf = (const T*)g.finf_b;
+  // this wavefront's row (periodic wrap for the halo rows)
+  int jr = j0 - 1 + w;
+  if (jr < 0) jr = per_j ? jr + nj : -1;
+  else if (jr >= nj) jr = per_j ? jr - nj : -1;
+  const bool core = (w >= 1) && (w <= RG) && (j0 - 1 + w < nj);
+  // the row above exists in the block (or by periodicity)
+  auto cell = [&](int x, int j) -> int { return c0 + x + ni * j; };
+  // reconstruction of cell (x, jr) into LDS slot (x & 1)
+  auto recon_step = [&](int x) {
+    if (jr < 0) return;
+    int xx = x;
+    if (xx >= ni) { if (!per_i) return; xx -= ni; }
+    if (xx < 0) { if (!per_i) return; xx += ni; }
+    const int c = __builtin_amdgcn_readfirstlane(cell(xx, jr));
+    if (g.type[c] == 0) return;
+    int nbc[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) nbc[s] = g.nb[4 * c + s];
+    const double* G = g.G + 4 * c;
+    LD6<C> L;
+    cell_recon<T, C>(g, h, hinf, c, nbc, G, kk, L.hv, L.hx, L.hy);
+    cell_recon<T, C>(g, b, binf, c, nbc, G, kk, L.bv, L.bx, L.by);
+    lds[x & 1][w][lane] = L;
+  };
+  // upwind interface data of a face between sides sl (low) and sh (high)
+  // with normal (nx, ny) and mesh velocity (ux, uy)
+  auto face_eval = [&](int f, const Side<C>& sl, const Side<C>& sh, int owner_write, double* facc) -> void {
+    const double* fg = g.fgeo + (size_t)f * 8;
+    const double nx = fg[0], ny = fg[1], ux = fg[3], uy = fg[4];
+    const double wn = exact_wn(vx, vy, ux, uy, nx, ny);
+    const double* r = rec + (size_t)f * NREC;
+    if (MODE == 0) {
+      // moments of the upwind data about the mean velocity of the sides
+      const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
+      const int inner = (L >= 0) ? L : R;
+      auto vel = [&](int code, double& ax, double& ay) {
+        const double* Wc = (code >= 0) ? W + (size_t)code * 4 : ((code == kNbFar) ? g.winf : W + (size_t)inner * 4);
+        ax = Wc[1] / Wc[0];
+        ay = Wc[2] / Wc[0];
+      };
+      double u1, v1, u2, v2;
+      vel(L, u1, v1);
+      vel(R, u2, v2);
+      const double sx = 0.5 * (u1 + u2), sy = 0.5 * (v1 + v2);
+      double fh = (wn > 0.0) ? (double)sl.hv : ((wn < 0.0) ? (double)sh.hv : 0.5 * ((double)sl.hv + (double)sh.hv));
+      double fb = (wn > 0.0) ? (double)sl.bv : ((wn < 0.0) ? (double)sh.bv : 0.5 * ((double)sl.bv + (double)sh.bv));
+      const double cx = vx - sx, cy = vy - sy;
+      const double e = (cx * cx + cy * cy) * fh + fb;
+      const double wh = wk * fh, we = wk * e;
+      double m[kMomP] = {wh, wh * cx, wh * cy, we, wh * cx * cx, wh * cx * cy, wh * cy * cy, we * cx, we * cy};
+#pragma unroll
+      for (int q = 0; q < kMomP; ++q) m[q] = wave_sum(m[q]);
+      if (owner_write && lane == 0) {
+        double* o = part + ((size_t)chunk * g.nface + f) * kMomP;
+#pragma unroll
+        for (int q = 0; q < kMomP; ++q) o[q] = m[q];
+      }
+      return;
+    }
+    FaceEq<C> e;
+    e.load(r);
+    const bool up_low = wn > 0.0;
+    const Side<C>& u = up_low ? sl : sh;
+    C Ih, Ib;
+    interface_avg<C>(e, 2, 1, (C)vx, (C)vy, (C)(vx - ux), (C)(vy - uy), u.hv, u.bv, u.hx, u.hy, u.bx, u.by, Ih, Ib);
+    double fh = (wn != 0.0) ? wn * (double)Ih : 0.0;
+    double fb = (wn != 0.0) ? wn * (double)Ib : 0.0;
+    fh = kin ? fh : 0.0;
+    fb = kin ? fb : 0.0;
+    facc[0] = fh;
+    facc[1] = fb;
+    double m[kFluxP] = {wk * fh, wk * vx * fh, wk * vy * fh, wk * 0.5 * ((vx * vx + vy * vy) * fh + fb)};
+    if (owner_write) {
+#pragma unroll
+      for (int q = 0; q < kFluxP; ++q) m[q] = wave_sum(m[q]);
+      if (lane == 0) {
+        double* o = part + ((size_t)chunk * g.nface + f) * kFluxP;
+#pragma unroll
+        for (int q = 0; q < kFluxP; ++q) o[q] = m[q];
+      }
+    }
+  };
+  // wall face seen from the interior cell c (slot s) with data L
+  auto wall_eval = [&](int f, int c, int s, const LD6<C>& L, int owner_write, double* facc) -> void {
+    const double* fg = g.fgeo + (size_t)f * 8;
+    const double* r = rec + (size_t)f * NREC;
+    const double sg = r[R_SGN];
+    const double wn = exact_wn(vx, vy, fg[3], fg[4], sg * fg[0], sg * fg[1]);
+    Side<C> S = side_from_cell<T, C>(g, L, c, s);
+    FaceEq<C> e;
+    e.load(r);
+    C Ih, Ib;
+    interface_avg<C>(e, 2, 1, (C)vx, (C)vy, (C)(vx - fg[3]), (C)(vy - fg[4]), S.hv, S.bv, S.hx, S.hy, S.bx, S.by,
+                     Ih, Ib);
+    if (MODE == 0) {
+      const double cx = vx - r[R_VWX], cy = vy - r[R_VWY];
+      const double hw = r[R_HWN] * exp(-r[R_LAMW] * (cx * cx + cy * cy));
+      double num = (wn > 0.0) ? wk * wn * (double)Ih : 0.0;
+      double den = (wn < 0.0) ? wk * wn * hw : 0.0;
+      num = wave_sum(num);
+      den = wave_sum(den);
+      if (owner_write && lane == 0) {
+        double* o = part + ((size_t)chunk * g.nface + f) * kMomP;
+        o[0] = num; o[1] = den;
+        for (int q = 2; q < kMomP; ++q) o[q] = 0.0;
+      }
+      return;
+    }
+    const double cx = vx - r[R_VWX], cy = vy - r[R_VWY];
+    const double hw = r[R_RHOW] * r[R_HWN] * exp(-r[R_LAMW] * (cx * cx + cy * cy));
+    const double rt = 0.5 / r[R_LAMW];
+    double fh = (wn > 0.0) ? sg * wn * (double)Ih : ((wn < 0.0) ? sg * wn * hw : 0.0);
+    double fb = (wn > 0.0) ? sg * wn * (double)Ib : ((wn < 0.0) ? sg * wn * rt * hw : 0.0);
+    fh = kin ? fh : 0.0;
+    fb = kin ? fb : 0.0;
+    facc[0] = fh;
+    facc[1] = fb;
+    double m[kFluxP] = {wk * fh, wk * vx * fh, wk * vy * fh, wk * 0.5 * ((vx * vx + vy * vy) * fh + fb)};
+    if (owner_write) {
+#pragma unroll
+      for (int q = 0; q < kFluxP; ++q) m[q] = wave_sum(m[q]);
+      if (lane == 0) {
+        double* o = part + ((size_t)chunk * g.nface + f) * kFluxP;
+#pragma unroll
+        for (int q = 0; q < kFluxP; ++q) o[q] = m[q];
+      }
+    }
+  };
+  // generic face between cell (x, jr) side slot s and its neighbour, given
+  // LDS data of both sides when they are cells; returns the flux along the
+  // face normal in facc
+  double fi_prev[2] = {0.0, 0.0};  // i-face (x-1|x) of this row
+  if (per_i) recon_step(-1);
+  __syncthreads();
+  for (int x = -1; x < ni; ++x) {
+    // reconstruction of the next cell
+    if (x + 1 <= ni) recon_step(x + 1);
+    __syncthreads();
+    double fi_cur[2] = {0.0, 0.0}, fj_cur[2] = {0.0, 0.0};
+    // i-face (x|x+1) of a core row
+    if (core && jr >= 0) {
+      const int cl = (x >= 0) ? cell(x, jr) : -1;
+      const int cr = (x + 1 < ni) ? cell(x + 1, jr) : -1;
+      int f;
+      if (cl >= 0) f = g.cf[4 * cl + 1];
+      else f = g.cf[4 * cr + 0];
+      if (f >= 0 && g.fact[f]) {
+        const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
+        // owner: the low cell, or the cell of a boundary face; a periodic
+        // seam face (x = -1) is written by the high end of the row
+        const bool owner = (x >= 0) || (L < 0);
+        if (L == kNbWall || R == kNbWall) {
+          const int c = (L == kNbWall) ? R : L;
+          const int s = (L == kNbWall) ? 0 : 1;
+          const int xc = (L == kNbWall) ? x + 1 : x;
+          wall_eval(f, c, s, lds[xc & 1][w][lane], owner, fi_cur);
+        } else {
+          Side<C> sl, sh;
+          // the low side of the seam face (x = -1) is cell ni-1, staged in slot (-1) & 1
+          if (L >= 0) sl = side_from_cell<T, C>(g, lds[x & 1][w][lane], L, 1);
+          if (R >= 0) sh = side_from_cell<T, C>(g, lds[(x + 1) & 1][w][lane], R, 0);
+          if (L < 0) sl = side_ghost<T, C>(g, lds[(x + 1) & 1][w][lane], L, kk);
+          if (R < 0) sh = side_ghost<T, C>(g, lds[x & 1][w][lane], R, kk);
+          face_eval(f, sl, sh, owner, fi_cur);
+        }
+      }
+    }
+    // j-face (jr|jr+1) at column x, for the bottom halo and the core rows
+    if (x >= 0 && w <= RG && (j0 - 1 + w < nj)) {
+      const int jl = jr;                                     // low row (may be absent: boundary below)
+      const int jh = (j0 + w < nj) ? j0 + w : (per_j ? j0 + w - nj : -1);  // high row
+      int f = -1, Lc = -1, Hc = -1;
+      if (jl >= 0) { Lc = cell(x, jl); f = g.cf[4 * Lc + 3]; }
+      if (jh >= 0) { Hc = cell(x, jh); if (f < 0) f = g.cf[4 * Hc + 2]; }
+      if (f >= 0 && g.fact[f]) {
+        const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
+        // core rows own the face above them; the bottom halo writes only
+        // the block's lower boundary face
+        const bool owner = (w >= 1) || (L < 0);
+        if (L == kNbWall || R == kNbWall) {
+          const int c = (L == kNbWall) ? R : L;
+          const int s = (L == kNbWall) ? 2 : 3;
+          const int wc = (L == kNbWall) ? w + 1 : w;
+          wall_eval(f, c, s, lds[x & 1][wc][lane], owner, fj_cur);
+        } else {
+          Side<C> sl, sh;
+          if (L >= 0) sl = side_from_cell<T, C>(g, lds[x & 1][w][lane], L, 3);
+          if (R >= 0) sh = side_from_cell<T, C>(g, lds[x & 1][w + 1][lane], R, 2);
+          if (L < 0) sl = side_ghost<T, C>(g, lds[x & 1][w + 1][lane], L, kk);
+          if (R < 0) sh = side_ghost<T, C>(g, lds[x & 1][w][lane], R, kk);
+          face_eval(f, sl, sh, owner, fj_cur);
+        }
+      }
+      if (MODE == 1) { jfl[w][0][lane] = (C)fj_cur[0]; jfl[w][1][lane] = (C)fj_cur[1]; }
+    }
+    if (MODE == 1) {
+      __syncthreads();
+      // divergence of cell (x, jr) of a core row
+      if (core && jr >= 0 && x >= 0) {
+        const int c = cell(x, jr);
+        if (kin) {
+          double dh = 0.0, db = 0.0;
+          if (g.type[c] == 1) {
+            const double ivol = 1.0 / g.vol[c];
+            const int f0 = g.cf[4 * c], f1 = g.cf[4 * c + 1], f2 = g.cf[4 * c + 2], f3 = g.cf[4 * c + 3];
+            const double S0 = (f0 >= 0) ? g.fgeo[(size_t)f0 * 8 + 2] : 0.0;
+            const double S1 = (f1 >= 0) ? g.fgeo[(size_t)f1 * 8 + 2] : 0.0;
+            const double S2 = (f2 >= 0) ? g.fgeo[(size_t)f2 * 8 + 2] : 0.0;
+            const double S3 = (f3 >= 0) ? g.fgeo[(size_t)f3 * 8 + 2] : 0.0;
+            const double bh = (double)jfl[w - 1][0][lane], bb = (double)jfl[w - 1][1][lane];
+            dh = -ivol * (-S0 * fi_prev[0] + S1 * fi_cur[0] - S2 * bh + S3 * fj_cur[0]);
+            db = -ivol * (-S0 * fi_prev[1] + S1 * fi_cur[1] - S2 * bb + S3 * fj_cur[1]);
+          }
+          Dh[(size_t)c * g.nv + k] = (T)dh;
+          Db[(size_t)c * g.nv + k] = (T)db;
+        }
+      }
+    }
+    fi_prev[0] = fi_cur[0];
+    fi_prev[1] = fi_cur[1];
+    __syncthreads();
+  }
+}
+
+// face records from the chunk partials of the face moments (interior and
+// ghost faces) and the wall density (wall faces)
+__global__ void k_face_fin(Dev g, double dts, int nchunk, const double* __restrict__ part,
+                           const double* __restrict__ W, const double* __restrict__ gW, double* __restrict__ rec) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= g.nface || !g.fact[f]) return;
+  const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
+  double m[kMomP];
+  for (int q = 0; q < kMomP; ++q) m[q] = 0.0;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const double* p = part + ((size_t)ch * g.nface + f) * kMomP;
+    for (int q = 0; q < kMomP; ++q) m[q] += p[q];
+  }
+  double* r = rec + (size_t)f * NREC;
+  if (L == kNbWall || R == kNbWall) {
+    r[R_RHOW] = -m[0] / m[1];
+    return;
+  }
+  const int inner = (L >= 0) ? L : R;
+  auto vel = [&](int code, double& ax, double& ay) {
+    const double* Wc = (code >= 0) ? W + (size_t)code * 4 : ((code == kNbFar) ? g.winf : W + (size_t)inner * 4);
+    ax = Wc[1] / Wc[0];
+    ay = Wc[2] / Wc[0];
+  };
+  double u1, v1, u2, v2;
+  vel(L, u1, v1);
+  vel(R, u2, v2);
+  const double sx = 0.5 * (u1 + u2), sy = 0.5 * (v1 + v2);
+  const double m0 = m[0], m1x = m[1], m1y = m[2], m2 = m[3], pxx = m[4], pxy = m[5], pyy = m[6], m3x = m[7],
+               m3y = m[8];
+  const double rho = m0;
+  const double dx = m1x / m0, dy = m1y / m0;
+  const double ux = sx + dx, uy = sy + dy;
+  const double eint = 0.5 * (m2 - (m1x * m1x + m1y * m1y) / m0);
+  const double lam = 0.75 * rho / eint;
+  const double dd = dx * dx + dy * dy;
+  const double qx = 0.5 * (m3x - 2.0 * (pxx * dx + pxy * dy) - dx * m2 + 2.0 * m0 * dd * dx);
+  const double qy = 0.5 * (m3y - 2.0 * (pxy * dx + pyy * dy) - dy * m2 + 2.0 * m0 * dd * dy);
+  r[R_RHO] = rho; r[R_UX] = ux; r[R_UY] = uy; r[R_LAM] = lam; r[R_QX] = qx; r[R_QY] = qy;
+  r[R_HN] = rho * (lam / kPi);
+  r[R_SH] = 4.0 * (1.0 - g.pr) * lam * lam / (5.0 * rho);
+  double dW[8];
+  for (int q = 0; q < 8; ++q) {
+    double gl = (L >= 0) ? gW[(size_t)L * 8 + q] : 0.0;
+    double gr = (R >= 0) ? gW[(size_t)R * 8 + q] : 0.0;
+    dW[q] = 0.5 * (gl + gr);
+  }
+  const double* fg = g.fgeo + (size_t)f * 8;
+  expansion(2, rho, ux, uy, lam, fg[3], fg[4], dW, r + R_AX, r + R_AY, r + R_AT);
+  double tq[5];
+  time_integrals(dts, inv_tau_of(g, rho, lam), tq);
+  for (int q = 0; q < 5; ++q) r[R_T1 + q] = tq[q] / dts;
+  r[R_ACT] = 1.0;
+}
+
+// macro flux per face (and the wall output) from the chunk partials
+__global__ void k_flux_fin(Dev g, int nchunk, const double* __restrict__ part, const double* __restrict__ rec,
+                           double* __restrict__ F, double* __restrict__ wall) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= g.nface || !g.fact[f]) return;
+  double m[kFluxP] = {0, 0, 0, 0};
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const double* p = part + ((size_t)ch * g.nface + f) * kFluxP;
+    for (int q = 0; q < kFluxP; ++q) m[q] += p[q];
+  }
+  if (F) for (int q = 0; q < kFluxP; ++q) F[(size_t)f * 4 + q] = m[q];
+  const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
+  if (wall && (L == kNbWall || R == kNbWall)) {
+    const double* r = rec + (size_t)f * NREC;
+    double* o = wall + (size_t)f * 5;
+    o[0] = r[R_RHOW];
+    for (int q = 0; q < 4; ++q) o[1 + q] = r[R_SGN] * m[q];
+  }
+}
+
+// ------------------------------------------------------------------------
 // moments
 // ------------------------------------------------------------------------
 // plain W and q about the velocity of that W (two passes over the velocities)
@@ -749,33 +1150,57 @@ __global__ void k_gamma(Dev g, const double* __restrict__ W, double* __restrict_
   gam[f] = fabs((mx - fg[3]) * fg[0] + (my - fg[4]) * fg[1]) + 0.5 * (a1 + a2);
 }
 
-// residual R and LU-SGS diagonal per field cell
+// macro record per cell (computed in parallel before the sweep):
+//   [0..3] residual R, [4] 1/D (LU-SGS diagonal), [5] 1/(4|Omega|),
+//   per slot s at 8 + 14 s: neighbour state W_nb (4), its Euler flux
+//   F_E(W_nb; n_out, U_f) (4), n_out (2), U_f.n_out, S, S Gamma, field flag
+constexpr int kMacRec = 64;
+constexpr int kMacSlot = 14;
+
+__device__ __forceinline__ void euler_flux_n(int dim, const double* w, double nx, double ny, double un, double* o);
+
 __global__ void k_macro_prep(Dev g, double dt, const double* __restrict__ W, const double* __restrict__ Wn,
                              const double* __restrict__ F, const double* __restrict__ Fn,
-                             const double* __restrict__ gam, double* __restrict__ R,
-                             double* __restrict__ Dg) {
+                             const double* __restrict__ gam, double* __restrict__ mac) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.ncell) return;
-  int nw = g.nw;
-  if (g.type[c] != 1) {
-    for (int m = 0; m < nw; ++m) R[(size_t)c * nw + m] = 0.0;
-    Dg[c] = 1.0;
-    return;
-  }
-  double ivol = 1.0 / g.vol[c];
-  double r[4], sg = 0.0;
+  const int nw = g.nw;
+  double* M = mac + (size_t)c * kMacRec;
+  for (int m = 0; m < kMacRec; ++m) M[m] = 0.0;
+  if (g.type[c] != 1) return;
+  const double ivol = 1.0 / g.vol[c];
+  double r[4] = {0, 0, 0, 0}, sg = 0.0;
   for (int m = 0; m < nw; ++m) r[m] = -(W[(size_t)c * nw + m] - Wn[(size_t)c * nw + m]) / dt;
   for (int s = 0; s < 2 * g.dim; ++s) {
     int f = g.cf[4 * c + s];
+    double* P = M + 8 + kMacSlot * s;
     if (f < 0) continue;
-    double S = g.fgeo[(size_t)f * 8 + 2];
-    double sig = (s & 1) ? 1.0 : -1.0;
+    const double* fg = g.fgeo + (size_t)f * 8;
+    const double S = fg[2];
+    const double sig = (s & 1) ? 1.0 : -1.0;
     for (int m = 0; m < nw; ++m)
       r[m] -= 0.5 * ivol * sig * S * (F[(size_t)f * nw + m] + Fn[(size_t)f * nw + m]);
     sg += S * gam[f];
+    const int o = g.nb[4 * c + s];
+    const double nx = sig * fg[0], ny = sig * fg[1];
+    const double un = fg[3] * nx + fg[4] * ny;
+    const bool fld = (o >= 0) && g.type[o] == 1;
+    const double* wn = fld ? W + (size_t)o * nw : W + (size_t)c * nw;
+    double wv[4] = {0, 0, 0, 0}, fe[4] = {0, 0, 0, 0};
+    for (int m = 0; m < nw; ++m) wv[m] = wn[m];
+    euler_flux_n(g.dim, wv, nx, ny, un, fe);
+    for (int m = 0; m < 4; ++m) { P[m] = wv[m]; P[4 + m] = fe[m]; }
+    P[8] = nx; P[9] = ny; P[10] = un;
+    P[11] = fld ? S : 0.0;
+    P[12] = fld ? S * gam[f] : 0.0;
+    P[13] = fld ? 1.0 : 0.0;
   }
-  for (int m = 0; m < nw; ++m) R[(size_t)c * nw + m] = r[m];
-  Dg[c] = 1.0 / g.dtp[c] + 1.0 / dt + 0.25 * ivol * sg;
+  for (int m = 0; m < 4; ++m) M[m] = r[m];
+  const double Dg = 1.0 / g.dtp[c] + 1.0 / dt + 0.25 * ivol * sg;
+  M[4] = 1.0 / Dg;
+  M[5] = 0.25 * ivol;
+  M[6] = Dg;
+  M[7] = 0.0;
 }
 
 // ALE Euler flux difference F_E(W + dW) - F_E(W) along n with mesh velocity U
@@ -790,6 +1215,20 @@ __device__ __forceinline__ void euler_flux4(int dim, int nxi, double w0, double 
   o[1] = w1 * th + p * nx;
   if (dim == 2) { o[2] = w2 * th + p * ny; o[3] = wE * th + p * (vx * nx + vy * ny); }
   else o[2] = wE * th + p * vx * nx;
+}
+
+// ALE Euler flux of w along n with the mesh normal velocity un = U.n
+__device__ __forceinline__ void euler_flux_n(int dim, const double* w, double nx, double ny, double un, double* o) {
+  const double ir = 1.0 / w[0];
+  const double vx = w[1] * ir, vy = (dim == 2) ? w[2] * ir : 0.0;
+  const double wE = w[dim + 1];
+  const double p = 2.0 / 3.0 * (wE - 0.5 * w[0] * (vx * vx + vy * vy));  // rho/(2 lam), D + N_xi = 3
+  const double vn = vx * nx + ((dim == 2) ? vy * ny : 0.0);
+  const double th = vn - un;
+  o[0] = w[0] * th;
+  o[1] = w[1] * th + p * nx;
+  if (dim == 2) { o[2] = w[2] * th + p * ny; o[3] = wE * th + p * vn; }
+  else o[2] = wE * th + p * vn;
 }
 
 __device__ __forceinline__ void euler_dflux(int dim, int nxi, const double* W, const double* dW, double nx,
@@ -816,77 +1255,59 @@ __device__ __forceinline__ void euler_dflux(int dim, int nxi, const double* W, c
 // hyperplane's inputs (residual, diagonal, neighbour states and face data)
 // are loaded before the current hyperplane is computed, so their latency
 // overlaps the computation and the barrier.
-struct MacroNb {
-  double W[4], nx, ny, ux, uy, S, G;
-  bool on;
-};
+// macro sweep: one workgroup per block, one thread per row j, hyperplane
+// order.  The inputs of the next hyperplane (macro record: residual or dW*,
+// 1/D, and the two structural couplings) are loaded before the current
+// hyperplane is computed.
 struct MacroRow {
-  int c;
   bool ok, fld;
-  double base[4], Dg, ivd;  // forward: R; backward: dW*
-  MacroNb nb[2];
+  int c;
+  double base[4], iD, ivd;
+  double nb[2][kMacSlot];
 };
 
+// forward (bwd = 0): base = residual from the record, lower couplings;
+// backward: base = dW* (`dws`), upper couplings
 template <int D>
-__device__ __forceinline__ void macro_nb_load(const Dev& g, const double* __restrict__ W,
-                                              const double* __restrict__ gam, int c, int s, int o, MacroNb& N) {
-  N.on = (o >= 0) && g.type[o] == 1;
-  int f = g.cf[4 * c + s];
-  if (f < 0) N.on = false;
-  if (!N.on) return;
-  const double* fg = g.fgeo + (size_t)f * 8;
-  double sg = (s & 1) ? 1.0 : -1.0;
-  N.nx = sg * fg[0]; N.ny = sg * fg[1]; N.ux = fg[3]; N.uy = fg[4]; N.S = fg[2]; N.G = gam[f];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) N.W[m] = (m < D + 2) ? W[(size_t)o * (D + 2) + m] : 0.0;
-}
-
-template <int D>
-__device__ __forceinline__ void macro_apply(const MacroNb& N, const double* x, double* acc) {
-  if (!N.on) return;
-  double dF[4];
-  euler_dflux(D, 3 - D, N.W, x, N.nx, N.ny, N.ux, N.uy, dF);
-#pragma unroll
-  for (int m = 0; m < D + 2; ++m) acc[m] += N.S * (dF[m] - N.G * x[m]);
-}
-
-// inputs of row j on hyperplane h: forward (bwd = 0) reads the residual and
-// the lower neighbours, backward the forward result and the upper neighbours
-template <int D>
-__device__ __forceinline__ void macro_row_load(const Dev& g, const double* __restrict__ W,
-                                               const double* __restrict__ gam, const double* __restrict__ base,
-                                               const double* __restrict__ Dg, int bwd, int ni, int nj, int c0,
-                                               int j, int h, MacroRow& M) {
-  constexpr int nw = D + 2;
+__device__ __forceinline__ void macro_row_load(const double* __restrict__ mac, const double* __restrict__ dws,
+                                               int bwd, int ni, int nj, int c0, int j, int h, MacroRow& M) {
   int i = h - j;
   M.ok = (j < nj) && (i >= 0) && (i < ni);
   M.fld = false;
-  M.nb[0].on = false;
-  M.nb[1].on = false;
   if (!M.ok) return;
-  int c = c0 + i + ni * j;
+  const int c = c0 + i + ni * j;
   M.c = c;
-  M.fld = g.type[c] == 1;
+  const double* R = mac + (size_t)c * kMacRec;
+  M.iD = R[4];
+  M.fld = M.iD > 0.0;
   if (!M.fld) return;
+  M.ivd = R[5];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) M.base[m] = (m < nw) ? base[(size_t)c * nw + m] : 0.0;
-  M.Dg = Dg[c];
-  M.ivd = bwd ? 0.25 / (g.vol[c] * M.Dg) : 0.25 / g.vol[c];
-  if (!bwd) {
-    macro_nb_load<D>(g, W, gam, c, 0, (i >= 1) ? c - 1 : -1, M.nb[0]);
-    macro_nb_load<D>(g, W, gam, c, 2, (j >= 1) ? c - ni : -1, M.nb[1]);
-  } else {
-    macro_nb_load<D>(g, W, gam, c, 1, (i + 1 < ni) ? c + 1 : -1, M.nb[0]);
-    macro_nb_load<D>(g, W, gam, c, 3, (j + 1 < nj) ? c + ni : -1, M.nb[1]);
+  for (int m = 0; m < 4; ++m) M.base[m] = bwd ? ((m < D + 2) ? dws[(size_t)c * (D + 2) + m] : 0.0) : R[m];
+  const int s0 = bwd ? 1 : 0, s1 = bwd ? 3 : 2;
+#pragma unroll
+  for (int m = 0; m < kMacSlot; ++m) {
+    M.nb[0][m] = R[8 + kMacSlot * s0 + m];
+    M.nb[1][m] = (D == 2) ? R[8 + kMacSlot * s1 + m] : 0.0;
   }
+}
+
+// S (F_E(W_nb + x) - F_E(W_nb) - Gamma x) added to acc
+template <int D>
+__device__ __forceinline__ void macro_couple(const double* P, const double* x, double* acc) {
+  if (P[13] == 0.0) return;
+  double w[4], fe[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) w[m] = P[m] + ((m < D + 2) ? x[m] : 0.0);
+  euler_flux_n(D, w, P[8], P[9], P[10], fe);
+#pragma unroll
+  for (int m = 0; m < D + 2; ++m) acc[m] += P[11] * (fe[m] - P[4 + m]) - P[12] * x[m];
 }
 
 template <int D>
 __global__ __launch_bounds__(512) void k_macro_sweep(Dev g, const int* __restrict__ binfo,
                                                      const double* __restrict__ W,
-                                                     const double* __restrict__ R,
-                                                     const double* __restrict__ Dg,
-                                                     const double* __restrict__ gam,
+                                                     const double* __restrict__ mac,
                                                      double* __restrict__ dWs, double* __restrict__ dW,
                                                      double* __restrict__ Wp, double* __restrict__ rpart) {
   extern __shared__ double msm[];
@@ -901,12 +1322,11 @@ __global__ __launch_bounds__(512) void k_macro_sweep(Dev g, const int* __restric
   double rs[4] = {0, 0, 0, 0};
   if (j < nj)
     for (int i = 0; i < ni; ++i) {
-      int c = c0 + i + ni * j;
-      if (g.type[c] != 1) continue;
-      for (int m = 0; m < nw; ++m) rs[m] += R[(size_t)c * nw + m] * R[(size_t)c * nw + m];
+      const double* R = mac + (size_t)(c0 + i + ni * j) * kMacRec;
+      if (!(R[4] > 0.0)) continue;
+      for (int m = 0; m < nw; ++m) rs[m] += R[m] * R[m];
     }
   for (int m = 0; m < 4; ++m) rs[m] = wave_sum(rs[m]);
-  // deterministic combination of the per-wave sums
   __shared__ double wsum[8][4];
   if ((j & 63) == 0) for (int m = 0; m < 4; ++m) wsum[j >> 6][m] = rs[m];
   __syncthreads();
@@ -921,28 +1341,23 @@ __global__ __launch_bounds__(512) void k_macro_sweep(Dev g, const int* __restric
   double prev[4] = {0, 0, 0, 0}, cw[4] = {0, 0, 0, 0};
   MacroRow cur, nxt;
   // forward sweep: (D + L) dW* = R
-  macro_row_load<D>(g, W, gam, R, Dg, 0, ni, nj, c0, j, 0, cur);
+  macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, 0, cur);
   for (int h = 0; h < H; ++h) {
-    if (h + 1 < H) macro_row_load<D>(g, W, gam, R, Dg, 0, ni, nj, c0, j, h + 1, nxt);
+    if (h + 1 < H) macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + 1, nxt);
     if (cur.ok) {
-      int i = h - j, c = cur.c;
+      const int i = h - j, c = cur.c;
       double x[4] = {0, 0, 0, 0};
       if (cur.fld) {
         double acc[4] = {0, 0, 0, 0};
-        macro_apply<D>(cur.nb[0], prev, acc);
-        if (j >= 1) macro_apply<D>(cur.nb[1], hand + ((h - 1) & 1) * NT * 4 + (j - 1) * 4, acc);
-        if (pi && i == ni - 1 && ni > 1) {
-          MacroNb N;
-          macro_nb_load<D>(g, W, gam, c, 1, c - (ni - 1), N);
-          macro_apply<D>(N, cw, acc);
-        }
-        if (pj && j == nj - 1 && nj > 1) {
-          MacroNb N;
-          macro_nb_load<D>(g, W, gam, c, 3, c0 + i, N);
-          macro_apply<D>(N, pjb + 4 * i, acc);
-        }
-        for (int m = 0; m < nw; ++m) x[m] = (cur.base[m] - cur.ivd * acc[m]) / cur.Dg;
+        if (i >= 1) macro_couple<D>(cur.nb[0], prev, acc);
+        if (D == 2 && j >= 1) macro_couple<D>(cur.nb[1], hand + ((h - 1) & 1) * NT * 4 + (j - 1) * 4, acc);
+        if (pi && i == ni - 1 && ni > 1) macro_couple<D>(mac + (size_t)c * kMacRec + 8 + kMacSlot * 1, cw, acc);
+        if (D == 2 && pj && j == nj - 1 && nj > 1)
+          macro_couple<D>(mac + (size_t)c * kMacRec + 8 + kMacSlot * 3, pjb + 4 * i, acc);
+#pragma unroll
+        for (int m = 0; m < nw; ++m) x[m] = (cur.base[m] - cur.ivd * acc[m]) * cur.iD;
       }
+#pragma unroll
       for (int m = 0; m < nw; ++m) {
         dWs[(size_t)c * nw + m] = x[m];
         prev[m] = x[m];
@@ -957,36 +1372,31 @@ __global__ __launch_bounds__(512) void k_macro_sweep(Dev g, const int* __restric
   for (int m = 0; m < 4; ++m) { prev[m] = 0.0; cw[m] = 0.0; }
   __syncthreads();
   // backward sweep: (D + U) dW = D dW*
-  macro_row_load<D>(g, W, gam, dWs, Dg, 1, ni, nj, c0, j, H - 1, cur);
+  macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, H - 1, cur);
   for (int h = H - 1; h >= 0; --h) {
-    if (h >= 1) macro_row_load<D>(g, W, gam, dWs, Dg, 1, ni, nj, c0, j, h - 1, nxt);
+    if (h >= 1) macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 1, nxt);
     if (cur.ok) {
-      int i = h - j, c = cur.c;
+      const int i = h - j, c = cur.c;
       double x[4] = {0, 0, 0, 0};
       if (cur.fld) {
         double acc[4] = {0, 0, 0, 0};
-        macro_apply<D>(cur.nb[0], prev, acc);
-        if (j + 1 < nj) macro_apply<D>(cur.nb[1], hand + ((h + 1) & 1) * NT * 4 + (j + 1) * 4, acc);
-        if (pi && i == 0 && ni > 1) {
-          MacroNb N;
-          macro_nb_load<D>(g, W, gam, c, 0, c + ni - 1, N);
-          macro_apply<D>(N, cw, acc);
-        }
-        if (pj && j == 0 && nj > 1) {
-          MacroNb N;
-          macro_nb_load<D>(g, W, gam, c, 2, c0 + i + ni * (nj - 1), N);
-          macro_apply<D>(N, pjb + 4 * i, acc);
-        }
-        for (int m = 0; m < nw; ++m) x[m] = cur.base[m] - cur.ivd * acc[m];
+        if (i + 1 < ni) macro_couple<D>(cur.nb[0], prev, acc);
+        if (D == 2 && j + 1 < nj) macro_couple<D>(cur.nb[1], hand + ((h + 1) & 1) * NT * 4 + (j + 1) * 4, acc);
+        if (pi && i == 0 && ni > 1) macro_couple<D>(mac + (size_t)c * kMacRec + 8 + kMacSlot * 0, cw, acc);
+        if (D == 2 && pj && j == 0 && nj > 1)
+          macro_couple<D>(mac + (size_t)c * kMacRec + 8 + kMacSlot * 2, pjb + 4 * i, acc);
+#pragma unroll
+        for (int m = 0; m < nw; ++m) x[m] = cur.base[m] - cur.ivd * cur.iD * acc[m];
       }
       // a non-physical predictor keeps the current state
       double wp[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) wp[m] = (m < nw) ? W[(size_t)c * nw + m] + x[m] : 0.0;
       const bool okp = physical_state(D, wp);
+#pragma unroll
       for (int m = 0; m < nw; ++m) {
         dW[(size_t)c * nw + m] = x[m];
-        Wp[(size_t)c * nw + m] = okp ? wp[m] : W[(size_t)c * nw + m];
+        Wp[(size_t)c * nw + m] = (okp && cur.fld) ? wp[m] : W[(size_t)c * nw + m];
         prev[m] = x[m];
         if (i == ni - 1) cw[m] = x[m];
         hand[(h & 1) * NT * 4 + j * 4 + m] = x[m];
@@ -1005,6 +1415,39 @@ __global__ void k_resid(int nblock, int nw, const double* __restrict__ rpart, do
   double s = 0.0;
   for (int b = 0; b < nblock; ++b) s += rpart[(size_t)b * 4 + m];
   out[m] = sqrt(s);
+}
+
+// micro residual r = S - f^s/dt + (D + (f+' - f^s)/tau')/2 of every field
+// pair (Eq. residual_micro_n+1,s with the stored level-n part S), written over
+// D: fully parallel, one wavefront per cell, the cell record is wave-uniform
+template <class T>
+__global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const double* __restrict__ crec,
+                                                   const T* __restrict__ h, const T* __restrict__ b,
+                                                   const T* __restrict__ Sh, const T* __restrict__ Sb,
+                                                   T* __restrict__ Dh, T* __restrict__ Db) {
+  const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  if (c >= g.ncell || g.type[c] != 1) return;
+  const double* r = crec + (size_t)c * NCREC;
+  const double ux = r[C_UX], uy = r[C_UY], lam = r[C_LAM], qx = r[C_QX], qy = r[C_QY];
+  const double hn = r[C_HN], sh = r[C_SH], it = r[C_ITAU];
+  const double idt = 1.0 / dt;
+  const double rt = 0.5 / lam;
+  const int D = g.dim;
+  for (int k = lane; k < g.nv; k += 64) {
+    const size_t o = (size_t)c * g.nv + k;
+    const double cx = g.vx[k] - ux, cy = (D == 2) ? g.vy[k] - uy : 0.0;
+    const double c2 = cx * cx + cy * cy;
+    const double H = hn * exp(-lam * c2);
+    const double B = (double)(3 - D) * rt * H;
+    const double sq = sh * (cx * qx + cy * qy);
+    const double tl = 2.0 * lam * c2;
+    const double hpl = H + sq * (tl - 2.0 - D) * H;
+    const double bpl = B + sq * (tl - D) * (double)(3 - D) * rt * H;
+    const double f0 = (double)h[o], f1 = (double)b[o];
+    Dh[o] = (T)((double)Sh[o] - f0 * idt + 0.5 * ((double)Dh[o] + (hpl - f0) * it));
+    Db[o] = (T)((double)Sb[o] - f1 * idt + 0.5 * ((double)Db[o] + (bpl - f1) * it));
+  }
 }
 
 // micro LU-SGS (Eq. dualTimeStepping_micro): forward and backward sweep of
@@ -1034,7 +1477,7 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   auto CEL = [&](int p) -> double* { return cells + (size_t)(p * nslot + j) * NCREC; };
   auto PJ = [&](int i) -> double* { return pjb + ((size_t)i * KC + lk) * 2; };
   const double vx = g.vx[kk], vy = g.vy[kk];
-  const double idt = 1.0 / dt;
+  (void)dt;
   const int HH = ni + nj - 1;
   const bool row = j < nj;
   double ph = 0.0, pb = 0.0, chh = 0.0, cbb = 0.0;
@@ -1068,14 +1511,13 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
     for (int e = lk + 2 * KC; e < NCREC; e += KC) d[e] = crec[(size_t)c * NCREC + e];
   };
   // streaming values of the next cell of this row
-  double n0 = 0, n1 = 0, n2 = 0, n3 = 0, n4 = 0, n5 = 0;
+  double n2 = 0, n3 = 0, n4 = 0, n5 = 0;
   int ncell_ = -1;
   auto stream_fwd = [&](int hp) {
     ncell_ = cell_of_hp(hp);
     if (ncell_ < 0 || g.type[ncell_] != 1) { ncell_ = -1; return; }
     size_t o = (size_t)ncell_ * g.nv + kk;
-    n0 = (double)Sh[o]; n1 = (double)Sb[o]; n2 = (double)h[o]; n3 = (double)b[o];
-    n4 = (double)Dh[o]; n5 = (double)Db[o];
+    n4 = (double)Dh[o]; n5 = (double)Db[o];  // the residual r
   };
   auto stream_bwd = [&](int hp) {
     ncell_ = cell_of_hp(hp);
@@ -1093,7 +1535,7 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   for (int hp = 0; hp < HH; ++hp) {
     const int p = hp & 1;
     const int c = ncell_;
-    const double s0 = n0, s1 = n1, f0 = n2, f1 = n3, d0v = n4, d1v = n5;
+    const double rh = n4, rb = n5;
     // issue the next hyperplane's loads
     if (hp + 1 < HH) { stage_load(hp + 1); stream_fwd(hp + 1); }
     const int i = hp - j;
@@ -1119,21 +1561,9 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
         const double* q = PJ(i);
         double w = fmin(ts[3], 0.0); oh += w * q[0]; ob += w * q[1];
       }
-      // Shakhov equilibrium of W' and the residual
-      double cx = vx - r[C_UX], cy = (D == 2) ? vy - r[C_UY] : 0.0;
-      double c2 = cx * cx + cy * cy, lam = r[C_LAM];
-      double H = r[C_HN] * exp(-lam * c2);
-      double rt = 0.5 / lam;
-      double B = (double)(3 - D) * rt * H;
-      double sq = r[C_SH] * (cx * r[C_QX] + cy * r[C_QY]);
-      double tl = 2.0 * lam * c2;
-      double hpl = H + sq * (tl - 2.0 - D) * H;
-      double bpl = B + sq * (tl - D) * (double)(3 - D) * rt * H;
-      double it = r[C_ITAU];
-      double rh = s0 - f0 * idt + 0.5 * (d0v + (hpl - f0) * it);
-      double rb = s1 - f1 * idt + 0.5 * (d1v + (bpl - f1) * it);
-      xh = (rh - oh) / d;
-      xb = (rb - ob) / d;
+      const double id = 1.0 / d;
+      xh = (rh - oh) * id;
+      xb = (rb - ob) * id;
       if (kin) {
         size_t o = (size_t)c * g.nv + k;
         Dh[o] = (T)xh;
@@ -1185,8 +1615,9 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
         const double* q = PJ(i);
         double w = fmin(ts[2], 0.0); oh += w * q[0]; ob += w * q[1];
       }
-      xh = x0 - oh / d;
-      xb = x1 - ob / d;
+      const double id = 1.0 / d;
+      xh = x0 - oh * id;
+      xb = x1 - ob * id;
       if (kin) {
         size_t o = (size_t)c * g.nv + k;
         h[o] = (T)(f0 + xh);
@@ -1223,12 +1654,33 @@ void launch_flux_t(const Dev& g, double dts, const void* h, const void* b, const
   k_flux<D, T, C><<<nb4(g.ncell), 256, 0, st>>>(g, (const T*)h, (const T*)b, rec, (T*)Dh, (T*)Db, F, wall);
 }
 
-void launch_flux(const Dev& g, int prec, double dts, const void* h, const void* b, const double* W,
-                 const double* q, double* gW, double* rec, void* Dh, void* Db, double* F, double* wall,
-                 hipStream_t st, hipEvent_t* ev) {
+constexpr int kRowGroup = 8;
+
+template <class T, class C>
+void launch_march_t(const Dev& g, const int* binfo, int max_nj, double dts, const void* h, const void* b,
+                    const double* W, const double* q, double* gW, double* rec, double* part, void* Dh, void* Db,
+                    double* F, double* wall, hipStream_t st, hipEvent_t* ev) {
+  const int nchunk = (g.nv + 63) / 64;
+  dim3 grid((unsigned)nchunk, (unsigned)((max_nj + kRowGroup - 1) / kRowGroup), (unsigned)g.nblock);
+  const int threads = 64 * (kRowGroup + 2);
+  k_gradW<<<nbl(g.ncell, 256), 256, 0, st>>>(g, W, gW);
+  k_wallprep<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, W, q, gW, rec);
+  if (ev) (void)hipEventRecord(ev[0], st);
+  k_march<kRowGroup, T, C, 0><<<grid, threads, 0, st>>>(g, binfo, nchunk, (const T*)h, (const T*)b, W, rec, part,
+                                                        (T*)Dh, (T*)Db);
+  k_face_fin<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, nchunk, part, W, gW, rec);
+  if (ev) (void)hipEventRecord(ev[1], st);
+  k_march<kRowGroup, T, C, 1><<<grid, threads, 0, st>>>(g, binfo, nchunk, (const T*)h, (const T*)b, W, rec, part,
+                                                        (T*)Dh, (T*)Db);
+  k_flux_fin<<<nbl(g.nface, 256), 256, 0, st>>>(g, nchunk, part, rec, F, wall);
+}
+
+void launch_flux(const Dev& g, int prec, const int* binfo, int max_nj, double dts, const void* h, const void* b,
+                 const double* W, const double* q, double* gW, double* rec, double* part, void* Dh, void* Db,
+                 double* F, double* wall, hipStream_t st, hipEvent_t* ev) {
   if (g.dim == 2) {
-    if (prec == 0) launch_flux_t<2, double, double>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st, ev);
-    else launch_flux_t<2, float, float>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st, ev);
+    if (prec == 0) launch_march_t<double, double>(g, binfo, max_nj, dts, h, b, W, q, gW, rec, part, Dh, Db, F, wall, st, ev);
+    else launch_march_t<float, float>(g, binfo, max_nj, dts, h, b, W, q, gW, rec, part, Dh, Db, F, wall, st, ev);
   } else {
     if (prec == 0) launch_flux_t<1, double, double>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st, ev);
     else launch_flux_t<1, float, float>(g, dts, h, b, W, q, gW, rec, Dh, Db, F, wall, st, ev);
@@ -1274,12 +1726,13 @@ void launch_step7(const Dev& g, int prec, int mode, const void* h, const void* b
 void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
                   const double* W, const double* Wn, const double* F, const double* Fn, double* gam, double* R,
                   double* Dg, double* dWs, double* dW, double* Wp, double* rpart, double* resid, hipStream_t st) {
+  (void)Dg;
   k_gamma<<<nbl(g.nface, 256), 256, 0, st>>>(g, W, gam);
-  k_macro_prep<<<nbl(g.ncell, 256), 256, 0, st>>>(g, dt, W, Wn, F, Fn, gam, R, Dg);
+  k_macro_prep<<<nbl(g.ncell, 256), 256, 0, st>>>(g, dt, W, Wn, F, Fn, gam, R);
   int nt = ((max_nj + 63) / 64) * 64;
   size_t lds = sizeof(double) * (size_t)(2 * nt * 4 + (any_pj ? 4 * max_ni : 0));
-  if (g.dim == 2) k_macro_sweep<2><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, Dg, gam, dWs, dW, Wp, rpart);
-  else k_macro_sweep<1><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, Dg, gam, dWs, dW, Wp, rpart);
+  if (g.dim == 2) k_macro_sweep<2><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, dWs, dW, Wp, rpart);
+  else k_macro_sweep<1><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, dWs, dW, Wp, rpart);
   if (resid) k_resid<<<1, 64, 0, st>>>(g.nblock, g.nw, rpart, resid);
 }
 
@@ -1314,6 +1767,13 @@ static void micro_t(const Dev& g, const int* binfo, int KC, int nslot, size_t ld
 void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
                   const double* crec, void* h, void* b, const void* Sh, const void* Sb, void* Dh, void* Db,
                   hipStream_t st) {
+  if (prec == 0)
+    k_micro_rhs<double><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const double*)h, (const double*)b,
+                                                      (const double*)Sh, (const double*)Sb, (double*)Dh,
+                                                      (double*)Db);
+  else
+    k_micro_rhs<float><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const float*)h, (const float*)b,
+                                                     (const float*)Sh, (const float*)Sb, (float*)Dh, (float*)Db);
   int KC = micro_kc(g.dim, max_nj);
   int nslot = (g.dim == 1) ? 1 : max_nj;
   size_t lds = micro_lds(g.dim, max_ni, max_nj, any_pj);

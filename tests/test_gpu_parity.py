@@ -128,3 +128,43 @@ def test_sod_tube_full_size():
     e = (rel_l2(host(hd), h), rel_l2(host(bd), b), rel_l2(host(Wd), W))
     say("  h b W", e)
     assert max(e) <= TOL
+
+
+# --------------------------------------------------------------------------
+# FP32 storage path (f, sources, divergences and the flux arithmetic in
+# float; moments, equilibrium solve and residual assembly in double) against
+# the FP64 oracle: relative L2 <= 1e-5
+# --------------------------------------------------------------------------
+TOL32 = 1e-5
+F32_CASES = [c for c in CASES if c.name in ("sod1d", "box2d", "cylinder", "cavity", "moving_cylinder",
+                                               "channel70")]
+
+
+@pytest.mark.parametrize("case", F32_CASES, ids=[c.name for c in F32_CASES])
+def test_f32_flux_and_step(case):
+    say("f32", case.name)
+    poses = _poses(case)
+    o, s = both(case, prec=ugks.F32, poses=poses)
+    h, b, W = wl.synthetic_f(case, amp=0.02)
+    q = o.heatflux(h, b, W)
+    dts, dtp = o.timesteps()
+    Dho, Dbo, Fo, _ = o.flux(dts, h, b, W, q)
+    Dhs, Dbs, Fs, _ = s.flux(dts, dev(h, torch.float32), dev(b, torch.float32), dev(W), dev(q))
+    idx = o.product_face_index()
+    e = (rel_l2(host(Dhs), Dho), rel_l2(host(Dbs), Dbo), rel_l2(host(Fs)[idx], Fo[:o.nface]))
+    say("  flux D_h D_b F", e)
+    assert max(e) <= TOL32
+    dt = case.dt if case.dt is not None else case.dt_over_dts * dts
+    hd, bd = dev(h, torch.float32), dev(b, torch.float32)
+    Wd, qd = dev(W), dev(q)
+    Wn = W.copy()
+    Sh, Sb, Fn = o.begin_step(dt, dts, h, b, W, q)
+    for _ in range(3):
+        o.pseudo_step(dt, dts, dtp, h, b, W, Wn, q, Sh, Sb, Fn)
+    Wnd = Wd.clone()
+    Shd, Sbd, Fnd = s.begin_step(dt, hd, bd, Wd, qd)
+    s.step(dt, 3, hd, bd, Wd, Wnd, qd, Shd, Sbd, Fnd)
+    field = o.types() == 1
+    e = (rel_l2(host(hd)[field], h[field]), rel_l2(host(bd)[field], b[field]), rel_l2(host(Wd)[field], W[field]))
+    say("  step h b W", e)
+    assert max(e) <= TOL32
