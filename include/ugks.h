@@ -105,7 +105,11 @@ typedef struct ugks_ctx ugks_ctx;
 
 /* Create a context on HIP device `device`: copies the problem, builds the
    geometry at the reference pose, uploads it and allocates scratch.
-   *out receives the context. */
+   *out receives the context.  Block sizes the sweeps accept (one workgroup
+   per block and velocity chunk, state in LDS): nj <= 512 in 2D; ni <= 256
+   when a block is periodic in j; the LU-SGS sweeps' LDS of the largest
+   block within 160 KiB (else UGKS_E_UNSUPPORTED, with the reason in
+   ugks_last_error). */
 int ugks_create(const ugks_problem* p, int device, ugks_ctx** out);
 /* Release the context and its device memory.  NULL is accepted. */
 int ugks_destroy(ugks_ctx* ctx);

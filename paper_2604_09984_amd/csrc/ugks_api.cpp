@@ -56,7 +56,7 @@ struct ugks_ctx {
   std::vector<double> vx, vy, wk;  // per k
   std::vector<Block> blk;
   int ncell = 0, nface = 0;
-  int max_ni = 0, max_nj = 0, any_pj = 0;
+  int max_ni = 0, max_nj = 0, any_pi = 0, any_pj = 0;
   // host geometry
   std::vector<double> xn, yn;  // current nodes, per block
   std::vector<size_t> node0;
@@ -480,12 +480,16 @@ int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
     c->max_ni = std::max(c->max_ni, B.ni);
     c->max_nj = std::max(c->max_nj, B.nj);
     if (B.bc[2] == UGKS_BC_PERIODIC) c->any_pj = 1;
+    if (B.bc[0] == UGKS_BC_PERIODIC) c->any_pi = 1;
     c->blk.push_back(std::move(B));
   }
   if (c->dim == 2 && c->max_nj > 512) { delete c; return fail(UGKS_E_UNSUPPORTED, "nj above 512"); }
   if (c->any_pj && c->max_ni > 256) { delete c; return fail(UGKS_E_UNSUPPORTED, "periodic j needs ni <= 256"); }
   if (micro_lds(c->dim, c->max_ni, c->max_nj, c->any_pj) > 160 * 1024) {
     delete c; return fail(UGKS_E_UNSUPPORTED, "micro sweep LDS above 160 KiB");
+  }
+  if (macro_lds(((c->max_nj + 63) / 64) * 64, c->max_ni, c->max_nj, c->any_pi, c->any_pj) > 160 * 1024) {
+    delete c; return fail(UGKS_E_UNSUPPORTED, "macro sweep LDS above 160 KiB");
   }
   c->ncell = ncell;
   c->xn.assign(nnode, 0.0);
@@ -770,7 +774,7 @@ static int run_inner(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, 
     launch_flux(g, c->prec, (const int*)c->d_binfo, c->max_nj, c->dts, h, b, W, q, (double*)c->s_gW,
                 (double*)c->s_rec, (double*)c->s_part, c->s_Dh, c->s_Db, F, nullptr, st, e ? e + 2 : nullptr);
     if (e) HIPCHK(hipEventRecord(e[4], st));
-    launch_macro(g, (const int*)c->d_binfo, c->max_ni, c->max_nj, c->any_pj, dt, W, Wn, F, Fn,
+    launch_macro(g, (const int*)c->d_binfo, c->max_ni, c->max_nj, c->any_pi, c->any_pj, dt, W, Wn, F, Fn,
                  (double*)c->s_gam, (double*)c->s_R,
                  (double*)c->s_Dg, (double*)c->s_dWs, (double*)c->s_dW, (double*)c->s_Wp, (double*)c->s_rpart,
                  resid ? resid + (size_t)s * c->nw : nullptr, st);

@@ -32,14 +32,24 @@ enum : int {
   R_HWN,       // (lam_w/pi)^(D/2)
   R_VWX, R_VWY,
   R_SGN,       // +1: face normal points into the wall
-  NREC = 32
+  R_RT = 32,   // 1/(2 lam)
+  R_SQX, R_SQY,  // R_SH * q
+  R_SX, R_SY,  // moment shift of the face (mean velocity of its two sides)
+  NREC = 40
 };
+
+// derived fields of a face record used per velocity
+__device__ __forceinline__ void record_derived(double* r) {
+  r[R_RT] = 0.5 / r[R_LAM];
+  r[R_SQX] = r[R_SH] * r[R_QX];
+  r[R_SQY] = r[R_SH] * r[R_QY];
+}
 
 // per-cell record (double): state of the Shakhov source, the micro LU-SGS
 // diagonal base 1/dt' + 1/dt + 1/(2 tau) and, per slot s, the face
 // coefficients (A, B, C) with S/(2|Omega|) * w.n_out = A vx + B vy - C
 enum : int {
-  C_RHO = 0, C_UX, C_UY, C_LAM, C_QX, C_QY, C_HN, C_SH, C_ITAU, C_D0, C_GEO = 10, NCREC = 24
+  C_RHO = 0, C_UX, C_UY, C_LAM, C_QX, C_QY, C_HN, C_SH, C_ITAU, C_GEO = 10, C_D0 = 22, C_FLD = 23, NCREC = 24
 };
 
 // per-cell moment record about a shift s: s(2), m0, m1(2), m2, P(3), m3(2)
@@ -230,6 +240,17 @@ __device__ inline void expansion(int dim, double rho, double U, double V, double
   if (dim == 1) { ax[3] = 0.0; At[3] = 0.0; }
 }
 
+// Workgroup barrier that orders LDS accesses only.  The LU-SGS sweeps hand
+// values between threads through LDS; their global stores are read back
+// only by the thread that wrote them, so the barrier need not wait for them
+// (the full __syncthreads fence would drain every outstanding global load
+// and store each hyperplane, defeating the prefetch).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------------------
 // wavefront reduction (64 lanes)
 // ------------------------------------------------------------------------
@@ -256,6 +277,75 @@ __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_perm<0x141>(v);  // row_half_mirror
   v += dpp_perm<0x140>(v);  // row_mirror
   return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
+}
+
+// exchange of doubles between lane groups (gfx950 permlane swaps): W = 32
+// swaps lanes 32-63 of x with lanes 0-31 of y; W = 16 swaps lanes 16-31 and
+// 48-63 of x with lanes 0-15 and 32-47 of y
+template <int W>
+__device__ __forceinline__ void lane_swap(double& x, double& y) {
+  const unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
+  const unsigned yl = (unsigned)__double2loint(y), yh = (unsigned)__double2hiint(y);
+  if constexpr (W == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+    x = __hiloint2double((int)hi[0], (int)lo[0]);
+    y = __hiloint2double((int)hi[1], (int)lo[1]);
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+    x = __hiloint2double((int)hi[0], (int)lo[0]);
+    y = __hiloint2double((int)hi[1], (int)lo[1]);
+  }
+}
+
+// one reduce-scatter stage over lane bit B: n values in, n/2 out (n >= 2),
+// the lanes with bit B set keep the upper half of the indices; with n = 1 a
+// butterfly (both partners get the pair sum)
+template <int B>
+__device__ __forceinline__ void rs_stage(double* v, int n, int lane) {
+  const bool up = (lane >> B) & 1;
+  if (n == 1) {
+    if constexpr (B == 5 || B == 4) {
+      double a = v[0], b = v[0];
+      lane_swap<(B == 5) ? 32 : 16>(a, b);
+      v[0] = a + b;
+    } else {
+      constexpr int CTRL = (B == 3) ? 0x140 : (B == 2) ? 0x141 : (B == 1) ? 0x4E : 0xB1;
+      v[0] = v[0] + dpp_perm<CTRL>(v[0]);
+    }
+    return;
+  }
+  const int hn = n / 2;
+  for (int i = 0; i < hn; ++i) {
+    if constexpr (B == 5 || B == 4) {
+      double a = v[i], b = v[i + hn];
+      lane_swap<(B == 5) ? 32 : 16>(a, b);
+      v[i] = a + b;
+    } else {
+      constexpr int CTRL = (B == 3) ? 0x140 : (B == 2) ? 0x141 : (B == 1) ? 0x4E : 0xB1;
+      const double send = up ? v[i] : v[i + hn];
+      const double keep = up ? v[i + hn] : v[i];
+      v[i] = keep + dpp_perm<CTRL>(send);
+    }
+  }
+}
+
+// Sums over the 64 lanes of V values at once (V = 1, 2, 4, 8 or 16), far
+// cheaper than V separate reductions: each stage halves the values a lane
+// carries.  On return v[0] of lane l holds the total of value l >> (6 - log2 V)
+// (every lane of that group holds the same, bit-identical total; the order of
+// the additions is fixed).
+template <int V>
+__device__ __forceinline__ void multi_sum(double* v, int lane) {
+  static_assert(V == 1 || V == 2 || V == 4 || V == 8 || V == 16, "V");
+  int n = V;
+  rs_stage<5>(v, n, lane); n = (n > 1) ? n / 2 : 1;
+  rs_stage<4>(v, n, lane); n = (n > 1) ? n / 2 : 1;
+  rs_stage<3>(v, n, lane); n = (n > 1) ? n / 2 : 1;
+  rs_stage<2>(v, n, lane); n = (n > 1) ? n / 2 : 1;
+  rs_stage<1>(v, n, lane); n = (n > 1) ? n / 2 : 1;
+  rs_stage<0>(v, n, lane);
 }
 
 template <class T>

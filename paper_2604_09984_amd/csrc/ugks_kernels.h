@@ -6,6 +6,7 @@ namespace ugks {
 
 int micro_kc(int dim, int max_nj);
 size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj);
+size_t macro_lds(int nt, int max_ni, int max_nj, int any_pi, int any_pj);
 
 void launch_flux(const Dev& g, int prec, const int* binfo, int max_nj, double dts, const void* h, const void* b,
                  const double* W, const double* q, double* gW, double* rec, double* part, void* Dh, void* Db,
@@ -22,7 +23,7 @@ void launch_source(const Dev& g, int prec, double dt, const void* h, const void*
                    void* Sh, void* Sb, hipStream_t st);
 void launch_step7(const Dev& g, int prec, int mode, const void* h, const void* b, const double* crec,
                   const double* Wp, double* W, double* q, double* mrec, hipStream_t st);
-void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
+void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int any_pi, int any_pj, double dt,
                   const double* W, const double* Wn, const double* F, const double* Fn, double* gam, double* R,
                   double* Dg, double* dWs, double* dW, double* Wp, double* rpart, double* resid, hipStream_t st);
 void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,

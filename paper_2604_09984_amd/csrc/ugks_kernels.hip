@@ -23,10 +23,10 @@ __device__ __attribute__((noinline)) double wnorm(double vx, double vy, double u
 // (m = 1), computed in type C
 template <class C>
 struct FaceEq {
-  C rho, ux, uy, lam, qx, qy, hn, sh, ax[4], ay[4], at[4], t[5];
+  C ux, uy, lam, rt, sqx, sqy, hn, ax[4], ay[4], at[4], t[5];
   __device__ void load(const double* r) {
-    rho = (C)r[R_RHO]; ux = (C)r[R_UX]; uy = (C)r[R_UY]; lam = (C)r[R_LAM];
-    qx = (C)r[R_QX]; qy = (C)r[R_QY]; hn = (C)r[R_HN]; sh = (C)r[R_SH];
+    ux = (C)r[R_UX]; uy = (C)r[R_UY]; lam = (C)r[R_LAM]; rt = (C)r[R_RT];
+    sqx = (C)r[R_SQX]; sqy = (C)r[R_SQY]; hn = (C)r[R_HN];
     for (int m = 0; m < 4; ++m) { ax[m] = (C)r[R_AX + m]; ay[m] = (C)r[R_AY + m]; at[m] = (C)r[R_AT + m]; }
     for (int m = 0; m < 5; ++m) t[m] = (C)r[R_T1 + m];
   }
@@ -45,9 +45,9 @@ __device__ inline void interface_avg(const FaceEq<C>& e, int dim, int nxi, C vx,
   C cx = vx - e.ux, cy = (dim == 2) ? vy - e.uy : C(0);
   C c2 = cx * cx + cy * cy;
   C H = e.hn * expo<C>(-e.lam * c2);
-  C rt = C(0.5) / e.lam;
+  const C rt = e.rt;
   C B = C(nxi) * rt * H;
-  C s = e.sh * (cx * e.qx + cy * e.qy);
+  C s = cx * e.sqx + cy * e.sqy;
   C twol = C(2) * e.lam * c2;
   C Hp = s * (twol - C(2) - C(dim)) * H;
   C Bp = s * (twol - C(dim)) * C(nxi) * rt * H;
@@ -106,8 +106,25 @@ __global__ void k_wallprep(Dev g, double dts, const double* __restrict__ W, cons
   int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= g.nface) return;
   int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
-  if (L != kNbWall && R != kNbWall) return;
   double* r = rec + (size_t)f * NREC;
+  if (L != kNbWall && R != kNbWall) {
+    // moment shift: mean velocity of the two sides (a ghost side is the far
+    // field or a copy of the interior cell)
+    const int inner = (L >= 0) ? L : R;
+    if (inner < 0) return;
+    auto vel = [&](int code, double& ax, double& ay) {
+      const double* Wc = (code >= 0) ? W + (size_t)code * g.nw
+                                     : ((code == kNbFar) ? g.winf : W + (size_t)inner * g.nw);
+      ax = Wc[1] / Wc[0];
+      ay = (g.dim == 2) ? Wc[2] / Wc[0] : 0.0;
+    };
+    double u1, v1, u2, v2;
+    vel(L, u1, v1);
+    vel(R, u2, v2);
+    r[R_SX] = 0.5 * (u1 + u2);
+    r[R_SY] = 0.5 * (v1 + v2);
+    return;
+  }
   for (int m = 0; m < NREC; ++m) r[m] = 0.0;
   int c = (L == kNbWall) ? R : L;
   if (c < 0 || g.type[c] != 1) return;
@@ -134,6 +151,7 @@ __global__ void k_wallprep(Dev g, double dts, const double* __restrict__ W, cons
   time_integrals(dts, inv_tau_of(g, rho, lam), tq);
   for (int m = 0; m < 5; ++m) r[R_T1 + m] = tq[m] / dts;
   r[R_ACT] = 1.0;
+  record_derived(r);
   r[R_LAMW] = 0.5 / fg[7];
   r[R_HWN] = pow(r[R_LAMW] / kPi, 0.5 * g.dim);
   r[R_VWX] = fg[5];
@@ -351,6 +369,7 @@ __global__ __launch_bounds__(256) void k_face_eq(Dev g, double dts, const T* __r
     time_integrals(dts, inv_tau_of(g, rho, lam), tq);
     for (int m = 0; m < 5; ++m) r[R_T1 + m] = tq[m] / dts;
     r[R_ACT] = 1.0;
+    record_derived(r);
   }
 }
 
@@ -608,37 +627,21 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   };
   // upwind interface data of a face between sides sl (low) and sh (high)
   // with normal (nx, ny) and mesh velocity (ux, uy)
-  auto face_eval = [&](int f, const Side<C>& sl, const Side<C>& sh, int owner_write, double* facc) -> void {
+  auto face_eval = [&](int f, const Side<C>& sl, const Side<C>& sh, double* facc, double* mom) -> void {
     const double* fg = g.fgeo + (size_t)f * 8;
     const double nx = fg[0], ny = fg[1], ux = fg[3], uy = fg[4];
     const double wn = exact_wn(vx, vy, ux, uy, nx, ny);
     const double* r = rec + (size_t)f * NREC;
     if (MODE == 0) {
       // moments of the upwind data about the mean velocity of the sides
-      const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
-      const int inner = (L >= 0) ? L : R;
-      auto vel = [&](int code, double& ax, double& ay) {
-        const double* Wc = (code >= 0) ? W + (size_t)code * 4 : ((code == kNbFar) ? g.winf : W + (size_t)inner * 4);
-        ax = Wc[1] / Wc[0];
-        ay = Wc[2] / Wc[0];
-      };
-      double u1, v1, u2, v2;
-      vel(L, u1, v1);
-      vel(R, u2, v2);
-      const double sx = 0.5 * (u1 + u2), sy = 0.5 * (v1 + v2);
+      const double sx = r[R_SX], sy = r[R_SY];
       double fh = (wn > 0.0) ? (double)sl.hv : ((wn < 0.0) ? (double)sh.hv : 0.5 * ((double)sl.hv + (double)sh.hv));
       double fb = (wn > 0.0) ? (double)sl.bv : ((wn < 0.0) ? (double)sh.bv : 0.5 * ((double)sl.bv + (double)sh.bv));
       const double cx = vx - sx, cy = vy - sy;
       const double e = (cx * cx + cy * cy) * fh + fb;
       const double wh = wk * fh, we = wk * e;
-      double m[kMomP] = {wh, wh * cx, wh * cy, we, wh * cx * cx, wh * cx * cy, wh * cy * cy, we * cx, we * cy};
-#pragma unroll
-      for (int q = 0; q < kMomP; ++q) m[q] = wave_sum(m[q]);
-      if (owner_write && lane == 0) {
-        double* o = part + ((size_t)chunk * g.nface + f) * kMomP;
-#pragma unroll
-        for (int q = 0; q < kMomP; ++q) o[q] = m[q];
-      }
+      mom[0] = wh; mom[1] = wh * cx; mom[2] = wh * cy; mom[3] = we; mom[4] = wh * cx * cx;
+      mom[5] = wh * cx * cy; mom[6] = wh * cy * cy; mom[7] = we * cx; mom[8] = we * cy;
       return;
     }
     FaceEq<C> e;
@@ -653,19 +656,12 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     fb = kin ? fb : 0.0;
     facc[0] = fh;
     facc[1] = fb;
-    double m[kFluxP] = {wk * fh, wk * vx * fh, wk * vy * fh, wk * 0.5 * ((vx * vx + vy * vy) * fh + fb)};
-    if (owner_write) {
-#pragma unroll
-      for (int q = 0; q < kFluxP; ++q) m[q] = wave_sum(m[q]);
-      if (lane == 0) {
-        double* o = part + ((size_t)chunk * g.nface + f) * kFluxP;
-#pragma unroll
-        for (int q = 0; q < kFluxP; ++q) o[q] = m[q];
-      }
-    }
+    mom[0] = wk * fh; mom[1] = wk * vx * fh; mom[2] = wk * vy * fh;
+    mom[3] = wk * 0.5 * ((vx * vx + vy * vy) * fh + fb);
   };
-  // wall face seen from the interior cell c (slot s) with data L
-  auto wall_eval = [&](int f, int c, int s, const LD6<C>& L, int owner_write, double* facc) -> void {
+  // wall face seen from the interior cell c (slot s) with data L: MODE 0
+  // gives the numerator and denominator of the wall density (Eq. rhow)
+  auto wall_eval = [&](int f, int c, int s, const LD6<C>& L, double* facc, double* mom) -> void {
     const double* fg = g.fgeo + (size_t)f * 8;
     const double* r = rec + (size_t)f * NREC;
     const double sg = r[R_SGN];
@@ -679,15 +675,8 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     if (MODE == 0) {
       const double cx = vx - r[R_VWX], cy = vy - r[R_VWY];
       const double hw = r[R_HWN] * exp(-r[R_LAMW] * (cx * cx + cy * cy));
-      double num = (wn > 0.0) ? wk * wn * (double)Ih : 0.0;
-      double den = (wn < 0.0) ? wk * wn * hw : 0.0;
-      num = wave_sum(num);
-      den = wave_sum(den);
-      if (owner_write && lane == 0) {
-        double* o = part + ((size_t)chunk * g.nface + f) * kMomP;
-        o[0] = num; o[1] = den;
-        for (int q = 2; q < kMomP; ++q) o[q] = 0.0;
-      }
+      mom[0] = (wn > 0.0) ? wk * wn * (double)Ih : 0.0;
+      mom[1] = (wn < 0.0) ? wk * wn * hw : 0.0;
       return;
     }
     const double cx = vx - r[R_VWX], cy = vy - r[R_VWY];
@@ -699,16 +688,39 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     fb = kin ? fb : 0.0;
     facc[0] = fh;
     facc[1] = fb;
-    double m[kFluxP] = {wk * fh, wk * vx * fh, wk * vy * fh, wk * 0.5 * ((vx * vx + vy * vy) * fh + fb)};
-    if (owner_write) {
+    mom[0] = wk * fh; mom[1] = wk * vx * fh; mom[2] = wk * vy * fh;
+    mom[3] = wk * 0.5 * ((vx * vx + vy * vy) * fh + fb);
+  };
+  // chunk partials of the faces evaluated at one column: the i-face (fiw)
+  // and the j-face (fjw), each written when this wavefront owns it (else
+  // -1), reduced over the 64 lanes together
+  auto write_partials = [&](int fiw, const double* mi, int fjw, const double* mj) {
+    if (fiw < 0 && fjw < 0) return;
+    if (MODE == 0) {
+      double v[16], u[2];
 #pragma unroll
-      for (int q = 0; q < kFluxP; ++q) m[q] = wave_sum(m[q]);
-      if (lane == 0) {
-        double* o = part + ((size_t)chunk * g.nface + f) * kFluxP;
+      for (int q = 0; q < kMomP; ++q) v[q] = mi[q];
 #pragma unroll
-        for (int q = 0; q < kFluxP; ++q) o[q] = m[q];
+      for (int q = 0; q < 7; ++q) v[kMomP + q] = mj[q];
+      u[0] = mj[7]; u[1] = mj[8];
+      multi_sum<16>(v, lane);
+      multi_sum<2>(u, lane);
+      const int qv = lane >> 2;  // value of v[0]
+      if ((lane & 3) == 0) {
+        if (qv < kMomP) { if (fiw >= 0) part[((size_t)chunk * g.nface + fiw) * kMomP + qv] = v[0]; }
+        else if (fjw >= 0) part[((size_t)chunk * g.nface + fjw) * kMomP + (qv - kMomP)] = v[0];
       }
+      if ((lane & 31) == 0 && fjw >= 0) part[((size_t)chunk * g.nface + fjw) * kMomP + 7 + (lane >> 5)] = u[0];
+    } else {
+      // MODE 1 reduces each face as soon as it is evaluated (see below)
+      (void)mi; (void)mj;
     }
+  };
+  // MODE 1: the four macro-flux partials of one face, reduced at once
+  auto write_flux = [&](int fw, double* m) {
+    if (fw < 0) return;
+    multi_sum<4>(m, lane);
+    if ((lane & 15) == 0) part[((size_t)chunk * g.nface + fw) * kFluxP + (lane >> 4)] = m[0];
   };
   // generic face between cell (x, jr) side slot s and its neighbour, given
   // LDS data of both sides when they are cells; returns the flux along the
@@ -721,6 +733,11 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     if (x + 1 <= ni) recon_step(x + 1);
     __syncthreads();
     double fi_cur[2] = {0.0, 0.0}, fj_cur[2] = {0.0, 0.0};
+    constexpr int NM = (MODE == 0) ? kMomP : kFluxP;
+    double mi[NM], mj[NM];
+#pragma unroll
+    for (int q = 0; q < NM; ++q) { mi[q] = 0.0; mj[q] = 0.0; }
+    int fiw = -1, fjw = -1;
     // i-face (x|x+1) of a core row
     if (core && jr >= 0) {
       const int cl = (x >= 0) ? cell(x, jr) : -1;
@@ -733,11 +750,12 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
         // owner: the low cell, or the cell of a boundary face; a periodic
         // seam face (x = -1) is written by the high end of the row
         const bool owner = (x >= 0) || (L < 0);
+        if (owner) fiw = f;
         if (L == kNbWall || R == kNbWall) {
           const int c = (L == kNbWall) ? R : L;
           const int s = (L == kNbWall) ? 0 : 1;
           const int xc = (L == kNbWall) ? x + 1 : x;
-          wall_eval(f, c, s, lds[xc & 1][w][lane], owner, fi_cur);
+          wall_eval(f, c, s, lds[xc & 1][w][lane], fi_cur, mi);
         } else {
           Side<C> sl, sh;
           // the low side of the seam face (x = -1) is cell ni-1, staged in slot (-1) & 1
@@ -745,8 +763,9 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
           if (R >= 0) sh = side_from_cell<T, C>(g, lds[(x + 1) & 1][w][lane], R, 0);
           if (L < 0) sl = side_ghost<T, C>(g, lds[(x + 1) & 1][w][lane], L, kk);
           if (R < 0) sh = side_ghost<T, C>(g, lds[x & 1][w][lane], R, kk);
-          face_eval(f, sl, sh, owner, fi_cur);
+          face_eval(f, sl, sh, fi_cur, mi);
         }
+        if (MODE == 1) write_flux(fiw, mi);
       }
     }
     // j-face (jr|jr+1) at column x, for the bottom halo and the core rows
@@ -761,22 +780,25 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
         // core rows own the face above them; the bottom halo writes only
         // the block's lower boundary face
         const bool owner = (w >= 1) || (L < 0);
+        if (owner) fjw = f;
         if (L == kNbWall || R == kNbWall) {
           const int c = (L == kNbWall) ? R : L;
           const int s = (L == kNbWall) ? 2 : 3;
           const int wc = (L == kNbWall) ? w + 1 : w;
-          wall_eval(f, c, s, lds[x & 1][wc][lane], owner, fj_cur);
+          wall_eval(f, c, s, lds[x & 1][wc][lane], fj_cur, mj);
         } else {
           Side<C> sl, sh;
           if (L >= 0) sl = side_from_cell<T, C>(g, lds[x & 1][w][lane], L, 3);
           if (R >= 0) sh = side_from_cell<T, C>(g, lds[x & 1][w + 1][lane], R, 2);
           if (L < 0) sl = side_ghost<T, C>(g, lds[x & 1][w + 1][lane], L, kk);
           if (R < 0) sh = side_ghost<T, C>(g, lds[x & 1][w][lane], R, kk);
-          face_eval(f, sl, sh, owner, fj_cur);
+          face_eval(f, sl, sh, fj_cur, mj);
         }
+        if (MODE == 1) write_flux(fjw, mj);
       }
       if (MODE == 1) { jfl[w][0][lane] = (C)fj_cur[0]; jfl[w][1][lane] = (C)fj_cur[1]; }
     }
+    if (MODE == 0) write_partials(fiw, mi, fjw, mj);
     if (MODE == 1) {
       __syncthreads();
       // divergence of cell (x, jr) of a core row
@@ -824,16 +846,7 @@ __global__ void k_face_fin(Dev g, double dts, int nchunk, const double* __restri
     r[R_RHOW] = -m[0] / m[1];
     return;
   }
-  const int inner = (L >= 0) ? L : R;
-  auto vel = [&](int code, double& ax, double& ay) {
-    const double* Wc = (code >= 0) ? W + (size_t)code * 4 : ((code == kNbFar) ? g.winf : W + (size_t)inner * 4);
-    ax = Wc[1] / Wc[0];
-    ay = Wc[2] / Wc[0];
-  };
-  double u1, v1, u2, v2;
-  vel(L, u1, v1);
-  vel(R, u2, v2);
-  const double sx = 0.5 * (u1 + u2), sy = 0.5 * (v1 + v2);
+  const double sx = r[R_SX], sy = r[R_SY];
   const double m0 = m[0], m1x = m[1], m1y = m[2], m2 = m[3], pxx = m[4], pxy = m[5], pyy = m[6], m3x = m[7],
                m3y = m[8];
   const double rho = m0;
@@ -859,6 +872,7 @@ __global__ void k_face_fin(Dev g, double dts, int nchunk, const double* __restri
   time_integrals(dts, inv_tau_of(g, rho, lam), tq);
   for (int q = 0; q < 5; ++q) r[R_T1 + q] = tq[q] / dts;
   r[R_ACT] = 1.0;
+  record_derived(r);
 }
 
 // macro flux per face (and the wall output) from the chunk partials
@@ -1016,7 +1030,9 @@ __global__ __launch_bounds__(256) void k_step7(Dev g, int mode, const T* __restr
 __global__ void k_cellrec(Dev g, double dt, const double* __restrict__ W, const double* __restrict__ q,
                           const double* __restrict__ mrec, double* __restrict__ crec) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.ncell || g.type[c] == 0) return;
+  if (c >= g.ncell) return;
+  crec[(size_t)c * NCREC + C_FLD] = (g.type[c] == 1) ? 1.0 : 0.0;
+  if (g.type[c] == 0) return;
   double rho, ux, uy, lam;
   prim_of(g, W + (size_t)c * g.nw, rho, ux, uy, lam);
   double qx, qy;
@@ -1030,7 +1046,6 @@ __global__ void k_cellrec(Dev g, double dt, const double* __restrict__ W, const 
   r[C_ITAU] = it;
   r[C_D0] = 1.0 / g.dtp[c] + 1.0 / dt + 0.5 * it;
   for (int m = 0; m < 12; ++m) r[C_GEO + m] = g.mgeo[(size_t)c * 12 + m];
-  r[22] = 0.0; r[23] = 0.0;
 }
 
 // Shakhov equilibrium h+, b+ of a cell record at velocity (vx, vy)
@@ -1257,10 +1272,11 @@ __device__ __forceinline__ void euler_dflux(int dim, int nxi, const double* W, c
 // overlaps the computation and the barrier.
 // macro sweep: one workgroup per block, one thread per row j, hyperplane
 // order.  The inputs of the next hyperplane (macro record: residual or dW*,
-// 1/D, and the two structural couplings) are loaded before the current
-// hyperplane is computed.
+// 1/D, and the two structural couplings) are requested before the current
+// hyperplane is computed and no load address depends on a loaded value; the
+// couplings across periodic seams are copied to LDS at the start.
 struct MacroRow {
-  bool ok, fld;
+  bool ok;
   int c;
   double base[4], iD, ivd;
   double nb[2][kMacSlot];
@@ -1273,14 +1289,11 @@ __device__ __forceinline__ void macro_row_load(const double* __restrict__ mac, c
                                                int bwd, int ni, int nj, int c0, int j, int h, MacroRow& M) {
   int i = h - j;
   M.ok = (j < nj) && (i >= 0) && (i < ni);
-  M.fld = false;
   if (!M.ok) return;
   const int c = c0 + i + ni * j;
   M.c = c;
   const double* R = mac + (size_t)c * kMacRec;
   M.iD = R[4];
-  M.fld = M.iD > 0.0;
-  if (!M.fld) return;
   M.ivd = R[5];
 #pragma unroll
   for (int m = 0; m < 4; ++m) M.base[m] = bwd ? ((m < D + 2) ? dws[(size_t)c * (D + 2) + m] : 0.0) : R[m];
@@ -1304,39 +1317,66 @@ __device__ __forceinline__ void macro_couple(const double* P, const double* x, d
   for (int m = 0; m < D + 2; ++m) acc[m] += P[11] * (fe[m] - P[4 + m]) - P[12] * x[m];
 }
 
+// LDS doubles of the macro sweep: hand-off [2][NT][4], periodic-j values
+// [ni][4], seam couplings [2][nj][14] (periodic i) and [2][ni][14] (periodic j)
+size_t macro_lds(int nt, int max_ni, int max_nj, int any_pi, int any_pj) {
+  return sizeof(double) * (size_t)(2 * nt * 4 + (any_pj ? 4 * max_ni + 2 * kMacSlot * max_ni : 0) +
+                                   (any_pi ? 2 * kMacSlot * max_nj : 0));
+}
+
 template <int D>
 __global__ __launch_bounds__(512) void k_macro_sweep(Dev g, const int* __restrict__ binfo,
                                                      const double* __restrict__ W,
                                                      const double* __restrict__ mac,
                                                      double* __restrict__ dWs, double* __restrict__ dW,
-                                                     double* __restrict__ Wp, double* __restrict__ rpart) {
+                                                     double* __restrict__ Wp, double* __restrict__ rpart,
+                                                     int max_ni, int max_nj, int any_pi, int any_pj) {
   extern __shared__ double msm[];
   const int* bi = binfo + 8 * blockIdx.x;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], pi = bi[3], pj = bi[4];
   const int j = threadIdx.x;
   const int NT = blockDim.x;
   constexpr int nw = D + 2;
-  double* hand = msm;              // [2][NT][4]
-  double* pjb = msm + 2 * NT * 4;  // [ni][4] (periodic j)
-  // residual norm over the block's field cells
+  double* hand = msm;                                              // [2][NT][4]
+  double* pjb = msm + 2 * NT * 4;                                  // [ni][4]
+  double* sjp = pjb + (any_pj ? 4 * max_ni : 0);                   // [2][ni][14]
+  double* sip = sjp + (any_pj ? 2 * kMacSlot * max_ni : 0);        // [2][nj][14]
+  (void)max_nj; (void)any_pi;
+  // seam couplings: periodic i (cell (ni-1, j) slot 1, cell (0, j) slot 0),
+  // periodic j (cell (i, nj-1) slot 3, cell (i, 0) slot 2)
+  if (pi && j < nj)
+    for (int m = 0; m < kMacSlot; ++m) {
+      sip[(0 * nj + j) * kMacSlot + m] = mac[(size_t)(c0 + ni - 1 + ni * j) * kMacRec + 8 + kMacSlot * 1 + m];
+      sip[(1 * nj + j) * kMacSlot + m] = mac[(size_t)(c0 + ni * j) * kMacRec + 8 + kMacSlot * 0 + m];
+    }
+  if (D == 2 && pj)
+    for (int i = j; i < ni; i += NT)
+      for (int m = 0; m < kMacSlot; ++m) {
+        sjp[(0 * ni + i) * kMacSlot + m] = mac[(size_t)(c0 + i + ni * (nj - 1)) * kMacRec + 8 + kMacSlot * 3 + m];
+        sjp[(1 * ni + i) * kMacSlot + m] = mac[(size_t)(c0 + i) * kMacRec + 8 + kMacSlot * 2 + m];
+      }
+  // residual norm over the block's field cells (the record of any other
+  // cell holds zeros)
   double rs[4] = {0, 0, 0, 0};
   if (j < nj)
     for (int i = 0; i < ni; ++i) {
       const double* R = mac + (size_t)(c0 + i + ni * j) * kMacRec;
-      if (!(R[4] > 0.0)) continue;
+#pragma unroll
       for (int m = 0; m < nw; ++m) rs[m] += R[m] * R[m];
     }
   for (int m = 0; m < 4; ++m) rs[m] = wave_sum(rs[m]);
-  __shared__ double wsum[8][4];
-  if ((j & 63) == 0) for (int m = 0; m < 4; ++m) wsum[j >> 6][m] = rs[m];
+  // per-wave sums combined in a fixed order (the hand-off buffer is free
+  // until the forward sweep starts; all LDS of this kernel is dynamic)
+  if ((j & 63) == 0) for (int m = 0; m < 4; ++m) hand[(j >> 6) * 4 + m] = rs[m];
   __syncthreads();
   if (j == 0) {
     for (int m = 0; m < nw; ++m) {
       double t = 0.0;
-      for (int w = 0; w < (NT + 63) / 64; ++w) t += wsum[w][m];
+      for (int w = 0; w < (NT + 63) / 64; ++w) t += hand[w * 4 + m];
       rpart[(size_t)blockIdx.x * 4 + m] = t;
     }
   }
+  __syncthreads();
   const int H = ni + nj - 1;
   double prev[4] = {0, 0, 0, 0}, cw[4] = {0, 0, 0, 0};
   MacroRow cur, nxt;
@@ -1347,13 +1387,12 @@ __global__ __launch_bounds__(512) void k_macro_sweep(Dev g, const int* __restric
     if (cur.ok) {
       const int i = h - j, c = cur.c;
       double x[4] = {0, 0, 0, 0};
-      if (cur.fld) {
+      if (cur.iD > 0.0) {
         double acc[4] = {0, 0, 0, 0};
         if (i >= 1) macro_couple<D>(cur.nb[0], prev, acc);
         if (D == 2 && j >= 1) macro_couple<D>(cur.nb[1], hand + ((h - 1) & 1) * NT * 4 + (j - 1) * 4, acc);
-        if (pi && i == ni - 1 && ni > 1) macro_couple<D>(mac + (size_t)c * kMacRec + 8 + kMacSlot * 1, cw, acc);
-        if (D == 2 && pj && j == nj - 1 && nj > 1)
-          macro_couple<D>(mac + (size_t)c * kMacRec + 8 + kMacSlot * 3, pjb + 4 * i, acc);
+        if (pi && i == ni - 1 && ni > 1) macro_couple<D>(sip + (0 * nj + j) * kMacSlot, cw, acc);
+        if (D == 2 && pj && j == nj - 1 && nj > 1) macro_couple<D>(sjp + (0 * ni + i) * kMacSlot, pjb + 4 * i, acc);
 #pragma unroll
         for (int m = 0; m < nw; ++m) x[m] = (cur.base[m] - cur.ivd * acc[m]) * cur.iD;
       }
@@ -1366,7 +1405,7 @@ __global__ __launch_bounds__(512) void k_macro_sweep(Dev g, const int* __restric
         if (pj && j == 0) pjb[4 * i + m] = x[m];
       }
     }
-    __syncthreads();
+    lds_barrier();
     cur = nxt;
   }
   for (int m = 0; m < 4; ++m) { prev[m] = 0.0; cw[m] = 0.0; }
@@ -1377,14 +1416,14 @@ __global__ __launch_bounds__(512) void k_macro_sweep(Dev g, const int* __restric
     if (h >= 1) macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 1, nxt);
     if (cur.ok) {
       const int i = h - j, c = cur.c;
+      const bool fld = cur.iD > 0.0;
       double x[4] = {0, 0, 0, 0};
-      if (cur.fld) {
+      if (fld) {
         double acc[4] = {0, 0, 0, 0};
         if (i + 1 < ni) macro_couple<D>(cur.nb[0], prev, acc);
         if (D == 2 && j + 1 < nj) macro_couple<D>(cur.nb[1], hand + ((h + 1) & 1) * NT * 4 + (j + 1) * 4, acc);
-        if (pi && i == 0 && ni > 1) macro_couple<D>(mac + (size_t)c * kMacRec + 8 + kMacSlot * 0, cw, acc);
-        if (D == 2 && pj && j == 0 && nj > 1)
-          macro_couple<D>(mac + (size_t)c * kMacRec + 8 + kMacSlot * 2, pjb + 4 * i, acc);
+        if (pi && i == 0 && ni > 1) macro_couple<D>(sip + (1 * nj + j) * kMacSlot, cw, acc);
+        if (D == 2 && pj && j == 0 && nj > 1) macro_couple<D>(sjp + (1 * ni + i) * kMacSlot, pjb + 4 * i, acc);
 #pragma unroll
         for (int m = 0; m < nw; ++m) x[m] = cur.base[m] - cur.ivd * cur.iD * acc[m];
       }
@@ -1396,14 +1435,14 @@ __global__ __launch_bounds__(512) void k_macro_sweep(Dev g, const int* __restric
 #pragma unroll
       for (int m = 0; m < nw; ++m) {
         dW[(size_t)c * nw + m] = x[m];
-        Wp[(size_t)c * nw + m] = (okp && cur.fld) ? wp[m] : W[(size_t)c * nw + m];
+        Wp[(size_t)c * nw + m] = (okp && fld) ? wp[m] : W[(size_t)c * nw + m];
         prev[m] = x[m];
         if (i == ni - 1) cw[m] = x[m];
         hand[(h & 1) * NT * 4 + j * 4 + m] = x[m];
         if (pj && j == nj - 1) pjb[4 * i + m] = x[m];
       }
     }
-    __syncthreads();
+    lds_barrier();
     cur = nxt;
   }
 }
@@ -1451,188 +1490,169 @@ __global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const doubl
 }
 
 // micro LU-SGS (Eq. dualTimeStepping_micro): forward and backward sweep of
-// one velocity chunk (KC lanes) of one block, one row per thread slot.
-// Dh/Db hold the flux divergence on entry and dF* afterwards; h, b are
-// updated to f^{s+1}.  Per-cell data of the next hyperplane is staged in LDS
-// by the lanes of its slot while the current hyperplane is computed.
-template <int D, class T>
-__global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ binfo, int KC, int nslot, double dt,
+// one velocity chunk (KC lanes) of one block, one row per thread slot, in
+// hyperplane order.  Dh/Db hold the residual r on entry and dF* after the
+// forward sweep; h, b are updated to f^{s+1} by the backward sweep.
+//
+// Latency and issue: everything a hyperplane needs from global memory (its
+// residual or dF*, h, b, and the cell's coefficient record: face geometry,
+// D0 and the field flag) is requested P hyperplanes ahead into a register
+// ring, at addresses clamped into the row so that no load is predicated or
+// depends on a loaded value.  The record of the next hyperplane is copied
+// from the ring to LDS (double buffered) by the KC lanes of its row.  The
+// row hand-off buffer has a zero slot below row 0 and above the last row,
+// so the couplings need no row tests; results are stored only for cells of
+// the block.
+constexpr int kMicroRec = 14;   // C_GEO (12), C_D0, C_FLD
+constexpr int kMicroRecLds = 16;
+
+// 1/d for d > 0 of moderate size: hardware estimate and two Newton steps
+__device__ __forceinline__ double recip_pos(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
+
+template <int D, class T, int KC, int P>
+__global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ binfo, int nslot,
                                                 const double* __restrict__ crec, T* __restrict__ h,
-                                                T* __restrict__ b, const T* __restrict__ Sh,
-                                                const T* __restrict__ Sb, T* __restrict__ Dh,
-                                                T* __restrict__ Db) {
+                                                T* __restrict__ b, T* __restrict__ Dh, T* __restrict__ Db) {
   extern __shared__ double smem[];
+  constexpr int NS = (kMicroRec + KC - 1) / KC;  // record entries per lane
   const int* bi = binfo + 8 * blockIdx.y;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], pi = bi[3], pj = bi[4];
   const int t = threadIdx.x;
   const int lk = t % KC, j = t / KC;
+  const int nv = g.nv;
   const int k = blockIdx.x * KC + lk;
-  const bool kin = k < g.nv;
-  const int kk = kin ? k : g.nv - 1;
-  // LDS: hand[2][nslot][KC][2], cells[2][nslot][NCREC], pj[ni][KC][2]
-  double* hand = smem;
-  double* cells = smem + 4 * nslot * KC;
-  double* pjb = cells + 2 * nslot * NCREC;
-  auto HND = [&](int p, int s) -> double* { return hand + ((size_t)(p * nslot + s) * KC + lk) * 2; };
-  auto CEL = [&](int p) -> double* { return cells + (size_t)(p * nslot + j) * NCREC; };
-  auto PJ = [&](int i) -> double* { return pjb + ((size_t)i * KC + lk) * 2; };
-  const double vx = g.vx[kk], vy = g.vy[kk];
-  (void)dt;
-  const int HH = ni + nj - 1;
+  const bool kin = k < nv;
+  const int kk = kin ? k : nv - 1;
   const bool row = j < nj;
-  double ph = 0.0, pb = 0.0, chh = 0.0, cbb = 0.0;
+  const int jl = row ? j : nj - 1;  // rows beyond the block read (not write) the last row's slots
+  const int cbase = c0 + ni * jl;   // cell (0, j)
+  // LDS: hand[2][nslot + 2][KC][2] (slot s + 1 holds row s), cells[2][nslot][16],
+  // pj[ni][KC][2]
+  double* hand = smem;
+  double* cells = smem + 4 * (nslot + 2) * KC;
+  double* pjb = cells + 2 * nslot * kMicroRecLds;
+  auto HND = [&](int p, int s) -> double* { return hand + ((size_t)(p * (nslot + 2) + s) * KC + lk) * 2; };
+  auto CEL = [&](int p) -> double* { return cells + (size_t)(p * nslot + jl) * kMicroRecLds; };
+  for (int e = t; e < 4 * (nslot + 2) * KC; e += blockDim.x) hand[e] = 0.0;
+  const double vx = g.vx[kk], vy = (D == 2) ? g.vy[kk] : 0.0;
+  const int HH = ni + nj - 1;
 
-  // stage the per-cell record of hyperplane hp into LDS buffer p (after the
-  // caller's barrier the buffer is read); loads are issued into registers
-  // first so that they overlap the current hyperplane's work
-  double st0 = 0.0, st1 = 0.0;
-  auto cell_of_hp = [&](int hp) -> int {
-    int i = hp - j;
-    return (row && i >= 0 && i < ni) ? c0 + i + ni * j : -1;
+  double ra[P], rb_[P], rf0[P], rf1[P];
+  double rr[P][NS];
+  auto issue = [&](int u, int hp, bool bwd) {
+    const int i = min(max(hp - j, 0), ni - 1);
+    const size_t o = (size_t)(cbase + i) * nv + kk;
+    ra[u] = (double)Dh[o];
+    rb_[u] = (double)Db[o];
+    if (bwd) { rf0[u] = (double)h[o]; rf1[u] = (double)b[o]; }
+    const double* r = crec + (size_t)(cbase + i) * NCREC + C_GEO;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) rr[u][m] = r[min(lk + KC * m, kMicroRec - 1)];  // unpredicated
   };
-  auto stage_load = [&](int hp) {
-    int c = cell_of_hp(hp);
-    st0 = 0.0; st1 = 0.0;
-    if (c < 0) return;
-    const double* r = crec + (size_t)c * NCREC;
-    if (lk < NCREC) st0 = r[lk];
-    if (lk + KC < NCREC) st1 = r[lk + KC];
-  };
-  auto stage_store = [&](int p) {
+  auto stage = [&](int u, int p) {
     if (!row) return;
     double* d = CEL(p);
-    if (lk < NCREC) d[lk] = st0;
-    if (lk + KC < NCREC) d[lk + KC] = st1;
+#pragma unroll
+    for (int m = 0; m < NS; ++m)
+      if (lk + KC * m < kMicroRec) d[lk + KC * m] = rr[u][m];
   };
-  auto stage_small = [&](int hp, int p) {  // narrow chunks: the remaining entries
-    int c = cell_of_hp(hp);
-    if (c < 0 || 2 * KC >= NCREC) return;
-    double* d = CEL(p);
-    for (int e = lk + 2 * KC; e < NCREC; e += KC) d[e] = crec[(size_t)c * NCREC + e];
-  };
-  // streaming values of the next cell of this row
-  double n2 = 0, n3 = 0, n4 = 0, n5 = 0;
-  int ncell_ = -1;
-  auto stream_fwd = [&](int hp) {
-    ncell_ = cell_of_hp(hp);
-    if (ncell_ < 0 || g.type[ncell_] != 1) { ncell_ = -1; return; }
-    size_t o = (size_t)ncell_ * g.nv + kk;
-    n4 = (double)Dh[o]; n5 = (double)Db[o];  // the residual r
-  };
-  auto stream_bwd = [&](int hp) {
-    ncell_ = cell_of_hp(hp);
-    if (ncell_ < 0 || g.type[ncell_] != 1) { ncell_ = -1; return; }
-    size_t o = (size_t)ncell_ * g.nv + kk;
-    n2 = (double)h[o]; n3 = (double)b[o]; n4 = (double)Dh[o]; n5 = (double)Db[o];
+  // one cell of a sweep: returns false when (i, j) is outside the block
+  double ph = 0.0, pb = 0.0, chh = 0.0, cbb = 0.0;
+  auto cell = [&](int hp, int p, bool bwd, double a0, double a1, double f0, double f1) {
+    const int i = hp - j;
+    const bool act = row && i >= 0 && i < ni;
+    const double* r = CEL(p);
+    double ts[4];
+    double d = r[12];
+#pragma unroll
+    for (int s = 0; s < 2 * D; ++s) {
+      ts[s] = r[3 * s] * vx + r[3 * s + 1] * vy - r[3 * s + 2];
+      d += fmax(ts[s], 0.0);
+    }
+    const bool fld = act && r[13] != 0.0;
+    // couplings: along i from the row's previous cell (zero before the first
+    // cell of the sweep), along j through the hand-off buffer, and across
+    // periodic seams
+    const int si = bwd ? 1 : 0, sj = bwd ? 3 : 2;
+    double w = fmin(ts[si], 0.0);
+    double oh = w * ph, ob = w * pb;
+    if (D == 2) {
+      const double* q = HND(p ^ 1, bwd ? jl + 2 : jl);
+      w = fmin(ts[sj], 0.0);
+      oh += w * q[0]; ob += w * q[1];
+    }
+    const bool seam_i = pi && ni > 1 && i == (bwd ? 0 : ni - 1);
+    w = seam_i ? fmin(ts[bwd ? 0 : 1], 0.0) : 0.0;
+    oh += w * chh; ob += w * cbb;
+    if (D == 2 && pj) {
+      const bool seam_j = nj > 1 && j == (bwd ? 0 : nj - 1);
+      if (seam_j && act) {
+        const double* q = pjb + ((size_t)i * KC + lk) * 2;
+        w = fmin(ts[bwd ? 2 : 3], 0.0);
+        oh += w * q[0]; ob += w * q[1];
+      }
+    }
+    const double id = recip_pos(d);
+    double xh = bwd ? a0 - oh * id : (a0 - oh) * id;
+    double xb = bwd ? a1 - ob * id : (a1 - ob) * id;
+    xh = fld ? xh : 0.0;
+    xb = fld ? xb : 0.0;
+    if (act) {
+      if (fld && kin) {
+        const size_t o = (size_t)(cbase + i) * nv + k;
+        if (bwd) { h[o] = (T)(f0 + xh); b[o] = (T)(f1 + xb); }
+        else { Dh[o] = (T)xh; Db[o] = (T)xb; }
+      }
+      ph = xh; pb = xb;
+      if (i == (bwd ? ni - 1 : 0)) { chh = xh; cbb = xb; }
+      double* q = HND(p, j + 1);
+      q[0] = xh; q[1] = xb;
+      if (D == 2 && pj && j == (bwd ? nj - 1 : 0)) {
+        double* z = pjb + ((size_t)i * KC + lk) * 2;
+        z[0] = xh; z[1] = xb;
+      }
+    }
   };
 
   // ---------------- forward sweep: (D + L) dF* = r ----------------
-  stage_load(0);
-  stage_store(0);
-  stage_small(0, 0);
-  stream_fwd(0);
-  __syncthreads();
-  for (int hp = 0; hp < HH; ++hp) {
-    const int p = hp & 1;
-    const int c = ncell_;
-    const double rh = n4, rb = n5;
-    // issue the next hyperplane's loads
-    if (hp + 1 < HH) { stage_load(hp + 1); stream_fwd(hp + 1); }
-    const int i = hp - j;
-    const bool has = row && i >= 0 && i < ni;
-    double xh = 0.0, xb = 0.0;
-    if (c >= 0) {
-      const double* r = CEL(p);
-      double ts[2 * D];
-      double d = r[C_D0];
+  // Each ring slot is consumed by its hyperplane and then refilled with the
+  // hyperplane P later, so a slot keeps its registers around the loop.  The
+  // loop runs whole groups of P hyperplanes; the extra ones (hp >= HH) have
+  // no cells in any row.
 #pragma unroll
-      for (int s = 0; s < 2 * D; ++s) {
-        ts[s] = r[C_GEO + 3 * s] * vx + r[C_GEO + 3 * s + 1] * vy - r[C_GEO + 3 * s + 2];
-        d += (ts[s] > 0.0) ? ts[s] : 0.0;
-      }
-      double oh = 0.0, ob = 0.0;
-      if (i >= 1) { double w = fmin(ts[0], 0.0); oh += w * ph; ob += w * pb; }
-      if (D == 2 && j >= 1) {
-        const double* q = HND(p ^ 1, j - 1);
-        double w = fmin(ts[2], 0.0); oh += w * q[0]; ob += w * q[1];
-      }
-      if (pi && i == ni - 1 && ni > 1) { double w = fmin(ts[1], 0.0); oh += w * chh; ob += w * cbb; }
-      if (D == 2 && pj && j == nj - 1 && nj > 1) {
-        const double* q = PJ(i);
-        double w = fmin(ts[3], 0.0); oh += w * q[0]; ob += w * q[1];
-      }
-      const double id = 1.0 / d;
-      xh = (rh - oh) * id;
-      xb = (rb - ob) * id;
-      if (kin) {
-        size_t o = (size_t)c * g.nv + k;
-        Dh[o] = (T)xh;
-        Db[o] = (T)xb;
-      }
+  for (int u = 0; u < P; ++u) issue(u, u, false);
+  stage(0, 0);
+  __syncthreads();
+  for (int h0 = 0; h0 < HH; h0 += P) {
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int hp = h0 + u;
+      cell(hp, hp & 1, false, ra[u], rb_[u], 0.0, 0.0);
+      issue(u, hp + P, false);
+      stage((u + 1) % P, (hp + 1) & 1);
+      lds_barrier();
     }
-    if (has) {
-      ph = xh; pb = xb;
-      if (i == 0) { chh = xh; cbb = xb; }
-      double* q = HND(p, j);
-      q[0] = xh; q[1] = xb;
-      if (D == 2 && pj && j == 0) { double* z = PJ(i); z[0] = xh; z[1] = xb; }
-    }
-    if (hp + 1 < HH) { stage_store(p ^ 1); stage_small(hp + 1, p ^ 1); }
-    __syncthreads();
   }
   // ---------------- backward sweep: (D + U) dF = D dF* ----------------
   ph = pb = chh = cbb = 0.0;
-  stage_load(HH - 1);
-  stage_store((HH - 1) & 1);
-  stage_small(HH - 1, (HH - 1) & 1);
-  stream_bwd(HH - 1);
-  __syncthreads();
-  for (int hp = HH - 1; hp >= 0; --hp) {
-    const int p = hp & 1;
-    const int c = ncell_;
-    const double f0 = n2, f1 = n3, x0 = n4, x1 = n5;
-    if (hp >= 1) { stage_load(hp - 1); stream_bwd(hp - 1); }
-    const int i = hp - j;
-    const bool has = row && i >= 0 && i < ni;
-    double xh = 0.0, xb = 0.0;
-    if (c >= 0) {
-      const double* r = CEL(p);
-      double ts[2 * D];
-      double d = r[C_D0];
 #pragma unroll
-      for (int s = 0; s < 2 * D; ++s) {
-        ts[s] = r[C_GEO + 3 * s] * vx + r[C_GEO + 3 * s + 1] * vy - r[C_GEO + 3 * s + 2];
-        d += (ts[s] > 0.0) ? ts[s] : 0.0;
-      }
-      double oh = 0.0, ob = 0.0;
-      if (i + 1 < ni) { double w = fmin(ts[1], 0.0); oh += w * ph; ob += w * pb; }
-      if (D == 2 && j + 1 < nj) {
-        const double* q = HND(p ^ 1, j + 1);
-        double w = fmin(ts[3], 0.0); oh += w * q[0]; ob += w * q[1];
-      }
-      if (pi && i == 0 && ni > 1) { double w = fmin(ts[0], 0.0); oh += w * chh; ob += w * cbb; }
-      if (D == 2 && pj && j == 0 && nj > 1) {
-        const double* q = PJ(i);
-        double w = fmin(ts[2], 0.0); oh += w * q[0]; ob += w * q[1];
-      }
-      const double id = 1.0 / d;
-      xh = x0 - oh * id;
-      xb = x1 - ob * id;
-      if (kin) {
-        size_t o = (size_t)c * g.nv + k;
-        h[o] = (T)(f0 + xh);
-        b[o] = (T)(f1 + xb);
-      }
+  for (int u = 0; u < P; ++u) issue(u, HH - 1 - u, true);
+  stage(0, (HH - 1) & 1);
+  __syncthreads();
+  for (int h0 = HH - 1; h0 >= 0; h0 -= P) {
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int hp = h0 - u;
+      cell(hp, hp & 1, true, ra[u], rb_[u], rf0[u], rf1[u]);
+      issue(u, hp - P, true);
+      stage((u + 1) % P, (hp - 1) & 1);
+      lds_barrier();
     }
-    if (has) {
-      ph = xh; pb = xb;
-      if (i == ni - 1) { chh = xh; cbb = xb; }
-      double* q = HND(p, j);
-      q[0] = xh; q[1] = xb;
-      if (D == 2 && pj && j == nj - 1) { double* z = PJ(i); z[0] = xh; z[1] = xb; }
-    }
-    if (hp >= 1) { stage_store(p ^ 1); stage_small(hp - 1, p ^ 1); }
-    __syncthreads();
   }
 }
 
@@ -1654,24 +1674,34 @@ void launch_flux_t(const Dev& g, double dts, const void* h, const void* b, const
   k_flux<D, T, C><<<nb4(g.ncell), 256, 0, st>>>(g, (const T*)h, (const T*)b, rec, (T*)Dh, (T*)Db, F, wall);
 }
 
-constexpr int kRowGroup = 8;
+// core rows per workgroup of the march kernels (face-equilibrium and flux
+// passes): RG + 2 wavefronts share the reconstruction of RG rows
+#ifndef UGKS_RG_EQ
+#define UGKS_RG_EQ 8
+#endif
+#ifndef UGKS_RG_FLUX
+#define UGKS_RG_FLUX 8
+#endif
+constexpr int kRowGroupEq = UGKS_RG_EQ;
+constexpr int kRowGroupFlux = UGKS_RG_FLUX;
 
 template <class T, class C>
 void launch_march_t(const Dev& g, const int* binfo, int max_nj, double dts, const void* h, const void* b,
                     const double* W, const double* q, double* gW, double* rec, double* part, void* Dh, void* Db,
                     double* F, double* wall, hipStream_t st, hipEvent_t* ev) {
   const int nchunk = (g.nv + 63) / 64;
-  dim3 grid((unsigned)nchunk, (unsigned)((max_nj + kRowGroup - 1) / kRowGroup), (unsigned)g.nblock);
-  const int threads = 64 * (kRowGroup + 2);
+  dim3 grid0((unsigned)nchunk, (unsigned)((max_nj + kRowGroupEq - 1) / kRowGroupEq), (unsigned)g.nblock);
+  dim3 grid1((unsigned)nchunk, (unsigned)((max_nj + kRowGroupFlux - 1) / kRowGroupFlux), (unsigned)g.nblock);
   k_gradW<<<nbl(g.ncell, 256), 256, 0, st>>>(g, W, gW);
   k_wallprep<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, W, q, gW, rec);
   if (ev) (void)hipEventRecord(ev[0], st);
-  k_march<kRowGroup, T, C, 0><<<grid, threads, 0, st>>>(g, binfo, nchunk, (const T*)h, (const T*)b, W, rec, part,
-                                                        (T*)Dh, (T*)Db);
+  k_march<kRowGroupEq, T, C, 0><<<grid0, 64 * (kRowGroupEq + 2), 0, st>>>(g, binfo, nchunk, (const T*)h,
+                                                                           (const T*)b, W, rec, part, (T*)Dh, (T*)Db);
   k_face_fin<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, nchunk, part, W, gW, rec);
   if (ev) (void)hipEventRecord(ev[1], st);
-  k_march<kRowGroup, T, C, 1><<<grid, threads, 0, st>>>(g, binfo, nchunk, (const T*)h, (const T*)b, W, rec, part,
-                                                        (T*)Dh, (T*)Db);
+  k_march<kRowGroupFlux, T, C, 1><<<grid1, 64 * (kRowGroupFlux + 2), 0, st>>>(g, binfo, nchunk, (const T*)h,
+                                                                               (const T*)b, W, rec, part, (T*)Dh,
+                                                                               (T*)Db);
   k_flux_fin<<<nbl(g.nface, 256), 256, 0, st>>>(g, nchunk, part, rec, F, wall);
 }
 
@@ -1723,45 +1753,72 @@ void launch_step7(const Dev& g, int prec, int mode, const void* h, const void* b
   else k_step7<float><<<nb4(g.ncell), 256, 0, st>>>(g, mode, (const float*)h, (const float*)b, crec, Wp, W, q, mrec);
 }
 
-void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
+void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int any_pi, int any_pj, double dt,
                   const double* W, const double* Wn, const double* F, const double* Fn, double* gam, double* R,
                   double* Dg, double* dWs, double* dW, double* Wp, double* rpart, double* resid, hipStream_t st) {
   (void)Dg;
   k_gamma<<<nbl(g.nface, 256), 256, 0, st>>>(g, W, gam);
   k_macro_prep<<<nbl(g.ncell, 256), 256, 0, st>>>(g, dt, W, Wn, F, Fn, gam, R);
-  int nt = ((max_nj + 63) / 64) * 64;
-  size_t lds = sizeof(double) * (size_t)(2 * nt * 4 + (any_pj ? 4 * max_ni : 0));
-  if (g.dim == 2) k_macro_sweep<2><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, dWs, dW, Wp, rpart);
-  else k_macro_sweep<1><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, dWs, dW, Wp, rpart);
+  const int nt = ((max_nj + 63) / 64) * 64;
+  const size_t lds = macro_lds(nt, max_ni, max_nj, any_pi, any_pj);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_macro_sweep<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_macro_sweep<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  if (g.dim == 2)
+    k_macro_sweep<2><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, dWs, dW, Wp, rpart, max_ni, max_nj, any_pi, any_pj);
+  else
+    k_macro_sweep<1><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, dWs, dW, Wp, rpart, max_ni, max_nj, any_pi, any_pj);
   if (resid) k_resid<<<1, 64, 0, st>>>(g.nblock, g.nw, rpart, resid);
 }
 
 // velocity-chunk width of the micro sweep for a block height
+#ifndef UGKS_MICRO_KC_MAX
+#define UGKS_MICRO_KC_MAX 16
+#endif
+#ifndef UGKS_MICRO_DEPTH
+#define UGKS_MICRO_DEPTH 2
+#endif
 int micro_kc(int dim, int max_nj) {
   if (dim == 1) return 64;
-  int kc = 16;
-  while (kc > 1 && kc * max_nj > 1024) kc >>= 1;
+  int kc = UGKS_MICRO_KC_MAX;
+  while (kc > 2 && kc * max_nj > 1024) kc >>= 1;
   return kc;
 }
 
 size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj) {
   int kc = micro_kc(dim, max_nj);
   int nslot = (dim == 1) ? 1 : max_nj;
-  return sizeof(double) * (size_t)(4 * nslot * kc + 2 * nslot * NCREC + (any_pj ? 2 * max_ni * kc : 0));
+  return sizeof(double) * (size_t)(4 * (nslot + 2) * kc + 2 * nslot * kMicroRecLds + (any_pj ? 2 * max_ni * kc : 0));
 }
 
-template <int D, class T>
-static void micro_t(const Dev& g, const int* binfo, int KC, int nslot, size_t lds, double dt, const double* crec,
-                    void* h, void* b, const void* Sh, const void* Sb, void* Dh, void* Db, hipStream_t st) {
+template <int D, class T, int KC>
+static void micro_t(const Dev& g, const int* binfo, int nslot, size_t lds, const double* crec, void* h, void* b,
+                    void* Dh, void* Db, hipStream_t st) {
+  constexpr int P = UGKS_MICRO_DEPTH;
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_micro<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_micro<D, T, KC, P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
     attr = true;
   }
   dim3 grid((unsigned)((g.nv + KC - 1) / KC), (unsigned)g.nblock);
   int threads = ((nslot * KC + 63) / 64) * 64;
-  k_micro<D, T><<<grid, threads, lds, st>>>(g, binfo, KC, nslot, dt, crec, (T*)h, (T*)b, (const T*)Sh,
-                                            (const T*)Sb, (T*)Dh, (T*)Db);
+  k_micro<D, T, KC, P><<<grid, threads, lds, st>>>(g, binfo, nslot, crec, (T*)h, (T*)b, (T*)Dh, (T*)Db);
+}
+
+template <class T>
+static void micro_prec(const Dev& g, const int* binfo, int KC, int nslot, size_t lds, const double* crec, void* h,
+                       void* b, void* Dh, void* Db, hipStream_t st) {
+  if (g.dim == 1) { micro_t<1, T, 64>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); return; }
+  switch (KC) {
+    case 16: micro_t<2, T, 16>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    case 8: micro_t<2, T, 8>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    case 4: micro_t<2, T, 4>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    default: micro_t<2, T, 2>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+  }
 }
 
 void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
@@ -1774,16 +1831,11 @@ void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_
   else
     k_micro_rhs<float><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const float*)h, (const float*)b,
                                                      (const float*)Sh, (const float*)Sb, (float*)Dh, (float*)Db);
-  int KC = micro_kc(g.dim, max_nj);
-  int nslot = (g.dim == 1) ? 1 : max_nj;
-  size_t lds = micro_lds(g.dim, max_ni, max_nj, any_pj);
-  if (g.dim == 2) {
-    if (prec == 0) micro_t<2, double>(g, binfo, KC, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st);
-    else micro_t<2, float>(g, binfo, KC, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st);
-  } else {
-    if (prec == 0) micro_t<1, double>(g, binfo, KC, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st);
-    else micro_t<1, float>(g, binfo, KC, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st);
-  }
+  const int KC = micro_kc(g.dim, max_nj);
+  const int nslot = (g.dim == 1) ? 1 : max_nj;
+  const size_t lds = micro_lds(g.dim, max_ni, max_nj, any_pj);
+  if (prec == 0) micro_prec<double>(g, binfo, KC, nslot, lds, crec, h, b, Dh, Db, st);
+  else micro_prec<float>(g, binfo, KC, nslot, lds, crec, h, b, Dh, Db, st);
 }
 
 }  // namespace ugks
