@@ -585,8 +585,11 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
                                                          const double* __restrict__ rec,
                                                          double* __restrict__ part, T* __restrict__ Dh,
                                                          T* __restrict__ Db) {
-  __shared__ LD6<C> lds[2][RG + 2][64];
-  __shared__ C jfl[RG + 2][2][64];  // j-face flux above each row (h, b)
+  // reconstruction of three columns (x - 1, x, x + 1 in flight), raw values
+  // of one column per row for the j-neighbours, j-face fluxes of two columns
+  __shared__ LD6<C> lds[3][RG + 2][64];
+  __shared__ C pub[2][RG + 2][2][64];
+  __shared__ C jfl[2][RG + 2][2][64];
   const int* bi = binfo + 8 * blockIdx.z;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], per_i = bi[3], per_j = bi[4];
   const int j0 = blockIdx.y * RG;
@@ -599,31 +602,77 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   const int kk = kin ? k : g.nv - 1;
   const double vx = g.vx[kk], vy = g.vy[kk];
   const double wk = kin ? g.wk[kk] : 0.0;
-  const T* hinf = (const T*)g.finf_h;
-  const T* binf = (const T*)g.finf_b;
-  // this wavefront's row (periodic wrap for the halo rows)
-  int jr = j0 - 1 + w;
-  if (jr < 0) jr = per_j ? jr + nj : -1;
-  else if (jr >= nj) jr = per_j ? jr - nj : -1;
+  const C finh = (C)((const T*)g.finf_h)[kk];
+  const C finb = (C)((const T*)g.finf_b)[kk];
+  auto wrap_row = [&](int j) -> int {
+    if (j >= 0 && j < nj) return j;
+    return per_j ? ((j % nj) + nj) % nj : -1;
+  };
+  // this wavefront's row (periodic wrap for the halo rows) and, for the two
+  // halo wavefronts, the row beyond it
+  const int jr = wrap_row(j0 - 1 + w);
+  const int jo = (jr < 0) ? -1 : (w == 0) ? wrap_row(j0 - 2) : (w == RG + 1) ? wrap_row(j0 + RG + 1) : -1;
   const bool core = (w >= 1) && (w <= RG) && (j0 - 1 + w < nj);
-  // the row above exists in the block (or by periodicity)
   auto cell = [&](int x, int j) -> int { return c0 + x + ni * j; };
-  // reconstruction of cell (x, jr) into LDS slot (x & 1)
-  auto recon_step = [&](int x) {
+  auto col = [&](int x) -> int {  // column in the block, or -1
+    if (x >= 0 && x < ni) return x;
+    return per_i ? ((x % ni) + ni) % ni : -1;
+  };
+  auto raw = [&](int row, int x, C& vh, C& vb) {
+    const int xw = col(x);
+    if (row < 0 || xw < 0) { vh = C(0); vb = C(0); return; }
+    const size_t o = (size_t)cell(xw, row) * g.nv + kk;
+    vh = (C)h[o];
+    vb = (C)b[o];
+  };
+  auto slot = [](int x) -> int { return (x + 6) % 3; };
+  // raw values of this row: window (x, x+1, x+2) and the next column in
+  // flight; the outer row of a halo wavefront at x+1 and x+2
+  C a0h, a0b, a1h, a1b, a2h, a2b, p_h, p_b, oc_h, oc_b, on_h, on_b;
+  // reconstruction of column x + 1 (window centre) into LDS
+  auto recon = [&](int x1) {
     if (jr < 0) return;
-    int xx = x;
-    if (xx >= ni) { if (!per_i) return; xx -= ni; }
-    if (xx < 0) { if (!per_i) return; xx += ni; }
-    const int c = __builtin_amdgcn_readfirstlane(cell(xx, jr));
+    const int xw = col(x1);
+    if (xw < 0) return;
+    const int c = __builtin_amdgcn_readfirstlane(cell(xw, jr));
     if (g.type[c] == 0) return;
     int nbc[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) nbc[s] = g.nb[4 * c + s];
+    for (int q = 0; q < 4; ++q) nbc[q] = g.nb[4 * c + q];
     const double* G = g.G + 4 * c;
+    const int pp = x1 & 1;
+    auto nbv = [&](int code, C cellv, C finv, C self) -> C {
+      return (code >= 0) ? cellv : ((code == kNbFar) ? finv : self);
+    };
+    const C lo_h = (w == 0) ? oc_h : pub[pp][(w == 0) ? 0 : w - 1][0][lane];
+    const C lo_b = (w == 0) ? oc_b : pub[pp][(w == 0) ? 0 : w - 1][1][lane];
+    const C hi_h = (w == RG + 1) ? oc_h : pub[pp][(w == RG + 1) ? RG + 1 : w + 1][0][lane];
+    const C hi_b = (w == RG + 1) ? oc_b : pub[pp][(w == RG + 1) ? RG + 1 : w + 1][1][lane];
     LD6<C> L;
-    cell_recon<T, C>(g, h, hinf, c, nbc, G, kk, L.hv, L.hx, L.hy);
-    cell_recon<T, C>(g, b, binf, c, nbc, G, kk, L.bv, L.bx, L.by);
-    lds[x & 1][w][lane] = L;
+    {
+      const C v = a1h;
+      const C si = climit<C>(nbc[0], nbc[1], nbv(nbc[0], a0h, finh, v), v, nbv(nbc[1], a2h, finh, v));
+      const C sj = climit<C>(nbc[2], nbc[3], nbv(nbc[2], lo_h, finh, v), v, nbv(nbc[3], hi_h, finh, v));
+      L.hv = v;
+      L.hx = (C)G[0] * si + (C)G[1] * sj;
+      L.hy = (C)G[2] * si + (C)G[3] * sj;
+    }
+    {
+      const C v = a1b;
+      const C si = climit<C>(nbc[0], nbc[1], nbv(nbc[0], a0b, finb, v), v, nbv(nbc[1], a2b, finb, v));
+      const C sj = climit<C>(nbc[2], nbc[3], nbv(nbc[2], lo_b, finb, v), v, nbv(nbc[3], hi_b, finb, v));
+      L.bv = v;
+      L.bx = (C)G[0] * si + (C)G[1] * sj;
+      L.by = (C)G[2] * si + (C)G[3] * sj;
+    }
+    lds[slot(x1)][w][lane] = L;
+  };
+  auto ghost = [&](const LD6<C>& L, int code) -> Side<C> {
+    Side<C> S;
+    S.hv = (code == kNbFar) ? finh : L.hv;
+    S.bv = (code == kNbFar) ? finb : L.bv;
+    S.hx = S.hy = S.bx = S.by = C(0);
+    return S;
   };
   // upwind interface data of a face between sides sl (low) and sh (high)
   // with normal (nx, ny) and mesh velocity (ux, uy)
@@ -722,109 +771,135 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     multi_sum<4>(m, lane);
     if ((lane & 15) == 0) part[((size_t)chunk * g.nface + fw) * kFluxP + (lane >> 4)] = m[0];
   };
-  // generic face between cell (x, jr) side slot s and its neighbour, given
-  // LDS data of both sides when they are cells; returns the flux along the
-  // face normal in facc
-  double fi_prev[2] = {0.0, 0.0};  // i-face (x-1|x) of this row
-  if (per_i) recon_step(-1);
-  __syncthreads();
-  for (int x = -1; x < ni; ++x) {
-    // reconstruction of the next cell
-    if (x + 1 <= ni) recon_step(x + 1);
-    __syncthreads();
+  // march: step x reconstructs column x + 1, then evaluates the faces of
+  // column x (i-face (x|x+1), j-face above x) and, in flux mode, gathers the
+  // divergence of column x - 1 from the faces of the previous step
+  raw(jr, -2, a0h, a0b);
+  raw(jr, -1, a1h, a1b);
+  raw(jr, 0, a2h, a2b);
+  raw(jr, 1, p_h, p_b);
+  raw(jo, -1, oc_h, oc_b);
+  raw(jo, 0, on_h, on_b);
+  pub[1][w][0][lane] = a1h;  // column -1
+  pub[1][w][1][lane] = a1b;
+  lds_barrier();
+  double fi_m2[2] = {0.0, 0.0}, fi_m1[2] = {0.0, 0.0}, fj_m1[2] = {0.0, 0.0};
+  auto divergence = [&](int x) {
+    // divergence of cell (x, jr) of a core row from the i-faces (x-1|x) and
+    // (x|x+1), the j-face above (this row) and below (the row beneath)
+    if (!(core && jr >= 0 && x >= 0 && kin)) return;
+    const int c = cell(x, jr);
+    double dh = 0.0, db = 0.0;
+    if (g.type[c] == 1) {
+      const double ivol = 1.0 / g.vol[c];
+      const int f0 = g.cf[4 * c], f1 = g.cf[4 * c + 1], f2 = g.cf[4 * c + 2], f3 = g.cf[4 * c + 3];
+      const double S0 = (f0 >= 0) ? g.fgeo[(size_t)f0 * 8 + 2] : 0.0;
+      const double S1 = (f1 >= 0) ? g.fgeo[(size_t)f1 * 8 + 2] : 0.0;
+      const double S2 = (f2 >= 0) ? g.fgeo[(size_t)f2 * 8 + 2] : 0.0;
+      const double S3 = (f3 >= 0) ? g.fgeo[(size_t)f3 * 8 + 2] : 0.0;
+      const double bh = (double)jfl[x & 1][w - 1][0][lane], bb = (double)jfl[x & 1][w - 1][1][lane];
+      dh = -ivol * (-S0 * fi_m2[0] + S1 * fi_m1[0] - S2 * bh + S3 * fj_m1[0]);
+      db = -ivol * (-S0 * fi_m2[1] + S1 * fi_m1[1] - S2 * bb + S3 * fj_m1[1]);
+    }
+    Dh[(size_t)c * g.nv + k] = (T)dh;
+    Db[(size_t)c * g.nv + k] = (T)db;
+  };
+  for (int x = -2; x < ni; ++x) {
+    recon(x + 1);
+    // publish column x + 2 of this row, advance the windows
+    pub[x & 1][w][0][lane] = a2h;
+    pub[x & 1][w][1][lane] = a2b;
+    a0h = a1h; a0b = a1b; a1h = a2h; a1b = a2b; a2h = p_h; a2b = p_b;
+    raw(jr, x + 4, p_h, p_b);
+    oc_h = on_h; oc_b = on_b;
+    raw(jo, x + 3, on_h, on_b);
+    lds_barrier();
+    if (MODE == 1) {
+      divergence(x - 1);
+      fi_m2[0] = fi_m1[0]; fi_m2[1] = fi_m1[1];
+    }
+    if (x < -1) continue;
+    const int sx0 = slot(x), sx1 = slot(x + 1);
     double fi_cur[2] = {0.0, 0.0}, fj_cur[2] = {0.0, 0.0};
     constexpr int NM = (MODE == 0) ? kMomP : kFluxP;
     double mi[NM], mj[NM];
 #pragma unroll
     for (int q = 0; q < NM; ++q) { mi[q] = 0.0; mj[q] = 0.0; }
     int fiw = -1, fjw = -1;
-    // i-face (x|x+1) of a core row
-    if (core && jr >= 0) {
-      const int cl = (x >= 0) ? cell(x, jr) : -1;
-      const int cr = (x + 1 < ni) ? cell(x + 1, jr) : -1;
-      int f;
-      if (cl >= 0) f = g.cf[4 * cl + 1];
-      else f = g.cf[4 * cr + 0];
-      if (f >= 0 && g.fact[f]) {
-        const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
-        // owner: the low cell, or the cell of a boundary face; a periodic
-        // seam face (x = -1) is written by the high end of the row
-        const bool owner = (x >= 0) || (L < 0);
+    // the two faces of this column: q = 0 the i-face (x|x+1) of a core row,
+    // q = 1 the j-face above (x, jr) for the bottom halo and core rows
+    auto face_q = [&](int q) {
+      int f = -1;
+      bool owner = false;
+      if (q == 0) {
+        if (!(core && jr >= 0)) return;
+        const int cl = (x >= 0) ? cell(x, jr) : -1;
+        const int cr = (x + 1 < ni) ? cell(x + 1, jr) : -1;
+        f = (cl >= 0) ? g.cf[4 * cl + 1] : g.cf[4 * cr + 0];
+      } else {
+        if (!(x >= 0 && w <= RG && (j0 - 1 + w < nj))) return;
+        const int jh = wrap_row(j0 + w);  // high row (the low row jr may be absent: boundary below)
+        if (jr >= 0) f = g.cf[4 * cell(x, jr) + 3];
+        if (f < 0 && jh >= 0) f = g.cf[4 * cell(x, jh) + 2];
+      }
+      if (f < 0 || !g.fact[f]) return;
+      const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
+      // owner: the low cell, or the cell of a boundary face; a periodic seam
+      // i-face (x = -1) is written by the high end of the row; the bottom
+      // halo writes only the block's lower boundary j-face
+      owner = ((q == 0) ? (x >= 0) : (w >= 1)) || (L < 0);
+      const LD6<C>& lo = lds[sx0][w][lane];
+      const LD6<C>& hi = (q == 0) ? lds[sx1][w][lane] : lds[sx0][w + 1][lane];
+      double fc[2] = {0.0, 0.0}, mom[NM];
+#pragma unroll
+      for (int m = 0; m < NM; ++m) mom[m] = 0.0;
+      if (L == kNbWall || R == kNbWall) {
+        const int c = (L == kNbWall) ? R : L;
+        const int sd = (q == 0) ? ((L == kNbWall) ? 0 : 1) : ((L == kNbWall) ? 2 : 3);
+        wall_eval(f, c, sd, (L == kNbWall) ? hi : lo, fc, mom);
+      } else {
+        // the low side of the seam face (x = -1) is cell ni-1, staged as column -1
+        const Side<C> sl = (L >= 0) ? side_from_cell<T, C>(g, lo, L, (q == 0) ? 1 : 3) : ghost(hi, L);
+        const Side<C> sh = (R >= 0) ? side_from_cell<T, C>(g, hi, R, (q == 0) ? 0 : 2) : ghost(lo, R);
+        face_eval(f, sl, sh, fc, mom);
+      }
+      if (MODE == 1) write_flux(owner ? f : -1, mom);
+      if (q == 0) {
+        fi_cur[0] = fc[0]; fi_cur[1] = fc[1];
         if (owner) fiw = f;
-        if (L == kNbWall || R == kNbWall) {
-          const int c = (L == kNbWall) ? R : L;
-          const int s = (L == kNbWall) ? 0 : 1;
-          const int xc = (L == kNbWall) ? x + 1 : x;
-          wall_eval(f, c, s, lds[xc & 1][w][lane], fi_cur, mi);
-        } else {
-          Side<C> sl, sh;
-          // the low side of the seam face (x = -1) is cell ni-1, staged in slot (-1) & 1
-          if (L >= 0) sl = side_from_cell<T, C>(g, lds[x & 1][w][lane], L, 1);
-          if (R >= 0) sh = side_from_cell<T, C>(g, lds[(x + 1) & 1][w][lane], R, 0);
-          if (L < 0) sl = side_ghost<T, C>(g, lds[(x + 1) & 1][w][lane], L, kk);
-          if (R < 0) sh = side_ghost<T, C>(g, lds[x & 1][w][lane], R, kk);
-          face_eval(f, sl, sh, fi_cur, mi);
+        if (MODE == 0) {
+#pragma unroll
+          for (int m = 0; m < NM; ++m) mi[m] = mom[m];
         }
-        if (MODE == 1) write_flux(fiw, mi);
-      }
-    }
-    // j-face (jr|jr+1) at column x, for the bottom halo and the core rows
-    if (x >= 0 && w <= RG && (j0 - 1 + w < nj)) {
-      const int jl = jr;                                     // low row (may be absent: boundary below)
-      const int jh = (j0 + w < nj) ? j0 + w : (per_j ? j0 + w - nj : -1);  // high row
-      int f = -1, Lc = -1, Hc = -1;
-      if (jl >= 0) { Lc = cell(x, jl); f = g.cf[4 * Lc + 3]; }
-      if (jh >= 0) { Hc = cell(x, jh); if (f < 0) f = g.cf[4 * Hc + 2]; }
-      if (f >= 0 && g.fact[f]) {
-        const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
-        // core rows own the face above them; the bottom halo writes only
-        // the block's lower boundary face
-        const bool owner = (w >= 1) || (L < 0);
+      } else {
+        fj_cur[0] = fc[0]; fj_cur[1] = fc[1];
         if (owner) fjw = f;
-        if (L == kNbWall || R == kNbWall) {
-          const int c = (L == kNbWall) ? R : L;
-          const int s = (L == kNbWall) ? 2 : 3;
-          const int wc = (L == kNbWall) ? w + 1 : w;
-          wall_eval(f, c, s, lds[x & 1][wc][lane], fj_cur, mj);
-        } else {
-          Side<C> sl, sh;
-          if (L >= 0) sl = side_from_cell<T, C>(g, lds[x & 1][w][lane], L, 3);
-          if (R >= 0) sh = side_from_cell<T, C>(g, lds[x & 1][w + 1][lane], R, 2);
-          if (L < 0) sl = side_ghost<T, C>(g, lds[x & 1][w + 1][lane], L, kk);
-          if (R < 0) sh = side_ghost<T, C>(g, lds[x & 1][w][lane], R, kk);
-          face_eval(f, sl, sh, fj_cur, mj);
+        if (MODE == 0) {
+#pragma unroll
+          for (int m = 0; m < NM; ++m) mj[m] = mom[m];
         }
-        if (MODE == 1) write_flux(fjw, mj);
       }
-      if (MODE == 1) { jfl[w][0][lane] = (C)fj_cur[0]; jfl[w][1][lane] = (C)fj_cur[1]; }
+    };
+    if constexpr (MODE == 0) {
+      face_q(0);
+      face_q(1);
+    } else {
+      // one evaluation path for both faces (not unrolled), so that only one
+      // face's data is live: the flux pass is register bound
+#pragma clang loop unroll(disable)
+      for (int q = 0; q < 2; ++q) face_q(q);
+    }
+    if (MODE == 1 && x >= 0 && w <= RG && (j0 - 1 + w < nj)) {
+      jfl[x & 1][w][0][lane] = (C)fj_cur[0];
+      jfl[x & 1][w][1][lane] = (C)fj_cur[1];
     }
     if (MODE == 0) write_partials(fiw, mi, fjw, mj);
-    if (MODE == 1) {
-      __syncthreads();
-      // divergence of cell (x, jr) of a core row
-      if (core && jr >= 0 && x >= 0) {
-        const int c = cell(x, jr);
-        if (kin) {
-          double dh = 0.0, db = 0.0;
-          if (g.type[c] == 1) {
-            const double ivol = 1.0 / g.vol[c];
-            const int f0 = g.cf[4 * c], f1 = g.cf[4 * c + 1], f2 = g.cf[4 * c + 2], f3 = g.cf[4 * c + 3];
-            const double S0 = (f0 >= 0) ? g.fgeo[(size_t)f0 * 8 + 2] : 0.0;
-            const double S1 = (f1 >= 0) ? g.fgeo[(size_t)f1 * 8 + 2] : 0.0;
-            const double S2 = (f2 >= 0) ? g.fgeo[(size_t)f2 * 8 + 2] : 0.0;
-            const double S3 = (f3 >= 0) ? g.fgeo[(size_t)f3 * 8 + 2] : 0.0;
-            const double bh = (double)jfl[w - 1][0][lane], bb = (double)jfl[w - 1][1][lane];
-            dh = -ivol * (-S0 * fi_prev[0] + S1 * fi_cur[0] - S2 * bh + S3 * fj_cur[0]);
-            db = -ivol * (-S0 * fi_prev[1] + S1 * fi_cur[1] - S2 * bb + S3 * fj_cur[1]);
-          }
-          Dh[(size_t)c * g.nv + k] = (T)dh;
-          Db[(size_t)c * g.nv + k] = (T)db;
-        }
-      }
-    }
-    fi_prev[0] = fi_cur[0];
-    fi_prev[1] = fi_cur[1];
-    __syncthreads();
+    fi_m1[0] = fi_cur[0]; fi_m1[1] = fi_cur[1];
+    fj_m1[0] = fj_cur[0]; fj_m1[1] = fj_cur[1];
+  }
+  if (MODE == 1) {
+    lds_barrier();
+    divergence(ni - 1);
   }
 }
 
