@@ -43,6 +43,9 @@ def lib():
         L.or_set_overset.argtypes = [C.c_void_p, C.c_int, I, I, I, D]
         L.or_get_overset.argtypes = [C.c_void_p, I, I, I, D]
         L.or_get_overset.restype = C.c_int
+        L.or_overset_count.argtypes = [C.c_void_p]
+        L.or_nodes.argtypes = [C.c_void_p, D, D]
+        L.or_overset_count.restype = C.c_int
         L.or_maxwellian.argtypes = [C.c_void_p, D, D, D]
         L.or_moments.argtypes = [C.c_void_p, D, D, D, D]
         L.or_heatflux.argtypes = [C.c_void_p, D, D, D, D]
@@ -161,6 +164,12 @@ class Oracle:
                           _d(fx), _d(fu))
         return dict(cx=cx, vol=vol, g=g, fl=fl, fr=fr, fn=fn, fs=fs, fx=fx, fu=fu)
 
+    def nodes(self):
+        nn = sum((b.ni + 1) * (b.nj + 1) for b in self.case.blocks)
+        x = np.zeros(nn); y = np.zeros(nn)
+        lib().or_nodes(self.ptr, _d(x), _d(y))
+        return x, y
+
     def face_ids(self):
         a = [np.zeros(self.nface, np.int32) for _ in range(4)]
         lib().or_face_ids(self.ptr, *[_i(x) for x in a])
@@ -203,12 +212,15 @@ class Oracle:
         return rc, int(n[0])
 
     def overset(self):
+        """Installed donor table: (rec, ptr, don, w)."""
         L = lib()
-        nrec = self.assemble_count if hasattr(self, "assemble_count") else None
-        ptr_probe = np.zeros(self.ncell + 1, np.int32)
+        ptr = np.zeros(self.ncell + 1, np.int32)
         rec = np.zeros(self.ncell, np.int32)
-        nd = L.or_get_overset(self.ptr, _i(rec), _i(ptr_probe), None, None)
-        return rec, ptr_probe, nd
+        nd = L.or_get_overset(self.ptr, _i(rec), _i(ptr), None, None)
+        nrec = int(L.or_overset_count(self.ptr))
+        don = np.zeros(max(nd, 1), np.int32); w = np.zeros(max(nd, 1))
+        L.or_get_overset(self.ptr, None, None, _i(don), _d(w))
+        return rec[:nrec], ptr[:nrec + 1], don[:nd], w[:nd]
 
     # physics --------------------------------------------------------------
     def maxwellian(self, W):

@@ -679,6 +679,13 @@ void or_geometry(const or_case* c, double* cx, double* vol, double* g, int* fl, 
   }
 }
 
+void or_nodes(const or_case* c, double* x, double* y) {
+  int nn = 0;
+  for (int b = 0; b < c->nblock; b++) nn += (c->blk[b].ni + 1) * (c->blk[b].nj + 1);
+  memcpy(x, c->xn, sizeof(double) * nn);
+  memcpy(y, c->yn, sizeof(double) * nn);
+}
+
 void or_face_ids(const or_case* c, int* blk, int* dir, int* fi, int* fj) {
   for (int f = 0; f < c->nface; f++) {
     const face_t* F = &c->face[f];
@@ -708,6 +715,8 @@ void or_set_overset(or_case* c, int nrec, const int* rec, const int* ptr, const 
   memcpy(c->dptr, ptr, sizeof(int) * (nrec + 1));
   if (nd > 0) { memcpy(c->don, don, sizeof(int) * nd); memcpy(c->dw, w, sizeof(double) * nd); }
 }
+
+int or_overset_count(const or_case* c) { return c->nrec; }
 
 int or_get_overset(const or_case* c, int* rec, int* ptr, int* don, double* w) {
   if (rec) memcpy(rec, c->rec, sizeof(int) * c->nrec);
@@ -1480,10 +1489,306 @@ void or_pseudo_step(const or_case* c, double dt, double dts, const double* dtp,
 }
 
 /* ------------------------------------------------------------------------ */
-/* overset assembly -- placeholder until the assembly section below exists   */
+/* overset assembly (Sec. 3.1) and interpolation weights (Sec. 3.2).        */
+/* Brute force: every node is tested against every cell of the other zones  */
+/* and every wall segment.  Each block is one grid zone.  Geometric          */
+/* predicates use the fixed expressions below (no contraction), so that the  */
+/* integer results are reproducible bit for bit:                             */
+/*   point in quad:  all edge cross products (q_{k+1} - q_k) x (p - q_k) of  */
+/*                   one sign or zero (edges and corners count as inside);   */
+/*   wall distance:  squared distance to the nearest wall segment of the     */
+/*                   zone, +inf for a zone without walls;                    */
+/*   inside a body:  crossing number against each closed wall polygon of     */
+/*                   the other zones (half-open in y).                       */
 /* ------------------------------------------------------------------------ */
+static int quad_contains(const double* qx, const double* qy, double px, double py) {
+  int pos = 0, neg = 0;
+  for (int k = 0; k < 4; k++) {
+    int k1 = (k + 1) % 4;
+    double cr = (qx[k1] - qx[k]) * (py - qy[k]) - (qy[k1] - qy[k]) * (px - qx[k]);
+    if (cr > 0.0) pos = 1;
+    if (cr < 0.0) neg = 1;
+  }
+  return !(pos && neg);
+}
+
+static void cell_quad(const or_case* c, int n, double* qx, double* qy) {
+  int b = c->cblk[n], i = c->ci[n], j = c->cj[n];
+  qx[0] = node_x(c, b, i, j);         qy[0] = node_y(c, b, i, j);
+  qx[1] = node_x(c, b, i + 1, j);     qy[1] = node_y(c, b, i + 1, j);
+  qx[2] = node_x(c, b, i + 1, j + 1); qy[2] = node_y(c, b, i + 1, j + 1);
+  qx[3] = node_x(c, b, i, j + 1);     qy[3] = node_y(c, b, i, j + 1);
+}
+
+static double seg_dist2(double px, double py, double ax, double ay, double bx, double by) {
+  double ex = bx - ax, ey = by - ay;
+  double l2 = ex * ex + ey * ey;
+  double t = 0.0;
+  if (l2 > 0.0) {
+    t = ((px - ax) * ex + (py - ay) * ey) / l2;
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+  }
+  double dx = px - (ax + t * ex), dy = py - (ay + t * ey);
+  return dx * dx + dy * dy;
+}
+
+/* the nodes of wall side s of block b, in order along the side */
+static int side_nodes(const or_case* c, int b, int s, double* x, double* y) {
+  const blk_t* B = &c->blk[b];
+  int n = (s < 2) ? B->nj + 1 : B->ni + 1;
+  for (int m = 0; m < n; m++) {
+    int i = (s == 0) ? 0 : (s == 1) ? B->ni : m;
+    int j = (s == 2) ? 0 : (s == 3) ? B->nj : m;
+    x[m] = node_x(c, b, i, j);
+    y[m] = node_y(c, b, i, j);
+  }
+  return n;
+}
+
+/* a wall side closes into a body outline when the block is periodic along it */
+static int side_closed(const or_case* c, int b, int s) {
+  const blk_t* B = &c->blk[b];
+  return (s < 2) ? B->bc[2] == OR_PERIODIC : B->bc[0] == OR_PERIODIC;
+}
+
+static double wall_dist2(const or_case* c, int b, double px, double py, double* bx, double* by) {
+  double d2 = INFINITY;
+  for (int s = 0; s < 4; s++) {
+    if (c->blk[b].bc[s] != OR_WALL) continue;
+    int n = side_nodes(c, b, s, bx, by);
+    for (int m = 0; m + 1 < n; m++) {
+      double e = seg_dist2(px, py, bx[m], by[m], bx[m + 1], by[m + 1]);
+      if (e < d2) d2 = e;
+    }
+  }
+  return d2;
+}
+
+static int inside_body(const or_case* c, int self, double px, double py, double* bx, double* by) {
+  for (int b = 0; b < c->nblock; b++) {
+    if (b == self) continue;
+    for (int s = 0; s < 4; s++) {
+      if (c->blk[b].bc[s] != OR_WALL || !side_closed(c, b, s)) continue;
+      int n = side_nodes(c, b, s, bx, by);
+      int in = 0;
+      for (int m = 0; m + 1 < n; m++) {
+        double ax = bx[m], ay = by[m], ex = bx[m + 1], ey = by[m + 1];
+        if ((ay > py) != (ey > py)) {
+          double xi = ax + (py - ay) * (ex - ax) / (ey - ay);
+          if (px < xi) in = !in;
+        }
+      }
+      if (in) return 1;
+    }
+  }
+  return 0;
+}
+
+/* cell layers between cell n and the nearest overset (no-face) side of its
+   block; a large number for a block without such a side */
+static int overset_depth(const or_case* c, int n) {
+  const blk_t* B = &c->blk[c->cblk[n]];
+  int i = c->ci[n], j = c->cj[n], d = 1 << 30;
+  if (B->bc[0] == OR_NONE && i < d) d = i;
+  if (B->bc[1] == OR_NONE && B->ni - 1 - i < d) d = B->ni - 1 - i;
+  if (B->bc[2] == OR_NONE && j < d) d = j;
+  if (B->bc[3] == OR_NONE && B->nj - 1 - j < d) d = B->nj - 1 - j;
+  return d;
+}
+
+/* lowest cell of block b containing (px, py), restricted to field cells
+   when `types` is given; -1 if none */
+static int containing_cell(const or_case* c, int b, double px, double py, const int8_t* types) {
+  const blk_t* B = &c->blk[b];
+  double qx[4], qy[4];
+  for (int n = B->cell0; n < B->cell0 + B->ni * B->nj; n++) {
+    if (types && types[n] != OR_FIELD) continue;
+    cell_quad(c, n, qx, qy);
+    if (quad_contains(qx, qy, px, py)) return n;
+  }
+  return -1;
+}
+
+/* index neighbour of cell n along dir (0: i, 1: j), side -1 / +1, inside
+   its block (periodic wrap), or -1 */
+static int index_nb(const or_case* c, int n, int dir, int side) {
+  int b = c->cblk[n], i = c->ci[n], j = c->cj[n];
+  const blk_t* B = &c->blk[b];
+  if (dir == 0) {
+    i += side;
+    if (i < 0 || i >= B->ni) {
+      if (B->bc[0] != OR_PERIODIC) return -1;
+      i = (i + B->ni) % B->ni;
+    }
+  } else {
+    j += side;
+    if (j < 0 || j >= B->nj) {
+      if (B->bc[2] != OR_PERIODIC) return -1;
+      j = (j + B->nj) % B->nj;
+    }
+  }
+  return cell_index(c, b, i, j);
+}
+
+/* bilinear weights of (px, py) in the quad of cell centres n[0..3] (Newton
+   for the inverse bilinear map, three steps from the middle) */
+static void bilinear(const or_case* c, const int* n, double px, double py, double* w) {
+  double x0 = c->cx[n[0]], x1 = c->cx[n[1]], x2 = c->cx[n[2]], x3 = c->cx[n[3]];
+  double y0 = c->cy[n[0]], y1 = c->cy[n[1]], y2 = c->cy[n[2]], y3 = c->cy[n[3]];
+  double s = 0.5, t = 0.5;
+  for (int it = 0; it < 3; it++) {
+    double rx = (1.0 - s) * (1.0 - t) * x0 + s * (1.0 - t) * x1 + s * t * x2 + (1.0 - s) * t * x3 - px;
+    double ry = (1.0 - s) * (1.0 - t) * y0 + s * (1.0 - t) * y1 + s * t * y2 + (1.0 - s) * t * y3 - py;
+    double xs = (1.0 - t) * (x1 - x0) + t * (x2 - x3), ys = (1.0 - t) * (y1 - y0) + t * (y2 - y3);
+    double xt = (1.0 - s) * (x3 - x0) + s * (x2 - x1), yt = (1.0 - s) * (y3 - y0) + s * (y2 - y1);
+    double det = xs * yt - xt * ys;
+    s -= (rx * yt - xt * ry) / det;
+    t -= (xs * ry - rx * ys) / det;
+  }
+  w[0] = (1.0 - s) * (1.0 - t); w[1] = s * (1.0 - t); w[2] = s * t; w[3] = (1.0 - s) * t;
+}
+
 int or_assemble(or_case* c, int wrule, int overlap, int* nrec_out) {
-  (void)c; (void)wrule; (void)overlap;
   *nrec_out = 0;
-  return -6;
+  if (c->dim != 2) return -6;
+  int ncell = c->ncell;
+  int maxside = 0;
+  for (int b = 0; b < c->nblock; b++) {
+    if (c->blk[b].ni + 1 > maxside) maxside = c->blk[b].ni + 1;
+    if (c->blk[b].nj + 1 > maxside) maxside = c->blk[b].nj + 1;
+  }
+  double* bx = (double*)malloc(sizeof(double) * maxside);
+  double* by = (double*)malloc(sizeof(double) * maxside);
+  /* 1. node classes: inactive inside another zone's body, or where another
+        zone has a cell containing the node (its lowest such cell lying at
+        least overlap + 3 layers inside that zone's overset sides) and a
+        nearer wall (ties: the higher zone) */
+  const int cut = overlap + 3;
+  int nnode = 0;
+  for (int b = 0; b < c->nblock; b++) nnode += (c->blk[b].ni + 1) * (c->blk[b].nj + 1);
+  int8_t* inact = (int8_t*)calloc(nnode > 0 ? nnode : 1, 1);
+  for (int b = 0; b < c->nblock; b++) {
+    const blk_t* B = &c->blk[b];
+    for (int j = 0; j <= B->nj; j++)
+      for (int i = 0; i <= B->ni; i++) {
+        double px = node_x(c, b, i, j), py = node_y(c, b, i, j);
+        int off = inside_body(c, b, px, py, bx, by);
+        double da = wall_dist2(c, b, px, py, bx, by);
+        for (int z = 0; z < c->nblock && !off; z++) {
+          if (z == b) continue;
+          int m = containing_cell(c, z, px, py, NULL);
+          if (m < 0 || overset_depth(c, m) < cut) continue;
+          double dz = wall_dist2(c, z, px, py, bx, by);
+          if (dz < da || (dz == da && z > b)) off = 1;
+        }
+        inact[c->node0[b] + i + (B->ni + 1) * j] = (int8_t)off;
+      }
+  }
+  /* 2. cell classes: field (all nodes active), hole (none), boundary */
+  int8_t* cls = (int8_t*)malloc(ncell > 0 ? ncell : 1);
+  for (int n = 0; n < ncell; n++) {
+    int b = c->cblk[n], i = c->ci[n], j = c->cj[n], ni1 = c->blk[b].ni + 1, o = c->node0[b];
+    int k = inact[o + i + ni1 * j] + inact[o + i + 1 + ni1 * j] + inact[o + i + 1 + ni1 * (j + 1)] +
+            inact[o + i + ni1 * (j + 1)];
+    cls[n] = (k == 0) ? OR_FIELD : (k == 4) ? OR_HOLE : OR_RECEPTOR;
+  }
+  /* 3. receptors: boundary cells, one buffer layer of field cells beside a
+        boundary or hole cell, and `overlap` layers beside an overset side */
+  int8_t* ty = (int8_t*)malloc(ncell > 0 ? ncell : 1);
+  for (int n = 0; n < ncell; n++) {
+    ty[n] = cls[n];
+    if (cls[n] != OR_FIELD) continue;
+    for (int dir = 0; dir < 2; dir++)
+      for (int sd = -1; sd <= 1; sd += 2) {
+        int m = index_nb(c, n, dir, sd);
+        if (m >= 0 && cls[m] != OR_FIELD) ty[n] = OR_RECEPTOR;
+      }
+    const blk_t* B = &c->blk[c->cblk[n]];
+    int i = c->ci[n], j = c->cj[n];
+    if ((B->bc[0] == OR_NONE && i < overlap) || (B->bc[1] == OR_NONE && i >= B->ni - overlap) ||
+        (B->bc[2] == OR_NONE && j < overlap) || (B->bc[3] == OR_NONE && j >= B->nj - overlap))
+      ty[n] = OR_RECEPTOR;
+  }
+  /* 4. donors (Sec. 3.2): the field cell of another zone containing the
+        receptor centre (lowest zone, then lowest cell); weights */
+  int nrec = 0;
+  for (int n = 0; n < ncell; n++) nrec += (ty[n] == OR_RECEPTOR);
+  int* rec = (int*)malloc(sizeof(int) * (nrec > 0 ? nrec : 1));
+  int* ptr = (int*)malloc(sizeof(int) * (nrec + 1));
+  int* don = (int*)malloc(sizeof(int) * (5 * nrec > 0 ? 5 * nrec : 1));
+  double* w = (double*)malloc(sizeof(double) * (5 * nrec > 0 ? 5 * nrec : 1));
+  int r = 0, nd = 0, rc = 0;
+  ptr[0] = 0;
+  for (int n = 0; n < ncell && !rc; n++) {
+    if (ty[n] != OR_RECEPTOR) continue;
+    double px = c->cx[n], py = c->cy[n];
+    int d = -1;
+    for (int z = 0; z < c->nblock && d < 0; z++)
+      if (z != c->cblk[n]) d = containing_cell(c, z, px, py, ty);
+    if (d < 0) { rc = -5; break; }
+    rec[r] = n;
+    int done = 0;
+    if (wrule == 1) {
+      /* the quad of donor-grid cell centres around the receptor centre:
+         dual quads with the donor as a corner, in a fixed order */
+      for (int q = 0; q < 4 && !done; q++) {
+        int a = q % 2, bb = q / 2;
+        int lo_i = (a == 0) ? index_nb(c, d, 0, -1) : d;
+        int c00 = (lo_i < 0) ? -1 : ((bb == 0) ? index_nb(c, lo_i, 1, -1) : lo_i);
+        if (c00 < 0) continue;
+        int c10 = index_nb(c, c00, 0, +1);
+        int c01 = index_nb(c, c00, 1, +1);
+        int c11 = (c10 < 0) ? -1 : index_nb(c, c10, 1, +1);
+        int nq[4] = {c00, c10, c11, c01};
+        int ok = 1;
+        for (int k = 0; k < 4; k++) ok = ok && nq[k] >= 0 && ty[nq[k]] == OR_FIELD;
+        if (!ok) continue;
+        double qx[4], qy[4];
+        for (int k = 0; k < 4; k++) { qx[k] = c->cx[nq[k]]; qy[k] = c->cy[nq[k]]; }
+        if (!quad_contains(qx, qy, px, py)) continue;
+        double wq[4];
+        bilinear(c, nq, px, py, wq);
+        for (int k = 0; k < 4; k++) { don[nd + k] = nq[k]; w[nd + k] = wq[k]; }
+        nd += 4;
+        done = 1;
+      }
+    }
+    if (!done) {
+      /* inverse distance squared over the donor and its field neighbours */
+      int set[5], ns = 0;
+      set[ns++] = d;
+      for (int dir = 0; dir < 2; dir++)
+        for (int sd = -1; sd <= 1; sd += 2) {
+          int m = index_nb(c, d, dir, sd), dup = 0;
+          if (m < 0 || ty[m] != OR_FIELD) continue;
+          for (int k = 0; k < ns; k++) dup = dup || set[k] == m;
+          if (!dup) set[ns++] = m;
+        }
+      double d2[5];
+      int exact = -1;
+      for (int k = 0; k < ns; k++) {
+        double dx = c->cx[set[k]] - px, dy = c->cy[set[k]] - py;
+        d2[k] = dx * dx + dy * dy;
+        if (exact < 0 && d2[k] <= 1e-28 * c->vol[set[k]]) exact = k;
+      }
+      if (exact >= 0) {
+        don[nd] = set[exact]; w[nd] = 1.0; nd += 1;
+      } else {
+        double sum = 0.0;
+        for (int k = 0; k < ns; k++) sum += 1.0 / d2[k];
+        for (int k = 0; k < ns; k++) { don[nd + k] = set[k]; w[nd + k] = (1.0 / d2[k]) / sum; }
+        nd += ns;
+      }
+    }
+    r++;
+    ptr[r] = nd;
+  }
+  if (!rc) {
+    memcpy(c->type, ty, ncell);
+    or_set_overset(c, nrec, rec, ptr, don, w);
+    *nrec_out = nrec;
+  }
+  free(bx); free(by); free(inact); free(cls); free(ty); free(rec); free(ptr); free(don); free(w);
+  return rc;
 }

@@ -140,6 +140,9 @@ void or_step7(const or_case* c, const double* Wp, const double* h, const double*
    Returns 0, or -5 if a receptor has no donor. */
 int or_assemble(or_case* c, int wrule, int overlap, int* nrec_out);
 int or_get_overset(const or_case* c, int* rec, int* ptr, int* don, double* w);
+int or_overset_count(const or_case* c);
+/* current node coordinates, blocks concatenated, (ni+1)(nj+1) per block */
+void or_nodes(const or_case* c, double* x, double* y);
 
 #ifdef __cplusplus
 }

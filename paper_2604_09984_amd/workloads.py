@@ -345,22 +345,48 @@ def channel(ni: int = 6, nj: int = 70, nv: int = 8, kn: float = 0.1, lid: float 
                 (-vmax, vmax, -vmax, vmax), winf, [blk], np.tile(winf, (ni * nj, 1)), dt_over_dts=10.0)
 
 
-def moving_body_box(ni_bg: int = 24, nb: int = 16, njb: int = 6, nv: int = 12, kn: float = 0.1,
-                    seed: int = SEED) -> Case:
-    """Small overset case: a periodic background box and a circular body grid
-    (no wall: an overset 'patch' whose inner side is far field) translating and
-    rotating rigidly -- used for free-stream preservation on moving meshes."""
+def overset_patch(ni_bg: int = 32, npatch: int = 16, half: float = 0.5, nv: int = 12, kn: float = 0.1,
+                  wrule: int = 0) -> Case:
+    """Overset case without walls: a periodic background box [-1, 1]^2 and a
+    square patch grid [-half, half]^2 (all four sides overset) translating and
+    rotating rigidly over it (free-stream preservation on moving overset
+    meshes)."""
     bg = cartesian_block(ni_bg, ni_bg, -1.0, 1.0, -1.0, 1.0, (PERIODIC, PERIODIC, PERIODIC, PERIODIC))
-    radii = np.linspace(0.15, 0.45, njb + 1)
-    body = o_block(nb, njb, radii, bc=(PERIODIC, PERIODIC, FARFIELD, NONE))
+    patch = cartesian_block(npatch, npatch, -half, half, -half, half, (NONE, NONE, NONE, NONE))
     vmax = 4.0
     v = uniform_points(nv, -vmax, vmax)
     winf = cons(2, 1.0, [0.4, 0.1], 0.5)
-    ncell = bg.ncell + body.ncell
+    ncell = bg.ncell + patch.ncell
 
     def motion(t):
         return [(0.0, 0.0, 0.0, 0.0, 0.0, 0.0),
                 (0.05 * t, 0.02 * t * t, 0.3 * t, 0.05, 0.04 * t, 0.3)]
-    return Case("movingbox", 2, 2.0 / 3.0, 0.5, mu_ref_from_kn(kn, 0.5), 0.5, v, v.copy(),
+    return Case("patch", 2, 2.0 / 3.0, 0.5, mu_ref_from_kn(kn, 0.5), 0.5, v, v.copy(),
+                (-vmax, vmax, -vmax, vmax), winf, [bg, patch], np.tile(winf, (ncell, 1)),
+                dt=0.02, motion=motion, overset={"wrule": wrule, "overlap": 2})
+
+
+def overset_cylinder(ni_bg: int = 40, nb: int = 40, njb: int = 12, nv: int = 12, kn: float = 0.05,
+                     mach: float = 0.5, wrule: int = 0) -> Case:
+    """Moving body on an overset mesh: far-field box [-2, 2]^2 and an O-grid
+    (diameter 0.5, isothermal wall, outer side overset out to r = 1) that
+    plunges and pitches rigidly through a uniform stream."""
+    bg = cartesian_block(ni_bg, ni_bg, -2.0, 2.0, -2.0, 2.0, (FARFIELD, FARFIELD, FARFIELD, FARFIELD))
+    radii = geometric_radii(0.25, 1.0, njb, 1.08)
+    body = o_block(nb, njb, radii, bc=(PERIODIC, PERIODIC, WALL, NONE), rtw=(0.5, 0.5, 0.55, 0.5),
+                   body=True)
+    vmax = 5.0
+    v = uniform_points(nv, -vmax, vmax)
+    u = mach * math.sqrt(5.0 / 3.0 * 0.5)
+    winf = cons(2, 1.0, [u, 0.0], 0.5)
+    ncell = bg.ncell + body.ncell
+
+    def motion(t):
+        # plunge y = 0.1 sin(2 pi t / 2), pitch 0.2 sin(2 pi t / 2)
+        w = math.pi
+        return [(0.0, 0.0, 0.0, 0.0, 0.0, 0.0),
+                (0.0, 0.1 * math.sin(w * t), 0.2 * math.sin(w * t), 0.0, 0.1 * w * math.cos(w * t),
+                 0.2 * w * math.cos(w * t))]
+    return Case("ovcyl", 2, 2.0 / 3.0, 0.5, mu_ref_from_kn(kn, 0.5), 0.5, v, v.copy(),
                 (-vmax, vmax, -vmax, vmax), winf, [bg, body], np.tile(winf, (ncell, 1)),
-                dt=0.02, motion=motion, overset={"wrule": 0, "overlap": 2})
+                dt_over_dts=5.0, motion=motion, overset={"wrule": wrule, "overlap": 2})

@@ -1,0 +1,312 @@
+"""Pins of the oracle's overset assembly (Sec. 3.1) and interpolation weights
+(Sec. 3.2) on small grids, against a pure-Python brute force written
+separately from the rules (node classes from donor existence and wall
+distance, cell classes, buffer and fringe layers, lowest-zone/lowest-cell
+donors), plus properties the weights must have whatever the search:
+positive partition of unity, exact constants (inverse distance) and exact
+linear fields (bilinear)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2604_09984_amd import workloads as wl
+from oracle.oracle import Oracle
+
+HOLE, FIELD, RECEPTOR = 0, 1, 2
+
+
+def _blocks(case):
+    out, c0, n0 = [], 0, 0
+    for b in case.blocks:
+        out.append(dict(ni=b.ni, nj=b.nj, bc=list(b.bc), c0=c0, n0=n0))
+        c0 += b.ni * b.nj
+        n0 += (b.ni + 1) * (b.nj + 1)
+    return out
+
+
+def brute_force(case, xn, yn, cx, vol, wrule, overlap):
+    """Independent restatement of the assembly rules, all-pairs search."""
+    B = _blocks(case)
+    nz = len(B)
+
+    def node(z, i, j):
+        k = B[z]["n0"] + i + (B[z]["ni"] + 1) * j
+        return xn[k], yn[k]
+
+    def quad(z, i, j):
+        return [node(z, i, j), node(z, i + 1, j), node(z, i + 1, j + 1), node(z, i, j + 1)]
+
+    def inside(q, p):
+        s = []
+        for k in range(4):
+            a, b = q[k], q[(k + 1) % 4]
+            s.append((b[0] - a[0]) * (p[1] - a[1]) - (b[1] - a[1]) * (p[0] - a[0]))
+        return not (any(v > 0.0 for v in s) and any(v < 0.0 for v in s))
+
+    def side(z, s):
+        ni, nj = B[z]["ni"], B[z]["nj"]
+        if s < 2:
+            return [node(z, 0 if s == 0 else ni, m) for m in range(nj + 1)]
+        return [node(z, m, 0 if s == 2 else nj) for m in range(ni + 1)]
+
+    def d2seg(p, a, b):
+        ex, ey = b[0] - a[0], b[1] - a[1]
+        l2 = ex * ex + ey * ey
+        t = 0.0
+        if l2 > 0.0:
+            t = min(max(((p[0] - a[0]) * ex + (p[1] - a[1]) * ey) / l2, 0.0), 1.0)
+        dx, dy = p[0] - (a[0] + t * ex), p[1] - (a[1] + t * ey)
+        return dx * dx + dy * dy
+
+    def dwall(z, p):
+        d = math.inf
+        for s in range(4):
+            if B[z]["bc"][s] == wl.WALL:
+                pts = side(z, s)
+                for m in range(len(pts) - 1):
+                    d = min(d, d2seg(p, pts[m], pts[m + 1]))
+        return d
+
+    def in_body(z0, p):
+        for z in range(nz):
+            if z == z0:
+                continue
+            for s in range(4):
+                closed = B[z]["bc"][2 if s < 2 else 0] == wl.PERIODIC
+                if B[z]["bc"][s] != wl.WALL or not closed:
+                    continue
+                pts, odd = side(z, s), False
+                for m in range(len(pts) - 1):
+                    a, b = pts[m], pts[m + 1]
+                    if (a[1] > p[1]) != (b[1] > p[1]):
+                        if p[0] < a[0] + (p[1] - a[1]) * (b[0] - a[0]) / (b[1] - a[1]):
+                            odd = not odd
+                if odd:
+                    return True
+        return False
+
+    def cells(z):
+        for j in range(B[z]["nj"]):
+            for i in range(B[z]["ni"]):
+                yield B[z]["c0"] + i + B[z]["ni"] * j, i, j
+
+    def depth(z, i, j):
+        ni, nj, bc = B[z]["ni"], B[z]["nj"], B[z]["bc"]
+        d = [v for s, v in enumerate((i, ni - 1 - i, j, nj - 1 - j)) if bc[s] == wl.NONE]
+        return min(d) if d else 1 << 30
+
+    def first_cell(z, p, types=None):
+        for n, i, j in cells(z):
+            if (types is None or types[n] == FIELD) and inside(quad(z, i, j), p):
+                return n, i, j
+        return None
+
+    off = {}
+    for z in range(nz):
+        for j in range(B[z]["nj"] + 1):
+            for i in range(B[z]["ni"] + 1):
+                p = node(z, i, j)
+                o = in_body(z, p)
+                da = dwall(z, p)
+                for y in range(nz):
+                    if o or y == z:
+                        continue
+                    hit = first_cell(y, p)
+                    if hit is None or depth(y, hit[1], hit[2]) < overlap + 3:
+                        continue
+                    dy = dwall(y, p)
+                    o = dy < da or (dy == da and y > z)
+                off[z, i, j] = int(bool(o))
+    ncell = sum(b["ni"] * b["nj"] for b in B)
+    cls = np.zeros(ncell, np.int8)
+    zone = np.zeros(ncell, np.int64)
+    ij = {}
+    for z in range(nz):
+        for n, i, j in cells(z):
+            k = off[z, i, j] + off[z, i + 1, j] + off[z, i + 1, j + 1] + off[z, i, j + 1]
+            cls[n] = FIELD if k == 0 else (HOLE if k == 4 else RECEPTOR)
+            zone[n] = z
+            ij[n] = (i, j)
+
+    def nbr(n, di, dj):
+        z = zone[n]
+        i, j = ij[n]
+        i, j = i + di, j + dj
+        ni, nj = B[z]["ni"], B[z]["nj"]
+        if not 0 <= i < ni:
+            if B[z]["bc"][0] != wl.PERIODIC:
+                return None
+            i %= ni
+        if not 0 <= j < nj:
+            if B[z]["bc"][2] != wl.PERIODIC:
+                return None
+            j %= nj
+        return B[z]["c0"] + i + ni * j
+
+    ty = cls.copy()
+    for n in range(ncell):
+        if cls[n] != FIELD:
+            continue
+        if any(m is not None and cls[m] != FIELD for m in (nbr(n, -1, 0), nbr(n, 1, 0), nbr(n, 0, -1), nbr(n, 0, 1))):
+            ty[n] = RECEPTOR
+        z = zone[n]
+        i, j = ij[n]
+        bc, ni, nj = B[z]["bc"], B[z]["ni"], B[z]["nj"]
+        if (bc[0] == wl.NONE and i < overlap) or (bc[1] == wl.NONE and i >= ni - overlap) or \
+           (bc[2] == wl.NONE and j < overlap) or (bc[3] == wl.NONE and j >= nj - overlap):
+            ty[n] = RECEPTOR
+    rec, ptr, don, w = [], [0], [], []
+    for n in range(ncell):
+        if ty[n] != RECEPTOR:
+            continue
+        p = (cx[n, 0], cx[n, 1])
+        d = None
+        for z in range(nz):
+            if z != zone[n] and d is None:
+                hit = first_cell(z, p, ty)
+                d = None if hit is None else hit[0]
+        assert d is not None, f"orphan {n}"
+        rec.append(n)
+        done = False
+        if wrule == 1:
+            for a, bb in ((0, 0), (1, 0), (0, 1), (1, 1)):
+                lo = nbr(d, -1, 0) if a == 0 else d
+                c00 = None if lo is None else (nbr(lo, 0, -1) if bb == 0 else lo)
+                if c00 is None:
+                    continue
+                c10, c01 = nbr(c00, 1, 0), nbr(c00, 0, 1)
+                c11 = None if c10 is None else nbr(c10, 0, 1)
+                q = [c00, c10, c11, c01]
+                if any(m is None or ty[m] != FIELD for m in q):
+                    continue
+                if not inside([(cx[m, 0], cx[m, 1]) for m in q], p):
+                    continue
+                X = [cx[m] for m in q]
+                s = t = 0.5
+                for _ in range(3):
+                    P = (1 - s) * (1 - t) * X[0] + s * (1 - t) * X[1] + s * t * X[2] + (1 - s) * t * X[3]
+                    Js = (1 - t) * (X[1] - X[0]) + t * (X[2] - X[3])
+                    Jt = (1 - s) * (X[3] - X[0]) + s * (X[2] - X[1])
+                    ds, dt = np.linalg.solve(np.array([Js, Jt]).T, P - np.array(p))
+                    s, t = s - ds, t - dt
+                don += q
+                w += [(1 - s) * (1 - t), s * (1 - t), s * t, (1 - s) * t]
+                done = True
+                break
+        if not done:
+            S = [d]
+            for m in (nbr(d, -1, 0), nbr(d, 1, 0), nbr(d, 0, -1), nbr(d, 0, 1)):
+                if m is not None and ty[m] == FIELD and m not in S:
+                    S.append(m)
+            d2 = [float(np.sum((cx[m] - np.array(p)) ** 2)) for m in S]
+            ex = [k for k in range(len(S)) if d2[k] <= 1e-28 * vol[S[k]]]
+            if ex:
+                don.append(S[ex[0]]); w.append(1.0)
+            else:
+                inv = [1.0 / v for v in d2]
+                don += S
+                w += [v / sum(inv) for v in inv]
+        ptr.append(len(don))
+    return ty, np.array(rec), np.array(ptr), np.array(don), np.array(w)
+
+
+CASES = [
+    ("patch", lambda r: wl.overset_patch(ni_bg=16, npatch=14, half=0.55, nv=4, wrule=r)),
+    ("cyl", lambda r: wl.overset_cylinder(ni_bg=28, nb=20, njb=8, nv=4, wrule=r)),
+]
+
+
+@pytest.mark.parametrize("name,mk", CASES)
+@pytest.mark.parametrize("wrule", [0, 1])
+@pytest.mark.parametrize("t", [0.0, 0.41])
+def test_assembly_matches_brute_force(name, mk, wrule, t):
+    """P12: classes, receptors and donors bit-exact; weights to round-off."""
+    case = mk(wrule)
+    o = Oracle(case)
+    o.set_poses(case.poses(t))
+    rc, nrec = o.assemble(wrule, case.overset["overlap"])
+    assert rc == 0
+    xn, yn = o.nodes()
+    g = o.geometry()
+    ty, rec, ptr, don, w = brute_force(case, xn, yn, g["cx"], g["vol"], wrule, case.overset["overlap"])
+    assert np.array_equal(o.types(), ty)
+    orec, optr, odon, ow = o.overset()
+    assert nrec == len(rec)
+    assert np.array_equal(orec, rec) and np.array_equal(optr, ptr) and np.array_equal(odon, don)
+    assert np.allclose(ow, w, rtol=0, atol=1e-14)
+    # a meaningful cut: holes, receptors on both grids
+    assert (ty == HOLE).sum() > 0 and (ty == RECEPTOR).sum() > 0
+
+
+@pytest.mark.parametrize("name,mk", CASES)
+@pytest.mark.parametrize("wrule", [0, 1])
+def test_weights_properties(name, mk, wrule):
+    """Weights: positive (IDW) partition of unity; donors are field cells of
+    another block; IDW reproduces constants, bilinear reproduces linear fields."""
+    case = mk(wrule)
+    o = Oracle(case)
+    o.set_poses(case.poses(0.73))
+    assert o.assemble(wrule, 2)[0] == 0
+    ty = o.types()
+    rec, ptr, don, w = o.overset()
+    cx = o.geometry()["cx"]
+    blk = np.repeat(np.arange(len(case.blocks)), [b.ncell for b in case.blocks])
+    lin = lambda p: 0.3 + 1.7 * p[..., 0] - 0.9 * p[..., 1]
+    c0 = np.cumsum([0] + [b.ncell for b in case.blocks])
+
+    def is_quad(d):
+        # bilinear sets are the centroid quad (i, j), (i+1, j), (i+1, j+1), (i, j+1)
+        if len(d) != 4 or len(set(blk[d])) != 1:
+            return False
+        b = case.blocks[blk[d[0]]]
+        ij = [((x - c0[blk[x]]) % b.ni, (x - c0[blk[x]]) // b.ni) for x in d]
+        i0, j0 = ij[0]
+        want = [(i0, j0), ((i0 + 1) % b.ni, j0), ((i0 + 1) % b.ni, (j0 + 1) % b.nj), (i0, (j0 + 1) % b.nj)]
+        return ij == want
+    nbil = 0
+    for r in range(len(rec)):
+        sl = slice(ptr[r], ptr[r + 1])
+        assert np.all(ty[don[sl]] == FIELD)
+        assert np.all(blk[don[sl]] != blk[rec[r]])
+        assert abs(w[sl].sum() - 1.0) <= 1e-14
+        if wrule == 1 and is_quad(don[sl]):
+            nbil += 1
+            assert abs(np.dot(w[sl], lin(cx[don[sl]])) - lin(cx[rec[r]])) <= 1e-9
+        else:
+            assert np.all(w[sl] > 0.0)
+            # inverse distance: a constant is reproduced to round-off
+            assert abs(np.dot(w[sl], np.full(ptr[r + 1] - ptr[r], 2.5)) - 2.5) <= 1e-14
+    if wrule == 1:
+        assert nbil > 0.8 * len(rec)
+
+
+def test_hole_inside_body():
+    """Background cells entirely inside the cylinder (all nodes at r < 0.25)
+    are holes; background cells far from the body are field."""
+    case = wl.overset_cylinder(ni_bg=28, nb=20, njb=8, nv=4)
+    o = Oracle(case)
+    assert o.assemble(0, 2)[0] == 0
+    ty = o.types()
+    xn, yn = o.nodes()
+    bg = case.blocks[0]
+    for j in range(bg.nj):
+        for i in range(bg.ni):
+            ks = [i + (bg.ni + 1) * j, i + 1 + (bg.ni + 1) * j, i + (bg.ni + 1) * (j + 1), i + 1 + (bg.ni + 1) * (j + 1)]
+            r = np.hypot(xn[ks], yn[ks])
+            if r.max() < 0.25:
+                assert ty[i + bg.ni * j] == HOLE
+            if r.min() > 1.3:
+                assert ty[i + bg.ni * j] == FIELD
+
+
+def test_orphan_reported():
+    """A receptor with no donor is an error and installs nothing."""
+    case = wl.overset_patch(ni_bg=16, npatch=14, half=0.55, nv=4)
+    o = Oracle(case)
+    # move the patch out of the background box: its fringe has no donor
+    o.set_poses([(0.0,) * 6, (5.0, 0.0, 0.0, 0.0, 0.0, 0.0)])
+    before = o.types()
+    rc, n = o.assemble(0, 2)
+    assert rc == -5 and n == 0
+    assert np.array_equal(o.types(), before)
