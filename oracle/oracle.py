@@ -45,6 +45,8 @@ def lib():
         L.or_get_overset.restype = C.c_int
         L.or_overset_count.argtypes = [C.c_void_p]
         L.or_nodes.argtypes = [C.c_void_p, D, D]
+        L.or_refill_count.argtypes = [C.c_void_p]
+        L.or_refill_count.restype = C.c_int
         L.or_overset_count.restype = C.c_int
         L.or_maxwellian.argtypes = [C.c_void_p, D, D, D]
         L.or_moments.argtypes = [C.c_void_p, D, D, D, D]
@@ -163,6 +165,9 @@ class Oracle:
         lib().or_geometry(self.ptr, _d(cx), _d(vol), _d(g), _i(fl), _i(fr), _d(fn), _d(fs),
                           _d(fx), _d(fu))
         return dict(cx=cx, vol=vol, g=g, fl=fl, fr=fr, fn=fn, fs=fs, fx=fx, fu=fu)
+
+    def refill_count(self):
+        return int(lib().or_refill_count(self.ptr))
 
     def nodes(self):
         nn = sum((b.ni + 1) * (b.nj + 1) for b in self.case.blocks)

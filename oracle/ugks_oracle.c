@@ -64,6 +64,7 @@ struct or_case {
   int* cface;                /* [ncell][4] face ids (-1 none): i-low, i-high, j-low, j-high */
   int* csign;                /* [ncell][4] +1 if the face normal points out of the cell */
   int nrec; int *rec, *dptr, *don; double* dw;
+  int nref;                  /* refill entries appended after the receptors */
 };
 
 int or_ncell(const or_case* c) { return c->ncell; }
@@ -706,6 +707,7 @@ void or_set_overset(or_case* c, int nrec, const int* rec, const int* ptr, const 
                     const double* w) {
   free(c->rec); free(c->dptr); free(c->don); free(c->dw);
   c->nrec = nrec;
+  c->nref = 0;
   c->rec = (int*)malloc(sizeof(int) * (nrec > 0 ? nrec : 1));
   c->dptr = (int*)malloc(sizeof(int) * (nrec + 1));
   int nd = (nrec > 0) ? ptr[nrec] : 0;
@@ -717,6 +719,7 @@ void or_set_overset(or_case* c, int nrec, const int* rec, const int* ptr, const 
 }
 
 int or_overset_count(const or_case* c) { return c->nrec; }
+int or_refill_count(const or_case* c) { return c->nref; }
 
 int or_get_overset(const or_case* c, int* rec, int* ptr, int* don, double* w) {
   if (rec) memcpy(rec, c->rec, sizeof(int) * c->nrec);
@@ -1142,9 +1145,11 @@ void or_flux(const or_case* c, double dts, const double* h, const double* b,
 /* ------------------------------------------------------------------------ */
 /* overset interpolation (Sec. 3.2) -- weights supplied by the assembly      */
 /* ------------------------------------------------------------------------ */
-void or_interp(const or_case* c, double* h, double* b, double* W, double* q) {
+/* rows r0 .. r0+nrow-1 of the donor table; their donors are not rows of
+   the same call, so the rows are independent */
+static void interp_rows(const or_case* c, int r0, int nrow, double* h, double* b, double* W, double* q) {
 #pragma omp parallel for schedule(static)
-  for (int r = 0; r < c->nrec; r++) {
+  for (int r = r0; r < r0 + nrow; r++) {
     int n = c->rec[r];
     for (int k = 0; k < c->nv; k++) {
       double sh = 0.0, sb = 0.0;
@@ -1169,6 +1174,10 @@ void or_interp(const or_case* c, double* h, double* b, double* W, double* q) {
   }
 }
 
+void or_interp(const or_case* c, double* h, double* b, double* W, double* q) {
+  interp_rows(c, 0, c->nrec, h, b, W, q);
+}
+
 /* ------------------------------------------------------------------------ */
 /* dual time stepping (Sec. 2.2)                                             */
 /* ------------------------------------------------------------------------ */
@@ -1183,12 +1192,16 @@ static void fplus(const or_case* c, double rho, const double* u, double lam, con
 }
 
 /* Steps 1-2: S = f^n/dt + r^n/2, r^n = D^n + (f+^n - f^n)/tau^n (Eq. residual_macro_n) */
-void or_begin_step(const or_case* c, double dt, double dts, double* h, double* b,
+void or_begin_step(or_case* c, double dt, double dts, double* h, double* b,
                    double* W, double* q, double* Sh, double* Sb, double* Fn) {
   size_t N = (size_t)c->ncell * c->nv;
   double* Dh = (double*)malloc(sizeof(double) * N);
   double* Db = (double*)malloc(sizeof(double) * N);
-  or_interp(c, h, b, W, q);
+  /* once after an assembly the cells uncovered from holes (their donors
+     are cells that were live), then the receptors (which may use them) */
+  interp_rows(c, c->nrec, c->nref, h, b, W, q);
+  c->nref = 0;
+  interp_rows(c, 0, c->nrec, h, b, W, q);
   or_flux(c, dts, h, b, W, q, Dh, Db, Fn, NULL);
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < c->ncell; n++) {
@@ -1649,6 +1662,65 @@ static void bilinear(const or_case* c, const int* n, double px, double py, doubl
   w[0] = (1.0 - s) * (1.0 - t); w[1] = s * (1.0 - t); w[2] = s * t; w[3] = (1.0 - s) * t;
 }
 
+/* donors and weights of cell n (Sec. 3.2): the field cell of another zone
+   containing its centroid (lowest zone, then lowest cell); bilinear over the
+   quad of donor-grid centroids around it (wrule 1, when such a quad of field
+   cells contains it), else inverse distance squared over the donor and its
+   field index neighbours.  Returns the donor count, or -1 if none. */
+static int donors_of(const or_case* c, const int8_t* ty, int n, int wrule, int* don, double* w) {
+  double px = c->cx[n], py = c->cy[n];
+  int d = -1;
+  for (int z = 0; z < c->nblock && d < 0; z++)
+    if (z != c->cblk[n]) d = containing_cell(c, z, px, py, ty);
+  if (d < 0) return -1;
+  if (wrule == 1) {
+    /* dual quads with the donor as a corner, in a fixed order */
+    for (int q = 0; q < 4; q++) {
+      int a = q % 2, bb = q / 2;
+      int lo_i = (a == 0) ? index_nb(c, d, 0, -1) : d;
+      int c00 = (lo_i < 0) ? -1 : ((bb == 0) ? index_nb(c, lo_i, 1, -1) : lo_i);
+      if (c00 < 0) continue;
+      int c10 = index_nb(c, c00, 0, +1);
+      int c01 = index_nb(c, c00, 1, +1);
+      int c11 = (c10 < 0) ? -1 : index_nb(c, c10, 1, +1);
+      int nq[4] = {c00, c10, c11, c01};
+      int ok = 1;
+      for (int k = 0; k < 4; k++) ok = ok && nq[k] >= 0 && ty[nq[k]] == OR_FIELD;
+      if (!ok) continue;
+      double qx[4], qy[4];
+      for (int k = 0; k < 4; k++) { qx[k] = c->cx[nq[k]]; qy[k] = c->cy[nq[k]]; }
+      if (!quad_contains(qx, qy, px, py)) continue;
+      bilinear(c, nq, px, py, w);
+      for (int k = 0; k < 4; k++) don[k] = nq[k];
+      return 4;
+    }
+  }
+  int set[5], ns = 0;
+  set[ns++] = d;
+  for (int dir = 0; dir < 2; dir++)
+    for (int sd = -1; sd <= 1; sd += 2) {
+      int m = index_nb(c, d, dir, sd), dup = 0;
+      if (m < 0 || ty[m] != OR_FIELD) continue;
+      for (int k = 0; k < ns; k++) dup = dup || set[k] == m;
+      if (!dup) set[ns++] = m;
+    }
+  double d2[5];
+  int exact = -1;
+  for (int k = 0; k < ns; k++) {
+    double dx = c->cx[set[k]] - px, dy = c->cy[set[k]] - py;
+    d2[k] = dx * dx + dy * dy;
+    if (exact < 0 && d2[k] <= 1e-28 * c->vol[set[k]]) exact = k;
+  }
+  if (exact >= 0) {
+    don[0] = set[exact]; w[0] = 1.0;
+    return 1;
+  }
+  double sum = 0.0;
+  for (int k = 0; k < ns; k++) sum += 1.0 / d2[k];
+  for (int k = 0; k < ns; k++) { don[k] = set[k]; w[k] = (1.0 / d2[k]) / sum; }
+  return ns;
+}
+
 int or_assemble(or_case* c, int wrule, int overlap, int* nrec_out) {
   *nrec_out = 0;
   if (c->dim != 2) return -6;
@@ -1710,85 +1782,45 @@ int or_assemble(or_case* c, int wrule, int overlap, int* nrec_out) {
         (B->bc[2] == OR_NONE && j < overlap) || (B->bc[3] == OR_NONE && j >= B->nj - overlap))
       ty[n] = OR_RECEPTOR;
   }
-  /* 4. donors (Sec. 3.2): the field cell of another zone containing the
-        receptor centre (lowest zone, then lowest cell); weights */
-  int nrec = 0;
-  for (int n = 0; n < ncell; n++) nrec += (ty[n] == OR_RECEPTOR);
-  int* rec = (int*)malloc(sizeof(int) * (nrec > 0 ? nrec : 1));
-  int* ptr = (int*)malloc(sizeof(int) * (nrec + 1));
-  int* don = (int*)malloc(sizeof(int) * (5 * nrec > 0 ? 5 * nrec : 1));
-  double* w = (double*)malloc(sizeof(double) * (5 * nrec > 0 ? 5 * nrec : 1));
+  /* 4. donors (Sec. 3.2) of the receptors, then of the cells that were
+        holes and are field now (filled once, at the start of the step) */
+  int nrec = 0, nref = 0;
+  for (int n = 0; n < ncell; n++) {
+    nrec += (ty[n] == OR_RECEPTOR);
+    nref += (c->type[n] == OR_HOLE && ty[n] == OR_FIELD);
+  }
+  int nrow = nrec + nref;
+  int* rec = (int*)malloc(sizeof(int) * (nrow > 0 ? nrow : 1));
+  int* ptr = (int*)malloc(sizeof(int) * (nrow + 1));
+  int* don = (int*)malloc(sizeof(int) * (5 * nrow > 0 ? 5 * nrow : 1));
+  double* w = (double*)malloc(sizeof(double) * (5 * nrow > 0 ? 5 * nrow : 1));
+  /* refill cells take donors among the cells that were not holes, so that
+     they can be filled before the receptors (which may use them) */
+  int8_t* tyr = (int8_t*)malloc(ncell > 0 ? ncell : 1);
+  for (int n = 0; n < ncell; n++) tyr[n] = (c->type[n] == OR_HOLE && ty[n] == OR_FIELD) ? OR_HOLE : ty[n];
   int r = 0, nd = 0, rc = 0;
   ptr[0] = 0;
-  for (int n = 0; n < ncell && !rc; n++) {
-    if (ty[n] != OR_RECEPTOR) continue;
-    double px = c->cx[n], py = c->cy[n];
-    int d = -1;
-    for (int z = 0; z < c->nblock && d < 0; z++)
-      if (z != c->cblk[n]) d = containing_cell(c, z, px, py, ty);
-    if (d < 0) { rc = -5; break; }
-    rec[r] = n;
-    int done = 0;
-    if (wrule == 1) {
-      /* the quad of donor-grid cell centres around the receptor centre:
-         dual quads with the donor as a corner, in a fixed order */
-      for (int q = 0; q < 4 && !done; q++) {
-        int a = q % 2, bb = q / 2;
-        int lo_i = (a == 0) ? index_nb(c, d, 0, -1) : d;
-        int c00 = (lo_i < 0) ? -1 : ((bb == 0) ? index_nb(c, lo_i, 1, -1) : lo_i);
-        if (c00 < 0) continue;
-        int c10 = index_nb(c, c00, 0, +1);
-        int c01 = index_nb(c, c00, 1, +1);
-        int c11 = (c10 < 0) ? -1 : index_nb(c, c10, 1, +1);
-        int nq[4] = {c00, c10, c11, c01};
-        int ok = 1;
-        for (int k = 0; k < 4; k++) ok = ok && nq[k] >= 0 && ty[nq[k]] == OR_FIELD;
-        if (!ok) continue;
-        double qx[4], qy[4];
-        for (int k = 0; k < 4; k++) { qx[k] = c->cx[nq[k]]; qy[k] = c->cy[nq[k]]; }
-        if (!quad_contains(qx, qy, px, py)) continue;
-        double wq[4];
-        bilinear(c, nq, px, py, wq);
-        for (int k = 0; k < 4; k++) { don[nd + k] = nq[k]; w[nd + k] = wq[k]; }
-        nd += 4;
-        done = 1;
-      }
+  for (int pass = 0; pass < 2 && !rc; pass++)
+    for (int n = 0; n < ncell && !rc; n++) {
+      int want = (pass == 0) ? ty[n] == OR_RECEPTOR : (c->type[n] == OR_HOLE && ty[n] == OR_FIELD);
+      if (!want) continue;
+      int k = donors_of(c, (pass == 0) ? ty : tyr, n, wrule, don + nd, w + nd);
+      if (k < 0) { rc = -5; break; }
+      rec[r] = n;
+      nd += k;
+      r++;
+      ptr[r] = nd;
     }
-    if (!done) {
-      /* inverse distance squared over the donor and its field neighbours */
-      int set[5], ns = 0;
-      set[ns++] = d;
-      for (int dir = 0; dir < 2; dir++)
-        for (int sd = -1; sd <= 1; sd += 2) {
-          int m = index_nb(c, d, dir, sd), dup = 0;
-          if (m < 0 || ty[m] != OR_FIELD) continue;
-          for (int k = 0; k < ns; k++) dup = dup || set[k] == m;
-          if (!dup) set[ns++] = m;
-        }
-      double d2[5];
-      int exact = -1;
-      for (int k = 0; k < ns; k++) {
-        double dx = c->cx[set[k]] - px, dy = c->cy[set[k]] - py;
-        d2[k] = dx * dx + dy * dy;
-        if (exact < 0 && d2[k] <= 1e-28 * c->vol[set[k]]) exact = k;
-      }
-      if (exact >= 0) {
-        don[nd] = set[exact]; w[nd] = 1.0; nd += 1;
-      } else {
-        double sum = 0.0;
-        for (int k = 0; k < ns; k++) sum += 1.0 / d2[k];
-        for (int k = 0; k < ns; k++) { don[nd + k] = set[k]; w[nd + k] = (1.0 / d2[k]) / sum; }
-        nd += ns;
-      }
-    }
-    r++;
-    ptr[r] = nd;
-  }
   if (!rc) {
     memcpy(c->type, ty, ncell);
     or_set_overset(c, nrec, rec, ptr, don, w);
+    /* the refill rows follow the receptors in the same table */
+    free(c->rec); free(c->dptr); free(c->don); free(c->dw);
+    c->rec = rec; c->dptr = ptr; c->don = don; c->dw = w;
+    rec = NULL; ptr = NULL; don = NULL; w = NULL;
+    c->nref = nref;
     *nrec_out = nrec;
   }
-  free(bx); free(by); free(inact); free(cls); free(ty); free(rec); free(ptr); free(don); free(w);
+  free(bx); free(by); free(inact); free(cls); free(ty); free(tyr); free(rec); free(ptr); free(don); free(w);
   return rc;
 }

@@ -117,7 +117,7 @@ void or_flux(const or_case* c, double dts, const double* h, const double* b,
 void or_interp(const or_case* c, double* h, double* b, double* W, double* q);
 
 /* Steps 1-2: source S = f^n/dt + r^n/2 and the level-n face flux Fn */
-void or_begin_step(const or_case* c, double dt, double dts, double* h, double* b,
+void or_begin_step(or_case* c, double dt, double dts, double* h, double* b,
                    double* W, double* q, double* Sh, double* Sb, double* Fn);
 /* Steps 3-7, one inner iteration; resid[nw] = L2 norm of R over field cells */
 void or_pseudo_step(const or_case* c, double dt, double dts, const double* dtp,
@@ -141,6 +141,8 @@ void or_step7(const or_case* c, const double* Wp, const double* h, const double*
 int or_assemble(or_case* c, int wrule, int overlap, int* nrec_out);
 int or_get_overset(const or_case* c, int* rec, int* ptr, int* don, double* w);
 int or_overset_count(const or_case* c);
+/* rows after the receptors: cells uncovered from holes, filled by the next or_begin_step */
+int or_refill_count(const or_case* c);
 /* current node coordinates, blocks concatenated, (ni+1)(nj+1) per block */
 void or_nodes(const or_case* c, double* x, double* y);
 

@@ -310,3 +310,52 @@ def test_orphan_reported():
     rc, n = o.assemble(0, 2)
     assert rc == -5 and n == 0
     assert np.array_equal(o.types(), before)
+
+
+def test_free_stream_on_moving_overset():
+    """P4: a resting uniform Maxwellian stays uniform to round-off while the
+    patch grid translates and rotates over the background, with the mesh
+    re-assembled every physical step (geometric conservation of the moving
+    faces, partition of unity of the interpolation)."""
+    for wrule in (0, 1):
+        case = wl.overset_patch(ni_bg=16, npatch=14, half=0.55, nv=8, wrule=wrule)
+        case.winf = wl.cons(2, 1.0, [0.0, 0.0], 0.5)
+        case.w_init = np.tile(case.winf, (case.ncell, 1))
+        o = Oracle(case)
+        h, b, W, q = o.init_state()
+        W0, h0 = W.copy(), h.copy()
+        t = 0.0
+        for _ in range(3):
+            t += case.dt
+            o.set_poses(case.poses(t))
+            assert o.assemble(wrule, 2)[0] == 0
+            o.physical_step(t, h, b, W, q, n_inner=3)
+        live = o.types() != HOLE
+        assert np.abs(W[live] - W0[live]).max() <= 1e-13
+        assert np.abs(h[live] - h0[live]).max() <= 1e-13 * h0.max()
+
+
+def test_uncovered_cells_refilled():
+    """A26: cells that were holes and are field after a jump of the patch are
+    filled once by the donor rule at the start of the next step (a constant
+    state is restored exactly where they held stale values)."""
+    case = wl.overset_patch(ni_bg=16, npatch=14, half=0.55, nv=4)
+    o = Oracle(case)
+    o.set_poses([(0.0,) * 6] * 2)
+    assert o.assemble(0, 2)[0] == 0
+    before = o.types()
+    o.set_poses([(0.0,) * 6, (0.18, 0.3, 0.09, 0.0, 0.0, 0.0)])
+    assert o.assemble(0, 2)[0] == 0
+    after = o.types()
+    fill = (before == HOLE) & (after == FIELD)
+    assert o.refill_count() == fill.sum() > 0
+    W = np.tile(case.winf, (case.ncell, 1))
+    h, b = o.maxwellian(W)
+    q = np.zeros((case.ncell, 2))
+    h[fill] = 0.0; b[fill] = 0.0; W[fill] = 0.0  # stale
+    h0 = h[~fill][0].copy()
+    dts, _ = o.timesteps()
+    o.begin_step(case.dt, dts, h, b, W, q)
+    assert np.allclose(h[fill], h0, rtol=1e-14, atol=0)
+    assert np.allclose(W[fill], case.winf, rtol=1e-14, atol=0)
+    assert o.refill_count() == 0
