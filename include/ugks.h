@@ -141,15 +141,30 @@ int ugks_set_overset(ugks_ctx* ctx, int32_t nrec, const int32_t* rec, const int3
                      const int32_t* don, const double* w);
 
 /*
- * Overset assembly at the current geometry (Sec. 3.1, host): node
- * classification, cell classification with one buffer layer, fringe layers
- * beside overset boundaries, donor search and weights (wrule 0: inverse
- * distance squared over the donor and its field neighbours; 1: bilinear in
- * the donor grid).  Installs the cell kinds and the donor table.
- * *nrec receives the receptor count.  UGKS_E_ORPHAN if a receptor has no
- * donor (nothing is installed then).
+ * Overset assembly at the current geometry (Sec. 3.1, host; 2D): each block
+ * is a grid zone.  A node is inactive inside another zone's body (closed
+ * wall outline) or where another zone has a cell containing it, at least
+ * overlap+3 cell layers inside that zone's overset (UGKS_BC_NONE) sides,
+ * and a nearer wall (ties: the higher zone).  Cells: field (all nodes
+ * active), hole (none active), else boundary; receptors = boundary cells,
+ * one buffer layer of field cells beside boundary or hole cells, and
+ * `overlap` layers beside overset sides.  Donor (Sec. 3.2): the field cell
+ * of another zone containing the receptor centroid (lowest zone, then
+ * lowest cell).  Weights, wrule 0: inverse distance squared over the donor
+ * and its field index neighbours; wrule 1: bilinear over the quad of
+ * donor-grid centroids around the receptor (inverse distance where no such
+ * quad of field cells contains it).  Installs the cell kinds and the donor
+ * table; *nrec receives the receptor count.  UGKS_E_ORPHAN if a receptor has
+ * no donor, UGKS_E_ARG for wrule not 0/1 or overlap < 0, UGKS_E_UNSUPPORTED
+ * in 1D; nothing is installed on error.  Synchronous.
  */
 int overset_assemble(ugks_ctx* ctx, int32_t wrule, int32_t overlap, int32_t* nrec);
+
+/* The installed donor table (host copies): *nrec receptors, *ndon donor
+   entries; rec[nrec], ptr[nrec+1], don[ndon], w[ndon] are filled when not
+   NULL (call once with NULL arrays to read the sizes). */
+int ugks_get_overset(const ugks_ctx* ctx, int32_t* nrec, int32_t* ndon, int32_t* rec, int32_t* ptr,
+                     int32_t* don, double* w);
 
 /* Discrete reduced Maxwellian h = H(W), b = B(W) at every cell
    (initialisation). */
@@ -189,7 +204,9 @@ int overset_interp(ugks_ctx* ctx, void* h, void* b, double* W, double* q, void* 
  * r^n of Eq. residual_macro_n (Sh, Sb [ncell][nv]) and the level-n face
  * flux Fn [nface][dim+2].  q [ncell][dim] is the heat flux of f^n about
  * the velocity of W^n (as ugks_heatflux returns); receptor rows of h, b, W, q
- * are refreshed by interpolation.
+ * are refreshed by interpolation, and so, once after an overset_assemble,
+ * are the cells that were holes and are field cells now (their data is
+ * stale: they are filled by the same donor rule).
  */
 int ugks_begin_step(ugks_ctx* ctx, double dt, void* h, void* b, double* W, double* q,
                     void* Sh, void* Sb, double* Fn, void* stream);

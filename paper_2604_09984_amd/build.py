@@ -17,9 +17,14 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-result"]
 
 
+# host files whose floating point decides integer results (geometry and
+# overset assembly) are compiled without contraction
+EXTRA = {"ugks_api.cpp": ["-ffp-contract=off"], "ugks_overset.cpp": ["-ffp-contract=off"]}
+
+
 def _compile(src):
     obj = os.path.join(OBJ, src + ".o")
-    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:

@@ -60,7 +60,7 @@ struct ugks_ctx {
   // host geometry
   std::vector<double> xn, yn;  // current nodes, per block
   std::vector<size_t> node0;
-  std::vector<double> vol, G, cdx, dtp, fgeo, mgeo;
+  std::vector<double> vol, G, cdx, dtp, fgeo, mgeo, ccx, ccy;  // ccx, ccy: cell centroids
   std::vector<int> nb, cf, fcell;
   std::vector<int8_t> type, fact;
   std::vector<int> cblk, ci, cj;
@@ -76,7 +76,8 @@ struct ugks_ctx {
        *s_dW = nullptr, *s_Wp = nullptr, *s_rpart = nullptr, *s_crec = nullptr, *s_mrec = nullptr,
        *s_Dh = nullptr, *s_Db = nullptr, *s_F = nullptr, *s_part = nullptr;
   // overset
-  int nrec = 0;
+  int nrec = 0;  // receptor rows of the donor table
+  int nref = 0;  // rows after them: cells uncovered from holes, interpolated once
   void *d_rec = nullptr, *d_ptr = nullptr, *d_don = nullptr, *d_w = nullptr;
   std::vector<int> h_rec, h_ptr, h_don;
   std::vector<double> h_w;
@@ -253,6 +254,7 @@ void compute_geometry(ugks_ctx* c) {
       double xa = X(b, i, 0), xb = X(b, i + 1, 0);
       c->vol[n] = xb - xa;
       double xc = 0.5 * (xa + xb);
+      c->ccx[n] = xc; c->ccy[n] = 0.0;
       G[0] = 1.0 / (xb - xa); G[1] = G[2] = G[3] = 0.0;
       for (int q = 0; q < 8; ++q) D[q] = 0.0;
       D[0] = xa - xc;
@@ -270,6 +272,7 @@ void compute_geometry(ugks_ctx* c) {
     A *= 0.5;
     double xc = sx / (6.0 * A), yc = sy / (6.0 * A);
     c->vol[n] = A;
+    c->ccx[n] = xc; c->ccy[n] = yc;
     double xxi = 0.5 * (px[1] + px[2]) - 0.5 * (px[0] + px[3]);
     double yxi = 0.5 * (py[1] + py[2]) - 0.5 * (py[0] + py[3]);
     double xet = 0.5 * (px[3] + px[2]) - 0.5 * (px[0] + px[1]);
@@ -502,7 +505,7 @@ int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
         c->cblk[n] = b; c->ci[n] = i; c->cj[n] = j;
       }
   c->type.assign(ncell, UGKS_FIELD);
-  c->vol.resize(ncell); c->G.resize(4 * (size_t)ncell); c->cdx.resize(8 * (size_t)ncell); c->dtp.resize(ncell);
+  c->vol.resize(ncell); c->ccx.resize(ncell); c->ccy.resize(ncell); c->G.resize(4 * (size_t)ncell); c->cdx.resize(8 * (size_t)ncell); c->dtp.resize(ncell);
   build_faces(c);
   build_tables(c);
   compute_geometry(c);
@@ -629,6 +632,25 @@ int ugks_get_types(const ugks_ctx* c, int8_t* types) {
   return UGKS_OK;
 }
 
+// donor table of nrow rows (the first nrec are receptors) to host and device
+static int install_overset(ugks_ctx* c, int nrow, int nrec, const int32_t* rec, const int32_t* ptr,
+                           const int32_t* don, const double* w) {
+  c->nrec = nrec;
+  c->nref = nrow - nrec;
+  c->h_rec.assign(rec, rec + nrow);
+  c->h_ptr.assign(ptr, ptr + nrow + 1);
+  const int nd = nrow > 0 ? ptr[nrow] : 0;
+  c->h_don.assign(don, don + nd);
+  c->h_w.assign(w, w + nd);
+  for (void** p : {&c->d_rec, &c->d_ptr, &c->d_don, &c->d_w})
+    if (*p) { (void)hipFree(*p); *p = nullptr; }
+  int rc = upload(c->d_rec, c->h_rec);
+  if (!rc) rc = upload(c->d_ptr, c->h_ptr);
+  if (!rc) rc = upload(c->d_don, c->h_don);
+  if (!rc) rc = upload(c->d_w, c->h_w);
+  return rc;
+}
+
 int ugks_set_overset(ugks_ctx* c, int32_t nrec, const int32_t* rec, const int32_t* ptr, const int32_t* don,
                      const double* w) {
   if (!c || nrec < 0) return fail(UGKS_E_ARG, "bad argument");
@@ -644,19 +666,23 @@ int ugks_set_overset(ugks_ctx* c, int32_t nrec, const int32_t* rec, const int32_
       if (c->type[don[p]] != UGKS_FIELD) return fail(UGKS_E_ARG, "donor is not a field cell");
     }
   }
-  c->nrec = nrec;
-  c->h_rec.assign(rec, rec + nrec);
-  c->h_ptr.assign(ptr, ptr + nrec + 1);
-  int nd = nrec > 0 ? ptr[nrec] : 0;
-  c->h_don.assign(don, don + nd);
-  c->h_w.assign(w, w + nd);
-  for (void** p : {&c->d_rec, &c->d_ptr, &c->d_don, &c->d_w})
-    if (*p) { (void)hipFree(*p); *p = nullptr; }
-  int rc = upload(c->d_rec, c->h_rec);
-  if (!rc) rc = upload(c->d_ptr, c->h_ptr);
-  if (!rc) rc = upload(c->d_don, c->h_don);
-  if (!rc) rc = upload(c->d_w, c->h_w);
-  return rc;
+  return install_overset(c, nrec, nrec, rec, ptr, don, w);
+}
+
+int ugks_get_overset(const ugks_ctx* c, int32_t* nrec, int32_t* ndon, int32_t* rec, int32_t* ptr, int32_t* don,
+                     double* w) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  const int nd = c->nrec > 0 ? c->h_ptr[c->nrec] : 0;
+  if (nrec) *nrec = c->nrec;
+  if (ndon) *ndon = nd;
+  if (rec && c->nrec) std::memcpy(rec, c->h_rec.data(), sizeof(int32_t) * c->nrec);
+  if (ptr) {
+    if (c->nrec) std::memcpy(ptr, c->h_ptr.data(), sizeof(int32_t) * (c->nrec + 1));
+    else ptr[0] = 0;
+  }
+  if (don && nd) std::memcpy(don, c->h_don.data(), sizeof(int32_t) * nd);
+  if (w && nd) std::memcpy(w, c->h_w.data(), sizeof(double) * nd);
+  return UGKS_OK;
 }
 
 int overset_assemble(ugks_ctx* c, int32_t wrule, int32_t overlap, int32_t* nrec) {
@@ -671,6 +697,8 @@ int overset_assemble(ugks_ctx* c, int32_t wrule, int32_t overlap, int32_t* nrec)
     for (int s = 0; s < 4; ++s) in.bc.push_back(B.bc[s]);
   }
   in.xn = &c->xn; in.yn = &c->yn; in.node0 = &c->node0;
+  in.cx = &c->ccx; in.cy = &c->ccy; in.vol = &c->vol;
+  in.old_type = &c->type;
   OversetOutput res;
   std::string msg;
   int rc = overset_build(in, wrule, overlap, res, msg);
@@ -682,8 +710,9 @@ int overset_assemble(ugks_ctx* c, int32_t wrule, int32_t overlap, int32_t* nrec)
   if (!rc) rc = upload_geometry(c);
   if (!rc) fill_dev(c);
   if (rc) return rc;
-  rc = ugks_set_overset(c, (int)res.rec.size(), res.rec.data(), res.ptr.data(), res.don.data(), res.w.data());
-  if (!rc && nrec) *nrec = (int)res.rec.size();
+  rc = install_overset(c, (int)res.rec.size(), res.nrec, res.rec.data(), res.ptr.data(), res.don.data(),
+                       res.w.data());
+  if (!rc && nrec) *nrec = res.nrec;
   return rc;
 }
 
@@ -743,6 +772,13 @@ int ugks_begin_step(ugks_ctx* c, double dt, void* h, void* b, double* W, double*
   if (int rc = check_dev(c, {h, b, W, q, Sh, Sb, Fn})) return rc;
   if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
   hipStream_t st = (hipStream_t)stream;
+  // once after an assembly the cells uncovered from holes (rows after the
+  // receptors; their donors were live cells), then the receptors, which may
+  // use them as donors
+  if (c->nref > 0)
+    launch_interp(c->dev, c->prec, c->nref, (const int*)c->d_rec + c->nrec, (const int*)c->d_ptr + c->nrec,
+                  (const int*)c->d_don, (const double*)c->d_w, h, b, W, q, st);
+  c->nref = 0;
   launch_interp(c->dev, c->prec, c->nrec, (const int*)c->d_rec, (const int*)c->d_ptr, (const int*)c->d_don,
                 (const double*)c->d_w, h, b, W, q, st);
   HIPCHK(hipMemsetAsync(Fn, 0, sizeof(double) * c->nw * (size_t)c->nface, st));

@@ -604,9 +604,14 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   const double wk = kin ? g.wk[kk] : 0.0;
   const C finh = (C)((const T*)g.finf_h)[kk];
   const C finb = (C)((const T*)g.finf_b)[kk];
+  // wrapping without integer division (offsets are a few cells; the loops
+  // run more than once only for blocks narrower than the stencil)
   auto wrap_row = [&](int j) -> int {
     if (j >= 0 && j < nj) return j;
-    return per_j ? ((j % nj) + nj) % nj : -1;
+    if (!per_j) return -1;
+    while (j < 0) j += nj;
+    while (j >= nj) j -= nj;
+    return j;
   };
   // this wavefront's row (periodic wrap for the halo rows) and, for the two
   // halo wavefronts, the row beyond it
@@ -616,7 +621,10 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   auto cell = [&](int x, int j) -> int { return c0 + x + ni * j; };
   auto col = [&](int x) -> int {  // column in the block, or -1
     if (x >= 0 && x < ni) return x;
-    return per_i ? ((x % ni) + ni) % ni : -1;
+    if (!per_i) return -1;
+    while (x < 0) x += ni;
+    while (x >= ni) x -= ni;
+    return x;
   };
   auto raw = [&](int row, int x, C& vh, C& vb) {
     const int xw = col(x);
@@ -625,7 +633,7 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     vh = (C)h[o];
     vb = (C)b[o];
   };
-  auto slot = [](int x) -> int { return (x + 6) % 3; };
+  auto slot = [](int x) -> int { return (x + 6) % 3; };  // x >= -6, constant divisor
   // raw values of this row: window (x, x+1, x+2) and the next column in
   // flight; the outer row of a halo wavefront at x+1 and x+2
   C a0h, a0b, a1h, a1b, a2h, a2b, p_h, p_b, oc_h, oc_b, on_h, on_b;
@@ -1078,7 +1086,10 @@ __global__ __launch_bounds__(256) void k_step7(Dev g, int mode, const T* __restr
   double* M = mrec + (size_t)c * NMREC;
   M[M_SX] = sx; M[M_SY] = sy; M[M_M0] = m0; M[M_M1X] = m1x; M[M_M1Y] = m1y; M[M_M2] = m2;
   M[M_PXX] = pxx; M[M_PXY] = pxy; M[M_PYY] = pyy; M[M_M3X] = m3x; M[M_M3Y] = m3y;
-  if (mode == 2) {
+  // mode 2, and the receptors in mode 1 (their W is the interpolated one,
+  // unchanged by the step): heat flux of f about the velocity of W, so that
+  // a receptor that turns into a field cell starts from q^n of its f^n
+  if (mode == 2 || (mode == 1 && !step)) {
     q[(size_t)c * g.dim] = 0.5 * m3x;
     if (g.dim == 2) q[(size_t)c * g.dim + 1] = 0.5 * m3y;
   }

@@ -52,6 +52,8 @@ def lib():
         L.ugks_get_types.argtypes = [vp, C.POINTER(C.c_int8)]
         L.ugks_set_overset.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(d)]
         L.overset_assemble.argtypes = [vp, i32, i32, C.POINTER(i32)]
+        L.ugks_get_overset.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                       C.POINTER(i32), C.POINTER(d)]
         L.ugks_maxwellian.argtypes = [vp, vp, vp, vp, vp]
         L.ugks_moments.argtypes = [vp, vp, vp, vp, vp, vp]
         L.ugks_heatflux.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -67,7 +69,7 @@ def lib():
 
 def exported_symbols():
     return ["ugks_create", "ugks_destroy", "ugks_sizes", "ugks_set_poses", "ugks_set_types",
-            "ugks_get_types", "ugks_set_overset", "overset_assemble", "ugks_maxwellian",
+            "ugks_get_types", "ugks_set_overset", "overset_assemble", "ugks_get_overset", "ugks_maxwellian",
             "ugks_moments", "ugks_heatflux", "ugks_flux", "overset_interp", "ugks_begin_step", "ugks_step",
             "ugks_timesteps", "ugks_step_profile", "ugks_last_error"]
 
@@ -169,6 +171,16 @@ class Solver:
         n = C.c_int32()
         _check(lib().overset_assemble(self.ctx, int(wrule), int(overlap), C.byref(n)))
         return n.value
+
+    def overset(self):
+        """Installed donor table: (rec, ptr, don, w) host arrays."""
+        nrec, nd = C.c_int32(), C.c_int32()
+        _check(lib().ugks_get_overset(self.ctx, C.byref(nrec), C.byref(nd), None, None, None, None))
+        rec = np.zeros(max(nrec.value, 1), np.int32); ptr = np.zeros(nrec.value + 1, np.int32)
+        don = np.zeros(max(nd.value, 1), np.int32); w = np.zeros(max(nd.value, 1))
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        _check(lib().ugks_get_overset(self.ctx, None, None, ip(rec), ip(ptr), ip(don), _dp(w)))
+        return rec[:nrec.value], ptr, don[:nd.value], w[:nd.value]
 
     # -------------------------------------------------------------- tensors
     def empty_f(self):

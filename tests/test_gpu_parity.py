@@ -25,7 +25,14 @@ def small_cases():
                           dt_over_dts=10.0)
     wallmov.name = "moving_cylinder"
     wallmov.motion = lambda t: [(0.0, 0.03 * t, 0.2 * t, 0.0, 0.03, 0.2)]
+    ffbox = wl.periodic_box(2, 9, 7, 10)
+    ffbox.blocks[0].bc = (wl.FARFIELD, wl.FARFIELD, wl.FARFIELD, wl.FARFIELD)
+    ffbox.name = "farfield_box"
+    mixbox = wl.periodic_box(2, 7, 9, 10)
+    mixbox.blocks[0].bc = (wl.COPY, wl.FARFIELD, wl.WALL, wl.COPY)
+    mixbox.name = "mixed_box"
     return [wl.sod_1d(ncell=40, nv=33), wl.periodic_box(1, 12, 1, 17), wl.periodic_box(2, 8, 6, 10),
+            ffbox, mixbox,
             wl.cylinder(ni=16, nj=8, nvx=16), wl.cavity(8, 12), wl.cavity(6, 10, periodic_x=True),
             mov, wallmov, wl.channel(6, 70, 8), wl.channel(5, 130, 6)]
 
