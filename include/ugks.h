@@ -228,9 +228,10 @@ int ugks_step(ugks_ctx* ctx, double dt, int32_t n_inner, void* h, void* b, doubl
  * with HIP events recorded on `stream` between the stages; waits for the
  * last event and writes host stage_ms[UGKS_NSTAGE], the mean milliseconds
  * per pseudo-iteration of: 0 overset interpolation, 1 W gradients and wall
- * incident states, 2 face equilibrium (k_face_eq), 3 flux (k_flux), 4 macro
- * LU-SGS, 5 cell equilibrium records, 6 micro LU-SGS sweeps (k_micro),
- * 7 Step-7 moments (k_step7).
+ * incident states, 2 face equilibrium (the face-moment march and its
+ * finalize), 3 flux (the flux march and its finalize), 4 macro LU-SGS,
+ * 5 cell equilibrium records, 6 micro LU-SGS (residual pass and sweeps),
+ * 7 Step-7 moments.
  */
 #define UGKS_NSTAGE 8
 int ugks_step_profile(ugks_ctx* ctx, double dt, int32_t n_inner, void* h, void* b, double* W,
@@ -240,6 +241,51 @@ int ugks_step_profile(ugks_ctx* ctx, double dt, int32_t n_inner, void* h, void* 
 /* Current explicit flux step dt_s and a copy of the virtual steps dt' (host
    array [ncell], may be NULL). */
 int ugks_timesteps(const ugks_ctx* ctx, double* dts, double* dtp);
+
+/*
+ * Replayed pseudo-iterations: the same work as ugks_step (Sec. 2.2, Steps
+ * 3-7, n_inner >= 1 times), captured once into a HIP graph on a private
+ * stream and launched on `stream`.  The graph is kept by the context and
+ * captured again when dt, n_inner, any array pointer, the geometry, the
+ * cell kinds, the donor table or the launch shapes change (an update of the
+ * executable graph in place when possible).  Results are identical to
+ * ugks_step.  Not thread-safe per context.
+ */
+int ugks_step_graph(ugks_ctx* ctx, double dt, int32_t n_inner, void* h, void* b, double* W, const double* Wn,
+                    double* q, const void* Sh, const void* Sb, const double* Fn, double* resid, void* stream);
+
+/*
+ * Batches of independent cases (ragged sizes, one context each, all on one
+ * device): ugks_batch_step runs n_inner pseudo-iterations of every case
+ * from one graph whose branches (up to four, round robin over the cases)
+ * run concurrently, launched on `stream`.  Array arguments are host arrays
+ * of ncase device pointers in case order (resid may be NULL, or hold NULL
+ * entries).  Cached like ugks_step_graph; results are identical to ugks_step
+ * per case.  The batch keeps the context pointers: destroy it before them.
+ */
+typedef struct ugks_batch ugks_batch;
+int ugks_batch_create(int32_t ncase, ugks_ctx* const* ctxs, ugks_batch** out);
+int ugks_batch_step(ugks_batch* batch, const double* dt, int32_t n_inner, void* const* h, void* const* b,
+                    double* const* W, const double* const* Wn, double* const* q, const void* const* Sh,
+                    const void* const* Sb, const double* const* Fn, double* const* resid, void* stream);
+int ugks_batch_destroy(ugks_batch* batch);
+
+/*
+ * Launch shapes (results do not depend on them): kc_max, the widest velocity
+ * chunk of a micro-sweep workgroup (16, 8 or 4; narrowed for tall blocks),
+ * and rg_eq, rg_flux, the core rows per workgroup of the face-equilibrium
+ * and flux march kernels (8 or 6).  ugks_autotune times every combination
+ * of kc_max {16, 8} x rg_eq {8, 6} x rg_flux {8, 6} over n_inner
+ * pseudo-iterations run on device copies of the given state (the caller's
+ * arrays are not written; scratch is allocated for the call), keeps the
+ * fastest and reports it in host choice[3] and its mean milliseconds per
+ * pseudo-iteration in *best_ms.  Synchronous.
+ */
+int ugks_set_tuning(ugks_ctx* ctx, int32_t kc_max, int32_t rg_eq, int32_t rg_flux);
+int ugks_get_tuning(const ugks_ctx* ctx, int32_t* kc_max, int32_t* rg_eq, int32_t* rg_flux);
+int ugks_autotune(ugks_ctx* ctx, double dt, int32_t n_inner, const void* h, const void* b, const double* W,
+                  const double* Wn, const double* q, const void* Sh, const void* Sb, const double* Fn,
+                  int32_t* choice, double* best_ms, void* stream);
 
 /* Thread-local message of the last failure ("" if none). */
 const char* ugks_last_error(void);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -48,6 +49,12 @@ struct DBuf {
 
 struct ugks_ctx {
   int device = 0;
+  // captured pseudo-iterations: the graph is rebuilt when its key changes;
+  // `version` counts changes of geometry, cell kinds and donor tables
+  unsigned version = 0;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint64_t> gkey;
   int dim = 2, nxi = 1, nw = 4, prec = 0;
   double pr, omega, mu_ref, rt_ref, cfl_s, cfl_p;
   int nvx, nvy, nv;
@@ -488,7 +495,7 @@ int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
   }
   if (c->dim == 2 && c->max_nj > 512) { delete c; return fail(UGKS_E_UNSUPPORTED, "nj above 512"); }
   if (c->any_pj && c->max_ni > 256) { delete c; return fail(UGKS_E_UNSUPPORTED, "periodic j needs ni <= 256"); }
-  if (micro_lds(c->dim, c->max_ni, c->max_nj, c->any_pj) > 160 * 1024) {
+  if (micro_lds(c->dim, c->max_ni, c->max_nj, c->any_pj, 16) > 160 * 1024) {
     delete c; return fail(UGKS_E_UNSUPPORTED, "micro sweep LDS above 160 KiB");
   }
   if (macro_lds(((c->max_nj + 63) / 64) * 64, c->max_ni, c->max_nj, c->any_pi, c->any_pj) > 160 * 1024) {
@@ -511,6 +518,13 @@ int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
   compute_geometry(c);
   // device
   if (hipSetDevice(device) != hipSuccess) { delete c; return fail(UGKS_E_DEVICE, "hipSetDevice failed"); }
+  {
+    static std::vector<int> ready;  // devices whose kernel attributes are set
+    if (std::find(ready.begin(), ready.end(), device) == ready.end()) {
+      if (init_kernel_attributes()) { delete c; return fail(UGKS_E_DEVICE, "kernel attributes"); }
+      ready.push_back(device);
+    }
+  }
   int rc = UGKS_OK;
   std::vector<int> binfo(8 * c->blk.size(), 0);
   for (size_t b = 0; b < c->blk.size(); ++b) {
@@ -577,6 +591,8 @@ int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
 int ugks_destroy(ugks_ctx* c) {
   if (!c) return UGKS_OK;
   (void)hipDeviceSynchronize();
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   free_all(c);
   delete c;
   return UGKS_OK;
@@ -593,6 +609,7 @@ int ugks_sizes(const ugks_ctx* c, int32_t* ncell, int32_t* nface, int32_t* nv, i
 
 int ugks_set_poses(ugks_ctx* c, const double* poses, double* dts) {
   if (!c || !poses) return fail(UGKS_E_ARG, "null argument");
+  ++c->version;
   for (size_t b = 0; b < c->blk.size(); ++b)
     for (int m = 0; m < 6; ++m) {
       if (!std::isfinite(poses[6 * b + m])) return fail(UGKS_E_ARG, "non-finite pose");
@@ -615,6 +632,7 @@ int ugks_timesteps(const ugks_ctx* c, double* dts, double* dtp) {
 
 int ugks_set_types(ugks_ctx* c, const int8_t* types) {
   if (!c || !types) return fail(UGKS_E_ARG, "null argument");
+  ++c->version;
   for (int n = 0; n < c->ncell; ++n)
     if (types[n] < 0 || types[n] > 2) return fail(UGKS_E_ARG, "bad cell kind");
   c->type.assign(types, types + c->ncell);
@@ -635,6 +653,7 @@ int ugks_get_types(const ugks_ctx* c, int8_t* types) {
 // donor table of nrow rows (the first nrec are receptors) to host and device
 static int install_overset(ugks_ctx* c, int nrow, int nrec, const int32_t* rec, const int32_t* ptr,
                            const int32_t* don, const double* w) {
+  ++c->version;
   c->nrec = nrec;
   c->nref = nrow - nrec;
   c->h_rec.assign(rec, rec + nrow);
@@ -687,6 +706,7 @@ int ugks_get_overset(const ugks_ctx* c, int32_t* nrec, int32_t* ndon, int32_t* r
 
 int overset_assemble(ugks_ctx* c, int32_t wrule, int32_t overlap, int32_t* nrec) {
   if (!c) return fail(UGKS_E_ARG, "null context");
+  ++c->version;
   if (wrule != 0 && wrule != 1) return fail(UGKS_E_ARG, "wrule must be 0 or 1");
   if (overlap < 0) return fail(UGKS_E_ARG, "negative overlap");
   if (c->dim != 2) return fail(UGKS_E_UNSUPPORTED, "overset assembly is 2D");
@@ -859,6 +879,232 @@ int ugks_step_profile(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b,
       }
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// captured pseudo-iterations, batches of cases, launch-shape tuning
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+std::vector<uint64_t> step_key(const ugks_ctx* c, double dt, int n_inner, std::initializer_list<const void*> ps) {
+  uint64_t bits;
+  std::memcpy(&bits, &dt, sizeof bits);
+  std::vector<uint64_t> k = {bits, (uint64_t)n_inner, c->version, (uint64_t)(uintptr_t)c,
+                             (uint64_t)(c->dev.kc_max | (c->dev.rg_eq << 8) | (c->dev.rg_flux << 16))};
+  for (const void* p : ps) k.push_back((uint64_t)(uintptr_t)p);
+  return k;
+}
+
+// instantiate `graph` into *exec, updating an existing executable in place
+// when the topology allows it
+int graph_to_exec(hipGraph_t graph, hipGraphExec_t* exec) {
+  if (*exec) {
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult res;
+    if (hipGraphExecUpdate(*exec, graph, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess)
+      return UGKS_OK;
+    (void)hipGetLastError();
+    (void)hipGraphExecDestroy(*exec);
+    *exec = nullptr;
+  }
+  if (hipGraphInstantiate(exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    *exec = nullptr;
+    return fail(UGKS_E_DEVICE, "hipGraphInstantiate failed");
+  }
+  return UGKS_OK;
+}
+
+struct StepArgs {
+  double dt;
+  void *h, *b;
+  double* W;
+  const double* Wn;
+  double* q;
+  const void *Sh, *Sb;
+  const double* Fn;
+  double* resid;
+};
+
+}  // namespace
+
+struct ugks_batch {
+  std::vector<ugks_ctx*> ctx;
+  std::vector<hipStream_t> st;  // private capture streams (branches of the graph)
+  std::vector<hipEvent_t> ev;   // fork and join events
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint64_t> gkey;
+};
+
+extern "C" {
+
+int ugks_step_graph(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, double* W, const double* Wn,
+                    double* q, const void* Sh, const void* Sb, const double* Fn, double* resid, void* stream) {
+  if (int rc = check_dev(c, {h, b, W, Wn, q, Sh, Sb, Fn})) return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
+  if (n_inner < 1) return fail(UGKS_E_ARG, "n_inner must be >= 1");
+  std::vector<uint64_t> key = step_key(c, dt, n_inner, {h, b, W, Wn, q, Sh, Sb, Fn, resid});
+  if (!c->gexec || key != c->gkey) {
+    if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    int rc = run_inner(c, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, resid, c->cap, nullptr);
+    hipError_t e = hipStreamEndCapture(c->cap, &graph);
+    if (!rc && e != hipSuccess) rc = fail(UGKS_E_DEVICE, "stream capture failed");
+    if (!rc) rc = graph_to_exec(graph, &c->gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) { c->gkey.clear(); return rc; }
+    c->gkey = key;
+  }
+  HIPCHK(hipGraphLaunch(c->gexec, (hipStream_t)stream));
+  return UGKS_OK;
+}
+
+int ugks_batch_create(int32_t ncase, ugks_ctx* const* ctxs, ugks_batch** out) {
+  if (!out || ncase < 1 || !ctxs) return fail(UGKS_E_ARG, "bad argument");
+  *out = nullptr;
+  for (int i = 0; i < ncase; ++i) {
+    if (!ctxs[i]) return fail(UGKS_E_ARG, "null context");
+    if (ctxs[i]->device != ctxs[0]->device) return fail(UGKS_E_ARG, "contexts on different devices");
+  }
+  auto* B = new ugks_batch;
+  B->ctx.assign(ctxs, ctxs + ncase);
+  const int ns = std::min(ncase, 4);  // branches: at most the hardware queues of a process
+  B->st.assign(ns, nullptr);
+  B->ev.assign(ns, nullptr);
+  for (int k = 0; k < ns; ++k) {
+    if (hipStreamCreateWithFlags(&B->st[k], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&B->ev[k], hipEventDisableTiming) != hipSuccess) {
+      ugks_batch_destroy(B);
+      return fail(UGKS_E_DEVICE, "stream or event creation failed");
+    }
+  }
+  *out = B;
+  return UGKS_OK;
+}
+
+int ugks_batch_destroy(ugks_batch* B) {
+  if (!B) return UGKS_OK;
+  (void)hipDeviceSynchronize();
+  if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+  for (auto s : B->st) if (s) (void)hipStreamDestroy(s);
+  for (auto e : B->ev) if (e) (void)hipEventDestroy(e);
+  delete B;
+  return UGKS_OK;
+}
+
+int ugks_batch_step(ugks_batch* B, const double* dt, int32_t n_inner, void* const* h, void* const* b,
+                    double* const* W, const double* const* Wn, double* const* q, const void* const* Sh,
+                    const void* const* Sb, const double* const* Fn, double* const* resid, void* stream) {
+  if (!B || !dt || !h || !b || !W || !Wn || !q || !Sh || !Sb || !Fn) return fail(UGKS_E_ARG, "null argument");
+  if (n_inner < 1) return fail(UGKS_E_ARG, "n_inner must be >= 1");
+  const int n = (int)B->ctx.size();
+  std::vector<uint64_t> key;
+  for (int i = 0; i < n; ++i) {
+    ugks_ctx* c = B->ctx[i];
+    double* r = resid ? resid[i] : nullptr;
+    if (int rc = check_dev(c, {h[i], b[i], W[i], Wn[i], q[i], Sh[i], Sb[i], Fn[i]})) return rc;
+    if (!(dt[i] > 0) || !std::isfinite(dt[i])) return fail(UGKS_E_ARG, "dt must be positive");
+    auto k = step_key(c, dt[i], n_inner, {h[i], b[i], W[i], Wn[i], q[i], Sh[i], Sb[i], Fn[i], r});
+    key.insert(key.end(), k.begin(), k.end());
+  }
+  if (!B->gexec || key != B->gkey) {
+    // one graph: the cases on parallel branches (round robin over the
+    // private streams), forked from and joined into the first stream
+    const int ns = (int)B->st.size();
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(B->st[0], hipStreamCaptureModeThreadLocal));
+    int rc = UGKS_OK;
+    if (hipEventRecord(B->ev[0], B->st[0]) != hipSuccess) rc = fail(UGKS_E_DEVICE, "fork");
+    for (int k = 1; k < ns && !rc; ++k)
+      if (hipStreamWaitEvent(B->st[k], B->ev[0], 0) != hipSuccess) rc = fail(UGKS_E_DEVICE, "fork");
+    for (int i = 0; i < n && !rc; ++i)
+      rc = run_inner(B->ctx[i], dt[i], n_inner, h[i], b[i], W[i], Wn[i], q[i], Sh[i], Sb[i], Fn[i],
+                     resid ? resid[i] : nullptr, B->st[i % ns], nullptr);
+    for (int k = 1; k < ns && !rc; ++k) {
+      if (hipEventRecord(B->ev[k], B->st[k]) != hipSuccess || hipStreamWaitEvent(B->st[0], B->ev[k], 0) != hipSuccess)
+        rc = fail(UGKS_E_DEVICE, "join");
+    }
+    hipError_t e = hipStreamEndCapture(B->st[0], &graph);
+    if (!rc && e != hipSuccess) rc = fail(UGKS_E_DEVICE, "stream capture failed");
+    if (!rc) rc = graph_to_exec(graph, &B->gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) { B->gkey.clear(); return rc; }
+    B->gkey = key;
+  }
+  HIPCHK(hipGraphLaunch(B->gexec, (hipStream_t)stream));
+  return UGKS_OK;
+}
+
+int ugks_set_tuning(ugks_ctx* c, int32_t kc_max, int32_t rg_eq, int32_t rg_flux) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  if ((kc_max != 16 && kc_max != 8 && kc_max != 4) || (rg_eq != 8 && rg_eq != 6) || (rg_flux != 8 && rg_flux != 6))
+    return fail(UGKS_E_ARG, "kc_max must be 16, 8 or 4 and row groups 8 or 6");
+  c->dev.kc_max = kc_max;
+  c->dev.rg_eq = rg_eq;
+  c->dev.rg_flux = rg_flux;
+  ++c->version;
+  return UGKS_OK;
+}
+
+int ugks_get_tuning(const ugks_ctx* c, int32_t* kc_max, int32_t* rg_eq, int32_t* rg_flux) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  if (kc_max) *kc_max = c->dev.kc_max;
+  if (rg_eq) *rg_eq = c->dev.rg_eq;
+  if (rg_flux) *rg_flux = c->dev.rg_flux;
+  return UGKS_OK;
+}
+
+int ugks_autotune(ugks_ctx* c, double dt, int32_t n_inner, const void* h, const void* b, const double* W,
+                  const double* Wn, const double* q, const void* Sh, const void* Sb, const double* Fn,
+                  int32_t* choice, double* best_ms, void* stream) {
+  if (int rc = check_dev(c, {h, b, W, Wn, q, Sh, Sb, Fn})) return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
+  if (n_inner < 1) return fail(UGKS_E_ARG, "n_inner must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t fb = (size_t)c->ncell * c->nv * (c->prec == UGKS_F64 ? 8 : 4);
+  const size_t wb = sizeof(double) * c->nw * (size_t)c->ncell, qb = sizeof(double) * c->dim * (size_t)c->ncell;
+  void *th = nullptr, *tb = nullptr, *tW = nullptr, *tq = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = UGKS_OK;
+  if (hipMalloc(&th, fb) != hipSuccess || hipMalloc(&tb, fb) != hipSuccess || hipMalloc(&tW, wb) != hipSuccess ||
+      hipMalloc(&tq, qb) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = fail(UGKS_E_DEVICE, "autotune scratch");
+  const Dev saved = c->dev;
+  double best = 1e300;
+  int bk = saved.kc_max, be = saved.rg_eq, bf = saved.rg_flux;
+  for (int kc : {16, 8})
+    for (int re : {8, 6})
+      for (int rf : {8, 6}) {
+        if (rc) break;
+        c->dev.kc_max = kc; c->dev.rg_eq = re; c->dev.rg_flux = rf;
+        if (micro_lds(c->dim, c->max_ni, c->max_nj, c->any_pj, kc) > 160 * 1024) continue;
+        // each candidate runs from the same inputs (copies; the caller's
+        // arrays are not written)
+        if (hipMemcpyAsync(th, h, fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(tb, b, fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(tW, W, wb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(tq, q, qb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipEventRecord(e0, st) != hipSuccess) { rc = fail(UGKS_E_DEVICE, "autotune copy"); break; }
+        rc = run_inner(c, dt, n_inner, th, tb, (double*)tW, Wn, (double*)tq, Sh, Sb, Fn, nullptr, st, nullptr);
+        if (rc) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = fail(UGKS_E_DEVICE, "autotune timing"); break; }
+        if (ms < best) { best = ms; bk = kc; be = re; bf = rf; }
+      }
+  c->dev = saved;
+  if (!rc) {
+    c->dev.kc_max = bk; c->dev.rg_eq = be; c->dev.rg_flux = bf;
+    ++c->version;
+    if (choice) { choice[0] = bk; choice[1] = be; choice[2] = bf; }
+    if (best_ms) *best_ms = best / n_inner;
+  }
+  for (void* p : {th, tb, tW, tq}) if (p) (void)hipFree(p);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   return rc;
 }
 

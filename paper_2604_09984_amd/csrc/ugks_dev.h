@@ -77,6 +77,10 @@ struct Dev {
   const void* finf_h;   // [nv] storage type
   const void* finf_b;
   const double* mgeo;   // [ncell][12] per slot (A, B, C) of the micro sweep
+  // launch shapes (read by the host launchers only; results do not depend
+  // on them): widest velocity chunk of the micro sweep, core rows per
+  // workgroup of the face-equilibrium and flux march kernels
+  int kc_max = 16, rg_eq = 8, rg_flux = 8;
 };
 
 // ------------------------------------------------------------------------

@@ -4,8 +4,10 @@
 
 namespace ugks {
 
-int micro_kc(int dim, int max_nj);
-size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj);
+// sets the kernels' dynamic LDS limits on the current device; 0 on success
+int init_kernel_attributes();
+int micro_kc(int dim, int max_nj, int kc_max);
+size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj, int kc_max);
 size_t macro_lds(int nt, int max_ni, int max_nj, int any_pi, int any_pj);
 
 void launch_flux(const Dev& g, int prec, const int* binfo, int max_nj, double dts, const void* h, const void* b,

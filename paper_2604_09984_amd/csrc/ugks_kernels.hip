@@ -1760,34 +1760,36 @@ void launch_flux_t(const Dev& g, double dts, const void* h, const void* b, const
   k_flux<D, T, C><<<nb4(g.ncell), 256, 0, st>>>(g, (const T*)h, (const T*)b, rec, (T*)Dh, (T*)Db, F, wall);
 }
 
-// core rows per workgroup of the march kernels (face-equilibrium and flux
-// passes): RG + 2 wavefronts share the reconstruction of RG rows
-#ifndef UGKS_RG_EQ
-#define UGKS_RG_EQ 8
-#endif
-#ifndef UGKS_RG_FLUX
-#define UGKS_RG_FLUX 8
-#endif
-constexpr int kRowGroupEq = UGKS_RG_EQ;
-constexpr int kRowGroupFlux = UGKS_RG_FLUX;
+// one march pass with RG core rows per workgroup (RG + 2 wavefronts share
+// the reconstruction of RG rows)
+template <int RG, class T, class C, int MODE>
+static void march_pass(const Dev& g, const int* binfo, int max_nj, int nchunk, const void* h, const void* b,
+                       const double* W, const double* rec, double* part, void* Dh, void* Db, hipStream_t st) {
+  dim3 grid((unsigned)nchunk, (unsigned)((max_nj + RG - 1) / RG), (unsigned)g.nblock);
+  k_march<RG, T, C, MODE><<<grid, 64 * (RG + 2), 0, st>>>(g, binfo, nchunk, (const T*)h, (const T*)b, W, rec,
+                                                          part, (T*)Dh, (T*)Db);
+}
+
+template <class T, class C, int MODE>
+static void march_rg(int rg, const Dev& g, const int* binfo, int max_nj, int nchunk, const void* h,
+                     const void* b, const double* W, const double* rec, double* part, void* Dh, void* Db,
+                     hipStream_t st) {
+  if (rg == 6) march_pass<6, T, C, MODE>(g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st);
+  else march_pass<8, T, C, MODE>(g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st);
+}
 
 template <class T, class C>
 void launch_march_t(const Dev& g, const int* binfo, int max_nj, double dts, const void* h, const void* b,
                     const double* W, const double* q, double* gW, double* rec, double* part, void* Dh, void* Db,
                     double* F, double* wall, hipStream_t st, hipEvent_t* ev) {
   const int nchunk = (g.nv + 63) / 64;
-  dim3 grid0((unsigned)nchunk, (unsigned)((max_nj + kRowGroupEq - 1) / kRowGroupEq), (unsigned)g.nblock);
-  dim3 grid1((unsigned)nchunk, (unsigned)((max_nj + kRowGroupFlux - 1) / kRowGroupFlux), (unsigned)g.nblock);
   k_gradW<<<nbl(g.ncell, 256), 256, 0, st>>>(g, W, gW);
   k_wallprep<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, W, q, gW, rec);
   if (ev) (void)hipEventRecord(ev[0], st);
-  k_march<kRowGroupEq, T, C, 0><<<grid0, 64 * (kRowGroupEq + 2), 0, st>>>(g, binfo, nchunk, (const T*)h,
-                                                                           (const T*)b, W, rec, part, (T*)Dh, (T*)Db);
+  march_rg<T, C, 0>(g.rg_eq, g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st);
   k_face_fin<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, nchunk, part, W, gW, rec);
   if (ev) (void)hipEventRecord(ev[1], st);
-  k_march<kRowGroupFlux, T, C, 1><<<grid1, 64 * (kRowGroupFlux + 2), 0, st>>>(g, binfo, nchunk, (const T*)h,
-                                                                               (const T*)b, W, rec, part, (T*)Dh,
-                                                                               (T*)Db);
+  march_rg<T, C, 1>(g.rg_flux, g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st);
   k_flux_fin<<<nbl(g.nface, 256), 256, 0, st>>>(g, nchunk, part, rec, F, wall);
 }
 
@@ -1847,12 +1849,6 @@ void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int an
   k_macro_prep<<<nbl(g.ncell, 256), 256, 0, st>>>(g, dt, W, Wn, F, Fn, gam, R);
   const int nt = ((max_nj + 63) / 64) * 64;
   const size_t lds = macro_lds(nt, max_ni, max_nj, any_pi, any_pj);
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_macro_sweep<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute((const void*)k_macro_sweep<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr = true;
-  }
   if (g.dim == 2)
     k_macro_sweep<2><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, dWs, dW, Wp, rpart, max_ni, max_nj, any_pi, any_pj);
   else
@@ -1861,21 +1857,18 @@ void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int an
 }
 
 // velocity-chunk width of the micro sweep for a block height
-#ifndef UGKS_MICRO_KC_MAX
-#define UGKS_MICRO_KC_MAX 16
-#endif
 #ifndef UGKS_MICRO_DEPTH
 #define UGKS_MICRO_DEPTH 2
 #endif
-int micro_kc(int dim, int max_nj) {
+int micro_kc(int dim, int max_nj, int kc_max) {
   if (dim == 1) return 64;
-  int kc = UGKS_MICRO_KC_MAX;
+  int kc = kc_max;
   while (kc > 2 && kc * max_nj > 1024) kc >>= 1;
   return kc;
 }
 
-size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj) {
-  int kc = micro_kc(dim, max_nj);
+size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj, int kc_max) {
+  int kc = micro_kc(dim, max_nj, kc_max);
   int nslot = (dim == 1) ? 1 : max_nj;
   return sizeof(double) * (size_t)(4 * (nslot + 2) * kc + 2 * nslot * kMicroRecLds + (any_pj ? 2 * max_ni * kc : 0));
 }
@@ -1884,12 +1877,6 @@ template <int D, class T, int KC>
 static void micro_t(const Dev& g, const int* binfo, int nslot, size_t lds, const double* crec, void* h, void* b,
                     void* Dh, void* Db, hipStream_t st) {
   constexpr int P = UGKS_MICRO_DEPTH;
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_micro<D, T, KC, P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-    attr = true;
-  }
   dim3 grid((unsigned)((g.nv + KC - 1) / KC), (unsigned)g.nblock);
   int threads = ((nslot * KC + 63) / 64) * 64;
   k_micro<D, T, KC, P><<<grid, threads, lds, st>>>(g, binfo, nslot, crec, (T*)h, (T*)b, (T*)Dh, (T*)Db);
@@ -1917,11 +1904,32 @@ void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_
   else
     k_micro_rhs<float><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const float*)h, (const float*)b,
                                                      (const float*)Sh, (const float*)Sb, (float*)Dh, (float*)Db);
-  const int KC = micro_kc(g.dim, max_nj);
+  const int KC = micro_kc(g.dim, max_nj, g.kc_max);
   const int nslot = (g.dim == 1) ? 1 : max_nj;
-  const size_t lds = micro_lds(g.dim, max_ni, max_nj, any_pj);
+  const size_t lds = micro_lds(g.dim, max_ni, max_nj, any_pj, g.kc_max);
   if (prec == 0) micro_prec<double>(g, binfo, KC, nslot, lds, crec, h, b, Dh, Db, st);
   else micro_prec<float>(g, binfo, KC, nslot, lds, crec, h, b, Dh, Db, st);
+}
+
+// dynamic LDS limits of the sweep kernels, set once per device before any
+// launch (kernel attributes are not stream work, so a captured graph never
+// depends on them)
+template <class T>
+static int micro_attrs() {
+  constexpr int P = UGKS_MICRO_DEPTH;
+  const void* f[] = {(const void*)k_micro<1, T, 64, P>, (const void*)k_micro<2, T, 16, P>,
+                     (const void*)k_micro<2, T, 8, P>, (const void*)k_micro<2, T, 4, P>,
+                     (const void*)k_micro<2, T, 2, P>};
+  for (const void* k : f)
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess) return -1;
+  return 0;
+}
+
+int init_kernel_attributes() {
+  if (micro_attrs<double>() || micro_attrs<float>()) return -1;
+  for (const void* k : {(const void*)k_macro_sweep<1>, (const void*)k_macro_sweep<2>})
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess) return -1;
+  return 0;
 }
 
 }  // namespace ugks

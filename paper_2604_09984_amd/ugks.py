@@ -63,6 +63,14 @@ def lib():
         L.ugks_step.argtypes = [vp, d, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ugks_timesteps.argtypes = [vp, C.POINTER(d), C.POINTER(d)]
         L.ugks_step_profile.argtypes = [vp, d, i32, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(d), vp]
+        L.ugks_step_graph.argtypes = [vp, d, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        pa = C.POINTER(vp)
+        L.ugks_batch_create.argtypes = [i32, pa, C.POINTER(vp)]
+        L.ugks_batch_destroy.argtypes = [vp]
+        L.ugks_batch_step.argtypes = [vp, C.POINTER(d), i32, pa, pa, pa, pa, pa, pa, pa, pa, pa, vp]
+        L.ugks_set_tuning.argtypes = [vp, i32, i32, i32]
+        L.ugks_get_tuning.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.ugks_autotune.argtypes = [vp, d, i32, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), C.POINTER(d), vp]
         _lib = L
     return _lib
 
@@ -71,7 +79,8 @@ def exported_symbols():
     return ["ugks_create", "ugks_destroy", "ugks_sizes", "ugks_set_poses", "ugks_set_types",
             "ugks_get_types", "ugks_set_overset", "overset_assemble", "ugks_get_overset", "ugks_maxwellian",
             "ugks_moments", "ugks_heatflux", "ugks_flux", "overset_interp", "ugks_begin_step", "ugks_step",
-            "ugks_timesteps", "ugks_step_profile", "ugks_last_error"]
+            "ugks_timesteps", "ugks_step_profile", "ugks_step_graph", "ugks_batch_create", "ugks_batch_step",
+            "ugks_batch_destroy", "ugks_set_tuning", "ugks_get_tuning", "ugks_autotune", "ugks_last_error"]
 
 
 def _check(rc):
@@ -233,6 +242,29 @@ class Solver:
                                _p(Sb), _p(Fn), _p(resid), self._stream(stream)))
         return resid
 
+    def step_graph(self, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, resid=None, stream=None):
+        """ugks_step through the context's captured graph (same results)."""
+        _check(lib().ugks_step_graph(self.ctx, float(dt), int(n_inner), _p(h), _p(b), _p(W), _p(Wn), _p(q),
+                                     _p(Sh), _p(Sb), _p(Fn), _p(resid), self._stream(stream)))
+        return resid
+
+    def set_tuning(self, kc_max=16, rg_eq=8, rg_flux=8):
+        _check(lib().ugks_set_tuning(self.ctx, int(kc_max), int(rg_eq), int(rg_flux)))
+
+    def tuning(self):
+        v = [C.c_int32() for _ in range(3)]
+        _check(lib().ugks_get_tuning(self.ctx, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def autotune(self, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, stream=None):
+        """Time the launch shapes on copies of the state; keeps and returns
+        the fastest ((kc_max, rg_eq, rg_flux), ms per pseudo-iteration)."""
+        ch = (C.c_int32 * 3)()
+        ms = C.c_double()
+        _check(lib().ugks_autotune(self.ctx, float(dt), int(n_inner), _p(h), _p(b), _p(W), _p(Wn), _p(q),
+                                   _p(Sh), _p(Sb), _p(Fn), ch, C.byref(ms), self._stream(stream)))
+        return tuple(ch), ms.value
+
     STAGES = ["interp", "gradW_wall", "face_eq", "flux", "macro_lusgs", "cell_rec", "micro_lusgs", "step7"]
 
     def step_profile(self, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, stream=None):
@@ -262,3 +294,33 @@ class Solver:
         n = self.case.n_inner if n_inner is None else n_inner
         self.step(dt, n, h, b, W, Wn, q, Sh, Sb, Fn, resid)
         return Wn
+
+
+class Batch:
+    """Independent cases (one Solver each, ragged sizes) advanced together
+    from one captured graph with concurrent branches."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        arr = (C.c_void_p * len(self.solvers))(*[s.ctx for s in self.solvers])
+        h = C.c_void_p()
+        _check(lib().ugks_batch_create(len(self.solvers), arr, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ugks_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self, dts, n_inner, states, resid=None, stream=None):
+        """states: per case (h, b, W, Wn, q, Sh, Sb, Fn) device tensors."""
+        n = len(self.solvers)
+        cols = list(zip(*states))
+        ptrs = [(C.c_void_p * n)(*[t.data_ptr() for t in col]) for col in cols]
+        rp = None if resid is None else (C.c_void_p * n)(*[0 if r is None else r.data_ptr() for r in resid])
+        dt = (C.c_double * n)(*[float(x) for x in dts])
+        st = self.solvers[0]._stream(stream)
+        _check(lib().ugks_batch_step(self.handle, dt, int(n_inner), *ptrs, rp, st))
