@@ -20,11 +20,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
-# algorithmic values moved per (cell, velocity) pair by each kernel
-# (storage-precision values: h, b, sources, divergences)
-KERNEL_VALUES = {"face_eq": 2, "flux": 4, "micro_lusgs": 14, "step7": 2}
-KERNEL_NAMES = {"face_eq": "k_face_eq", "flux": "k_flux", "micro_lusgs": "k_micro", "step7": "k_step7"}
+# algorithmic values moved per (cell, velocity) pair by each measured kernel
+# (storage-precision values of h, b, the sources and the D/residual buffer):
+#   face_eq      face-moment march: read h, b
+#   flux         flux march: read h, b; write D_h, D_b
+#   micro_rhs    micro residual: read S, f, D; write r over D
+#   micro_sweep  forward: read r, write dF*; backward: read dF*, f, write f
+#   step7        Step-7 moments: read h, b
+KERNEL_VALUES = {"face_eq": 2, "flux": 4, "micro_rhs": 8, "micro_sweep": 10, "step7": 2}
+KERNEL_NAMES = {"face_eq": "k_march (face-moment pass, MODE 0)", "flux": "k_march (flux pass, MODE 1)",
+                "micro_rhs": "k_micro_rhs", "micro_sweep": "k_micro", "step7": "k_step7"}
+KERNEL_KEYS = {"face_eq": "k_march<8, {t}, {t}, 0>", "flux": "k_march<8, {t}, {t}, 1>",
+               "micro_rhs": "k_micro_rhs<{t}>", "micro_sweep": "k_micro<2, {t}, 16, 2>", "step7": "k_step7<{t}>"}
 
 
 def parse():
@@ -35,6 +42,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle pseudo-iterations (0: skip)")
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--nvx", type=int, default=64)
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device copy of GIB GiB (HBM counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -68,31 +77,47 @@ def run_gpu(case, prec_name, steps, warmup):
     h, b, W, q = s.init_state()
     Wn = W.clone()
     Sh, Sb, Fn = s.begin_step(dt, h, b, W, q)
+    chunk = 10  # one physical step's inner loop per graph replay
+    # warm-up: eager, then the first replay captures the graph
     if warmup > 0:
         s.step(dt, warmup, h, b, W, Wn, q, Sh, Sb, Fn)
+    s.step_graph(dt, chunk, h, b, W, Wn, q, Sh, Sb, Fn)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev0.record()
     left = steps
     while left > 0:
-        n = min(10, left)  # one physical step's inner loop per call
-        s.step(dt, n, h, b, W, Wn, q, Sh, Sb, Fn)
+        n = min(chunk, left)
+        (s.step_graph if n == chunk else s.step)(dt, n, h, b, W, Wn, q, Sh, Sb, Fn)
         left -= n
-    ev1.record()
     torch.cuda.synchronize()
     wall_s = time.perf_counter() - t0
-    ev_ms = ev0.elapsed_time(ev1)
-    # stage timing (HIP events on the library's stream), separate short run
-    prof = s.step_profile(dt, 10, h, b, W, Wn, q, Sh, Sb, Fn)
+    # the same pseudo-iterations launched one kernel at a time, for comparison
+    t1 = time.perf_counter()
+    s.step(dt, chunk, h, b, W, Wn, q, Sh, Sb, Fn)
+    torch.cuda.synchronize()
+    eager_ms = 1e3 * (time.perf_counter() - t1) / chunk
+    # per-kernel timing: HIP events on the library's stream, separate run
+    prof = s.step_profile(dt, chunk, h, b, W, Wn, q, Sh, Sb, Fn)
     torch.cuda.synchronize()
     pairs = int((s.types() == 1).sum()) * s.nv
-    out = dict(prec=prec_name, pairs=pairs, wall_s=wall_s, ev_ms=ev_ms, steps=steps, stages=prof,
+    out = dict(prec=prec_name, pairs=pairs, wall_s=wall_s, eager_ms=eager_ms, steps=steps, stages=prof,
                finite=bool(torch.isfinite(h).all().item() and torch.isfinite(W).all().item()))
     out["h"] = h.to(torch.float64).cpu()
     s.close()
     return out
+
+
+def copy_calibration(gib):
+    """A plain device-to-device copy of known size (read n bytes, write n
+    bytes), the reference of the HBM counters."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 8 * n, "launches": 3}), flush=True)
 
 
 def cpu_baseline(case, nsteps):
@@ -117,6 +142,20 @@ def cpu_baseline(case, nsteps):
                       f"{pairs} pairs, {sec:.1f} s"}
 
 
+def roofline(stages, pairs, prec):
+    """Dominant measured kernel: algorithmic bytes per launch over its mean
+    launch time (HIP events), against the HBM peak."""
+    dom = max(KERNEL_VALUES, key=lambda k: stages[k])
+    nbytes = 8 if prec == "f64" else 4
+    algo = KERNEL_VALUES[dom] * nbytes * pairs
+    t = stages[dom] * 1e-3
+    achieved = algo / t / 1e9
+    key = KERNEL_KEYS[dom].format(t="double" if prec == "f64" else "float")
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(key, prec),
+            "kernel": KERNEL_NAMES[dom], "kernel_ms": round(stages[dom], 4), "algorithmic_bytes_per_launch": algo}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -132,23 +171,20 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(3)
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
     case = wl.cylinder(nvx=args.nvx)
     r64 = run_gpu(case, "f64", args.steps, args.warmup)
     r32 = None if args.no_f32 else run_gpu(case, "f32", args.steps, args.warmup)
     ms64 = 1e3 * r64["wall_s"] / args.steps
     value = r64["pairs"] * args.steps / r64["wall_s"]
-    # dominant kernel of the FP64 path
     st = r64["stages"]
-    dom = max(KERNEL_VALUES, key=lambda k: st[k])
-    t_launch = st[dom] * 1e-3
-    algo_bytes = KERNEL_VALUES[dom] * 8 * r64["pairs"]
-    achieved = algo_bytes / t_launch / 1e9
-    traffic = traffic_from_profiles(KERNEL_NAMES[dom], "f64")
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": KERNEL_NAMES[dom], "kernel_ms": round(st[dom], 4),
-            "algorithmic_bytes_per_launch": algo_bytes}
-    total_algo = sum(KERNEL_VALUES.values()) * 8 * r64["pairs"]
+    per_kernel = {}
+    for k, nv in KERNEL_VALUES.items():
+        gbs = nv * 8 * r64["pairs"] / (st[k] * 1e-3) / 1e9
+        per_kernel[k] = {"ms": round(st[k], 4), "algorithmic_GBs": round(gbs, 1)}
+    total_values = sum(KERNEL_VALUES.values())
     line = {
         "metric": "(cell x velocity) updates/s per pseudo-step",
         "value": value,
@@ -164,10 +200,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"Ma5 cylinder, O-mesh 128x64 cells, {args.nvx}x{args.nvx} velocities on "
                                f"[-15,15]^2, Kn 0.01 hard sphere, isothermal wall, dt = 20 dt_s",
-                   "pairs": r64["pairs"], "pseudo_steps": args.steps},
-        "roofline": roof,
+                   "pairs": r64["pairs"], "pseudo_steps": args.steps, "launch": "hipGraph replay, 10 per replay"},
+        "roofline": roofline(st, r64["pairs"], "f64"),
+        "kernels_f64": per_kernel,
         "stages_ms_f64": {k: round(v, 4) for k, v in st.items()},
-        "hbm_algorithmic_GBs_f64": round(total_algo / (ms64 * 1e-3) / 1e9, 1),
+        "eager_ms_per_step_f64": round(r64["eager_ms"], 4),
+        "hbm_algorithmic_GBs_f64": round(total_values * 8 * r64["pairs"] / (ms64 * 1e-3) / 1e9, 1),
     }
     if r32 is not None:
         ms32 = 1e3 * r32["wall_s"] / args.steps
@@ -178,6 +216,7 @@ def main():
         line["f32"] = {"value": r32["pairs"] * args.steps / r32["wall_s"], "ms_per_step": ms32,
                        "speedup_vs_f64": ms64 / ms32,
                        "rel_l2_h_vs_f64_after_run": rel,
+                       "roofline": roofline(r32["stages"], r32["pairs"], "f32"),
                        "stages_ms": {k: round(v, 4) for k, v in r32["stages"].items()}}
     line["finite"] = r64["finite"] and (r32 is None or r32["finite"])
     if args.cpu_steps > 0:

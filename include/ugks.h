@@ -225,15 +225,16 @@ int ugks_step(ugks_ctx* ctx, double dt, int32_t n_inner, void* h, void* b, doubl
 
 /*
  * Instrumented ugks_step for measurement: the same n_inner pseudo-iterations,
- * with HIP events recorded on `stream` between the stages; waits for the
+ * with HIP events recorded on `stream` between the kernels; waits for the
  * last event and writes host stage_ms[UGKS_NSTAGE], the mean milliseconds
  * per pseudo-iteration of: 0 overset interpolation, 1 W gradients and wall
- * incident states, 2 face equilibrium (the face-moment march and its
- * finalize), 3 flux (the flux march and its finalize), 4 macro LU-SGS,
- * 5 cell equilibrium records, 6 micro LU-SGS (residual pass and sweeps),
- * 7 Step-7 moments.
+ * incident states, 2 face-moment pass (the face-equilibrium march kernel;
+ * 1D: the face-equilibrium kernel), 3 face-equilibrium finalize, 4 flux
+ * pass (the flux march kernel; 1D: the flux kernel), 5 flux finalize,
+ * 6 macro LU-SGS, 7 cell equilibrium records, 8 micro residual pass,
+ * 9 micro LU-SGS sweeps, 10 Step-7 moments.
  */
-#define UGKS_NSTAGE 8
+#define UGKS_NSTAGE 11
 int ugks_step_profile(ugks_ctx* ctx, double dt, int32_t n_inner, void* h, void* b, double* W,
                       const double* Wn, double* q, const void* Sh, const void* Sb, const double* Fn,
                       double* stage_ms, void* stream);

@@ -822,27 +822,27 @@ static int run_inner(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, 
   // micro step)
   launch_step7(g, c->prec, 0, h, b, nullptr, nullptr, W, q, (double*)c->s_mrec, st);
   for (int s = 0; s < n_inner; ++s) {
-    hipEvent_t* e = ev ? &(*ev)[9 * (size_t)s] : nullptr;
+    hipEvent_t* e = ev ? &(*ev)[(UGKS_NSTAGE + 1) * (size_t)s] : nullptr;
     if (e) HIPCHK(hipEventRecord(e[0], st));
     launch_interp(g, c->prec, c->nrec, (const int*)c->d_rec, (const int*)c->d_ptr, (const int*)c->d_don,
                   (const double*)c->d_w, h, b, W, q, st);
     if (e) HIPCHK(hipEventRecord(e[1], st));
     launch_flux(g, c->prec, (const int*)c->d_binfo, c->max_nj, c->dts, h, b, W, q, (double*)c->s_gW,
                 (double*)c->s_rec, (double*)c->s_part, c->s_Dh, c->s_Db, F, nullptr, st, e ? e + 2 : nullptr);
-    if (e) HIPCHK(hipEventRecord(e[4], st));
+    if (e) HIPCHK(hipEventRecord(e[6], st));
     launch_macro(g, (const int*)c->d_binfo, c->max_ni, c->max_nj, c->any_pi, c->any_pj, dt, W, Wn, F, Fn,
                  (double*)c->s_gam, (double*)c->s_R,
                  (double*)c->s_Dg, (double*)c->s_dWs, (double*)c->s_dW, (double*)c->s_Wp, (double*)c->s_rpart,
                  resid ? resid + (size_t)s * c->nw : nullptr, st);
-    if (e) HIPCHK(hipEventRecord(e[5], st));
-    launch_cellrec(g, dt, (const double*)c->s_Wp, nullptr, (const double*)c->s_mrec, (double*)c->s_crec, st);
-    if (e) HIPCHK(hipEventRecord(e[6], st));
-    launch_micro(g, c->prec, (const int*)c->d_binfo, c->max_ni, c->max_nj, c->any_pj, dt,
-                 (const double*)c->s_crec, h, b, Sh, Sb, c->s_Dh, c->s_Db, st);
     if (e) HIPCHK(hipEventRecord(e[7], st));
+    launch_cellrec(g, dt, (const double*)c->s_Wp, nullptr, (const double*)c->s_mrec, (double*)c->s_crec, st);
+    if (e) HIPCHK(hipEventRecord(e[8], st));
+    launch_micro(g, c->prec, (const int*)c->d_binfo, c->max_ni, c->max_nj, c->any_pj, dt,
+                 (const double*)c->s_crec, h, b, Sh, Sb, c->s_Dh, c->s_Db, st, e ? e + 9 : nullptr);
+    if (e) HIPCHK(hipEventRecord(e[10], st));
     launch_step7(g, c->prec, 1, h, b, (const double*)c->s_crec, (const double*)c->s_Wp, W, q,
                  (double*)c->s_mrec, st);
-    if (e) HIPCHK(hipEventRecord(e[8], st));
+    if (e) HIPCHK(hipEventRecord(e[11], st));
   }
   HIPCHK(hipGetLastError());
   return UGKS_OK;
@@ -863,7 +863,7 @@ int ugks_step_profile(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b,
   if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
   if (n_inner < 1) return fail(UGKS_E_ARG, "n_inner must be >= 1");
   hipStream_t st = (hipStream_t)stream;
-  std::vector<hipEvent_t> ev(9 * (size_t)n_inner);
+  std::vector<hipEvent_t> ev((UGKS_NSTAGE + 1) * (size_t)n_inner);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   int rc = run_inner(c, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, nullptr, st, &ev);
   if (!rc) {
@@ -874,7 +874,7 @@ int ugks_step_profile(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b,
     for (int s = 0; s < n_inner; ++s)
       for (int k = 0; k < UGKS_NSTAGE; ++k) {
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, ev[9 * (size_t)s + k], ev[9 * (size_t)s + k + 1]);
+        (void)hipEventElapsedTime(&ms, ev[(UGKS_NSTAGE + 1) * (size_t)s + k], ev[(UGKS_NSTAGE + 1) * (size_t)s + k + 1]);
         stage_ms[k] += ms / n_inner;
       }
   }

@@ -10,6 +10,8 @@ int micro_kc(int dim, int max_nj, int kc_max);
 size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj, int kc_max);
 size_t macro_lds(int nt, int max_ni, int max_nj, int any_pi, int any_pj);
 
+// with ev, four events are recorded: after the wall preparation, after the
+// face-moment pass, after its finalize, after the flux pass
 void launch_flux(const Dev& g, int prec, const int* binfo, int max_nj, double dts, const void* h, const void* b,
                  const double* W, const double* q, double* gW, double* rec, double* part, void* Dh, void* Db,
                  double* F, double* wall, hipStream_t st, hipEvent_t* ev = nullptr);
@@ -30,6 +32,6 @@ void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int an
                   double* Dg, double* dWs, double* dW, double* Wp, double* rpart, double* resid, hipStream_t st);
 void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
                   const double* crec, void* h, void* b, const void* Sh, const void* Sb, void* Dh, void* Db,
-                  hipStream_t st);
+                  hipStream_t st, hipEvent_t* ev = nullptr);
 
 }  // namespace ugks

@@ -1756,8 +1756,9 @@ void launch_flux_t(const Dev& g, double dts, const void* h, const void* b, const
   k_wallprep<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, W, q, gW, rec);
   if (ev) (void)hipEventRecord(ev[0], st);
   k_face_eq<D, T><<<nb4(g.ncell), 256, 0, st>>>(g, dts, (const T*)h, (const T*)b, W, gW, rec);
-  if (ev) (void)hipEventRecord(ev[1], st);
+  if (ev) { (void)hipEventRecord(ev[1], st); (void)hipEventRecord(ev[2], st); }
   k_flux<D, T, C><<<nb4(g.ncell), 256, 0, st>>>(g, (const T*)h, (const T*)b, rec, (T*)Dh, (T*)Db, F, wall);
+  if (ev) (void)hipEventRecord(ev[3], st);
 }
 
 // one march pass with RG core rows per workgroup (RG + 2 wavefronts share
@@ -1787,9 +1788,11 @@ void launch_march_t(const Dev& g, const int* binfo, int max_nj, double dts, cons
   k_wallprep<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, W, q, gW, rec);
   if (ev) (void)hipEventRecord(ev[0], st);
   march_rg<T, C, 0>(g.rg_eq, g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st);
-  k_face_fin<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, nchunk, part, W, gW, rec);
   if (ev) (void)hipEventRecord(ev[1], st);
+  k_face_fin<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, nchunk, part, W, gW, rec);
+  if (ev) (void)hipEventRecord(ev[2], st);
   march_rg<T, C, 1>(g.rg_flux, g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st);
+  if (ev) (void)hipEventRecord(ev[3], st);
   k_flux_fin<<<nbl(g.nface, 256), 256, 0, st>>>(g, nchunk, part, rec, F, wall);
 }
 
@@ -1896,7 +1899,7 @@ static void micro_prec(const Dev& g, const int* binfo, int KC, int nslot, size_t
 
 void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
                   const double* crec, void* h, void* b, const void* Sh, const void* Sb, void* Dh, void* Db,
-                  hipStream_t st) {
+                  hipStream_t st, hipEvent_t* ev) {
   if (prec == 0)
     k_micro_rhs<double><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const double*)h, (const double*)b,
                                                       (const double*)Sh, (const double*)Sb, (double*)Dh,
@@ -1904,6 +1907,7 @@ void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_
   else
     k_micro_rhs<float><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const float*)h, (const float*)b,
                                                      (const float*)Sh, (const float*)Sb, (float*)Dh, (float*)Db);
+  if (ev) (void)hipEventRecord(ev[0], st);
   const int KC = micro_kc(g.dim, max_nj, g.kc_max);
   const int nslot = (g.dim == 1) ? 1 : max_nj;
   const size_t lds = micro_lds(g.dim, max_ni, max_nj, any_pj, g.kc_max);

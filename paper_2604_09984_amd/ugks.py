@@ -265,12 +265,13 @@ class Solver:
                                    _p(Sh), _p(Sb), _p(Fn), ch, C.byref(ms), self._stream(stream)))
         return tuple(ch), ms.value
 
-    STAGES = ["interp", "gradW_wall", "face_eq", "flux", "macro_lusgs", "cell_rec", "micro_lusgs", "step7"]
+    STAGES = ["interp", "gradW_wall", "face_eq", "face_fin", "flux", "flux_fin", "macro_lusgs", "cell_rec",
+              "micro_rhs", "micro_sweep", "step7"]
 
     def step_profile(self, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, stream=None):
         """Run n_inner pseudo-iterations with stage timing; returns
         {stage: mean ms per pseudo-iteration} (synchronous)."""
-        ms = (C.c_double * 8)()
+        ms = (C.c_double * len(self.STAGES))()
         _check(lib().ugks_step_profile(self.ctx, float(dt), int(n_inner), _p(h), _p(b), _p(W), _p(Wn), _p(q),
                                        _p(Sh), _p(Sb), _p(Fn), ms, self._stream(stream)))
         return dict(zip(self.STAGES, list(ms)))
