@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_VALUES = {"face_eq": 2, "flux": 4, "micro_rhs": 8, "micro_sweep": 10, "step7": 2}
 KERNEL_NAMES = {"face_eq": "k_march (face-moment pass, MODE 0)", "flux": "k_march (flux pass, MODE 1)",
                 "micro_rhs": "k_micro_rhs", "micro_sweep": "k_micro", "step7": "k_step7"}
-KERNEL_KEYS = {"face_eq": "k_march<8, {t}, {t}, 0>", "flux": "k_march<8, {t}, {t}, 1>",
-               "micro_rhs": "k_micro_rhs<{t}>", "micro_sweep": "k_micro<2, {t}, 16, 2>", "step7": "k_step7<{t}>"}
+KERNEL_KEYS = {"face_eq": "k_march<{re}, {t}, {t}, 0>", "flux": "k_march<{rf}, {t}, {t}, 1>",
+               "micro_rhs": "k_micro_rhs<{t}>", "micro_sweep": "k_micro<2, {t}, {kc}, 2>", "step7": "k_step7<{t}>"}
 
 
 def parse():
@@ -78,9 +78,11 @@ def run_gpu(case, prec_name, steps, warmup):
     Wn = W.clone()
     Sh, Sb, Fn = s.begin_step(dt, h, b, W, q)
     chunk = 10  # one physical step's inner loop per graph replay
-    # warm-up: eager, then the first replay captures the graph
+    # warm-up: eager, the launch-shape autotuner (on copies of the state),
+    # then the first replay captures the graph
     if warmup > 0:
         s.step(dt, warmup, h, b, W, Wn, q, Sh, Sb, Fn)
+    tuning, _ = s.autotune(dt, 3, h, b, W, Wn, q, Sh, Sb, Fn)
     s.step_graph(dt, chunk, h, b, W, Wn, q, Sh, Sb, Fn)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -101,6 +103,7 @@ def run_gpu(case, prec_name, steps, warmup):
     torch.cuda.synchronize()
     pairs = int((s.types() == 1).sum()) * s.nv
     out = dict(prec=prec_name, pairs=pairs, wall_s=wall_s, eager_ms=eager_ms, steps=steps, stages=prof,
+               tuning=dict(zip(("kc_max", "rg_eq", "rg_flux"), tuning)),
                finite=bool(torch.isfinite(h).all().item() and torch.isfinite(W).all().item()))
     out["h"] = h.to(torch.float64).cpu()
     s.close()
@@ -142,7 +145,7 @@ def cpu_baseline(case, nsteps):
                       f"{pairs} pairs, {sec:.1f} s"}
 
 
-def roofline(stages, pairs, prec):
+def roofline(stages, pairs, prec, tuning):
     """Dominant measured kernel: algorithmic bytes per launch over its mean
     launch time (HIP events), against the HBM peak."""
     dom = max(KERNEL_VALUES, key=lambda k: stages[k])
@@ -150,10 +153,11 @@ def roofline(stages, pairs, prec):
     algo = KERNEL_VALUES[dom] * nbytes * pairs
     t = stages[dom] * 1e-3
     achieved = algo / t / 1e9
-    key = KERNEL_KEYS[dom].format(t="double" if prec == "f64" else "float")
+    key = KERNEL_KEYS[dom].format(t="double" if prec == "f64" else "float", re=tuning["rg_eq"],
+                                  rf=tuning["rg_flux"], kc=tuning["kc_max"])
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(key, prec),
-            "kernel": KERNEL_NAMES[dom], "kernel_ms": round(stages[dom], 4), "algorithmic_bytes_per_launch": algo}
+            "kernel": KERNEL_NAMES[dom], "kernel_instance": key, "kernel_ms": round(stages[dom], 4), "algorithmic_bytes_per_launch": algo}
 
 
 def main():
@@ -201,10 +205,11 @@ def main():
         "config": {"workload": f"Ma5 cylinder, O-mesh 128x64 cells, {args.nvx}x{args.nvx} velocities on "
                                f"[-15,15]^2, Kn 0.01 hard sphere, isothermal wall, dt = 20 dt_s",
                    "pairs": r64["pairs"], "pseudo_steps": args.steps, "launch": "hipGraph replay, 10 per replay"},
-        "roofline": roofline(st, r64["pairs"], "f64"),
+        "roofline": roofline(st, r64["pairs"], "f64", r64["tuning"]),
         "kernels_f64": per_kernel,
         "stages_ms_f64": {k: round(v, 4) for k, v in st.items()},
         "eager_ms_per_step_f64": round(r64["eager_ms"], 4),
+        "launch_shapes_f64": r64["tuning"],
         "hbm_algorithmic_GBs_f64": round(total_values * 8 * r64["pairs"] / (ms64 * 1e-3) / 1e9, 1),
     }
     if r32 is not None:
@@ -216,7 +221,8 @@ def main():
         line["f32"] = {"value": r32["pairs"] * args.steps / r32["wall_s"], "ms_per_step": ms32,
                        "speedup_vs_f64": ms64 / ms32,
                        "rel_l2_h_vs_f64_after_run": rel,
-                       "roofline": roofline(r32["stages"], r32["pairs"], "f32"),
+                       "roofline": roofline(r32["stages"], r32["pairs"], "f32", r32["tuning"]),
+                       "launch_shapes": r32["tuning"],
                        "stages_ms": {k: round(v, 4) for k, v in r32["stages"].items()}}
     line["finite"] = r64["finite"] and (r32 is None or r32["finite"])
     if args.cpu_steps > 0:

@@ -68,6 +68,7 @@ struct ugks_ctx {
   std::vector<double> xn, yn;  // current nodes, per block
   std::vector<size_t> node0;
   std::vector<double> vol, G, cdx, dtp, fgeo, mgeo, ccx, ccy;  // ccx, ccy: cell centroids
+  std::vector<double> cplan, fplan;                            // packed march tables
   std::vector<int> nb, cf, fcell;
   std::vector<int8_t> type, fact;
   std::vector<int> cblk, ci, cj;
@@ -76,7 +77,7 @@ struct ugks_ctx {
   Dev dev{};
   void *d_vx = nullptr, *d_vy = nullptr, *d_wk = nullptr, *d_vol = nullptr, *d_G = nullptr, *d_cdx = nullptr,
        *d_dtp = nullptr, *d_type = nullptr, *d_nb = nullptr, *d_cf = nullptr, *d_fcell = nullptr,
-       *d_fgeo = nullptr, *d_fact = nullptr, *d_finf_h = nullptr, *d_finf_b = nullptr, *d_binfo = nullptr,
+       *d_fgeo = nullptr, *d_fact = nullptr, *d_cplan = nullptr, *d_fplan = nullptr, *d_finf_h = nullptr, *d_finf_b = nullptr, *d_binfo = nullptr,
        *d_mgeo = nullptr;
   // scratch
   void *s_gW = nullptr, *s_rec = nullptr, *s_gam = nullptr, *s_R = nullptr, *s_Dg = nullptr, *s_dWs = nullptr,
@@ -372,6 +373,49 @@ void compute_geometry(ugks_ctx* c) {
     }
 }
 
+// packed per-cell and per-face tables of the march kernels
+int upload_plans(ugks_ctx* c) {
+  // built once both the geometry and the topology tables exist
+  if (c->vol.size() != (size_t)c->ncell || c->fgeo.size() != 8 * (size_t)c->nface ||
+      c->nb.size() != 4 * (size_t)c->ncell || c->cf.size() != 4 * (size_t)c->ncell ||
+      c->fact.size() != (size_t)c->nface || c->fcell.size() != 2 * (size_t)c->nface ||
+      c->cdx.size() != 8 * (size_t)c->ncell || c->G.size() != 4 * (size_t)c->ncell)
+    return UGKS_OK;
+  c->cplan.assign((size_t)kCpN * c->ncell, 0.0);
+  for (int n = 0; n < c->ncell; ++n) {
+    double* P = &c->cplan[(size_t)kCpN * n];
+    P[kCpType] = c->type[n];
+    for (int s = 0; s < 4; ++s) {
+      const int f = c->cf[4 * (size_t)n + s];
+      P[kCpNb + s] = c->nb[4 * (size_t)n + s];
+      P[kCpG + s] = c->G[4 * (size_t)n + s];
+      P[kCpS + s] = (f >= 0) ? c->fgeo[8 * (size_t)f + 2] : 0.0;
+      P[kCpFace + s] = f;
+    }
+    P[kCpIvol] = 1.0 / c->vol[n];
+  }
+  c->fplan.assign((size_t)kFpN * c->nface, 0.0);
+  for (int f = 0; f < c->nface; ++f) {
+    double* P = &c->fplan[(size_t)kFpN * f];
+    const double* fg = &c->fgeo[8 * (size_t)f];
+    P[kFpN0] = fg[0]; P[kFpN0 + 1] = fg[1]; P[kFpS] = fg[2]; P[kFpU] = fg[3]; P[kFpU + 1] = fg[4];
+    const int L = c->fcell[2 * (size_t)f], R = c->fcell[2 * (size_t)f + 1];
+    P[kFpL] = L; P[kFpR] = R; P[kFpAct] = c->fact[f];
+    for (int side = 0; side < 2; ++side) {
+      const int cell = side ? R : L;
+      if (cell < 0) continue;
+      for (int s = 0; s < 4; ++s)
+        if (c->cf[4 * (size_t)cell + s] == f) {
+          P[(side ? kFpDR : kFpDL)] = c->cdx[8 * (size_t)cell + 2 * s];
+          P[(side ? kFpDR : kFpDL) + 1] = c->cdx[8 * (size_t)cell + 2 * s + 1];
+        }
+    }
+  }
+  int rc = upload(c->d_cplan, c->cplan);
+  if (!rc) rc = upload(c->d_fplan, c->fplan);
+  return rc;
+}
+
 int upload_geometry(ugks_ctx* c) {
   int rc;
   if ((rc = upload(c->d_vol, c->vol))) return rc;
@@ -380,7 +424,7 @@ int upload_geometry(ugks_ctx* c) {
   if ((rc = upload(c->d_dtp, c->dtp))) return rc;
   if ((rc = upload(c->d_fgeo, c->fgeo))) return rc;
   if ((rc = upload(c->d_mgeo, c->mgeo))) return rc;
-  return UGKS_OK;
+  return upload_plans(c);
 }
 
 int upload_tables(ugks_ctx* c) {
@@ -388,7 +432,7 @@ int upload_tables(ugks_ctx* c) {
   if ((rc = upload(c->d_type, c->type))) return rc;
   if ((rc = upload(c->d_nb, c->nb))) return rc;
   if ((rc = upload(c->d_fact, c->fact))) return rc;
-  return UGKS_OK;
+  return upload_plans(c);
 }
 
 void fill_dev(ugks_ctx* c) {
@@ -403,13 +447,15 @@ void fill_dev(ugks_ctx* c) {
   g.cf = (const int*)c->d_cf; g.fcell = (const int*)c->d_fcell; g.fgeo = (const double*)c->d_fgeo;
   g.fact = (const int8_t*)c->d_fact; g.finf_h = c->d_finf_h; g.finf_b = c->d_finf_b;
   g.mgeo = (const double*)c->d_mgeo;
+  g.cplan = (const double*)c->d_cplan;
+  g.fplan = (const double*)c->d_fplan;
 }
 
 void free_all(ugks_ctx* c) {
   void* ps[] = {c->d_vx, c->d_vy, c->d_wk, c->d_vol, c->d_G, c->d_cdx, c->d_dtp, c->d_type, c->d_nb, c->d_cf,
                 c->d_fcell, c->d_fgeo, c->d_fact, c->d_finf_h, c->d_finf_b, c->d_binfo, c->d_mgeo, c->s_gW, c->s_rec,
                 c->s_gam, c->s_R, c->s_Dg, c->s_dWs, c->s_dW, c->s_Wp, c->s_rpart, c->s_crec, c->s_mrec,
-                c->s_Dh, c->s_Db, c->s_F, c->s_part, c->d_rec, c->d_ptr, c->d_don, c->d_w};
+                c->s_Dh, c->s_Db, c->s_F, c->s_part, c->d_rec, c->d_ptr, c->d_don, c->d_w, c->d_cplan, c->d_fplan};
   for (void* p : ps)
     if (p) (void)hipFree(p);
 }
@@ -584,6 +630,12 @@ int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
     free_all(c); delete c; return fail(UGKS_E_DEVICE, "hipMemset failed");
   }
   fill_dev(c);
+  // default launch shapes (measured on the cylinder workload; ugks_autotune
+  // refines them per case): the FP64 flux pass keeps more registers per
+  // wavefront with six core rows per workgroup
+  c->dev.kc_max = 16;
+  c->dev.rg_eq = 8;
+  c->dev.rg_flux = (c->prec == UGKS_F64) ? 6 : 8;
   *out = c;
   return UGKS_OK;
 }

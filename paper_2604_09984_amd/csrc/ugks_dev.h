@@ -45,6 +45,15 @@ __device__ __forceinline__ void record_derived(double* r) {
   r[R_SQY] = r[R_SH] * r[R_QY];
 }
 
+// packed per-cell table of the march kernels (double, exact small integers
+// for kinds and indices): kind, neighbour codes per slot, J^{-T}, face area
+// per slot (0 without a face), 1/|Omega|, face id per slot (-1 none)
+enum : int { kCpType = 0, kCpNb = 1, kCpG = 5, kCpS = 9, kCpIvol = 13, kCpFace = 14, kCpN = 20 };
+// packed per-face table: unit normal, area, grid velocity, offsets from the
+// centroids of the low and high cells to the face centre (zero on a ghost or
+// wall side), low and high cell or ghost code, 1 if the face carries flux
+enum : int { kFpN0 = 0, kFpS = 2, kFpU = 3, kFpDL = 5, kFpDR = 7, kFpL = 9, kFpR = 10, kFpAct = 11, kFpN = 12 };
+
 // per-cell record (double): state of the Shakhov source, the micro LU-SGS
 // diagonal base 1/dt' + 1/dt + 1/(2 tau) and, per slot s, the face
 // coefficients (A, B, C) with S/(2|Omega|) * w.n_out = A vx + B vy - C
@@ -77,6 +86,10 @@ struct Dev {
   const void* finf_h;   // [nv] storage type
   const void* finf_b;
   const double* mgeo;   // [ncell][12] per slot (A, B, C) of the micro sweep
+  // packed per-cell and per-face tables of the march kernels (layouts
+  // kCp* and kFp* below), rebuilt with the geometry and the cell kinds
+  const double* cplan;  // [ncell][kCpN]
+  const double* fplan;  // [nface][kFpN]
   // launch shapes (read by the host launchers only; results do not depend
   // on them): widest velocity chunk of the micro sweep, core rows per
   // workgroup of the face-equilibrium and flux march kernels

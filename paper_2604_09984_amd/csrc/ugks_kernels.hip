@@ -578,18 +578,28 @@ __device__ __forceinline__ Side<C> side_ghost(const Dev& g, const LD6<C>& L, int
   return S;
 }
 
+// lane-held tables: lane l of a wavefront holds entry l of a record; a
+// wave-uniform entry is read back with two lane reads
+__device__ __forceinline__ double rec_at(double v, int l) { return lane_read(v, l); }
+__device__ __forceinline__ int rec_int(double v, int l) { return (int)lane_read(v, l); }
+
+// one staged face: its record (NREC entries) then its packed geometry
+constexpr int kStg = NREC + kFpN;
+
 template <int RG, class T, class C, int MODE>
 __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __restrict__ binfo, int nchunk,
                                                          const T* __restrict__ h, const T* __restrict__ b,
-                                                         const double* __restrict__ W,
                                                          const double* __restrict__ rec,
                                                          double* __restrict__ part, T* __restrict__ Dh,
                                                          T* __restrict__ Db) {
-  // reconstruction of three columns (x - 1, x, x + 1 in flight), raw values
-  // of one column per row for the j-neighbours, j-face fluxes of two columns
-  __shared__ LD6<C> lds[3][RG + 2][64];
-  __shared__ C pub[2][RG + 2][2][64];
-  __shared__ C jfl[2][RG + 2][2][64];
+  constexpr int NW = RG + 2;
+  // reconstructions of three columns, raw values of one column per row for
+  // the j-neighbours, j-face fluxes of two columns (flux pass), the face
+  // records of two columns (staged one column ahead)
+  __shared__ LD6<C> lds[3][NW][64];
+  __shared__ C pub[2][NW][2][64];
+  __shared__ C jfl[(MODE == 1) ? 2 : 1][NW][2][64];
+  __shared__ double stg[2][NW][2][kStg];
   const int* bi = binfo + 8 * blockIdx.z;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], per_i = bi[3], per_j = bi[4];
   const int j0 = blockIdx.y * RG;
@@ -613,12 +623,6 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     while (j >= nj) j -= nj;
     return j;
   };
-  // this wavefront's row (periodic wrap for the halo rows) and, for the two
-  // halo wavefronts, the row beyond it
-  const int jr = wrap_row(j0 - 1 + w);
-  const int jo = (jr < 0) ? -1 : (w == 0) ? wrap_row(j0 - 2) : (w == RG + 1) ? wrap_row(j0 + RG + 1) : -1;
-  const bool core = (w >= 1) && (w <= RG) && (j0 - 1 + w < nj);
-  auto cell = [&](int x, int j) -> int { return c0 + x + ni * j; };
   auto col = [&](int x) -> int {  // column in the block, or -1
     if (x >= 0 && x < ni) return x;
     if (!per_i) return -1;
@@ -626,6 +630,16 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     while (x >= ni) x -= ni;
     return x;
   };
+  // this wavefront's row (periodic wrap for the halo rows), the row beyond
+  // it for the two halo wavefronts, the row above (for the j-face of a
+  // wavefront whose own row is outside the block)
+  const int jr = wrap_row(j0 - 1 + w);
+  const int jo = (jr < 0) ? -1 : (w == 0) ? wrap_row(j0 - 2) : (w == RG + 1) ? wrap_row(j0 + RG + 1) : -1;
+  const int jh = wrap_row(j0 + w);
+  const bool core = (w >= 1) && (w <= RG) && (j0 - 1 + w < nj);
+  const bool jface = (w <= RG) && (j0 - 1 + w < nj);  // evaluates the j-face above its row
+  const int prow = (jr >= 0) ? jr : jh;              // row of the packed cell records it reads
+  auto cell = [&](int x, int j) -> int { return c0 + x + ni * j; };
   auto raw = [&](int row, int x, C& vh, C& vb) {
     const int xw = col(x);
     if (row < 0 || xw < 0) { vh = C(0); vb = C(0); return; }
@@ -634,20 +648,49 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     vb = (C)b[o];
   };
   auto slot = [](int x) -> int { return (x + 6) % 3; };  // x >= -6, constant divisor
+  // packed cell record of column x of row prow (lane l: entry l), zeros
+  // outside the block
+  auto cplan_load = [&](int x) -> double {
+    const int xw = col(x);
+    if (prow < 0 || xw < 0) return (lane == kCpType) ? 0.0 : -1.0;
+    return (lane < kCpN) ? g.cplan[(size_t)cell(xw, prow) * kCpN + lane] : 0.0;
+  };
+  // the two faces of column x from the cell records of columns x (and 0 for
+  // the seam face x = -1): i-face (x|x+1) of a core row, j-face above (x, jr)
+  auto face_ids = [&](int x, double cpx, double cp0, int& fi, int& fj) {
+    fi = -1; fj = -1;
+    if (core && jr >= 0 && x >= -1 && x < ni)
+      fi = (x >= 0) ? rec_int(cpx, kCpFace + 1) : rec_int(cp0, kCpFace + 0);
+    if (jface && x >= 0 && x < ni) fj = (jr >= 0) ? rec_int(cpx, kCpFace + 3) : rec_int(cpx, kCpFace + 2);
+  };
+  // lane l: entry l of the staged record of face f (record, then geometry)
+  auto face_load = [&](int f) -> double {
+    if (f < 0 || lane >= kStg) return 0.0;
+    return (lane < NREC) ? rec[(size_t)f * NREC + lane] : g.fplan[(size_t)f * kFpN + (lane - NREC)];
+  };
+  // side data at a face from the reconstruction of a cell and the offset
+  // from its centroid to the face centre
+  auto side_at = [](const LD6<C>& L, double dx, double dy) -> Side<C> {
+    Side<C> S;
+    S.hv = L.hv + L.hx * (C)dx + L.hy * (C)dy;
+    S.bv = L.bv + L.bx * (C)dx + L.by * (C)dy;
+    S.hx = L.hx; S.hy = L.hy; S.bx = L.bx; S.by = L.by;
+    return S;
+  };
   // raw values of this row: window (x, x+1, x+2) and the next column in
   // flight; the outer row of a halo wavefront at x+1 and x+2
   C a0h, a0b, a1h, a1b, a2h, a2b, p_h, p_b, oc_h, oc_b, on_h, on_b;
   // reconstruction of column x + 1 (window centre) into LDS
-  auto recon = [&](int x1) {
+  auto recon = [&](int x1, double cp) {
     if (jr < 0) return;
-    const int xw = col(x1);
-    if (xw < 0) return;
-    const int c = __builtin_amdgcn_readfirstlane(cell(xw, jr));
-    if (g.type[c] == 0) return;
+    if (col(x1) < 0) return;
+    if (rec_int(cp, kCpType) == 0) return;
     int nbc[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) nbc[q] = g.nb[4 * c + q];
-    const double* G = g.G + 4 * c;
+    for (int q = 0; q < 4; ++q) nbc[q] = rec_int(cp, kCpNb + q);
+    double G[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) G[q] = rec_at(cp, kCpG + q);
     const int pp = x1 & 1;
     auto nbv = [&](int code, C cellv, C finv, C self) -> C {
       return (code >= 0) ? cellv : ((code == kNbFar) ? finv : self);
@@ -684,11 +727,10 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   };
   // upwind interface data of a face between sides sl (low) and sh (high)
   // with normal (nx, ny) and mesh velocity (ux, uy)
-  auto face_eval = [&](int f, const Side<C>& sl, const Side<C>& sh, double* facc, double* mom) -> void {
-    const double* fg = g.fgeo + (size_t)f * 8;
-    const double nx = fg[0], ny = fg[1], ux = fg[3], uy = fg[4];
+  auto face_eval = [&](const double* r, const Side<C>& sl, const Side<C>& sh, double* facc, double* mom) -> void {
+    const double* fp = r + NREC;
+    const double nx = fp[kFpN0], ny = fp[kFpN0 + 1], ux = fp[kFpU], uy = fp[kFpU + 1];
     const double wn = exact_wn(vx, vy, ux, uy, nx, ny);
-    const double* r = rec + (size_t)f * NREC;
     if (MODE == 0) {
       // moments of the upwind data about the mean velocity of the sides
       const double sx = r[R_SX], sy = r[R_SY];
@@ -718,12 +760,12 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   };
   // wall face seen from the interior cell c (slot s) with data L: MODE 0
   // gives the numerator and denominator of the wall density (Eq. rhow)
-  auto wall_eval = [&](int f, int c, int s, const LD6<C>& L, double* facc, double* mom) -> void {
-    const double* fg = g.fgeo + (size_t)f * 8;
-    const double* r = rec + (size_t)f * NREC;
+  auto wall_eval = [&](const double* r, bool low, const LD6<C>& L, double* facc, double* mom) -> void {
+    const double* fp = r + NREC;
     const double sg = r[R_SGN];
+    const double fg[5] = {fp[kFpN0], fp[kFpN0 + 1], fp[kFpS], fp[kFpU], fp[kFpU + 1]};
     const double wn = exact_wn(vx, vy, fg[3], fg[4], sg * fg[0], sg * fg[1]);
-    Side<C> S = side_from_cell<T, C>(g, L, c, s);
+    const Side<C> S = side_at(L, low ? fp[kFpDL] : fp[kFpDR], low ? fp[kFpDL + 1] : fp[kFpDR + 1]);
     FaceEq<C> e;
     e.load(r);
     C Ih, Ib;
@@ -781,7 +823,9 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   };
   // march: step x reconstructs column x + 1, then evaluates the faces of
   // column x (i-face (x|x+1), j-face above x) and, in flux mode, gathers the
-  // divergence of column x - 1 from the faces of the previous step
+  // divergence of column x - 1 from the faces of the previous step.  Ahead
+  // of use, in registers: raw values (two columns), packed cell records
+  // (three columns), face records (two columns, then staged in LDS).
   raw(jr, -2, a0h, a0b);
   raw(jr, -1, a1h, a1b);
   raw(jr, 0, a2h, a2b);
@@ -790,21 +834,30 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   raw(jo, 0, on_h, on_b);
   pub[1][w][0][lane] = a1h;  // column -1
   pub[1][w][1][lane] = a1b;
+  // cell records of columns -3 .. 1 and 0
+  double cpm1 = cplan_load(-3), cp0c = cplan_load(-2), cp1 = cplan_load(-1), cp2 = cplan_load(0),
+         cp3 = cplan_load(1);
+  const double cpz = cplan_load(0);
+  // face records of column -1 in registers (staged during the first step)
+  double fn_i, fn_j;
+  {
+    int fi, fj;
+    face_ids(-1, cp1, cpz, fi, fj);
+    fn_i = face_load(fi);
+    fn_j = face_load(fj);
+  }
   lds_barrier();
   double fi_m2[2] = {0.0, 0.0}, fi_m1[2] = {0.0, 0.0}, fj_m1[2] = {0.0, 0.0};
-  auto divergence = [&](int x) {
+  auto divergence = [&](int x, double cp) {
     // divergence of cell (x, jr) of a core row from the i-faces (x-1|x) and
     // (x|x+1), the j-face above (this row) and below (the row beneath)
     if (!(core && jr >= 0 && x >= 0 && kin)) return;
     const int c = cell(x, jr);
     double dh = 0.0, db = 0.0;
-    if (g.type[c] == 1) {
-      const double ivol = 1.0 / g.vol[c];
-      const int f0 = g.cf[4 * c], f1 = g.cf[4 * c + 1], f2 = g.cf[4 * c + 2], f3 = g.cf[4 * c + 3];
-      const double S0 = (f0 >= 0) ? g.fgeo[(size_t)f0 * 8 + 2] : 0.0;
-      const double S1 = (f1 >= 0) ? g.fgeo[(size_t)f1 * 8 + 2] : 0.0;
-      const double S2 = (f2 >= 0) ? g.fgeo[(size_t)f2 * 8 + 2] : 0.0;
-      const double S3 = (f3 >= 0) ? g.fgeo[(size_t)f3 * 8 + 2] : 0.0;
+    if (rec_int(cp, kCpType) == 1) {
+      const double ivol = rec_at(cp, kCpIvol);
+      const double S0 = rec_at(cp, kCpS), S1 = rec_at(cp, kCpS + 1), S2 = rec_at(cp, kCpS + 2),
+                   S3 = rec_at(cp, kCpS + 3);
       const double bh = (double)jfl[x & 1][w - 1][0][lane], bb = (double)jfl[x & 1][w - 1][1][lane];
       dh = -ivol * (-S0 * fi_m2[0] + S1 * fi_m1[0] - S2 * bh + S3 * fj_m1[0]);
       db = -ivol * (-S0 * fi_m2[1] + S1 * fi_m1[1] - S2 * bb + S3 * fj_m1[1]);
@@ -813,7 +866,9 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     Db[(size_t)c * g.nv + k] = (T)db;
   };
   for (int x = -2; x < ni; ++x) {
-    recon(x + 1);
+    // registers: cell records cpm1 .. cp3 of columns x-1 .. x+3 (cp3 in
+    // flight); face records fn of column x + 1
+    recon(x + 1, cp1);
     // publish column x + 2 of this row, advance the windows
     pub[x & 1][w][0][lane] = a2h;
     pub[x & 1][w][1][lane] = a2b;
@@ -821,93 +876,98 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     raw(jr, x + 4, p_h, p_b);
     oc_h = on_h; oc_b = on_b;
     raw(jo, x + 3, on_h, on_b);
+    // face records of column x + 2 (ids from the record of column x + 2)
+    int fi2, fj2;
+    face_ids(x + 2, cp2, cpz, fi2, fj2);
+    const double f2_i = face_load(fi2), f2_j = face_load(fj2);
+    const double cdiv = cpm1;  // column x - 1
+    const double cfac = cp0c;  // column x
+    cpm1 = cp0c; cp0c = cp1; cp1 = cp2; cp2 = cp3;
+    cp3 = cplan_load(x + 4);
     lds_barrier();
+    // stage the face records of column x + 1 (the buffer was last read at
+    // column x - 1, before this barrier)
+    if (lane < kStg) { stg[(x + 1) & 1][w][0][lane] = fn_i; stg[(x + 1) & 1][w][1][lane] = fn_j; }
+    fn_i = f2_i; fn_j = f2_j;
     if (MODE == 1) {
-      divergence(x - 1);
+      divergence(x - 1, cdiv);
       fi_m2[0] = fi_m1[0]; fi_m2[1] = fi_m1[1];
     }
-    if (x < -1) continue;
-    const int sx0 = slot(x), sx1 = slot(x + 1);
-    double fi_cur[2] = {0.0, 0.0}, fj_cur[2] = {0.0, 0.0};
-    constexpr int NM = (MODE == 0) ? kMomP : kFluxP;
-    double mi[NM], mj[NM];
+    if (x >= -1) {
+      const int sx0 = slot(x), sx1 = slot(x + 1);
+      double fi_cur[2] = {0.0, 0.0}, fj_cur[2] = {0.0, 0.0};
+      constexpr int NM = (MODE == 0) ? kMomP : kFluxP;
+      double mi[NM], mj[NM];
 #pragma unroll
-    for (int q = 0; q < NM; ++q) { mi[q] = 0.0; mj[q] = 0.0; }
-    int fiw = -1, fjw = -1;
-    // the two faces of this column: q = 0 the i-face (x|x+1) of a core row,
-    // q = 1 the j-face above (x, jr) for the bottom halo and core rows
-    auto face_q = [&](int q) {
-      int f = -1;
-      bool owner = false;
-      if (q == 0) {
-        if (!(core && jr >= 0)) return;
-        const int cl = (x >= 0) ? cell(x, jr) : -1;
-        const int cr = (x + 1 < ni) ? cell(x + 1, jr) : -1;
-        f = (cl >= 0) ? g.cf[4 * cl + 1] : g.cf[4 * cr + 0];
-      } else {
-        if (!(x >= 0 && w <= RG && (j0 - 1 + w < nj))) return;
-        const int jh = wrap_row(j0 + w);  // high row (the low row jr may be absent: boundary below)
-        if (jr >= 0) f = g.cf[4 * cell(x, jr) + 3];
-        if (f < 0 && jh >= 0) f = g.cf[4 * cell(x, jh) + 2];
-      }
-      if (f < 0 || !g.fact[f]) return;
-      const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
-      // owner: the low cell, or the cell of a boundary face; a periodic seam
-      // i-face (x = -1) is written by the high end of the row; the bottom
-      // halo writes only the block's lower boundary j-face
-      owner = ((q == 0) ? (x >= 0) : (w >= 1)) || (L < 0);
-      const LD6<C>& lo = lds[sx0][w][lane];
-      const LD6<C>& hi = (q == 0) ? lds[sx1][w][lane] : lds[sx0][w + 1][lane];
-      double fc[2] = {0.0, 0.0}, mom[NM];
+      for (int q = 0; q < NM; ++q) { mi[q] = 0.0; mj[q] = 0.0; }
+      int fiw = -1, fjw = -1;
+      int fid[2];
+      face_ids(x, cfac, cpz, fid[0], fid[1]);
+      // the two faces of this column: q = 0 the i-face (x|x+1) of a core
+      // row, q = 1 the j-face above (x, jr) for the bottom halo and core rows
+      auto face_q = [&](int q) {
+        const int f = (q == 0) ? fid[0] : fid[1];
+        if (f < 0) return;
+        const double* r = &stg[x & 1][w][q][0];
+        const double* fp = r + NREC;
+        if (__builtin_amdgcn_readfirstlane((int)fp[kFpAct]) == 0) return;
+        const int L = __builtin_amdgcn_readfirstlane((int)fp[kFpL]);
+        const int R = __builtin_amdgcn_readfirstlane((int)fp[kFpR]);
+        // owner: the low cell, or the cell of a boundary face; a periodic
+        // seam i-face (x = -1) is written by the high end of the row; the
+        // bottom halo writes only the block's lower boundary j-face
+        const bool owner = ((q == 0) ? (x >= 0) : (w >= 1)) || (L < 0);
+        const LD6<C>& lo = lds[sx0][w][lane];
+        const LD6<C>& hi = (q == 0) ? lds[sx1][w][lane] : lds[sx0][w + 1][lane];
+        double fc[2] = {0.0, 0.0}, mom[NM];
 #pragma unroll
-      for (int m = 0; m < NM; ++m) mom[m] = 0.0;
-      if (L == kNbWall || R == kNbWall) {
-        const int c = (L == kNbWall) ? R : L;
-        const int sd = (q == 0) ? ((L == kNbWall) ? 0 : 1) : ((L == kNbWall) ? 2 : 3);
-        wall_eval(f, c, sd, (L == kNbWall) ? hi : lo, fc, mom);
-      } else {
-        // the low side of the seam face (x = -1) is cell ni-1, staged as column -1
-        const Side<C> sl = (L >= 0) ? side_from_cell<T, C>(g, lo, L, (q == 0) ? 1 : 3) : ghost(hi, L);
-        const Side<C> sh = (R >= 0) ? side_from_cell<T, C>(g, hi, R, (q == 0) ? 0 : 2) : ghost(lo, R);
-        face_eval(f, sl, sh, fc, mom);
-      }
-      if (MODE == 1) write_flux(owner ? f : -1, mom);
-      if (q == 0) {
-        fi_cur[0] = fc[0]; fi_cur[1] = fc[1];
-        if (owner) fiw = f;
-        if (MODE == 0) {
-#pragma unroll
-          for (int m = 0; m < NM; ++m) mi[m] = mom[m];
+        for (int m = 0; m < NM; ++m) mom[m] = 0.0;
+        if (L == kNbWall || R == kNbWall) {
+          wall_eval(r, L != kNbWall, (L == kNbWall) ? hi : lo, fc, mom);
+        } else {
+          // the low side of the seam face (x = -1) is cell ni-1, staged as column -1
+          const Side<C> sl = (L >= 0) ? side_at(lo, fp[kFpDL], fp[kFpDL + 1]) : ghost(hi, L);
+          const Side<C> sh = (R >= 0) ? side_at(hi, fp[kFpDR], fp[kFpDR + 1]) : ghost(lo, R);
+          face_eval(r, sl, sh, fc, mom);
         }
-      } else {
-        fj_cur[0] = fc[0]; fj_cur[1] = fc[1];
-        if (owner) fjw = f;
-        if (MODE == 0) {
+        if (MODE == 1) write_flux(owner ? f : -1, mom);
+        if (q == 0) {
+          fi_cur[0] = fc[0]; fi_cur[1] = fc[1];
+          if (owner) fiw = f;
+          if (MODE == 0) {
 #pragma unroll
-          for (int m = 0; m < NM; ++m) mj[m] = mom[m];
+            for (int m = 0; m < NM; ++m) mi[m] = mom[m];
+          }
+        } else {
+          fj_cur[0] = fc[0]; fj_cur[1] = fc[1];
+          if (owner) fjw = f;
+          if (MODE == 0) {
+#pragma unroll
+            for (int m = 0; m < NM; ++m) mj[m] = mom[m];
+          }
         }
-      }
-    };
-    if constexpr (MODE == 0) {
-      face_q(0);
-      face_q(1);
-    } else {
-      // one evaluation path for both faces (not unrolled), so that only one
-      // face's data is live: the flux pass is register bound
+      };
+      if constexpr (MODE == 0) {
+        face_q(0);
+        face_q(1);
+      } else {
+        // one evaluation path for both faces (not unrolled), so that only one
+        // face's data is live: the flux pass is register bound
 #pragma clang loop unroll(disable)
-      for (int q = 0; q < 2; ++q) face_q(q);
+        for (int q = 0; q < 2; ++q) face_q(q);
+      }
+      if (MODE == 1 && x >= 0 && jface) {
+        jfl[x & 1][w][0][lane] = (C)fj_cur[0];
+        jfl[x & 1][w][1][lane] = (C)fj_cur[1];
+      }
+      if (MODE == 0) write_partials(fiw, mi, fjw, mj);
+      fi_m1[0] = fi_cur[0]; fi_m1[1] = fi_cur[1];
+      fj_m1[0] = fj_cur[0]; fj_m1[1] = fj_cur[1];
     }
-    if (MODE == 1 && x >= 0 && w <= RG && (j0 - 1 + w < nj)) {
-      jfl[x & 1][w][0][lane] = (C)fj_cur[0];
-      jfl[x & 1][w][1][lane] = (C)fj_cur[1];
-    }
-    if (MODE == 0) write_partials(fiw, mi, fjw, mj);
-    fi_m1[0] = fi_cur[0]; fi_m1[1] = fi_cur[1];
-    fj_m1[0] = fj_cur[0]; fj_m1[1] = fj_cur[1];
   }
   if (MODE == 1) {
     lds_barrier();
-    divergence(ni - 1);
+    divergence(ni - 1, cpm1);
   }
 }
 
@@ -1767,8 +1827,9 @@ template <int RG, class T, class C, int MODE>
 static void march_pass(const Dev& g, const int* binfo, int max_nj, int nchunk, const void* h, const void* b,
                        const double* W, const double* rec, double* part, void* Dh, void* Db, hipStream_t st) {
   dim3 grid((unsigned)nchunk, (unsigned)((max_nj + RG - 1) / RG), (unsigned)g.nblock);
-  k_march<RG, T, C, MODE><<<grid, 64 * (RG + 2), 0, st>>>(g, binfo, nchunk, (const T*)h, (const T*)b, W, rec,
-                                                          part, (T*)Dh, (T*)Db);
+  (void)W;
+  k_march<RG, T, C, MODE><<<grid, 64 * (RG + 2), 0, st>>>(g, binfo, nchunk, (const T*)h, (const T*)b, rec, part,
+                                                          (T*)Dh, (T*)Db);
 }
 
 template <class T, class C, int MODE>
