@@ -20,9 +20,9 @@
 /* ------------------------------------------------------------------------ */
 typedef struct {
   int ni, nj, bc[4];
-  double rtw[4], vwx[4], vwy[4], xc0, yc0;
-  double *x0, *y0;          /* reference nodes */
-  double dx, dy, th, ux, uy, om;
+  real rtw[4], vwx[4], vwy[4], xc0, yc0;
+  real *x0, *y0;          /* reference nodes */
+  real dx, dy, th, ux, uy, om;
   int cell0;
 } blk_t;
 
@@ -40,30 +40,30 @@ typedef struct {
   int gkind, gcell;  /* ghost side: NB_FF or NB_COPY (gcell = copied cell) */
   int blk, side;     /* boundary side id for ghost / wall faces */
   int dir;           /* 0: i-face, 1: j-face */
-  double nx, ny, S, xf, yf, ux, uy;
-  double rtw, vwx, vwy;  /* wall temperature and wall velocity (lab frame) */
+  real nx, ny, S, xf, yf, ux, uy;
+  real rtw, vwx, vwy;  /* wall temperature and wall velocity (lab frame) */
 } face_t;
 
 struct or_case {
   int dim, nxi, nw;
-  double pr, omega, mu_ref, rt_ref, cfl_s, cfl_p;
+  real pr, omega, mu_ref, rt_ref, cfl_s, cfl_p;
   int nvx, nvy, nv;
-  double vx0, vx1, vy0, vy1;
-  double *vk_x, *vk_y, *wk;  /* per k */
-  double winf[4];
-  double *finf_h, *finf_b;   /* far-field Maxwellian per k */
+  real vx0, vx1, vy0, vy1;
+  real *vk_x, *vk_y, *wk;  /* per k */
+  real winf[4];
+  real *finf_h, *finf_b;   /* far-field Maxwellian per k */
   int nblock; blk_t* blk;
   int ncell;
   int8_t* type;
   int* cblk; int* ci; int* cj;
-  double *xn, *yn;           /* current nodes, per block concatenated */
+  real *xn, *yn;           /* current nodes, per block concatenated */
   int* node0;
-  double *cx, *cy, *vol, *g; /* g: J^{-T}, 4 per cell */
-  double* cdx;               /* [ncell][4][2] face centre (cell's own nodes) - centroid */
+  real *cx, *cy, *vol, *g; /* g: J^{-T}, 4 per cell */
+  real* cdx;               /* [ncell][4][2] face centre (cell's own nodes) - centroid */
   int nface; face_t* face;
   int* cface;                /* [ncell][4] face ids (-1 none): i-low, i-high, j-low, j-high */
   int* csign;                /* [ncell][4] +1 if the face normal points out of the cell */
-  int nrec; int *rec, *dptr, *don; double* dw;
+  int nrec; int *rec, *dptr, *don; real* dw;
   int nref;                  /* refill entries appended after the receptors */
 };
 
@@ -87,23 +87,23 @@ int or_nv(const or_case* c) { return c->nv; }
  * Every rule but n = 6 is mirror symmetric, so a resting Maxwellian keeps
  * zero odd moments.
  */
-static void add_simpson(double* w, int i0, int m, double h) {
+static void add_simpson(real* w, int i0, int m, real h) {
   for (int p = 0; p < m; p += 2) {
     w[i0 + p] += h / 3.0;
     w[i0 + p + 1] += 4.0 * h / 3.0;
     w[i0 + p + 2] += h / 3.0;
   }
 }
-static void add_38(double* w, int i0, double h) {
+static void add_38(real* w, int i0, real h) {
   w[i0] += 3.0 * h / 8.0;
   w[i0 + 1] += 9.0 * h / 8.0;
   w[i0 + 2] += 9.0 * h / 8.0;
   w[i0 + 3] += 3.0 * h / 8.0;
 }
-void or_nc_weights(int n, double a, double b, double* w) {
+void or_nc_weights(int n, real a, real b, real* w) {
   for (int i = 0; i < n; i++) w[i] = 0.0;
   if (n == 1) { w[0] = 1.0; return; }
-  double h = (b - a) / (n - 1);
+  real h = (b - a) / (n - 1);
   int m = n - 1;
   if (n == 2) { w[0] = w[1] = h / 2.0; return; }
   if (m % 4 == 0) {
@@ -138,43 +138,43 @@ void or_nc_weights(int n, double a, double b, double* w) {
 /* kinetic model, Sec. 2.1                                                   */
 /* ------------------------------------------------------------------------ */
 /* lambda = 1/(2RT) from W: rho E = rho|U|^2/2 + (D+N_xi) rho/(4 lambda) */
-static void prim(const or_case* c, const double* W, double* rho, double* u, double* lam) {
+static void prim(const or_case* c, const real* W, real* rho, real* u, real* lam) {
   int d = c->dim;
   *rho = W[0];
-  double ke = 0.0;
+  real ke = 0.0;
   for (int i = 0; i < d; i++) { u[i] = W[1 + i] / W[0]; ke += u[i] * u[i]; }
   for (int i = d; i < 2; i++) u[i] = 0.0;
-  double e = W[d + 1] - 0.5 * W[0] * ke;
-  *lam = (double)(d + c->nxi) * W[0] / (4.0 * e);
+  real e = W[d + 1] - 0.5 * W[0] * ke;
+  *lam = (real)(d + c->nxi) * W[0] / (4.0 * e);
 }
 
 /* positive density and internal energy */
-static int physical(const or_case* c, const double* W) {
+static int physical(const or_case* c, const real* W) {
   int d = c->dim;
   if (!(W[0] > 0.0)) return 0;
-  double ke = 0.0;
+  real ke = 0.0;
   for (int i = 0; i < d; i++) ke += W[1 + i] * W[1 + i];
-  double e = W[d + 1] - 0.5 * ke / W[0];
+  real e = W[d + 1] - 0.5 * ke / W[0];
   return e > 0.0;
 }
 
 /* collision time tau = mu/p, mu = mu_ref (RT/RT_ref)^omega; 1/tau returned */
-static double inv_tau(const or_case* c, double rho, double lam) {
+static real inv_tau(const or_case* c, real rho, real lam) {
   if (c->mu_ref <= 0.0) return 0.0;
-  double rt = 1.0 / (2.0 * lam);
-  double mu = c->mu_ref * pow(rt / c->rt_ref, c->omega);
-  double p = rho * rt;
+  real rt = 1.0 / (2.0 * lam);
+  real mu = c->mu_ref * pow(rt / c->rt_ref, c->omega);
+  real p = rho * rt;
   return p / mu;
 }
 
 /* reduced Maxwellian H = rho (lam/pi)^{D/2} exp(-lam |v-U|^2), B = N_xi/(2 lam) H */
-static void maxw(const or_case* c, double rho, const double* u, double lam,
-                 double vx, double vy, double* H, double* B) {
-  double cx = vx - u[0], cy = (c->dim == 2) ? vy - u[1] : 0.0;
-  double nrm = rho * pow(lam / PI, 0.5 * c->dim);
-  double e = nrm * exp(-lam * (cx * cx + cy * cy));
+static void maxw(const or_case* c, real rho, const real* u, real lam,
+                 real vx, real vy, real* H, real* B) {
+  real cx = vx - u[0], cy = (c->dim == 2) ? vy - u[1] : 0.0;
+  real nrm = rho * pow(lam / PI, 0.5 * c->dim);
+  real e = nrm * exp(-lam * (cx * cx + cy * cy));
   *H = e;
-  *B = (double)c->nxi / (2.0 * lam) * e;
+  *B = (real)c->nxi / (2.0 * lam) * e;
 }
 
 /*
@@ -183,16 +183,16 @@ static void maxw(const or_case* c, double rho, const double* u, double lam,
  *   H+ = 4(1-Pr) lam^2/(5 rho) (c.q) (2 lam c^2 - 2 - D) H
  *   B+ = 4(1-Pr) lam^2/(5 rho) (c.q) (2 lam c^2 - D) N_xi H/(2 lam)
  */
-void or_shakhov(int dim, double pr, double rho, const double* u, double lam,
-                const double* q, const double* v, double* hp, double* bp) {
+void or_shakhov(int dim, real pr, real rho, const real* u, real lam,
+                const real* q, const real* v, real* hp, real* bp) {
   int nxi = 3 - dim;
-  double cx = v[0] - u[0], cy = (dim == 2) ? v[1] - u[1] : 0.0;
-  double c2 = cx * cx + cy * cy;
-  double cq = cx * q[0] + ((dim == 2) ? cy * q[1] : 0.0);
-  double H = rho * pow(lam / PI, 0.5 * dim) * exp(-lam * c2);
-  double s = 4.0 * (1.0 - pr) * lam * lam / (5.0 * rho) * cq;
+  real cx = v[0] - u[0], cy = (dim == 2) ? v[1] - u[1] : 0.0;
+  real c2 = cx * cx + cy * cy;
+  real cq = cx * q[0] + ((dim == 2) ? cy * q[1] : 0.0);
+  real H = rho * pow(lam / PI, 0.5 * dim) * exp(-lam * c2);
+  real s = 4.0 * (1.0 - pr) * lam * lam / (5.0 * rho) * cq;
   *hp = s * (2.0 * lam * c2 - 2.0 - dim) * H;
-  *bp = s * (2.0 * lam * c2 - dim) * (double)nxi * H / (2.0 * lam);
+  *bp = s * (2.0 * lam * c2 - dim) * (real)nxi * H / (2.0 * lam);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -200,7 +200,7 @@ void or_shakhov(int dim, double pr, double rho, const double* u, double lam,
 /* (Sec. 2.1: f+ ~ g0 + g0+ + x.grad g0 + t dg0/dt; grad g0 = g0 (a.psi),     */
 /*  dg0/dt = g0 (A.psi), with psi = (1, v, (v^2 + xi^2)/2))                   */
 /* ------------------------------------------------------------------------ */
-typedef struct { int n; double c[8]; int px[8], py[8], r[8]; } poly;
+typedef struct { int n; real c[8]; int px[8], py[8], r[8]; } poly;
 
 static poly psi_poly(int dim, int a) {
   poly p; p.n = 0;
@@ -216,10 +216,10 @@ static poly psi_poly(int dim, int a) {
 }
 
 /* <psi_a * v_dir^e * psi_b> under the normalised Maxwellian (rho = 1) */
-static double gmom(int dim, const double* mx, const double* my, const double* mxi,
+static real gmom(int dim, const real* mx, const real* my, const real* mxi,
                    int a, int b, int dir, int e) {
   poly pa = psi_poly(dim, a), pb = psi_poly(dim, b);
-  double s = 0.0;
+  real s = 0.0;
   for (int i = 0; i < pa.n; i++)
     for (int j = 0; j < pb.n; j++) {
       int px = pa.px[i] + pb.px[j] + ((dir == 0) ? e : 0);
@@ -231,30 +231,30 @@ static double gmom(int dim, const double* mx, const double* my, const double* mx
 }
 
 /* raw moments of a 1D Gaussian with mean u and variance 1/(2 lam) */
-static void gauss1(double u, double lam, int nmax, double* m) {
+static void gauss1(real u, real lam, int nmax, real* m) {
   m[0] = 1.0;
   m[1] = u;
-  for (int n = 1; n < nmax; n++) m[n + 1] = u * m[n] + (double)n / (2.0 * lam) * m[n - 1];
+  for (int n = 1; n < nmax; n++) m[n + 1] = u * m[n] + (real)n / (2.0 * lam) * m[n - 1];
 }
 
 /* plain Gaussian elimination with partial pivoting, n <= 4 */
-static void solve(int n, double* M, double* x) {
+static void solve(int n, real* M, real* x) {
   for (int k = 0; k < n; k++) {
     int p = k;
     for (int i = k + 1; i < n; i++)
       if (fabs(M[i * n + k]) > fabs(M[p * n + k])) p = i;
     if (p != k) {
-      for (int j = 0; j < n; j++) { double t = M[k * n + j]; M[k * n + j] = M[p * n + j]; M[p * n + j] = t; }
-      double t = x[k]; x[k] = x[p]; x[p] = t;
+      for (int j = 0; j < n; j++) { real t = M[k * n + j]; M[k * n + j] = M[p * n + j]; M[p * n + j] = t; }
+      real t = x[k]; x[k] = x[p]; x[p] = t;
     }
     for (int i = k + 1; i < n; i++) {
-      double f = M[i * n + k] / M[k * n + k];
+      real f = M[i * n + k] / M[k * n + k];
       for (int j = k; j < n; j++) M[i * n + j] -= f * M[k * n + j];
       x[i] -= f * x[k];
     }
   }
   for (int i = n - 1; i >= 0; i--) {
-    double s = x[i];
+    real s = x[i];
     for (int j = i + 1; j < n; j++) s -= M[i * n + j] * x[j];
     x[i] = s / M[i * n + i];
   }
@@ -267,46 +267,46 @@ static void solve(int n, double* M, double* x) {
  * w = v - U_f of the moving face (Eq. BGK: w = v - U).  Moments are the
  * analytic Gaussian ones.  dW is [dim][nw], a is [dim][nw].
  */
-void or_slope_coeffs(int dim, double rho, const double* u, double lam,
-                     const double* uf, const double* dW, double* a, double* A) {
+void or_slope_coeffs(int dim, real rho, const real* u, real lam,
+                     const real* uf, const real* dW, real* a, real* A) {
   int nw = dim + 2, nxi = 3 - dim;
-  double mx[8], my[8], mxi[3];
+  real mx[8], my[8], mxi[3];
   gauss1(u[0], lam, 7, mx);
   if (dim == 2) gauss1(u[1], lam, 7, my);
   else { for (int i = 0; i < 8; i++) my[i] = (i == 0) ? 1.0 : 0.0; }
   mxi[0] = 1.0;
-  mxi[1] = (double)nxi / (2.0 * lam);
-  mxi[2] = (double)nxi * (nxi + 2) / (4.0 * lam * lam);
-  double M[16], Mc[16], rhs[4];
+  mxi[1] = (real)nxi / (2.0 * lam);
+  mxi[2] = (real)nxi * (nxi + 2) / (4.0 * lam * lam);
+  real M[16], Mc[16], rhs[4];
   for (int i = 0; i < nw; i++)
     for (int j = 0; j < nw; j++) M[i * nw + j] = gmom(dim, mx, my, mxi, i, j, 0, 0);
-  double b[4] = {0, 0, 0, 0};
+  real b[4] = {0, 0, 0, 0};
   for (int d = 0; d < dim; d++) {
-    memcpy(Mc, M, sizeof(double) * nw * nw);
+    memcpy(Mc, M, sizeof(real) * nw * nw);
     for (int i = 0; i < nw; i++) rhs[i] = dW[d * nw + i] / rho;
     solve(nw, Mc, rhs);
     for (int i = 0; i < nw; i++) a[d * nw + i] = rhs[i];
     /* b -= <psi w_d (a_d.psi)> with w_d = v_d - uf_d */
     for (int i = 0; i < nw; i++) {
-      double s = 0.0;
+      real s = 0.0;
       for (int j = 0; j < nw; j++)
         s += (gmom(dim, mx, my, mxi, i, j, d, 1) - uf[d] * M[i * nw + j]) * a[d * nw + j];
       b[i] -= s;
     }
   }
-  memcpy(Mc, M, sizeof(double) * nw * nw);
+  memcpy(Mc, M, sizeof(real) * nw * nw);
   solve(nw, Mc, b);
   for (int i = 0; i < nw; i++) A[i] = b[i];
 }
 
 /* (a.psi) integrated over xi, for h (m = 0) and for b (m = 1):
    a0 + a.v + a_E/2 (|v|^2 + (N_xi + 2m)/(2 lam)) */
-static double apsi(int dim, const double* a, double vx, double vy, double lam, int m) {
+static real apsi(int dim, const real* a, real vx, real vy, real lam, int m) {
   int nxi = 3 - dim;
-  double v2 = vx * vx + ((dim == 2) ? vy * vy : 0.0);
-  double s = a[0] + a[1] * vx;
+  real v2 = vx * vx + ((dim == 2) ? vy * vy : 0.0);
+  real s = a[0] + a[1] * vx;
   if (dim == 2) s += a[2] * vy;
-  s += 0.5 * a[dim + 1] * (v2 + (double)(nxi + 2 * m) / (2.0 * lam));
+  s += 0.5 * a[dim + 1] * (v2 + (real)(nxi + 2 * m) / (2.0 * lam));
   return s;
 }
 
@@ -318,15 +318,15 @@ static double apsi(int dim, const double* a, double vx, double vy, double lam, i
  * which keeps every digit as tau grows (the closed forms cancel like 1/x^3);
  * tau = inf is x = 0.
  */
-void or_time_coeffs(double dts, double tau, double* q) {
-  double x = isinf(tau) ? 0.0 : dts / tau;
+void or_time_coeffs(real dts, real tau, real* q) {
+  real x = isinf(tau) ? 0.0 : dts / tau;
   if (x < 1.0) {
-    double s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
-    double fact = 1.0, xp = 1.0; /* xp = x^(m-1) at the top of step m */
-    double xpm2 = 0.0;
+    real s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
+    real fact = 1.0, xp = 1.0; /* xp = x^(m-1) at the top of step m */
+    real xpm2 = 0.0;
     for (int m = 1; m <= 24; m++) {
       fact *= m;
-      double sg = (m % 2 == 0) ? 1.0 : -1.0; /* (-1)^m */
+      real sg = (m % 2 == 0) ? 1.0 : -1.0; /* (-1)^m */
       s1 += -sg * xp / fact;
       if (m >= 2) {
         s3 += sg * xp / fact;
@@ -345,7 +345,7 @@ void or_time_coeffs(double dts, double tau, double* q) {
     q[3] = dts * dts * s4;
     q[4] = dts * dts * s5;
   } else {
-    double e = exp(-x);
+    real e = exp(-x);
     q[0] = tau * (1.0 - e);
     q[1] = tau * tau * (-1.0 + (1.0 + x) * e);
     q[2] = dts - q[0];
@@ -452,17 +452,26 @@ static void build_faces(or_case* c) {
   c->nface = nf;
 }
 
-static double node_x(const or_case* c, int b, int i, int j) {
+static real node_x(const or_case* c, int b, int i, int j) {
   return c->xn[c->node0[b] + i + (c->blk[b].ni + 1) * j];
 }
-static double node_y(const or_case* c, int b, int i, int j) {
+static real node_y(const or_case* c, int b, int i, int j) {
   return c->yn[c->node0[b] + i + (c->blk[b].ni + 1) * j];
 }
 
-void or_set_pose(or_case* c, int b, double dx, double dy, double th, double ux,
-                 double uy, double om) {
+void or_set_pose(or_case* c, int b, real dx, real dy, real th, real ux,
+                 real uy, real om) {
   blk_t* B = &c->blk[b];
   B->dx = dx; B->dy = dy; B->th = th; B->ux = ux; B->uy = uy; B->om = om;
+}
+
+/* wall RT of one side of a block (the isothermal wall of Eq. maxWalldes) */
+void or_set_wall_rt(or_case* c, int b, int side, real rtw) {
+  c->blk[b].rtw[side] = rtw;
+  for (int f = 0; f < c->nface; f++) {
+    face_t* F = &c->face[f];
+    if (F->kind == F_WALL && F->blk == b && F->side == side) F->rtw = rtw;
+  }
 }
 
 /* rigid motion: x = xc0 + d + R(th)(x0 - xc0); U = u + om x (x - xc0 - d) */
@@ -470,10 +479,10 @@ void or_update_geometry(or_case* c) {
   for (int b = 0; b < c->nblock; b++) {
     blk_t* B = &c->blk[b];
     int nn = (B->ni + 1) * ((c->dim == 2) ? (B->nj + 1) : 1);
-    double cs = cos(B->th), sn = sin(B->th);
+    real cs = cos(B->th), sn = sin(B->th);
     for (int n = 0; n < nn; n++) {
-      double rx = B->x0[n] - B->xc0;
-      double ry = (c->dim == 2) ? B->y0[n] - B->yc0 : 0.0;
+      real rx = B->x0[n] - B->xc0;
+      real ry = (c->dim == 2) ? B->y0[n] - B->yc0 : 0.0;
       c->xn[c->node0[b] + n] = B->xc0 + B->dx + (cs * rx - sn * ry);
       c->yn[c->node0[b] + n] = (c->dim == 2) ? B->yc0 + B->dy + (sn * rx + cs * ry) : 0.0;
     }
@@ -482,7 +491,7 @@ void or_update_geometry(or_case* c) {
   for (int n = 0; n < c->ncell; n++) {
     int b = c->cblk[n], i = c->ci[n], j = c->cj[n];
     if (c->dim == 1) {
-      double xa = node_x(c, b, i, 0), xb = node_x(c, b, i + 1, 0);
+      real xa = node_x(c, b, i, 0), xb = node_x(c, b, i + 1, 0);
       c->vol[n] = xb - xa;
       c->cx[n] = 0.5 * (xa + xb); c->cy[n] = 0.0;
       c->g[4 * n + 0] = 1.0 / (xb - xa);
@@ -492,12 +501,12 @@ void or_update_geometry(or_case* c) {
       c->cdx[8 * n + 2] = xb - c->cx[n];
       continue;
     }
-    double px[4] = {node_x(c, b, i, j), node_x(c, b, i + 1, j), node_x(c, b, i + 1, j + 1), node_x(c, b, i, j + 1)};
-    double py[4] = {node_y(c, b, i, j), node_y(c, b, i + 1, j), node_y(c, b, i + 1, j + 1), node_y(c, b, i, j + 1)};
-    double A = 0.0, sx = 0.0, sy = 0.0;
+    real px[4] = {node_x(c, b, i, j), node_x(c, b, i + 1, j), node_x(c, b, i + 1, j + 1), node_x(c, b, i, j + 1)};
+    real py[4] = {node_y(c, b, i, j), node_y(c, b, i + 1, j), node_y(c, b, i + 1, j + 1), node_y(c, b, i, j + 1)};
+    real A = 0.0, sx = 0.0, sy = 0.0;
     for (int k = 0; k < 4; k++) {
       int k1 = (k + 1) % 4;
-      double cr = px[k] * py[k1] - px[k1] * py[k];
+      real cr = px[k] * py[k1] - px[k1] * py[k];
       A += cr; sx += (px[k] + px[k1]) * cr; sy += (py[k] + py[k1]) * cr;
     }
     A *= 0.5;
@@ -505,19 +514,19 @@ void or_update_geometry(or_case* c) {
     c->cx[n] = sx / (6.0 * A);
     c->cy[n] = sy / (6.0 * A);
     /* metric from face-centre differences: J = [[x_xi, x_eta],[y_xi, y_eta]] */
-    double xxi = 0.5 * (px[1] + px[2]) - 0.5 * (px[0] + px[3]);
-    double yxi = 0.5 * (py[1] + py[2]) - 0.5 * (py[0] + py[3]);
-    double xet = 0.5 * (px[3] + px[2]) - 0.5 * (px[0] + px[1]);
-    double yet = 0.5 * (py[3] + py[2]) - 0.5 * (py[0] + py[1]);
-    double det = xxi * yet - xet * yxi;
+    real xxi = 0.5 * (px[1] + px[2]) - 0.5 * (px[0] + px[3]);
+    real yxi = 0.5 * (py[1] + py[2]) - 0.5 * (py[0] + py[3]);
+    real xet = 0.5 * (px[3] + px[2]) - 0.5 * (px[0] + px[1]);
+    real yet = 0.5 * (py[3] + py[2]) - 0.5 * (py[0] + py[1]);
+    real det = xxi * yet - xet * yxi;
     /* grad f = J^{-T} (df/dxi, df/deta) */
     c->g[4 * n + 0] = yet / det;
     c->g[4 * n + 1] = -yxi / det;
     c->g[4 * n + 2] = -xet / det;
     c->g[4 * n + 3] = xxi / det;
     /* face centres from the cell's own nodes: i-low, i-high, j-low, j-high */
-    double fxs[4] = {0.5 * (px[0] + px[3]), 0.5 * (px[1] + px[2]), 0.5 * (px[0] + px[1]), 0.5 * (px[3] + px[2])};
-    double fys[4] = {0.5 * (py[0] + py[3]), 0.5 * (py[1] + py[2]), 0.5 * (py[0] + py[1]), 0.5 * (py[3] + py[2])};
+    real fxs[4] = {0.5 * (px[0] + px[3]), 0.5 * (px[1] + px[2]), 0.5 * (px[0] + px[1]), 0.5 * (px[3] + px[2])};
+    real fys[4] = {0.5 * (py[0] + py[3]), 0.5 * (py[1] + py[2]), 0.5 * (py[0] + py[1]), 0.5 * (py[3] + py[2])};
     for (int q = 0; q < 4; q++) {
       c->cdx[8 * n + 2 * q] = fxs[q] - c->cx[n];
       c->cdx[8 * n + 2 * q + 1] = fys[q] - c->cy[n];
@@ -538,7 +547,7 @@ void or_update_geometry(or_case* c) {
       F->S = 1.0; F->nx = 1.0; F->ny = 0.0;
       F->xf = node_x(c, b, fi, 0); F->yf = 0.0;
     } else {
-      double x0, y0, x1, y1;
+      real x0, y0, x1, y1;
       if (dir == 0) {
         x0 = node_x(c, b, fi, fj); y0 = node_y(c, b, fi, fj);
         x1 = node_x(c, b, fi, fj + 1); y1 = node_y(c, b, fi, fj + 1);
@@ -546,13 +555,13 @@ void or_update_geometry(or_case* c) {
         x0 = node_x(c, b, fi, fj); y0 = node_y(c, b, fi, fj);
         x1 = node_x(c, b, fi + 1, fj); y1 = node_y(c, b, fi + 1, fj);
       }
-      double ex = x1 - x0, ey = y1 - y0;
+      real ex = x1 - x0, ey = y1 - y0;
       F->S = sqrt(ex * ex + ey * ey);
       if (dir == 0) { F->nx = ey / F->S; F->ny = -ex / F->S; }
       else { F->nx = -ey / F->S; F->ny = ex / F->S; }
       F->xf = 0.5 * (x0 + x1); F->yf = 0.5 * (y0 + y1);
     }
-    double rx = F->xf - (B->xc0 + B->dx), ry = F->yf - (B->yc0 + B->dy);
+    real rx = F->xf - (B->xc0 + B->dx), ry = F->yf - (B->yc0 + B->dy);
     F->ux = B->ux - B->om * ry;
     F->uy = (c->dim == 2) ? B->uy + B->om * rx : 0.0;
     if (F->kind == F_WALL) {
@@ -562,10 +571,10 @@ void or_update_geometry(or_case* c) {
   }
 }
 
-or_case* or_create(int dim, const double* gas, const int* nv, const double* vrange,
-                   const double* vx, const double* vy, const double* winf,
-                   const double* cfl, int nblock, const int* bint,
-                   const double* bdbl, const double* nodes) {
+or_case* or_create(int dim, const real* gas, const int* nv, const real* vrange,
+                   const real* vx, const real* vy, const real* winf,
+                   const real* cfl, int nblock, const int* bint,
+                   const real* bdbl, const real* nodes) {
   if (dim != 1 && dim != 2) return NULL;
   or_case* c = (or_case*)calloc(1, sizeof(or_case));
   c->dim = dim; c->nxi = 3 - dim; c->nw = dim + 2;
@@ -574,13 +583,13 @@ or_case* or_create(int dim, const double* gas, const int* nv, const double* vran
   c->nvx = nv[0]; c->nvy = (dim == 2) ? nv[1] : 1; c->nv = c->nvx * c->nvy;
   c->vx0 = vrange[0]; c->vx1 = vrange[1]; c->vy0 = vrange[2]; c->vy1 = vrange[3];
   for (int i = 0; i < 4; i++) c->winf[i] = winf[i];
-  double* wx = (double*)malloc(sizeof(double) * c->nvx);
-  double* wy = (double*)malloc(sizeof(double) * c->nvy);
+  real* wx = (real*)malloc(sizeof(real) * c->nvx);
+  real* wy = (real*)malloc(sizeof(real) * c->nvy);
   or_nc_weights(c->nvx, c->vx0, c->vx1, wx);
   if (dim == 2) or_nc_weights(c->nvy, c->vy0, c->vy1, wy); else wy[0] = 1.0;
-  c->vk_x = (double*)malloc(sizeof(double) * c->nv);
-  c->vk_y = (double*)malloc(sizeof(double) * c->nv);
-  c->wk = (double*)malloc(sizeof(double) * c->nv);
+  c->vk_x = (real*)malloc(sizeof(real) * c->nv);
+  c->vk_y = (real*)malloc(sizeof(real) * c->nv);
+  c->wk = (real*)malloc(sizeof(real) * c->nv);
   for (int iy = 0; iy < c->nvy; iy++)
     for (int ix = 0; ix < c->nvx; ix++) {
       int k = ix + c->nvx * iy;
@@ -590,10 +599,10 @@ or_case* or_create(int dim, const double* gas, const int* nv, const double* vran
     }
   free(wx); free(wy);
   /* far-field Maxwellian */
-  c->finf_h = (double*)malloc(sizeof(double) * c->nv);
-  c->finf_b = (double*)malloc(sizeof(double) * c->nv);
+  c->finf_h = (real*)malloc(sizeof(real) * c->nv);
+  c->finf_b = (real*)malloc(sizeof(real) * c->nv);
   {
-    double rho, u[2], lam;
+    real rho, u[2], lam;
     prim(c, c->winf, &rho, u, &lam);
     for (int k = 0; k < c->nv; k++) maxw(c, rho, u, lam, c->vk_x[k], c->vk_y[k], &c->finf_h[k], &c->finf_b[k]);
   }
@@ -601,7 +610,7 @@ or_case* or_create(int dim, const double* gas, const int* nv, const double* vran
   c->blk = (blk_t*)calloc(nblock, sizeof(blk_t));
   c->node0 = (int*)malloc(sizeof(int) * nblock);
   int ncell = 0, nnode = 0;
-  const double* np = nodes;
+  const real* np = nodes;
   for (int b = 0; b < nblock; b++) {
     blk_t* B = &c->blk[b];
     B->ni = bint[6 * b]; B->nj = (dim == 2) ? bint[6 * b + 1] : 1;
@@ -615,11 +624,11 @@ or_case* or_create(int dim, const double* gas, const int* nv, const double* vran
     if ((B->bc[0] == OR_PERIODIC) != (B->bc[1] == OR_PERIODIC)) { or_free(c); return NULL; }
     if ((B->bc[2] == OR_PERIODIC) != (B->bc[3] == OR_PERIODIC)) { or_free(c); return NULL; }
     int nn = (B->ni + 1) * ((dim == 2) ? (B->nj + 1) : 1);
-    B->x0 = (double*)malloc(sizeof(double) * nn);
-    B->y0 = (double*)malloc(sizeof(double) * nn);
-    memcpy(B->x0, np, sizeof(double) * nn); np += nn;
-    if (dim == 2) { memcpy(B->y0, np, sizeof(double) * nn); np += nn; }
-    else memset(B->y0, 0, sizeof(double) * nn);
+    B->x0 = (real*)malloc(sizeof(real) * nn);
+    B->y0 = (real*)malloc(sizeof(real) * nn);
+    memcpy(B->x0, np, sizeof(real) * nn); np += nn;
+    if (dim == 2) { memcpy(B->y0, np, sizeof(real) * nn); np += nn; }
+    else memset(B->y0, 0, sizeof(real) * nn);
     B->cell0 = ncell;
     c->node0[b] = nnode;
     ncell += B->ni * B->nj;
@@ -637,13 +646,13 @@ or_case* or_create(int dim, const double* gas, const int* nv, const double* vran
         int n = cell_index(c, b, i, j);
         c->cblk[n] = b; c->ci[n] = i; c->cj[n] = j;
       }
-  c->xn = (double*)malloc(sizeof(double) * nnode);
-  c->yn = (double*)malloc(sizeof(double) * nnode);
-  c->cx = (double*)malloc(sizeof(double) * ncell);
-  c->cy = (double*)malloc(sizeof(double) * ncell);
-  c->vol = (double*)malloc(sizeof(double) * ncell);
-  c->g = (double*)malloc(sizeof(double) * 4 * ncell);
-  c->cdx = (double*)malloc(sizeof(double) * 8 * ncell);
+  c->xn = (real*)malloc(sizeof(real) * nnode);
+  c->yn = (real*)malloc(sizeof(real) * nnode);
+  c->cx = (real*)malloc(sizeof(real) * ncell);
+  c->cy = (real*)malloc(sizeof(real) * ncell);
+  c->vol = (real*)malloc(sizeof(real) * ncell);
+  c->g = (real*)malloc(sizeof(real) * 4 * ncell);
+  c->cdx = (real*)malloc(sizeof(real) * 8 * ncell);
   build_faces(c);
   or_update_geometry(c);
   return c;
@@ -660,12 +669,12 @@ void or_free(or_case* c) {
   free(c);
 }
 
-void or_dvs(const or_case* c, double* vx, double* vy, double* wk) {
+void or_dvs(const or_case* c, real* vx, real* vy, real* wk) {
   for (int k = 0; k < c->nv; k++) { vx[k] = c->vk_x[k]; vy[k] = c->vk_y[k]; wk[k] = c->wk[k]; }
 }
 
-void or_geometry(const or_case* c, double* cx, double* vol, double* g, int* fl, int* fr,
-                 double* fn, double* fs, double* fx, double* fu) {
+void or_geometry(const or_case* c, real* cx, real* vol, real* g, int* fl, int* fr,
+                 real* fn, real* fs, real* fx, real* fu) {
   for (int n = 0; n < c->ncell; n++) {
     cx[2 * n] = c->cx[n]; cx[2 * n + 1] = c->cy[n]; vol[n] = c->vol[n];
     for (int i = 0; i < 4; i++) g[4 * n + i] = c->g[4 * n + i];
@@ -680,11 +689,11 @@ void or_geometry(const or_case* c, double* cx, double* vol, double* g, int* fl, 
   }
 }
 
-void or_nodes(const or_case* c, double* x, double* y) {
+void or_nodes(const or_case* c, real* x, real* y) {
   int nn = 0;
   for (int b = 0; b < c->nblock; b++) nn += (c->blk[b].ni + 1) * (c->blk[b].nj + 1);
-  memcpy(x, c->xn, sizeof(double) * nn);
-  memcpy(y, c->yn, sizeof(double) * nn);
+  memcpy(x, c->xn, sizeof(real) * nn);
+  memcpy(y, c->yn, sizeof(real) * nn);
 }
 
 void or_face_ids(const or_case* c, int* blk, int* dir, int* fi, int* fj) {
@@ -704,7 +713,7 @@ void or_set_types(or_case* c, const int8_t* type) { memcpy(c->type, type, c->nce
 void or_get_types(const or_case* c, int8_t* type) { memcpy(type, c->type, c->ncell); }
 
 void or_set_overset(or_case* c, int nrec, const int* rec, const int* ptr, const int* don,
-                    const double* w) {
+                    const real* w) {
   free(c->rec); free(c->dptr); free(c->don); free(c->dw);
   c->nrec = nrec;
   c->nref = 0;
@@ -712,80 +721,80 @@ void or_set_overset(or_case* c, int nrec, const int* rec, const int* ptr, const 
   c->dptr = (int*)malloc(sizeof(int) * (nrec + 1));
   int nd = (nrec > 0) ? ptr[nrec] : 0;
   c->don = (int*)malloc(sizeof(int) * (nd > 0 ? nd : 1));
-  c->dw = (double*)malloc(sizeof(double) * (nd > 0 ? nd : 1));
+  c->dw = (real*)malloc(sizeof(real) * (nd > 0 ? nd : 1));
   if (nrec > 0) memcpy(c->rec, rec, sizeof(int) * nrec);
   memcpy(c->dptr, ptr, sizeof(int) * (nrec + 1));
-  if (nd > 0) { memcpy(c->don, don, sizeof(int) * nd); memcpy(c->dw, w, sizeof(double) * nd); }
+  if (nd > 0) { memcpy(c->don, don, sizeof(int) * nd); memcpy(c->dw, w, sizeof(real) * nd); }
 }
 
 int or_overset_count(const or_case* c) { return c->nrec; }
 int or_refill_count(const or_case* c) { return c->nref; }
 
-int or_get_overset(const or_case* c, int* rec, int* ptr, int* don, double* w) {
+int or_get_overset(const or_case* c, int* rec, int* ptr, int* don, real* w) {
   if (rec) memcpy(rec, c->rec, sizeof(int) * c->nrec);
   if (ptr) memcpy(ptr, c->dptr, sizeof(int) * (c->nrec + 1));
   int nd = c->dptr ? c->dptr[c->nrec] : 0;
   if (don && nd) memcpy(don, c->don, sizeof(int) * nd);
-  if (w && nd) memcpy(w, c->dw, sizeof(double) * nd);
+  if (w && nd) memcpy(w, c->dw, sizeof(real) * nd);
   return nd;
 }
 
 /* ------------------------------------------------------------------------ */
 /* moments (Sec. 2.1: W = int Psi f, q = 1/2 int c (c^2 + xi^2) f)           */
 /* ------------------------------------------------------------------------ */
-static void cell_moments(const or_case* c, const double* h, const double* b, double* W) {
+static void cell_moments(const or_case* c, const real* h, const real* b, real* W) {
   int d = c->dim;
   for (int m = 0; m < c->nw; m++) W[m] = 0.0;
   for (int k = 0; k < c->nv; k++) {
-    double vx = c->vk_x[k], vy = c->vk_y[k], w = c->wk[k];
+    real vx = c->vk_x[k], vy = c->vk_y[k], w = c->wk[k];
     W[0] += w * h[k];
     W[1] += w * vx * h[k];
     if (d == 2) W[2] += w * vy * h[k];
     W[d + 1] += w * 0.5 * ((vx * vx + vy * vy) * h[k] + b[k]);
   }
 }
-static void cell_heatflux(const or_case* c, const double* h, const double* b,
-                          const double* u, double* q) {
+static void cell_heatflux(const or_case* c, const real* h, const real* b,
+                          const real* u, real* q) {
   q[0] = q[1] = 0.0;
   for (int k = 0; k < c->nv; k++) {
-    double cx = c->vk_x[k] - u[0], cy = (c->dim == 2) ? c->vk_y[k] - u[1] : 0.0;
-    double e = (cx * cx + cy * cy) * h[k] + b[k];
+    real cx = c->vk_x[k] - u[0], cy = (c->dim == 2) ? c->vk_y[k] - u[1] : 0.0;
+    real e = (cx * cx + cy * cy) * h[k] + b[k];
     q[0] += c->wk[k] * 0.5 * cx * e;
     if (c->dim == 2) q[1] += c->wk[k] * 0.5 * cy * e;
   }
 }
 
-void or_moments(const or_case* c, const double* h, const double* b, double* W, double* q) {
+void or_moments(const or_case* c, const real* h, const real* b, real* W, real* q) {
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < c->ncell; n++) {
-    const double* hn = h + (size_t)n * c->nv;
-    const double* bn = b + (size_t)n * c->nv;
+    const real* hn = h + (size_t)n * c->nv;
+    const real* bn = b + (size_t)n * c->nv;
     cell_moments(c, hn, bn, W + (size_t)n * c->nw);
-    double rho, u[2], lam;
+    real rho, u[2], lam;
     prim(c, W + (size_t)n * c->nw, &rho, u, &lam);
     if (q) {
-      double qq[2];
+      real qq[2];
       cell_heatflux(c, hn, bn, u, qq);
       for (int i = 0; i < c->dim; i++) q[(size_t)n * c->dim + i] = qq[i];
     }
   }
 }
 
-void or_heatflux(const or_case* c, const double* h, const double* b, const double* W, double* q) {
+void or_heatflux(const or_case* c, const real* h, const real* b, const real* W, real* q) {
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < c->ncell; n++) {
-    double rho, u[2], lam;
+    real rho, u[2], lam;
     prim(c, W + (size_t)n * c->nw, &rho, u, &lam);
-    double qq[2];
+    real qq[2];
     cell_heatflux(c, h + (size_t)n * c->nv, b + (size_t)n * c->nv, u, qq);
     for (int i = 0; i < c->dim; i++) q[(size_t)n * c->dim + i] = qq[i];
   }
 }
 
-void or_maxwellian(const or_case* c, const double* W, double* h, double* b) {
+void or_maxwellian(const or_case* c, const real* W, real* h, real* b) {
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < c->ncell; n++) {
-    double rho, u[2], lam;
+    real rho, u[2], lam;
     prim(c, W + (size_t)n * c->nw, &rho, u, &lam);
     for (int k = 0; k < c->nv; k++)
       maxw(c, rho, u, lam, c->vk_x[k], c->vk_y[k], &h[(size_t)n * c->nv + k], &b[(size_t)n * c->nv + k]);
@@ -796,29 +805,29 @@ void or_maxwellian(const or_case* c, const double* W, double* h, double* b) {
 /* time steps (Sec. 2.2: dt_s with CFL 0.5, virtual step dt' with CFL 100)   */
 /* ------------------------------------------------------------------------ */
 /* per face: max_k |(v_k - U_f).n| */
-static double face_smax(const or_case* c, const face_t* F) {
-  double m = 0.0;
+static real face_smax(const or_case* c, const face_t* F) {
+  real m = 0.0;
   for (int k = 0; k < c->nv; k++) {
-    double wn = (c->vk_x[k] - F->ux) * F->nx + (c->vk_y[k] - F->uy) * F->ny;
+    real wn = (c->vk_x[k] - F->ux) * F->nx + (c->vk_y[k] - F->uy) * F->ny;
     if (fabs(wn) > m) m = fabs(wn);
   }
   return m;
 }
 /* Reading: dt_s = CFL_s min over field cells of |Omega| / sum_f S_f smax_f / 2,
    dt'_i = CFL' |Omega_i| / sum_f S_f smax_f / 2. */
-double or_timesteps(const or_case* c, double* dtp) {
-  double* sm = (double*)malloc(sizeof(double) * (c->nface > 0 ? c->nface : 1));
+real or_timesteps(const or_case* c, real* dtp) {
+  real* sm = (real*)malloc(sizeof(real) * (c->nface > 0 ? c->nface : 1));
   for (int f = 0; f < c->nface; f++) sm[f] = face_smax(c, &c->face[f]);
-  double dts = INFINITY;
+  real dts = INFINITY;
   for (int n = 0; n < c->ncell; n++) {
-    double s = 0.0;
+    real s = 0.0;
     for (int q = 0; q < 4; q++) {
       int f = c->cface[4 * n + q];
       if (f >= 0) s += 0.5 * c->face[f].S * sm[f];
     }
     if (dtp) dtp[n] = c->cfl_p * c->vol[n] / s;
     if (c->type[n] == OR_FIELD) {
-      double t = c->cfl_s * c->vol[n] / s;
+      real t = c->cfl_s * c->vol[n] / s;
       if (t < dts) dts = t;
     }
   }
@@ -832,14 +841,14 @@ double or_timesteps(const or_case* c, double* dtp) {
 /* the cell metric; one-sided difference beside a wall; zero when a          */
 /* neighbour is a hole or missing; virtual ghost cells have zero slope.      */
 /* ------------------------------------------------------------------------ */
-static double vanleer(double s1, double s2) {
+static real vanleer(real s1, real s2) {
   if (s1 * s2 <= 0.0) return 0.0;
   return (s1 * fabs(s2) + fabs(s1) * s2) / (fabs(s1) + fabs(s2));
 }
 
 /* value accessor over f arrays (stride nv) or W arrays (stride nw) */
-typedef struct { const double* a; const double* inf; int stride; } acc_t;
-static double acc_get(const acc_t* A, nbref r, int cell, int m) {
+typedef struct { const real* a; const real* inf; int stride; } acc_t;
+static real acc_get(const acc_t* A, nbref r, int cell, int m) {
   switch (r.kind) {
     case NB_CELL: return A->a[(size_t)r.cell * A->stride + m];
     case NB_FF: return A->inf[m];
@@ -847,19 +856,19 @@ static double acc_get(const acc_t* A, nbref r, int cell, int m) {
     default: return 0.0;
   }
 }
-static double index_slope(const or_case* c, const acc_t* A, int cell, int dir, int m) {
+static real index_slope(const or_case* c, const acc_t* A, int cell, int dir, int m) {
   nbref lo = nbr(c, cell, dir, -1), hi = nbr(c, cell, dir, +1);
   if (lo.kind == NB_MISSING || hi.kind == NB_MISSING) return 0.0;
-  double v0 = A->a[(size_t)cell * A->stride + m];
+  real v0 = A->a[(size_t)cell * A->stride + m];
   if (lo.kind == NB_WALL && hi.kind == NB_WALL) return 0.0;
   if (lo.kind == NB_WALL) return acc_get(A, hi, cell, m) - v0;
   if (hi.kind == NB_WALL) return v0 - acc_get(A, lo, cell, m);
   return vanleer(v0 - acc_get(A, lo, cell, m), acc_get(A, hi, cell, m) - v0);
 }
-static void phys_grad(const or_case* c, const acc_t* A, int cell, int m, double* gx, double* gy) {
-  double si = index_slope(c, A, cell, 0, m);
-  double sj = (c->dim == 2) ? index_slope(c, A, cell, 1, m) : 0.0;
-  const double* g = c->g + 4 * cell;
+static void phys_grad(const or_case* c, const acc_t* A, int cell, int m, real* gx, real* gy) {
+  real si = index_slope(c, A, cell, 0, m);
+  real sj = (c->dim == 2) ? index_slope(c, A, cell, 1, m) : 0.0;
+  const real* g = c->g + 4 * cell;
   *gx = g[0] * si + g[1] * sj;
   *gy = (c->dim == 2) ? g[2] * si + g[3] * sj : 0.0;
 }
@@ -870,25 +879,25 @@ static void phys_grad(const or_case* c, const acc_t* A, int cell, int m, double*
 /* ------------------------------------------------------------------------ */
 typedef struct {
   int active;
-  double rho, u[2], lam, q[2], tau;
-  double a[2][4], A[4], tc[5];
+  real rho, u[2], lam, q[2], tau;
+  real a[2][4], A[4], tc[5];
   /* wall */
-  double nwx, nwy, sgn;  /* normal into the wall, and +-1 face-normal sign */
-  double rhow, lamw;
+  real nwx, nwy, sgn;  /* normal into the wall, and +-1 face-normal sign */
+  real rhow, lamw;
 } frec_t;
 
 typedef struct {
   const or_case* c;
-  const double *h, *b, *W, *q;
-  double* gW;     /* [ncell][2][nw] physical gradients of W */
+  const real *h, *b, *W, *q;
+  real* gW;     /* [ncell][2][nw] physical gradients of W */
   frec_t* rec;
-  double dts;
+  real dts;
 } flux_ctx;
 
 /* reconstructed value and gradient of f (h: comp 0, b: comp 1) from side s
    (0 = L, 1 = R) of face f at velocity k */
 static void side_value(const flux_ctx* X, const face_t* F, int s, int k,
-                       double* vh, double* vb, double* gh, double* gb) {
+                       real* vh, real* vb, real* gh, real* gb) {
   const or_case* c = X->c;
   int cell = (s == 0) ? F->L : F->R;
   if (cell < 0) { /* virtual ghost, zero slope */
@@ -902,7 +911,7 @@ static void side_value(const flux_ctx* X, const face_t* F, int s, int k,
   phys_grad(c, &Ah, cell, 0, &gh[0], &gh[1]);
   phys_grad(c, &Ab, cell, 0, &gb[0], &gb[1]);
   int slot = 2 * F->dir + ((s == 0) ? 1 : 0);
-  double dx = c->cdx[8 * cell + 2 * slot], dy = c->cdx[8 * cell + 2 * slot + 1];
+  real dx = c->cdx[8 * cell + 2 * slot], dy = c->cdx[8 * cell + 2 * slot + 1];
   *vh = X->h[(size_t)cell * c->nv + k] + gh[0] * dx + gh[1] * dy;
   *vb = X->b[(size_t)cell * c->nv + k] + gb[0] * dx + gb[1] * dy;
 }
@@ -910,32 +919,32 @@ static void side_value(const flux_ctx* X, const face_t* F, int s, int k,
 /* interface distribution integrated over [0, dts] (Eq. fullSolution) for the
    upwind data (fh, fb, gh, gb) and the equilibrium record R, at velocity k */
 static void interface_integral(const or_case* c, const frec_t* R, const face_t* F, int k,
-                               double fh, double fb, const double* gh, const double* gb,
-                               double* Ih, double* Ib) {
+                               real fh, real fb, const real* gh, const real* gb,
+                               real* Ih, real* Ib) {
   int d = c->dim;
-  double vx = c->vk_x[k], vy = c->vk_y[k];
-  double wx = vx - F->ux, wy = (d == 2) ? vy - F->uy : 0.0;
-  double H, B, Hp, Bp;
+  real vx = c->vk_x[k], vy = c->vk_y[k];
+  real wx = vx - F->ux, wy = (d == 2) ? vy - F->uy : 0.0;
+  real H, B, Hp, Bp;
   maxw(c, R->rho, R->u, R->lam, vx, vy, &H, &B);
-  double v[2] = {vx, vy};
+  real v[2] = {vx, vy};
   or_shakhov(d, c->pr, R->rho, R->u, R->lam, R->q, v, &Hp, &Bp);
-  double wah = wx * apsi(d, R->a[0], vx, vy, R->lam, 0);
-  double wab = wx * apsi(d, R->a[0], vx, vy, R->lam, 1);
+  real wah = wx * apsi(d, R->a[0], vx, vy, R->lam, 0);
+  real wab = wx * apsi(d, R->a[0], vx, vy, R->lam, 1);
   if (d == 2) {
     wah += wy * apsi(d, R->a[1], vx, vy, R->lam, 0);
     wab += wy * apsi(d, R->a[1], vx, vy, R->lam, 1);
   }
-  double Ah = apsi(d, R->A, vx, vy, R->lam, 0), Ab = apsi(d, R->A, vx, vy, R->lam, 1);
-  double wgh = wx * gh[0] + wy * gh[1], wgb = wx * gb[0] + wy * gb[1];
-  const double* t = R->tc;
+  real Ah = apsi(d, R->A, vx, vy, R->lam, 0), Ab = apsi(d, R->A, vx, vy, R->lam, 1);
+  real wgh = wx * gh[0] + wy * gh[1], wgb = wx * gb[0] + wy * gb[1];
+  const real* t = R->tc;
   *Ih = t[0] * fh + t[1] * wgh + t[2] * (H + Hp) + t[3] * wah * H + t[4] * Ah * H;
   *Ib = t[0] * fb + t[1] * wgb + t[2] * (B + Bp) + t[3] * wab * B + t[4] * Ab * B;
 }
 
-static void set_coeffs(const or_case* c, frec_t* R, const double* uf, const double* dW, double dts) {
-  double itau = inv_tau(c, R->rho, R->lam);
+static void set_coeffs(const or_case* c, frec_t* R, const real* uf, const real* dW, real dts) {
+  real itau = inv_tau(c, R->rho, R->lam);
   R->tau = (itau == 0.0) ? INFINITY : 1.0 / itau;
-  double a[8], A[4];
+  real a[8], A[4];
   or_slope_coeffs(c->dim, R->rho, R->u, R->lam, uf, dW, a, A);
   for (int d = 0; d < c->dim; d++)
     for (int m = 0; m < c->nw; m++) R->a[d][m] = a[d * c->nw + m];
@@ -959,9 +968,9 @@ static void face_record(const flux_ctx* X, int f) {
     R->sgn = (F->R < 0) ? 1.0 : -1.0; /* wall on the R side: face normal points into the wall */
     R->nwx = R->sgn * F->nx; R->nwy = R->sgn * F->ny;
     /* incident state: one-sided extrapolation of W to the wall face */
-    const double* gw = X->gW + (size_t)cell * 2 * nw;
+    const real* gw = X->gW + (size_t)cell * 2 * nw;
     int slot = 2 * F->dir + ((F->L >= 0) ? 1 : 0);
-    double Win[4], dx = c->cdx[8 * cell + 2 * slot], dy = c->cdx[8 * cell + 2 * slot + 1];
+    real Win[4], dx = c->cdx[8 * cell + 2 * slot], dy = c->cdx[8 * cell + 2 * slot + 1];
     for (int m = 0; m < nw; m++) Win[m] = X->W[(size_t)cell * nw + m] + gw[m] * dx + gw[nw + m] * dy;
     /* Reading (the paper is silent on positivity): an extrapolated state
        with non-positive density or internal energy is replaced by the cell
@@ -971,22 +980,22 @@ static void face_record(const flux_ctx* X, int f) {
     prim(c, Win, &R->rho, R->u, &R->lam);
     R->q[0] = X->q[(size_t)cell * d];
     R->q[1] = (d == 2) ? X->q[(size_t)cell * d + 1] : 0.0;
-    double uf[2] = {F->ux, F->uy};
+    real uf[2] = {F->ux, F->uy};
     set_coeffs(c, R, uf, gw, X->dts);
     /* wall density from zero net mass flux (Eq. maxWalldes) */
     R->lamw = 1.0 / (2.0 * F->rtw);
-    double num = 0.0, den = 0.0;
-    double nrm = pow(R->lamw / PI, 0.5 * d);
+    real num = 0.0, den = 0.0;
+    real nrm = pow(R->lamw / PI, 0.5 * d);
     for (int k = 0; k < c->nv; k++) {
-      double vx = c->vk_x[k], vy = c->vk_y[k];
-      double wn = (vx - F->ux) * R->nwx + (vy - F->uy) * R->nwy;
+      real vx = c->vk_x[k], vy = c->vk_y[k];
+      real wn = (vx - F->ux) * R->nwx + (vy - F->uy) * R->nwy;
       if (wn > 0.0) {
-        double fh, fb, gh[2], gb[2], Ih, Ib;
+        real fh, fb, gh[2], gb[2], Ih, Ib;
         side_value(X, F, (F->L >= 0) ? 0 : 1, k, &fh, &fb, gh, gb);
         interface_integral(c, R, F, k, fh, fb, gh, gb, &Ih, &Ib);
         num += c->wk[k] * wn * Ih;
       } else if (wn < 0.0) {
-        double cx = vx - F->vwx, cy = (d == 2) ? vy - F->vwy : 0.0;
+        real cx = vx - F->vwx, cy = (d == 2) ? vy - F->vwy : 0.0;
         den += c->wk[k] * wn * nrm * exp(-R->lamw * (cx * cx + cy * cy));
       }
     }
@@ -997,17 +1006,17 @@ static void face_record(const flux_ctx* X, int f) {
   int Rf = (F->R >= 0 && c->type[F->R] == OR_FIELD);
   if (!Lf && !Rf) return;
   R->active = 1;
-  double W0[4] = {0, 0, 0, 0};
+  real W0[4] = {0, 0, 0, 0};
   for (int k = 0; k < c->nv; k++) {
-    double vx = c->vk_x[k], vy = c->vk_y[k];
-    double wn = (vx - F->ux) * F->nx + (vy - F->uy) * F->ny;
-    double hl, bl, hr, br, g[2], gb[2], fh, fb;
+    real vx = c->vk_x[k], vy = c->vk_y[k];
+    real wn = (vx - F->ux) * F->nx + (vy - F->uy) * F->ny;
+    real hl, bl, hr, br, g[2], gb[2], fh, fb;
     side_value(X, F, 0, k, &hl, &bl, g, gb);
     side_value(X, F, 1, k, &hr, &br, g, gb);
     if (wn > 0.0) { fh = hl; fb = bl; }
     else if (wn < 0.0) { fh = hr; fb = br; }
     else { fh = 0.5 * (hl + hr); fb = 0.5 * (bl + br); }
-    double w = c->wk[k];
+    real w = c->wk[k];
     W0[0] += w * fh;
     W0[1] += w * vx * fh;
     if (d == 2) W0[2] += w * vy * fh;
@@ -1016,70 +1025,70 @@ static void face_record(const flux_ctx* X, int f) {
   prim(c, W0, &R->rho, R->u, &R->lam);
   R->q[0] = R->q[1] = 0.0;
   for (int k = 0; k < c->nv; k++) {
-    double vx = c->vk_x[k], vy = c->vk_y[k];
-    double wn = (vx - F->ux) * F->nx + (vy - F->uy) * F->ny;
-    double hl, bl, hr, br, g[2], gb[2], fh, fb;
+    real vx = c->vk_x[k], vy = c->vk_y[k];
+    real wn = (vx - F->ux) * F->nx + (vy - F->uy) * F->ny;
+    real hl, bl, hr, br, g[2], gb[2], fh, fb;
     side_value(X, F, 0, k, &hl, &bl, g, gb);
     side_value(X, F, 1, k, &hr, &br, g, gb);
     if (wn > 0.0) { fh = hl; fb = bl; }
     else if (wn < 0.0) { fh = hr; fb = br; }
     else { fh = 0.5 * (hl + hr); fb = 0.5 * (bl + br); }
-    double cx = vx - R->u[0], cy = (d == 2) ? vy - R->u[1] : 0.0;
-    double e = (cx * cx + cy * cy) * fh + fb;
+    real cx = vx - R->u[0], cy = (d == 2) ? vy - R->u[1] : 0.0;
+    real e = (cx * cx + cy * cy) * fh + fb;
     R->q[0] += c->wk[k] * 0.5 * cx * e;
     if (d == 2) R->q[1] += c->wk[k] * 0.5 * cy * e;
   }
-  double dW[8];
+  real dW[8];
   for (int dd = 0; dd < 2; dd++)
     for (int m = 0; m < nw; m++) {
-      double gl = (F->L >= 0) ? X->gW[(size_t)F->L * 2 * nw + dd * nw + m] : 0.0;
-      double gr = (F->R >= 0) ? X->gW[(size_t)F->R * 2 * nw + dd * nw + m] : 0.0;
+      real gl = (F->L >= 0) ? X->gW[(size_t)F->L * 2 * nw + dd * nw + m] : 0.0;
+      real gr = (F->R >= 0) ? X->gW[(size_t)F->R * 2 * nw + dd * nw + m] : 0.0;
       dW[dd * nw + m] = 0.5 * (gl + gr);
     }
-  double uf[2] = {F->ux, F->uy};
+  real uf[2] = {F->ux, F->uy};
   set_coeffs(c, R, uf, dW, X->dts);
 }
 
 /* time-averaged flux along the face normal (L -> R) at velocity k */
-static void face_flux_k(const flux_ctx* X, int f, int k, double* Fh, double* Fb) {
+static void face_flux_k(const flux_ctx* X, int f, int k, real* Fh, real* Fb) {
   const or_case* c = X->c;
   const face_t* F = &c->face[f];
   const frec_t* R = &X->rec[f];
   *Fh = *Fb = 0.0;
   if (!R->active) return;
-  double vx = c->vk_x[k], vy = c->vk_y[k];
+  real vx = c->vk_x[k], vy = c->vk_y[k];
   if (F->kind == F_WALL) {
-    double wn = (vx - F->ux) * R->nwx + (vy - F->uy) * R->nwy;
-    double fh = 0.0, fb = 0.0;
+    real wn = (vx - F->ux) * R->nwx + (vy - F->uy) * R->nwy;
+    real fh = 0.0, fb = 0.0;
     if (wn > 0.0) {
-      double vh, vb, gh[2], gb[2], Ih, Ib;
+      real vh, vb, gh[2], gb[2], Ih, Ib;
       side_value(X, F, (F->L >= 0) ? 0 : 1, k, &vh, &vb, gh, gb);
       interface_integral(c, R, F, k, vh, vb, gh, gb, &Ih, &Ib);
       fh = wn * Ih / X->dts;
       fb = wn * Ib / X->dts;
     } else if (wn < 0.0) {
-      double cx = vx - F->vwx, cy = (c->dim == 2) ? vy - F->vwy : 0.0;
-      double Hw = R->rhow * pow(R->lamw / PI, 0.5 * c->dim) * exp(-R->lamw * (cx * cx + cy * cy));
+      real cx = vx - F->vwx, cy = (c->dim == 2) ? vy - F->vwy : 0.0;
+      real Hw = R->rhow * pow(R->lamw / PI, 0.5 * c->dim) * exp(-R->lamw * (cx * cx + cy * cy));
       fh = wn * Hw;
-      fb = wn * (double)c->nxi / (2.0 * R->lamw) * Hw;
+      fb = wn * (real)c->nxi / (2.0 * R->lamw) * Hw;
     }
     *Fh = R->sgn * fh;
     *Fb = R->sgn * fb;
     return;
   }
-  double wn = (vx - F->ux) * F->nx + (vy - F->uy) * F->ny;
+  real wn = (vx - F->ux) * F->nx + (vy - F->uy) * F->ny;
   if (wn == 0.0) return;
-  double vh, vb, gh[2], gb[2], Ih, Ib;
+  real vh, vb, gh[2], gb[2], Ih, Ib;
   side_value(X, F, (wn > 0.0) ? 0 : 1, k, &vh, &vb, gh, gb);
   interface_integral(c, R, F, k, vh, vb, gh, gb, &Ih, &Ib);
   *Fh = wn * Ih / X->dts;
   *Fb = wn * Ib / X->dts;
 }
 
-static void cell_grad_W(const or_case* c, const double* W, double* gW) {
+static void cell_grad_W(const or_case* c, const real* W, real* gW) {
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < c->ncell; n++) {
-    double* g = gW + (size_t)n * 2 * c->nw;
+    real* g = gW + (size_t)n * 2 * c->nw;
     for (int m = 0; m < 2 * c->nw; m++) g[m] = 0.0;
     if (c->type[n] == OR_HOLE) continue;
     acc_t A = {W, c->winf, c->nw};
@@ -1087,11 +1096,11 @@ static void cell_grad_W(const or_case* c, const double* W, double* gW) {
   }
 }
 
-void or_flux(const or_case* c, double dts, const double* h, const double* b,
-             const double* W, const double* q, double* Dh, double* Db,
-             double* F, double* wall) {
+void or_flux(const or_case* c, real dts, const real* h, const real* b,
+             const real* W, const real* q, real* Dh, real* Db,
+             real* F, real* wall) {
   flux_ctx X = {c, h, b, W, q, NULL, NULL, dts};
-  X.gW = (double*)malloc(sizeof(double) * 2 * c->nw * (size_t)c->ncell);
+  X.gW = (real*)malloc(sizeof(real) * 2 * c->nw * (size_t)c->ncell);
   X.rec = (frec_t*)calloc(c->nface > 0 ? c->nface : 1, sizeof(frec_t));
   cell_grad_W(c, W, X.gW);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -1099,11 +1108,11 @@ void or_flux(const or_case* c, double dts, const double* h, const double* b,
   /* macro flux per face (Eq. macroscopicFlux) */
 #pragma omp parallel for schedule(dynamic, 4)
   for (int f = 0; f < c->nface; f++) {
-    double Fm[4] = {0, 0, 0, 0};
+    real Fm[4] = {0, 0, 0, 0};
     for (int k = 0; k < c->nv; k++) {
-      double fh, fb;
+      real fh, fb;
       face_flux_k(&X, f, k, &fh, &fb);
-      double vx = c->vk_x[k], vy = c->vk_y[k], w = c->wk[k];
+      real vx = c->vk_x[k], vy = c->vk_y[k], w = c->wk[k];
       Fm[0] += w * fh;
       Fm[1] += w * vx * fh;
       if (c->dim == 2) Fm[2] += w * vy * fh;
@@ -1111,7 +1120,7 @@ void or_flux(const or_case* c, double dts, const double* h, const double* b,
     }
     for (int m = 0; m < c->nw; m++) F[(size_t)f * c->nw + m] = Fm[m];
     if (wall) {
-      double* o = wall + (size_t)f * (1 + c->nw);
+      real* o = wall + (size_t)f * (1 + c->nw);
       for (int m = 0; m <= c->nw; m++) o[m] = 0.0;
       if (c->face[f].kind == F_WALL && X.rec[f].active) {
         o[0] = X.rec[f].rhow;
@@ -1122,16 +1131,16 @@ void or_flux(const or_case* c, double dts, const double* h, const double* b,
   /* divergence, gathered per cell: D = -(1/|Omega|) sum_f sigma S F */
 #pragma omp parallel for schedule(dynamic, 4)
   for (int n = 0; n < c->ncell; n++) {
-    double* dh = Dh + (size_t)n * c->nv;
-    double* db = Db + (size_t)n * c->nv;
+    real* dh = Dh + (size_t)n * c->nv;
+    real* db = Db + (size_t)n * c->nv;
     for (int k = 0; k < c->nv; k++) { dh[k] = 0.0; db[k] = 0.0; }
     if (c->type[n] != OR_FIELD) continue;
     for (int s = 0; s < 4; s++) {
       int f = c->cface[4 * n + s];
       if (f < 0) continue;
-      double sg = (double)c->csign[4 * n + s], S = c->face[f].S;
+      real sg = (real)c->csign[4 * n + s], S = c->face[f].S;
       for (int k = 0; k < c->nv; k++) {
-        double fh, fb;
+        real fh, fb;
         face_flux_k(&X, f, k, &fh, &fb);
         dh[k] -= sg * S * fh / c->vol[n];
         db[k] -= sg * S * fb / c->vol[n];
@@ -1147,12 +1156,12 @@ void or_flux(const or_case* c, double dts, const double* h, const double* b,
 /* ------------------------------------------------------------------------ */
 /* rows r0 .. r0+nrow-1 of the donor table; their donors are not rows of
    the same call, so the rows are independent */
-static void interp_rows(const or_case* c, int r0, int nrow, double* h, double* b, double* W, double* q) {
+static void interp_rows(const or_case* c, int r0, int nrow, real* h, real* b, real* W, real* q) {
 #pragma omp parallel for schedule(static)
   for (int r = r0; r < r0 + nrow; r++) {
     int n = c->rec[r];
     for (int k = 0; k < c->nv; k++) {
-      double sh = 0.0, sb = 0.0;
+      real sh = 0.0, sb = 0.0;
       for (int p = c->dptr[r]; p < c->dptr[r + 1]; p++) {
         sh += c->dw[p] * h[(size_t)c->don[p] * c->nv + k];
         sb += c->dw[p] * b[(size_t)c->don[p] * c->nv + k];
@@ -1161,20 +1170,20 @@ static void interp_rows(const or_case* c, int r0, int nrow, double* h, double* b
       b[(size_t)n * c->nv + k] = sb;
     }
     for (int m = 0; m < c->nw; m++) {
-      double s = 0.0;
+      real s = 0.0;
       for (int p = c->dptr[r]; p < c->dptr[r + 1]; p++) s += c->dw[p] * W[(size_t)c->don[p] * c->nw + m];
       W[(size_t)n * c->nw + m] = s;
     }
     if (q)
       for (int m = 0; m < c->dim; m++) {
-        double s = 0.0;
+        real s = 0.0;
         for (int p = c->dptr[r]; p < c->dptr[r + 1]; p++) s += c->dw[p] * q[(size_t)c->don[p] * c->dim + m];
         q[(size_t)n * c->dim + m] = s;
       }
   }
 }
 
-void or_interp(const or_case* c, double* h, double* b, double* W, double* q) {
+void or_interp(const or_case* c, real* h, real* b, real* W, real* q) {
   interp_rows(c, 0, c->nrec, h, b, W, q);
 }
 
@@ -1182,9 +1191,9 @@ void or_interp(const or_case* c, double* h, double* b, double* W, double* q) {
 /* dual time stepping (Sec. 2.2)                                             */
 /* ------------------------------------------------------------------------ */
 /* Shakhov equilibrium h+ = H + H+, b+ = B + B+ of (W, q) at velocity k */
-static void fplus(const or_case* c, double rho, const double* u, double lam, const double* q,
-                  int k, double* hp, double* bp) {
-  double H, B, Hs, Bs, v[2] = {c->vk_x[k], c->vk_y[k]};
+static void fplus(const or_case* c, real rho, const real* u, real lam, const real* q,
+                  int k, real* hp, real* bp) {
+  real H, B, Hs, Bs, v[2] = {c->vk_x[k], c->vk_y[k]};
   maxw(c, rho, u, lam, v[0], v[1], &H, &B);
   or_shakhov(c->dim, c->pr, rho, u, lam, q, v, &Hs, &Bs);
   *hp = H + Hs;
@@ -1192,11 +1201,11 @@ static void fplus(const or_case* c, double rho, const double* u, double lam, con
 }
 
 /* Steps 1-2: S = f^n/dt + r^n/2, r^n = D^n + (f+^n - f^n)/tau^n (Eq. residual_macro_n) */
-void or_begin_step(or_case* c, double dt, double dts, double* h, double* b,
-                   double* W, double* q, double* Sh, double* Sb, double* Fn) {
+void or_begin_step(or_case* c, real dt, real dts, real* h, real* b,
+                   real* W, real* q, real* Sh, real* Sb, real* Fn) {
   size_t N = (size_t)c->ncell * c->nv;
-  double* Dh = (double*)malloc(sizeof(double) * N);
-  double* Db = (double*)malloc(sizeof(double) * N);
+  real* Dh = (real*)malloc(sizeof(real) * N);
+  real* Db = (real*)malloc(sizeof(real) * N);
   /* once after an assembly the cells uncovered from holes (their donors
      are cells that were live), then the receptors (which may use them) */
   interp_rows(c, c->nrec, c->nref, h, b, W, q);
@@ -1205,14 +1214,14 @@ void or_begin_step(or_case* c, double dt, double dts, double* h, double* b,
   or_flux(c, dts, h, b, W, q, Dh, Db, Fn, NULL);
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < c->ncell; n++) {
-    double rho, u[2], lam, qq[2] = {0, 0};
+    real rho, u[2], lam, qq[2] = {0, 0};
     prim(c, W + (size_t)n * c->nw, &rho, u, &lam);
     for (int i = 0; i < c->dim; i++) qq[i] = q[(size_t)n * c->dim + i];
-    double it = inv_tau(c, rho, lam);
+    real it = inv_tau(c, rho, lam);
     for (int k = 0; k < c->nv; k++) {
       size_t o = (size_t)n * c->nv + k;
       if (c->type[n] != OR_FIELD) { Sh[o] = 0.0; Sb[o] = 0.0; continue; }
-      double hp, bp;
+      real hp, bp;
       fplus(c, rho, u, lam, qq, k, &hp, &bp);
       Sh[o] = h[o] / dt + 0.5 * (Dh[o] + (hp - h[o]) * it);
       Sb[o] = b[o] / dt + 0.5 * (Db[o] + (bp - b[o]) * it);
@@ -1223,28 +1232,28 @@ void or_begin_step(or_case* c, double dt, double dts, double* h, double* b,
 
 /* ALE Euler flux F_E(W; n, U) = (rho th, rho V th + p n, rho E th + p V.n),
    th = (V - U).n */
-static void euler_flux(const or_case* c, const double* W, double nx, double ny,
-                       double ux, double uy, double* Fe) {
-  double rho, u[2], lam;
+static void euler_flux(const or_case* c, const real* W, real nx, real ny,
+                       real ux, real uy, real* Fe) {
+  real rho, u[2], lam;
   prim(c, W, &rho, u, &lam);
-  double p = rho / (2.0 * lam);
+  real p = rho / (2.0 * lam);
   int d = c->dim;
-  double th = (u[0] - ux) * nx + ((d == 2) ? (u[1] - uy) * ny : 0.0);
+  real th = (u[0] - ux) * nx + ((d == 2) ? (u[1] - uy) * ny : 0.0);
   Fe[0] = rho * th;
   Fe[1] = W[1] * th + p * nx;
   if (d == 2) Fe[2] = W[2] * th + p * ny;
   Fe[d + 1] = W[d + 1] * th + p * (u[0] * nx + ((d == 2) ? u[1] * ny : 0.0));
 }
 
-static double sound(const or_case* c, const double* W) {
-  double rho, u[2], lam;
+static real sound(const or_case* c, const real* W) {
+  real rho, u[2], lam;
   prim(c, W, &rho, u, &lam);
-  double gam = (double)(c->dim + c->nxi + 2) / (double)(c->dim + c->nxi);
+  real gam = (real)(c->dim + c->nxi + 2) / (real)(c->dim + c->nxi);
   return sqrt(gam / (2.0 * lam));
 }
 
 /* W of the neighbour across face slot s of cell n, for the spectral radius */
-static const double* nb_W(const or_case* c, const double* W, int n, int s) {
+static const real* nb_W(const or_case* c, const real* W, int n, int s) {
   int f = c->cface[4 * n + s];
   const face_t* F = &c->face[f];
   if (F->kind == F_GHOST) return (F->gkind == NB_FF) ? c->winf : W + (size_t)F->gcell * c->nw;
@@ -1254,23 +1263,23 @@ static const double* nb_W(const or_case* c, const double* W, int n, int s) {
 
 /* spectral radius Gamma of the face in slot s of cell n (Sec. 2.2; reading:
    arithmetic means of both sides; a wall face uses the cell alone) */
-static double face_gamma(const or_case* c, const double* W, int n, int s) {
+static real face_gamma(const or_case* c, const real* W, int n, int s) {
   int f = c->cface[4 * n + s];
   const face_t* F = &c->face[f];
-  const double* Wi = W + (size_t)n * c->nw;
-  double ri, ui[2], li;
+  const real* Wi = W + (size_t)n * c->nw;
+  real ri, ui[2], li;
   prim(c, Wi, &ri, ui, &li);
-  double ai = sound(c, Wi);
+  real ai = sound(c, Wi);
   if (F->kind == F_WALL) {
-    double th = (ui[0] - F->ux) * F->nx + ((c->dim == 2) ? (ui[1] - F->uy) * F->ny : 0.0);
+    real th = (ui[0] - F->ux) * F->nx + ((c->dim == 2) ? (ui[1] - F->uy) * F->ny : 0.0);
     return fabs(th) + ai;
   }
-  const double* Wj = nb_W(c, W, n, s);
-  double rj, uj[2], lj;
+  const real* Wj = nb_W(c, W, n, s);
+  real rj, uj[2], lj;
   prim(c, Wj, &rj, uj, &lj);
-  double aj = sound(c, Wj);
-  double mx = 0.5 * (ui[0] + uj[0]), my = 0.5 * (ui[1] + uj[1]);
-  double th = (mx - F->ux) * F->nx + ((c->dim == 2) ? (my - F->uy) * F->ny : 0.0);
+  real aj = sound(c, Wj);
+  real mx = 0.5 * (ui[0] + uj[0]), my = 0.5 * (ui[1] + uj[1]);
+  real th = (mx - F->ux) * F->nx + ((c->dim == 2) ? (my - F->uy) * F->ny : 0.0);
   return fabs(th) + 0.5 * (ai + aj);
 }
 
@@ -1290,24 +1299,24 @@ static int field_nb(const or_case* c, int n, int s) {
  * cell's own dF_E term cancels (sum_f S n = 0 and sum_f S U.n = 0 for a rigid
  * cell).  Order: ascending global cell index (lexicographic per block).
  */
-void or_macro_lusgs(const or_case* c, double dt, const double* dtp, const double* W,
-                    const double* Wn, const double* F, const double* Fn, double* Wp,
-                    double* resid) {
+void or_macro_lusgs(const or_case* c, real dt, const real* dtp, const real* W,
+                    const real* Wn, const real* F, const real* Fn, real* Wp,
+                    real* resid) {
   int nw = c->nw;
   size_t NW = (size_t)c->ncell * nw;
-  double* R = (double*)calloc(NW, sizeof(double));
-  double* Dg = (double*)calloc(c->ncell, sizeof(double));
-  double* dWs = (double*)calloc(NW, sizeof(double));
-  double* dW = (double*)calloc(NW, sizeof(double));
-  double rs[4] = {0, 0, 0, 0};
+  real* R = (real*)calloc(NW, sizeof(real));
+  real* Dg = (real*)calloc(c->ncell, sizeof(real));
+  real* dWs = (real*)calloc(NW, sizeof(real));
+  real* dW = (real*)calloc(NW, sizeof(real));
+  real rs[4] = {0, 0, 0, 0};
   for (int n = 0; n < c->ncell; n++) {
     if (c->type[n] != OR_FIELD) continue;
-    double sg = 0.0;
+    real sg = 0.0;
     for (int m = 0; m < nw; m++) R[n * nw + m] = -(W[n * nw + m] - Wn[n * nw + m]) / dt;
     for (int s = 0; s < 4; s++) {
       int f = c->cface[4 * n + s];
       if (f < 0) continue;
-      double S = c->face[f].S, sig = (double)c->csign[4 * n + s];
+      real S = c->face[f].S, sig = (real)c->csign[4 * n + s];
       for (int m = 0; m < nw; m++)
         R[n * nw + m] -= sig * S * (F[(size_t)f * nw + m] + Fn[(size_t)f * nw + m]) / (2.0 * c->vol[n]);
       sg += S * face_gamma(c, W, n, s);
@@ -1319,19 +1328,19 @@ void or_macro_lusgs(const or_case* c, double dt, const double* dtp, const double
   /* forward sweep */
   for (int n = 0; n < c->ncell; n++) {
     if (c->type[n] != OR_FIELD) continue;
-    double acc[4] = {0, 0, 0, 0};
+    real acc[4] = {0, 0, 0, 0};
     for (int s = 0; s < 4; s++) {
       int j = field_nb(c, n, s);
       if (j < 0 || j >= n) continue;
       int f = c->cface[4 * n + s];
       const face_t* Fc = &c->face[f];
-      double sig = (double)c->csign[4 * n + s];
-      double nx = sig * Fc->nx, ny = sig * Fc->ny;
-      double Wt[4], F1[4], F0[4];
+      real sig = (real)c->csign[4 * n + s];
+      real nx = sig * Fc->nx, ny = sig * Fc->ny;
+      real Wt[4], F1[4], F0[4];
       for (int m = 0; m < nw; m++) Wt[m] = W[j * nw + m] + dWs[j * nw + m];
       euler_flux(c, Wt, nx, ny, Fc->ux, Fc->uy, F1);
       euler_flux(c, W + (size_t)j * nw, nx, ny, Fc->ux, Fc->uy, F0);
-      double G = face_gamma(c, W, n, s);
+      real G = face_gamma(c, W, n, s);
       for (int m = 0; m < nw; m++) acc[m] += Fc->S * ((F1[m] - F0[m]) - G * dWs[j * nw + m]);
     }
     for (int m = 0; m < nw; m++)
@@ -1340,19 +1349,19 @@ void or_macro_lusgs(const or_case* c, double dt, const double* dtp, const double
   /* backward sweep */
   for (int n = c->ncell - 1; n >= 0; n--) {
     if (c->type[n] != OR_FIELD) continue;
-    double acc[4] = {0, 0, 0, 0};
+    real acc[4] = {0, 0, 0, 0};
     for (int s = 0; s < 4; s++) {
       int j = field_nb(c, n, s);
       if (j < 0 || j <= n) continue;
       int f = c->cface[4 * n + s];
       const face_t* Fc = &c->face[f];
-      double sig = (double)c->csign[4 * n + s];
-      double nx = sig * Fc->nx, ny = sig * Fc->ny;
-      double Wt[4], F1[4], F0[4];
+      real sig = (real)c->csign[4 * n + s];
+      real nx = sig * Fc->nx, ny = sig * Fc->ny;
+      real Wt[4], F1[4], F0[4];
       for (int m = 0; m < nw; m++) Wt[m] = W[j * nw + m] + dW[j * nw + m];
       euler_flux(c, Wt, nx, ny, Fc->ux, Fc->uy, F1);
       euler_flux(c, W + (size_t)j * nw, nx, ny, Fc->ux, Fc->uy, F0);
-      double G = face_gamma(c, W, n, s);
+      real G = face_gamma(c, W, n, s);
       for (int m = 0; m < nw; m++) acc[m] += Fc->S * ((F1[m] - F0[m]) - G * dW[j * nw + m]);
     }
     for (int m = 0; m < nw; m++)
@@ -1375,48 +1384,48 @@ void or_macro_lusgs(const or_case* c, double dt, const double* dtp, const double
  * Neighbours that are not field cells of the same block are explicit.
  * On return h, b hold f^{s+1}.
  */
-void or_micro_lusgs(const or_case* c, double dt, const double* dtp, const double* Wp,
-                    const double* qp, double* h, double* b, const double* Sh,
-                    const double* Sb, const double* Dh, const double* Db) {
+void or_micro_lusgs(const or_case* c, real dt, const real* dtp, const real* Wp,
+                    const real* qp, real* h, real* b, const real* Sh,
+                    const real* Sb, const real* Dh, const real* Db) {
   int nv = c->nv;
-  double* crho = (double*)malloc(sizeof(double) * c->ncell);
-  double* cu = (double*)malloc(sizeof(double) * 2 * c->ncell);
-  double* clam = (double*)malloc(sizeof(double) * c->ncell);
-  double* citau = (double*)malloc(sizeof(double) * c->ncell);
+  real* crho = (real*)malloc(sizeof(real) * c->ncell);
+  real* cu = (real*)malloc(sizeof(real) * 2 * c->ncell);
+  real* clam = (real*)malloc(sizeof(real) * c->ncell);
+  real* citau = (real*)malloc(sizeof(real) * c->ncell);
   for (int n = 0; n < c->ncell; n++) {
     prim(c, Wp + (size_t)n * c->nw, &crho[n], cu + 2 * n, &clam[n]);
     citau[n] = inv_tau(c, crho[n], clam[n]);
   }
 #pragma omp parallel
   {
-    double* xs_h = (double*)malloc(sizeof(double) * c->ncell);
-    double* xs_b = (double*)malloc(sizeof(double) * c->ncell);
-    double* dd = (double*)malloc(sizeof(double) * c->ncell);
+    real* xs_h = (real*)malloc(sizeof(real) * c->ncell);
+    real* xs_b = (real*)malloc(sizeof(real) * c->ncell);
+    real* dd = (real*)malloc(sizeof(real) * c->ncell);
 #pragma omp for schedule(static)
     for (int k = 0; k < nv; k++) {
-      double vx = c->vk_x[k], vy = c->vk_y[k];
+      real vx = c->vk_x[k], vy = c->vk_y[k];
       /* forward sweep: (D + L) df* = r */
       for (int n = 0; n < c->ncell; n++) {
         xs_h[n] = 0.0; xs_b[n] = 0.0;
         if (c->type[n] != OR_FIELD) continue;
         size_t o = (size_t)n * nv + k;
-        double qq[2] = {qp[(size_t)n * c->dim], (c->dim == 2) ? qp[(size_t)n * c->dim + 1] : 0.0};
-        double hp, bp;
+        real qq[2] = {qp[(size_t)n * c->dim], (c->dim == 2) ? qp[(size_t)n * c->dim + 1] : 0.0};
+        real hp, bp;
         fplus(c, crho[n], cu + 2 * n, clam[n], qq, k, &hp, &bp);
-        double rh = Sh[o] - h[o] / dt + 0.5 * (Dh[o] + (hp - h[o]) * citau[n]);
-        double rb = Sb[o] - b[o] / dt + 0.5 * (Db[o] + (bp - b[o]) * citau[n]);
-        double diag = 1.0 / dtp[n] + 1.0 / dt + 0.5 * citau[n];
-        double offh = 0.0, offb = 0.0;
+        real rh = Sh[o] - h[o] / dt + 0.5 * (Dh[o] + (hp - h[o]) * citau[n]);
+        real rb = Sb[o] - b[o] / dt + 0.5 * (Db[o] + (bp - b[o]) * citau[n]);
+        real diag = 1.0 / dtp[n] + 1.0 / dt + 0.5 * citau[n];
+        real offh = 0.0, offb = 0.0;
         for (int s = 0; s < 4; s++) {
           int f = c->cface[4 * n + s];
           if (f < 0) continue;
           const face_t* F = &c->face[f];
-          double sig = (double)c->csign[4 * n + s];
-          double wn = sig * ((vx - F->ux) * F->nx + (vy - F->uy) * F->ny);
+          real sig = (real)c->csign[4 * n + s];
+          real wn = sig * ((vx - F->ux) * F->nx + (vy - F->uy) * F->ny);
           diag += F->S * ((wn > 0.0) ? wn : 0.0) / (2.0 * c->vol[n]);
           int j = field_nb(c, n, s);
           if (j < 0 || j >= n) continue;
-          double wm = (wn < 0.0) ? wn : 0.0;
+          real wm = (wn < 0.0) ? wn : 0.0;
           offh += F->S * wm * xs_h[j];
           offb += F->S * wm * xs_b[j];
         }
@@ -1427,15 +1436,15 @@ void or_micro_lusgs(const or_case* c, double dt, const double* dtp, const double
       /* backward sweep: (D + U) df = D df* ; overwrite xs with df */
       for (int n = c->ncell - 1; n >= 0; n--) {
         if (c->type[n] != OR_FIELD) continue;
-        double offh = 0.0, offb = 0.0;
+        real offh = 0.0, offb = 0.0;
         for (int s = 0; s < 4; s++) {
           int j = field_nb(c, n, s);
           if (j < 0 || j <= n) continue;
           int f = c->cface[4 * n + s];
           const face_t* F = &c->face[f];
-          double sig = (double)c->csign[4 * n + s];
-          double wn = sig * ((vx - F->ux) * F->nx + (vy - F->uy) * F->ny);
-          double wm = (wn < 0.0) ? wn : 0.0;
+          real sig = (real)c->csign[4 * n + s];
+          real wn = sig * ((vx - F->ux) * F->nx + (vy - F->uy) * F->ny);
+          real wm = (wn < 0.0) ? wn : 0.0;
           offh += F->S * wm * xs_h[j];
           offb += F->S * wm * xs_b[j];
         }
@@ -1455,22 +1464,22 @@ void or_micro_lusgs(const or_case* c, double dt, const double* dtp, const double
 
 /* Step 7 (reading of the garbled formula): W^{s+1} = W' + sum_k V_k Psi_k
    (f^{s+1} - g(W')), g the plain Maxwellian of W' */
-void or_step7(const or_case* c, const double* Wp, const double* h, const double* b, double* W) {
+void or_step7(const or_case* c, const real* Wp, const real* h, const real* b, real* W) {
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < c->ncell; n++) {
-    const double* wp = Wp + (size_t)n * c->nw;
-    double* w = W + (size_t)n * c->nw;
+    const real* wp = Wp + (size_t)n * c->nw;
+    real* w = W + (size_t)n * c->nw;
     if (c->type[n] != OR_FIELD) { for (int m = 0; m < c->nw; m++) w[m] = wp[m]; continue; }
-    double rho, u[2], lam;
+    real rho, u[2], lam;
     prim(c, wp, &rho, u, &lam);
-    double s[4] = {0, 0, 0, 0};
+    real s[4] = {0, 0, 0, 0};
     int d = c->dim;
     for (int k = 0; k < c->nv; k++) {
-      double H, B;
-      double vx = c->vk_x[k], vy = c->vk_y[k];
+      real H, B;
+      real vx = c->vk_x[k], vy = c->vk_y[k];
       maxw(c, rho, u, lam, vx, vy, &H, &B);
-      double dh = h[(size_t)n * c->nv + k] - H, db = b[(size_t)n * c->nv + k] - B;
-      double wk = c->wk[k];
+      real dh = h[(size_t)n * c->nv + k] - H, db = b[(size_t)n * c->nv + k] - B;
+      real wk = c->wk[k];
       s[0] += wk * dh;
       s[1] += wk * vx * dh;
       if (d == 2) s[2] += wk * vy * dh;
@@ -1481,18 +1490,19 @@ void or_step7(const or_case* c, const double* Wp, const double* h, const double*
 }
 
 /* Steps 3-7: one inner iteration of the dual time stepping */
-void or_pseudo_step(const or_case* c, double dt, double dts, const double* dtp,
-                    double* h, double* b, double* W, const double* Wn, double* q,
-                    const double* Sh, const double* Sb, const double* Fn,
-                    double* resid) {
+void or_pseudo_step(const or_case* c, real dt, real dts, const real* dtp,
+                    real* h, real* b, real* W, const real* Wn, real* q,
+                    const real* Sh, const real* Sb, const real* Fn,
+                    real* resid, real* Fout) {
   size_t N = (size_t)c->ncell * c->nv, NW = (size_t)c->ncell * c->nw;
-  double* Dh = (double*)malloc(sizeof(double) * N);
-  double* Db = (double*)malloc(sizeof(double) * N);
-  double* F = (double*)malloc(sizeof(double) * (size_t)(c->nface > 0 ? c->nface : 1) * c->nw);
-  double* Wp = (double*)malloc(sizeof(double) * NW);
-  double* qp = (double*)malloc(sizeof(double) * (size_t)c->ncell * c->dim);
+  real* Dh = (real*)malloc(sizeof(real) * N);
+  real* Db = (real*)malloc(sizeof(real) * N);
+  real* F = (real*)malloc(sizeof(real) * (size_t)(c->nface > 0 ? c->nface : 1) * c->nw);
+  real* Wp = (real*)malloc(sizeof(real) * NW);
+  real* qp = (real*)malloc(sizeof(real) * (size_t)c->ncell * c->dim);
   or_interp(c, h, b, W, q);                                  /* receptors first */
   or_flux(c, dts, h, b, W, q, Dh, Db, F, NULL);              /* Step 3 */
+  if (Fout) memcpy(Fout, F, sizeof(real) * (size_t)c->nface * c->nw);
   or_macro_lusgs(c, dt, dtp, W, Wn, F, Fn, Wp, resid);       /* Step 4 */
   or_heatflux(c, h, b, Wp, qp);                              /* q' from f^s about V' */
   or_micro_lusgs(c, dt, dtp, Wp, qp, h, b, Sh, Sb, Dh, Db);  /* Steps 5-6 */
@@ -1514,18 +1524,18 @@ void or_pseudo_step(const or_case* c, double dt, double dts, const double* dtp,
 /*   inside a body:  crossing number against each closed wall polygon of     */
 /*                   the other zones (half-open in y).                       */
 /* ------------------------------------------------------------------------ */
-static int quad_contains(const double* qx, const double* qy, double px, double py) {
+static int quad_contains(const real* qx, const real* qy, real px, real py) {
   int pos = 0, neg = 0;
   for (int k = 0; k < 4; k++) {
     int k1 = (k + 1) % 4;
-    double cr = (qx[k1] - qx[k]) * (py - qy[k]) - (qy[k1] - qy[k]) * (px - qx[k]);
+    real cr = (qx[k1] - qx[k]) * (py - qy[k]) - (qy[k1] - qy[k]) * (px - qx[k]);
     if (cr > 0.0) pos = 1;
     if (cr < 0.0) neg = 1;
   }
   return !(pos && neg);
 }
 
-static void cell_quad(const or_case* c, int n, double* qx, double* qy) {
+static void cell_quad(const or_case* c, int n, real* qx, real* qy) {
   int b = c->cblk[n], i = c->ci[n], j = c->cj[n];
   qx[0] = node_x(c, b, i, j);         qy[0] = node_y(c, b, i, j);
   qx[1] = node_x(c, b, i + 1, j);     qy[1] = node_y(c, b, i + 1, j);
@@ -1533,21 +1543,21 @@ static void cell_quad(const or_case* c, int n, double* qx, double* qy) {
   qx[3] = node_x(c, b, i, j + 1);     qy[3] = node_y(c, b, i, j + 1);
 }
 
-static double seg_dist2(double px, double py, double ax, double ay, double bx, double by) {
-  double ex = bx - ax, ey = by - ay;
-  double l2 = ex * ex + ey * ey;
-  double t = 0.0;
+static real seg_dist2(real px, real py, real ax, real ay, real bx, real by) {
+  real ex = bx - ax, ey = by - ay;
+  real l2 = ex * ex + ey * ey;
+  real t = 0.0;
   if (l2 > 0.0) {
     t = ((px - ax) * ex + (py - ay) * ey) / l2;
     if (t < 0.0) t = 0.0;
     if (t > 1.0) t = 1.0;
   }
-  double dx = px - (ax + t * ex), dy = py - (ay + t * ey);
+  real dx = px - (ax + t * ex), dy = py - (ay + t * ey);
   return dx * dx + dy * dy;
 }
 
 /* the nodes of wall side s of block b, in order along the side */
-static int side_nodes(const or_case* c, int b, int s, double* x, double* y) {
+static int side_nodes(const or_case* c, int b, int s, real* x, real* y) {
   const blk_t* B = &c->blk[b];
   int n = (s < 2) ? B->nj + 1 : B->ni + 1;
   for (int m = 0; m < n; m++) {
@@ -1565,20 +1575,20 @@ static int side_closed(const or_case* c, int b, int s) {
   return (s < 2) ? B->bc[2] == OR_PERIODIC : B->bc[0] == OR_PERIODIC;
 }
 
-static double wall_dist2(const or_case* c, int b, double px, double py, double* bx, double* by) {
-  double d2 = INFINITY;
+static real wall_dist2(const or_case* c, int b, real px, real py, real* bx, real* by) {
+  real d2 = INFINITY;
   for (int s = 0; s < 4; s++) {
     if (c->blk[b].bc[s] != OR_WALL) continue;
     int n = side_nodes(c, b, s, bx, by);
     for (int m = 0; m + 1 < n; m++) {
-      double e = seg_dist2(px, py, bx[m], by[m], bx[m + 1], by[m + 1]);
+      real e = seg_dist2(px, py, bx[m], by[m], bx[m + 1], by[m + 1]);
       if (e < d2) d2 = e;
     }
   }
   return d2;
 }
 
-static int inside_body(const or_case* c, int self, double px, double py, double* bx, double* by) {
+static int inside_body(const or_case* c, int self, real px, real py, real* bx, real* by) {
   for (int b = 0; b < c->nblock; b++) {
     if (b == self) continue;
     for (int s = 0; s < 4; s++) {
@@ -1586,9 +1596,9 @@ static int inside_body(const or_case* c, int self, double px, double py, double*
       int n = side_nodes(c, b, s, bx, by);
       int in = 0;
       for (int m = 0; m + 1 < n; m++) {
-        double ax = bx[m], ay = by[m], ex = bx[m + 1], ey = by[m + 1];
+        real ax = bx[m], ay = by[m], ex = bx[m + 1], ey = by[m + 1];
         if ((ay > py) != (ey > py)) {
-          double xi = ax + (py - ay) * (ex - ax) / (ey - ay);
+          real xi = ax + (py - ay) * (ex - ax) / (ey - ay);
           if (px < xi) in = !in;
         }
       }
@@ -1612,9 +1622,9 @@ static int overset_depth(const or_case* c, int n) {
 
 /* lowest cell of block b containing (px, py), restricted to field cells
    when `types` is given; -1 if none */
-static int containing_cell(const or_case* c, int b, double px, double py, const int8_t* types) {
+static int containing_cell(const or_case* c, int b, real px, real py, const int8_t* types) {
   const blk_t* B = &c->blk[b];
-  double qx[4], qy[4];
+  real qx[4], qy[4];
   for (int n = B->cell0; n < B->cell0 + B->ni * B->nj; n++) {
     if (types && types[n] != OR_FIELD) continue;
     cell_quad(c, n, qx, qy);
@@ -1646,16 +1656,16 @@ static int index_nb(const or_case* c, int n, int dir, int side) {
 
 /* bilinear weights of (px, py) in the quad of cell centres n[0..3] (Newton
    for the inverse bilinear map, three steps from the middle) */
-static void bilinear(const or_case* c, const int* n, double px, double py, double* w) {
-  double x0 = c->cx[n[0]], x1 = c->cx[n[1]], x2 = c->cx[n[2]], x3 = c->cx[n[3]];
-  double y0 = c->cy[n[0]], y1 = c->cy[n[1]], y2 = c->cy[n[2]], y3 = c->cy[n[3]];
-  double s = 0.5, t = 0.5;
+static void bilinear(const or_case* c, const int* n, real px, real py, real* w) {
+  real x0 = c->cx[n[0]], x1 = c->cx[n[1]], x2 = c->cx[n[2]], x3 = c->cx[n[3]];
+  real y0 = c->cy[n[0]], y1 = c->cy[n[1]], y2 = c->cy[n[2]], y3 = c->cy[n[3]];
+  real s = 0.5, t = 0.5;
   for (int it = 0; it < 3; it++) {
-    double rx = (1.0 - s) * (1.0 - t) * x0 + s * (1.0 - t) * x1 + s * t * x2 + (1.0 - s) * t * x3 - px;
-    double ry = (1.0 - s) * (1.0 - t) * y0 + s * (1.0 - t) * y1 + s * t * y2 + (1.0 - s) * t * y3 - py;
-    double xs = (1.0 - t) * (x1 - x0) + t * (x2 - x3), ys = (1.0 - t) * (y1 - y0) + t * (y2 - y3);
-    double xt = (1.0 - s) * (x3 - x0) + s * (x2 - x1), yt = (1.0 - s) * (y3 - y0) + s * (y2 - y1);
-    double det = xs * yt - xt * ys;
+    real rx = (1.0 - s) * (1.0 - t) * x0 + s * (1.0 - t) * x1 + s * t * x2 + (1.0 - s) * t * x3 - px;
+    real ry = (1.0 - s) * (1.0 - t) * y0 + s * (1.0 - t) * y1 + s * t * y2 + (1.0 - s) * t * y3 - py;
+    real xs = (1.0 - t) * (x1 - x0) + t * (x2 - x3), ys = (1.0 - t) * (y1 - y0) + t * (y2 - y3);
+    real xt = (1.0 - s) * (x3 - x0) + s * (x2 - x1), yt = (1.0 - s) * (y3 - y0) + s * (y2 - y1);
+    real det = xs * yt - xt * ys;
     s -= (rx * yt - xt * ry) / det;
     t -= (xs * ry - rx * ys) / det;
   }
@@ -1667,8 +1677,8 @@ static void bilinear(const or_case* c, const int* n, double px, double py, doubl
    quad of donor-grid centroids around it (wrule 1, when such a quad of field
    cells contains it), else inverse distance squared over the donor and its
    field index neighbours.  Returns the donor count, or -1 if none. */
-static int donors_of(const or_case* c, const int8_t* ty, int n, int wrule, int* don, double* w) {
-  double px = c->cx[n], py = c->cy[n];
+static int donors_of(const or_case* c, const int8_t* ty, int n, int wrule, int* don, real* w) {
+  real px = c->cx[n], py = c->cy[n];
   int d = -1;
   for (int z = 0; z < c->nblock && d < 0; z++)
     if (z != c->cblk[n]) d = containing_cell(c, z, px, py, ty);
@@ -1687,7 +1697,7 @@ static int donors_of(const or_case* c, const int8_t* ty, int n, int wrule, int* 
       int ok = 1;
       for (int k = 0; k < 4; k++) ok = ok && nq[k] >= 0 && ty[nq[k]] == OR_FIELD;
       if (!ok) continue;
-      double qx[4], qy[4];
+      real qx[4], qy[4];
       for (int k = 0; k < 4; k++) { qx[k] = c->cx[nq[k]]; qy[k] = c->cy[nq[k]]; }
       if (!quad_contains(qx, qy, px, py)) continue;
       bilinear(c, nq, px, py, w);
@@ -1704,10 +1714,10 @@ static int donors_of(const or_case* c, const int8_t* ty, int n, int wrule, int* 
       for (int k = 0; k < ns; k++) dup = dup || set[k] == m;
       if (!dup) set[ns++] = m;
     }
-  double d2[5];
+  real d2[5];
   int exact = -1;
   for (int k = 0; k < ns; k++) {
-    double dx = c->cx[set[k]] - px, dy = c->cy[set[k]] - py;
+    real dx = c->cx[set[k]] - px, dy = c->cy[set[k]] - py;
     d2[k] = dx * dx + dy * dy;
     if (exact < 0 && d2[k] <= 1e-28 * c->vol[set[k]]) exact = k;
   }
@@ -1715,7 +1725,7 @@ static int donors_of(const or_case* c, const int8_t* ty, int n, int wrule, int* 
     don[0] = set[exact]; w[0] = 1.0;
     return 1;
   }
-  double sum = 0.0;
+  real sum = 0.0;
   for (int k = 0; k < ns; k++) sum += 1.0 / d2[k];
   for (int k = 0; k < ns; k++) { don[k] = set[k]; w[k] = (1.0 / d2[k]) / sum; }
   return ns;
@@ -1730,8 +1740,8 @@ int or_assemble(or_case* c, int wrule, int overlap, int* nrec_out) {
     if (c->blk[b].ni + 1 > maxside) maxside = c->blk[b].ni + 1;
     if (c->blk[b].nj + 1 > maxside) maxside = c->blk[b].nj + 1;
   }
-  double* bx = (double*)malloc(sizeof(double) * maxside);
-  double* by = (double*)malloc(sizeof(double) * maxside);
+  real* bx = (real*)malloc(sizeof(real) * maxside);
+  real* by = (real*)malloc(sizeof(real) * maxside);
   /* 1. node classes: inactive inside another zone's body, or where another
         zone has a cell containing the node (its lowest such cell lying at
         least overlap + 3 layers inside that zone's overset sides) and a
@@ -1744,14 +1754,14 @@ int or_assemble(or_case* c, int wrule, int overlap, int* nrec_out) {
     const blk_t* B = &c->blk[b];
     for (int j = 0; j <= B->nj; j++)
       for (int i = 0; i <= B->ni; i++) {
-        double px = node_x(c, b, i, j), py = node_y(c, b, i, j);
+        real px = node_x(c, b, i, j), py = node_y(c, b, i, j);
         int off = inside_body(c, b, px, py, bx, by);
-        double da = wall_dist2(c, b, px, py, bx, by);
+        real da = wall_dist2(c, b, px, py, bx, by);
         for (int z = 0; z < c->nblock && !off; z++) {
           if (z == b) continue;
           int m = containing_cell(c, z, px, py, NULL);
           if (m < 0 || overset_depth(c, m) < cut) continue;
-          double dz = wall_dist2(c, z, px, py, bx, by);
+          real dz = wall_dist2(c, z, px, py, bx, by);
           if (dz < da || (dz == da && z > b)) off = 1;
         }
         inact[c->node0[b] + i + (B->ni + 1) * j] = (int8_t)off;
@@ -1793,7 +1803,7 @@ int or_assemble(or_case* c, int wrule, int overlap, int* nrec_out) {
   int* rec = (int*)malloc(sizeof(int) * (nrow > 0 ? nrow : 1));
   int* ptr = (int*)malloc(sizeof(int) * (nrow + 1));
   int* don = (int*)malloc(sizeof(int) * (5 * nrow > 0 ? 5 * nrow : 1));
-  double* w = (double*)malloc(sizeof(double) * (5 * nrow > 0 ? 5 * nrow : 1));
+  real* w = (real*)malloc(sizeof(real) * (5 * nrow > 0 ? 5 * nrow : 1));
   /* refill cells take donors among the cells that were not holes, so that
      they can be filled before the receptors (which may use them) */
   int8_t* tyr = (int8_t*)malloc(ncell > 0 ? ncell : 1);

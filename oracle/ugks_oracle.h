@@ -20,6 +20,15 @@
 #define UGKS_ORACLE_H
 #include <stdint.h>
 
+/* Scalar type of every value: double.  The tangent build (ugks_oracle_tl.cpp)
+   compiles this same source as C++ with a forward-mode dual number instead,
+   which carries one directional derivative beside each value. */
+#ifdef OR_TANGENT
+#include "or_dual.h"
+#else
+typedef double real;
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -50,10 +59,10 @@ typedef struct or_case or_case;
  *               (ni+1)*(nj+1) values, index i + (ni+1)*j (1D: x only, ni+1).
  * Returns NULL on bad input.
  */
-or_case* or_create(int dim, const double* gas, const int* nv, const double* vrange,
-                   const double* vx, const double* vy, const double* winf,
-                   const double* cfl, int nblock, const int* bint,
-                   const double* bdbl, const double* nodes);
+or_case* or_create(int dim, const real* gas, const int* nv, const real* vrange,
+                   const real* vx, const real* vy, const real* winf,
+                   const real* cfl, int nblock, const int* bint,
+                   const real* bdbl, const real* nodes);
 void or_free(or_case* c);
 
 int or_ncell(const or_case* c);
@@ -62,21 +71,24 @@ int or_nv(const or_case* c);
 
 /* rigid pose of a block: translation (dx,dy), rotation th about the moved
    centre, and the rigid velocity (ux,uy) and angular velocity om. */
-void or_set_pose(or_case* c, int blk, double dx, double dy, double th,
-                 double ux, double uy, double om);
+void or_set_pose(or_case* c, int blk, real dx, real dy, real th,
+                 real ux, real uy, real om);
+/* wall RT of side `side` (0 i-min, 1 i-max, 2 j-min, 3 j-max) of a wall
+   block side, for the faces already built */
+void or_set_wall_rt(or_case* c, int blk, int side, real rtw);
 /* node positions, cell and face geometry, face grid velocity at the current
    poses. */
 void or_update_geometry(or_case* c);
 
 /* velocity points and quadrature weights V_k (k = ix + nvx*iy) */
-void or_dvs(const or_case* c, double* vx, double* vy, double* wk);
+void or_dvs(const or_case* c, real* vx, real* vy, real* wk);
 /* one-axis composite Newton-Cotes weights (reading of the velocity grid) */
-void or_nc_weights(int n, double a, double b, double* w);
+void or_nc_weights(int n, real a, real b, real* w);
 
 /* geometry export: cell centroid [ncell][2], volume, metric [ncell][4];
    face L,R (cell or -1-side), normal [2], area, centre [2], grid velocity [2] */
-void or_geometry(const or_case* c, double* cx, double* vol, double* g,
-                 int* fl, int* fr, double* fn, double* fs, double* fx, double* fu);
+void or_geometry(const or_case* c, real* cx, real* vol, real* g,
+                 int* fl, int* fr, real* fn, real* fs, real* fx, real* fu);
 
 /* structured position of every face: block, direction (0 i, 1 j) and the
    (i, j) of the face in its block's face grid */
@@ -85,66 +97,67 @@ void or_face_ids(const or_case* c, int* blk, int* dir, int* fi, int* fj);
 void or_set_types(or_case* c, const int8_t* type);
 void or_get_types(const or_case* c, int8_t* type);
 void or_set_overset(or_case* c, int nrec, const int* rec, const int* ptr,
-                    const int* don, const double* w);
+                    const int* don, const real* w);
 
 /* discrete reduced Maxwellian (H,B) of W at every cell (no Shakhov part) */
-void or_maxwellian(const or_case* c, const double* W, double* h, double* b);
+void or_maxwellian(const or_case* c, const real* W, real* h, real* b);
 /* W = sum_k V_k Psi_k f and q about the velocity of that W, every cell */
-void or_moments(const or_case* c, const double* h, const double* b, double* W, double* q);
+void or_moments(const or_case* c, const real* h, const real* b, real* W, real* q);
 /* heat flux of f about the velocity of a given W (every cell) */
-void or_heatflux(const or_case* c, const double* h, const double* b, const double* W, double* q);
+void or_heatflux(const or_case* c, const real* h, const real* b, const real* W, real* q);
 
 /* explicit flux time step dt_s (global) and virtual steps dtp[ncell] */
-double or_timesteps(const or_case* c, double* dtp);
+real or_timesteps(const or_case* c, real* dtp);
 
 /* time-integration coefficients q1..q5 of the interface solution */
-void or_time_coeffs(double dts, double tau, double* q);
+void or_time_coeffs(real dts, real tau, real* q);
 /* equilibrium slope and time coefficients: a[d][nw], A[nw] */
-void or_slope_coeffs(int dim, double rho, const double* u, double lam,
-                     const double* uf, const double* dW, double* a, double* A);
+void or_slope_coeffs(int dim, real rho, const real* u, real lam,
+                     const real* uf, const real* dW, real* a, real* A);
 /* reduced Shakhov equilibrium at one velocity */
-void or_shakhov(int dim, double pr, double rho, const double* u, double lam,
-                const double* q, const double* v, double* hp, double* bp);
+void or_shakhov(int dim, real pr, real rho, const real* u, real lam,
+                const real* q, const real* v, real* hp, real* bp);
 
 /* Step 1 / Step 3 flux: divergence D[ncell][nv] (h,b), face macro flux
    F[nface][nw] along the face normal, wall output [nface][1+nw]
    (rho_w, then the macro flux into the wall). */
-void or_flux(const or_case* c, double dts, const double* h, const double* b,
-             const double* W, const double* q, double* Dh, double* Db,
-             double* F, double* wall);
+void or_flux(const or_case* c, real dts, const real* h, const real* b,
+             const real* W, const real* q, real* Dh, real* Db,
+             real* F, real* wall);
 
 /* overset interpolation of f, W, q into receptors */
-void or_interp(const or_case* c, double* h, double* b, double* W, double* q);
+void or_interp(const or_case* c, real* h, real* b, real* W, real* q);
 
 /* Steps 1-2: source S = f^n/dt + r^n/2 and the level-n face flux Fn */
-void or_begin_step(or_case* c, double dt, double dts, double* h, double* b,
-                   double* W, double* q, double* Sh, double* Sb, double* Fn);
-/* Steps 3-7, one inner iteration; resid[nw] = L2 norm of R over field cells */
-void or_pseudo_step(const or_case* c, double dt, double dts, const double* dtp,
-                    double* h, double* b, double* W, const double* Wn, double* q,
-                    const double* Sh, const double* Sb, const double* Fn,
-                    double* resid);
+void or_begin_step(or_case* c, real dt, real dts, real* h, real* b,
+                   real* W, real* q, real* Sh, real* Sb, real* Fn);
+/* Steps 3-7, one inner iteration; resid[nw] = L2 norm of R over field cells;
+   Fout[nface][nw] (may be NULL) receives the face macro flux of Step 3 */
+void or_pseudo_step(const or_case* c, real dt, real dts, const real* dtp,
+                    real* h, real* b, real* W, const real* Wn, real* q,
+                    const real* Sh, const real* Sb, const real* Fn,
+                    real* resid, real* Fout);
 
 /* exposed pieces of one inner iteration, for tests */
-void or_macro_lusgs(const or_case* c, double dt, const double* dtp, const double* W,
-                    const double* Wn, const double* F, const double* Fn, double* Wp,
-                    double* resid);
-void or_micro_lusgs(const or_case* c, double dt, const double* dtp, const double* Wp,
-                    const double* qp, double* h, double* b, const double* Sh,
-                    const double* Sb, const double* Dh, const double* Db);
-void or_step7(const or_case* c, const double* Wp, const double* h, const double* b, double* W);
+void or_macro_lusgs(const or_case* c, real dt, const real* dtp, const real* W,
+                    const real* Wn, const real* F, const real* Fn, real* Wp,
+                    real* resid);
+void or_micro_lusgs(const or_case* c, real dt, const real* dtp, const real* Wp,
+                    const real* qp, real* h, real* b, const real* Sh,
+                    const real* Sb, const real* Dh, const real* Db);
+void or_step7(const or_case* c, const real* Wp, const real* h, const real* b, real* W);
 
 /* overset assembly (hole cutting, buffer layer, donors and weights) at the
    current geometry.  wrule 0 = inverse distance squared, 1 = bilinear.
    overlap = fringe depth (cell layers) kept beside an overset boundary.
    Returns 0, or -5 if a receptor has no donor. */
 int or_assemble(or_case* c, int wrule, int overlap, int* nrec_out);
-int or_get_overset(const or_case* c, int* rec, int* ptr, int* don, double* w);
+int or_get_overset(const or_case* c, int* rec, int* ptr, int* don, real* w);
 int or_overset_count(const or_case* c);
 /* rows after the receptors: cells uncovered from holes, filled by the next or_begin_step */
 int or_refill_count(const or_case* c);
 /* current node coordinates, blocks concatenated, (ni+1)(nj+1) per block */
-void or_nodes(const or_case* c, double* x, double* y);
+void or_nodes(const or_case* c, real* x, real* y);
 
 #ifdef __cplusplus
 }
