@@ -288,6 +288,74 @@ int ugks_autotune(ugks_ctx* ctx, double dt, int32_t n_inner, const void* h, cons
                   const double* Wn, const double* q, const void* Sh, const void* Sb, const double* Fn,
                   int32_t* choice, double* best_ms, void* stream);
 
+/*
+ * Wall temperature (Eq. maxWalldes): RT of the isothermal wall on side
+ * `side` (0 i-min, 1 i-max, 2 j-min, 3 j-max) of block `blk`; updates the
+ * face data of that side.  UGKS_E_ARG for a bad block, side or rtw <= 0.
+ */
+int ugks_set_wall_rt(ugks_ctx* ctx, int32_t blk, int32_t side, double rtw);
+
+/* Device copy of the face macro flux F [nface][dim+2] of the last flux
+   evaluation (Step 3 of the last pseudo-iteration run by ugks_step,
+   ugks_step_graph or ugks_step_adjoint's recomputation, or ugks_flux). */
+int ugks_last_flux(const ugks_ctx* ctx, double* F, void* stream);
+
+/*
+ * Reverse mode (hand-written adjoint, vector-Jacobian products) of the
+ * dual-time stepping, for FP64 contexts in 2D (else UGKS_E_UNSUPPORTED).
+ * "x_bar" is the cotangent of x: a device FP64 array in x's layout; output
+ * cotangents of the map are inputs (NULL means zero), input cotangents are
+ * written (not accumulated).  face_bar (may be NULL) receives [nface][5]:
+ * the cotangents of the face grid velocity U_f (x, y; Eq. BGK w = v - U),
+ * of the wall velocity (x, y) and of the wall RT (Eq. maxWalldes) of each
+ * face, so that a rigid body velocity's gradient is the sum of the U_f and
+ * wall-velocity entries over the body's faces, and a wall temperature's the
+ * sum of the RT entries over its faces.  Node positions, cell kinds, donor
+ * tables, dt, dt_s and dt' are held fixed.  At the method's kinks (limiter
+ * switches, upwind sign, positivity fallbacks, |.| of the spectral radius)
+ * the derivative of the branch the forward pass takes is returned.  Each
+ * call recomputes the forward quantities it needs from the given inputs
+ * (the inputs are not modified) and allocates its FP64 workspace (about 14
+ * arrays of [ncell][nv]) on first use; the context's scratch is overwritten.
+ * The cotangent of a hole cell's value is not defined.  Asynchronous on
+ * `stream`.
+ *
+ * ugks_flux_adjoint: the map (h, b, W, q) -> (Dh, Db, F) of ugks_flux at
+ * dt_s (Sec. 2.1, Eqs. microscopicFlux, macroscopicFlux, fullSolution,
+ * maxWalldes).
+ */
+int ugks_flux_adjoint(ugks_ctx* ctx, const void* h, const void* b, const double* W, const double* q,
+                      const double* Dh_bar, const double* Db_bar, const double* F_bar, double* h_bar,
+                      double* b_bar, double* W_bar, double* q_bar, double* face_bar, void* stream);
+
+/*
+ * One inner iteration (Sec. 2.2, Steps 3-7; ugks_step with n_inner = 1)
+ * reversed: the map (h, b, W, q; Wn, Sh, Sb, Fn) -> (h', b', W', q'; F) at
+ * the given inputs, F being the face macro flux of its Step 3 (as
+ * ugks_last_flux returns).  Output cotangents h1_bar, b1_bar [ncell][nv],
+ * W1_bar [ncell][dim+2], q1_bar [ncell][dim], F_bar [nface][dim+2]; input
+ * cotangents h_bar, b_bar, W_bar, Wn_bar, q_bar, Sh_bar, Sb_bar, Fn_bar.
+ */
+int ugks_step_adjoint(ugks_ctx* ctx, double dt, const void* h, const void* b, const double* W, const double* Wn,
+                      const double* q, const void* Sh, const void* Sb, const double* Fn, const double* h1_bar,
+                      const double* b1_bar, const double* W1_bar, const double* q1_bar, const double* F_bar,
+                      double* h_bar, double* b_bar, double* W_bar, double* Wn_bar, double* q_bar,
+                      double* Sh_bar, double* Sb_bar, double* Fn_bar, double* face_bar, void* stream);
+
+/*
+ * Steps 1-2 (ugks_begin_step) reversed: the map (h, b, W, q) -> (h', b', W',
+ * q'; Sh, Sb, Fn), the primed state being the input with its receptor rows
+ * (and, with refill != 0, first the rows of the cells uncovered from holes
+ * by the last overset_assemble) interpolated.  refill must say whether the
+ * forward call filled those cells (ugks_begin_step does once after an
+ * assembly); the donor table must be the one that call used.
+ */
+int ugks_begin_step_adjoint(ugks_ctx* ctx, double dt, const void* h, const void* b, const double* W,
+                            const double* q, int32_t refill, const double* h1_bar, const double* b1_bar,
+                            const double* W1_bar, const double* q1_bar, const double* Sh_bar,
+                            const double* Sb_bar, const double* Fn_bar, double* h_bar, double* b_bar,
+                            double* W_bar, double* q_bar, double* face_bar, void* stream);
+
 /* Thread-local message of the last failure ("" if none). */
 const char* ugks_last_error(void);
 

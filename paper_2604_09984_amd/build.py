@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libugks.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["ugks_kernels.hip", "ugks_api.cpp", "ugks_overset.cpp"]
+SOURCES = ["ugks_kernels.hip", "ugks_adjoint.hip", "ugks_api.cpp", "ugks_overset.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

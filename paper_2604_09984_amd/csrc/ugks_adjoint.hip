@@ -1,0 +1,1386 @@
+// Hand-written reverse mode (vector-Jacobian products) of the dual-time
+// pseudo-iteration (Sec. 2.2, Steps 3-7) and of Steps 1-2, FP64 storage.
+//
+// Each kernel is the transpose of one stage of the solver, applied to
+// cotangents ("bars") at a forward state that the host recomputes first
+// (checkpointed recomputation): the stages run backwards, Step 7 and the
+// heat flux first, then the micro LU-SGS sweeps (transposed sweeps in
+// reversed hyperplane order), the macro LU-SGS (reverse of the two nonlinear
+// sweeps), the UGKS interface flux (per face, lanes over velocities) and the
+// overset interpolation.  Small dense per-face maps (the equilibrium
+// expansion coefficients and the time integrals of Eq. fullSolution) are
+// differentiated in forward mode, one input direction per lane, and the
+// resulting Jacobian columns are contracted with the cotangent in the same
+// lanes.  Contributions that several threads add to one cell or face use
+// device-scope atomic additions (the sums are exact up to their order).
+//
+// Differentiated quantities: the distribution (h, b), W, q and the dual-time
+// sources of a step; the face grid velocity U_f (Eq. BGK, w = v - U), the
+// wall velocity and the wall temperature (Eq. maxWalldes) per face.  Frozen:
+// node positions, cell kinds and donor tables, dt, dt_s and the virtual
+// steps dt'.  At the kinks of the method (limiter switch, upwind sign,
+// positivity fallbacks, |.| in the spectral radius) the derivative of the
+// branch the forward pass took is used.
+#include "ugks_adjoint.h"
+#include "ugks_dev.h"
+
+namespace ugks {
+
+// ------------------------------------------------------------------------
+// forward-mode scalar (value and one directional derivative)
+// ------------------------------------------------------------------------
+struct Fwd {
+  double v, d;
+  Fwd() = default;
+  __device__ constexpr Fwd(double x) : v(x), d(0.0) {}
+  __device__ constexpr Fwd(double x, double t) : v(x), d(t) {}
+};
+__device__ inline Fwd operator+(Fwd a, Fwd b) { return Fwd(a.v + b.v, a.d + b.d); }
+__device__ inline Fwd operator-(Fwd a, Fwd b) { return Fwd(a.v - b.v, a.d - b.d); }
+__device__ inline Fwd operator-(Fwd a) { return Fwd(-a.v, -a.d); }
+__device__ inline Fwd operator*(Fwd a, Fwd b) { return Fwd(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ inline Fwd operator/(Fwd a, Fwd b) {
+  double q = a.v / b.v;
+  return Fwd(q, (a.d - q * b.d) / b.v);
+}
+__device__ inline Fwd& operator+=(Fwd& a, Fwd b) { a = a + b; return a; }
+__device__ inline Fwd& operator-=(Fwd& a, Fwd b) { a = a - b; return a; }
+__device__ inline Fwd& operator*=(Fwd& a, Fwd b) { a = a * b; return a; }
+__device__ inline bool operator<(Fwd a, Fwd b) { return a.v < b.v; }
+__device__ inline bool operator>(Fwd a, Fwd b) { return a.v > b.v; }
+__device__ inline Fwd exp(Fwd a) { double e = ::exp(a.v); return Fwd(e, e * a.d); }
+__device__ inline Fwd pow(Fwd a, double b) {
+  double p = ::pow(a.v, b);
+  return Fwd(p, b * ::pow(a.v, b - 1.0) * a.d);
+}
+// the double overloads stay visible beside the ones above
+using ::exp;
+using ::pow;
+
+// ------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void atomic_add(double* p, double v) {
+  if (v != 0.0) unsafeAtomicAdd(p, v);
+}
+
+// (v - U).n with the same rounding as the solver's upwind decision
+__device__ __forceinline__ double wn_exact(double vx, double vy, double ux, double uy, double nx, double ny) {
+#pragma clang fp contract(off)
+  double a = (vx - ux) * nx;
+  double b = (vy - uy) * ny;
+  return a + b;
+}
+
+// reverse of (rho, U, lam) = prim(W): W_bar += J^T (rho_bar, u_bar, lam_bar)
+__device__ inline void prim_rev(int dim, int nxi, const double* W, double rb, double uxb, double uyb, double lb,
+                                double* Wb) {
+  double rho = W[0];
+  double ux = W[1] / rho, uy = (dim == 2) ? W[2] / rho : 0.0;
+  double e = W[dim + 1] - 0.5 * rho * (ux * ux + uy * uy);
+  double lam = 0.25 * (double)(dim + nxi) * rho / e;
+  // lam = K rho / (4 e): d/drho (explicit) = lam/rho, d/de = -lam/e
+  double eb = -lb * lam / e;
+  Wb[0] += rb - uxb * ux / rho - uyb * uy / rho + lb * lam / rho + eb * 0.5 * (ux * ux + uy * uy);
+  Wb[1] += uxb / rho - eb * ux;
+  if (dim == 2) Wb[2] += uyb / rho - eb * uy;
+  Wb[dim + 1] += eb;
+}
+
+__device__ inline void prim_d(int dim, int nxi, const double* W, double& rho, double& ux, double& uy, double& lam) {
+  rho = W[0];
+  ux = W[1] / rho;
+  uy = (dim == 2) ? W[2] / rho : 0.0;
+  double e = W[dim + 1] - 0.5 * rho * (ux * ux + uy * uy);
+  lam = 0.25 * (double)(dim + nxi) * rho / e;
+}
+
+// d(1/tau)/d(rho, lam) at (rho, lam)
+__device__ inline void itau_partials(const Dev& g, double rho, double lam, double& dr, double& dl) {
+  double it = inv_tau_of(g, rho, lam);
+  dr = it / rho;
+  dl = -it * (1.0 - g.omega) / lam;
+}
+
+// Reverse of the reduced Shakhov equilibrium (Sec. 2.1) at one velocity:
+// (rho, U, lam, q) -> H, B (Maxwellian), Hp = H+ and Bp = B+ (the Shakhov
+// corrections), given the cotangents of those four values; accumulates into
+// a[0..5] = (rho, ux, uy, lam, qx, qy) bars.
+__device__ inline void eq_rev(const Dev& g, double rho, double ux, double uy, double lam, double qx, double qy,
+                              double vx, double vy, double Hb, double Bb, double Hpb, double Bpb, double* a) {
+  const int D = g.dim, nxi = g.nxi;
+  double cx = vx - ux, cy = (D == 2) ? vy - uy : 0.0;
+  double c2 = cx * cx + cy * cy;
+  double H = rho * pow(lam / kPi, 0.5 * D) * exp(-lam * c2);
+  double beta = (double)nxi / (2.0 * lam);
+  double sh = 4.0 * (1.0 - g.pr) * lam * lam / (5.0 * rho);
+  double cq = cx * qx + cy * qy;
+  double s = sh * cq;
+  double P = s * (2.0 * lam * c2 - 2.0 - D), Qb = s * (2.0 * lam * c2 - D);
+  double Ht = Hb + Bb * beta + Hpb * P + Bpb * Qb * beta;
+  double betab = Bb * H + Bpb * Qb * H;
+  double Pb = Hpb * H, Qbb = Bpb * beta * H;
+  double sb = Pb * (2.0 * lam * c2 - 2.0 - D) + Qbb * (2.0 * lam * c2 - D);
+  double lb = (Pb + Qbb) * s * 2.0 * c2 - betab * beta / lam;
+  double c2b = (Pb + Qbb) * s * 2.0 * lam;
+  double shb = sb * cq, cqb = sb * sh;
+  lb += shb * 2.0 * sh / lam;
+  double rb = -shb * sh / rho;
+  a[4] += cqb * cx;
+  if (D == 2) a[5] += cqb * cy;
+  double cxb = cqb * qx, cyb = cqb * qy;
+  lb += Ht * H * (0.5 * D / lam - c2);
+  rb += Ht * H / rho;
+  c2b += -Ht * H * lam;
+  cxb += 2.0 * cx * c2b;
+  cyb += 2.0 * cy * c2b;
+  a[0] += rb;
+  a[1] -= cxb;
+  if (D == 2) a[2] -= cyb;
+  a[3] += lb;
+}
+
+// heat flux q = 1/2 sum_k V_k c (|c|^2 h + b), c = v - U: per-velocity part of
+// its reverse (u_bar contribution; the h, b bars are returned)
+__device__ inline void heat_rev_k(int D, double w, double vx, double vy, double ux, double uy, double hv,
+                                  double bv, double qxb, double qyb, double& hb, double& bb, double& uxb,
+                                  double& uyb) {
+  double cx = vx - ux, cy = (D == 2) ? vy - uy : 0.0;
+  double c2 = cx * cx + cy * cy;
+  double cqb = cx * qxb + cy * qyb;
+  hb = w * 0.5 * cqb * c2;
+  bb = w * 0.5 * cqb;
+  double e = c2 * hv + bv;
+  uxb += -0.5 * w * (qxb * (e + 2.0 * cx * cx * hv) + qyb * 2.0 * cx * cy * hv);
+  if (D == 2) uyb += -0.5 * w * (qyb * (e + 2.0 * cy * cy * hv) + qxb * 2.0 * cx * cy * hv);
+}
+
+// ------------------------------------------------------------------------
+// face equilibrium record and the per-velocity interface integral
+// ------------------------------------------------------------------------
+// expansion coefficients (a_x, a_y, A) and time integrals q1..q5 of a face
+// state; inputs x = (rho, ux, uy, lam, dW[8] as the gradient layout, ufx, ufy)
+constexpr int kRecIn = 14, kRecOut = 17;
+template <class R>
+__device__ inline void face_coeffs(const Dev& g, double dts, const R* x, R* o) {
+  expansion(g.dim, x[0], x[1], x[2], x[3], x[12], x[13], x + 4, o, o + 4, o + 8);
+  time_integrals(dts, inv_tau_of(g, x[0], x[3]), o + 12);
+}
+
+// values of the record (all lanes) and, in lane j < kRecIn, the derivatives
+// of the outputs along input j
+__device__ inline void face_coeffs_lanes(const Dev& g, double dts, const double* x, int lane, double* val,
+                                         double* col) {
+  Fwd xi[kRecIn], o[kRecOut];
+  for (int j = 0; j < kRecIn; ++j) xi[j] = Fwd(x[j], (j == lane) ? 1.0 : 0.0);
+  face_coeffs(g, dts, xi, o);
+  for (int i = 0; i < kRecOut; ++i) { val[i] = o[i].v; col[i] = o[i].d; }
+}
+
+struct Rec {
+  double rho, ux, uy, lam, qx, qy;
+  double c[kRecOut];  // ax[4], ay[4], A[4], t[5]
+};
+
+// record cotangent: [0..5] rho, ux, uy, lam, qx, qy; [6..22] the kRecOut
+// coefficients; [23..24] w = v - U_f (its bar is minus the U_f bar)
+constexpr int kRecBar = 25;
+
+// Interface integral of Eq. fullSolution at one velocity (Ih, Ib: the time
+// integral over [0, dt_s] of the interface distribution) and its reverse
+// for the cotangents Ihb, Ibb.  Per-velocity bars of the side data are
+// returned; record bars are accumulated into acc[kRecBar].
+__device__ inline void iint_rev(const Dev& g, const Rec& e, double vx, double vy, double wx, double wy, double fh,
+                                double fb, double ghx, double ghy, double gbx, double gby, double Ihb, double Ibb,
+                                double& fhb, double& fbb, double* ghb, double* gbb, double* acc, double& Ih,
+                                double& Ib) {
+  const int D = g.dim, nxi = g.nxi, E = D + 1;
+  const double* ax = e.c;
+  const double* ay = e.c + 4;
+  const double* At = e.c + 8;
+  const double* t = e.c + 12;
+  double cx = vx - e.ux, cy = (D == 2) ? vy - e.uy : 0.0;
+  double c2 = cx * cx + cy * cy;
+  double H = e.rho * pow(e.lam / kPi, 0.5 * D) * exp(-e.lam * c2);
+  double beta = (double)nxi / (2.0 * e.lam);
+  double B = beta * H;
+  double sh = 4.0 * (1.0 - g.pr) * e.lam * e.lam / (5.0 * e.rho);
+  double s = sh * (cx * e.qx + cy * e.qy);
+  double Hp = s * (2.0 * e.lam * c2 - 2.0 - D) * H;
+  double Bp = s * (2.0 * e.lam * c2 - D) * beta * H;
+  double v2 = vx * vx + ((D == 2) ? vy * vy : 0.0);
+  double kh = 0.5 * (v2 + (double)nxi / (2.0 * e.lam)), kb = 0.5 * (v2 + (double)(nxi + 2) / (2.0 * e.lam));
+  auto lin = [&](const double* a) { return a[0] + a[1] * vx + ((D == 2) ? a[2] * vy : 0.0); };
+  double pax = lin(ax), pay = (D == 2) ? lin(ay) : 0.0, pat = lin(At);
+  double wah = wx * (pax + ax[E] * kh) + wy * (pay + ay[E] * kh);
+  double wab = wx * (pax + ax[E] * kb) + wy * (pay + ay[E] * kb);
+  double Ah = pat + At[E] * kh, Ab = pat + At[E] * kb;
+  double wgh = wx * ghx + wy * ghy, wgb = wx * gbx + wy * gby;
+  Ih = t[0] * fh + t[1] * wgh + t[2] * (H + Hp) + t[3] * wah * H + t[4] * Ah * H;
+  Ib = t[0] * fb + t[1] * wgb + t[2] * (B + Bp) + t[3] * wab * B + t[4] * Ab * B;
+  // reverse
+  fhb = t[0] * Ihb;
+  fbb = t[0] * Ibb;
+  ghb[0] = t[1] * Ihb * wx; ghb[1] = t[1] * Ihb * wy;
+  gbb[0] = t[1] * Ibb * wx; gbb[1] = t[1] * Ibb * wy;
+  double* tb = acc + 6 + 12;
+  tb[0] += fh * Ihb + fb * Ibb;
+  tb[1] += wgh * Ihb + wgb * Ibb;
+  tb[2] += (H + Hp) * Ihb + (B + Bp) * Ibb;
+  tb[3] += wah * H * Ihb + wab * B * Ibb;
+  tb[4] += Ah * H * Ihb + Ab * B * Ibb;
+  double ch = t[3] * H * Ihb, cb = t[3] * B * Ibb;
+  double dh = t[4] * H * Ihb, db = t[4] * B * Ibb;
+  // w bar
+  acc[23] += t[1] * (Ihb * ghx + Ibb * gbx) + ch * (pax + ax[E] * kh) + cb * (pax + ax[E] * kb);
+  if (D == 2) acc[24] += t[1] * (Ihb * ghy + Ibb * gby) + ch * (pay + ay[E] * kh) + cb * (pay + ay[E] * kb);
+  // slope and time coefficients
+  double* axb = acc + 6;
+  double* ayb = acc + 10;
+  double* Atb = acc + 14;
+  {
+    double wc = wx * (ch + cb);
+    axb[0] += wc; axb[1] += wc * vx;
+    if (D == 2) axb[2] += wc * vy;
+    axb[E] += wx * (ch * kh + cb * kb);
+    if (D == 2) {
+      double wy2 = wy * (ch + cb);
+      ayb[0] += wy2; ayb[1] += wy2 * vx; ayb[2] += wy2 * vy;
+      ayb[E] += wy * (ch * kh + cb * kb);
+    }
+    double dd = dh + db;
+    Atb[0] += dd; Atb[1] += dd * vx;
+    if (D == 2) Atb[2] += dd * vy;
+    Atb[E] += dh * kh + db * kb;
+  }
+  // lam through the 1/(2 lam) of the energy moments
+  double il2 = -1.0 / (2.0 * e.lam * e.lam);
+  double aE = wx * ax[E] + wy * ((D == 2) ? ay[E] : 0.0);
+  acc[3] += (ch * 0.5 * nxi + cb * 0.5 * (nxi + 2)) * aE * il2 + (dh * 0.5 * nxi + db * 0.5 * (nxi + 2)) * At[E] * il2;
+  // the equilibrium values
+  double Hb = Ihb * (t[2] + t[3] * wah + t[4] * Ah), Hpb = Ihb * t[2];
+  double Bb = Ibb * (t[2] + t[3] * wab + t[4] * Ab), Bpb = Ibb * t[2];
+  eq_rev(g, e.rho, e.ux, e.uy, e.lam, e.qx, e.qy, vx, vy, Hb, Bb, Hpb, Bpb, acc);
+}
+
+// ------------------------------------------------------------------------
+// reconstruction (Sec. 2.1, f0 = f + x . grad f, van Leer per index
+// direction) and its reverse
+// ------------------------------------------------------------------------
+// limited index slope and its partials with respect to (low, centre, high)
+__device__ inline double lim_d(int lo, int hi, double vlo, double v0, double vhi, double& dlo, double& d0,
+                               double& dhi) {
+  dlo = d0 = dhi = 0.0;
+  if (lo == kNbMiss || hi == kNbMiss) return 0.0;
+  if (lo == kNbWall && hi == kNbWall) return 0.0;
+  if (lo == kNbWall) { dhi = 1.0; d0 = -1.0; return vhi - v0; }
+  if (hi == kNbWall) { d0 = 1.0; dlo = -1.0; return v0 - vlo; }
+  double s1 = v0 - vlo, s2 = vhi - v0;
+  if (s1 * s2 <= 0.0) return 0.0;
+  double vl = (s1 * fabs(s2) + fabs(s1) * s2) / (fabs(s1) + fabs(s2));
+  double sm = s1 + s2;
+  double p1 = 2.0 * s2 * s2 / (sm * sm), p2 = 2.0 * s1 * s1 / (sm * sm);
+  d0 = p1 - p2; dlo = -p1; dhi = p2;
+  return vl;
+}
+
+__device__ __forceinline__ double nbval(const double* f, const double* finf, int code, double self, int nv, int k) {
+  if (code >= 0) return f[(size_t)code * nv + k];
+  if (code == kNbFar) return finf[k];
+  return self;
+}
+
+// reconstructed value and physical slope of f at velocity k on the side of
+// cell c whose face offset is (dx, dy); with bars (vb, gxb, gyb) the
+// reverse is scattered into fb (atomic)
+struct SideK {
+  double v, gx, gy;
+};
+
+__device__ inline SideK side_val(const Dev& g, const double* f, const double* finf, int c, double dx, double dy,
+                                 int k) {
+  const int* nb = g.nb + 4 * c;
+  double v0 = f[(size_t)c * g.nv + k];
+  double dl, d0, dh;
+  double si = lim_d(nb[0], nb[1], nbval(f, finf, nb[0], v0, g.nv, k), v0, nbval(f, finf, nb[1], v0, g.nv, k), dl,
+                    d0, dh);
+  double sj = 0.0;
+  if (g.dim == 2)
+    sj = lim_d(nb[2], nb[3], nbval(f, finf, nb[2], v0, g.nv, k), v0, nbval(f, finf, nb[3], v0, g.nv, k), dl, d0,
+               dh);
+  const double* G = g.G + 4 * c;
+  SideK s;
+  s.gx = G[0] * si + G[1] * sj;
+  s.gy = (g.dim == 2) ? G[2] * si + G[3] * sj : 0.0;
+  s.v = v0 + s.gx * dx + s.gy * dy;
+  return s;
+}
+
+__device__ __forceinline__ void scatter_code(double* fb, int code, int c, int nv, int k, double v) {
+  if (code >= 0) atomic_add(fb + (size_t)code * nv + k, v);
+  else if (code == kNbCopy) atomic_add(fb + (size_t)c * nv + k, v);
+}
+
+__device__ inline void side_rev(const Dev& g, const double* f, const double* finf, int c, double dx, double dy,
+                                int k, double vb, double gxb, double gyb, double* fbar) {
+  if (vb == 0.0 && gxb == 0.0 && gyb == 0.0) return;
+  const int* nb = g.nb + 4 * c;
+  const double* G = g.G + 4 * c;
+  double v0 = f[(size_t)c * g.nv + k];
+  gxb += vb * dx;
+  gyb += vb * dy;
+  double sib = G[0] * gxb + ((g.dim == 2) ? G[2] * gyb : 0.0);
+  double sjb = (g.dim == 2) ? G[1] * gxb + G[3] * gyb : 0.0;
+  double own = vb;
+  for (int dir = 0; dir < g.dim; ++dir) {
+    double sb = dir ? sjb : sib;
+    int lo = nb[2 * dir], hi = nb[2 * dir + 1];
+    double dl, d0, dh;
+    lim_d(lo, hi, nbval(f, finf, lo, v0, g.nv, k), v0, nbval(f, finf, hi, v0, g.nv, k), dl, d0, dh);
+    own += sb * d0;
+    scatter_code(fbar, lo, c, g.nv, k, sb * dl);
+    scatter_code(fbar, hi, c, g.nv, k, sb * dh);
+  }
+  atomic_add(fbar + (size_t)c * g.nv + k, own);
+}
+
+// side data of face f at velocity k: cell code, centroid-to-face offset
+__device__ inline void face_side(const Dev& g, const double* fp, int s, int& code, int& inner, double& dx,
+                                 double& dy) {
+  int L = (int)fp[kFpL], R = (int)fp[kFpR];
+  code = s ? R : L;
+  inner = (L >= 0) ? L : R;
+  dx = fp[s ? kFpDR : kFpDL];
+  dy = fp[(s ? kFpDR : kFpDL) + 1];
+}
+
+// value of the side distribution (ghost: far-field Maxwellian or a copy of
+// the interior cell, zero slope)
+__device__ inline SideK side_any(const Dev& g, const double* f, const double* finf, int code, int inner, double dx,
+                                 double dy, int k) {
+  if (code >= 0) return side_val(g, f, finf, code, dx, dy, k);
+  SideK s;
+  s.gx = s.gy = 0.0;
+  s.v = (code == kNbFar) ? finf[k] : f[(size_t)inner * g.nv + k];
+  return s;
+}
+
+__device__ inline void side_any_rev(const Dev& g, const double* f, const double* finf, int code, int inner,
+                                    double dx, double dy, int k, double vb, double gxb, double gyb, double* fbar) {
+  if (code >= 0) side_rev(g, f, finf, code, dx, dy, k, vb, gxb, gyb, fbar);
+  else if (code == kNbCopy) atomic_add(fbar + (size_t)inner * g.nv + k, vb);
+}
+
+// cotangent of the flux F_k (along the face normal) of face f from the
+// divergence bars of its field cells and the face macro-flux bar
+__device__ inline void flux_bar_k(const Dev& g, const double* fp, const double* Dbh, const double* Dbb,
+                                  const double* Fbf, int k, double& Fhb, double& Fbb) {
+  int L = (int)fp[kFpL], R = (int)fp[kFpR];
+  double S = fp[kFpS];
+  double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
+  Fhb = w * (Fbf[0] + Fbf[1] * vx + ((g.dim == 2) ? Fbf[2] * vy : 0.0) + Fbf[g.dim + 1] * 0.5 * (vx * vx + vy * vy));
+  Fbb = w * 0.5 * Fbf[g.dim + 1];
+  if (L >= 0 && g.type[L] == 1) {
+    double a = -S / g.vol[L];
+    Fhb += a * Dbh[(size_t)L * g.nv + k];
+    Fbb += a * Dbb[(size_t)L * g.nv + k];
+  }
+  if (R >= 0 && g.type[R] == 1) {
+    double a = S / g.vol[R];
+    Fhb += a * Dbh[(size_t)R * g.nv + k];
+    Fbb += a * Dbb[(size_t)R * g.nv + k];
+  }
+}
+
+// ------------------------------------------------------------------------
+// flux reverse, faces between cells (interior and ghost faces): one
+// wavefront per face, lanes over velocities
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adj_face(Dev g, double dts, const double* __restrict__ h,
+                                                  const double* __restrict__ b, const double* __restrict__ gW,
+                                                  const double* __restrict__ Dbh, const double* __restrict__ Dbb,
+                                                  const double* __restrict__ Fb, double* __restrict__ hbar,
+                                                  double* __restrict__ bbar, double* __restrict__ gWbar,
+                                                  double* __restrict__ fbar) {
+  const int f = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (f >= g.nface) return;
+  const double* fp = g.fplan + (size_t)f * kFpN;
+  if (fp[kFpAct] == 0.0) return;
+  const int L = (int)fp[kFpL], R = (int)fp[kFpR];
+  if (L == kNbWall || R == kNbWall) return;
+  const int D = g.dim, nw = g.nw, nv = g.nv;
+  const double nx = fp[kFpN0], ny = fp[kFpN0 + 1], ufx = fp[kFpU], ufy = fp[kFpU + 1];
+  const double* hinf = (const double*)g.finf_h;
+  const double* binf = (const double*)g.finf_b;
+  int cL, cR, inner;
+  double dLx, dLy, dRx, dRy;
+  face_side(g, fp, 0, cL, inner, dLx, dLy);
+  face_side(g, fp, 1, cR, inner, dRx, dRy);
+  auto upwind = [&](int k, double wn, double& fh, double& fb) {
+    SideK hl = side_any(g, h, hinf, cL, inner, dLx, dLy, k), hr = side_any(g, h, hinf, cR, inner, dRx, dRy, k);
+    SideK bl = side_any(g, b, binf, cL, inner, dLx, dLy, k), br = side_any(g, b, binf, cR, inner, dRx, dRy, k);
+    if (wn > 0.0) { fh = hl.v; fb = bl.v; }
+    else if (wn < 0.0) { fh = hr.v; fb = br.v; }
+    else { fh = 0.5 * (hl.v + hr.v); fb = 0.5 * (bl.v + br.v); }
+  };
+  // pass 1: W0 from the upwind interface data
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int k = lane; k < nv; k += 64) {
+    double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
+    double fh, fb;
+    upwind(k, wn_exact(vx, vy, ufx, ufy, nx, ny), fh, fb);
+    s0 += w * fh; s1 += w * vx * fh; s2 += w * vy * fh; s3 += w * 0.5 * ((vx * vx + vy * vy) * fh + fb);
+  }
+  double W0[4] = {wave_sum(s0), wave_sum(s1), 0.0, 0.0};
+  if (D == 2) { W0[2] = wave_sum(s2); W0[3] = wave_sum(s3); }
+  else W0[2] = wave_sum(s3);
+  Rec e;
+  prim_d(D, g.nxi, W0, e.rho, e.ux, e.uy, e.lam);
+  // pass 2: heat flux q0 and the sums of its derivative along U
+  double q0x = 0, q0y = 0, T1 = 0, Txx = 0, Tyy = 0, Txy = 0;
+  for (int k = lane; k < nv; k += 64) {
+    double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
+    double fh, fb;
+    upwind(k, wn_exact(vx, vy, ufx, ufy, nx, ny), fh, fb);
+    double cx = vx - e.ux, cy = (D == 2) ? vy - e.uy : 0.0;
+    double en = (cx * cx + cy * cy) * fh + fb;
+    q0x += w * 0.5 * cx * en; q0y += w * 0.5 * cy * en;
+    T1 += w * en; Txx += w * cx * cx * fh; Tyy += w * cy * cy * fh; Txy += w * cx * cy * fh;
+  }
+  e.qx = wave_sum(q0x); e.qy = (D == 2) ? wave_sum(q0y) : 0.0;
+  T1 = wave_sum(T1); Txx = wave_sum(Txx); Tyy = wave_sum(Tyy); Txy = wave_sum(Txy);
+  // record: values in every lane, Jacobian column j in lane j
+  double x[kRecIn];
+  x[0] = e.rho; x[1] = e.ux; x[2] = e.uy; x[3] = e.lam;
+  for (int m = 0; m < 8; ++m) {
+    double gl = (L >= 0) ? gW[(size_t)L * 8 + m] : 0.0;
+    double gr = (R >= 0) ? gW[(size_t)R * 8 + m] : 0.0;
+    x[4 + m] = 0.5 * (gl + gr);
+  }
+  x[12] = ufx; x[13] = ufy;
+  double col[kRecOut];
+  face_coeffs_lanes(g, dts, x, lane, e.c, col);
+  // pass 3: reverse of the flux at every velocity, record bars
+  double acc[kRecBar];
+  for (int i = 0; i < kRecBar; ++i) acc[i] = 0.0;
+  double ufb_x = 0.0, ufb_y = 0.0;
+  const double* Fbf = Fb + (size_t)f * nw;
+  for (int k = lane; k < nv; k += 64) {
+    double vx = g.vx[k], vy = g.vy[k];
+    double wn = wn_exact(vx, vy, ufx, ufy, nx, ny);
+    if (wn == 0.0) continue;
+    double Fhb, Fbb;
+    flux_bar_k(g, fp, Dbh, Dbb, Fbf, k, Fhb, Fbb);
+    int up = (wn > 0.0) ? cL : cR;
+    double ux_ = (wn > 0.0) ? dLx : dRx, uy_ = (wn > 0.0) ? dLy : dRy;
+    SideK sh = side_any(g, h, hinf, up, inner, ux_, uy_, k), sb = side_any(g, b, binf, up, inner, ux_, uy_, k);
+    double fhb, fbb, ghb[2], gbb[2], Ih, Ib;
+    iint_rev(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy,
+             Fhb * wn / dts, Fbb * wn / dts, fhb, fbb, ghb, gbb, acc, Ih, Ib);
+    double wnb = (Fhb * Ih + Fbb * Ib) / dts;
+    ufb_x -= wnb * nx;
+    ufb_y -= wnb * ny;
+  }
+  for (int i = 0; i < kRecBar; ++i) acc[i] = wave_sum(acc[i]);
+  ufb_x = wave_sum(ufb_x) - acc[23];
+  ufb_y = wave_sum(ufb_y) - acc[24];
+  // contraction with the record Jacobian: lane j < kRecIn holds input j's bar
+  double inb = 0.0;
+  for (int i = 0; i < kRecOut; ++i) inb += acc[6 + i] * col[i];
+  double xb[kRecIn];
+  for (int j = 0; j < kRecIn; ++j) xb[j] = lane_read(inb, j);
+  double rb = acc[0] + xb[0], uxb = acc[1] + xb[1], uyb = acc[2] + xb[2], lb = acc[3] + xb[3];
+  double qxb = acc[4], qyb = acc[5];
+  ufb_x += xb[12];
+  ufb_y += xb[13];
+  // q0 depends on U0 through c = v - U0
+  uxb += -0.5 * (T1 + 2.0 * Txx) * qxb - Txy * qyb;
+  if (D == 2) uyb += -Txy * qxb - 0.5 * (T1 + 2.0 * Tyy) * qyb;
+  double W0b[4] = {0, 0, 0, 0};
+  prim_rev(D, g.nxi, W0, rb, uxb, uyb, lb, W0b);
+  // gradient bars of the two cells (the face slope is their mean)
+  if (lane < 8) {
+    double v = 0.5 * xb[4 + lane];
+    if (L >= 0) atomic_add(gWbar + (size_t)L * 8 + lane, v);
+    if (R >= 0) atomic_add(gWbar + (size_t)R * 8 + lane, v);
+  }
+  if (lane == 0) {
+    fbar[(size_t)f * 5 + 0] += ufb_x;
+    fbar[(size_t)f * 5 + 1] += ufb_y;
+  }
+  // pass 4: per-velocity bars of the interface data, scattered to the cells
+  for (int k = lane; k < nv; k += 64) {
+    double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
+    double wn = wn_exact(vx, vy, ufx, ufy, nx, ny);
+    double cx = vx - e.ux, cy = (D == 2) ? vy - e.uy : 0.0;
+    double cqb = cx * qxb + cy * qyb;
+    double mh = w * (W0b[0] + W0b[1] * vx + ((D == 2) ? W0b[2] * vy : 0.0) +
+                     W0b[D + 1] * 0.5 * (vx * vx + vy * vy)) + w * 0.5 * cqb * (cx * cx + cy * cy);
+    double mb = w * 0.5 * W0b[D + 1] + w * 0.5 * cqb;
+    double lh = 0, lb_ = 0, rh = 0, rb_ = 0;
+    double lgh[2] = {0, 0}, lgb[2] = {0, 0}, rgh[2] = {0, 0}, rgb[2] = {0, 0};
+    if (wn > 0.0) { lh = mh; lb_ = mb; }
+    else if (wn < 0.0) { rh = mh; rb_ = mb; }
+    else { lh = rh = 0.5 * mh; lb_ = rb_ = 0.5 * mb; }
+    if (wn != 0.0) {
+      double Fhb, Fbb;
+      flux_bar_k(g, fp, Dbh, Dbb, Fbf, k, Fhb, Fbb);
+      int up = (wn > 0.0) ? cL : cR;
+      double ux_ = (wn > 0.0) ? dLx : dRx, uy_ = (wn > 0.0) ? dLy : dRy;
+      SideK sh = side_any(g, h, hinf, up, inner, ux_, uy_, k), sb = side_any(g, b, binf, up, inner, ux_, uy_, k);
+      double fhb, fbb, ghb[2], gbb[2], Ih, Ib, dummy[kRecBar];
+      iint_rev(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy,
+               Fhb * wn / dts, Fbb * wn / dts, fhb, fbb, ghb, gbb, dummy, Ih, Ib);
+      if (wn > 0.0) { lh += fhb; lb_ += fbb; lgh[0] = ghb[0]; lgh[1] = ghb[1]; lgb[0] = gbb[0]; lgb[1] = gbb[1]; }
+      else { rh += fhb; rb_ += fbb; rgh[0] = ghb[0]; rgh[1] = ghb[1]; rgb[0] = gbb[0]; rgb[1] = gbb[1]; }
+    }
+    side_any_rev(g, h, hinf, cL, inner, dLx, dLy, k, lh, lgh[0], lgh[1], hbar);
+    side_any_rev(g, b, binf, cL, inner, dLx, dLy, k, lb_, lgb[0], lgb[1], bbar);
+    side_any_rev(g, h, hinf, cR, inner, dRx, dRy, k, rh, rgh[0], rgh[1], hbar);
+    side_any_rev(g, b, binf, cR, inner, dRx, dRy, k, rb_, rgb[0], rgb[1], bbar);
+  }
+}
+
+// ------------------------------------------------------------------------
+// flux reverse, isothermal wall faces (Eq. maxWalldes): one wavefront per
+// face
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const double* __restrict__ h,
+                                                  const double* __restrict__ b, const double* __restrict__ W,
+                                                  const double* __restrict__ q, const double* __restrict__ gW,
+                                                  const double* __restrict__ Dbh, const double* __restrict__ Dbb,
+                                                  const double* __restrict__ Fb, double* __restrict__ hbar,
+                                                  double* __restrict__ bbar, double* __restrict__ Wbar,
+                                                  double* __restrict__ qbar, double* __restrict__ gWbar,
+                                                  double* __restrict__ fbar) {
+  const int f = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (f >= g.nface) return;
+  const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
+  if (L != kNbWall && R != kNbWall) return;
+  const int c = (L == kNbWall) ? R : L;
+  if (c < 0 || g.type[c] != 1) return;
+  const int D = g.dim, nw = g.nw, nv = g.nv, nxi = g.nxi;
+  int slot = 0;
+  for (int s = 0; s < 4; ++s) if (g.cf[4 * c + s] == f) slot = s;
+  const double* fg = g.fgeo + (size_t)f * 8;
+  const double sgn = (R == kNbWall) ? 1.0 : -1.0;
+  const double nwx = sgn * fg[0], nwy = sgn * fg[1], ufx = fg[3], ufy = fg[4];
+  const double vwx = fg[5], vwy = fg[6], rtw = fg[7];
+  const double dx = g.cdx[8 * c + 2 * slot], dy = g.cdx[8 * c + 2 * slot + 1];
+  const double* hinf = (const double*)g.finf_h;
+  const double* binf = (const double*)g.finf_b;
+  // incident state: one-sided extrapolation of W, cell state if unphysical
+  const double* gw = gW + (size_t)c * 8;
+  double Win[4] = {0, 0, 0, 0};
+  for (int m = 0; m < nw; ++m) Win[m] = W[(size_t)c * nw + m] + gw[m] * dx + gw[nw + m] * dy;
+  const bool extrap = physical_state(D, Win);
+  if (!extrap)
+    for (int m = 0; m < nw; ++m) Win[m] = W[(size_t)c * nw + m];
+  Rec e;
+  prim_d(D, nxi, Win, e.rho, e.ux, e.uy, e.lam);
+  e.qx = q[(size_t)c * D];
+  e.qy = (D == 2) ? q[(size_t)c * D + 1] : 0.0;
+  double x[kRecIn];
+  x[0] = e.rho; x[1] = e.ux; x[2] = e.uy; x[3] = e.lam;
+  for (int m = 0; m < 8; ++m) x[4 + m] = gw[m];
+  x[12] = ufx; x[13] = ufy;
+  double col[kRecOut];
+  face_coeffs_lanes(g, dts, x, lane, e.c, col);
+  const double lamw = 0.5 / rtw;
+  const double nrm = pow(lamw / kPi, 0.5 * D);
+  const double betaw = (double)nxi / (2.0 * lamw);
+  // pass 1: incident mass flux and the wall normaliser
+  double num = 0.0, den = 0.0;
+  for (int k = lane; k < nv; k += 64) {
+    double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
+    double wn = wn_exact(vx, vy, ufx, ufy, nwx, nwy);
+    if (wn > 0.0) {
+      SideK sh = side_val(g, h, hinf, c, dx, dy, k), sb = side_val(g, b, binf, c, dx, dy, k);
+      double fhb, fbb, ghb[2], gbb[2], Ih, Ib, dummy[kRecBar];
+      iint_rev(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy, 0.0, 0.0,
+               fhb, fbb, ghb, gbb, dummy, Ih, Ib);
+      num += w * wn * Ih;
+    } else if (wn < 0.0) {
+      double cx = vx - vwx, cy = (D == 2) ? vy - vwy : 0.0;
+      den += w * wn * nrm * exp(-lamw * (cx * cx + cy * cy));
+    }
+  }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  const double rhow = -num / (dts * den);
+  const double* Fbf = Fb + (size_t)f * nw;
+  const double* fpw = g.fplan + (size_t)f * kFpN;
+  // pass 2: the reflected part (wn < 0) and the normaliser's derivatives
+  double rhowb = 0, lamwb = 0, vwbx = 0, vwby = 0, ufbx = 0, ufby = 0;
+  double dden_l = 0, dden_vx = 0, dden_vy = 0, dden_u = 0;
+  for (int k = lane; k < nv; k += 64) {
+    double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
+    double wn = wn_exact(vx, vy, ufx, ufy, nwx, nwy);
+    if (!(wn < 0.0)) continue;
+    double Fhb, Fbb;
+    flux_bar_k(g, fpw, Dbh, Dbb, Fbf, k, Fhb, Fbb);
+    double fhb = sgn * Fhb, fbb = sgn * Fbb;
+    double cx = vx - vwx, cy = (D == 2) ? vy - vwy : 0.0;
+    double c2 = cx * cx + cy * cy;
+    double Ek = nrm * exp(-lamw * c2);
+    double Hw = rhow * Ek;
+    double t = fhb + fbb * betaw;
+    rhowb += t * wn * Ek;
+    lamwb += fhb * wn * Hw * (0.5 * D / lamw - c2) + fbb * wn * betaw * Hw * (0.5 * D / lamw - c2 - 1.0 / lamw);
+    vwbx += t * wn * Hw * 2.0 * lamw * cx;
+    vwby += t * wn * Hw * 2.0 * lamw * cy;
+    ufbx -= t * Hw * nwx;
+    ufby -= t * Hw * nwy;
+    dden_l += w * wn * Ek * (0.5 * D / lamw - c2);
+    dden_vx += w * wn * Ek * 2.0 * lamw * cx;
+    dden_vy += w * wn * Ek * 2.0 * lamw * cy;
+    dden_u += w * Ek;
+  }
+  rhowb = wave_sum(rhowb); lamwb = wave_sum(lamwb);
+  vwbx = wave_sum(vwbx); vwby = wave_sum(vwby);
+  ufbx = wave_sum(ufbx); ufby = wave_sum(ufby);
+  dden_l = wave_sum(dden_l); dden_vx = wave_sum(dden_vx); dden_vy = wave_sum(dden_vy); dden_u = wave_sum(dden_u);
+  const double numb = -rhowb / (dts * den);
+  const double denb = -rhowb * rhow / den;
+  lamwb += denb * dden_l;
+  vwbx += denb * dden_vx;
+  vwby += denb * dden_vy;
+  ufbx -= denb * dden_u * nwx;
+  ufby -= denb * dden_u * nwy;
+  // pass 3: incident part (wn > 0), record bars
+  double acc[kRecBar];
+  for (int i = 0; i < kRecBar; ++i) acc[i] = 0.0;
+  double ufb2x = 0, ufb2y = 0;
+  for (int k = lane; k < nv; k += 64) {
+    double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
+    double wn = wn_exact(vx, vy, ufx, ufy, nwx, nwy);
+    if (!(wn > 0.0)) continue;
+    double Fhb, Fbb;
+    flux_bar_k(g, fpw, Dbh, Dbb, Fbf, k, Fhb, Fbb);
+    double fhb_ = sgn * Fhb, fbb_ = sgn * Fbb;
+    SideK sh = side_val(g, h, hinf, c, dx, dy, k), sb = side_val(g, b, binf, c, dx, dy, k);
+    double Ihb = fhb_ * wn / dts + numb * w * wn, Ibb = fbb_ * wn / dts;
+    double fhb, fbb, ghb[2], gbb[2], Ih, Ib;
+    iint_rev(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy, Ihb, Ibb,
+             fhb, fbb, ghb, gbb, acc, Ih, Ib);
+    double wnb = fhb_ * Ih / dts + fbb_ * Ib / dts + numb * w * Ih;
+    ufb2x -= wnb * nwx;
+    ufb2y -= wnb * nwy;
+  }
+  for (int i = 0; i < kRecBar; ++i) acc[i] = wave_sum(acc[i]);
+  ufbx += wave_sum(ufb2x) - acc[23];
+  ufby += wave_sum(ufb2y) - acc[24];
+  double inb = 0.0;
+  for (int i = 0; i < kRecOut; ++i) inb += acc[6 + i] * col[i];
+  double xb[kRecIn];
+  for (int j = 0; j < kRecIn; ++j) xb[j] = lane_read(inb, j);
+  ufbx += xb[12];
+  ufby += xb[13];
+  double Winb[4] = {0, 0, 0, 0};
+  prim_rev(D, nxi, Win, acc[0] + xb[0], acc[1] + xb[1], acc[2] + xb[2], acc[3] + xb[3], Winb);
+  if (lane == 0) {
+    atomic_add(qbar + (size_t)c * D, acc[4]);
+    if (D == 2) atomic_add(qbar + (size_t)c * D + 1, acc[5]);
+    for (int m = 0; m < nw; ++m) atomic_add(Wbar + (size_t)c * nw + m, Winb[m]);
+    double* o = fbar + (size_t)f * 5;
+    o[0] += ufbx; o[1] += ufby;
+    o[2] += vwbx; o[3] += vwby;
+    o[4] += -lamwb * 2.0 * lamw * lamw;  // lam_w = 1/(2 RT_w)
+  }
+  if (lane < 8) {
+    // the slope input and, through the extrapolation, the incident state
+    double v = xb[4 + lane];
+    if (extrap) {
+      if (lane < nw) v += Winb[lane] * dx;
+      else if (lane >= nw && lane < 2 * nw) v += Winb[lane - nw] * dy;
+    }
+    atomic_add(gWbar + (size_t)c * 8 + lane, v);
+  }
+  // pass 4: per-velocity bars of the incident data
+  for (int k = lane; k < nv; k += 64) {
+    double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
+    double wn = wn_exact(vx, vy, ufx, ufy, nwx, nwy);
+    if (!(wn > 0.0)) continue;
+    double Fhb, Fbb;
+    flux_bar_k(g, fpw, Dbh, Dbb, Fbf, k, Fhb, Fbb);
+    SideK sh = side_val(g, h, hinf, c, dx, dy, k), sb = side_val(g, b, binf, c, dx, dy, k);
+    double Ihb = sgn * Fhb * wn / dts + numb * w * wn, Ibb = sgn * Fbb * wn / dts;
+    double fhb, fbb, ghb[2], gbb[2], Ih, Ib, dummy[kRecBar];
+    iint_rev(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy, Ihb, Ibb,
+             fhb, fbb, ghb, gbb, dummy, Ih, Ib);
+    side_rev(g, h, hinf, c, dx, dy, k, fhb, ghb[0], ghb[1], hbar);
+    side_rev(g, b, binf, c, dx, dy, k, fbb, gbb[0], gbb[1], bbar);
+  }
+}
+
+
+// ------------------------------------------------------------------------
+// limited W gradients (reconstruction of W for the slopes and the wall
+// incident state): gW bars to W bars, one thread per cell
+// ------------------------------------------------------------------------
+__global__ void k_adj_gradW(Dev g, const double* __restrict__ W, const double* __restrict__ gWbar,
+                            double* __restrict__ Wbar) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ncell || g.type[c] == 0) return;
+  const int nw = g.nw;
+  const double* gb = gWbar + (size_t)c * 8;
+  const double* G = g.G + 4 * c;
+  const int* nb = g.nb + 4 * c;
+  for (int m = 0; m < nw; ++m) {
+    double gxb = gb[m], gyb = (g.dim == 2) ? gb[nw + m] : 0.0;
+    double sib = G[0] * gxb + ((g.dim == 2) ? G[2] * gyb : 0.0);
+    double sjb = (g.dim == 2) ? G[1] * gxb + G[3] * gyb : 0.0;
+    double v0 = W[(size_t)c * nw + m];
+    auto val = [&](int code) -> double {
+      if (code >= 0) return W[(size_t)code * nw + m];
+      if (code == kNbFar) return g.winf[m];
+      return v0;
+    };
+    double own = 0.0;
+    for (int dir = 0; dir < g.dim; ++dir) {
+      double sb = dir ? sjb : sib;
+      if (sb == 0.0) continue;
+      int lo = nb[2 * dir], hi = nb[2 * dir + 1];
+      double dl, d0, dh;
+      lim_d(lo, hi, val(lo), v0, val(hi), dl, d0, dh);
+      own += sb * d0;
+      if (lo >= 0) atomic_add(Wbar + (size_t)lo * nw + m, sb * dl);
+      else if (lo == kNbCopy) own += sb * dl;
+      if (hi >= 0) atomic_add(Wbar + (size_t)hi * nw + m, sb * dh);
+      else if (hi == kNbCopy) own += sb * dh;
+    }
+    atomic_add(Wbar + (size_t)c * nw + m, own);
+  }
+}
+
+// ------------------------------------------------------------------------
+// Step 7 (W' = W~ + sum_k V_k Psi_k (f' - g(W~))) and the heat flux of the
+// new state, reversed: one wavefront per cell.  hb, bb hold the bars of f'
+// on entry and on return (plus the contributions of these two maps); Wpb
+// receives the bar of the macro predictor W~.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adj_step7(Dev g, const double* __restrict__ h1,
+                                                   const double* __restrict__ b1, const double* __restrict__ W1,
+                                                   const double* __restrict__ Wp, const double* __restrict__ W1b,
+                                                   const double* __restrict__ q1b, double* __restrict__ hb,
+                                                   double* __restrict__ bb, double* __restrict__ Wpb) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= g.ncell) return;
+  const int D = g.dim, nw = g.nw, nv = g.nv;
+  double Wb[4] = {0, 0, 0, 0};
+  for (int m = 0; m < nw; ++m) Wb[m] = W1b[(size_t)c * nw + m];
+  if (g.type[c] == 0) {
+    if (lane < nw) Wpb[(size_t)c * nw + lane] = Wb[lane];
+    return;
+  }
+  // q' = heat flux of f' about the velocity of W'
+  double rho1, ux1, uy1, lam1;
+  prim_d(D, g.nxi, W1 + (size_t)c * nw, rho1, ux1, uy1, lam1);
+  const double qxb = q1b[(size_t)c * D], qyb = (D == 2) ? q1b[(size_t)c * D + 1] : 0.0;
+  double uxb = 0.0, uyb = 0.0;
+  for (int k = lane; k < nv; k += 64) {
+    size_t o = (size_t)c * nv + k;
+    double dh, db;
+    heat_rev_k(D, g.wk[k], g.vx[k], g.vy[k], ux1, uy1, h1[o], b1[o], qxb, qyb, dh, db, uxb, uyb);
+    hb[o] += dh;
+    bb[o] += db;
+  }
+  uxb = wave_sum(uxb);
+  uyb = wave_sum(uyb);
+  prim_rev(D, g.nxi, W1 + (size_t)c * nw, 0.0, uxb, uyb, 0.0, Wb);
+  if (g.type[c] != 1) {
+    if (lane < nw) Wpb[(size_t)c * nw + lane] = Wb[lane];
+    return;
+  }
+  double rho, ux, uy, lam;
+  prim_d(D, g.nxi, Wp + (size_t)c * nw, rho, ux, uy, lam);
+  double a[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = lane; k < nv; k += 64) {
+    size_t o = (size_t)c * nv + k;
+    double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
+    double P = Wb[0] + Wb[1] * vx + ((D == 2) ? Wb[2] * vy : 0.0) + Wb[D + 1] * 0.5 * (vx * vx + vy * vy);
+    double Pb = 0.5 * Wb[D + 1];
+    hb[o] += w * P;
+    bb[o] += w * Pb;
+    eq_rev(g, rho, ux, uy, lam, 0.0, 0.0, vx, vy, -w * P, -w * Pb, 0.0, 0.0, a);
+  }
+  for (int i = 0; i < 4; ++i) a[i] = wave_sum(a[i]);
+  double Wpbl[4] = {Wb[0], Wb[1], Wb[2], Wb[3]};
+  prim_rev(D, g.nxi, Wp + (size_t)c * nw, a[0], a[1], a[2], a[3], Wpbl);
+  if (lane < nw) Wpb[(size_t)c * nw + lane] = Wpbl[lane];
+}
+
+// ------------------------------------------------------------------------
+// micro LU-SGS reversed (Eq. dualTimeStepping_micro).  With the forward
+// sweeps x = (D+U)^{-1} D (D+L)^{-1} r, the bar of the residual is
+// r_bar = (D+L)^{-T} D (D+U)^{-T} x_bar: an ascending transposed sweep for
+// y = (D+U)^{-T} x_bar, then a descending one for r_bar.  One workgroup per
+// block and 64-velocity chunk, lanes over velocities, waves over the rows of
+// a hyperplane.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double micro_coef(const double* mg, int s, double vx, double vy) {
+  return mg[3 * s] * vx + mg[3 * s + 1] * vy - mg[3 * s + 2];
+}
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_adj_micro_sweep(Dev g, const int* __restrict__ binfo,
+                                                          const double* __restrict__ crec,
+                                                          const double* __restrict__ inh,
+                                                          const double* __restrict__ inb,
+                                                          double* __restrict__ outh, double* __restrict__ outb) {
+  const int blk = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwav = blockDim.x >> 6;
+  const int k = blockIdx.y * 64 + lane;
+  const int ni = binfo[8 * blk], nj = binfo[8 * blk + 1], c0 = binfo[8 * blk + 2];
+  const bool kok = k < g.nv;
+  const int kk = kok ? k : 0;
+  const double vx = g.vx[kk], vy = g.vy[kk];
+  const int nh = ni + nj - 1;
+  const int ns = 2 * g.dim;
+  for (int it = 0; it < nh; ++it) {
+    const int hp = (MODE == 0) ? it : nh - 1 - it;
+    for (int j = wave; j < nj; j += nwav) {
+      const int i = hp - j;
+      if (i < 0 || i >= ni || !kok) continue;
+      const int n = c0 + i + ni * j;
+      if (g.type[n] != 1) continue;
+      const double* mg = g.mgeo + (size_t)n * 12;
+      double dd = crec[(size_t)n * NCREC + C_D0];
+      for (int s = 0; s < ns; ++s) dd += fmax(micro_coef(mg, s, vx, vy), 0.0);
+      double sh = 0.0, sb = 0.0;
+      for (int s = 0; s < ns; ++s) {
+        const int m = g.nb[4 * n + s];
+        if (m < 0 || g.type[m] != 1) continue;
+        if ((MODE == 0) ? (m < n) : (m > n)) {
+          const double cf = fmin(micro_coef(g.mgeo + (size_t)m * 12, s ^ 1, vx, vy), 0.0);
+          sh += cf * outh[(size_t)m * g.nv + k];
+          sb += cf * outb[(size_t)m * g.nv + k];
+        }
+      }
+      const size_t o = (size_t)n * g.nv + k;
+      if (MODE == 0) {
+        outh[o] = (inh[o] - sh) / dd;
+        outb[o] = (inb[o] - sb) / dd;
+      } else {
+        outh[o] = inh[o] - sh / dd;
+        outb[o] = inb[o] - sb / dd;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Coefficient and residual bars of the micro step, one wavefront per cell:
+// with x = f' - f (the micro increment), x* the forward-sweep result, y and
+// r_bar from the two transposed sweeps, the bars of the diagonal d, of the
+// lower couplings L (cell n, neighbour m < n) and the upper couplings U are
+//   d_bar = -r_bar x + (y - r_bar)(x* - x),  L_bar = -r_bar_n x*_m,
+//   U_bar = -y_n x_m,
+// summed over h and b.  Then the residual r = S - f/dt + (D + (f+ - f)/tau)/2
+// is reversed (its f+ through the Shakhov equilibrium of (W~, q~)), and q~,
+// the heat flux of f about the velocity of W~.
+__global__ __launch_bounds__(256) void k_adj_micro_coef(
+    Dev g, double dt, const double* __restrict__ crec, const double* __restrict__ Wp,
+    const double* __restrict__ h0, const double* __restrict__ b0, const double* __restrict__ h1,
+    const double* __restrict__ b1, const double* __restrict__ xsh, const double* __restrict__ xsb,
+    const double* __restrict__ yh, const double* __restrict__ yb, const double* __restrict__ rh,
+    const double* __restrict__ rb, const double* __restrict__ xbh, const double* __restrict__ xbb,
+    double* __restrict__ hbar, double* __restrict__ bbar, double* __restrict__ Shb, double* __restrict__ Sbb,
+    double* __restrict__ Dbh, double* __restrict__ Dbb, double* __restrict__ Wpb, double* __restrict__ fbar) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= g.ncell) return;
+  const int D = g.dim, nv = g.nv, nw = g.nw, ns = 2 * D;
+  if (g.type[c] != 1) {
+    for (int k = lane; k < nv; k += 64) {
+      size_t o = (size_t)c * nv + k;
+      hbar[o] = xbh[o];
+      bbar[o] = xbb[o];
+      Shb[o] = 0.0; Sbb[o] = 0.0; Dbh[o] = 0.0; Dbb[o] = 0.0;
+    }
+    return;
+  }
+  const double* r = crec + (size_t)c * NCREC;
+  const double rho = r[C_RHO], ux = r[C_UX], uy = r[C_UY], lam = r[C_LAM], qx = r[C_QX], qy = r[C_QY];
+  const double it = r[C_ITAU];
+  const double* mg = g.mgeo + (size_t)c * 12;
+  int nbm[4];
+  for (int s = 0; s < 4; ++s) {
+    int m = (s < ns) ? g.nb[4 * c + s] : -1;
+    nbm[s] = (m >= 0 && g.type[m] == 1) ? m : -1;
+  }
+  double a[6] = {0, 0, 0, 0, 0, 0};
+  double itb = 0.0;
+  double ab[4] = {0, 0, 0, 0};  // bars of the face coefficients per slot
+  const double hn = rho * pow(lam / kPi, 0.5 * D);
+  const double shc = 4.0 * (1.0 - g.pr) * lam * lam / (5.0 * rho);
+  for (int k = lane; k < nv; k += 64) {
+    const size_t o = (size_t)c * nv + k;
+    const double vx = g.vx[k], vy = g.vy[k];
+    const double xh = h1[o] - h0[o], xb = b1[o] - b0[o];
+    const double ddb = -rh[o] * xh + (yh[o] - rh[o]) * (xsh[o] - xh) - rb[o] * xb + (yb[o] - rb[o]) * (xsb[o] - xb);
+    itb += 0.5 * ddb;
+    for (int s = 0; s < ns; ++s) {
+      const double cf = micro_coef(mg, s, vx, vy);
+      double t = 0.0;
+      if (cf > 0.0) t = ddb;
+      else if (cf < 0.0 && nbm[s] >= 0) {
+        const int m = nbm[s];
+        const size_t om = (size_t)m * nv + k;
+        if (m < c) t = -(rh[o] * xsh[om] + rb[o] * xsb[om]);
+        else t = -(yh[o] * (h1[om] - h0[om]) + yb[o] * (b1[om] - b0[om]));
+      }
+      ab[s] += t;
+    }
+    // residual: r = S - f/dt + (D + (f+ - f) / tau) / 2
+    const double cx = vx - ux, cy = (D == 2) ? vy - uy : 0.0;
+    const double c2 = cx * cx + cy * cy;
+    const double H = hn * exp(-lam * c2);
+    const double beta = (double)g.nxi / (2.0 * lam);
+    const double sq = shc * (cx * qx + cy * qy);
+    const double hp = H + sq * (2.0 * lam * c2 - 2.0 - D) * H;
+    const double bp = beta * H + sq * (2.0 * lam * c2 - D) * beta * H;
+    Shb[o] = rh[o];
+    Sbb[o] = rb[o];
+    Dbh[o] = 0.5 * rh[o];
+    Dbb[o] = 0.5 * rb[o];
+    hbar[o] = xbh[o] + rh[o] * (-1.0 / dt - 0.5 * it);
+    bbar[o] = xbb[o] + rb[o] * (-1.0 / dt - 0.5 * it);
+    itb += 0.5 * (rh[o] * (hp - h0[o]) + rb[o] * (bp - b0[o]));
+    const double eh = 0.5 * it * rh[o], eb = 0.5 * it * rb[o];
+    eq_rev(g, rho, ux, uy, lam, qx, qy, vx, vy, eh, eb, eh, eb, a);
+  }
+  for (int i = 0; i < 6; ++i) a[i] = wave_sum(a[i]);
+  itb = wave_sum(itb);
+  for (int s = 0; s < ns; ++s) ab[s] = wave_sum(ab[s]);
+  double dr, dl;
+  itau_partials(g, rho, lam, dr, dl);
+  if (g.mu_ref > 0.0) { a[0] += itb * dr; a[3] += itb * dl; }
+  // q~ = heat flux of f about the velocity of W~
+  const double qxb = a[4], qyb = a[5];
+  double uxq = 0.0, uyq = 0.0;
+  for (int k = lane; k < nv; k += 64) {
+    const size_t o = (size_t)c * nv + k;
+    double dh, db;
+    heat_rev_k(D, g.wk[k], g.vx[k], g.vy[k], ux, uy, h0[o], b0[o], qxb, qyb, dh, db, uxq, uyq);
+    hbar[o] += dh;
+    bbar[o] += db;
+  }
+  const double uxb = a[1] + wave_sum(uxq);
+  const double uyb = a[2] + wave_sum(uyq);
+  double Wl[4] = {0, 0, 0, 0};
+  prim_rev(D, g.nxi, Wp + (size_t)c * nw, a[0], uxb, uyb, a[3], Wl);
+  if (lane < nw) Wpb[(size_t)c * nw + lane] += Wl[lane];
+  // face coefficient a = S/(2|Omega|) (v - U_f).n_out = A vx + B vy - C:
+  // its U_f bar is -(A, B) a_bar
+  if (lane < ns) {
+    const int s = lane;
+    const int f = g.cf[4 * c + s];
+    if (f >= 0) {
+      atomic_add(fbar + (size_t)f * 5 + 0, -mg[3 * s] * ab[s]);
+      atomic_add(fbar + (size_t)f * 5 + 1, -mg[3 * s + 1] * ab[s]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// macro LU-SGS reversed (Eq. dualTimeStepping_macro)
+// ------------------------------------------------------------------------
+// ALE Euler flux along n with mesh normal velocity un (D + N_xi = 3)
+__device__ inline void euler_f(int D, const double* w, double nx, double ny, double un, double* o) {
+  double vx = w[1] / w[0], vy = (D == 2) ? w[2] / w[0] : 0.0;
+  double wE = w[D + 1];
+  double p = 2.0 / 3.0 * (wE - 0.5 * w[0] * (vx * vx + vy * vy));
+  double vn = vx * nx + ((D == 2) ? vy * ny : 0.0);
+  double th = vn - un;
+  o[0] = w[0] * th;
+  o[1] = w[1] * th + p * nx;
+  if (D == 2) { o[2] = w[2] * th + p * ny; o[3] = wE * th + p * vn; }
+  else o[2] = wE * th + p * vn;
+}
+
+// Wb += (d F_E / d W)^T ab
+__device__ inline void euler_vjp(int D, const double* w, double nx, double ny, double un, const double* ab,
+                                 double* Wb) {
+  const int E = D + 1;
+  double rho = w[0];
+  double vx = w[1] / rho, vy = (D == 2) ? w[2] / rho : 0.0;
+  double p = 2.0 / 3.0 * (w[E] - 0.5 * rho * (vx * vx + vy * vy));
+  double vn = vx * nx + ((D == 2) ? vy * ny : 0.0);
+  double th = vn - un;
+  double thb = 0.0;
+  for (int m = 0; m <= E; ++m) { thb += ab[m] * w[m]; Wb[m] += ab[m] * th; }
+  double pb = ab[1] * nx + ((D == 2) ? ab[2] * ny : 0.0) + ab[E] * vn;
+  double vnb = thb + ab[E] * p;
+  Wb[1] += vnb * nx / rho;
+  if (D == 2) Wb[2] += vnb * ny / rho;
+  Wb[0] += -vnb * vn / rho;
+  const double k = 2.0 / 3.0;
+  Wb[E] += k * pb;
+  Wb[1] += -k * pb * vx;
+  if (D == 2) Wb[2] += -k * pb * vy;
+  Wb[0] += k * pb * 0.5 * (vx * vx + vy * vy);
+}
+
+// base bar of dW: the predictor W~ = W + dW (or W where W + dW is not a
+// physical state: the solver keeps W there)
+__global__ void k_adj_macro_init(Dev g, const double* __restrict__ W, const double* __restrict__ dW,
+                                 const double* __restrict__ Wpb, double* __restrict__ Wbar,
+                                 double* __restrict__ dWb) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  const int nw = g.nw;
+  bool upd = false;
+  if (g.type[c] == 1) {
+    double t[4] = {0, 0, 0, 0};
+    for (int m = 0; m < nw; ++m) t[m] = W[(size_t)c * nw + m] + dW[(size_t)c * nw + m];
+    upd = physical_state(g.dim, t);
+  }
+  for (int m = 0; m < nw; ++m) {
+    double v = Wpb[(size_t)c * nw + m];
+    Wbar[(size_t)c * nw + m] += v;
+    dWb[(size_t)c * nw + m] = upd ? v : 0.0;
+  }
+}
+
+// reverse of the two nonlinear sweeps, one workgroup per block, one thread
+// per row; pass 1 (ascending hyperplanes) reverses the backward sweep,
+// pass 2 (descending) the forward sweep
+__global__ __launch_bounds__(512) void k_adj_macro_sweep(
+    Dev g, const int* __restrict__ binfo, double dt, const double* __restrict__ W,
+    const double* __restrict__ dWs, const double* __restrict__ dW, const double* __restrict__ gam,
+    const double* __restrict__ dWb, double* __restrict__ abar, double* __restrict__ bbarm,
+    double* __restrict__ dWsb, double* __restrict__ Rb, double* __restrict__ Dgb, double* __restrict__ gamb,
+    double* __restrict__ Wbar, double* __restrict__ fbar) {
+  const int blk = blockIdx.x;
+  const int ni = binfo[8 * blk], nj = binfo[8 * blk + 1], c0 = binfo[8 * blk + 2];
+  const int D = g.dim, nw = g.nw, ns = 2 * D;
+  const int nh = ni + nj - 1;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int it = 0; it < nh; ++it) {
+      const int hp = (pass == 0) ? it : nh - 1 - it;
+      for (int j = threadIdx.x; j < nj; j += blockDim.x) {
+        const int i = hp - j;
+        if (i < 0 || i >= ni) continue;
+        const int n = c0 + i + ni * j;
+        if (g.type[n] != 1) continue;
+        const double ivol = 1.0 / g.vol[n];
+        double sg = 0.0;
+        for (int s = 0; s < ns; ++s) {
+          int f = g.cf[4 * n + s];
+          if (f >= 0) sg += g.fgeo[(size_t)f * 8 + 2] * gam[f];
+        }
+        const double Dg = 1.0 / g.dtp[n] + 1.0 / dt + 0.25 * ivol * sg;
+        const double* Wn_ = W + (size_t)n * nw;
+        const double* x = (pass == 0) ? dW + (size_t)n * nw : dWs + (size_t)n * nw;
+        double base[4] = {0, 0, 0, 0}, Wl[4] = {0, 0, 0, 0}, acc[4] = {0, 0, 0, 0};
+        for (int m = 0; m < nw; ++m) base[m] = (pass == 0) ? dWb[(size_t)n * nw + m] : dWsb[(size_t)n * nw + m];
+        double Wt[4] = {0, 0, 0, 0};
+        for (int m = 0; m < nw; ++m) Wt[m] = Wn_[m] + x[m];
+        for (int s = 0; s < ns; ++s) {
+          const int m_ = g.nb[4 * n + s];
+          if (m_ < 0 || g.type[m_] != 1) continue;
+          const int f = g.cf[4 * n + s];
+          const double* fg = g.fgeo + (size_t)f * 8;
+          const double S = fg[2];
+          const double sig = (s & 1) ? 1.0 : -1.0;
+          const double nx = sig * fg[0], ny = sig * fg[1];
+          const double un = fg[3] * nx + fg[4] * ny;
+          const bool lower = m_ < n;
+          if (lower == (pass == 0)) {
+            // the neighbour coupled this cell into its own sweep: gather its bar
+            const double* am = ((pass == 0) ? abar : bbarm) + (size_t)m_ * nw;
+            double v1[4] = {0, 0, 0, 0}, v0[4] = {0, 0, 0, 0};
+            euler_vjp(D, Wt, -nx, -ny, -un, am, v1);
+            euler_vjp(D, Wn_, -nx, -ny, -un, am, v0);
+            double ax_ = 0.0;
+            for (int m = 0; m < nw; ++m) {
+              base[m] += S * (v1[m] - gam[f] * am[m]);
+              Wl[m] += S * (v1[m] - v0[m]);
+              ax_ += am[m] * x[m];
+            }
+            gamb[f] += -S * ax_;
+            // un of the neighbour's normal is -un: F_E depends on it through -W
+            fbar[(size_t)f * 5 + 0] += -S * ax_ * (-nx);
+            fbar[(size_t)f * 5 + 1] += -S * ax_ * (-ny);
+          } else if (pass == 0) {
+            // this cell's own backward-sweep coupling (recomputed)
+            const double* xm = dW + (size_t)m_ * nw;
+            const double* Wm = W + (size_t)m_ * nw;
+            double w1[4] = {0, 0, 0, 0}, e1[4], e0[4];
+            for (int m = 0; m < nw; ++m) w1[m] = Wm[m] + xm[m];
+            euler_f(D, w1, nx, ny, un, e1);
+            euler_f(D, Wm, nx, ny, un, e0);
+            for (int m = 0; m < nw; ++m) acc[m] += S * (e1[m] - e0[m]) - S * gam[f] * xm[m];
+          }
+        }
+        const double ab = -0.25 * ivol / Dg;
+        double dgb = 0.0;
+        for (int m = 0; m < nw; ++m) {
+          Wbar[(size_t)n * nw + m] += Wl[m];
+          if (pass == 0) {
+            abar[(size_t)n * nw + m] = ab * base[m];
+            dWsb[(size_t)n * nw + m] = base[m];
+            dgb += 0.25 * ivol * base[m] * acc[m] / (Dg * Dg);
+          } else {
+            bbarm[(size_t)n * nw + m] = ab * base[m];
+            Rb[(size_t)n * nw + m] = base[m] / Dg;
+            dgb += -base[m] * x[m] / Dg;
+          }
+        }
+        Dgb[n] += dgb;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// residual and diagonal bars to W, Wn, F, Fn and Gamma; one thread per cell
+__global__ void k_adj_macro_post(Dev g, double dt, const double* __restrict__ Rb, const double* __restrict__ Dgb,
+                                 double* __restrict__ Wbar, double* __restrict__ Wnb, double* __restrict__ Fbar,
+                                 double* __restrict__ Fnb, double* __restrict__ gamb) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  const int nw = g.nw;
+  if (g.type[c] != 1) return;
+  const double ivol = 1.0 / g.vol[c];
+  for (int m = 0; m < nw; ++m) {
+    double r = Rb[(size_t)c * nw + m];
+    Wbar[(size_t)c * nw + m] -= r / dt;
+    Wnb[(size_t)c * nw + m] += r / dt;
+  }
+  for (int s = 0; s < 2 * g.dim; ++s) {
+    int f = g.cf[4 * c + s];
+    if (f < 0) continue;
+    const double S = g.fgeo[(size_t)f * 8 + 2];
+    const double sig = (s & 1) ? 1.0 : -1.0;
+    for (int m = 0; m < nw; ++m) {
+      double v = -0.5 * ivol * sig * S * Rb[(size_t)c * nw + m];
+      atomic_add(Fbar + (size_t)f * nw + m, v);
+      atomic_add(Fnb + (size_t)f * nw + m, v);
+    }
+    atomic_add(gamb + f, 0.25 * ivol * S * Dgb[c]);
+  }
+}
+
+// spectral radius Gamma of a face reversed: one thread per face
+__global__ void k_adj_gamma(Dev g, const double* __restrict__ W, const double* __restrict__ gamb,
+                            double* __restrict__ Wbar, double* __restrict__ fbar) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= g.nface) return;
+  const double gb = gamb[f];
+  if (gb == 0.0) return;
+  const int D = g.dim, nw = g.nw;
+  const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
+  const double* fg = g.fgeo + (size_t)f * 8;
+  const double nx = fg[0], ny = fg[1];
+  const double gma = (double)(D + g.nxi + 2) / (double)(D + g.nxi);
+  auto side = [&](int code, int inner, double wgt_u, double wgt_a, double thb) {
+    const double* w;
+    int tgt;
+    if (code >= 0) { w = W + (size_t)code * nw; tgt = code; }
+    else if (code == kNbFar) return;
+    else { w = W + (size_t)inner * nw; tgt = inner; }
+    double rho, ux, uy, lam;
+    prim_d(D, g.nxi, w, rho, ux, uy, lam);
+    double a = sqrt(gma * 0.5 / lam);
+    double lb = -wgt_a * gb * a / (2.0 * lam);
+    double Wl[4] = {0, 0, 0, 0};
+    prim_rev(D, g.nxi, w, 0.0, wgt_u * thb * nx, wgt_u * thb * ny, lb, Wl);
+    for (int m = 0; m < nw; ++m) atomic_add(Wbar + (size_t)tgt * nw + m, Wl[m]);
+  };
+  double thv;
+  if (L == kNbWall || R == kNbWall) {
+    int c = (L == kNbWall) ? R : L;
+    if (c < 0) return;
+    double rho, ux, uy, lam;
+    prim_d(D, g.nxi, W + (size_t)c * nw, rho, ux, uy, lam);
+    thv = (ux - fg[3]) * nx + (uy - fg[4]) * ny;
+    double thb = gb * ((thv < 0.0) ? -1.0 : 1.0);
+    side(c, c, 1.0, 1.0, thb);
+    fbar[(size_t)f * 5 + 0] += -thb * nx;
+    fbar[(size_t)f * 5 + 1] += -thb * ny;
+    return;
+  }
+  int inner = (L >= 0) ? L : R;
+  if (inner < 0) return;
+  auto vel = [&](int code, double& ux, double& uy) {
+    const double* w = (code >= 0) ? W + (size_t)code * nw : ((code == kNbFar) ? g.winf : W + (size_t)inner * nw);
+    ux = w[1] / w[0];
+    uy = (D == 2) ? w[2] / w[0] : 0.0;
+  };
+  double u1, v1, u2, v2;
+  vel(L, u1, v1);
+  vel(R, u2, v2);
+  thv = (0.5 * (u1 + u2) - fg[3]) * nx + (0.5 * (v1 + v2) - fg[4]) * ny;
+  double thb = gb * ((thv < 0.0) ? -1.0 : 1.0);
+  side(L, inner, 0.5, 0.5, thb);
+  side(R, inner, 0.5, 0.5, thb);
+  fbar[(size_t)f * 5 + 0] += -thb * nx;
+  fbar[(size_t)f * 5 + 1] += -thb * ny;
+}
+
+// ------------------------------------------------------------------------
+// Steps 1-2 source S = f/dt + (D + (f+ - f)/tau)/2 reversed (one wavefront
+// per cell): bars of f, of the divergence D and of (W, q) through f+ and tau
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adj_source(Dev g, double dt, const double* __restrict__ crec,
+                                                    const double* __restrict__ W, const double* __restrict__ h,
+                                                    const double* __restrict__ b, const double* __restrict__ Shb,
+                                                    const double* __restrict__ Sbb, double* __restrict__ hbar,
+                                                    double* __restrict__ bbar, double* __restrict__ Dbh,
+                                                    double* __restrict__ Dbb, double* __restrict__ Wbar,
+                                                    double* __restrict__ qbar) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= g.ncell) return;
+  const int D = g.dim, nv = g.nv, nw = g.nw;
+  if (g.type[c] != 1) {
+    for (int k = lane; k < nv; k += 64) { Dbh[(size_t)c * nv + k] = 0.0; Dbb[(size_t)c * nv + k] = 0.0; }
+    return;
+  }
+  const double* r = crec + (size_t)c * NCREC;
+  const double rho = r[C_RHO], ux = r[C_UX], uy = r[C_UY], lam = r[C_LAM], qx = r[C_QX], qy = r[C_QY];
+  const double it = r[C_ITAU];
+  const double hn = rho * pow(lam / kPi, 0.5 * D);
+  const double shc = 4.0 * (1.0 - g.pr) * lam * lam / (5.0 * rho);
+  double a[6] = {0, 0, 0, 0, 0, 0};
+  double itb = 0.0;
+  for (int k = lane; k < nv; k += 64) {
+    const size_t o = (size_t)c * nv + k;
+    const double vx = g.vx[k], vy = g.vy[k];
+    const double sh = Shb[o], sb = Sbb[o];
+    const double cx = vx - ux, cy = (D == 2) ? vy - uy : 0.0;
+    const double c2 = cx * cx + cy * cy;
+    const double H = hn * exp(-lam * c2);
+    const double beta = (double)g.nxi / (2.0 * lam);
+    const double sq = shc * (cx * qx + cy * qy);
+    const double hp = H + sq * (2.0 * lam * c2 - 2.0 - D) * H;
+    const double bp = beta * H + sq * (2.0 * lam * c2 - D) * beta * H;
+    hbar[o] += sh * (1.0 / dt - 0.5 * it);
+    bbar[o] += sb * (1.0 / dt - 0.5 * it);
+    Dbh[o] = 0.5 * sh;
+    Dbb[o] = 0.5 * sb;
+    itb += 0.5 * (sh * (hp - h[o]) + sb * (bp - b[o]));
+    eq_rev(g, rho, ux, uy, lam, qx, qy, vx, vy, 0.5 * it * sh, 0.5 * it * sb, 0.5 * it * sh, 0.5 * it * sb, a);
+  }
+  for (int i = 0; i < 6; ++i) a[i] = wave_sum(a[i]);
+  itb = wave_sum(itb);
+  double dr, dl;
+  itau_partials(g, rho, lam, dr, dl);
+  if (g.mu_ref > 0.0) { a[0] += itb * dr; a[3] += itb * dl; }
+  double Wl[4] = {0, 0, 0, 0};
+  prim_rev(D, g.nxi, W + (size_t)c * nw, a[0], a[1], a[2], a[3], Wl);
+  if (lane < nw) atomic_add(Wbar + (size_t)c * nw + lane, Wl[lane]);
+  if (lane == 0) {
+    atomic_add(qbar + (size_t)c * D, a[4]);
+    if (D == 2) atomic_add(qbar + (size_t)c * D + 1, a[5]);
+  }
+}
+
+// ------------------------------------------------------------------------
+// overset interpolation reversed (Sec. 3.2): the bars of the rows' target
+// cells move to their donors and the targets' bars become zero; one
+// wavefront per row (donors are never targets of the same call)
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adj_interp(Dev g, int nrow, const int* __restrict__ rec,
+                                                    const int* __restrict__ ptr, const int* __restrict__ don,
+                                                    const double* __restrict__ wt, double* __restrict__ hbar,
+                                                    double* __restrict__ bbar, double* __restrict__ Wbar,
+                                                    double* __restrict__ qbar) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= nrow) return;
+  const int c = rec[r], p0 = ptr[r], p1 = ptr[r + 1];
+  for (int k = lane; k < g.nv; k += 64) {
+    const size_t o = (size_t)c * g.nv + k;
+    const double vh = hbar[o], vb = bbar[o];
+    for (int p = p0; p < p1; ++p) {
+      atomic_add(hbar + (size_t)don[p] * g.nv + k, wt[p] * vh);
+      atomic_add(bbar + (size_t)don[p] * g.nv + k, wt[p] * vb);
+    }
+    hbar[o] = 0.0;
+    bbar[o] = 0.0;
+  }
+  if (lane < g.nw) {
+    const double v = Wbar[(size_t)c * g.nw + lane];
+    for (int p = p0; p < p1; ++p) atomic_add(Wbar + (size_t)don[p] * g.nw + lane, wt[p] * v);
+    Wbar[(size_t)c * g.nw + lane] = 0.0;
+  }
+  if (lane >= 8 && lane < 8 + g.dim) {
+    const int m = lane - 8;
+    const double v = qbar[(size_t)c * g.dim + m];
+    for (int p = p0; p < p1; ++p) atomic_add(qbar + (size_t)don[p] * g.dim + m, wt[p] * v);
+    qbar[(size_t)c * g.dim + m] = 0.0;
+  }
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+static inline unsigned nblk(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+void adj_flux(const Dev& g, double dts, const double* h, const double* b, const double* W, const double* q,
+              const double* gW, const double* Dbh, const double* Dbb, const double* Fb, double* hbar,
+              double* bbar, double* Wbar, double* qbar, double* gWbar, double* fbar, hipStream_t st) {
+  if (g.nface > 0) {
+    hipLaunchKernelGGL(k_adj_face, dim3(nblk(g.nface, 4)), dim3(256), 0, st, g, dts, h, b, gW, Dbh, Dbb, Fb, hbar,
+                       bbar, gWbar, fbar);
+    hipLaunchKernelGGL(k_adj_wall, dim3(nblk(g.nface, 4)), dim3(256), 0, st, g, dts, h, b, W, q, gW, Dbh, Dbb, Fb,
+                       hbar, bbar, Wbar, qbar, gWbar, fbar);
+  }
+  hipLaunchKernelGGL(k_adj_gradW, dim3(nblk(g.ncell, 128)), dim3(128), 0, st, g, W, gWbar, Wbar);
+}
+
+void adj_step7(const Dev& g, const double* h1, const double* b1, const double* W1, const double* Wp,
+               const double* W1b, const double* q1b, double* hb, double* bb, double* Wpb, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_step7, dim3(nblk(g.ncell, 4)), dim3(256), 0, st, g, h1, b1, W1, Wp, W1b, q1b, hb, bb,
+                     Wpb);
+}
+
+void adj_micro(const Dev& g, const int* binfo, int nblock, double dt, const double* crec, const double* Wp,
+               const double* h0, const double* b0, const double* h1, const double* b1, const double* xsh,
+               const double* xsb, const double* xbh, const double* xbb, double* yh, double* yb, double* rh,
+               double* rb, double* hbar, double* bbar, double* Shb, double* Sbb, double* Dbh, double* Dbb,
+               double* Wpb, double* fbar, hipStream_t st) {
+  dim3 grid(nblock, nblk(g.nv, 64));
+  hipLaunchKernelGGL(k_adj_micro_sweep<0>, grid, dim3(1024), 0, st, g, binfo, crec, xbh, xbb, yh, yb);
+  hipLaunchKernelGGL(k_adj_micro_sweep<1>, grid, dim3(1024), 0, st, g, binfo, crec, (const double*)yh,
+                     (const double*)yb, rh, rb);
+  hipLaunchKernelGGL(k_adj_micro_coef, dim3(nblk(g.ncell, 4)), dim3(256), 0, st, g, dt, crec, Wp, h0, b0, h1, b1,
+                     xsh, xsb, (const double*)yh, (const double*)yb, (const double*)rh, (const double*)rb, xbh, xbb,
+                     hbar, bbar, Shb, Sbb, Dbh, Dbb, Wpb, fbar);
+}
+
+void adj_macro(const Dev& g, const int* binfo, int nblock, double dt, const double* W, const double* dWs,
+               const double* dW, const double* gam, const double* Wpb, double* dWb, double* abar, double* bbarm,
+               double* dWsb, double* Rb, double* Dgb, double* gamb, double* Wbar, double* Wnb, double* Fbar,
+               double* Fnb, double* fbar, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_macro_init, dim3(nblk(g.ncell, 128)), dim3(128), 0, st, g, W, dW, Wpb, Wbar, dWb);
+  hipLaunchKernelGGL(k_adj_macro_sweep, dim3(nblock), dim3(512), 0, st, g, binfo, dt, W, dWs, dW, gam,
+                     (const double*)dWb, abar, bbarm, dWsb, Rb, Dgb, gamb, Wbar, fbar);
+  hipLaunchKernelGGL(k_adj_macro_post, dim3(nblk(g.ncell, 128)), dim3(128), 0, st, g, dt, (const double*)Rb,
+                     (const double*)Dgb, Wbar, Wnb, Fbar, Fnb, gamb);
+  if (g.nface > 0)
+    hipLaunchKernelGGL(k_adj_gamma, dim3(nblk(g.nface, 128)), dim3(128), 0, st, g, W, (const double*)gamb, Wbar,
+                       fbar);
+}
+
+void adj_source(const Dev& g, double dt, const double* crec, const double* W, const double* h, const double* b,
+                const double* Shb, const double* Sbb, double* hbar, double* bbar, double* Dbh, double* Dbb,
+                double* Wbar, double* qbar, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_source, dim3(nblk(g.ncell, 4)), dim3(256), 0, st, g, dt, crec, W, h, b, Shb, Sbb, hbar,
+                     bbar, Dbh, Dbb, Wbar, qbar);
+}
+
+void adj_interp(const Dev& g, int nrow, const int* rec, const int* ptr, const int* don, const double* w,
+                double* hbar, double* bbar, double* Wbar, double* qbar, hipStream_t st) {
+  if (nrow <= 0) return;
+  hipLaunchKernelGGL(k_adj_interp, dim3(nblk(nrow, 4)), dim3(256), 0, st, g, nrow, rec, ptr, don, w, hbar, bbar,
+                     Wbar, qbar);
+}
+
+}  // namespace ugks

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "ugks.h"
+#include "ugks_adjoint.h"
 #include "ugks_kernels.h"
 #include "ugks_overset.h"
 
@@ -89,6 +90,8 @@ struct ugks_ctx {
   void *d_rec = nullptr, *d_ptr = nullptr, *d_don = nullptr, *d_w = nullptr;
   std::vector<int> h_rec, h_ptr, h_don;
   std::vector<double> h_w;
+  // workspace of the reverse-mode entry points (allocated on first use)
+  std::vector<void*> adj;
 };
 
 namespace {
@@ -458,6 +461,9 @@ void free_all(ugks_ctx* c) {
                 c->s_Dh, c->s_Db, c->s_F, c->s_part, c->d_rec, c->d_ptr, c->d_don, c->d_w, c->d_cplan, c->d_fplan};
   for (void* p : ps)
     if (p) (void)hipFree(p);
+  for (void* p : c->adj)
+    if (p) (void)hipFree(p);
+  c->adj.clear();
 }
 
 }  // namespace
@@ -672,6 +678,23 @@ int ugks_set_poses(ugks_ctx* c, const double* poses, double* dts) {
   int rc = upload_geometry(c);
   if (rc) return rc;
   if (dts) *dts = c->dts;
+  return UGKS_OK;
+}
+
+int ugks_set_wall_rt(ugks_ctx* c, int32_t blk, int32_t side, double rtw) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  if (blk < 0 || blk >= (int)c->blk.size() || side < 0 || side > 3) return fail(UGKS_E_ARG, "bad block side");
+  if (!(rtw > 0.0) || !std::isfinite(rtw)) return fail(UGKS_E_ARG, "wall RT must be positive");
+  ++c->version;
+  c->blk[blk].rtw[side] = rtw;
+  compute_geometry(c);
+  return upload_geometry(c);
+}
+
+int ugks_last_flux(const ugks_ctx* c, double* F, void* stream) {
+  if (!c || !F) return fail(UGKS_E_ARG, "null argument");
+  HIPCHK(hipMemcpyAsync(F, c->s_F, sizeof(double) * c->nw * (size_t)c->nface, hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
   return UGKS_OK;
 }
 
@@ -1157,6 +1180,252 @@ int ugks_autotune(ugks_ctx* c, double dt, int32_t n_inner, const void* h, const 
   for (void* p : {th, tb, tW, tq}) if (p) (void)hipFree(p);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
+  return rc;
+}
+
+
+// ---------------------------------------------------------------------------
+// reverse mode (adjoint) of Steps 1-2, of the pseudo-iteration and of the flux
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+enum AdjBuf {
+  // [ncell][nv]
+  A_H0, A_B0, A_H1, A_B1, A_XBH, A_XBB, A_YH, A_YB, A_RH, A_RB, A_DBH, A_DBB, A_HB, A_BB,
+  // [ncell][nw], [ncell][dim]
+  A_W0, A_W1, A_Q0, A_Q1, A_WPB, A_DWB, A_ABAR, A_BBAR, A_DWSB, A_RBAR, A_WB, A_QB,
+  // others
+  A_DGB, A_GWB, A_GAMB, A_FB, A_FBAR, A_NBUF
+};
+
+int adj_alloc(ugks_ctx* c) {
+  if (!c->adj.empty()) return UGKS_OK;
+  c->adj.assign(A_NBUF, nullptr);
+  const size_t N = (size_t)c->ncell * c->nv, NW = (size_t)c->ncell * c->nw, NQ = (size_t)c->ncell * c->dim;
+  for (int i = 0; i < A_NBUF; ++i) {
+    size_t n;
+    if (i <= A_BB) n = N;
+    else if (i == A_Q0 || i == A_Q1 || i == A_QB) n = NQ;
+    else if (i <= A_WB) n = NW;
+    else if (i == A_DGB) n = c->ncell;
+    else if (i == A_GWB) n = 8 * (size_t)c->ncell;
+    else if (i == A_GAMB) n = c->nface;
+    else if (i == A_FB) n = (size_t)c->nface * c->nw;
+    else n = (size_t)c->nface * 5;
+    if (hipMalloc(&c->adj[i], sizeof(double) * std::max<size_t>(n, 1)) != hipSuccess) {
+      for (void*& p : c->adj) { if (p) (void)hipFree(p); p = nullptr; }
+      c->adj.clear();
+      return fail(UGKS_E_DEVICE, "adjoint workspace allocation");
+    }
+  }
+  return UGKS_OK;
+}
+
+double* A(ugks_ctx* c, int i) { return (double*)c->adj[i]; }
+
+int adj_check(ugks_ctx* c) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  if (c->prec != UGKS_F64) return fail(UGKS_E_UNSUPPORTED, "the adjoint needs FP64 storage");
+  if (c->dim != 2) return fail(UGKS_E_UNSUPPORTED, "the adjoint is built for 2D cases");
+  return adj_alloc(c);
+}
+
+int dcopy(void* dst, const void* src, size_t n, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  return UGKS_OK;
+}
+
+int dzero(void* dst, size_t n, hipStream_t st) {
+  HIPCHK(hipMemsetAsync(dst, 0, sizeof(double) * n, st));
+  return UGKS_OK;
+}
+
+// copy of a cotangent argument, or zeros when it is NULL
+int dcopy_or_zero(void* dst, const void* src, size_t n, hipStream_t st) {
+  return src ? dcopy(dst, src, n, st) : dzero(dst, n, st);
+}
+
+// the flux reverse at (H0, B0, W0, Q0) with divergence bars A_DBH/A_DBB and
+// face-flux bar A_FB: accumulates into A_HB, A_BB, A_WB, A_QB, A_FBAR
+// (s_gW must hold the forward gradients of W0)
+int flux_reverse(ugks_ctx* c, hipStream_t st) {
+  if (int rc = dzero(A(c, A_GWB), 8 * (size_t)c->ncell, st)) return rc;
+  adj_flux(c->dev, c->dts, A(c, A_H0), A(c, A_B0), A(c, A_W0), A(c, A_Q0), (const double*)c->s_gW, A(c, A_DBH),
+           A(c, A_DBB), A(c, A_FB), A(c, A_HB), A(c, A_BB), A(c, A_WB), A(c, A_QB), A(c, A_GWB), A(c, A_FBAR), st);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+int interp_rows(ugks_ctx* c, int r0, int nrow, double* h, double* b, double* W, double* q, hipStream_t st) {
+  if (nrow <= 0) return UGKS_OK;
+  launch_interp(c->dev, c->prec, nrow, (const int*)c->d_rec + r0, (const int*)c->d_ptr + r0, (const int*)c->d_don,
+                (const double*)c->d_w, h, b, W, q, st);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+int interp_rows_rev(ugks_ctx* c, int r0, int nrow, hipStream_t st) {
+  if (nrow <= 0) return UGKS_OK;
+  adj_interp(c->dev, nrow, (const int*)c->d_rec + r0, (const int*)c->d_ptr + r0, (const int*)c->d_don,
+             (const double*)c->d_w, A(c, A_HB), A(c, A_BB), A(c, A_WB), A(c, A_QB), st);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+// load the state into the workspace (H0.. = copies)
+int load_state(ugks_ctx* c, const void* h, const void* b, const double* W, const double* q, hipStream_t st) {
+  const size_t N = (size_t)c->ncell * c->nv;
+  int rc = dcopy(A(c, A_H0), h, N, st);
+  if (!rc) rc = dcopy(A(c, A_B0), b, N, st);
+  if (!rc) rc = dcopy(A(c, A_W0), W, (size_t)c->ncell * c->nw, st);
+  if (!rc) rc = dcopy(A(c, A_Q0), q, (size_t)c->ncell * c->dim, st);
+  return rc;
+}
+
+int store_bars(ugks_ctx* c, double* hb, double* bb, double* Wb, double* qb, double* faceb, hipStream_t st) {
+  const size_t N = (size_t)c->ncell * c->nv;
+  int rc = UGKS_OK;
+  if (!rc && hb) rc = dcopy(hb, A(c, A_HB), N, st);
+  if (!rc && bb) rc = dcopy(bb, A(c, A_BB), N, st);
+  if (!rc && Wb) rc = dcopy(Wb, A(c, A_WB), (size_t)c->ncell * c->nw, st);
+  if (!rc && qb) rc = dcopy(qb, A(c, A_QB), (size_t)c->ncell * c->dim, st);
+  if (!rc && faceb) rc = dcopy(faceb, A(c, A_FBAR), 5 * (size_t)c->nface, st);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ugks_flux_adjoint(ugks_ctx* c, const void* h, const void* b, const double* W, const double* q,
+                      const double* Dh_bar, const double* Db_bar, const double* F_bar, double* h_bar, double* b_bar,
+                      double* W_bar, double* q_bar, double* face_bar, void* stream) {
+  if (int rc = check_dev(c, {h, b, W, q, h_bar, b_bar, W_bar, q_bar})) return rc;
+  if (int rc = adj_check(c)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t N = (size_t)c->ncell * c->nv;
+  int rc = load_state(c, h, b, W, q, st);
+  // forward: the W gradients (the divergence and face fluxes land in scratch)
+  if (!rc) rc = dzero(c->s_F, (size_t)c->nw * c->nface, st);
+  if (rc) return rc;
+  launch_flux(c->dev, c->prec, (const int*)c->d_binfo, c->max_nj, c->dts, A(c, A_H0), A(c, A_B0), A(c, A_W0),
+              A(c, A_Q0), (double*)c->s_gW, (double*)c->s_rec, (double*)c->s_part, c->s_Dh, c->s_Db,
+              (double*)c->s_F, nullptr, st);
+  HIPCHK(hipGetLastError());
+  rc = dcopy_or_zero(A(c, A_DBH), Dh_bar, N, st);
+  if (!rc) rc = dcopy_or_zero(A(c, A_DBB), Db_bar, N, st);
+  if (!rc) rc = dcopy_or_zero(A(c, A_FB), F_bar, (size_t)c->nface * c->nw, st);
+  for (int i : {A_HB, A_BB}) if (!rc) rc = dzero(A(c, i), N, st);
+  if (!rc) rc = dzero(A(c, A_WB), (size_t)c->ncell * c->nw, st);
+  if (!rc) rc = dzero(A(c, A_QB), (size_t)c->ncell * c->dim, st);
+  if (!rc) rc = dzero(A(c, A_FBAR), 5 * (size_t)c->nface, st);
+  if (!rc) rc = flux_reverse(c, st);
+  if (!rc) rc = store_bars(c, h_bar, b_bar, W_bar, q_bar, face_bar, st);
+  return rc;
+}
+
+int ugks_step_adjoint(ugks_ctx* c, double dt, const void* h, const void* b, const double* W, const double* Wn,
+                      const double* q, const void* Sh, const void* Sb, const double* Fn, const double* h1_bar,
+                      const double* b1_bar, const double* W1_bar, const double* q1_bar, const double* F_bar,
+                      double* h_bar, double* b_bar, double* W_bar, double* Wn_bar, double* q_bar, double* Sh_bar,
+                      double* Sb_bar, double* Fn_bar, double* face_bar, void* stream) {
+  if (int rc = check_dev(c, {h, b, W, Wn, q, Sh, Sb, Fn, h_bar, b_bar, W_bar, Wn_bar, q_bar, Sh_bar, Sb_bar,
+                             Fn_bar}))
+    return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
+  if (int rc = adj_check(c)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Dev& g = c->dev;
+  const size_t N = (size_t)c->ncell * c->nv, NW = (size_t)c->ncell * c->nw, NQ = (size_t)c->ncell * c->dim;
+  const int nblock = (int)c->blk.size();
+  // forward recomputation: the interpolated input state (H0..) and one
+  // pseudo-iteration from it (H1..); the solver's scratch keeps the
+  // intermediates (W gradients, Gamma, dW*, dW, W~ and its record, dF*)
+  int rc = load_state(c, h, b, W, q, st);
+  if (!rc) rc = interp_rows(c, 0, c->nrec, A(c, A_H0), A(c, A_B0), A(c, A_W0), A(c, A_Q0), st);
+  if (!rc) rc = dcopy(A(c, A_H1), A(c, A_H0), N, st);
+  if (!rc) rc = dcopy(A(c, A_B1), A(c, A_B0), N, st);
+  if (!rc) rc = dcopy(A(c, A_W1), A(c, A_W0), NW, st);
+  if (!rc) rc = dcopy(A(c, A_Q1), A(c, A_Q0), NQ, st);
+  if (!rc) rc = run_inner(c, dt, 1, A(c, A_H1), A(c, A_B1), A(c, A_W1), Wn, A(c, A_Q1), Sh, Sb, Fn, nullptr, st,
+                          nullptr);
+  if (rc) return rc;
+  // Step 7 and the new heat flux
+  rc = dcopy_or_zero(A(c, A_XBH), h1_bar, N, st);
+  if (!rc) rc = dcopy_or_zero(A(c, A_XBB), b1_bar, N, st);
+  if (!rc) rc = dcopy_or_zero(A(c, A_RBAR), W1_bar, NW, st);  // staging of W' bar
+  if (!rc) rc = dcopy_or_zero(A(c, A_QB), q1_bar, NQ, st);    // staging of q' bar
+  if (rc) return rc;
+  adj_step7(g, A(c, A_H1), A(c, A_B1), A(c, A_W1), (const double*)c->s_Wp, A(c, A_RBAR), A(c, A_QB), A(c, A_XBH),
+            A(c, A_XBB), A(c, A_WPB), st);
+  HIPCHK(hipGetLastError());
+  // micro LU-SGS (Steps 5-6); dF* is in s_Dh, s_Db
+  rc = dzero(A(c, A_FBAR), 5 * (size_t)c->nface, st);
+  if (rc) return rc;
+  adj_micro(g, (const int*)c->d_binfo, nblock, dt, (const double*)c->s_crec, (const double*)c->s_Wp, A(c, A_H0),
+            A(c, A_B0), A(c, A_H1), A(c, A_B1), (const double*)c->s_Dh, (const double*)c->s_Db, A(c, A_XBH),
+            A(c, A_XBB), A(c, A_YH), A(c, A_YB), A(c, A_RH), A(c, A_RB), A(c, A_HB), A(c, A_BB), Sh_bar, Sb_bar,
+            A(c, A_DBH), A(c, A_DBB), A(c, A_WPB), A(c, A_FBAR), st);
+  HIPCHK(hipGetLastError());
+  // macro LU-SGS (Step 4)
+  rc = dzero(A(c, A_WB), NW, st);
+  if (!rc) rc = dzero(Wn_bar, NW, st);
+  if (!rc) rc = dzero(Fn_bar, (size_t)c->nface * c->nw, st);
+  if (!rc) rc = dcopy_or_zero(A(c, A_FB), F_bar, (size_t)c->nface * c->nw, st);
+  if (!rc) rc = dzero(A(c, A_DGB), c->ncell, st);
+  if (!rc) rc = dzero(A(c, A_GAMB), c->nface, st);
+  if (rc) return rc;
+  adj_macro(g, (const int*)c->d_binfo, nblock, dt, A(c, A_W0), (const double*)c->s_dWs, (const double*)c->s_dW,
+            (const double*)c->s_gam, A(c, A_WPB), A(c, A_DWB), A(c, A_ABAR), A(c, A_BBAR), A(c, A_DWSB),
+            A(c, A_RBAR), A(c, A_DGB), A(c, A_GAMB), A(c, A_WB), Wn_bar, A(c, A_FB), Fn_bar, A(c, A_FBAR), st);
+  HIPCHK(hipGetLastError());
+  // flux (Step 3) at the interpolated state, then the interpolation
+  rc = dzero(A(c, A_QB), NQ, st);
+  if (!rc) rc = flux_reverse(c, st);
+  if (!rc) rc = interp_rows_rev(c, 0, c->nrec, st);
+  if (!rc) rc = store_bars(c, h_bar, b_bar, W_bar, q_bar, face_bar, st);
+  return rc;
+}
+
+int ugks_begin_step_adjoint(ugks_ctx* c, double dt, const void* h, const void* b, const double* W, const double* q,
+                            int32_t refill, const double* h1_bar, const double* b1_bar, const double* W1_bar,
+                            const double* q1_bar, const double* Sh_bar, const double* Sb_bar, const double* Fn_bar,
+                            double* h_bar, double* b_bar, double* W_bar, double* q_bar, double* face_bar,
+                            void* stream) {
+  if (int rc = check_dev(c, {h, b, W, q, Sh_bar, Sb_bar, h_bar, b_bar, W_bar, q_bar})) return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
+  if (int rc = adj_check(c)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t N = (size_t)c->ncell * c->nv, NW = (size_t)c->ncell * c->nw, NQ = (size_t)c->ncell * c->dim;
+  const int nref = refill ? (int)c->h_rec.size() - c->nrec : 0;
+  // forward: refills, receptors, the W gradients and the cell records
+  int rc = load_state(c, h, b, W, q, st);
+  if (!rc) rc = interp_rows(c, c->nrec, nref, A(c, A_H0), A(c, A_B0), A(c, A_W0), A(c, A_Q0), st);
+  if (!rc) rc = interp_rows(c, 0, c->nrec, A(c, A_H0), A(c, A_B0), A(c, A_W0), A(c, A_Q0), st);
+  if (!rc) rc = dzero(A(c, A_FB), (size_t)c->nface * c->nw, st);
+  if (rc) return rc;
+  launch_flux(c->dev, c->prec, (const int*)c->d_binfo, c->max_nj, c->dts, A(c, A_H0), A(c, A_B0), A(c, A_W0),
+              A(c, A_Q0), (double*)c->s_gW, (double*)c->s_rec, (double*)c->s_part, A(c, A_DBH), A(c, A_DBB),
+              A(c, A_FB), nullptr, st);
+  launch_cellrec(c->dev, dt, A(c, A_W0), A(c, A_Q0), nullptr, (double*)c->s_crec, st);
+  HIPCHK(hipGetLastError());
+  // reverse
+  rc = dcopy_or_zero(A(c, A_HB), h1_bar, N, st);
+  if (!rc) rc = dcopy_or_zero(A(c, A_BB), b1_bar, N, st);
+  if (!rc) rc = dcopy_or_zero(A(c, A_WB), W1_bar, NW, st);
+  if (!rc) rc = dcopy_or_zero(A(c, A_QB), q1_bar, NQ, st);
+  if (!rc) rc = dcopy_or_zero(A(c, A_FB), Fn_bar, (size_t)c->nface * c->nw, st);
+  if (!rc) rc = dzero(A(c, A_FBAR), 5 * (size_t)c->nface, st);
+  if (rc) return rc;
+  adj_source(c->dev, dt, (const double*)c->s_crec, A(c, A_W0), A(c, A_H0), A(c, A_B0), Sh_bar, Sb_bar, A(c, A_HB),
+             A(c, A_BB), A(c, A_DBH), A(c, A_DBB), A(c, A_WB), A(c, A_QB), st);
+  HIPCHK(hipGetLastError());
+  rc = flux_reverse(c, st);
+  if (!rc) rc = interp_rows_rev(c, 0, c->nrec, st);
+  if (!rc) rc = interp_rows_rev(c, c->nrec, nref, st);
+  if (!rc) rc = store_bars(c, h_bar, b_bar, W_bar, q_bar, face_bar, st);
   return rc;
 }
 

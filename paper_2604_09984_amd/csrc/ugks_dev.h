@@ -115,21 +115,25 @@ __device__ __host__ inline bool physical_state(int dim, const double* W) {
   return W[dim + 1] - 0.5 * ke / W[0] > 0.0;
 }
 
-__device__ inline double inv_tau_of(const Dev& g, double rho, double lam) {
-  if (g.mu_ref <= 0.0) return 0.0;
-  double rt = 0.5 / lam;
-  double mu = g.mu_ref * pow(rt / g.rt_ref, g.omega);
+// (the gas relations below are templates on the scalar type R: double in
+// the solver, a forward-mode dual number in the adjoint's local Jacobians)
+template <class R>
+__device__ inline R inv_tau_of(const Dev& g, R rho, R lam) {
+  if (g.mu_ref <= 0.0) return R(0.0);
+  R rt = 0.5 / lam;
+  R mu = g.mu_ref * pow(rt / g.rt_ref, g.omega);
   return rho * rt / mu;
 }
 
 // time integrals q1..q5 over [0, dts] of the interface-solution coefficients;
 // Taylor series below x = 1 (m <= 24), closed forms above
-__device__ inline void time_integrals(double dts, double itau, double* q) {
-  double x = dts * itau;
+template <class R>
+__device__ inline void time_integrals(double dts, R itau, R* q) {
+  R x = dts * itau;
   if (x < 1.0) {
-    double a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
-    double p = 1.0;  // x^(m-1)
-    double pp = 0.0; // x^(m-2)
+    R a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0;
+    R p = 1.0;  // x^(m-1)
+    R pp = 0.0; // x^(m-2)
     double fac = 1.0;
     for (int m = 1; m <= 24; ++m) {
       fac *= (double)m;
@@ -152,8 +156,8 @@ __device__ inline void time_integrals(double dts, double itau, double* q) {
     q[3] = dts * dts * a4;
     q[4] = dts * dts * a5;
   } else {
-    double tau = 1.0 / itau;
-    double e = exp(-x);
+    R tau = 1.0 / itau;
+    R e = exp(-x);
     q[0] = tau * (1.0 - e);
     q[1] = tau * tau * ((1.0 + x) * e - 1.0);
     q[2] = dts - q[0];
@@ -164,23 +168,23 @@ __device__ inline void time_integrals(double dts, double itau, double* q) {
 
 // closed-form inverse of the Maxwellian moment matrix: a with <psi psi^T> a = d
 // (gas-kinetic micro-slope formulas; K' = N_xi internal components)
-__device__ inline void slope_inverse(int dim, double U, double V, double lam, const double* d,
-                                     double* a) {
+template <class R>
+__device__ inline void slope_inverse(int dim, R U, R V, R lam, const R* d, R* a) {
   if (dim == 2) {
     const double K = 1.0;
-    double e2 = U * U + V * V + (K + 2.0) / (2.0 * lam);
-    double r4 = 2.0 * d[3] - e2 * d[0];
-    double r3 = d[2] - V * d[0];
-    double r2 = d[1] - U * d[0];
+    R e2 = U * U + V * V + (K + 2.0) / (2.0 * lam);
+    R r4 = 2.0 * d[3] - e2 * d[0];
+    R r3 = d[2] - V * d[0];
+    R r2 = d[1] - U * d[0];
     a[3] = 4.0 * lam * lam / (K + 2.0) * (r4 - 2.0 * U * r2 - 2.0 * V * r3);
     a[2] = 2.0 * lam * r3 - V * a[3];
     a[1] = 2.0 * lam * r2 - U * a[3];
     a[0] = d[0] - U * a[1] - V * a[2] - 0.5 * a[3] * e2;
   } else {
     const double K = 2.0;
-    double e2 = U * U + (K + 1.0) / (2.0 * lam);
-    double r3 = 2.0 * d[2] - e2 * d[0];
-    double r2 = d[1] - U * d[0];
+    R e2 = U * U + (K + 1.0) / (2.0 * lam);
+    R r3 = 2.0 * d[2] - e2 * d[0];
+    R r2 = d[1] - U * d[0];
     a[2] = 4.0 * lam * lam / (K + 1.0) * (r3 - 2.0 * U * r2);
     a[1] = 2.0 * lam * r2 - U * a[2];
     a[0] = d[0] - U * a[1] - 0.5 * a[2] * e2;
@@ -188,10 +192,10 @@ __device__ inline void slope_inverse(int dim, double U, double V, double lam, co
 }
 
 // <psi v_dir (a . psi)> under the normalised Maxwellian (mean U, V; 1/(2 lam))
-__device__ inline void psi_v_apsi(int dim, int dir, double U, double V, double lam,
-                                  const double* a, double* out) {
-  double th = 0.5 / lam;
-  double mu[7], mv[7];
+template <class R>
+__device__ inline void psi_v_apsi(int dim, int dir, R U, R V, R lam, const R* a, R* out) {
+  R th = 0.5 / lam;
+  R mu[7], mv[7];
   mu[0] = 1.0; mu[1] = U;
   mv[0] = 1.0; mv[1] = V;
   for (int n = 1; n < 6; ++n) {
@@ -199,32 +203,32 @@ __device__ inline void psi_v_apsi(int dim, int dir, double U, double V, double l
     mv[n + 1] = V * mv[n] + n * th * mv[n - 1];
   }
   if (dim == 1) {
-    double x1 = 2.0 * th, x2 = 8.0 * th * th;  // <xi^2>, <xi^4> for 2 components
-    double uE = 0.5 * (mu[3] + mu[1] * x1);
-    double u2E = 0.5 * (mu[4] + mu[2] * x1);
-    double uE2 = 0.25 * (mu[5] + 2.0 * mu[3] * x1 + mu[1] * x2);
+    R x1 = 2.0 * th, x2 = 8.0 * th * th;  // <xi^2>, <xi^4> for 2 components
+    R uE = 0.5 * (mu[3] + mu[1] * x1);
+    R u2E = 0.5 * (mu[4] + mu[2] * x1);
+    R uE2 = 0.25 * (mu[5] + 2.0 * mu[3] * x1 + mu[1] * x2);
     out[0] = a[0] * mu[1] + a[1] * mu[2] + a[2] * uE;
     out[1] = a[0] * mu[2] + a[1] * mu[3] + a[2] * u2E;
     out[2] = a[0] * uE + a[1] * u2E + a[2] * uE2;
     return;
   }
-  double x1 = th, x2 = 3.0 * th * th;  // one internal component
+  R x1 = th, x2 = 3.0 * th * th;  // one internal component
   if (dir == 1) {  // swap roles of the two axes
-    for (int n = 0; n < 7; ++n) { double t = mu[n]; mu[n] = mv[n]; mv[n] = t; }
+    for (int n = 0; n < 7; ++n) { R t = mu[n]; mu[n] = mv[n]; mv[n] = t; }
   }
   // moments with w the chosen axis (mu) and z the other (mv)
-  double wE = 0.5 * (mu[3] + mu[1] * mv[2] + mu[1] * x1);
-  double w2E = 0.5 * (mu[4] + mu[2] * mv[2] + mu[2] * x1);
-  double wzE = 0.5 * (mu[3] * mv[1] + mu[1] * mv[3] + mu[1] * mv[1] * x1);
-  double wE2 = 0.25 * (mu[5] + mu[1] * mv[4] + mu[1] * x2 + 2.0 * mu[3] * mv[2] +
-                       2.0 * mu[3] * x1 + 2.0 * mu[1] * mv[2] * x1);
+  R wE = 0.5 * (mu[3] + mu[1] * mv[2] + mu[1] * x1);
+  R w2E = 0.5 * (mu[4] + mu[2] * mv[2] + mu[2] * x1);
+  R wzE = 0.5 * (mu[3] * mv[1] + mu[1] * mv[3] + mu[1] * mv[1] * x1);
+  R wE2 = 0.25 * (mu[5] + mu[1] * mv[4] + mu[1] * x2 + 2.0 * mu[3] * mv[2] +
+                  2.0 * mu[3] * x1 + 2.0 * mu[1] * mv[2] * x1);
   // coefficient along the chosen axis and along the other
-  double aw = (dir == 0) ? a[1] : a[2];
-  double az = (dir == 0) ? a[2] : a[1];
-  double o0 = a[0] * mu[1] + aw * mu[2] + az * mu[1] * mv[1] + a[3] * wE;
-  double ow = a[0] * mu[2] + aw * mu[3] + az * mu[2] * mv[1] + a[3] * w2E;
-  double oz = a[0] * mu[1] * mv[1] + aw * mu[2] * mv[1] + az * mu[1] * mv[2] + a[3] * wzE;
-  double oE = a[0] * wE + aw * w2E + az * wzE + a[3] * wE2;
+  R aw = (dir == 0) ? a[1] : a[2];
+  R az = (dir == 0) ? a[2] : a[1];
+  R o0 = a[0] * mu[1] + aw * mu[2] + az * mu[1] * mv[1] + a[3] * wE;
+  R ow = a[0] * mu[2] + aw * mu[3] + az * mu[2] * mv[1] + a[3] * w2E;
+  R oz = a[0] * mu[1] * mv[1] + aw * mu[2] * mv[1] + az * mu[1] * mv[2] + a[3] * wzE;
+  R oE = a[0] * wE + aw * w2E + az * wzE + a[3] * wE2;
   out[0] = o0;
   out[1] = (dir == 0) ? ow : oz;
   out[2] = (dir == 0) ? oz : ow;
@@ -234,15 +238,15 @@ __device__ inline void psi_v_apsi(int dim, int dir, double U, double V, double l
 // equilibrium expansion coefficients of a face state: slopes a_d from the
 // gradient dW[d][nw] and time coefficient A from the compatibility condition
 // with the relative velocity w = v - U_f
-__device__ inline void expansion(int dim, double rho, double U, double V, double lam, double ufx,
-                                 double ufy, const double* dW, double* ax, double* ay,
-                                 double* At) {
+template <class R>
+__device__ inline void expansion(int dim, R rho, R U, R V, R lam, R ufx, R ufy, const R* dW, R* ax, R* ay,
+                                 R* At) {
   int nw = dim + 2;
-  double d[4];
+  R d[4];
   for (int m = 0; m < nw; ++m) d[m] = dW[m] / rho;
   slope_inverse(dim, U, V, lam, d, ax);
-  double b[4] = {0, 0, 0, 0};
-  double t[4];
+  R b[4] = {0.0, 0.0, 0.0, 0.0};
+  R t[4];
   psi_v_apsi(dim, 0, U, V, lam, ax, t);
   for (int m = 0; m < nw; ++m) b[m] = -t[m] + ufx * d[m];
   if (dim == 2) {
@@ -251,10 +255,10 @@ __device__ inline void expansion(int dim, double rho, double U, double V, double
     psi_v_apsi(dim, 1, U, V, lam, ay, t);
     for (int m = 0; m < nw; ++m) b[m] += -t[m] + ufy * d[m];
   } else {
-    for (int m = 0; m < 4; ++m) ay[m] = 0.0;
+    for (int m = 0; m < 4; ++m) ay[m] = R(0.0);
   }
   slope_inverse(dim, U, V, lam, b, At);
-  if (dim == 1) { ax[3] = 0.0; At[3] = 0.0; }
+  if (dim == 1) { ax[3] = R(0.0); At[3] = R(0.0); }
 }
 
 // Workgroup barrier that orders LDS accesses only.  The LU-SGS sweeps hand

@@ -71,6 +71,11 @@ def lib():
         L.ugks_set_tuning.argtypes = [vp, i32, i32, i32]
         L.ugks_get_tuning.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.ugks_autotune.argtypes = [vp, d, i32, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), C.POINTER(d), vp]
+        L.ugks_set_wall_rt.argtypes = [vp, i32, i32, d]
+        L.ugks_last_flux.argtypes = [vp, vp, vp]
+        L.ugks_flux_adjoint.argtypes = [vp] + [vp] * 12 + [vp]
+        L.ugks_step_adjoint.argtypes = [vp, d] + [vp] * 22 + [vp]
+        L.ugks_begin_step_adjoint.argtypes = [vp, d, vp, vp, vp, vp, i32] + [vp] * 12 + [vp]
         _lib = L
     return _lib
 
@@ -80,7 +85,9 @@ def exported_symbols():
             "ugks_get_types", "ugks_set_overset", "overset_assemble", "ugks_get_overset", "ugks_maxwellian",
             "ugks_moments", "ugks_heatflux", "ugks_flux", "overset_interp", "ugks_begin_step", "ugks_step",
             "ugks_timesteps", "ugks_step_profile", "ugks_step_graph", "ugks_batch_create", "ugks_batch_step",
-            "ugks_batch_destroy", "ugks_set_tuning", "ugks_get_tuning", "ugks_autotune", "ugks_last_error"]
+            "ugks_batch_destroy", "ugks_set_tuning", "ugks_get_tuning", "ugks_autotune", "ugks_set_wall_rt",
+            "ugks_last_flux", "ugks_flux_adjoint", "ugks_step_adjoint", "ugks_begin_step_adjoint",
+            "ugks_last_error"]
 
 
 def _check(rc):
@@ -264,6 +271,63 @@ class Solver:
         _check(lib().ugks_autotune(self.ctx, float(dt), int(n_inner), _p(h), _p(b), _p(W), _p(Wn), _p(q),
                                    _p(Sh), _p(Sb), _p(Fn), ch, C.byref(ms), self._stream(stream)))
         return tuple(ch), ms.value
+
+    def set_wall_rt(self, blk, side, rtw):
+        """RT of the isothermal wall on one side of a block."""
+        _check(lib().ugks_set_wall_rt(self.ctx, int(blk), int(side), float(rtw)))
+
+    def last_flux(self, stream=None):
+        """Face macro flux [nface][nw] of the last flux evaluation."""
+        F = self.zeros_face(self.nw)
+        _check(lib().ugks_last_flux(self.ctx, _p(F), self._stream(stream)))
+        return F
+
+    # ------------------------------------------------ reverse mode (adjoint)
+    def _bar(self, t, shape):
+        if t is None:
+            return None
+        assert t.dtype == torch.float64 and tuple(t.shape) == shape, (t.dtype, t.shape, shape)
+        return t.contiguous()
+
+    def flux_adjoint(self, h, b, W, q, Dh_bar=None, Db_bar=None, F_bar=None, stream=None):
+        """Cotangents (h, b, W, q, face[nface][5]) of ugks_flux at dt_s."""
+        f, fw = (self.ncell, self.nv), (self.nface, self.nw)
+        Dh_bar, Db_bar, F_bar = self._bar(Dh_bar, f), self._bar(Db_bar, f), self._bar(F_bar, fw)
+        out = [torch.empty(f, dtype=torch.float64, device=self.device) for _ in range(2)]
+        out += [self.zeros_w(), self.zeros_q(), self.zeros_face(5)]
+        _check(lib().ugks_flux_adjoint(self.ctx, _p(h), _p(b), _p(W), _p(q), _p(Dh_bar), _p(Db_bar), _p(F_bar),
+                                       *[_p(t) for t in out], self._stream(stream)))
+        return tuple(out)
+
+    def step_adjoint(self, dt, h, b, W, Wn, q, Sh, Sb, Fn, h1_bar=None, b1_bar=None, W1_bar=None, q1_bar=None,
+                     F_bar=None, stream=None):
+        """Cotangents of one inner iteration at its inputs: returns
+        (h, b, W, Wn, q, Sh, Sb, Fn, face[nface][5]) bars."""
+        f, w, qq, fw = (self.ncell, self.nv), (self.ncell, self.nw), (self.ncell, self.dim), (self.nface, self.nw)
+        bars = [self._bar(h1_bar, f), self._bar(b1_bar, f), self._bar(W1_bar, w), self._bar(q1_bar, qq),
+                self._bar(F_bar, fw)]
+        out = [torch.empty(f, dtype=torch.float64, device=self.device) for _ in range(2)]
+        out += [self.zeros_w(), self.zeros_w(), self.zeros_q()]
+        out += [torch.empty(f, dtype=torch.float64, device=self.device) for _ in range(2)]
+        out += [self.zeros_face(self.nw), self.zeros_face(5)]
+        _check(lib().ugks_step_adjoint(self.ctx, float(dt), _p(h), _p(b), _p(W), _p(Wn), _p(q), _p(Sh), _p(Sb),
+                                       _p(Fn), *[_p(t) for t in bars], *[_p(t) for t in out],
+                                       self._stream(stream)))
+        return tuple(out)
+
+    def begin_step_adjoint(self, dt, h, b, W, q, h1_bar=None, b1_bar=None, W1_bar=None, q1_bar=None,
+                           Sh_bar=None, Sb_bar=None, Fn_bar=None, refill=False, stream=None):
+        """Cotangents of Steps 1-2 at their inputs: (h, b, W, q, face) bars."""
+        f, w, qq, fw = (self.ncell, self.nv), (self.ncell, self.nw), (self.ncell, self.dim), (self.nface, self.nw)
+        Sh_bar = torch.zeros(f, dtype=torch.float64, device=self.device) if Sh_bar is None else Sh_bar
+        Sb_bar = torch.zeros(f, dtype=torch.float64, device=self.device) if Sb_bar is None else Sb_bar
+        bars = [self._bar(h1_bar, f), self._bar(b1_bar, f), self._bar(W1_bar, w), self._bar(q1_bar, qq),
+                self._bar(Sh_bar, f), self._bar(Sb_bar, f), self._bar(Fn_bar, fw)]
+        out = [torch.empty(f, dtype=torch.float64, device=self.device) for _ in range(2)]
+        out += [self.zeros_w(), self.zeros_q(), self.zeros_face(5)]
+        _check(lib().ugks_begin_step_adjoint(self.ctx, float(dt), _p(h), _p(b), _p(W), _p(q), int(bool(refill)),
+                                             *[_p(t) for t in bars], *[_p(t) for t in out], self._stream(stream)))
+        return tuple(out)
 
     STAGES = ["interp", "gradW_wall", "face_eq", "face_fin", "flux", "flux_fin", "macro_lusgs", "cell_rec",
               "micro_rhs", "micro_sweep", "step7"]
