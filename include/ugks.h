@@ -295,6 +295,24 @@ int ugks_autotune(ugks_ctx* ctx, double dt, int32_t n_inner, const void* h, cons
  */
 int ugks_set_wall_rt(ugks_ctx* ctx, int32_t blk, int32_t side, double rtw);
 
+/*
+ * Rigid velocity (ux, uy) and angular velocity om of block `blk` at the
+ * current node positions (the prescribed body motion of Sec. 3): face grid
+ * velocities U_f and wall velocities are recomputed; node positions, dt_s and
+ * the virtual steps dt' stay those of the last ugks_set_poses.  Synchronous.
+ */
+int ugks_set_block_velocity(ugks_ctx* ctx, int32_t blk, double ux, double uy, double om);
+
+/* Host copy of the face data [nface][8]: unit normal (x, y; from the low to
+   the high cell of the face), area, grid velocity (x, y), wall velocity
+   (x, y) and wall RT (wall faces; zero elsewhere). */
+int ugks_face_geometry(const ugks_ctx* ctx, double* fgeo);
+
+/* Rows of the installed donor table: receptors, rows of the cells uncovered
+   from holes by the last overset_assemble, and whether those are still to be
+   filled by the next ugks_begin_step (1) or not (0). */
+int ugks_overset_rows(const ugks_ctx* ctx, int32_t* nrec, int32_t* nrefill, int32_t* pending);
+
 /* Device copy of the face macro flux F [nface][dim+2] of the last flux
    evaluation (Step 3 of the last pseudo-iteration run by ugks_step,
    ugks_step_graph or ugks_step_adjoint's recomputation, or ugks_flux). */

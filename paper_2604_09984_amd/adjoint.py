@@ -1,0 +1,288 @@
+"""Differentiable dual-time stepping: torch.autograd.Function wrappers of the
+library's hand-written adjoint (reverse mode of Sec. 2.2's Steps 1-2 and of
+the inner iteration, Steps 3-7) and checkpointed recomputation across
+dual-time steps.
+
+Argument marshalling only: every forward and reverse pass runs in the HIP
+library (ugks_begin_step, ugks_step, ugks_begin_step_adjoint,
+ugks_step_adjoint).  Differentiable inputs are the state (h, b, W, q), the
+dual-time inputs of an inner iteration (Wn, Sh, Sb, Fn) and two sets of
+parameters of the prescribed motion and boundaries:
+
+  U    [nblock][2]  rigid velocity of each block (the face grid velocity and
+                    wall velocity of its faces; node positions, dt_s and dt'
+                    are those of the block's pose and are not differentiated),
+  rtw  [nblock][4]  RT of the isothermal wall on each side of each block
+                    (entries of sides that are not walls are ignored).
+
+U and rtw are float64 tensors on any device; their gradients come back on the
+same device.  Objectives are functions of the returned states and of F, the
+face macro flux of the last inner iteration (wall force and heat flux:
+wall_weights()).
+
+Checkpointing: physical_step() stores only its inputs; its backward re-runs
+the step's forward (Steps 1-2 and the n_inner inner iterations, keeping the
+inner states) and then the reverse passes.  A `setup` callable restores the
+step's geometry (poses, overset assembly) before the forward and before the
+recomputation, so moving-mesh runs are differentiated step by step.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import ugks
+
+
+# --------------------------------------------------------------------------
+# face bookkeeping (product face numbering of include/ugks.h)
+# --------------------------------------------------------------------------
+def face_blocks(case):
+    """Block and boundary side (-1: none) of every face."""
+    blk, side = [], []
+    for b, B in enumerate(case.blocks):
+        ni, nj = B.ni, B.nj
+        if case.dim == 1:
+            for i in range(ni + 1):
+                blk.append(b)
+                side.append(0 if i == 0 else (1 if i == ni else -1))
+            continue
+        for j in range(nj):
+            for i in range(ni + 1):
+                blk.append(b)
+                side.append(0 if i == 0 else (1 if i == ni else -1))
+        for j in range(nj + 1):
+            for i in range(ni):
+                blk.append(b)
+                side.append(2 if j == 0 else (3 if j == nj else -1))
+    return np.asarray(blk, np.int64), np.asarray(side, np.int64)
+
+
+def wall_weights(solver, blk, sides=(0, 1, 2, 3)):
+    """Weights w [nface] with sum_f w_f F[f, m] = the flux of component m into
+    the walls of block `blk` on `sides` (area times +-1 for the orientation of
+    the face normal): m = 1, 2 give the force on the body, m = dim+1 the
+    energy flux into it."""
+    fb, fs = face_blocks(solver.case)
+    g = solver.face_geometry()
+    B = solver.case.blocks[blk]
+    w = np.zeros(solver.nface)
+    for s in sides:
+        if B.bc[s] != 3:  # not a wall
+            continue
+        sel = (fb == blk) & (fs == s)
+        sgn = 1.0 if s in (1, 3) else -1.0  # normal points into the wall on high sides
+        w[sel] = sgn * g[sel, 2]
+    return torch.tensor(w, dtype=torch.float64, device=solver.device)
+
+
+class _Faces:
+    def __init__(self, solver):
+        b, s = face_blocks(solver.case)
+        self.blk = torch.tensor(b, device=solver.device)
+        self.side = torch.tensor(s, device=solver.device)
+        self.nblock = len(solver.case.blocks)
+
+    def param_grads(self, face_bar):
+        """Block velocity and wall-RT gradients from per-face bars."""
+        gU = torch.zeros((self.nblock, 2), dtype=torch.float64, device=face_bar.device)
+        gU.index_add_(0, self.blk, torch.stack([face_bar[:, 0] + face_bar[:, 2], face_bar[:, 1] + face_bar[:, 3]], 1))
+        gR = torch.zeros((self.nblock * 4,), dtype=torch.float64, device=face_bar.device)
+        ok = self.side >= 0
+        gR.index_add_(0, (self.blk * 4 + self.side)[ok], face_bar[ok, 4])
+        return gU, gR.reshape(self.nblock, 4)
+
+
+def _faces(solver):
+    f = getattr(solver, "_adj_faces", None)
+    if f is None:
+        f = solver._adj_faces = _Faces(solver)
+    return f
+
+
+def apply_params(solver, U, rtw):
+    """Set the block velocities and wall temperatures (angular velocities from
+    the current poses are kept; dt_s and dt' stay fixed)."""
+    if U is not None:
+        Uh = U.detach().double().cpu().numpy()
+        poses = getattr(solver, "poses", None)
+        for b in range(len(solver.case.blocks)):
+            solver.set_block_velocity(b, Uh[b, 0], Uh[b, 1], 0.0 if poses is None else poses[b, 5])
+    if rtw is not None:
+        Rh = rtw.detach().double().cpu().numpy()
+        for b, B in enumerate(solver.case.blocks):
+            for s in range(4):
+                if B.bc[s] == 3:
+                    solver.set_wall_rt(b, s, Rh[b, s])
+
+
+def _out_grad(U, g):
+    return None if U is None else g.to(U.device, U.dtype)
+
+
+def _clone(*ts):
+    return [t.clone() for t in ts]
+
+
+# --------------------------------------------------------------------------
+# one inner iteration and Steps 1-2
+# --------------------------------------------------------------------------
+class PseudoStep(torch.autograd.Function):
+    """(h, b, W, q, Wn, Sh, Sb, Fn, U, rtw) -> (h', b', W', q', F): one inner
+    iteration (Steps 3-7); F is the face macro flux of its Step 3."""
+
+    @staticmethod
+    def forward(ctx, solver, dt, setup, h, b, W, q, Wn, Sh, Sb, Fn, U, rtw):
+        if setup is not None:
+            setup()
+        apply_params(solver, U, rtw)
+        h1, b1, W1, q1 = _clone(h, b, W, q)
+        solver.step(dt, 1, h1, b1, W1, Wn, q1, Sh, Sb, Fn)
+        F = solver.last_flux()
+        ctx.solver, ctx.dt, ctx.setup = solver, dt, setup
+        ctx.save_for_backward(h, b, W, q, Wn, Sh, Sb, Fn, U, rtw)
+        return h1, b1, W1, q1, F
+
+    @staticmethod
+    def backward(ctx, gh, gb, gW, gq, gF):
+        h, b, W, q, Wn, Sh, Sb, Fn, U, rtw = ctx.saved_tensors
+        s = ctx.solver
+        if ctx.setup is not None:
+            ctx.setup()
+        apply_params(s, U, rtw)
+        hb, bb, Wb, Wnb, qb, Shb, Sbb, Fnb, fb = s.step_adjoint(ctx.dt, h, b, W, Wn, q, Sh, Sb, Fn,
+                                                                 _c(gh), _c(gb), _c(gW), _c(gq), _c(gF))
+        gU, gR = _faces(s).param_grads(fb)
+        return None, None, None, hb, bb, Wb, qb, Wnb, Shb, Sbb, Fnb, _out_grad(U, gU), _out_grad(rtw, gR)
+
+
+class BeginStep(torch.autograd.Function):
+    """(h, b, W, q, U, rtw) -> (h', b', W', q', Sh, Sb, Fn): Steps 1-2 (the
+    primed state has its receptor rows, and once after an assembly the cells
+    uncovered from holes, interpolated)."""
+
+    @staticmethod
+    def forward(ctx, solver, dt, setup, h, b, W, q, U, rtw):
+        if setup is not None:
+            setup()
+        apply_params(solver, U, rtw)
+        ctx.refill = solver.overset_rows()[2] != 0
+        h1, b1, W1, q1 = _clone(h, b, W, q)
+        Sh, Sb, Fn = solver.begin_step(dt, h1, b1, W1, q1)
+        ctx.solver, ctx.dt, ctx.setup = solver, dt, setup
+        ctx.save_for_backward(h, b, W, q, U, rtw)
+        return h1, b1, W1, q1, Sh, Sb, Fn
+
+    @staticmethod
+    def backward(ctx, gh, gb, gW, gq, gSh, gSb, gFn):
+        h, b, W, q, U, rtw = ctx.saved_tensors
+        s = ctx.solver
+        if ctx.setup is not None:
+            ctx.setup()
+        apply_params(s, U, rtw)
+        hb, bb, Wb, qb, fb = s.begin_step_adjoint(ctx.dt, h, b, W, q, _c(gh), _c(gb), _c(gW), _c(gq), _c(gSh),
+                                                  _c(gSb), _c(gFn), refill=ctx.refill)
+        gU, gR = _faces(s).param_grads(fb)
+        return None, None, None, hb, bb, Wb, qb, _out_grad(U, gU), _out_grad(rtw, gR)
+
+
+def _c(t):
+    return None if t is None else t.contiguous()
+
+
+# --------------------------------------------------------------------------
+# one physical step, checkpointed
+# --------------------------------------------------------------------------
+class PhysicalStep(torch.autograd.Function):
+    """(h, b, W, q, U, rtw) -> (h', b', W', q', F): Steps 1-8 of one physical
+    step (Steps 1-2, then n_inner inner iterations); F is the face macro flux
+    of the last inner iteration.  Only the inputs are kept; the backward pass
+    recomputes the step."""
+
+    @staticmethod
+    def forward(ctx, solver, dt, n_inner, setup, h, b, W, q, U, rtw):
+        # the cell kinds before the step's setup decide which cells an
+        # overset assembly refills; the recomputation restores them
+        ctx.types0 = solver.types() if setup is not None else None
+        if setup is not None:
+            setup()
+        apply_params(solver, U, rtw)
+        ctx.refill = solver.overset_rows()[2] != 0
+        h1, b1, W1, q1 = _clone(h, b, W, q)
+        Wn = W1.clone()
+        Sh, Sb, Fn = solver.begin_step(dt, h1, b1, W1, q1)
+        solver.step(dt, n_inner, h1, b1, W1, Wn, q1, Sh, Sb, Fn)
+        F = solver.last_flux()
+        ctx.solver, ctx.dt, ctx.n_inner, ctx.setup = solver, dt, n_inner, setup
+        ctx.save_for_backward(h, b, W, q, U, rtw)
+        return h1, b1, W1, q1, F
+
+    @staticmethod
+    def backward(ctx, gh, gb, gW, gq, gF):
+        h, b, W, q, U, rtw = ctx.saved_tensors
+        s, dt = ctx.solver, ctx.dt
+        if ctx.setup is not None:
+            s.set_types(ctx.types0)
+            ctx.setup()
+        apply_params(s, U, rtw)
+        # recomputation: Steps 1-2, then the inner iterations, keeping their inputs
+        hs, bs, Ws, qs = _clone(h, b, W, q)
+        Wn = W.clone()
+        Sh, Sb, Fn = s.begin_step(dt, hs, bs, Ws, qs)
+        states = []
+        for _ in range(ctx.n_inner):
+            states.append(_clone(hs, bs, Ws, qs))
+            s.step(dt, 1, hs, bs, Ws, Wn, qs, Sh, Sb, Fn)
+        del hs, bs, Ws, qs
+        # reverse through the inner iterations
+        gh, gb, gW, gq = _c(gh), _c(gb), _c(gW), _c(gq)
+        gSh = torch.zeros_like(Sh); gSb = torch.zeros_like(Sb)
+        gFn = torch.zeros_like(Fn); gWn = torch.zeros_like(W)
+        faces = torch.zeros((s.nface, 5), dtype=torch.float64, device=h.device)
+        for it in range(ctx.n_inner - 1, -1, -1):
+            hi, bi, Wi, qi = states.pop()
+            out = s.step_adjoint(dt, hi, bi, Wi, Wn, qi, Sh, Sb, Fn, gh, gb, gW, gq,
+                                 _c(gF) if it == ctx.n_inner - 1 else None)
+            gh, gb, gW, gWn_i, gq, gSh_i, gSb_i, gFn_i, fb = out
+            gWn += gWn_i; gSh += gSh_i; gSb += gSb_i; gFn += gFn_i; faces += fb
+        # Steps 1-2 (Wn is the input W)
+        hb, bb, Wb, qb, fb = s.begin_step_adjoint(dt, h, b, W, q, gh, gb, gW, gq, gSh, gSb, gFn,
+                                                  refill=ctx.refill)
+        faces += fb
+        Wb = Wb + gWn
+        gU, gR = _faces(s).param_grads(faces)
+        return None, None, None, None, hb, bb, Wb, qb, _out_grad(U, gU), _out_grad(rtw, gR)
+
+
+def physical_step(solver, dt, n_inner, h, b, W, q, U=None, rtw=None, setup=None, checkpoint=True):
+    """One differentiable physical step; returns (h', b', W', q', F).  With
+    checkpoint=False the step is composed of BeginStep and PseudoStep nodes
+    whose inputs autograd keeps (n_inner states of f; fixed geometry)."""
+    if checkpoint:
+        return PhysicalStep.apply(solver, dt, n_inner, setup, h, b, W, q, U, rtw)
+    if setup is not None:
+        raise ValueError("checkpoint=False keeps every node of the step for one geometry: no setup")
+    Wn = W
+    h, b, W, q, Sh, Sb, Fn = BeginStep.apply(solver, dt, setup, h, b, W, q, U, rtw)
+    F = None
+    for _ in range(n_inner):
+        h, b, W, q, F = PseudoStep.apply(solver, dt, setup, h, b, W, q, Wn, Sh, Sb, Fn, U, rtw)
+    return h, b, W, q, F
+
+
+def default_params(solver):
+    """U and rtw tensors holding the block velocities of the solver's current
+    poses (zero before any set_poses) and the case's wall temperatures (1 on
+    sides that are not walls)."""
+    case = solver.case
+    nb = len(case.blocks)
+    U = torch.zeros((nb, 2), dtype=torch.float64)
+    poses = getattr(solver, "poses", None)
+    if poses is not None:
+        U[:] = torch.tensor(poses[:, 3:5])
+    R = torch.ones((nb, 4), dtype=torch.float64)
+    for bi, B in enumerate(case.blocks):
+        for s in range(4):
+            if B.bc[s] == 3:
+                R[bi, s] = float(B.rtw[s])
+    return U, R

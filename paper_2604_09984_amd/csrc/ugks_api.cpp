@@ -681,14 +681,49 @@ int ugks_set_poses(ugks_ctx* c, const double* poses, double* dts) {
   return UGKS_OK;
 }
 
+// face data recomputed after a change of block velocities or wall
+// temperatures, keeping the time steps dt_s and dt' of the last pose
+static int refresh_frozen_steps(ugks_ctx* c) {
+  const double dts = c->dts;
+  const std::vector<double> dtp = c->dtp;
+  compute_geometry(c);
+  c->dts = dts;
+  c->dtp = dtp;
+  return upload_geometry(c);
+}
+
 int ugks_set_wall_rt(ugks_ctx* c, int32_t blk, int32_t side, double rtw) {
   if (!c) return fail(UGKS_E_ARG, "null context");
   if (blk < 0 || blk >= (int)c->blk.size() || side < 0 || side > 3) return fail(UGKS_E_ARG, "bad block side");
   if (!(rtw > 0.0) || !std::isfinite(rtw)) return fail(UGKS_E_ARG, "wall RT must be positive");
   ++c->version;
   c->blk[blk].rtw[side] = rtw;
-  compute_geometry(c);
-  return upload_geometry(c);
+  return refresh_frozen_steps(c);
+}
+
+int ugks_set_block_velocity(ugks_ctx* c, int32_t blk, double ux, double uy, double om) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  if (blk < 0 || blk >= (int)c->blk.size()) return fail(UGKS_E_ARG, "bad block");
+  if (!std::isfinite(ux) || !std::isfinite(uy) || !std::isfinite(om)) return fail(UGKS_E_ARG, "non-finite velocity");
+  ++c->version;
+  c->blk[blk].pose[3] = ux;
+  c->blk[blk].pose[4] = uy;
+  c->blk[blk].pose[5] = om;
+  return refresh_frozen_steps(c);
+}
+
+int ugks_face_geometry(const ugks_ctx* c, double* fgeo) {
+  if (!c || !fgeo) return fail(UGKS_E_ARG, "null argument");
+  std::memcpy(fgeo, c->fgeo.data(), sizeof(double) * 8 * (size_t)c->nface);
+  return UGKS_OK;
+}
+
+int ugks_overset_rows(const ugks_ctx* c, int32_t* nrec, int32_t* nrefill, int32_t* pending) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  if (nrec) *nrec = c->nrec;
+  if (nrefill) *nrefill = (int32_t)c->h_rec.size() - c->nrec;
+  if (pending) *pending = c->nref;
+  return UGKS_OK;
 }
 
 int ugks_last_flux(const ugks_ctx* c, double* F, void* stream) {

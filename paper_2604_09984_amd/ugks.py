@@ -72,6 +72,9 @@ def lib():
         L.ugks_get_tuning.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.ugks_autotune.argtypes = [vp, d, i32, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), C.POINTER(d), vp]
         L.ugks_set_wall_rt.argtypes = [vp, i32, i32, d]
+        L.ugks_set_block_velocity.argtypes = [vp, i32, d, d, d]
+        L.ugks_face_geometry.argtypes = [vp, C.POINTER(d)]
+        L.ugks_overset_rows.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.ugks_last_flux.argtypes = [vp, vp, vp]
         L.ugks_flux_adjoint.argtypes = [vp] + [vp] * 12 + [vp]
         L.ugks_step_adjoint.argtypes = [vp, d] + [vp] * 22 + [vp]
@@ -86,7 +89,8 @@ def exported_symbols():
             "ugks_moments", "ugks_heatflux", "ugks_flux", "overset_interp", "ugks_begin_step", "ugks_step",
             "ugks_timesteps", "ugks_step_profile", "ugks_step_graph", "ugks_batch_create", "ugks_batch_step",
             "ugks_batch_destroy", "ugks_set_tuning", "ugks_get_tuning", "ugks_autotune", "ugks_set_wall_rt",
-            "ugks_last_flux", "ugks_flux_adjoint", "ugks_step_adjoint", "ugks_begin_step_adjoint",
+            "ugks_last_flux", "ugks_set_block_velocity", "ugks_face_geometry", "ugks_overset_rows",
+            "ugks_flux_adjoint", "ugks_step_adjoint", "ugks_begin_step_adjoint",
             "ugks_last_error"]
 
 
@@ -160,6 +164,7 @@ class Solver:
         a = np.ascontiguousarray(np.asarray(poses, dtype=np.float64).reshape(-1, 6))
         dts = C.c_double()
         _check(lib().ugks_set_poses(self.ctx, _dp(a), C.byref(dts)))
+        self.poses = a.copy()
         return dts.value
 
     def timesteps(self):
@@ -275,6 +280,23 @@ class Solver:
     def set_wall_rt(self, blk, side, rtw):
         """RT of the isothermal wall on one side of a block."""
         _check(lib().ugks_set_wall_rt(self.ctx, int(blk), int(side), float(rtw)))
+
+    def set_block_velocity(self, blk, ux, uy, om=0.0):
+        """Rigid velocity of a block; geometry, dt_s and dt' stay fixed."""
+        _check(lib().ugks_set_block_velocity(self.ctx, int(blk), float(ux), float(uy), float(om)))
+
+    def face_geometry(self):
+        """Host [nface][8]: normal (2), area, grid velocity (2), wall velocity
+        (2), wall RT."""
+        g = np.zeros((self.nface, 8))
+        _check(lib().ugks_face_geometry(self.ctx, _dp(g)))
+        return g
+
+    def overset_rows(self):
+        """(receptor rows, refill rows, refills pending) of the donor table."""
+        v = [C.c_int32() for _ in range(3)]
+        _check(lib().ugks_overset_rows(self.ctx, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def last_flux(self, stream=None):
         """Face macro flux [nface][nw] of the last flux evaluation."""
