@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle pseudo-iterations (0: skip)")
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--nvx", type=int, default=64)
+    ap.add_argument("--adjoint-calls", type=int, default=3,
+                    help="timed reverse passes of one pseudo-iteration (FP64; 0: skip)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of GIB GiB (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -67,7 +69,7 @@ def traffic_from_profiles(kernel, prec):
         return None
 
 
-def run_gpu(case, prec_name, steps, warmup):
+def run_gpu(case, prec_name, steps, warmup, adjoint_calls=0):
     import torch
     from paper_2604_09984_amd import ugks
     prec = ugks.F64 if prec_name == "f64" else ugks.F32
@@ -101,10 +103,24 @@ def run_gpu(case, prec_name, steps, warmup):
     # per-kernel timing: HIP events on the library's stream, separate run
     prof = s.step_profile(dt, chunk, h, b, W, Wn, q, Sh, Sb, Fn)
     torch.cuda.synchronize()
+    adj_ms = None
+    if adjoint_calls > 0 and prec == ugks.F64:
+        # reverse pass of one pseudo-iteration at the current state with random
+        # cotangents (one call = the iteration's forward recomputation plus the
+        # reverse kernels); the first call allocates the workspace
+        gen = torch.Generator(device=h.device).manual_seed(1)
+        ys = [torch.randn(t.shape, dtype=torch.float64, device=h.device, generator=gen) for t in (h, b, W, q)]
+        s.step_adjoint(dt, h, b, W, Wn, q, Sh, Sb, Fn, *ys)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(adjoint_calls):
+            s.step_adjoint(dt, h, b, W, Wn, q, Sh, Sb, Fn, *ys)
+        torch.cuda.synchronize()
+        adj_ms = 1e3 * (time.perf_counter() - t2) / adjoint_calls
     pairs = int((s.types() == 1).sum()) * s.nv
     out = dict(prec=prec_name, pairs=pairs, wall_s=wall_s, eager_ms=eager_ms, steps=steps, stages=prof,
                tuning=dict(zip(("kc_max", "rg_eq", "rg_flux"), tuning)),
-               finite=bool(torch.isfinite(h).all().item() and torch.isfinite(W).all().item()))
+               finite=bool(torch.isfinite(h).all().item() and torch.isfinite(W).all().item()), adjoint_ms=adj_ms)
     out["h"] = h.to(torch.float64).cpu()
     s.close()
     return out
@@ -179,7 +195,7 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     case = wl.cylinder(nvx=args.nvx)
-    r64 = run_gpu(case, "f64", args.steps, args.warmup)
+    r64 = run_gpu(case, "f64", args.steps, args.warmup, adjoint_calls=args.adjoint_calls)
     r32 = None if args.no_f32 else run_gpu(case, "f32", args.steps, args.warmup)
     ms64 = 1e3 * r64["wall_s"] / args.steps
     value = r64["pairs"] * args.steps / r64["wall_s"]
@@ -224,6 +240,12 @@ def main():
                        "roofline": roofline(r32["stages"], r32["pairs"], "f32", r32["tuning"]),
                        "launch_shapes": r32["tuning"],
                        "stages_ms": {k: round(v, 4) for k, v in r32["stages"].items()}}
+    if r64["adjoint_ms"] is not None:
+        line["adjoint_f64"] = {"ms_per_pseudo_step": round(r64["adjoint_ms"], 3),
+                               "ratio_to_forward_eager": round(r64["adjoint_ms"] / r64["eager_ms"], 2),
+                               "what": "ugks_step_adjoint: recomputation of one pseudo-iteration and its "
+                                       "reverse pass (vector-Jacobian product w.r.t. f, W, q, S, Fn, block "
+                                       "velocity and wall temperature)"}
     line["finite"] = r64["finite"] and (r32 is None or r32["finite"])
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
