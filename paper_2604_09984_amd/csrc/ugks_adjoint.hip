@@ -26,6 +26,11 @@
 
 namespace ugks {
 
+// The reverse-mode entry points accept 2D cases only (checked on the host);
+// compile-time sizes keep the small per-face and per-cell arrays in registers.
+constexpr int kD = 2, kNxi = 1, kNw = 4;
+
+
 // ------------------------------------------------------------------------
 // forward-mode scalar (value and one directional derivative)
 // ------------------------------------------------------------------------
@@ -108,7 +113,7 @@ __device__ inline void itau_partials(const Dev& g, double rho, double lam, doubl
 // a[0..5] = (rho, ux, uy, lam, qx, qy) bars.
 __device__ inline void eq_rev(const Dev& g, double rho, double ux, double uy, double lam, double qx, double qy,
                               double vx, double vy, double Hb, double Bb, double Hpb, double Bpb, double* a) {
-  const int D = g.dim, nxi = g.nxi;
+  const int D = kD, nxi = kNxi;
   double cx = vx - ux, cy = (D == 2) ? vy - uy : 0.0;
   double c2 = cx * cx + cy * cy;
   double H = rho * pow(lam / kPi, 0.5 * D) * exp(-lam * c2);
@@ -163,7 +168,7 @@ __device__ inline void heat_rev_k(int D, double w, double vx, double vy, double 
 constexpr int kRecIn = 14, kRecOut = 17;
 template <class R>
 __device__ inline void face_coeffs(const Dev& g, double dts, const R* x, R* o) {
-  expansion(g.dim, x[0], x[1], x[2], x[3], x[12], x[13], x + 4, o, o + 4, o + 8);
+  expansion(kD, x[0], x[1], x[2], x[3], x[12], x[13], x + 4, o, o + 4, o + 8);
   time_integrals(dts, inv_tau_of(g, x[0], x[3]), o + 12);
 }
 
@@ -190,11 +195,12 @@ constexpr int kRecBar = 25;
 // integral over [0, dt_s] of the interface distribution) and its reverse
 // for the cotangents Ihb, Ibb.  Per-velocity bars of the side data are
 // returned; record bars are accumulated into acc[kRecBar].
-__device__ inline void iint_rev(const Dev& g, const Rec& e, double vx, double vy, double wx, double wy, double fh,
-                                double fb, double ghx, double ghy, double gbx, double gby, double Ihb, double Ibb,
-                                double& fhb, double& fbb, double* ghb, double* gbb, double* acc, double& Ih,
-                                double& Ib) {
-  const int D = g.dim, nxi = g.nxi, E = D + 1;
+template <bool ACC>
+__device__ __forceinline__ void iint_rev(const Dev& g, const Rec& e, double vx, double vy, double wx, double wy,
+                                         double fh, double fb, double ghx, double ghy, double gbx, double gby,
+                                         double Ihb, double Ibb, double& fhb, double& fbb, double* ghb, double* gbb,
+                                         double* acc, double& Ih, double& Ib) {
+  const int D = kD, nxi = kNxi, E = D + 1;
   const double* ax = e.c;
   const double* ay = e.c + 4;
   const double* At = e.c + 8;
@@ -223,6 +229,7 @@ __device__ inline void iint_rev(const Dev& g, const Rec& e, double vx, double vy
   fbb = t[0] * Ibb;
   ghb[0] = t[1] * Ihb * wx; ghb[1] = t[1] * Ihb * wy;
   gbb[0] = t[1] * Ibb * wx; gbb[1] = t[1] * Ibb * wy;
+  if constexpr (!ACC) return;
   double* tb = acc + 6 + 12;
   tb[0] += fh * Ihb + fb * Ibb;
   tb[1] += wgh * Ihb + wgb * Ibb;
@@ -305,13 +312,13 @@ __device__ inline SideK side_val(const Dev& g, const double* f, const double* fi
   double si = lim_d(nb[0], nb[1], nbval(f, finf, nb[0], v0, g.nv, k), v0, nbval(f, finf, nb[1], v0, g.nv, k), dl,
                     d0, dh);
   double sj = 0.0;
-  if (g.dim == 2)
+  if (kD == 2)
     sj = lim_d(nb[2], nb[3], nbval(f, finf, nb[2], v0, g.nv, k), v0, nbval(f, finf, nb[3], v0, g.nv, k), dl, d0,
                dh);
   const double* G = g.G + 4 * c;
   SideK s;
   s.gx = G[0] * si + G[1] * sj;
-  s.gy = (g.dim == 2) ? G[2] * si + G[3] * sj : 0.0;
+  s.gy = (kD == 2) ? G[2] * si + G[3] * sj : 0.0;
   s.v = v0 + s.gx * dx + s.gy * dy;
   return s;
 }
@@ -329,10 +336,10 @@ __device__ inline void side_rev(const Dev& g, const double* f, const double* fin
   double v0 = f[(size_t)c * g.nv + k];
   gxb += vb * dx;
   gyb += vb * dy;
-  double sib = G[0] * gxb + ((g.dim == 2) ? G[2] * gyb : 0.0);
-  double sjb = (g.dim == 2) ? G[1] * gxb + G[3] * gyb : 0.0;
+  double sib = G[0] * gxb + ((kD == 2) ? G[2] * gyb : 0.0);
+  double sjb = (kD == 2) ? G[1] * gxb + G[3] * gyb : 0.0;
   double own = vb;
-  for (int dir = 0; dir < g.dim; ++dir) {
+  for (int dir = 0; dir < kD; ++dir) {
     double sb = dir ? sjb : sib;
     int lo = nb[2 * dir], hi = nb[2 * dir + 1];
     double dl, d0, dh;
@@ -371,6 +378,59 @@ __device__ inline void side_any_rev(const Dev& g, const double* f, const double*
   else if (code == kNbCopy) atomic_add(fbar + (size_t)inner * g.nv + k, vb);
 }
 
+// reconstruction with the partials of its two limited index slopes kept,
+// for a reverse pass right after the forward evaluation
+struct SideD {
+  double v, gx, gy;
+  double p[2][3];  // d slope / d (low, centre, high value) per index direction
+};
+
+__device__ __forceinline__ SideD side_val_d(const Dev& g, const double* f, const double* finf, int code, int inner,
+                                            double dx, double dy, int k) {
+  SideD s;
+  for (int d = 0; d < 2; ++d) s.p[d][0] = s.p[d][1] = s.p[d][2] = 0.0;
+  if (code < 0) {
+    s.gx = s.gy = 0.0;
+    s.v = (code == kNbFar) ? finf[k] : f[(size_t)inner * g.nv + k];
+    return s;
+  }
+  const int* nb = g.nb + 4 * code;
+  const double v0 = f[(size_t)code * g.nv + k];
+  const double si = lim_d(nb[0], nb[1], nbval(f, finf, nb[0], v0, g.nv, k), v0, nbval(f, finf, nb[1], v0, g.nv, k),
+                          s.p[0][0], s.p[0][1], s.p[0][2]);
+  const double sj = lim_d(nb[2], nb[3], nbval(f, finf, nb[2], v0, g.nv, k), v0, nbval(f, finf, nb[3], v0, g.nv, k),
+                          s.p[1][0], s.p[1][1], s.p[1][2]);
+  const double* G = g.G + 4 * code;
+  s.gx = G[0] * si + G[1] * sj;
+  s.gy = G[2] * si + G[3] * sj;
+  s.v = v0 + s.gx * dx + s.gy * dy;
+  return s;
+}
+
+__device__ __forceinline__ void side_rev_d(const Dev& g, const SideD& s, int code, int inner, double dx, double dy,
+                                           int k, double vb, double gxb, double gyb, double* fbar) {
+  if (code < 0) {
+    if (code == kNbCopy) atomic_add(fbar + (size_t)inner * g.nv + k, vb);
+    return;
+  }
+  const int* nb = g.nb + 4 * code;
+  const double* G = g.G + 4 * code;
+  gxb += vb * dx;
+  gyb += vb * dy;
+  const double sb[2] = {G[0] * gxb + G[2] * gyb, G[1] * gxb + G[3] * gyb};
+  double own = vb;
+  for (int d = 0; d < 2; ++d) {
+    own += sb[d] * s.p[d][1];
+    const int lo = nb[2 * d], hi = nb[2 * d + 1];
+    const double a = sb[d] * s.p[d][0], c = sb[d] * s.p[d][2];
+    if (lo >= 0) atomic_add(fbar + (size_t)lo * g.nv + k, a);
+    else if (lo == kNbCopy) own += a;
+    if (hi >= 0) atomic_add(fbar + (size_t)hi * g.nv + k, c);
+    else if (hi == kNbCopy) own += c;
+  }
+  atomic_add(fbar + (size_t)code * g.nv + k, own);
+}
+
 // cotangent of the flux F_k (along the face normal) of face f from the
 // divergence bars of its field cells and the face macro-flux bar
 __device__ inline void flux_bar_k(const Dev& g, const double* fp, const double* Dbh, const double* Dbb,
@@ -378,8 +438,8 @@ __device__ inline void flux_bar_k(const Dev& g, const double* fp, const double* 
   int L = (int)fp[kFpL], R = (int)fp[kFpR];
   double S = fp[kFpS];
   double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
-  Fhb = w * (Fbf[0] + Fbf[1] * vx + ((g.dim == 2) ? Fbf[2] * vy : 0.0) + Fbf[g.dim + 1] * 0.5 * (vx * vx + vy * vy));
-  Fbb = w * 0.5 * Fbf[g.dim + 1];
+  Fhb = w * (Fbf[0] + Fbf[1] * vx + ((kD == 2) ? Fbf[2] * vy : 0.0) + Fbf[kD + 1] * 0.5 * (vx * vx + vy * vy));
+  Fbb = w * 0.5 * Fbf[kD + 1];
   if (L >= 0 && g.type[L] == 1) {
     double a = -S / g.vol[L];
     Fhb += a * Dbh[(size_t)L * g.nv + k];
@@ -394,22 +454,39 @@ __device__ inline void flux_bar_k(const Dev& g, const double* fp, const double* 
 
 // ------------------------------------------------------------------------
 // flux reverse, faces between cells (interior and ghost faces): one
-// wavefront per face, lanes over velocities
+// wavefront per face, lanes over velocities.  The face record lives in LDS
+// (every lane writes the same values and reads back its own writes).
+// Pass 1: W0; pass 2: q0 and the sums of its U-derivative; pass 3: the flux
+// reversed per velocity (its bars of the upwind data scattered at once) with
+// the record bars accumulated; the record Jacobian, one input per lane;
+// pass 4: the moment bars (W0, q0) scattered to both sides.
 // ------------------------------------------------------------------------
+__device__ __forceinline__ void store_rec(Rec& e, double rho, double ux, double uy, double lam, double qx, double qy,
+                                          const double* c) {
+  e.rho = rho; e.ux = ux; e.uy = uy; e.lam = lam; e.qx = qx; e.qy = qy;
+  for (int i = 0; i < kRecOut; ++i) e.c[i] = c[i];
+}
+
+__device__ __forceinline__ void rec_values(const Dev& g, double dts, const double* x, double* c) {
+  face_coeffs(g, dts, x, c);
+}
+
 __global__ __launch_bounds__(256) void k_adj_face(Dev g, double dts, const double* __restrict__ h,
                                                   const double* __restrict__ b, const double* __restrict__ gW,
                                                   const double* __restrict__ Dbh, const double* __restrict__ Dbb,
                                                   const double* __restrict__ Fb, double* __restrict__ hbar,
                                                   double* __restrict__ bbar, double* __restrict__ gWbar,
                                                   double* __restrict__ fbar) {
+  __shared__ Rec srec[4];
   const int f = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (f >= g.nface) return;
+  Rec& e = srec[threadIdx.x >> 6];
   const double* fp = g.fplan + (size_t)f * kFpN;
   if (fp[kFpAct] == 0.0) return;
   const int L = (int)fp[kFpL], R = (int)fp[kFpR];
   if (L == kNbWall || R == kNbWall) return;
-  const int D = g.dim, nw = g.nw, nv = g.nv;
+  const int D = kD, nv = g.nv;
   const double nx = fp[kFpN0], ny = fp[kFpN0 + 1], ufx = fp[kFpU], ufy = fp[kFpU + 1];
   const double* hinf = (const double*)g.finf_h;
   const double* binf = (const double*)g.finf_b;
@@ -417,88 +494,111 @@ __global__ __launch_bounds__(256) void k_adj_face(Dev g, double dts, const doubl
   double dLx, dLy, dRx, dRy;
   face_side(g, fp, 0, cL, inner, dLx, dLy);
   face_side(g, fp, 1, cR, inner, dRx, dRy);
+  // upwind interface data (the mean of both sides on a tie); the side is
+  // chosen per lane, so the wavefront runs one reconstruction per component
   auto upwind = [&](int k, double wn, double& fh, double& fb) {
-    SideK hl = side_any(g, h, hinf, cL, inner, dLx, dLy, k), hr = side_any(g, h, hinf, cR, inner, dRx, dRy, k);
-    SideK bl = side_any(g, b, binf, cL, inner, dLx, dLy, k), br = side_any(g, b, binf, cR, inner, dRx, dRy, k);
-    if (wn > 0.0) { fh = hl.v; fb = bl.v; }
-    else if (wn < 0.0) { fh = hr.v; fb = br.v; }
-    else { fh = 0.5 * (hl.v + hr.v); fb = 0.5 * (bl.v + br.v); }
+    const bool lft = wn > 0.0;
+    const int up = lft ? cL : cR;
+    const double ox = lft ? dLx : dRx, oy = lft ? dLy : dRy;
+    fh = side_any(g, h, hinf, up, inner, ox, oy, k).v;
+    fb = side_any(g, b, binf, up, inner, ox, oy, k).v;
+    if (wn == 0.0) {
+      fh = 0.5 * (fh + side_any(g, h, hinf, cL, inner, dLx, dLy, k).v);
+      fb = 0.5 * (fb + side_any(g, b, binf, cL, inner, dLx, dLy, k).v);
+    }
   };
-  // pass 1: W0 from the upwind interface data
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  for (int k = lane; k < nv; k += 64) {
-    double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
-    double fh, fb;
-    upwind(k, wn_exact(vx, vy, ufx, ufy, nx, ny), fh, fb);
-    s0 += w * fh; s1 += w * vx * fh; s2 += w * vy * fh; s3 += w * 0.5 * ((vx * vx + vy * vy) * fh + fb);
+  auto grad_in = [&](double* x) {
+    for (int m = 0; m < 8; ++m) {
+      double gl = (L >= 0) ? gW[(size_t)L * 8 + m] : 0.0;
+      double gr = (R >= 0) ? gW[(size_t)R * 8 + m] : 0.0;
+      x[4 + m] = 0.5 * (gl + gr);
+    }
+    x[12] = ufx; x[13] = ufy;
+  };
+  double W0[4] = {0, 0, 0, 0};
+  double T1, Txx, Tyy, Txy;
+  {
+    // pass 1: W0 from the upwind interface data
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int k = lane; k < nv; k += 64) {
+      double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
+      double fh, fb;
+      upwind(k, wn_exact(vx, vy, ufx, ufy, nx, ny), fh, fb);
+      s0 += w * fh; s1 += w * vx * fh; s2 += w * vy * fh; s3 += w * 0.5 * ((vx * vx + vy * vy) * fh + fb);
+    }
+    W0[0] = wave_sum(s0); W0[1] = wave_sum(s1);
+    if (D == 2) { W0[2] = wave_sum(s2); W0[3] = wave_sum(s3); }
+    else W0[2] = wave_sum(s3);
+    double rho, ux, uy, lam;
+    prim_d(D, kNxi, W0, rho, ux, uy, lam);
+    // pass 2: heat flux q0 and the sums of its derivative along U
+    double q0x = 0, q0y = 0;
+    T1 = Txx = Tyy = Txy = 0.0;
+    for (int k = lane; k < nv; k += 64) {
+      double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
+      double fh, fb;
+      upwind(k, wn_exact(vx, vy, ufx, ufy, nx, ny), fh, fb);
+      double cx = vx - ux, cy = (D == 2) ? vy - uy : 0.0;
+      double en = (cx * cx + cy * cy) * fh + fb;
+      q0x += w * 0.5 * cx * en; q0y += w * 0.5 * cy * en;
+      T1 += w * en; Txx += w * cx * cx * fh; Tyy += w * cy * cy * fh; Txy += w * cx * cy * fh;
+    }
+    q0x = wave_sum(q0x); q0y = (D == 2) ? wave_sum(q0y) : 0.0;
+    T1 = wave_sum(T1); Txx = wave_sum(Txx); Tyy = wave_sum(Tyy); Txy = wave_sum(Txy);
+    double x[kRecIn], c[kRecOut];
+    x[0] = rho; x[1] = ux; x[2] = uy; x[3] = lam;
+    grad_in(x);
+    rec_values(g, dts, x, c);
+    store_rec(e, rho, ux, uy, lam, q0x, q0y, c);
   }
-  double W0[4] = {wave_sum(s0), wave_sum(s1), 0.0, 0.0};
-  if (D == 2) { W0[2] = wave_sum(s2); W0[3] = wave_sum(s3); }
-  else W0[2] = wave_sum(s3);
-  Rec e;
-  prim_d(D, g.nxi, W0, e.rho, e.ux, e.uy, e.lam);
-  // pass 2: heat flux q0 and the sums of its derivative along U
-  double q0x = 0, q0y = 0, T1 = 0, Txx = 0, Tyy = 0, Txy = 0;
-  for (int k = lane; k < nv; k += 64) {
-    double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
-    double fh, fb;
-    upwind(k, wn_exact(vx, vy, ufx, ufy, nx, ny), fh, fb);
-    double cx = vx - e.ux, cy = (D == 2) ? vy - e.uy : 0.0;
-    double en = (cx * cx + cy * cy) * fh + fb;
-    q0x += w * 0.5 * cx * en; q0y += w * 0.5 * cy * en;
-    T1 += w * en; Txx += w * cx * cx * fh; Tyy += w * cy * cy * fh; Txy += w * cx * cy * fh;
-  }
-  e.qx = wave_sum(q0x); e.qy = (D == 2) ? wave_sum(q0y) : 0.0;
-  T1 = wave_sum(T1); Txx = wave_sum(Txx); Tyy = wave_sum(Tyy); Txy = wave_sum(Txy);
-  // record: values in every lane, Jacobian column j in lane j
-  double x[kRecIn];
-  x[0] = e.rho; x[1] = e.ux; x[2] = e.uy; x[3] = e.lam;
-  for (int m = 0; m < 8; ++m) {
-    double gl = (L >= 0) ? gW[(size_t)L * 8 + m] : 0.0;
-    double gr = (R >= 0) ? gW[(size_t)R * 8 + m] : 0.0;
-    x[4 + m] = 0.5 * (gl + gr);
-  }
-  x[12] = ufx; x[13] = ufy;
-  double col[kRecOut];
-  face_coeffs_lanes(g, dts, x, lane, e.c, col);
-  // pass 3: reverse of the flux at every velocity, record bars
+  // pass 3: reverse of the flux at every velocity; the bars of the upwind
+  // data go to the cells at once, the record bars are accumulated
   double acc[kRecBar];
   for (int i = 0; i < kRecBar; ++i) acc[i] = 0.0;
   double ufb_x = 0.0, ufb_y = 0.0;
-  const double* Fbf = Fb + (size_t)f * nw;
+  const double* Fbf = Fb + (size_t)f * kNw;
   for (int k = lane; k < nv; k += 64) {
     double vx = g.vx[k], vy = g.vy[k];
     double wn = wn_exact(vx, vy, ufx, ufy, nx, ny);
     if (wn == 0.0) continue;
     double Fhb, Fbb;
     flux_bar_k(g, fp, Dbh, Dbb, Fbf, k, Fhb, Fbb);
-    int up = (wn > 0.0) ? cL : cR;
-    double ux_ = (wn > 0.0) ? dLx : dRx, uy_ = (wn > 0.0) ? dLy : dRy;
-    SideK sh = side_any(g, h, hinf, up, inner, ux_, uy_, k), sb = side_any(g, b, binf, up, inner, ux_, uy_, k);
+    const bool lft = wn > 0.0;
+    const int up = lft ? cL : cR;
+    const double ox = lft ? dLx : dRx, oy = lft ? dLy : dRy;
+    SideD sh = side_val_d(g, h, hinf, up, inner, ox, oy, k), sb = side_val_d(g, b, binf, up, inner, ox, oy, k);
     double fhb, fbb, ghb[2], gbb[2], Ih, Ib;
-    iint_rev(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy,
-             Fhb * wn / dts, Fbb * wn / dts, fhb, fbb, ghb, gbb, acc, Ih, Ib);
+    iint_rev<true>(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy,
+                   Fhb * wn / dts, Fbb * wn / dts, fhb, fbb, ghb, gbb, acc, Ih, Ib);
     double wnb = (Fhb * Ih + Fbb * Ib) / dts;
     ufb_x -= wnb * nx;
     ufb_y -= wnb * ny;
+    side_rev_d(g, sh, up, inner, ox, oy, k, fhb, ghb[0], ghb[1], hbar);
+    side_rev_d(g, sb, up, inner, ox, oy, k, fbb, gbb[0], gbb[1], bbar);
   }
   for (int i = 0; i < kRecBar; ++i) acc[i] = wave_sum(acc[i]);
   ufb_x = wave_sum(ufb_x) - acc[23];
   ufb_y = wave_sum(ufb_y) - acc[24];
   // contraction with the record Jacobian: lane j < kRecIn holds input j's bar
-  double inb = 0.0;
-  for (int i = 0; i < kRecOut; ++i) inb += acc[6 + i] * col[i];
   double xb[kRecIn];
-  for (int j = 0; j < kRecIn; ++j) xb[j] = lane_read(inb, j);
-  double rb = acc[0] + xb[0], uxb = acc[1] + xb[1], uyb = acc[2] + xb[2], lb = acc[3] + xb[3];
-  double qxb = acc[4], qyb = acc[5];
+  {
+    double x[kRecIn], val[kRecOut], col[kRecOut];
+    x[0] = e.rho; x[1] = e.ux; x[2] = e.uy; x[3] = e.lam;
+    grad_in(x);
+    face_coeffs_lanes(g, dts, x, lane, val, col);
+    double inb = 0.0;
+    for (int i = 0; i < kRecOut; ++i) inb += acc[6 + i] * col[i];
+    for (int j = 0; j < kRecIn; ++j) xb[j] = lane_read(inb, j);
+  }
+  double uxb = acc[1] + xb[1], uyb = acc[2] + xb[2];
+  const double qxb = acc[4], qyb = acc[5];
   ufb_x += xb[12];
   ufb_y += xb[13];
   // q0 depends on U0 through c = v - U0
   uxb += -0.5 * (T1 + 2.0 * Txx) * qxb - Txy * qyb;
   if (D == 2) uyb += -Txy * qxb - 0.5 * (T1 + 2.0 * Tyy) * qyb;
   double W0b[4] = {0, 0, 0, 0};
-  prim_rev(D, g.nxi, W0, rb, uxb, uyb, lb, W0b);
+  prim_rev(D, kNxi, W0, acc[0] + xb[0], uxb, uyb, acc[3] + xb[3], W0b);
   // gradient bars of the two cells (the face slope is their mean)
   if (lane < 8) {
     double v = 0.5 * xb[4 + lane];
@@ -509,42 +609,37 @@ __global__ __launch_bounds__(256) void k_adj_face(Dev g, double dts, const doubl
     fbar[(size_t)f * 5 + 0] += ufb_x;
     fbar[(size_t)f * 5 + 1] += ufb_y;
   }
-  // pass 4: per-velocity bars of the interface data, scattered to the cells
+  // pass 4: the moment bars of the upwind data (W0, q0), to both sides
+  const double ux0 = e.ux, uy0 = e.uy;
   for (int k = lane; k < nv; k += 64) {
     double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
     double wn = wn_exact(vx, vy, ufx, ufy, nx, ny);
-    double cx = vx - e.ux, cy = (D == 2) ? vy - e.uy : 0.0;
+    double cx = vx - ux0, cy = (D == 2) ? vy - uy0 : 0.0;
     double cqb = cx * qxb + cy * qyb;
     double mh = w * (W0b[0] + W0b[1] * vx + ((D == 2) ? W0b[2] * vy : 0.0) +
                      W0b[D + 1] * 0.5 * (vx * vx + vy * vy)) + w * 0.5 * cqb * (cx * cx + cy * cy);
     double mb = w * 0.5 * W0b[D + 1] + w * 0.5 * cqb;
-    double lh = 0, lb_ = 0, rh = 0, rb_ = 0;
-    double lgh[2] = {0, 0}, lgb[2] = {0, 0}, rgh[2] = {0, 0}, rgb[2] = {0, 0};
-    if (wn > 0.0) { lh = mh; lb_ = mb; }
-    else if (wn < 0.0) { rh = mh; rb_ = mb; }
-    else { lh = rh = 0.5 * mh; lb_ = rb_ = 0.5 * mb; }
-    if (wn != 0.0) {
-      double Fhb, Fbb;
-      flux_bar_k(g, fp, Dbh, Dbb, Fbf, k, Fhb, Fbb);
-      int up = (wn > 0.0) ? cL : cR;
-      double ux_ = (wn > 0.0) ? dLx : dRx, uy_ = (wn > 0.0) ? dLy : dRy;
-      SideK sh = side_any(g, h, hinf, up, inner, ux_, uy_, k), sb = side_any(g, b, binf, up, inner, ux_, uy_, k);
-      double fhb, fbb, ghb[2], gbb[2], Ih, Ib, dummy[kRecBar];
-      iint_rev(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy,
-               Fhb * wn / dts, Fbb * wn / dts, fhb, fbb, ghb, gbb, dummy, Ih, Ib);
-      if (wn > 0.0) { lh += fhb; lb_ += fbb; lgh[0] = ghb[0]; lgh[1] = ghb[1]; lgb[0] = gbb[0]; lgb[1] = gbb[1]; }
-      else { rh += fhb; rb_ += fbb; rgh[0] = ghb[0]; rgh[1] = ghb[1]; rgb[0] = gbb[0]; rgb[1] = gbb[1]; }
+    // the upwind side (on a tie: half to each side), chosen per lane
+    const bool tie = (wn == 0.0);
+    const double sl = tie ? 0.5 : 1.0;
+    const bool lft = wn > 0.0;
+    const int up = lft ? cL : cR;
+    const double ox = lft ? dLx : dRx, oy = lft ? dLy : dRy;
+    side_any_rev(g, h, hinf, up, inner, ox, oy, k, sl * mh, 0.0, 0.0, hbar);
+    side_any_rev(g, b, binf, up, inner, ox, oy, k, sl * mb, 0.0, 0.0, bbar);
+    if (tie) {
+      side_any_rev(g, h, hinf, cL, inner, dLx, dLy, k, 0.5 * mh, 0.0, 0.0, hbar);
+      side_any_rev(g, b, binf, cL, inner, dLx, dLy, k, 0.5 * mb, 0.0, 0.0, bbar);
     }
-    side_any_rev(g, h, hinf, cL, inner, dLx, dLy, k, lh, lgh[0], lgh[1], hbar);
-    side_any_rev(g, b, binf, cL, inner, dLx, dLy, k, lb_, lgb[0], lgb[1], bbar);
-    side_any_rev(g, h, hinf, cR, inner, dRx, dRy, k, rh, rgh[0], rgh[1], hbar);
-    side_any_rev(g, b, binf, cR, inner, dRx, dRy, k, rb_, rgb[0], rgb[1], bbar);
   }
 }
 
 // ------------------------------------------------------------------------
 // flux reverse, isothermal wall faces (Eq. maxWalldes): one wavefront per
-// face
+// face.  Pass 1: incident mass flux and the wall normaliser; pass 2: the
+// reflected part reversed (bars of rho_w, T_w, v_w, U_f); pass 3: the
+// incident part reversed, its bars scattered at once, record bars
+// accumulated; then the record Jacobian and the incident state.
 // ------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const double* __restrict__ h,
                                                   const double* __restrict__ b, const double* __restrict__ W,
@@ -554,14 +649,16 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
                                                   double* __restrict__ bbar, double* __restrict__ Wbar,
                                                   double* __restrict__ qbar, double* __restrict__ gWbar,
                                                   double* __restrict__ fbar) {
+  __shared__ Rec srec[4];
   const int f = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (f >= g.nface) return;
+  Rec& e = srec[threadIdx.x >> 6];
   const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
   if (L != kNbWall && R != kNbWall) return;
   const int c = (L == kNbWall) ? R : L;
   if (c < 0 || g.type[c] != 1) return;
-  const int D = g.dim, nw = g.nw, nv = g.nv, nxi = g.nxi;
+  const int D = kD, nw = kNw, nv = g.nv, nxi = kNxi;
   int slot = 0;
   for (int s = 0; s < 4; ++s) if (g.cf[4 * c + s] == f) slot = s;
   const double* fg = g.fgeo + (size_t)f * 8;
@@ -578,16 +675,17 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
   const bool extrap = physical_state(D, Win);
   if (!extrap)
     for (int m = 0; m < nw; ++m) Win[m] = W[(size_t)c * nw + m];
-  Rec e;
-  prim_d(D, nxi, Win, e.rho, e.ux, e.uy, e.lam);
-  e.qx = q[(size_t)c * D];
-  e.qy = (D == 2) ? q[(size_t)c * D + 1] : 0.0;
-  double x[kRecIn];
-  x[0] = e.rho; x[1] = e.ux; x[2] = e.uy; x[3] = e.lam;
-  for (int m = 0; m < 8; ++m) x[4 + m] = gw[m];
-  x[12] = ufx; x[13] = ufy;
-  double col[kRecOut];
-  face_coeffs_lanes(g, dts, x, lane, e.c, col);
+  auto rec_in = [&](double* x) {
+    prim_d(D, nxi, Win, x[0], x[1], x[2], x[3]);
+    for (int m = 0; m < 8; ++m) x[4 + m] = gw[m];
+    x[12] = ufx; x[13] = ufy;
+  };
+  {
+    double x[kRecIn], cc[kRecOut];
+    rec_in(x);
+    rec_values(g, dts, x, cc);
+    store_rec(e, x[0], x[1], x[2], x[3], q[(size_t)c * D], (D == 2) ? q[(size_t)c * D + 1] : 0.0, cc);
+  }
   const double lamw = 0.5 / rtw;
   const double nrm = pow(lamw / kPi, 0.5 * D);
   const double betaw = (double)nxi / (2.0 * lamw);
@@ -598,9 +696,9 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
     double wn = wn_exact(vx, vy, ufx, ufy, nwx, nwy);
     if (wn > 0.0) {
       SideK sh = side_val(g, h, hinf, c, dx, dy, k), sb = side_val(g, b, binf, c, dx, dy, k);
-      double fhb, fbb, ghb[2], gbb[2], Ih, Ib, dummy[kRecBar];
-      iint_rev(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy, 0.0, 0.0,
-               fhb, fbb, ghb, gbb, dummy, Ih, Ib);
+      double fhb, fbb, ghb[2], gbb[2], Ih, Ib;
+      iint_rev<false>(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy,
+                      0.0, 0.0, fhb, fbb, ghb, gbb, nullptr, Ih, Ib);
       num += w * wn * Ih;
     } else if (wn < 0.0) {
       double cx = vx - vwx, cy = (D == 2) ? vy - vwy : 0.0;
@@ -649,7 +747,8 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
   vwby += denb * dden_vy;
   ufbx -= denb * dden_u * nwx;
   ufby -= denb * dden_u * nwy;
-  // pass 3: incident part (wn > 0), record bars
+  // pass 3: incident part (wn > 0): bars of the incident data scattered,
+  // record bars accumulated
   double acc[kRecBar];
   for (int i = 0; i < kRecBar; ++i) acc[i] = 0.0;
   double ufb2x = 0, ufb2y = 0;
@@ -660,22 +759,29 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
     double Fhb, Fbb;
     flux_bar_k(g, fpw, Dbh, Dbb, Fbf, k, Fhb, Fbb);
     double fhb_ = sgn * Fhb, fbb_ = sgn * Fbb;
-    SideK sh = side_val(g, h, hinf, c, dx, dy, k), sb = side_val(g, b, binf, c, dx, dy, k);
+    SideD sh = side_val_d(g, h, hinf, c, c, dx, dy, k), sb = side_val_d(g, b, binf, c, c, dx, dy, k);
     double Ihb = fhb_ * wn / dts + numb * w * wn, Ibb = fbb_ * wn / dts;
     double fhb, fbb, ghb[2], gbb[2], Ih, Ib;
-    iint_rev(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy, Ihb, Ibb,
-             fhb, fbb, ghb, gbb, acc, Ih, Ib);
+    iint_rev<true>(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy, Ihb,
+                   Ibb, fhb, fbb, ghb, gbb, acc, Ih, Ib);
     double wnb = fhb_ * Ih / dts + fbb_ * Ib / dts + numb * w * Ih;
     ufb2x -= wnb * nwx;
     ufb2y -= wnb * nwy;
+    side_rev_d(g, sh, c, c, dx, dy, k, fhb, ghb[0], ghb[1], hbar);
+    side_rev_d(g, sb, c, c, dx, dy, k, fbb, gbb[0], gbb[1], bbar);
   }
   for (int i = 0; i < kRecBar; ++i) acc[i] = wave_sum(acc[i]);
   ufbx += wave_sum(ufb2x) - acc[23];
   ufby += wave_sum(ufb2y) - acc[24];
-  double inb = 0.0;
-  for (int i = 0; i < kRecOut; ++i) inb += acc[6 + i] * col[i];
   double xb[kRecIn];
-  for (int j = 0; j < kRecIn; ++j) xb[j] = lane_read(inb, j);
+  {
+    double x[kRecIn], val[kRecOut], col[kRecOut];
+    rec_in(x);
+    face_coeffs_lanes(g, dts, x, lane, val, col);
+    double inb = 0.0;
+    for (int i = 0; i < kRecOut; ++i) inb += acc[6 + i] * col[i];
+    for (int j = 0; j < kRecIn; ++j) xb[j] = lane_read(inb, j);
+  }
   ufbx += xb[12];
   ufby += xb[13];
   double Winb[4] = {0, 0, 0, 0};
@@ -698,23 +804,7 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
     }
     atomic_add(gWbar + (size_t)c * 8 + lane, v);
   }
-  // pass 4: per-velocity bars of the incident data
-  for (int k = lane; k < nv; k += 64) {
-    double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
-    double wn = wn_exact(vx, vy, ufx, ufy, nwx, nwy);
-    if (!(wn > 0.0)) continue;
-    double Fhb, Fbb;
-    flux_bar_k(g, fpw, Dbh, Dbb, Fbf, k, Fhb, Fbb);
-    SideK sh = side_val(g, h, hinf, c, dx, dy, k), sb = side_val(g, b, binf, c, dx, dy, k);
-    double Ihb = sgn * Fhb * wn / dts + numb * w * wn, Ibb = sgn * Fbb * wn / dts;
-    double fhb, fbb, ghb[2], gbb[2], Ih, Ib, dummy[kRecBar];
-    iint_rev(g, e, vx, vy, vx - ufx, (D == 2) ? vy - ufy : 0.0, sh.v, sb.v, sh.gx, sh.gy, sb.gx, sb.gy, Ihb, Ibb,
-             fhb, fbb, ghb, gbb, dummy, Ih, Ib);
-    side_rev(g, h, hinf, c, dx, dy, k, fhb, ghb[0], ghb[1], hbar);
-    side_rev(g, b, binf, c, dx, dy, k, fbb, gbb[0], gbb[1], bbar);
-  }
 }
-
 
 // ------------------------------------------------------------------------
 // limited W gradients (reconstruction of W for the slopes and the wall
@@ -724,14 +814,14 @@ __global__ void k_adj_gradW(Dev g, const double* __restrict__ W, const double* _
                             double* __restrict__ Wbar) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.ncell || g.type[c] == 0) return;
-  const int nw = g.nw;
+  const int nw = kNw;
   const double* gb = gWbar + (size_t)c * 8;
   const double* G = g.G + 4 * c;
   const int* nb = g.nb + 4 * c;
   for (int m = 0; m < nw; ++m) {
-    double gxb = gb[m], gyb = (g.dim == 2) ? gb[nw + m] : 0.0;
-    double sib = G[0] * gxb + ((g.dim == 2) ? G[2] * gyb : 0.0);
-    double sjb = (g.dim == 2) ? G[1] * gxb + G[3] * gyb : 0.0;
+    double gxb = gb[m], gyb = (kD == 2) ? gb[nw + m] : 0.0;
+    double sib = G[0] * gxb + ((kD == 2) ? G[2] * gyb : 0.0);
+    double sjb = (kD == 2) ? G[1] * gxb + G[3] * gyb : 0.0;
     double v0 = W[(size_t)c * nw + m];
     auto val = [&](int code) -> double {
       if (code >= 0) return W[(size_t)code * nw + m];
@@ -739,7 +829,7 @@ __global__ void k_adj_gradW(Dev g, const double* __restrict__ W, const double* _
       return v0;
     };
     double own = 0.0;
-    for (int dir = 0; dir < g.dim; ++dir) {
+    for (int dir = 0; dir < kD; ++dir) {
       double sb = dir ? sjb : sib;
       if (sb == 0.0) continue;
       int lo = nb[2 * dir], hi = nb[2 * dir + 1];
@@ -769,7 +859,7 @@ __global__ __launch_bounds__(256) void k_adj_step7(Dev g, const double* __restri
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= g.ncell) return;
-  const int D = g.dim, nw = g.nw, nv = g.nv;
+  const int D = kD, nw = kNw, nv = g.nv;
   double Wb[4] = {0, 0, 0, 0};
   for (int m = 0; m < nw; ++m) Wb[m] = W1b[(size_t)c * nw + m];
   if (g.type[c] == 0) {
@@ -778,7 +868,7 @@ __global__ __launch_bounds__(256) void k_adj_step7(Dev g, const double* __restri
   }
   // q' = heat flux of f' about the velocity of W'
   double rho1, ux1, uy1, lam1;
-  prim_d(D, g.nxi, W1 + (size_t)c * nw, rho1, ux1, uy1, lam1);
+  prim_d(D, kNxi, W1 + (size_t)c * nw, rho1, ux1, uy1, lam1);
   const double qxb = q1b[(size_t)c * D], qyb = (D == 2) ? q1b[(size_t)c * D + 1] : 0.0;
   double uxb = 0.0, uyb = 0.0;
   for (int k = lane; k < nv; k += 64) {
@@ -790,13 +880,13 @@ __global__ __launch_bounds__(256) void k_adj_step7(Dev g, const double* __restri
   }
   uxb = wave_sum(uxb);
   uyb = wave_sum(uyb);
-  prim_rev(D, g.nxi, W1 + (size_t)c * nw, 0.0, uxb, uyb, 0.0, Wb);
+  prim_rev(D, kNxi, W1 + (size_t)c * nw, 0.0, uxb, uyb, 0.0, Wb);
   if (g.type[c] != 1) {
     if (lane < nw) Wpb[(size_t)c * nw + lane] = Wb[lane];
     return;
   }
   double rho, ux, uy, lam;
-  prim_d(D, g.nxi, Wp + (size_t)c * nw, rho, ux, uy, lam);
+  prim_d(D, kNxi, Wp + (size_t)c * nw, rho, ux, uy, lam);
   double a[6] = {0, 0, 0, 0, 0, 0};
   for (int k = lane; k < nv; k += 64) {
     size_t o = (size_t)c * nv + k;
@@ -809,7 +899,7 @@ __global__ __launch_bounds__(256) void k_adj_step7(Dev g, const double* __restri
   }
   for (int i = 0; i < 4; ++i) a[i] = wave_sum(a[i]);
   double Wpbl[4] = {Wb[0], Wb[1], Wb[2], Wb[3]};
-  prim_rev(D, g.nxi, Wp + (size_t)c * nw, a[0], a[1], a[2], a[3], Wpbl);
+  prim_rev(D, kNxi, Wp + (size_t)c * nw, a[0], a[1], a[2], a[3], Wpbl);
   if (lane < nw) Wpb[(size_t)c * nw + lane] = Wpbl[lane];
 }
 
@@ -818,8 +908,8 @@ __global__ __launch_bounds__(256) void k_adj_step7(Dev g, const double* __restri
 // sweeps x = (D+U)^{-1} D (D+L)^{-1} r, the bar of the residual is
 // r_bar = (D+L)^{-T} D (D+U)^{-T} x_bar: an ascending transposed sweep for
 // y = (D+U)^{-T} x_bar, then a descending one for r_bar.  One workgroup per
-// block and 64-velocity chunk, lanes over velocities, waves over the rows of
-// a hyperplane.
+// block and 16-velocity chunk, groups of 16 lanes over the rows of a
+// hyperplane.
 // ------------------------------------------------------------------------
 __device__ __forceinline__ double micro_coef(const double* mg, int s, double vx, double vy) {
   return mg[3 * s] * vx + mg[3 * s + 1] * vy - mg[3 * s + 2];
@@ -831,15 +921,17 @@ __global__ __launch_bounds__(1024) void k_adj_micro_sweep(Dev g, const int* __re
                                                           const double* __restrict__ inh,
                                                           const double* __restrict__ inb,
                                                           double* __restrict__ outh, double* __restrict__ outb) {
+  // 16 velocities per workgroup (one per lane of a 16-lane group), the
+  // groups over the rows of a hyperplane
   const int blk = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwav = blockDim.x >> 6;
-  const int k = blockIdx.y * 64 + lane;
+  const int wave = threadIdx.x >> 4, nwav = blockDim.x >> 4;
+  const int k = blockIdx.y * 16 + (threadIdx.x & 15);
   const int ni = binfo[8 * blk], nj = binfo[8 * blk + 1], c0 = binfo[8 * blk + 2];
   const bool kok = k < g.nv;
   const int kk = kok ? k : 0;
   const double vx = g.vx[kk], vy = g.vy[kk];
   const int nh = ni + nj - 1;
-  const int ns = 2 * g.dim;
+  const int ns = 2 * kD;
   for (int it = 0; it < nh; ++it) {
     const int hp = (MODE == 0) ? it : nh - 1 - it;
     for (int j = wave; j < nj; j += nwav) {
@@ -882,7 +974,7 @@ __global__ __launch_bounds__(1024) void k_adj_micro_sweep(Dev g, const int* __re
 // summed over h and b.  Then the residual r = S - f/dt + (D + (f+ - f)/tau)/2
 // is reversed (its f+ through the Shakhov equilibrium of (W~, q~)), and q~,
 // the heat flux of f about the velocity of W~.
-__global__ __launch_bounds__(256) void k_adj_micro_coef(
+__global__ __launch_bounds__(256, 2) void k_adj_micro_coef(
     Dev g, double dt, const double* __restrict__ crec, const double* __restrict__ Wp,
     const double* __restrict__ h0, const double* __restrict__ b0, const double* __restrict__ h1,
     const double* __restrict__ b1, const double* __restrict__ xsh, const double* __restrict__ xsb,
@@ -893,7 +985,7 @@ __global__ __launch_bounds__(256) void k_adj_micro_coef(
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= g.ncell) return;
-  const int D = g.dim, nv = g.nv, nw = g.nw, ns = 2 * D;
+  const int D = kD, nv = g.nv, nw = kNw, ns = 2 * D;
   if (g.type[c] != 1) {
     for (int k = lane; k < nv; k += 64) {
       size_t o = (size_t)c * nv + k;
@@ -939,7 +1031,7 @@ __global__ __launch_bounds__(256) void k_adj_micro_coef(
     const double cx = vx - ux, cy = (D == 2) ? vy - uy : 0.0;
     const double c2 = cx * cx + cy * cy;
     const double H = hn * exp(-lam * c2);
-    const double beta = (double)g.nxi / (2.0 * lam);
+    const double beta = (double)kNxi / (2.0 * lam);
     const double sq = shc * (cx * qx + cy * qy);
     const double hp = H + sq * (2.0 * lam * c2 - 2.0 - D) * H;
     const double bp = beta * H + sq * (2.0 * lam * c2 - D) * beta * H;
@@ -972,7 +1064,7 @@ __global__ __launch_bounds__(256) void k_adj_micro_coef(
   const double uxb = a[1] + wave_sum(uxq);
   const double uyb = a[2] + wave_sum(uyq);
   double Wl[4] = {0, 0, 0, 0};
-  prim_rev(D, g.nxi, Wp + (size_t)c * nw, a[0], uxb, uyb, a[3], Wl);
+  prim_rev(D, kNxi, Wp + (size_t)c * nw, a[0], uxb, uyb, a[3], Wl);
   if (lane < nw) Wpb[(size_t)c * nw + lane] += Wl[lane];
   // face coefficient a = S/(2|Omega|) (v - U_f).n_out = A vx + B vy - C:
   // its U_f bar is -(A, B) a_bar
@@ -1032,12 +1124,12 @@ __global__ void k_adj_macro_init(Dev g, const double* __restrict__ W, const doub
                                  double* __restrict__ dWb) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.ncell) return;
-  const int nw = g.nw;
+  const int nw = kNw;
   bool upd = false;
   if (g.type[c] == 1) {
     double t[4] = {0, 0, 0, 0};
     for (int m = 0; m < nw; ++m) t[m] = W[(size_t)c * nw + m] + dW[(size_t)c * nw + m];
-    upd = physical_state(g.dim, t);
+    upd = physical_state(kD, t);
   }
   for (int m = 0; m < nw; ++m) {
     double v = Wpb[(size_t)c * nw + m];
@@ -1057,7 +1149,7 @@ __global__ __launch_bounds__(512) void k_adj_macro_sweep(
     double* __restrict__ Wbar, double* __restrict__ fbar) {
   const int blk = blockIdx.x;
   const int ni = binfo[8 * blk], nj = binfo[8 * blk + 1], c0 = binfo[8 * blk + 2];
-  const int D = g.dim, nw = g.nw, ns = 2 * D;
+  const int D = kD, nw = kNw, ns = 2 * D;
   const int nh = ni + nj - 1;
   for (int pass = 0; pass < 2; ++pass) {
     for (int it = 0; it < nh; ++it) {
@@ -1144,7 +1236,7 @@ __global__ void k_adj_macro_post(Dev g, double dt, const double* __restrict__ Rb
                                  double* __restrict__ Fnb, double* __restrict__ gamb) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.ncell) return;
-  const int nw = g.nw;
+  const int nw = kNw;
   if (g.type[c] != 1) return;
   const double ivol = 1.0 / g.vol[c];
   for (int m = 0; m < nw; ++m) {
@@ -1152,7 +1244,7 @@ __global__ void k_adj_macro_post(Dev g, double dt, const double* __restrict__ Rb
     Wbar[(size_t)c * nw + m] -= r / dt;
     Wnb[(size_t)c * nw + m] += r / dt;
   }
-  for (int s = 0; s < 2 * g.dim; ++s) {
+  for (int s = 0; s < 2 * kD; ++s) {
     int f = g.cf[4 * c + s];
     if (f < 0) continue;
     const double S = g.fgeo[(size_t)f * 8 + 2];
@@ -1173,11 +1265,11 @@ __global__ void k_adj_gamma(Dev g, const double* __restrict__ W, const double* _
   if (f >= g.nface) return;
   const double gb = gamb[f];
   if (gb == 0.0) return;
-  const int D = g.dim, nw = g.nw;
+  const int D = kD, nw = kNw;
   const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
   const double* fg = g.fgeo + (size_t)f * 8;
   const double nx = fg[0], ny = fg[1];
-  const double gma = (double)(D + g.nxi + 2) / (double)(D + g.nxi);
+  const double gma = (double)(D + kNxi + 2) / (double)(D + kNxi);
   auto side = [&](int code, int inner, double wgt_u, double wgt_a, double thb) {
     const double* w;
     int tgt;
@@ -1185,11 +1277,11 @@ __global__ void k_adj_gamma(Dev g, const double* __restrict__ W, const double* _
     else if (code == kNbFar) return;
     else { w = W + (size_t)inner * nw; tgt = inner; }
     double rho, ux, uy, lam;
-    prim_d(D, g.nxi, w, rho, ux, uy, lam);
+    prim_d(D, kNxi, w, rho, ux, uy, lam);
     double a = sqrt(gma * 0.5 / lam);
     double lb = -wgt_a * gb * a / (2.0 * lam);
     double Wl[4] = {0, 0, 0, 0};
-    prim_rev(D, g.nxi, w, 0.0, wgt_u * thb * nx, wgt_u * thb * ny, lb, Wl);
+    prim_rev(D, kNxi, w, 0.0, wgt_u * thb * nx, wgt_u * thb * ny, lb, Wl);
     for (int m = 0; m < nw; ++m) atomic_add(Wbar + (size_t)tgt * nw + m, Wl[m]);
   };
   double thv;
@@ -1197,7 +1289,7 @@ __global__ void k_adj_gamma(Dev g, const double* __restrict__ W, const double* _
     int c = (L == kNbWall) ? R : L;
     if (c < 0) return;
     double rho, ux, uy, lam;
-    prim_d(D, g.nxi, W + (size_t)c * nw, rho, ux, uy, lam);
+    prim_d(D, kNxi, W + (size_t)c * nw, rho, ux, uy, lam);
     thv = (ux - fg[3]) * nx + (uy - fg[4]) * ny;
     double thb = gb * ((thv < 0.0) ? -1.0 : 1.0);
     side(c, c, 1.0, 1.0, thb);
@@ -1237,7 +1329,7 @@ __global__ __launch_bounds__(256) void k_adj_source(Dev g, double dt, const doub
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= g.ncell) return;
-  const int D = g.dim, nv = g.nv, nw = g.nw;
+  const int D = kD, nv = g.nv, nw = kNw;
   if (g.type[c] != 1) {
     for (int k = lane; k < nv; k += 64) { Dbh[(size_t)c * nv + k] = 0.0; Dbb[(size_t)c * nv + k] = 0.0; }
     return;
@@ -1256,7 +1348,7 @@ __global__ __launch_bounds__(256) void k_adj_source(Dev g, double dt, const doub
     const double cx = vx - ux, cy = (D == 2) ? vy - uy : 0.0;
     const double c2 = cx * cx + cy * cy;
     const double H = hn * exp(-lam * c2);
-    const double beta = (double)g.nxi / (2.0 * lam);
+    const double beta = (double)kNxi / (2.0 * lam);
     const double sq = shc * (cx * qx + cy * qy);
     const double hp = H + sq * (2.0 * lam * c2 - 2.0 - D) * H;
     const double bp = beta * H + sq * (2.0 * lam * c2 - D) * beta * H;
@@ -1273,7 +1365,7 @@ __global__ __launch_bounds__(256) void k_adj_source(Dev g, double dt, const doub
   itau_partials(g, rho, lam, dr, dl);
   if (g.mu_ref > 0.0) { a[0] += itb * dr; a[3] += itb * dl; }
   double Wl[4] = {0, 0, 0, 0};
-  prim_rev(D, g.nxi, W + (size_t)c * nw, a[0], a[1], a[2], a[3], Wl);
+  prim_rev(D, kNxi, W + (size_t)c * nw, a[0], a[1], a[2], a[3], Wl);
   if (lane < nw) atomic_add(Wbar + (size_t)c * nw + lane, Wl[lane]);
   if (lane == 0) {
     atomic_add(qbar + (size_t)c * D, a[4]);
@@ -1305,16 +1397,16 @@ __global__ __launch_bounds__(256) void k_adj_interp(Dev g, int nrow, const int* 
     hbar[o] = 0.0;
     bbar[o] = 0.0;
   }
-  if (lane < g.nw) {
-    const double v = Wbar[(size_t)c * g.nw + lane];
-    for (int p = p0; p < p1; ++p) atomic_add(Wbar + (size_t)don[p] * g.nw + lane, wt[p] * v);
-    Wbar[(size_t)c * g.nw + lane] = 0.0;
+  if (lane < kNw) {
+    const double v = Wbar[(size_t)c * kNw + lane];
+    for (int p = p0; p < p1; ++p) atomic_add(Wbar + (size_t)don[p] * kNw + lane, wt[p] * v);
+    Wbar[(size_t)c * kNw + lane] = 0.0;
   }
-  if (lane >= 8 && lane < 8 + g.dim) {
+  if (lane >= 8 && lane < 8 + kD) {
     const int m = lane - 8;
-    const double v = qbar[(size_t)c * g.dim + m];
-    for (int p = p0; p < p1; ++p) atomic_add(qbar + (size_t)don[p] * g.dim + m, wt[p] * v);
-    qbar[(size_t)c * g.dim + m] = 0.0;
+    const double v = qbar[(size_t)c * kD + m];
+    for (int p = p0; p < p1; ++p) atomic_add(qbar + (size_t)don[p] * kD + m, wt[p] * v);
+    qbar[(size_t)c * kD + m] = 0.0;
   }
 }
 
@@ -1346,7 +1438,7 @@ void adj_micro(const Dev& g, const int* binfo, int nblock, double dt, const doub
                const double* xsb, const double* xbh, const double* xbb, double* yh, double* yb, double* rh,
                double* rb, double* hbar, double* bbar, double* Shb, double* Sbb, double* Dbh, double* Dbb,
                double* Wpb, double* fbar, hipStream_t st) {
-  dim3 grid(nblock, nblk(g.nv, 64));
+  dim3 grid(nblock, nblk(g.nv, 16));
   hipLaunchKernelGGL(k_adj_micro_sweep<0>, grid, dim3(1024), 0, st, g, binfo, crec, xbh, xbb, yh, yb);
   hipLaunchKernelGGL(k_adj_micro_sweep<1>, grid, dim3(1024), 0, st, g, binfo, crec, (const double*)yh,
                      (const double*)yb, rh, rb);
