@@ -1671,7 +1671,16 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   const int t = threadIdx.x;
   const int lk = t % KC, j = t / KC;
   const int nv = g.nv;
-  const int k = blockIdx.x * KC + lk;
+  // velocity chunk: chunks that share a 128-byte line of f go to workgroups
+  // that the round-robin dispatch places on the same XCD (every 8th
+  // workgroup), so each line is fetched once into that XCD's L2
+  constexpr int G = (128 / (KC * (int)sizeof(T)) > 1) ? 128 / (KC * (int)sizeof(T)) : 1;
+  int chunk = blockIdx.x;
+  if constexpr (G > 1) {
+    const int span = 8 * G, base = (chunk / span) * span;
+    if (base + span <= (int)gridDim.x) chunk = base + G * (chunk % 8) + (chunk / 8) % G;
+  }
+  const int k = chunk * KC + lk;
   const bool kin = k < nv;
   const int kk = kin ? k : nv - 1;
   const bool row = j < nj;
