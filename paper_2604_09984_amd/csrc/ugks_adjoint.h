@@ -9,12 +9,13 @@
 namespace ugks {
 
 // UGKS flux (Sec. 2.1) reversed at the state (h, b, W, q) with the cell
-// gradients gW of W: divergence bars Dbh, Dbb [ncell][nv] and face macro
-// flux bar Fb [nface][nw] in; bars of h, b, W, q, of gW (scratch, zero on
-// entry) and of the face parameters accumulated.
+// gradients gW of W and the forward face records rec (their moment shifts
+// are used): divergence bars Dbh, Dbb [ncell][nv] and face macro flux bar
+// Fb [nface][nw] in; bars of h, b, W, q, of gW (scratch, zero on entry) and
+// of the face parameters accumulated.
 void adj_flux(const Dev& g, double dts, const double* h, const double* b, const double* W, const double* q,
-              const double* gW, const double* Dbh, const double* Dbb, const double* Fb, double* hbar,
-              double* bbar, double* Wbar, double* qbar, double* gWbar, double* fbar, hipStream_t st);
+              const double* gW, const double* rec, const double* Dbh, const double* Dbb, const double* Fb,
+              double* hbar, double* bbar, double* Wbar, double* qbar, double* gWbar, double* fbar, hipStream_t st);
 
 // Step 7 and the heat flux of the new state reversed: hb, bb (bars of f')
 // updated in place, Wpb = bar of the macro predictor (written)

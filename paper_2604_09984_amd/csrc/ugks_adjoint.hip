@@ -471,8 +471,9 @@ __device__ __forceinline__ void rec_values(const Dev& g, double dts, const doubl
   face_coeffs(g, dts, x, c);
 }
 
-__global__ __launch_bounds__(256) void k_adj_face(Dev g, double dts, const double* __restrict__ h,
+__global__ __launch_bounds__(256, 2) void k_adj_face(Dev g, double dts, const double* __restrict__ h,
                                                   const double* __restrict__ b, const double* __restrict__ gW,
+                                                  const double* __restrict__ rec,
                                                   const double* __restrict__ Dbh, const double* __restrict__ Dbb,
                                                   const double* __restrict__ Fb, double* __restrict__ hbar,
                                                   double* __restrict__ bbar, double* __restrict__ gWbar,
@@ -518,33 +519,46 @@ __global__ __launch_bounds__(256) void k_adj_face(Dev g, double dts, const doubl
   double W0[4] = {0, 0, 0, 0};
   double T1, Txx, Tyy, Txy;
   {
-    // pass 1: W0 from the upwind interface data
-    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    // pass 1: velocity moments of the upwind interface data about the shift
+    // sx, sy (the mean velocity of the face's two sides), up to third order
+    // for h and first order for b; W0, q0 and the U-derivative sums of q0
+    // follow from them
+    const double* fr = rec + (size_t)f * NREC;
+    const double sx = fr[R_SX], sy = fr[R_SY];
+    double m[13];
+    for (int i = 0; i < 13; ++i) m[i] = 0.0;
     for (int k = lane; k < nv; k += 64) {
       double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
       double fh, fb;
       upwind(k, wn_exact(vx, vy, ufx, ufy, nx, ny), fh, fb);
-      s0 += w * fh; s1 += w * vx * fh; s2 += w * vy * fh; s3 += w * 0.5 * ((vx * vx + vy * vy) * fh + fb);
+      const double cx = vx - sx, cy = vy - sy;
+      const double a0 = w * fh, ax = a0 * cx, ay = a0 * cy;
+      m[0] += a0; m[1] += ax; m[2] += ay;
+      m[3] += ax * cx; m[4] += ax * cy; m[5] += ay * cy;
+      m[6] += ax * cx * cx; m[7] += ax * cx * cy; m[8] += ax * cy * cy; m[9] += ay * cy * cy;
+      const double b0 = w * fb;
+      m[10] += b0; m[11] += b0 * cx; m[12] += b0 * cy;
     }
-    W0[0] = wave_sum(s0); W0[1] = wave_sum(s1);
-    if (D == 2) { W0[2] = wave_sum(s2); W0[3] = wave_sum(s3); }
-    else W0[2] = wave_sum(s3);
+    for (int i = 0; i < 13; ++i) m[i] = wave_sum(m[i]);
+    const double M0 = m[0], M1x = m[1], M1y = m[2], Mxx = m[3], Mxy = m[4], Myy = m[5];
+    const double Mxxx = m[6], Mxxy = m[7], Mxyy = m[8], Myyy = m[9], B0 = m[10], B1x = m[11], B1y = m[12];
+    W0[0] = M0;
+    W0[1] = M1x + sx * M0;
+    W0[2] = M1y + sy * M0;
+    W0[3] = 0.5 * (Mxx + Myy + 2.0 * (sx * M1x + sy * M1y) + (sx * sx + sy * sy) * M0) + 0.5 * B0;
     double rho, ux, uy, lam;
     prim_d(D, kNxi, W0, rho, ux, uy, lam);
-    // pass 2: heat flux q0 and the sums of its derivative along U
-    double q0x = 0, q0y = 0;
-    T1 = Txx = Tyy = Txy = 0.0;
-    for (int k = lane; k < nv; k += 64) {
-      double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
-      double fh, fb;
-      upwind(k, wn_exact(vx, vy, ufx, ufy, nx, ny), fh, fb);
-      double cx = vx - ux, cy = (D == 2) ? vy - uy : 0.0;
-      double en = (cx * cx + cy * cy) * fh + fb;
-      q0x += w * 0.5 * cx * en; q0y += w * 0.5 * cy * en;
-      T1 += w * en; Txx += w * cx * cx * fh; Tyy += w * cy * cy * fh; Txy += w * cx * cy * fh;
-    }
-    q0x = wave_sum(q0x); q0y = (D == 2) ? wave_sum(q0y) : 0.0;
-    T1 = wave_sum(T1); Txx = wave_sum(Txx); Tyy = wave_sum(Tyy); Txy = wave_sum(Txy);
+    // c = v - U0 = (v - s) - d with d = U0 - s
+    const double dx = ux - sx, dy = uy - sy, d2 = dx * dx + dy * dy;
+    const double dM1 = dx * M1x + dy * M1y;
+    const double q0x = 0.5 * ((Mxxx + Mxyy) - 2.0 * (dx * Mxx + dy * Mxy) + d2 * M1x - dx * (Mxx + Myy) +
+                              2.0 * dx * dM1 - dx * d2 * M0 + B1x - dx * B0);
+    const double q0y = 0.5 * ((Mxxy + Myyy) - 2.0 * (dx * Mxy + dy * Myy) + d2 * M1y - dy * (Mxx + Myy) +
+                              2.0 * dy * dM1 - dy * d2 * M0 + B1y - dy * B0);
+    T1 = (Mxx + Myy) - 2.0 * dM1 + d2 * M0 + B0;
+    Txx = Mxx - 2.0 * dx * M1x + dx * dx * M0;
+    Tyy = Myy - 2.0 * dy * M1y + dy * dy * M0;
+    Txy = Mxy - dx * M1y - dy * M1x + dx * dy * M0;
     double x[kRecIn], c[kRecOut];
     x[0] = rho; x[1] = ux; x[2] = uy; x[3] = lam;
     grad_in(x);
@@ -1416,11 +1430,11 @@ __global__ __launch_bounds__(256) void k_adj_interp(Dev g, int nrow, const int* 
 static inline unsigned nblk(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
 void adj_flux(const Dev& g, double dts, const double* h, const double* b, const double* W, const double* q,
-              const double* gW, const double* Dbh, const double* Dbb, const double* Fb, double* hbar,
-              double* bbar, double* Wbar, double* qbar, double* gWbar, double* fbar, hipStream_t st) {
+              const double* gW, const double* rec, const double* Dbh, const double* Dbb, const double* Fb,
+              double* hbar, double* bbar, double* Wbar, double* qbar, double* gWbar, double* fbar, hipStream_t st) {
   if (g.nface > 0) {
-    hipLaunchKernelGGL(k_adj_face, dim3(nblk(g.nface, 4)), dim3(256), 0, st, g, dts, h, b, gW, Dbh, Dbb, Fb, hbar,
-                       bbar, gWbar, fbar);
+    hipLaunchKernelGGL(k_adj_face, dim3(nblk(g.nface, 4)), dim3(256), 0, st, g, dts, h, b, gW, rec, Dbh, Dbb, Fb,
+                       hbar, bbar, gWbar, fbar);
     hipLaunchKernelGGL(k_adj_wall, dim3(nblk(g.nface, 4)), dim3(256), 0, st, g, dts, h, b, W, q, gW, Dbh, Dbb, Fb,
                        hbar, bbar, Wbar, qbar, gWbar, fbar);
   }

@@ -1284,10 +1284,11 @@ int dcopy_or_zero(void* dst, const void* src, size_t n, hipStream_t st) {
 
 // the flux reverse at (H0, B0, W0, Q0) with divergence bars A_DBH/A_DBB and
 // face-flux bar A_FB: accumulates into A_HB, A_BB, A_WB, A_QB, A_FBAR
-// (s_gW must hold the forward gradients of W0)
+// (s_gW and s_rec must hold the forward gradients of W0 and face records)
 int flux_reverse(ugks_ctx* c, hipStream_t st) {
   if (int rc = dzero(A(c, A_GWB), 8 * (size_t)c->ncell, st)) return rc;
-  adj_flux(c->dev, c->dts, A(c, A_H0), A(c, A_B0), A(c, A_W0), A(c, A_Q0), (const double*)c->s_gW, A(c, A_DBH),
+  adj_flux(c->dev, c->dts, A(c, A_H0), A(c, A_B0), A(c, A_W0), A(c, A_Q0), (const double*)c->s_gW,
+           (const double*)c->s_rec, A(c, A_DBH),
            A(c, A_DBB), A(c, A_FB), A(c, A_HB), A(c, A_BB), A(c, A_WB), A(c, A_QB), A(c, A_GWB), A(c, A_FBAR), st);
   HIPCHK(hipGetLastError());
   return UGKS_OK;
