@@ -722,7 +722,7 @@ int ugks_overset_rows(const ugks_ctx* c, int32_t* nrec, int32_t* nrefill, int32_
   if (!c) return fail(UGKS_E_ARG, "null context");
   if (nrec) *nrec = c->nrec;
   if (nrefill) *nrefill = (int32_t)c->h_rec.size() - c->nrec;
-  if (pending) *pending = c->nref;
+  if (pending) *pending = (c->nref > 0) ? 1 : 0;
   return UGKS_OK;
 }
 

@@ -310,3 +310,45 @@ def test_step_adjoint_finite_difference(case):
     rel = abs(fd - ad) / max(abs(ad), 1e-300)
     say(f"  finite difference {fd:.12e} adjoint {ad:.12e} rel {rel:.2e}")
     assert rel <= 1e-6
+
+
+# --------------------------------------------------------------------------
+# Steps 1-2 with the cells uncovered from holes refilled (after a jump)
+# --------------------------------------------------------------------------
+def test_begin_step_adjoint_with_refill():
+    case = wl.overset_patch(ni_bg=16, npatch=14, half=0.55, nv=8)
+    say("begin-step adjoint with refill", case.name)
+    jump = [(0.0,) * 6, (0.18, 0.3, 0.09, 0.0, 0.0, 0.0)]
+    o, ot, s = Oracle(case), Oracle(case, tangent=True), ugks.Solver(case, ugks.F64)
+    for x in (o, ot, s):
+        x.set_poses(case.poses(0.0))
+        x.assemble(0, 2)
+        x.set_poses(jump)
+        x.assemble(0, 2)
+    nrec, nref, pending = s.overset_rows()
+    assert nref > 0 and pending == 1 and o.refill_count() == nref
+    h, b, W = wl.synthetic_f(case, amp=0.02)
+    q = o.heatflux(h, b, W)
+    dts, _ = o.timesteps()
+    dt = case.dt
+    rng = np.random.default_rng(21)
+    live = o.types() != 0
+    dh = rng.standard_normal(h.shape) * h * 0.1
+    db = rng.standard_normal(b.shape) * b * 0.1
+    dW = rng.standard_normal(W.shape) * 0.01
+    dq = rng.standard_normal(q.shape) * 0.05
+    hd, bd, Wd, qd = dual(h, dh), dual(b, db), dual(W, dW), dual(q, dq)
+    Sh, Sb, Fn = ot.begin_step((dt, 0.0), (dts, 0.0), hd, bd, Wd, qd)
+    idx = o.product_face_index()
+    y = {k: rng.standard_normal(a.shape) * live.reshape((-1,) + (1,) * (a.ndim - 1))
+         for k, a in (("h", h), ("b", b), ("W", W), ("q", q))}
+    field = (o.types() == 1)[:, None]
+    ySh = rng.standard_normal(h.shape) * field
+    ySb = rng.standard_normal(b.shape) * field
+    yF = np.zeros((s.nface, case.nw)); yF[idx] = rng.standard_normal((o.nface, case.nw))
+    lhs = (dot(y["h"], hd[..., 1]) + dot(y["b"], bd[..., 1]) + dot(y["W"], Wd[..., 1]) + dot(y["q"], qd[..., 1])
+           + dot(ySh, Sh[..., 1]) + dot(ySb, Sb[..., 1]) + dot(yF[idx], Fn[:o.nface, :, 1]))
+    out = s.begin_step_adjoint(dt, dev(h), dev(b), dev(W), dev(q), dev(y["h"]), dev(y["b"]), dev(y["W"]),
+                               dev(y["q"]), dev(ySh), dev(ySb), dev(yF), refill=True)
+    rhs = dot(host(out[0]), dh) + dot(host(out[1]), db) + dot(host(out[2]), dW) + dot(host(out[3]), dq)
+    check("begin with refill", lhs, rhs)
