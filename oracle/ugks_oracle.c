@@ -1750,22 +1750,32 @@ int or_assemble(or_case* c, int wrule, int overlap, int* nrec_out) {
   int nnode = 0;
   for (int b = 0; b < c->nblock; b++) nnode += (c->blk[b].ni + 1) * (c->blk[b].nj + 1);
   int8_t* inact = (int8_t*)calloc(nnode > 0 ? nnode : 1, 1);
+  /* every node is classified on its own (OpenMP over the rows of a block,
+     each thread with its own wall-outline buffers) */
   for (int b = 0; b < c->nblock; b++) {
     const blk_t* B = &c->blk[b];
-    for (int j = 0; j <= B->nj; j++)
-      for (int i = 0; i <= B->ni; i++) {
-        real px = node_x(c, b, i, j), py = node_y(c, b, i, j);
-        int off = inside_body(c, b, px, py, bx, by);
-        real da = wall_dist2(c, b, px, py, bx, by);
-        for (int z = 0; z < c->nblock && !off; z++) {
-          if (z == b) continue;
-          int m = containing_cell(c, z, px, py, NULL);
-          if (m < 0 || overset_depth(c, m) < cut) continue;
-          real dz = wall_dist2(c, z, px, py, bx, by);
-          if (dz < da || (dz == da && z > b)) off = 1;
+#pragma omp parallel
+    {
+      real* tx = (real*)malloc(sizeof(real) * maxside);
+      real* ty_ = (real*)malloc(sizeof(real) * maxside);
+#pragma omp for schedule(dynamic, 1)
+      for (int j = 0; j <= B->nj; j++)
+        for (int i = 0; i <= B->ni; i++) {
+          real px = node_x(c, b, i, j), py = node_y(c, b, i, j);
+          int off = inside_body(c, b, px, py, tx, ty_);
+          real da = wall_dist2(c, b, px, py, tx, ty_);
+          for (int z = 0; z < c->nblock && !off; z++) {
+            if (z == b) continue;
+            int m = containing_cell(c, z, px, py, NULL);
+            if (m < 0 || overset_depth(c, m) < cut) continue;
+            real dz = wall_dist2(c, z, px, py, tx, ty_);
+            if (dz < da || (dz == da && z > b)) off = 1;
+          }
+          inact[c->node0[b] + i + (B->ni + 1) * j] = (int8_t)off;
         }
-        inact[c->node0[b] + i + (B->ni + 1) * j] = (int8_t)off;
-      }
+      free(tx);
+      free(ty_);
+    }
   }
   /* 2. cell classes: field (all nodes active), hole (none), boundary */
   int8_t* cls = (int8_t*)malloc(ncell > 0 ? ncell : 1);

@@ -390,3 +390,94 @@ def overset_cylinder(ni_bg: int = 40, nb: int = 40, njb: int = 12, nv: int = 12,
     return Case("ovcyl", 2, 2.0 / 3.0, 0.5, mu_ref_from_kn(kn, 0.5), 0.5, v, v.copy(),
                 (-vmax, vmax, -vmax, vmax), winf, [bg, body], np.tile(winf, (ncell, 1)),
                 dt_over_dts=5.0, motion=motion, overset={"wrule": wrule, "overlap": 2})
+
+
+def rounded_rect_point(phi: float, a: float, b: float, d: float) -> tuple:
+    """Point at polar angle phi on the boundary of the set of points within
+    distance d of the rectangle [-a, a] x [-b, b] (bisection along the ray)."""
+    ux, uy = math.cos(phi), math.sin(phi)
+    lo, hi = 0.0, a + b + d + 1.0
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        px, py = mid * ux, mid * uy
+        dist = math.hypot(max(abs(px) - a, 0.0), max(abs(py) - b, 0.0))
+        if dist > d:
+            hi = mid
+        else:
+            lo = mid
+    return lo * ux, lo * uy
+
+
+def mems_plate(n_bg: int = 256, ni: int = 128, nj: int = 64, nv: int = 48, kn: float = 0.1,
+               wrule: int = 1) -> Case:
+    """Thermal MEMS plate: a 1 x 0.1 plate, 10 % hotter than the gas, heaving
+    as y = 0.2 sin(2 pi t / T) (T = 10) inside a closed box [-2, 2]^2 with
+    diffuse walls at T0; background 256 x 256 Cartesian cells, body-fitted
+    O-mesh 128 x 64 extending 0.25 from the plate (rays through the points of
+    the ellipse of the plate's half-widths, geometric spacing), overset with
+    bilinear donors; 48 x 48 velocities on [-6, 6]^2; gas at rest (rho 1,
+    RT 1/2); dt = T/400."""
+    bg = cartesian_block(n_bg, n_bg, -2.0, 2.0, -2.0, 2.0, (WALL, WALL, WALL, WALL))
+    a, bh = 0.5, 0.05
+    offs = geometric_radii(0.0, 0.25, nj, 1.05)
+    shape = lambda t, r: rounded_rect_point(math.atan2(bh * math.sin(t), a * math.cos(t)), a, bh, r)
+    body = o_block(ni, nj, offs, shape=shape, bc=(PERIODIC, PERIODIC, WALL, NONE),
+                   rtw=(0.5, 0.5, 0.55, 0.5), body=True)
+    v = uniform_points(nv, -6.0, 6.0)
+    winf = cons(2, 1.0, [0.0, 0.0], 0.5)
+    ncell = bg.ncell + body.ncell
+    period = 10.0
+    w = 2.0 * math.pi / period
+
+    def motion(t):
+        return [(0.0, 0.0, 0.0, 0.0, 0.0, 0.0),
+                (0.0, 0.2 * math.sin(w * t), 0.0, 0.0, 0.2 * w * math.cos(w * t), 0.0)]
+    return Case("mems_plate", 2, 2.0 / 3.0, 0.5, mu_ref_from_kn(kn, 0.5), 0.5, v, v.copy(),
+                (-6.0, 6.0, -6.0, 6.0), winf, [bg, body], np.tile(winf, (ncell, 1)),
+                dt=period / 400.0, n_inner=10, n_phys=20, motion=motion,
+                overset={"wrule": wrule, "overlap": 2})
+
+
+def two_body(nx: int = 512, ny: int = 256, ni: int = 128, nj: int = 96, nv: int = 100, kn: float = 1e-3,
+             mach: float = 6.0) -> Case:
+    """Two-body separation: background [-3, 13] x [-4, 4] (512 x 256,
+    far field); a circle of diameter 1 at the origin and one of diameter 0.3
+    at (0.2, 0.75), each inside a 128 x 96 O-mesh (outer radii 1.5 and 0.6);
+    the small body moves as dy = t^2 / 2, dtheta = t / 5; isothermal walls at
+    the free-stream temperature; Ma 6 along +x; 100 x 100 velocities on
+    [-20, 20]^2; dt = 10 dt_s."""
+    bg = cartesian_block(nx, ny, -3.0, 13.0, -4.0, 4.0, (FARFIELD, FARFIELD, FARFIELD, FARFIELD))
+    big = o_block(ni, nj, geometric_radii(0.5, 1.5, nj, 1.02), bc=(PERIODIC, PERIODIC, WALL, NONE),
+                  rtw=(0.5, 0.5, 0.5, 0.5), body=True)
+    small = o_block(ni, nj, geometric_radii(0.15, 0.6, nj, 1.02), centre=(0.2, 0.75),
+                    bc=(PERIODIC, PERIODIC, WALL, NONE), rtw=(0.5, 0.5, 0.5, 0.5), body=True)
+    rt = 0.5
+    u = mach * math.sqrt(5.0 / 3.0 * rt)
+    winf = cons(2, 1.0, [u, 0.0], rt)
+    v = uniform_points(nv, -20.0, 20.0)
+    ncell = bg.ncell + big.ncell + small.ncell
+
+    def motion(t):
+        return [(0.0,) * 6, (0.0,) * 6, (0.0, 0.5 * t * t, 0.2 * t, 0.0, t, 0.2)]
+    return Case("two_body", 2, 2.0 / 3.0, 0.5, mu_ref_from_kn(kn, 0.5), rt, v, v.copy(),
+                (-20.0, 20.0, -20.0, 20.0), winf, [bg, big, small], np.tile(winf, (ncell, 1)),
+                dt_over_dts=10.0, n_inner=15, n_phys=20, motion=motion, overset={"wrule": 0, "overlap": 2})
+
+
+def batch_cases(count: int = 64, seed: int = SEED) -> list:
+    """Seeded batch of ragged cavity / plate cases: case i has n x n cells
+    (n uniform in 32..128) and m x m velocities on [-5 sqrt(RT0), 5 sqrt(RT0)]^2
+    (m uniform in 24..64), Kn = 10^U(-4, 1), an even case is a lid-driven
+    cavity and an odd one a plate (periodic in x, moving top wall), wall speed
+    U(0.1, 1) times sqrt(2 RT0); dt = 10 dt_s."""
+    rng = np.random.default_rng(seed + 97)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(32, 129))
+        m = int(rng.integers(24, 65))
+        kn = float(10.0 ** rng.uniform(-4.0, 1.0))
+        lid = float(rng.uniform(0.1, 1.0))
+        c = cavity(n, m, kn=kn, lid=lid, periodic_x=(i % 2 == 1))
+        c.name = f"batch{i:02d}_{c.name}_{n}x{n}_v{m}"
+        out.append(c)
+    return out
