@@ -60,6 +60,7 @@ def _bind(L, S):
     L.or_flux.argtypes = [C.c_void_p, S, D, D, D, D, D, D, D, D]
     L.or_interp.argtypes = [C.c_void_p, D, D, D, D]
     L.or_begin_step.argtypes = [C.c_void_p, S, S, D, D, D, D, D, D, D]
+    L.or_begin_step_cells.argtypes = [C.c_void_p, S, S, D, D, D, D, C.c_int, I, D, D, D]
     L.or_pseudo_step.argtypes = [C.c_void_p, S, S, D, D, D, D, D, D, D, D, D, D, D]
     L.or_macro_lusgs.argtypes = [C.c_void_p, S, D, D, D, D, D, D, D]
     L.or_micro_lusgs.argtypes = [C.c_void_p, S, D, D, D, D, D, D, D, D, D]
@@ -321,6 +322,19 @@ class Oracle:
         self.L.or_begin_step(self.ptr, self._s(dt), self._s(dts), _d(h), _d(b), _d(W), _d(q),
                              _d(Sh), _d(Sb), _d(Fn))
         return Sh, Sb, Fn
+
+    def begin_step_cells(self, dt, dts, h, b, W, q, cells):
+        """Steps 1-2 at the listed cells only (h, b, W, q interpolated in
+        place over the whole field as in begin_step): rows of Sh and Sb
+        [ns][nv] and the macro flux of each face slot of each cell
+        [ns][4][nw]."""
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        ns = len(cells)
+        Sh = self._z(max(ns, 1), self.nv); Sb = self._z(max(ns, 1), self.nv)
+        Fc = self._z(max(ns, 1), 4, self.nw)
+        self.L.or_begin_step_cells(self.ptr, self._s(dt), self._s(dts), _d(h), _d(b), _d(W), _d(q), ns,
+                                   _i(cells), _d(Sh), _d(Sb), _d(Fc))
+        return Sh[:ns], Sb[:ns], Fc[:ns]
 
     def pseudo_step(self, dt, dts, dtp, h, b, W, Wn, q, Sh, Sb, Fn, F=None):
         """One inner iteration in place; F (optional, [nface][nw]) receives the

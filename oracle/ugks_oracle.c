@@ -1085,6 +1085,40 @@ static void face_flux_k(const flux_ctx* X, int f, int k, real* Fh, real* Fb) {
   *Fb = wn * Ib / X->dts;
 }
 
+/* macro flux of face f (Eq. macroscopicFlux): velocity sums of Psi times
+   the time-integrated interface flux */
+static void face_macro(const flux_ctx* X, int f, real* Fm) {
+  const or_case* c = X->c;
+  for (int k = 0; k < c->nv; k++) {
+    real fh, fb;
+    face_flux_k(X, f, k, &fh, &fb);
+    real vx = c->vk_x[k], vy = c->vk_y[k], w = c->wk[k];
+    Fm[0] += w * fh;
+    Fm[1] += w * vx * fh;
+    if (c->dim == 2) Fm[2] += w * vy * fh;
+    Fm[c->dim + 1] += w * 0.5 * ((vx * vx + vy * vy) * fh + fb);
+  }
+}
+
+/* flux divergence of cell n, D = -(1/|Omega|) sum_f sigma S F, zero for a
+   cell that is not a field cell */
+static void cell_div(const flux_ctx* X, int n, real* dh, real* db) {
+  const or_case* c = X->c;
+  for (int k = 0; k < c->nv; k++) { dh[k] = 0.0; db[k] = 0.0; }
+  if (c->type[n] != OR_FIELD) return;
+  for (int s = 0; s < 4; s++) {
+    int f = c->cface[4 * n + s];
+    if (f < 0) continue;
+    real sg = (real)c->csign[4 * n + s], S = c->face[f].S;
+    for (int k = 0; k < c->nv; k++) {
+      real fh, fb;
+      face_flux_k(X, f, k, &fh, &fb);
+      dh[k] -= sg * S * fh / c->vol[n];
+      db[k] -= sg * S * fb / c->vol[n];
+    }
+  }
+}
+
 static void cell_grad_W(const or_case* c, const real* W, real* gW) {
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < c->ncell; n++) {
@@ -1109,15 +1143,7 @@ void or_flux(const or_case* c, real dts, const real* h, const real* b,
 #pragma omp parallel for schedule(dynamic, 4)
   for (int f = 0; f < c->nface; f++) {
     real Fm[4] = {0, 0, 0, 0};
-    for (int k = 0; k < c->nv; k++) {
-      real fh, fb;
-      face_flux_k(&X, f, k, &fh, &fb);
-      real vx = c->vk_x[k], vy = c->vk_y[k], w = c->wk[k];
-      Fm[0] += w * fh;
-      Fm[1] += w * vx * fh;
-      if (c->dim == 2) Fm[2] += w * vy * fh;
-      Fm[c->dim + 1] += w * 0.5 * ((vx * vx + vy * vy) * fh + fb);
-    }
+    face_macro(&X, f, Fm);
     for (int m = 0; m < c->nw; m++) F[(size_t)f * c->nw + m] = Fm[m];
     if (wall) {
       real* o = wall + (size_t)f * (1 + c->nw);
@@ -1130,23 +1156,8 @@ void or_flux(const or_case* c, real dts, const real* h, const real* b,
   }
   /* divergence, gathered per cell: D = -(1/|Omega|) sum_f sigma S F */
 #pragma omp parallel for schedule(dynamic, 4)
-  for (int n = 0; n < c->ncell; n++) {
-    real* dh = Dh + (size_t)n * c->nv;
-    real* db = Db + (size_t)n * c->nv;
-    for (int k = 0; k < c->nv; k++) { dh[k] = 0.0; db[k] = 0.0; }
-    if (c->type[n] != OR_FIELD) continue;
-    for (int s = 0; s < 4; s++) {
-      int f = c->cface[4 * n + s];
-      if (f < 0) continue;
-      real sg = (real)c->csign[4 * n + s], S = c->face[f].S;
-      for (int k = 0; k < c->nv; k++) {
-        real fh, fb;
-        face_flux_k(&X, f, k, &fh, &fb);
-        dh[k] -= sg * S * fh / c->vol[n];
-        db[k] -= sg * S * fb / c->vol[n];
-      }
-    }
-  }
+  for (int n = 0; n < c->ncell; n++)
+    cell_div(&X, n, Dh + (size_t)n * c->nv, Db + (size_t)n * c->nv);
   free(X.gW);
   free(X.rec);
 }
@@ -1200,7 +1211,29 @@ static void fplus(const or_case* c, real rho, const real* u, real lam, const rea
   *bp = B + Bs;
 }
 
-/* Steps 1-2: S = f^n/dt + r^n/2, r^n = D^n + (f+^n - f^n)/tau^n (Eq. residual_macro_n) */
+/* S = f^n/dt + r^n/2 of cell n, r^n = D^n + (f+^n - f^n)/tau^n
+   (Eq. residual_macro_n); h, b, dh, db, sh, sb are the cell's rows; zero
+   outside the field cells */
+static void cell_source(const or_case* c, real dt, int n, const real* h, const real* b,
+                        const real* W, const real* q, const real* dh, const real* db,
+                        real* sh, real* sb) {
+  if (c->type[n] != OR_FIELD) {
+    for (int k = 0; k < c->nv; k++) { sh[k] = 0.0; sb[k] = 0.0; }
+    return;
+  }
+  real rho, u[2], lam, qq[2] = {0, 0};
+  prim(c, W + (size_t)n * c->nw, &rho, u, &lam);
+  for (int i = 0; i < c->dim; i++) qq[i] = q[(size_t)n * c->dim + i];
+  real it = inv_tau(c, rho, lam);
+  for (int k = 0; k < c->nv; k++) {
+    real hp, bp;
+    fplus(c, rho, u, lam, qq, k, &hp, &bp);
+    sh[k] = h[k] / dt + 0.5 * (dh[k] + (hp - h[k]) * it);
+    sb[k] = b[k] / dt + 0.5 * (db[k] + (bp - b[k]) * it);
+  }
+}
+
+/* Steps 1-2: S = f^n/dt + r^n/2 at every cell, and the level-n face flux */
 void or_begin_step(or_case* c, real dt, real dts, real* h, real* b,
                    real* W, real* q, real* Sh, real* Sb, real* Fn) {
   size_t N = (size_t)c->ncell * c->nv;
@@ -1214,20 +1247,50 @@ void or_begin_step(or_case* c, real dt, real dts, real* h, real* b,
   or_flux(c, dts, h, b, W, q, Dh, Db, Fn, NULL);
 #pragma omp parallel for schedule(static)
   for (int n = 0; n < c->ncell; n++) {
-    real rho, u[2], lam, qq[2] = {0, 0};
-    prim(c, W + (size_t)n * c->nw, &rho, u, &lam);
-    for (int i = 0; i < c->dim; i++) qq[i] = q[(size_t)n * c->dim + i];
-    real it = inv_tau(c, rho, lam);
-    for (int k = 0; k < c->nv; k++) {
-      size_t o = (size_t)n * c->nv + k;
-      if (c->type[n] != OR_FIELD) { Sh[o] = 0.0; Sb[o] = 0.0; continue; }
-      real hp, bp;
-      fplus(c, rho, u, lam, qq, k, &hp, &bp);
-      Sh[o] = h[o] / dt + 0.5 * (Dh[o] + (hp - h[o]) * it);
-      Sb[o] = b[o] / dt + 0.5 * (Db[o] + (bp - b[o]) * it);
-    }
+    size_t o = (size_t)n * c->nv;
+    cell_source(c, dt, n, h + o, b + o, W, q, Dh + o, Db + o, Sh + o, Sb + o);
   }
   free(Dh); free(Db);
+}
+
+/* Steps 1-2 at a sample of cells only: the same interpolation into the
+   rows of the donor table (over the whole field), then for each listed cell
+   its flux divergence and S (rows [ns][nv]) and the macro flux of each of its
+   four face slots (Fc [ns][4][nw], zero where a slot has no face).  The
+   face records are formed only for the faces of the listed cells, so a
+   sample of a large case costs little beyond the interpolation. */
+void or_begin_step_cells(or_case* c, real dt, real dts, real* h, real* b, real* W, real* q,
+                         int ns, const int* cells, real* Sh, real* Sb, real* Fc) {
+  interp_rows(c, c->nrec, c->nref, h, b, W, q);
+  c->nref = 0;
+  interp_rows(c, 0, c->nrec, h, b, W, q);
+  flux_ctx X = {c, h, b, W, q, NULL, NULL, dts};
+  X.gW = (real*)malloc(sizeof(real) * 2 * c->nw * (size_t)c->ncell);
+  X.rec = (frec_t*)calloc(c->nface > 0 ? c->nface : 1, sizeof(frec_t));
+  cell_grad_W(c, W, X.gW);
+  for (int i = 0; i < ns; i++)
+    for (int s = 0; s < 4; s++) {
+      int f = c->cface[4 * cells[i] + s];
+      if (f >= 0) face_record(&X, f);
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int i = 0; i < ns; i++) {
+    int n = cells[i];
+    real* dh = (real*)malloc(sizeof(real) * 2 * (size_t)c->nv);
+    real* db = dh + c->nv;
+    cell_div(&X, n, dh, db);
+    cell_source(c, dt, n, h + (size_t)n * c->nv, b + (size_t)n * c->nv, W, q, dh, db,
+                Sh + (size_t)i * c->nv, Sb + (size_t)i * c->nv);
+    for (int s = 0; s < 4; s++) {
+      real Fm[4] = {0, 0, 0, 0};
+      int f = c->cface[4 * n + s];
+      if (f >= 0) face_macro(&X, f, Fm);
+      for (int m = 0; m < c->nw; m++) Fc[((size_t)i * 4 + s) * c->nw + m] = Fm[m];
+    }
+    free(dh);
+  }
+  free(X.gW);
+  free(X.rec);
 }
 
 /* ALE Euler flux F_E(W; n, U) = (rho th, rho V th + p n, rho E th + p V.n),

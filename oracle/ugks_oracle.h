@@ -131,6 +131,11 @@ void or_interp(const or_case* c, real* h, real* b, real* W, real* q);
 /* Steps 1-2: source S = f^n/dt + r^n/2 and the level-n face flux Fn */
 void or_begin_step(or_case* c, real dt, real dts, real* h, real* b,
                    real* W, real* q, real* Sh, real* Sb, real* Fn);
+/* Steps 1-2 at listed cells only (same interpolation over the whole field):
+   Sh, Sb [ns][nv] and the macro flux of each face slot of each listed cell,
+   Fc [ns][4][nw] (zero where a slot has no face) */
+void or_begin_step_cells(or_case* c, real dt, real dts, real* h, real* b, real* W, real* q,
+                         int ns, const int* cells, real* Sh, real* Sb, real* Fc);
 /* Steps 3-7, one inner iteration; resid[nw] = L2 norm of R over field cells;
    Fout[nface][nw] (may be NULL) receives the face macro flux of Step 3 */
 void or_pseudo_step(const or_case* c, real dt, real dts, const real* dtp,
