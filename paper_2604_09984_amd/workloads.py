@@ -456,35 +456,37 @@ def mems_plate(n_bg: int = 256, ni: int = 128, nj: int = 64, nv: int = 48, kn: f
 
 
 def two_body(nx: int = 512, ny: int = 256, ni: int = 128, nj: int = 96, nv: int = 100, kn: float = 1e-3,
-             mach: float = 6.0) -> Case:
+             mach: float = 6.0, vmax: float = 20.0) -> Case:
     """Two-body separation: background [-3, 13] x [-4, 4] (512 x 256,
     far field); a circle of diameter 1 at the origin inside a 128 x 96 O-mesh
     out to radius 1.5 (radial ratio 1.02), and one of diameter 0.3 at
     (0.5, 2.55) inside a 128 x 96 O-mesh out to radius 1.0 (ratio 1.03); the
     small body moves as dy = t^2 / 2, dtheta = t / 5 about its centre;
     isothermal walls at the free-stream temperature; Ma 6 along +x;
-    100 x 100 velocities on [-20, 20]^2; dt = 10 dt_s.
+    100 x 100 velocities on [-vmax, vmax]^2 (vmax = 20); dt = 10 dt_s.
 
     The two body meshes overlap the background only: where two body-fitted
     meshes of like spacing overlap, the wall-distance rule switches both at
     the same line and leaves receptors without a field donor.  The outer
     spacing of each O-mesh is close to the background's, so that its
-    receptors fall in field cells of the background at any pose."""
+    receptors fall in field cells of the background at any pose (with
+    fewer radial cells the radial ratios grow so that the outer spacing
+    stays the same)."""
     bg = cartesian_block(nx, ny, -3.0, 13.0, -4.0, 4.0, (FARFIELD, FARFIELD, FARFIELD, FARFIELD))
-    big = o_block(ni, nj, geometric_radii(0.5, 1.5, nj, 1.02), bc=(PERIODIC, PERIODIC, WALL, NONE),
+    big = o_block(ni, nj, geometric_radii(0.5, 1.5, nj, 1.02 ** (96 / nj)), bc=(PERIODIC, PERIODIC, WALL, NONE),
                   rtw=(0.5, 0.5, 0.5, 0.5), body=True)
-    small = o_block(ni, nj, geometric_radii(0.15, 1.0, nj, 1.03), centre=(0.5, 2.55),
+    small = o_block(ni, nj, geometric_radii(0.15, 1.0, nj, 1.03 ** (96 / nj)), centre=(0.5, 2.55),
                     bc=(PERIODIC, PERIODIC, WALL, NONE), rtw=(0.5, 0.5, 0.5, 0.5), body=True)
     rt = 0.5
     u = mach * math.sqrt(5.0 / 3.0 * rt)
     winf = cons(2, 1.0, [u, 0.0], rt)
-    v = uniform_points(nv, -20.0, 20.0)
+    v = uniform_points(nv, -vmax, vmax)
     ncell = bg.ncell + big.ncell + small.ncell
 
     def motion(t):
         return [(0.0,) * 6, (0.0,) * 6, (0.0, 0.5 * t * t, 0.2 * t, 0.0, t, 0.2)]
     return Case("two_body", 2, 2.0 / 3.0, 0.5, mu_ref_from_kn(kn, 0.5), rt, v, v.copy(),
-                (-20.0, 20.0, -20.0, 20.0), winf, [bg, big, small], np.tile(winf, (ncell, 1)),
+                (-vmax, vmax, -vmax, vmax), winf, [bg, big, small], np.tile(winf, (ncell, 1)),
                 dt_over_dts=10.0, n_inner=15, n_phys=20, motion=motion, overset={"wrule": 0, "overlap": 2})
 
 
