@@ -39,7 +39,8 @@ class Run:
     iterations, objective J, on the library; and the same sequence on the
     oracle's tangent build."""
 
-    def __init__(self, case, n_phys, n_inner, body, sides, seed=3):
+    def __init__(self, case, n_phys, n_inner, body, sides, seed=3, c=(1.0, 0.3, -0.2), yh_scale=0.1,
+                 times=None):
         self.case, self.n_phys, self.n_inner, self.body, self.sides = case, n_phys, n_inner, body, sides
         self.s = ugks.Solver(case, ugks.F64)
         self.o = Oracle(case)
@@ -48,10 +49,10 @@ class Run:
         self.h0, self.b0, self.W0 = h, b, W
         self.q0 = self.o.heatflux(h, b, W)  # held fixed (not a function of h0)
         rng = np.random.default_rng(seed + 1)
-        self.yh = rng.standard_normal(h.shape) * 0.1
-        self.c = (1.0, 0.3, -0.2)  # weights of energy flux, x force, y force
+        self.yh = rng.standard_normal(h.shape) * yh_scale
+        self.c = c  # weights of energy flux, x force, y force
         self.dt_over = case.dt_over_dts
-        self.times = [0.05 * (k + 1) for k in range(n_phys)]
+        self.times = [0.05 * (k + 1) for k in range(n_phys)] if times is None else list(times)
 
     def setup_fn(self, k, types_prev):
         """Restores step k's geometry: the kinds before its assembly, the
@@ -214,3 +215,76 @@ def test_autograd_gradient_matches_finite_differences():
             else:
                 fd = (float(R.gpu(U, Pp)) - float(R.gpu(U, Pm))) / (2 * eps)
             _close(fd, float(G[i]), 1e-6, what)
+
+
+@pytest.mark.timeout(400)
+def test_two_body_lift_gradient():
+    """The two-body separation, reduced (96 x 48 background, two 24 x 10
+    O-meshes, 16 x 16 velocities on [-6, 6]^2): gradient of the small body's
+    lift (y force on its wall, summed over the steps) through 20 checkpointed
+    physical steps with re-assembly at each, with respect to the small body's
+    velocity and wall temperature; against the oracle's tangent build and
+    central differences of the HIP forward path.  Ma 0.5 and Kn 0.1 at this
+    resolution: an impulsive start at Ma 6 empties the thin lee-side wall
+    cells within a few large implicit steps."""
+    case = wl.two_body(nx=96, ny=48, ni=24, nj=10, nv=16, vmax=6.0, mach=0.5, kn=0.1)
+    say("two-body lift gradient", case.ncell * case.nv, "pairs, 20 physical steps")
+    R = Run(case, n_phys=20, n_inner=2, body=2, sides=(2,), c=(0.0, 0.0, 1.0), yh_scale=0.0,
+            times=[0.02 * (k + 1) for k in range(20)])
+    U, rt = _params(R)
+    Ug = U.clone().requires_grad_(True)
+    rtg = rt.clone().requires_grad_(True)
+    J = R.gpu(Ug, rtg)
+    gU, gR = torch.autograd.grad(J, [Ug, rtg])
+    nb = len(case.blocks)
+    dU = np.zeros((nb, 2)); dU[2, 1] = 1.0
+    Jv, Jd = R.oracle(U, rt, dU=dU)
+    _close(Jv, float(J), 1e-9, "lift")
+    _close(Jd, float(gU[2, 1]), 1e-8, "dlift/dU_y")
+    dU = np.zeros((nb, 2)); dU[2, 0] = 1.0
+    _, Jd = R.oracle(U, rt, dU=dU)
+    _close(Jd, float(gU[2, 0]), 1e-8, "dlift/dU_x")
+    drt = np.zeros((nb, 4)); drt[2, 2] = 1.0
+    _, Jd = R.oracle(U, rt, drt=drt)
+    _close(Jd, float(gR[2, 2]), 1e-8, "dlift/dRTw")
+    eps = 1e-6
+    with torch.no_grad():
+        for what, i in (("U_y", (2, 1)), ("RTw", (2, 2))):
+            P = U if what == "U_y" else rt
+            Pp, Pm = P.clone(), P.clone()
+            Pp[i] += eps; Pm[i] -= eps
+            if P is U:
+                fd = (float(R.gpu(Pp, rt)) - float(R.gpu(Pm, rt))) / (2 * eps)
+            else:
+                fd = (float(R.gpu(U, Pp)) - float(R.gpu(U, Pm))) / (2 * eps)
+            _close(fd, float((gU if P is U else gR)[i]), 1e-6, "finite difference " + what)
+
+
+@pytest.mark.timeout(300)
+def test_batch_cases_wall_heat_flux_gradient():
+    """The adjoint of the wall heat flux (energy flux through the moving top
+    wall, summed over two checkpointed physical steps of two inner
+    iterations) for the two smallest cases of the seeded 64-case batch, with
+    respect to the top wall's temperature and the initial distribution,
+    against the oracle's tangent build."""
+    cases = wl.batch_cases(64)
+    pairs = [c.ncell * c.nv for c in cases]
+    for i in np.argsort(pairs, kind="stable")[:2]:
+        case = cases[int(i)]
+        say("batch case heat-flux gradient", case.name)
+        R = Run(case, n_phys=2, n_inner=2, body=0, sides=(3,), c=(1.0, 0.0, 0.0), yh_scale=0.0)
+        U, rt = _params(R)
+        rtg = rt.clone().requires_grad_(True)
+        h0 = dev(R.h0).requires_grad_(True)
+        J = R.gpu(U, rtg, h0=h0)
+        gR, gh = torch.autograd.grad(J, [rtg, h0])
+        nb = len(case.blocks)
+        drt = np.zeros((nb, 4)); drt[0, 3] = 1.0
+        Jv, Jd = R.oracle(U, rt, drt=drt)
+        _close(Jv, float(J), 1e-9, "heat flux")
+        _close(Jd, float(gR[0, 3]), 1e-8, "d/dRTw")
+        rng = np.random.default_rng(int(i))
+        dh = rng.standard_normal(R.h0.shape) * R.h0 * 0.1
+        _, Jd = R.oracle(U, rt, dh0=dh)
+        _close(Jd, float((gh * dev(dh)).sum()), 1e-8, "d/dh0 . v")
+        R.s.close()

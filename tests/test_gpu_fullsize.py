@@ -215,3 +215,59 @@ def test_two_body_full_size_sampled(two_body_ref, prec, tol):
     assert np.all(np.isfinite(r)) and np.all(np.isfinite(Wh)) and Wh[:, 0].min() > 0
     assert bool(torch.isfinite(h).all())
     s.close()
+
+
+# ----------------------------------------------------------------------------
+# The 64-case batch (ragged cavities and plates, 0.97 G pairs in all): every
+# case advanced by the batch graph equals its own captured-graph step bit for
+# bit, and three cases (the smallest, the median and the largest) equal the
+# oracle's Steps 1-2 and one inner iteration.
+
+@pytest.fixture(scope="module")
+def batch_ref():
+    cases = wl.batch_cases(64)
+    pairs = np.array([c.ncell * c.nv for c in cases])
+    order = np.argsort(pairs, kind="stable")
+    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    refs = {i: _oracle_step(cases[i], _perturbed(cases[i]), 0.0) for i in pick}
+    return cases, refs, int(pairs.sum())
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("prec,tol", [(ugks.F32, 1e-5), (ugks.F64, 1e-10)], ids=["f32", "f64"])
+def test_batch_full_size(batch_ref, prec, tol):
+    cases, refs, total = batch_ref
+    say("full-size batch", len(cases), "cases,", total, "pairs,", "f64" if prec == ugks.F64 else "f32")
+    dt_t = torch.float64 if prec == ugks.F64 else torch.float32
+    solvers = [ugks.Solver(c, prec) for c in cases]
+    dts, states = [], []
+    for i, (c, s) in enumerate(zip(cases, solvers)):
+        if i in refs:
+            x = refs[i]["inputs"]
+            h, b, W, q = dev(x["h"], dt_t), dev(x["b"], dt_t), dev(x["W"]), dev(x["q"])
+        else:
+            h, b, W, q = s.init_state()
+        d, _ = s.timesteps()
+        dt = c.dt_over_dts * d
+        Wn = W.clone()
+        Sh, Sb, Fn = s.begin_step(dt, h, b, W, q)
+        s.autotune(dt, 1, h, b, W, Wn, q, Sh, Sb, Fn)
+        dts.append(dt)
+        states.append([h, b, W, Wn, q, Sh, Sb, Fn])
+    own = [[t.clone() for t in st] for st in states]
+    batch = ugks.Batch(solvers)
+    batch.step(dts, 1, states)
+    for s, st, dt in zip(solvers, own, dts):
+        s.step_graph(dt, 1, *st)
+    torch.cuda.synchronize()
+    for i in range(len(cases)):
+        assert all(torch.equal(a, b) for a, b in zip(states[i][:5], own[i][:5])), cases[i].name
+    for i, ref in refs.items():
+        f = ref["live"]
+        out = ref["out"]
+        e = [rel_l2(host(t)[f], out[k][f]) for k, t in zip("hbW", states[i][:3])]
+        say(" ", cases[i].name, "rel L2 h b W", e)
+        assert max(e) <= tol
+    batch.close()
+    for s in solvers:
+        s.close()
