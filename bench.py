@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10, help="untimed pseudo-iterations")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle pseudo-iterations (0: skip)")
     ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--workload-steps", type=int, default=5,
+                    help="pseudo-iterations timed on each of the other workloads (0: skip)")
     ap.add_argument("--nvx", type=int, default=64)
     ap.add_argument("--adjoint-calls", type=int, default=3,
                     help="timed reverse passes of one pseudo-iteration (FP64; 0: skip)")
@@ -124,6 +126,91 @@ def run_gpu(case, prec_name, steps, warmup, adjoint_calls=0):
     out["h"] = h.to(torch.float64).cpu()
     s.close()
     return out
+
+
+def time_workload(case, prec_name, iters, t_pose=0.0):
+    """One workload at its full size: the state at its initial Maxwellian
+    after Steps 1-2 (moving overset: the pose at t_pose assembled first),
+    launch shapes autotuned, then `iters` pseudo-iterations replayed from
+    one captured graph and timed (wall clock around the replay)."""
+    import torch
+    from paper_2604_09984_amd import ugks
+    prec = ugks.F64 if prec_name == "f64" else ugks.F32
+    s = ugks.Solver(case, prec)
+    out = {"prec": prec_name}
+    if case.overset is not None:
+        s.set_poses(case.poses(t_pose))
+        t0 = time.perf_counter()
+        s.assemble(case.overset["wrule"], case.overset["overlap"])
+        out["assembly_ms"] = round(1e3 * (time.perf_counter() - t0), 2)
+    dts, _ = s.timesteps()
+    dt = case.dt if case.dt is not None else case.dt_over_dts * dts
+    h, b, W, q = s.init_state()
+    Wn = W.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Sh, Sb, Fn = s.begin_step(dt, h, b, W, q)
+    torch.cuda.synchronize()
+    out["begin_step_ms"] = round(1e3 * (time.perf_counter() - t0), 3)
+    tuning, _ = s.autotune(dt, 1, h, b, W, Wn, q, Sh, Sb, Fn)
+    s.step_graph(dt, iters, h, b, W, Wn, q, Sh, Sb, Fn)  # capture, warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step_graph(dt, iters, h, b, W, Wn, q, Sh, Sb, Fn)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / iters
+    pairs = int((s.types() == 1).sum()) * s.nv
+    out.update(pairs=pairs, pseudo_steps=iters, ms_per_pseudo_step=round(ms, 4), value=pairs / (ms * 1e-3),
+               launch_shapes=dict(zip(("kc_max", "rg_eq", "rg_flux"), tuning)))
+    s.close()
+    del h, b, W, Wn, q, Sh, Sb, Fn
+    torch.cuda.empty_cache()
+    return out
+
+
+def time_batch(count, prec_name, iters):
+    """The seeded batch of ragged cavity / plate cases advanced together from
+    one captured graph (per-case launch shapes autotuned first), against the
+    same cases advanced one after another, each from its own graph."""
+    import torch
+    from paper_2604_09984_amd import ugks, workloads as wl
+    prec = ugks.F64 if prec_name == "f64" else ugks.F32
+    cases = wl.batch_cases(count)
+    solvers = [ugks.Solver(c, prec) for c in cases]
+    dts, states = [], []
+    for c, s in zip(cases, solvers):
+        d, _ = s.timesteps()
+        dt = c.dt_over_dts * d
+        h, b, W, q = s.init_state()
+        Wn = W.clone()
+        Sh, Sb, Fn = s.begin_step(dt, h, b, W, q)
+        s.autotune(dt, 1, h, b, W, Wn, q, Sh, Sb, Fn)
+        dts.append(dt)
+        states.append([h, b, W, Wn, q, Sh, Sb, Fn])
+    batch = ugks.Batch(solvers)
+    batch.step(dts, iters, states)  # capture, warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(dts, iters, states)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / iters
+    for s, st, dt in zip(solvers, states, dts):
+        s.step_graph(dt, iters, *st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, st, dt in zip(solvers, states, dts):
+        s.step_graph(dt, iters, *st)
+    torch.cuda.synchronize()
+    ms_seq = 1e3 * (time.perf_counter() - t0) / iters
+    pairs = sum(int((s.types() == 1).sum()) * s.nv for s in solvers)
+    batch.close()
+    for s in solvers:
+        s.close()
+    del states
+    torch.cuda.empty_cache()
+    return {"prec": prec_name, "cases": count, "pairs": pairs, "pseudo_steps": iters,
+            "ms_per_pseudo_step": round(ms, 4), "value": pairs / (ms * 1e-3),
+            "sequential_ms_per_pseudo_step": round(ms_seq, 4)}
 
 
 def copy_calibration(gib):
@@ -247,6 +334,20 @@ def main():
                                        "reverse pass (vector-Jacobian product w.r.t. f, W, q, S, Fn, block "
                                        "velocity and wall temperature)"}
     line["finite"] = r64["finite"] and (r32 is None or r32["finite"])
+    if args.workload_steps > 0:
+        # the other workloads at their full sizes (same metric, pair-updates/s)
+        k = args.workload_steps
+        wk = {}
+        wk["sod_1d_f64"] = time_workload(wl.sod_1d(), "f64", 10 * k)
+        for kn in (0.1, 1.0):
+            plate = wl.mems_plate(kn=kn)
+            for p in ("f32", "f64"):
+                wk[f"mems_plate_kn{kn:g}_{p}"] = time_workload(plate, p, k, t_pose=plate.dt)
+        tb = wl.two_body()
+        for p in ("f32", "f64"):
+            wk[f"two_body_{p}"] = time_workload(tb, p, k, t_pose=0.25)
+        wk["batch64_f32"] = time_batch(64, "f32", k)
+        line["workloads"] = wk
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
     print(json.dumps(line), flush=True)

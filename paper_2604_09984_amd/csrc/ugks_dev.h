@@ -109,7 +109,7 @@ __device__ __host__ inline void prim_of(const Dev& g, const double* W, double& r
 }
 
 // positive density and internal energy
-__device__ __host__ inline bool physical_state(int dim, const double* W) {
+__device__ __host__ __forceinline__ bool physical_state(int dim, const double* W) {
   if (!(W[0] > 0.0)) return false;
   double ke = W[1] * W[1] + ((dim == 2) ? W[2] * W[2] : 0.0);
   return W[dim + 1] - 0.5 * ke / W[0] > 0.0;

@@ -1470,8 +1470,11 @@ size_t macro_lds(int nt, int max_ni, int max_nj, int any_pi, int any_pj) {
                                    (any_pi ? 2 * kMacSlot * max_nj : 0));
 }
 
-template <int D>
-__global__ __launch_bounds__(512) void k_macro_sweep(Dev g, const int* __restrict__ binfo,
+// NTB: the launch's thread bound (64 for blocks up to 64 cells tall: one
+// wavefront, whose ring of prefetched rows then has the register file to
+// itself; 512 otherwise)
+template <int D, int NTB>
+__global__ __launch_bounds__(NTB) void k_macro_sweep(Dev g, const int* __restrict__ binfo,
                                                      const double* __restrict__ W,
                                                      const double* __restrict__ mac,
                                                      double* __restrict__ dWs, double* __restrict__ dW,
@@ -1525,71 +1528,123 @@ __global__ __launch_bounds__(512) void k_macro_sweep(Dev g, const int* __restric
   __syncthreads();
   const int H = ni + nj - 1;
   double prev[4] = {0, 0, 0, 0}, cw[4] = {0, 0, 0, 0};
-  MacroRow cur, nxt;
-  // forward sweep: (D + L) dW* = R
-  macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, 0, cur);
-  for (int h = 0; h < H; ++h) {
-    if (h + 1 < H) macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + 1, nxt);
-    if (cur.ok) {
-      const int i = h - j, c = cur.c;
-      double x[4] = {0, 0, 0, 0};
-      if (cur.iD > 0.0) {
-        double acc[4] = {0, 0, 0, 0};
-        if (i >= 1) macro_couple<D>(cur.nb[0], prev, acc);
-        if (D == 2 && j >= 1) macro_couple<D>(cur.nb[1], hand + ((h - 1) & 1) * NT * 4 + (j - 1) * 4, acc);
-        if (pi && i == ni - 1 && ni > 1) macro_couple<D>(sip + (0 * nj + j) * kMacSlot, cw, acc);
-        if (D == 2 && pj && j == nj - 1 && nj > 1) macro_couple<D>(sjp + (0 * ni + i) * kMacSlot, pjb + 4 * i, acc);
+  // forward sweep: (D + L) dW* = R.  The records of hyperplane h + 2 are
+  // loaded while h is solved (a ring of three rows in registers): the sweep
+  // is one wavefront per block, so each hyperplane's latency is exposed
+  auto fwd_step = [&](int h, const MacroRow& cur) __attribute__((always_inline)) {
+    if (!cur.ok) return;
+    const int i = h - j, c = cur.c;
+    double x[4] = {0, 0, 0, 0};
+    if (cur.iD > 0.0) {
+      double acc[4] = {0, 0, 0, 0};
+      if (i >= 1) macro_couple<D>(cur.nb[0], prev, acc);
+      if (D == 2 && j >= 1) macro_couple<D>(cur.nb[1], hand + ((h - 1) & 1) * NT * 4 + (j - 1) * 4, acc);
+      if (pi && i == ni - 1 && ni > 1) macro_couple<D>(sip + (0 * nj + j) * kMacSlot, cw, acc);
+      if (D == 2 && pj && j == nj - 1 && nj > 1) macro_couple<D>(sjp + (0 * ni + i) * kMacSlot, pjb + 4 * i, acc);
 #pragma unroll
-        for (int m = 0; m < nw; ++m) x[m] = (cur.base[m] - cur.ivd * acc[m]) * cur.iD;
-      }
-#pragma unroll
-      for (int m = 0; m < nw; ++m) {
-        dWs[(size_t)c * nw + m] = x[m];
-        prev[m] = x[m];
-        if (i == 0) cw[m] = x[m];
-        hand[(h & 1) * NT * 4 + j * 4 + m] = x[m];
-        if (pj && j == 0) pjb[4 * i + m] = x[m];
-      }
+      for (int m = 0; m < nw; ++m) x[m] = (cur.base[m] - cur.ivd * acc[m]) * cur.iD;
     }
-    lds_barrier();
-    cur = nxt;
+#pragma unroll
+    for (int m = 0; m < nw; ++m) {
+      dWs[(size_t)c * nw + m] = x[m];
+      prev[m] = x[m];
+      if (i == 0) cw[m] = x[m];
+      hand[(h & 1) * NT * 4 + j * 4 + m] = x[m];
+      if (pj && j == 0) pjb[4 * i + m] = x[m];
+    }
+  };
+  // ring of three rows for a one-wavefront launch; of two (prefetch one
+  // hyperplane ahead) for the wide launch, whose registers it would exceed
+  constexpr int RING = (NTB == 64) ? 3 : 2;
+  MacroRow ra, rb, rc;
+  macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, 0, ra);
+  if constexpr (RING == 3) {
+    macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, 1, rb);
+    for (int h = 0; h < H; h += 3) {
+      macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + 2, rc);
+      fwd_step(h, ra);
+      lds_barrier();
+      if (h + 1 >= H) break;
+      macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + 3, ra);
+      fwd_step(h + 1, rb);
+      lds_barrier();
+      if (h + 2 >= H) break;
+      macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + 4, rb);
+      fwd_step(h + 2, rc);
+      lds_barrier();
+    }
+  } else {
+    for (int h = 0; h < H; h += 2) {
+      macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + 1, rb);
+      fwd_step(h, ra);
+      lds_barrier();
+      if (h + 1 >= H) break;
+      macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + 2, ra);
+      fwd_step(h + 1, rb);
+      lds_barrier();
+    }
   }
   for (int m = 0; m < 4; ++m) { prev[m] = 0.0; cw[m] = 0.0; }
   __syncthreads();
-  // backward sweep: (D + U) dW = D dW*
-  macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, H - 1, cur);
-  for (int h = H - 1; h >= 0; --h) {
-    if (h >= 1) macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 1, nxt);
-    if (cur.ok) {
-      const int i = h - j, c = cur.c;
-      const bool fld = cur.iD > 0.0;
-      double x[4] = {0, 0, 0, 0};
-      if (fld) {
-        double acc[4] = {0, 0, 0, 0};
-        if (i + 1 < ni) macro_couple<D>(cur.nb[0], prev, acc);
-        if (D == 2 && j + 1 < nj) macro_couple<D>(cur.nb[1], hand + ((h + 1) & 1) * NT * 4 + (j + 1) * 4, acc);
-        if (pi && i == 0 && ni > 1) macro_couple<D>(sip + (1 * nj + j) * kMacSlot, cw, acc);
-        if (D == 2 && pj && j == 0 && nj > 1) macro_couple<D>(sjp + (1 * ni + i) * kMacSlot, pjb + 4 * i, acc);
+  // backward sweep: (D + U) dW = D dW*, the same ring of rows descending
+  auto bwd_step = [&](int h, const MacroRow& cur) __attribute__((always_inline)) {
+    if (!cur.ok) return;
+    const int i = h - j, c = cur.c;
+    const bool fld = cur.iD > 0.0;
+    double wc[4];
 #pragma unroll
-        for (int m = 0; m < nw; ++m) x[m] = cur.base[m] - cur.ivd * cur.iD * acc[m];
-      }
-      // a non-physical predictor keeps the current state
-      double wp[4];
+    for (int m = 0; m < 4; ++m) wc[m] = (m < nw) ? W[(size_t)c * nw + m] : 0.0;
+    double x[4] = {0, 0, 0, 0};
+    if (fld) {
+      double acc[4] = {0, 0, 0, 0};
+      if (i + 1 < ni) macro_couple<D>(cur.nb[0], prev, acc);
+      if (D == 2 && j + 1 < nj) macro_couple<D>(cur.nb[1], hand + ((h + 1) & 1) * NT * 4 + (j + 1) * 4, acc);
+      if (pi && i == 0 && ni > 1) macro_couple<D>(sip + (1 * nj + j) * kMacSlot, cw, acc);
+      if (D == 2 && pj && j == 0 && nj > 1) macro_couple<D>(sjp + (1 * ni + i) * kMacSlot, pjb + 4 * i, acc);
 #pragma unroll
-      for (int m = 0; m < 4; ++m) wp[m] = (m < nw) ? W[(size_t)c * nw + m] + x[m] : 0.0;
-      const bool okp = physical_state(D, wp);
-#pragma unroll
-      for (int m = 0; m < nw; ++m) {
-        dW[(size_t)c * nw + m] = x[m];
-        Wp[(size_t)c * nw + m] = (okp && fld) ? wp[m] : W[(size_t)c * nw + m];
-        prev[m] = x[m];
-        if (i == ni - 1) cw[m] = x[m];
-        hand[(h & 1) * NT * 4 + j * 4 + m] = x[m];
-        if (pj && j == nj - 1) pjb[4 * i + m] = x[m];
-      }
+      for (int m = 0; m < nw; ++m) x[m] = cur.base[m] - cur.ivd * cur.iD * acc[m];
     }
-    lds_barrier();
-    cur = nxt;
+    // a non-physical predictor keeps the current state
+    double wp[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) wp[m] = (m < nw) ? wc[m] + x[m] : 0.0;
+    const bool keep = physical_state(D, wp) && fld;
+#pragma unroll
+    for (int m = 0; m < nw; ++m) {
+      dW[(size_t)c * nw + m] = x[m];
+      Wp[(size_t)c * nw + m] = wc[m] + (keep ? x[m] : 0.0);  // (a select of wp / wc here goes to scratch)
+      prev[m] = x[m];
+      if (i == ni - 1) cw[m] = x[m];
+      hand[(h & 1) * NT * 4 + j * 4 + m] = x[m];
+      if (pj && j == nj - 1) pjb[4 * i + m] = x[m];
+    }
+  };
+  macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, H - 1, ra);
+  if constexpr (RING == 3) {
+    macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, H - 2, rb);
+    for (int h = H - 1; h >= 0; h -= 3) {
+      macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 2, rc);
+      bwd_step(h, ra);
+      lds_barrier();
+      if (h - 1 < 0) break;
+      macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 3, ra);
+      bwd_step(h - 1, rb);
+      lds_barrier();
+      if (h - 2 < 0) break;
+      macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 4, rb);
+      bwd_step(h - 2, rc);
+      lds_barrier();
+    }
+  } else {
+    for (int h = H - 1; h >= 0; h -= 2) {
+      macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 1, rb);
+      bwd_step(h, ra);
+      lds_barrier();
+      if (h - 1 < 0) break;
+      macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 2, ra);
+      bwd_step(h - 1, rb);
+      lds_barrier();
+    }
   }
 }
 
@@ -1787,9 +1842,12 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
 #pragma unroll
     for (int u = 0; u < P; ++u) {
       const int hp = h0 + u;
+      // stage first: the record it waits for was loaded P - 1 hyperplanes
+      // ago, and the wait then covers no store of this hyperplane (stores
+      // and loads share one in-order counter)
+      stage((u + 1) % P, (hp + 1) & 1);
       cell(hp, hp & 1, false, ra[u], rb_[u], 0.0, 0.0);
       issue(u, hp + P, false);
-      stage((u + 1) % P, (hp + 1) & 1);
       lds_barrier();
     }
   }
@@ -1803,9 +1861,9 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
 #pragma unroll
     for (int u = 0; u < P; ++u) {
       const int hp = h0 - u;
+      stage((u + 1) % P, (hp - 1) & 1);
       cell(hp, hp & 1, true, ra[u], rb_[u], rf0[u], rf1[u]);
       issue(u, hp - P, true);
-      stage((u + 1) % P, (hp - 1) & 1);
       lds_barrier();
     }
   }
@@ -1922,16 +1980,23 @@ void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int an
   k_macro_prep<<<nbl(g.ncell, 256), 256, 0, st>>>(g, dt, W, Wn, F, Fn, gam, R);
   const int nt = ((max_nj + 63) / 64) * 64;
   const size_t lds = macro_lds(nt, max_ni, max_nj, any_pi, any_pj);
-  if (g.dim == 2)
-    k_macro_sweep<2><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, dWs, dW, Wp, rpart, max_ni, max_nj, any_pi, any_pj);
-  else
-    k_macro_sweep<1><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, dWs, dW, Wp, rpart, max_ni, max_nj, any_pi, any_pj);
+  if (g.dim == 2) {
+    if (nt == 64)
+      k_macro_sweep<2, 64><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, dWs, dW, Wp, rpart, max_ni, max_nj, any_pi,
+                                                     any_pj);
+    else
+      k_macro_sweep<2, 512><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, dWs, dW, Wp, rpart, max_ni, max_nj, any_pi,
+                                                      any_pj);
+  } else {
+    k_macro_sweep<1, 64><<<g.nblock, nt, lds, st>>>(g, binfo, W, R, dWs, dW, Wp, rpart, max_ni, max_nj, any_pi,
+                                                   any_pj);
+  }
   if (resid) k_resid<<<1, 64, 0, st>>>(g.nblock, g.nw, rpart, resid);
 }
 
 // velocity-chunk width of the micro sweep for a block height
 #ifndef UGKS_MICRO_DEPTH
-#define UGKS_MICRO_DEPTH 2
+#define UGKS_MICRO_DEPTH 3
 #endif
 int micro_kc(int dim, int max_nj, int kc_max) {
   if (dim == 1) return 64;
@@ -2001,7 +2066,8 @@ static int micro_attrs() {
 
 int init_kernel_attributes() {
   if (micro_attrs<double>() || micro_attrs<float>()) return -1;
-  for (const void* k : {(const void*)k_macro_sweep<1>, (const void*)k_macro_sweep<2>})
+  for (const void* k : {(const void*)k_macro_sweep<1, 64>, (const void*)k_macro_sweep<2, 64>,
+                        (const void*)k_macro_sweep<2, 512>})
     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess) return -1;
   return 0;
 }
