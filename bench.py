@@ -24,14 +24,14 @@ HBM_PEAK_GBS = 8000.0
 # (storage-precision values of h, b, the sources and the D/residual buffer):
 #   face_eq      face-moment march: read h, b
 #   flux         flux march: read h, b; write D_h, D_b
-#   micro_sweep  forward: read D, f, S (the residual is formed in the sweep),
-#                write dF*; backward: read dF*, f, write f
+#   micro_rhs    micro residual: read S, f, D; write r over D
+#   micro_sweep  forward: read r, write dF*; backward: read dF*, f, write f
 #   step7        Step-7 moments: read h, b
-KERNEL_VALUES = {"face_eq": 2, "flux": 4, "micro_sweep": 14, "step7": 2}
+KERNEL_VALUES = {"face_eq": 2, "flux": 4, "micro_rhs": 8, "micro_sweep": 10, "step7": 2}
 KERNEL_NAMES = {"face_eq": "k_march (face-moment pass, MODE 0)", "flux": "k_march (flux pass, MODE 1)",
-                "micro_sweep": "k_micro (residual and both sweeps)", "step7": "k_step7"}
+                "micro_rhs": "k_micro_rhs", "micro_sweep": "k_micro", "step7": "k_step7"}
 KERNEL_KEYS = {"face_eq": "k_march<{re}, {t}, {t}, 0>", "flux": "k_march<{rf}, {t}, {t}, 1>",
-               "micro_sweep": "k_micro<2, {t}, {kc}, 2>", "step7": "k_step7<{t}>"}
+               "micro_rhs": "k_micro_rhs<{t}>", "micro_sweep": "k_micro<2, {t}, {kc}, 2>", "step7": "k_step7<{t}>"}
 
 
 def parse():

@@ -231,8 +231,7 @@ int ugks_step(ugks_ctx* ctx, double dt, int32_t n_inner, void* h, void* b, doubl
  * incident states, 2 face-moment pass (the face-equilibrium march kernel;
  * 1D: the face-equilibrium kernel), 3 face-equilibrium finalize, 4 flux
  * pass (the flux march kernel; 1D: the flux kernel), 5 flux finalize,
- * 6 macro LU-SGS, 7 cell equilibrium records, 8 micro residual pass (empty:
- * the residual is formed inside the forward sweep),
+ * 6 macro LU-SGS, 7 cell equilibrium records, 8 micro residual pass,
  * 9 micro LU-SGS sweeps, 10 Step-7 moments.
  */
 #define UGKS_NSTAGE 11

@@ -1660,29 +1660,52 @@ __global__ void k_resid(int nblock, int nw, const double* __restrict__ rpart, do
 // micro residual r = S - f^s/dt + (D + (f+' - f^s)/tau')/2 of every field
 // pair (Eq. residual_micro_n+1,s with the stored level-n part S), written over
 // D: fully parallel, one wavefront per cell, the cell record is wave-uniform
+template <class T>
+__global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const double* __restrict__ crec,
+                                                   const T* __restrict__ h, const T* __restrict__ b,
+                                                   const T* __restrict__ Sh, const T* __restrict__ Sb,
+                                                   T* __restrict__ Dh, T* __restrict__ Db) {
+  const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  if (c >= g.ncell || g.type[c] != 1) return;
+  const double* r = crec + (size_t)c * NCREC;
+  const double ux = r[C_UX], uy = r[C_UY], lam = r[C_LAM], qx = r[C_QX], qy = r[C_QY];
+  const double hn = r[C_HN], sh = r[C_SH], it = r[C_ITAU];
+  const double idt = 1.0 / dt;
+  const double rt = 0.5 / lam;
+  const int D = g.dim;
+  for (int k = lane; k < g.nv; k += 64) {
+    const size_t o = (size_t)c * g.nv + k;
+    const double cx = g.vx[k] - ux, cy = (D == 2) ? g.vy[k] - uy : 0.0;
+    const double c2 = cx * cx + cy * cy;
+    const double H = hn * exp(-lam * c2);
+    const double B = (double)(3 - D) * rt * H;
+    const double sq = sh * (cx * qx + cy * qy);
+    const double tl = 2.0 * lam * c2;
+    const double hpl = H + sq * (tl - 2.0 - D) * H;
+    const double bpl = B + sq * (tl - D) * (double)(3 - D) * rt * H;
+    const double f0 = (double)h[o], f1 = (double)b[o];
+    Dh[o] = (T)((double)Sh[o] - f0 * idt + 0.5 * ((double)Dh[o] + (hpl - f0) * it));
+    Db[o] = (T)((double)Sb[o] - f1 * idt + 0.5 * ((double)Db[o] + (bpl - f1) * it));
+  }
+}
+
 // micro LU-SGS (Eq. dualTimeStepping_micro): forward and backward sweep of
 // one velocity chunk (KC lanes) of one block, one row per thread slot, in
-// hyperplane order.  Dh/Db hold the flux divergence D on entry and dF* after
-// the forward sweep, which forms the residual r of each pair from S, f, D and
-// the cell's equilibrium as it reaches the pair; h, b are updated to f^{s+1}
-// by the backward sweep.
+// hyperplane order.  Dh/Db hold the residual r on entry and dF* after the
+// forward sweep; h, b are updated to f^{s+1} by the backward sweep.
 //
-// Latency and issue: everything a hyperplane needs from global memory (D or
-// dF*, h, b, S, and the cell's record: equilibrium of W', face geometry, D0
-// and the field flag) is requested P hyperplanes ahead into a register
+// Latency and issue: everything a hyperplane needs from global memory (its
+// residual or dF*, h, b, and the cell's coefficient record: face geometry,
+// D0 and the field flag) is requested P hyperplanes ahead into a register
 // ring, at addresses clamped into the row so that no load is predicated or
 // depends on a loaded value.  The record of the next hyperplane is copied
 // from the ring to LDS (double buffered) by the KC lanes of its row.  The
 // row hand-off buffer has a zero slot below row 0 and above the last row,
 // so the couplings need no row tests; results are stored only for cells of
 // the block.
-struct PairOut {
-  bool st;
-  int i;
-  double v0, v1;
-};
-constexpr int kMicroRec = NCREC;  // the whole cell record: equilibrium of W', geometry, D0, flag
-constexpr int kMicroRecLds = NCREC;
+constexpr int kMicroRec = 14;   // C_GEO (12), C_D0, C_FLD
+constexpr int kMicroRecLds = 16;
 
 // 1/d for d > 0 of moderate size: hardware estimate and two Newton steps
 __device__ __forceinline__ double recip_pos(double d) {
@@ -1693,11 +1716,9 @@ __device__ __forceinline__ double recip_pos(double d) {
 }
 
 template <int D, class T, int KC, int P>
-__global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ binfo, int nslot, double dt,
+__global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ binfo, int nslot,
                                                 const double* __restrict__ crec, T* __restrict__ h,
-                                                T* __restrict__ b, const T* __restrict__ Sh,
-                                                const T* __restrict__ Sb, T* __restrict__ Dh,
-                                                T* __restrict__ Db) {
+                                                T* __restrict__ b, T* __restrict__ Dh, T* __restrict__ Db) {
   extern __shared__ double smem[];
   constexpr int NS = (kMicroRec + KC - 1) / KC;  // record entries per lane
   const int* bi = binfo + 8 * blockIdx.y;
@@ -1731,18 +1752,15 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   const double vx = g.vx[kk], vy = (D == 2) ? g.vy[kk] : 0.0;
   const int HH = ni + nj - 1;
 
-  const double idt = 1.0 / dt;
-  double ra[P], rb_[P], rf0[P], rf1[P], rs0[P], rs1[P];
+  double ra[P], rb_[P], rf0[P], rf1[P];
   double rr[P][NS];
   auto issue = [&](int u, int hp, bool bwd) {
     const int i = min(max(hp - j, 0), ni - 1);
     const size_t o = (size_t)(cbase + i) * nv + kk;
     ra[u] = (double)Dh[o];
     rb_[u] = (double)Db[o];
-    rf0[u] = (double)h[o];
-    rf1[u] = (double)b[o];
-    if (!bwd) { rs0[u] = (double)Sh[o]; rs1[u] = (double)Sb[o]; }
-    const double* r = crec + (size_t)(cbase + i) * NCREC;
+    if (bwd) { rf0[u] = (double)h[o]; rf1[u] = (double)b[o]; }
+    const double* r = crec + (size_t)(cbase + i) * NCREC + C_GEO;
 #pragma unroll
     for (int m = 0; m < NS; ++m) rr[u][m] = r[min(lk + KC * m, kMicroRec - 1)];  // unpredicated
   };
@@ -1755,36 +1773,18 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   };
   // one cell of a sweep: returns false when (i, j) is outside the block
   double ph = 0.0, pb = 0.0, chh = 0.0, cbb = 0.0;
-  auto cell = [&](int hp, int p, bool bwd, double a0, double a1, double f0, double f1, double s0, double s1) {
+  auto cell = [&](int hp, int p, bool bwd, double a0, double a1, double f0, double f1) {
     const int i = hp - j;
     const bool act = row && i >= 0 && i < ni;
     const double* r = CEL(p);
-    if (!bwd) {
-      // the micro residual (Eq. residual_micro_n+1,s) from S, f^s, D and the
-      // Shakhov equilibrium of W', q': r = S - f/dt + (D + (f+ - f)/tau')/2.
-      // It needs no neighbour, so it stays off the sweep's dependence chain
-      const double lam = r[C_LAM];
-      const double cx = vx - r[C_UX], cy = (D == 2) ? vy - r[C_UY] : 0.0;
-      const double c2 = cx * cx + cy * cy;
-      const double H = r[C_HN] * exp(-lam * c2);
-      const double rt = 0.5 / lam;
-      const double B = (double)(3 - D) * rt * H;
-      const double sq = r[C_SH] * (cx * r[C_QX] + cy * r[C_QY]);
-      const double tl = 2.0 * lam * c2;
-      const double hpl = H + sq * (tl - 2.0 - D) * H;
-      const double bpl = B + sq * (tl - D) * (double)(3 - D) * rt * H;
-      const double it = r[C_ITAU];
-      a0 = s0 - f0 * idt + 0.5 * (a0 + (hpl - f0) * it);
-      a1 = s1 - f1 * idt + 0.5 * (a1 + (bpl - f1) * it);
-    }
     double ts[4];
-    double d = r[C_D0];
+    double d = r[12];
 #pragma unroll
     for (int s = 0; s < 2 * D; ++s) {
-      ts[s] = r[C_GEO + 3 * s] * vx + r[C_GEO + 3 * s + 1] * vy - r[C_GEO + 3 * s + 2];
+      ts[s] = r[3 * s] * vx + r[3 * s + 1] * vy - r[3 * s + 2];
       d += fmax(ts[s], 0.0);
     }
-    const bool fld = act && r[C_FLD] != 0.0;
+    const bool fld = act && r[13] != 0.0;
     // couplings: along i from the row's previous cell (zero before the first
     // cell of the sweep), along j through the hand-off buffer, and across
     // periodic seams
@@ -1812,14 +1812,12 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
     double xb = bwd ? a1 - ob * id : (a1 - ob) * id;
     xh = fld ? xh : 0.0;
     xb = fld ? xb : 0.0;
-    // the pair's result is stored by the caller after it has issued the
-    // next loads (see the sweep loops)
-    PairOut out;
-    out.st = act && fld && kin;
-    out.i = i;
-    out.v0 = bwd ? f0 + xh : xh;
-    out.v1 = bwd ? f1 + xb : xb;
     if (act) {
+      if (fld && kin) {
+        const size_t o = (size_t)(cbase + i) * nv + k;
+        if (bwd) { h[o] = (T)(f0 + xh); b[o] = (T)(f1 + xb); }
+        else { Dh[o] = (T)xh; Db[o] = (T)xb; }
+      }
       ph = xh; pb = xb;
       if (i == (bwd ? ni - 1 : 0)) { chh = xh; cbb = xb; }
       double* q = HND(p, j + 1);
@@ -1829,13 +1827,6 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
         z[0] = xh; z[1] = xb;
       }
     }
-    return out;
-  };
-  auto store = [&](const PairOut& out, bool bwd) {
-    if (!out.st) return;
-    const size_t o = (size_t)(cbase + out.i) * nv + k;
-    if (bwd) { h[o] = (T)out.v0; b[o] = (T)out.v1; }
-    else { Dh[o] = (T)out.v0; Db[o] = (T)out.v1; }
   };
 
   // ---------------- forward sweep: (D + L) dF* = r ----------------
@@ -1851,13 +1842,12 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
 #pragma unroll
     for (int u = 0; u < P; ++u) {
       const int hp = h0 + u;
-      // stage first, store last: stores and loads share one in-order
-      // counter, so the wait for the record (loaded P - 1 hyperplanes ago,
-      // ahead of that hyperplane's stores) covers no store
+      // stage first: the record it waits for was loaded P - 1 hyperplanes
+      // ago, and the wait then covers no store of this hyperplane (stores
+      // and loads share one in-order counter)
       stage((u + 1) % P, (hp + 1) & 1);
-      const PairOut out = cell(hp, hp & 1, false, ra[u], rb_[u], rf0[u], rf1[u], rs0[u], rs1[u]);
+      cell(hp, hp & 1, false, ra[u], rb_[u], 0.0, 0.0);
       issue(u, hp + P, false);
-      store(out, false);
       lds_barrier();
     }
   }
@@ -1872,9 +1862,8 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
     for (int u = 0; u < P; ++u) {
       const int hp = h0 - u;
       stage((u + 1) % P, (hp - 1) & 1);
-      const PairOut out = cell(hp, hp & 1, true, ra[u], rb_[u], rf0[u], rf1[u], 0.0, 0.0);
+      cell(hp, hp & 1, true, ra[u], rb_[u], rf0[u], rf1[u]);
       issue(u, hp - P, true);
-      store(out, true);
       lds_barrier();
     }
   }
@@ -2007,7 +1996,7 @@ void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int an
 
 // velocity-chunk width of the micro sweep for a block height
 #ifndef UGKS_MICRO_DEPTH
-#define UGKS_MICRO_DEPTH 2
+#define UGKS_MICRO_DEPTH 3
 #endif
 int micro_kc(int dim, int max_nj, int kc_max) {
   if (dim == 1) return 64;
@@ -2023,38 +2012,42 @@ size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj, int kc_max) {
 }
 
 template <int D, class T, int KC>
-static void micro_t(const Dev& g, const int* binfo, int nslot, size_t lds, double dt, const double* crec, void* h,
-                    void* b, const void* Sh, const void* Sb, void* Dh, void* Db, hipStream_t st) {
+static void micro_t(const Dev& g, const int* binfo, int nslot, size_t lds, const double* crec, void* h, void* b,
+                    void* Dh, void* Db, hipStream_t st) {
   constexpr int P = UGKS_MICRO_DEPTH;
   dim3 grid((unsigned)((g.nv + KC - 1) / KC), (unsigned)g.nblock);
   int threads = ((nslot * KC + 63) / 64) * 64;
-  k_micro<D, T, KC, P><<<grid, threads, lds, st>>>(g, binfo, nslot, dt, crec, (T*)h, (T*)b, (const T*)Sh,
-                                                   (const T*)Sb, (T*)Dh, (T*)Db);
+  k_micro<D, T, KC, P><<<grid, threads, lds, st>>>(g, binfo, nslot, crec, (T*)h, (T*)b, (T*)Dh, (T*)Db);
 }
 
 template <class T>
-static void micro_prec(const Dev& g, const int* binfo, int KC, int nslot, size_t lds, double dt, const double* crec,
-                       void* h, void* b, const void* Sh, const void* Sb, void* Dh, void* Db, hipStream_t st) {
-  if (g.dim == 1) { micro_t<1, T, 64>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); return; }
+static void micro_prec(const Dev& g, const int* binfo, int KC, int nslot, size_t lds, const double* crec, void* h,
+                       void* b, void* Dh, void* Db, hipStream_t st) {
+  if (g.dim == 1) { micro_t<1, T, 64>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); return; }
   switch (KC) {
-    case 16: micro_t<2, T, 16>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); break;
-    case 8: micro_t<2, T, 8>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); break;
-    case 4: micro_t<2, T, 4>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); break;
-    default: micro_t<2, T, 2>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); break;
+    case 16: micro_t<2, T, 16>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    case 8: micro_t<2, T, 8>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    case 4: micro_t<2, T, 4>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    default: micro_t<2, T, 2>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
   }
 }
 
-// Steps 5-6: one launch; the residual is formed inside the forward sweep (the
-// profile's residual stage is empty)
 void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
                   const double* crec, void* h, void* b, const void* Sh, const void* Sb, void* Dh, void* Db,
                   hipStream_t st, hipEvent_t* ev) {
+  if (prec == 0)
+    k_micro_rhs<double><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const double*)h, (const double*)b,
+                                                      (const double*)Sh, (const double*)Sb, (double*)Dh,
+                                                      (double*)Db);
+  else
+    k_micro_rhs<float><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const float*)h, (const float*)b,
+                                                     (const float*)Sh, (const float*)Sb, (float*)Dh, (float*)Db);
   if (ev) (void)hipEventRecord(ev[0], st);
   const int KC = micro_kc(g.dim, max_nj, g.kc_max);
   const int nslot = (g.dim == 1) ? 1 : max_nj;
   const size_t lds = micro_lds(g.dim, max_ni, max_nj, any_pj, g.kc_max);
-  if (prec == 0) micro_prec<double>(g, binfo, KC, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st);
-  else micro_prec<float>(g, binfo, KC, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st);
+  if (prec == 0) micro_prec<double>(g, binfo, KC, nslot, lds, crec, h, b, Dh, Db, st);
+  else micro_prec<float>(g, binfo, KC, nslot, lds, crec, h, b, Dh, Db, st);
 }
 
 // dynamic LDS limits of the sweep kernels, set once per device before any
