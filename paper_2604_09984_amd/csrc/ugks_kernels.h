@@ -6,7 +6,7 @@ namespace ugks {
 
 // sets the kernels' dynamic LDS limits on the current device; 0 on success
 int init_kernel_attributes();
-int micro_kc(int dim, int max_nj, int kc_max);
+void micro_shape(int dim, int max_ni, int max_nj, int any_pj, int kc_max, int& kc, int& rows);
 size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj, int kc_max);
 size_t macro_lds(int nt, int max_ni, int max_nj, int any_pi, int any_pj);
 

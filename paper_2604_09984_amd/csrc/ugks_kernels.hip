@@ -1715,7 +1715,7 @@ __device__ __forceinline__ double recip_pos(double d) {
   return r;
 }
 
-template <int D, class T, int KC, int P>
+template <int D, class T, int KC, int P, int R>
 __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ binfo, int nslot,
                                                 const double* __restrict__ crec, T* __restrict__ h,
                                                 T* __restrict__ b, T* __restrict__ Dh, T* __restrict__ Db) {
@@ -1724,7 +1724,10 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   const int* bi = binfo + 8 * blockIdx.y;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], pi = bi[3], pj = bi[4];
   const int t = threadIdx.x;
-  const int lk = t % KC, j = t / KC;
+  const int lk = t % KC, jt = t / KC;
+  // rows of this thread: jt, jt + NTR, ... (R of them; the cells of one
+  // hyperplane in different rows are independent)
+  const int NTR = (nslot + R - 1) / R;
   const int nv = g.nv;
   // velocity chunk: chunks that share a 128-byte line of f go to workgroups
   // that the round-robin dispatch places on the same XCD (every 8th
@@ -1738,45 +1741,54 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   const int k = chunk * KC + lk;
   const bool kin = k < nv;
   const int kk = kin ? k : nv - 1;
-  const bool row = j < nj;
-  const int jl = row ? j : nj - 1;  // rows beyond the block read (not write) the last row's slots
-  const int cbase = c0 + ni * jl;   // cell (0, j)
+  int jr[R], jl[R], cbase[R];
+  bool row[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    jr[q] = jt + NTR * q;
+    row[q] = jr[q] < nj;
+    jl[q] = row[q] ? jr[q] : nj - 1;  // rows beyond the block read (not write) the last row's slots
+    cbase[q] = c0 + ni * jl[q];       // cell (0, j)
+  }
   // LDS: hand[2][nslot + 2][KC][2] (slot s + 1 holds row s), cells[2][nslot][16],
   // pj[ni][KC][2]
   double* hand = smem;
   double* cells = smem + 4 * (nslot + 2) * KC;
   double* pjb = cells + 2 * nslot * kMicroRecLds;
   auto HND = [&](int p, int s) -> double* { return hand + ((size_t)(p * (nslot + 2) + s) * KC + lk) * 2; };
-  auto CEL = [&](int p) -> double* { return cells + (size_t)(p * nslot + jl) * kMicroRecLds; };
+  auto CEL = [&](int p, int q) -> double* { return cells + (size_t)(p * nslot + jl[q]) * kMicroRecLds; };
   for (int e = t; e < 4 * (nslot + 2) * KC; e += blockDim.x) hand[e] = 0.0;
   const double vx = g.vx[kk], vy = (D == 2) ? g.vy[kk] : 0.0;
   const int HH = ni + nj - 1;
 
-  double ra[P], rb_[P], rf0[P], rf1[P];
-  double rr[P][NS];
-  auto issue = [&](int u, int hp, bool bwd) {
-    const int i = min(max(hp - j, 0), ni - 1);
-    const size_t o = (size_t)(cbase + i) * nv + kk;
-    ra[u] = (double)Dh[o];
-    rb_[u] = (double)Db[o];
-    if (bwd) { rf0[u] = (double)h[o]; rf1[u] = (double)b[o]; }
-    const double* r = crec + (size_t)(cbase + i) * NCREC + C_GEO;
+  double ra[R][P], rb_[R][P], rf0[R][P], rf1[R][P];
+  double rr[R][P][NS];
+  auto issue = [&](int q, int u, int hp, bool bwd) {
+    const int i = min(max(hp - jr[q], 0), ni - 1);
+    const size_t o = (size_t)(cbase[q] + i) * nv + kk;
+    ra[q][u] = (double)Dh[o];
+    rb_[q][u] = (double)Db[o];
+    if (bwd) { rf0[q][u] = (double)h[o]; rf1[q][u] = (double)b[o]; }
+    const double* r = crec + (size_t)(cbase[q] + i) * NCREC + C_GEO;
 #pragma unroll
-    for (int m = 0; m < NS; ++m) rr[u][m] = r[min(lk + KC * m, kMicroRec - 1)];  // unpredicated
+    for (int m = 0; m < NS; ++m) rr[q][u][m] = r[min(lk + KC * m, kMicroRec - 1)];  // unpredicated
   };
-  auto stage = [&](int u, int p) {
-    if (!row) return;
-    double* d = CEL(p);
+  auto stage = [&](int q, int u, int p) {
+    if (!row[q]) return;
+    double* d = CEL(p, q);
 #pragma unroll
     for (int m = 0; m < NS; ++m)
-      if (lk + KC * m < kMicroRec) d[lk + KC * m] = rr[u][m];
+      if (lk + KC * m < kMicroRec) d[lk + KC * m] = rr[q][u][m];
   };
-  // one cell of a sweep: returns false when (i, j) is outside the block
-  double ph = 0.0, pb = 0.0, chh = 0.0, cbb = 0.0;
-  auto cell = [&](int hp, int p, bool bwd, double a0, double a1, double f0, double f1) {
+  // one cell of a sweep (nothing is written when (i, j) is outside the block)
+  double ph[R], pb[R], chh[R], cbb[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) { ph[q] = pb[q] = chh[q] = cbb[q] = 0.0; }
+  auto cell = [&](int q, int hp, int p, bool bwd, double a0, double a1, double f0, double f1) {
+    const int j = jr[q];
     const int i = hp - j;
-    const bool act = row && i >= 0 && i < ni;
-    const double* r = CEL(p);
+    const bool act = row[q] && i >= 0 && i < ni;
+    const double* r = CEL(p, q);
     double ts[4];
     double d = r[12];
 #pragma unroll
@@ -1790,21 +1802,21 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
     // periodic seams
     const int si = bwd ? 1 : 0, sj = bwd ? 3 : 2;
     double w = fmin(ts[si], 0.0);
-    double oh = w * ph, ob = w * pb;
+    double oh = w * ph[q], ob = w * pb[q];
     if (D == 2) {
-      const double* q = HND(p ^ 1, bwd ? jl + 2 : jl);
+      const double* hq = HND(p ^ 1, bwd ? jl[q] + 2 : jl[q]);
       w = fmin(ts[sj], 0.0);
-      oh += w * q[0]; ob += w * q[1];
+      oh += w * hq[0]; ob += w * hq[1];
     }
     const bool seam_i = pi && ni > 1 && i == (bwd ? 0 : ni - 1);
     w = seam_i ? fmin(ts[bwd ? 0 : 1], 0.0) : 0.0;
-    oh += w * chh; ob += w * cbb;
+    oh += w * chh[q]; ob += w * cbb[q];
     if (D == 2 && pj) {
       const bool seam_j = nj > 1 && j == (bwd ? 0 : nj - 1);
       if (seam_j && act) {
-        const double* q = pjb + ((size_t)i * KC + lk) * 2;
+        const double* z = pjb + ((size_t)i * KC + lk) * 2;
         w = fmin(ts[bwd ? 2 : 3], 0.0);
-        oh += w * q[0]; ob += w * q[1];
+        oh += w * z[0]; ob += w * z[1];
       }
     }
     const double id = recip_pos(d);
@@ -1814,14 +1826,14 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
     xb = fld ? xb : 0.0;
     if (act) {
       if (fld && kin) {
-        const size_t o = (size_t)(cbase + i) * nv + k;
+        const size_t o = (size_t)(cbase[q] + i) * nv + k;
         if (bwd) { h[o] = (T)(f0 + xh); b[o] = (T)(f1 + xb); }
         else { Dh[o] = (T)xh; Db[o] = (T)xb; }
       }
-      ph = xh; pb = xb;
-      if (i == (bwd ? ni - 1 : 0)) { chh = xh; cbb = xb; }
-      double* q = HND(p, j + 1);
-      q[0] = xh; q[1] = xb;
+      ph[q] = xh; pb[q] = xb;
+      if (i == (bwd ? ni - 1 : 0)) { chh[q] = xh; cbb[q] = xb; }
+      double* hq = HND(p, j + 1);
+      hq[0] = xh; hq[1] = xb;
       if (D == 2 && pj && j == (bwd ? nj - 1 : 0)) {
         double* z = pjb + ((size_t)i * KC + lk) * 2;
         z[0] = xh; z[1] = xb;
@@ -1835,8 +1847,11 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   // loop runs whole groups of P hyperplanes; the extra ones (hp >= HH) have
   // no cells in any row.
 #pragma unroll
-  for (int u = 0; u < P; ++u) issue(u, u, false);
-  stage(0, 0);
+  for (int u = 0; u < P; ++u)
+#pragma unroll
+    for (int q = 0; q < R; ++q) issue(q, u, u, false);
+#pragma unroll
+  for (int q = 0; q < R; ++q) stage(q, 0, 0);
   __syncthreads();
   for (int h0 = 0; h0 < HH; h0 += P) {
 #pragma unroll
@@ -1845,25 +1860,35 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
       // stage first: the record it waits for was loaded P - 1 hyperplanes
       // ago, and the wait then covers no store of this hyperplane (stores
       // and loads share one in-order counter)
-      stage((u + 1) % P, (hp + 1) & 1);
-      cell(hp, hp & 1, false, ra[u], rb_[u], 0.0, 0.0);
-      issue(u, hp + P, false);
+#pragma unroll
+      for (int q = 0; q < R; ++q) stage(q, (u + 1) % P, (hp + 1) & 1);
+#pragma unroll
+      for (int q = 0; q < R; ++q) cell(q, hp, hp & 1, false, ra[q][u], rb_[q][u], 0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < R; ++q) issue(q, u, hp + P, false);
       lds_barrier();
     }
   }
   // ---------------- backward sweep: (D + U) dF = D dF* ----------------
-  ph = pb = chh = cbb = 0.0;
 #pragma unroll
-  for (int u = 0; u < P; ++u) issue(u, HH - 1 - u, true);
-  stage(0, (HH - 1) & 1);
+  for (int q = 0; q < R; ++q) { ph[q] = pb[q] = chh[q] = cbb[q] = 0.0; }
+#pragma unroll
+  for (int u = 0; u < P; ++u)
+#pragma unroll
+    for (int q = 0; q < R; ++q) issue(q, u, HH - 1 - u, true);
+#pragma unroll
+  for (int q = 0; q < R; ++q) stage(q, 0, (HH - 1) & 1);
   __syncthreads();
   for (int h0 = HH - 1; h0 >= 0; h0 -= P) {
 #pragma unroll
     for (int u = 0; u < P; ++u) {
       const int hp = h0 - u;
-      stage((u + 1) % P, (hp - 1) & 1);
-      cell(hp, hp & 1, true, ra[u], rb_[u], rf0[u], rf1[u]);
-      issue(u, hp - P, true);
+#pragma unroll
+      for (int q = 0; q < R; ++q) stage(q, (u + 1) % P, (hp - 1) & 1);
+#pragma unroll
+      for (int q = 0; q < R; ++q) cell(q, hp, hp & 1, true, ra[q][u], rb_[q][u], rf0[q][u], rf1[q][u]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) issue(q, u, hp - P, true);
       lds_barrier();
     }
   }
@@ -1998,37 +2023,60 @@ void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int an
 #ifndef UGKS_MICRO_DEPTH
 #define UGKS_MICRO_DEPTH 3
 #endif
-int micro_kc(int dim, int max_nj, int kc_max) {
-  if (dim == 1) return 64;
-  int kc = kc_max;
-  while (kc > 2 && kc * max_nj > 1024) kc >>= 1;
-  return kc;
-}
-
-size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj, int kc_max) {
-  int kc = micro_kc(dim, max_nj, kc_max);
-  int nslot = (dim == 1) ? 1 : max_nj;
+static size_t micro_lds_of(int dim, int max_ni, int max_nj, int any_pj, int kc) {
+  const int nslot = (dim == 1) ? 1 : max_nj;
   return sizeof(double) * (size_t)(4 * (nslot + 2) * kc + 2 * nslot * kMicroRecLds + (any_pj ? 2 * max_ni * kc : 0));
 }
 
-template <int D, class T, int KC>
+// velocity-chunk width KC and rows per thread R of the micro sweep: the
+// widest chunk up to kc_max whose LDS fits 160 KiB, one row per thread
+// before two, with KC * ceil(nj / R) <= 1024 threads; kc = 0 when none fits
+void micro_shape(int dim, int max_ni, int max_nj, int any_pj, int kc_max, int& kc, int& rows) {
+  rows = 1;
+  if (dim == 1) { kc = 64; return; }
+  for (kc = kc_max; kc >= 2; kc >>= 1) {
+    if (micro_lds_of(dim, max_ni, max_nj, any_pj, kc) > 160 * 1024) continue;
+    for (rows = 1; rows <= 2; ++rows)
+      if (kc * ((max_nj + rows - 1) / rows) <= 1024) return;
+  }
+  kc = 0;
+  rows = 1;
+}
+
+size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj, int kc_max) {
+  int kc, rows;
+  micro_shape(dim, max_ni, max_nj, any_pj, kc_max, kc, rows);
+  if (kc == 0) return (size_t)1 << 40;  // no shape fits
+  return micro_lds_of(dim, max_ni, max_nj, any_pj, kc);
+}
+
+// ring depth of the sweep: two rows per thread (of FP64 values, or with
+// records spread over few lanes) take the registers a third slot would need
+template <class T, int KC, int R>
+constexpr int micro_depth() { return (R == 2 && (sizeof(T) == 8 || KC <= 4)) ? 2 : UGKS_MICRO_DEPTH; }
+
+template <int D, class T, int KC, int R>
 static void micro_t(const Dev& g, const int* binfo, int nslot, size_t lds, const double* crec, void* h, void* b,
                     void* Dh, void* Db, hipStream_t st) {
-  constexpr int P = UGKS_MICRO_DEPTH;
+  constexpr int P = micro_depth<T, KC, R>();
   dim3 grid((unsigned)((g.nv + KC - 1) / KC), (unsigned)g.nblock);
-  int threads = ((nslot * KC + 63) / 64) * 64;
-  k_micro<D, T, KC, P><<<grid, threads, lds, st>>>(g, binfo, nslot, crec, (T*)h, (T*)b, (T*)Dh, (T*)Db);
+  int threads = ((((nslot + R - 1) / R) * KC + 63) / 64) * 64;
+  k_micro<D, T, KC, P, R><<<grid, threads, lds, st>>>(g, binfo, nslot, crec, (T*)h, (T*)b, (T*)Dh, (T*)Db);
 }
 
 template <class T>
-static void micro_prec(const Dev& g, const int* binfo, int KC, int nslot, size_t lds, const double* crec, void* h,
-                       void* b, void* Dh, void* Db, hipStream_t st) {
-  if (g.dim == 1) { micro_t<1, T, 64>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); return; }
-  switch (KC) {
-    case 16: micro_t<2, T, 16>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
-    case 8: micro_t<2, T, 8>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
-    case 4: micro_t<2, T, 4>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
-    default: micro_t<2, T, 2>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+static void micro_prec(const Dev& g, const int* binfo, int KC, int R, int nslot, size_t lds, const double* crec,
+                       void* h, void* b, void* Dh, void* Db, hipStream_t st) {
+  if (g.dim == 1) { micro_t<1, T, 64, 1>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); return; }
+  switch (KC * 4 + R) {
+    case 16 * 4 + 1: micro_t<2, T, 16, 1>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    case 16 * 4 + 2: micro_t<2, T, 16, 2>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    case 8 * 4 + 1: micro_t<2, T, 8, 1>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    case 8 * 4 + 2: micro_t<2, T, 8, 2>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    case 4 * 4 + 1: micro_t<2, T, 4, 1>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    case 4 * 4 + 2: micro_t<2, T, 4, 2>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    case 2 * 4 + 1: micro_t<2, T, 2, 1>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    default: micro_t<2, T, 2, 2>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
   }
 }
 
@@ -2043,11 +2091,12 @@ void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_
     k_micro_rhs<float><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const float*)h, (const float*)b,
                                                      (const float*)Sh, (const float*)Sb, (float*)Dh, (float*)Db);
   if (ev) (void)hipEventRecord(ev[0], st);
-  const int KC = micro_kc(g.dim, max_nj, g.kc_max);
+  int KC, R;
+  micro_shape(g.dim, max_ni, max_nj, any_pj, g.kc_max, KC, R);
   const int nslot = (g.dim == 1) ? 1 : max_nj;
-  const size_t lds = micro_lds(g.dim, max_ni, max_nj, any_pj, g.kc_max);
-  if (prec == 0) micro_prec<double>(g, binfo, KC, nslot, lds, crec, h, b, Dh, Db, st);
-  else micro_prec<float>(g, binfo, KC, nslot, lds, crec, h, b, Dh, Db, st);
+  const size_t lds = micro_lds_of(g.dim, max_ni, max_nj, any_pj, KC);
+  if (prec == 0) micro_prec<double>(g, binfo, KC, R, nslot, lds, crec, h, b, Dh, Db, st);
+  else micro_prec<float>(g, binfo, KC, R, nslot, lds, crec, h, b, Dh, Db, st);
 }
 
 // dynamic LDS limits of the sweep kernels, set once per device before any
@@ -2055,10 +2104,15 @@ void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_
 // depends on them)
 template <class T>
 static int micro_attrs() {
-  constexpr int P = UGKS_MICRO_DEPTH;
-  const void* f[] = {(const void*)k_micro<1, T, 64, P>, (const void*)k_micro<2, T, 16, P>,
-                     (const void*)k_micro<2, T, 8, P>, (const void*)k_micro<2, T, 4, P>,
-                     (const void*)k_micro<2, T, 2, P>};
+  const void* f[] = {(const void*)k_micro<1, T, 64, micro_depth<T, 64, 1>(), 1>,
+                     (const void*)k_micro<2, T, 16, micro_depth<T, 16, 1>(), 1>,
+                     (const void*)k_micro<2, T, 16, micro_depth<T, 16, 2>(), 2>,
+                     (const void*)k_micro<2, T, 8, micro_depth<T, 8, 1>(), 1>,
+                     (const void*)k_micro<2, T, 8, micro_depth<T, 8, 2>(), 2>,
+                     (const void*)k_micro<2, T, 4, micro_depth<T, 4, 1>(), 1>,
+                     (const void*)k_micro<2, T, 4, micro_depth<T, 4, 2>(), 2>,
+                     (const void*)k_micro<2, T, 2, micro_depth<T, 2, 1>(), 1>,
+                     (const void*)k_micro<2, T, 2, micro_depth<T, 2, 2>(), 2>};
   for (const void* k : f)
     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess) return -1;
   return 0;
