@@ -31,7 +31,7 @@ KERNEL_VALUES = {"face_eq": 2, "flux": 4, "micro_rhs": 8, "micro_sweep": 10, "st
 KERNEL_NAMES = {"face_eq": "k_march (face-moment pass, MODE 0)", "flux": "k_march (flux pass, MODE 1)",
                 "micro_rhs": "k_micro_rhs", "micro_sweep": "k_micro", "step7": "k_step7"}
 KERNEL_KEYS = {"face_eq": "k_march<{re}, {t}, {t}, 0>", "flux": "k_march<{rf}, {t}, {t}, 1>",
-               "micro_rhs": "k_micro_rhs<{t}>", "micro_sweep": "k_micro<2, {t}, {kc}, 2>", "step7": "k_step7<{t}>"}
+               "micro_rhs": "k_micro_rhs<{t}>", "micro_sweep": "k_micro<2, {t}, {kc}, 3, 1>", "step7": "k_step7<{t}>"}
 
 
 def parse():
