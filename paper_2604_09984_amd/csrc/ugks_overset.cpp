@@ -32,6 +32,7 @@
 #include <algorithm>
 #include <cmath>
 #include <limits>
+#include <thread>
 
 #include "ugks.h"
 
@@ -359,24 +360,34 @@ int overset_build(const OversetInput& in, int wrule, int overlap, OversetOutput&
   const Walls W = collect_walls(C);
   const int cut = overlap + 3;
   // node classes
+  // (every node on its own: node rows of a zone are shared among threads)
   std::vector<std::vector<char>> off(nb);
+  const int nthr = (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
   for (int b = 0; b < nb; ++b) {
     const Zone& Z = C.z[b];
     off[b].assign((size_t)(Z.ni + 1) * (Z.nj + 1), 0);
-    for (int j = 0; j <= Z.nj; ++j)
-      for (int i = 0; i <= Z.ni; ++i) {
-        const double px = C.X(b, i, j), py = C.Y(b, i, j);
-        bool o = in_body(W, b, px, py);
-        const double da = wall_d2(W, b, px, py);
-        for (int z = 0; z < nb && !o; ++z) {
-          if (z == b) continue;
-          const int m = locate(C, z, px, py, nullptr);
-          if (m < 0 || depth(C, z, m) < cut) continue;
-          const double dz = wall_d2(W, z, px, py);
-          o = (dz < da) || (dz == da && z > b);
+    auto rows = [&](int j0) {
+      for (int j = j0; j <= Z.nj; j += nthr)
+        for (int i = 0; i <= Z.ni; ++i) {
+          const double px = C.X(b, i, j), py = C.Y(b, i, j);
+          bool o = in_body(W, b, px, py);
+          // the own wall distance only where another zone covers the node
+          double da = -1.0;
+          for (int z = 0; z < nb && !o; ++z) {
+            if (z == b) continue;
+            const int m = locate(C, z, px, py, nullptr);
+            if (m < 0 || depth(C, z, m) < cut) continue;
+            if (da < 0.0) da = wall_d2(W, b, px, py);
+            const double dz = wall_d2(W, z, px, py);
+            o = (dz < da) || (dz == da && z > b);
+          }
+          off[b][i + (size_t)(Z.ni + 1) * j] = o ? 1 : 0;
         }
-        off[b][i + (size_t)(Z.ni + 1) * j] = o ? 1 : 0;
-      }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthr; ++t) pool.emplace_back(rows, t);
+    rows(0);
+    for (auto& th : pool) th.join();
   }
   // cell classes
   std::vector<signed char> cls(ncell);
