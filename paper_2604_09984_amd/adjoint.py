@@ -24,9 +24,20 @@ Checkpointing: physical_step() stores only its inputs; its backward re-runs
 the step's forward (Steps 1-2 and the n_inner inner iterations, keeping the
 inner states) and then the reverse passes.  A `setup` callable restores the
 step's geometry (poses, overset assembly) before the forward and before the
-recomputation, so moving-mesh runs are differentiated step by step.
+recomputation, so moving-mesh runs are differentiated step by step; it is
+called as setup(solver) when it takes an argument, else as setup().
+
+FP32 storage: the library's reverse passes work on FP64 storage, so the
+backward of a solver with FP32 storage runs on an FP64 twin context of the
+same case: the checkpointed step is recomputed there from the (exactly
+representable) FP32 inputs, and the gradients are those of the FP64 map at
+those inputs, returned in the inputs' dtypes.  The twin takes the solver's
+poses, cell kinds and donor table (or, with a setup, runs setup(twin), so a
+moving FP32 run needs a setup that takes the solver).
 """
 from __future__ import annotations
+
+import inspect
 
 import numpy as np
 import torch
@@ -120,6 +131,55 @@ def _out_grad(U, g):
     return None if U is None else g.to(U.device, U.dtype)
 
 
+def _run_setup(setup, solver):
+    if setup is None:
+        return
+    try:
+        takes = len(inspect.signature(setup).parameters) > 0
+    except (TypeError, ValueError):
+        takes = False
+    if takes:
+        setup(solver)
+    elif getattr(solver, "_adj_owner", None) is not None:
+        raise ValueError("the FP64 twin of an FP32 solver needs a setup(solver) that takes the solver")
+    else:
+        setup()
+
+
+def _twin(solver):
+    """The context that runs the reverse passes: the solver itself (FP64
+    storage) or its FP64 twin (FP32 storage)."""
+    if solver.prec == ugks.F64:
+        return solver
+    t = getattr(solver, "_adj_twin", None)
+    if t is None:
+        t = ugks.Solver(solver.case, ugks.F64, device=solver.device.index)
+        t._adj_owner = solver
+        solver._adj_twin = t
+    return t
+
+
+def _mirror(src, dst):
+    """dst takes src's poses, cell kinds and receptor donor table."""
+    if dst is src:
+        return
+    poses = getattr(src, "poses", None)
+    if poses is not None:
+        dst.set_poses(poses)
+    dst.set_types(src.types())
+    rec, ptr, don, w = src.overset()
+    if len(rec) > 0:
+        dst.set_overset(rec, ptr, don, w)
+
+
+def _f64(t):
+    return None if t is None else t.double().contiguous()
+
+
+def _as(t, like):
+    return t if t.dtype == like.dtype else t.to(like.dtype)
+
+
 def _clone(*ts):
     return [t.clone() for t in ts]
 
@@ -133,8 +193,7 @@ class PseudoStep(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, solver, dt, setup, h, b, W, q, Wn, Sh, Sb, Fn, U, rtw):
-        if setup is not None:
-            setup()
+        _run_setup(setup, solver)
         apply_params(solver, U, rtw)
         h1, b1, W1, q1 = _clone(h, b, W, q)
         solver.step(dt, 1, h1, b1, W1, Wn, q1, Sh, Sb, Fn)
@@ -147,13 +206,16 @@ class PseudoStep(torch.autograd.Function):
     def backward(ctx, gh, gb, gW, gq, gF):
         h, b, W, q, Wn, Sh, Sb, Fn, U, rtw = ctx.saved_tensors
         s = ctx.solver
-        if ctx.setup is not None:
-            ctx.setup()
-        apply_params(s, U, rtw)
-        hb, bb, Wb, Wnb, qb, Shb, Sbb, Fnb, fb = s.step_adjoint(ctx.dt, h, b, W, Wn, q, Sh, Sb, Fn,
-                                                                 _c(gh), _c(gb), _c(gW), _c(gq), _c(gF))
-        gU, gR = _faces(s).param_grads(fb)
-        return None, None, None, hb, bb, Wb, qb, Wnb, Shb, Sbb, Fnb, _out_grad(U, gU), _out_grad(rtw, gR)
+        _run_setup(ctx.setup, s)
+        t = _twin(s)
+        _mirror(s, t)
+        apply_params(t, U, rtw)
+        hb, bb, Wb, Wnb, qb, Shb, Sbb, Fnb, fb = t.step_adjoint(ctx.dt, _f64(h), _f64(b), W, Wn, q, _f64(Sh),
+                                                                 _f64(Sb), Fn, _f64(gh), _f64(gb), _c(gW),
+                                                                 _c(gq), _c(gF))
+        gU, gR = _faces(t).param_grads(fb)
+        return (None, None, None, _as(hb, h), _as(bb, b), Wb, qb, Wnb, _as(Shb, Sh), _as(Sbb, Sb), Fnb,
+                _out_grad(U, gU), _out_grad(rtw, gR))
 
 
 class BeginStep(torch.autograd.Function):
@@ -163,10 +225,11 @@ class BeginStep(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, solver, dt, setup, h, b, W, q, U, rtw):
-        if setup is not None:
-            setup()
+        _run_setup(setup, solver)
         apply_params(solver, U, rtw)
         ctx.refill = solver.overset_rows()[2] != 0
+        if ctx.refill and solver.prec != ugks.F64:
+            raise ValueError("cells to refill with FP32 storage: use the checkpointed physical_step")
         h1, b1, W1, q1 = _clone(h, b, W, q)
         Sh, Sb, Fn = solver.begin_step(dt, h1, b1, W1, q1)
         ctx.solver, ctx.dt, ctx.setup = solver, dt, setup
@@ -177,13 +240,14 @@ class BeginStep(torch.autograd.Function):
     def backward(ctx, gh, gb, gW, gq, gSh, gSb, gFn):
         h, b, W, q, U, rtw = ctx.saved_tensors
         s = ctx.solver
-        if ctx.setup is not None:
-            ctx.setup()
-        apply_params(s, U, rtw)
-        hb, bb, Wb, qb, fb = s.begin_step_adjoint(ctx.dt, h, b, W, q, _c(gh), _c(gb), _c(gW), _c(gq), _c(gSh),
-                                                  _c(gSb), _c(gFn), refill=ctx.refill)
-        gU, gR = _faces(s).param_grads(fb)
-        return None, None, None, hb, bb, Wb, qb, _out_grad(U, gU), _out_grad(rtw, gR)
+        _run_setup(ctx.setup, s)
+        t = _twin(s)
+        _mirror(s, t)
+        apply_params(t, U, rtw)
+        hb, bb, Wb, qb, fb = t.begin_step_adjoint(ctx.dt, _f64(h), _f64(b), W, q, _f64(gh), _f64(gb), _c(gW),
+                                                  _c(gq), _f64(gSh), _f64(gSb), _c(gFn), refill=ctx.refill)
+        gU, gR = _faces(t).param_grads(fb)
+        return None, None, None, _as(hb, h), _as(bb, b), Wb, qb, _out_grad(U, gU), _out_grad(rtw, gR)
 
 
 def _c(t):
@@ -204,8 +268,7 @@ class PhysicalStep(torch.autograd.Function):
         # the cell kinds before the step's setup decide which cells an
         # overset assembly refills; the recomputation restores them
         ctx.types0 = solver.types() if setup is not None else None
-        if setup is not None:
-            setup()
+        _run_setup(setup, solver)
         apply_params(solver, U, rtw)
         ctx.refill = solver.overset_rows()[2] != 0
         h1, b1, W1, q1 = _clone(h, b, W, q)
@@ -220,12 +283,18 @@ class PhysicalStep(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gh, gb, gW, gq, gF):
         h, b, W, q, U, rtw = ctx.saved_tensors
-        s, dt = ctx.solver, ctx.dt
+        dt = ctx.dt
+        s = _twin(ctx.solver)
         if ctx.setup is not None:
             s.set_types(ctx.types0)
-            ctx.setup()
+            _run_setup(ctx.setup, s)
+        else:
+            _mirror(ctx.solver, s)
         apply_params(s, U, rtw)
-        # recomputation: Steps 1-2, then the inner iterations, keeping their inputs
+        # recomputation: Steps 1-2, then the inner iterations, keeping their
+        # inputs (FP64 storage: the twin's, from the FP32 inputs if need be)
+        h_in, b_in = h, b
+        h, b = _f64(h), _f64(b)
         hs, bs, Ws, qs = _clone(h, b, W, q)
         Wn = W.clone()
         Sh, Sb, Fn = s.begin_step(dt, hs, bs, Ws, qs)
@@ -235,7 +304,7 @@ class PhysicalStep(torch.autograd.Function):
             s.step(dt, 1, hs, bs, Ws, Wn, qs, Sh, Sb, Fn)
         del hs, bs, Ws, qs
         # reverse through the inner iterations
-        gh, gb, gW, gq = _c(gh), _c(gb), _c(gW), _c(gq)
+        gh, gb, gW, gq = _f64(gh), _f64(gb), _c(gW), _c(gq)
         gSh = torch.zeros_like(Sh); gSb = torch.zeros_like(Sb)
         gFn = torch.zeros_like(Fn); gWn = torch.zeros_like(W)
         faces = torch.zeros((s.nface, 5), dtype=torch.float64, device=h.device)
@@ -251,7 +320,7 @@ class PhysicalStep(torch.autograd.Function):
         faces += fb
         Wb = Wb + gWn
         gU, gR = _faces(s).param_grads(faces)
-        return None, None, None, None, hb, bb, Wb, qb, _out_grad(U, gU), _out_grad(rtw, gR)
+        return None, None, None, None, _as(hb, h_in), _as(bb, b_in), Wb, qb, _out_grad(U, gU), _out_grad(rtw, gR)
 
 
 def physical_step(solver, dt, n_inner, h, b, W, q, U=None, rtw=None, setup=None, checkpoint=True):
