@@ -268,8 +268,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): the pseudo-iteration "
-              "is measured on a single MI355X; the multi-GPU velocity-sharded design is described "
-              "in DESIGN.md and not built.", file=sys.stderr)
+              "is measured on a single MI355X; sharding the velocities over GPUs is designed, not built.",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2604_09984_amd import workloads as wl
