@@ -1691,9 +1691,11 @@ __global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const doubl
 }
 
 // micro LU-SGS (Eq. dualTimeStepping_micro): forward and backward sweep of
-// one velocity chunk (KC lanes) of one block, one row per thread slot, in
-// hyperplane order.  Dh/Db hold the residual r on entry and dF* after the
-// forward sweep; h, b are updated to f^{s+1} by the backward sweep.
+// one velocity chunk (KC lanes) of one block, R rows per thread slot (rows
+// j, j + ceil(nj/R), ...: cells of one hyperplane in different rows are
+// independent), in hyperplane order.  Dh/Db hold the residual r on entry and
+// dF* after the forward sweep; h, b are updated to f^{s+1} by the backward
+// sweep.
 //
 // Latency and issue: everything a hyperplane needs from global memory (its
 // residual or dF*, h, b, and the cell's coefficient record: face geometry,
