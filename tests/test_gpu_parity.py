@@ -31,10 +31,19 @@ def small_cases():
     mixbox = wl.periodic_box(2, 7, 9, 10)
     mixbox.blocks[0].bc = (wl.COPY, wl.FARFIELD, wl.WALL, wl.COPY)
     mixbox.name = "mixed_box"
+    # degenerate regimes: no collisions (tau infinite: free transport) and
+    # tau far below dt_s (the time integrals' large-argument forms)
+    free = wl.periodic_box(2, 8, 6, 10)
+    free.mu_ref = 0.0
+    free.name = "collisionless_box"
+    dense = wl.periodic_box(2, 8, 6, 10, kn=1e-5)
+    dense.name = "continuum_box"
+    # blocks of 70, 130 and 300 rows: the sweep's two-rows-per-thread shapes
+    # (16 x 2, 8 x 2 and 4 x 2 velocities x rows)
     return [wl.sod_1d(ncell=40, nv=33), wl.periodic_box(1, 12, 1, 17), wl.periodic_box(2, 8, 6, 10),
-            ffbox, mixbox,
+            ffbox, mixbox, free, dense,
             wl.cylinder(ni=16, nj=8, nvx=16), wl.cavity(8, 12), wl.cavity(6, 10, periodic_x=True),
-            mov, wallmov, wl.channel(6, 70, 8), wl.channel(5, 130, 6)]
+            mov, wallmov, wl.channel(6, 70, 8), wl.channel(5, 130, 6), wl.channel(4, 300, 6)]
 
 
 CASES = small_cases()
