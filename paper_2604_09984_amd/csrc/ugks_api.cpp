@@ -1150,8 +1150,9 @@ int ugks_batch_step(ugks_batch* B, const double* dt, int32_t n_inner, void* cons
 
 int ugks_set_tuning(ugks_ctx* c, int32_t kc_max, int32_t rg_eq, int32_t rg_flux) {
   if (!c) return fail(UGKS_E_ARG, "null context");
-  if ((kc_max != 16 && kc_max != 8 && kc_max != 4) || (rg_eq != 8 && rg_eq != 6) || (rg_flux != 8 && rg_flux != 6))
-    return fail(UGKS_E_ARG, "kc_max must be 16, 8 or 4 and row groups 8 or 6");
+  if ((kc_max != 16 && kc_max != 8 && kc_max != 4) || (rg_eq != 8 && rg_eq != 6) ||
+      (rg_flux != 10 && rg_flux != 8 && rg_flux != 6))
+    return fail(UGKS_E_ARG, "kc_max must be 16, 8 or 4, rg_eq 8 or 6, rg_flux 10, 8 or 6");
   c->dev.kc_max = kc_max;
   c->dev.rg_eq = rg_eq;
   c->dev.rg_flux = rg_flux;
@@ -1187,8 +1188,9 @@ int ugks_autotune(ugks_ctx* c, double dt, int32_t n_inner, const void* h, const 
   int bk = saved.kc_max, be = saved.rg_eq, bf = saved.rg_flux;
   for (int kc : {16, 8})
     for (int re : {8, 6})
-      for (int rf : {8, 6}) {
+      for (int rf : {10, 8, 6}) {
         if (rc) break;
+        if (rf == 10 && c->prec != 0) continue;  // 10 rows: the FP64 flux pass only
         c->dev.kc_max = kc; c->dev.rg_eq = re; c->dev.rg_flux = rf;
         if (micro_lds(c->dim, c->max_ni, c->max_nj, c->any_pj, kc) > 160 * 1024) continue;
         // each candidate runs from the same inputs (copies; the caller's

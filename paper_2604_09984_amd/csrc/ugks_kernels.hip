@@ -590,16 +590,22 @@ template <int RG, class T, class C, int MODE>
 __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __restrict__ binfo, int nchunk,
                                                          const T* __restrict__ h, const T* __restrict__ b,
                                                          const double* __restrict__ rec,
+                                                         const double* __restrict__ fpl,
                                                          double* __restrict__ part, T* __restrict__ Dh,
                                                          T* __restrict__ Db) {
   constexpr int NW = RG + 2;
+  // FP64 flux pass: face records and geometry read through the scalar cache
+  // (uniform addresses, read-only), which frees the registers and LDS of
+  // staging them; elsewhere they are staged in LDS one column ahead
+  constexpr bool SREC = (MODE == 1) && (sizeof(C) == 8);
+  constexpr int SG = SREC ? 1 : 2, SQ = SREC ? 1 : 2, SN = SREC ? 1 : kStg;
   // reconstructions of three columns, raw values of one column per row for
   // the j-neighbours, j-face fluxes of two columns (flux pass), the face
   // records of two columns (staged one column ahead)
   __shared__ LD6<C> lds[3][NW][64];
   __shared__ C pub[2][NW][2][64];
   __shared__ C jfl[(MODE == 1) ? 2 : 1][NW][2][64];
-  __shared__ double stg[2][NW][2][kStg];
+  __shared__ double stg[SG][NW][SQ][SN];
   const int* bi = binfo + 8 * blockIdx.z;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], per_i = bi[3], per_j = bi[4];
   const int j0 = blockIdx.y * RG;
@@ -727,8 +733,8 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   };
   // upwind interface data of a face between sides sl (low) and sh (high)
   // with normal (nx, ny) and mesh velocity (ux, uy)
-  auto face_eval = [&](const double* r, const Side<C>& sl, const Side<C>& sh, double* facc, double* mom) -> void {
-    const double* fp = r + NREC;
+  auto face_eval = [&](const double* r, const double* fp, const Side<C>& sl, const Side<C>& sh, double* facc,
+                       double* mom) -> void {
     const double nx = fp[kFpN0], ny = fp[kFpN0 + 1], ux = fp[kFpU], uy = fp[kFpU + 1];
     const double wn = exact_wn(vx, vy, ux, uy, nx, ny);
     if (MODE == 0) {
@@ -760,8 +766,8 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   };
   // wall face seen from the interior cell c (slot s) with data L: MODE 0
   // gives the numerator and denominator of the wall density (Eq. rhow)
-  auto wall_eval = [&](const double* r, bool low, const LD6<C>& L, double* facc, double* mom) -> void {
-    const double* fp = r + NREC;
+  auto wall_eval = [&](const double* r, const double* fp, bool low, const LD6<C>& L, double* facc,
+                       double* mom) -> void {
     const double sg = r[R_SGN];
     const double fg[5] = {fp[kFpN0], fp[kFpN0 + 1], fp[kFpS], fp[kFpU], fp[kFpU + 1]};
     const double wn = exact_wn(vx, vy, fg[3], fg[4], sg * fg[0], sg * fg[1]);
@@ -839,8 +845,8 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
          cp3 = cplan_load(1);
   const double cpz = cplan_load(0);
   // face records of column -1 in registers (staged during the first step)
-  double fn_i, fn_j;
-  {
+  double fn_i = 0.0, fn_j = 0.0;
+  if constexpr (!SREC) {
     int fi, fj;
     face_ids(-1, cp1, cpz, fi, fj);
     fn_i = face_load(fi);
@@ -877,9 +883,13 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     oc_h = on_h; oc_b = on_b;
     raw(jo, x + 3, on_h, on_b);
     // face records of column x + 2 (ids from the record of column x + 2)
-    int fi2, fj2;
-    face_ids(x + 2, cp2, cpz, fi2, fj2);
-    const double f2_i = face_load(fi2), f2_j = face_load(fj2);
+    double f2_i = 0.0, f2_j = 0.0;
+    if constexpr (!SREC) {
+      int fi2, fj2;
+      face_ids(x + 2, cp2, cpz, fi2, fj2);
+      f2_i = face_load(fi2);
+      f2_j = face_load(fj2);
+    }
     const double cdiv = cpm1;  // column x - 1
     const double cfac = cp0c;  // column x
     cpm1 = cp0c; cp0c = cp1; cp1 = cp2; cp2 = cp3;
@@ -887,8 +897,10 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     lds_barrier();
     // stage the face records of column x + 1 (the buffer was last read at
     // column x - 1, before this barrier)
-    if (lane < kStg) { stg[(x + 1) & 1][w][0][lane] = fn_i; stg[(x + 1) & 1][w][1][lane] = fn_j; }
-    fn_i = f2_i; fn_j = f2_j;
+    if constexpr (!SREC) {
+      if (lane < kStg) { stg[(x + 1) & 1][w][0][lane] = fn_i; stg[(x + 1) & 1][w][1][lane] = fn_j; }
+      fn_i = f2_i; fn_j = f2_j;
+    }
     if (MODE == 1) {
       divergence(x - 1, cdiv);
       fi_m2[0] = fi_m1[0]; fi_m2[1] = fi_m1[1];
@@ -908,8 +920,16 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
       auto face_q = [&](int q) {
         const int f = (q == 0) ? fid[0] : fid[1];
         if (f < 0) return;
-        const double* r = &stg[x & 1][w][q][0];
-        const double* fp = r + NREC;
+        const double* r;
+        const double* fp;
+        if constexpr (SREC) {
+          const int fu = __builtin_amdgcn_readfirstlane(f);
+          r = rec + (size_t)fu * NREC;
+          fp = fpl + (size_t)fu * kFpN;
+        } else {
+          r = &stg[x & 1][w][q][0];
+          fp = r + NREC;
+        }
         if (__builtin_amdgcn_readfirstlane((int)fp[kFpAct]) == 0) return;
         const int L = __builtin_amdgcn_readfirstlane((int)fp[kFpL]);
         const int R = __builtin_amdgcn_readfirstlane((int)fp[kFpR]);
@@ -923,12 +943,12 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
 #pragma unroll
         for (int m = 0; m < NM; ++m) mom[m] = 0.0;
         if (L == kNbWall || R == kNbWall) {
-          wall_eval(r, L != kNbWall, (L == kNbWall) ? hi : lo, fc, mom);
+          wall_eval(r, fp, L != kNbWall, (L == kNbWall) ? hi : lo, fc, mom);
         } else {
           // the low side of the seam face (x = -1) is cell ni-1, staged as column -1
           const Side<C> sl = (L >= 0) ? side_at(lo, fp[kFpDL], fp[kFpDL + 1]) : ghost(hi, L);
           const Side<C> sh = (R >= 0) ? side_at(hi, fp[kFpDR], fp[kFpDR + 1]) : ghost(lo, R);
-          face_eval(r, sl, sh, fc, mom);
+          face_eval(r, fp, sl, sh, fc, mom);
         }
         if (MODE == 1) write_flux(owner ? f : -1, mom);
         if (q == 0) {
@@ -1922,16 +1942,21 @@ static void march_pass(const Dev& g, const int* binfo, int max_nj, int nchunk, c
                        const double* W, const double* rec, double* part, void* Dh, void* Db, hipStream_t st) {
   dim3 grid((unsigned)nchunk, (unsigned)((max_nj + RG - 1) / RG), (unsigned)g.nblock);
   (void)W;
-  k_march<RG, T, C, MODE><<<grid, 64 * (RG + 2), 0, st>>>(g, binfo, nchunk, (const T*)h, (const T*)b, rec, part,
-                                                          (T*)Dh, (T*)Db);
+  k_march<RG, T, C, MODE><<<grid, 64 * (RG + 2), 0, st>>>(g, binfo, nchunk, (const T*)h, (const T*)b, rec, g.fplan,
+                                                           part, (T*)Dh, (T*)Db);
 }
 
 template <class T, class C, int MODE>
 static void march_rg(int rg, const Dev& g, const int* binfo, int max_nj, int nchunk, const void* h,
                      const void* b, const double* W, const double* rec, double* part, void* Dh, void* Db,
                      hipStream_t st) {
-  if (rg == 6) march_pass<6, T, C, MODE>(g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st);
-  else march_pass<8, T, C, MODE>(g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st);
+  if (rg == 6) { march_pass<6, T, C, MODE>(g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st); return; }
+  // 10 core rows (12 wavefronts, 3 per SIMD) fit the registers and LDS only
+  // where face records are not staged: the FP64 flux pass; elsewhere 10 runs 8
+  if constexpr (MODE == 1 && sizeof(C) == 8) {
+    if (rg == 10) { march_pass<10, T, C, MODE>(g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st); return; }
+  }
+  march_pass<8, T, C, MODE>(g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st);
 }
 
 template <class T, class C>
