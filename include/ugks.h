@@ -275,12 +275,12 @@ int ugks_batch_destroy(ugks_batch* batch);
  * Launch shapes (results do not depend on them): kc_max, the widest velocity
  * chunk of a micro-sweep workgroup (16, 8 or 4; narrowed for tall blocks),
  * and rg_eq, rg_flux, the core rows per workgroup of the face-equilibrium
- * (8 or 6) and flux (10, 8 or 6; 10 applies to FP64 storage, FP32 runs it
- * as 8) march kernels.  ugks_autotune times every combination of kc_max
- * {16, 8} x rg_eq {8, 6} x rg_flux {10 (FP64 only), 8, 6} over n_inner
+ * and flux march kernels (10, 8 or 6 each).  ugks_autotune times n_inner
  * pseudo-iterations run on device copies of the given state (the caller's
- * arrays are not written; scratch is allocated for the call), keeps the
- * fastest and reports it in host choice[3] and its mean milliseconds per
+ * arrays are not written; scratch is allocated for the call) for kc_max
+ * {16, 8}, then rg_eq {8, 10, 6} and then rg_flux {8, 10, 6}, each with the
+ * others at their best so far (the three act on different kernels), keeps
+ * the fastest and reports it in host choice[3] and its mean milliseconds per
  * pseudo-iteration in *best_ms.  Synchronous.
  */
 int ugks_set_tuning(ugks_ctx* ctx, int32_t kc_max, int32_t rg_eq, int32_t rg_flux);

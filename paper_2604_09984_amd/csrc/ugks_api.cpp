@@ -641,7 +641,7 @@ int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
   // wavefront with six core rows per workgroup
   c->dev.kc_max = 16;
   c->dev.rg_eq = 8;
-  c->dev.rg_flux = (c->prec == UGKS_F64) ? 6 : 8;
+  c->dev.rg_flux = 8;
   *out = c;
   return UGKS_OK;
 }
@@ -1150,9 +1150,9 @@ int ugks_batch_step(ugks_batch* B, const double* dt, int32_t n_inner, void* cons
 
 int ugks_set_tuning(ugks_ctx* c, int32_t kc_max, int32_t rg_eq, int32_t rg_flux) {
   if (!c) return fail(UGKS_E_ARG, "null context");
-  if ((kc_max != 16 && kc_max != 8 && kc_max != 4) || (rg_eq != 8 && rg_eq != 6) ||
+  if ((kc_max != 16 && kc_max != 8 && kc_max != 4) || (rg_eq != 10 && rg_eq != 8 && rg_eq != 6) ||
       (rg_flux != 10 && rg_flux != 8 && rg_flux != 6))
-    return fail(UGKS_E_ARG, "kc_max must be 16, 8 or 4, rg_eq 8 or 6, rg_flux 10, 8 or 6");
+    return fail(UGKS_E_ARG, "kc_max must be 16, 8 or 4, rg_eq and rg_flux 10, 8 or 6");
   c->dev.kc_max = kc_max;
   c->dev.rg_eq = rg_eq;
   c->dev.rg_flux = rg_flux;
@@ -1186,27 +1186,36 @@ int ugks_autotune(ugks_ctx* c, double dt, int32_t n_inner, const void* h, const 
   const Dev saved = c->dev;
   double best = 1e300;
   int bk = saved.kc_max, be = saved.rg_eq, bf = saved.rg_flux;
-  for (int kc : {16, 8})
-    for (int re : {8, 6})
-      for (int rf : {10, 8, 6}) {
-        if (rc) break;
-        if (rf == 10 && c->prec != 0) continue;  // 10 rows: the FP64 flux pass only
-        c->dev.kc_max = kc; c->dev.rg_eq = re; c->dev.rg_flux = rf;
-        if (micro_lds(c->dim, c->max_ni, c->max_nj, c->any_pj, kc) > 160 * 1024) continue;
-        // each candidate runs from the same inputs (copies; the caller's
-        // arrays are not written)
-        if (hipMemcpyAsync(th, h, fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(tb, b, fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(tW, W, wb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(tq, q, qb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
-            hipEventRecord(e0, st) != hipSuccess) { rc = fail(UGKS_E_DEVICE, "autotune copy"); break; }
-        rc = run_inner(c, dt, n_inner, th, tb, (double*)tW, Wn, (double*)tq, Sh, Sb, Fn, nullptr, st, nullptr);
-        if (rc) break;
-        float ms = 0.f;
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = fail(UGKS_E_DEVICE, "autotune timing"); break; }
-        if (ms < best) { best = ms; bk = kc; be = re; bf = rf; }
-      }
+  // one run from the same inputs (copies; the caller's arrays are not
+  // written) with shapes (kc, re, rf); its time in ms, or < 0 when skipped
+  auto trial = [&](int kc, int re, int rf) -> double {
+    if (rc) return -1.0;
+    if (micro_lds(c->dim, c->max_ni, c->max_nj, c->any_pj, kc) > 160 * 1024) return -1.0;
+    c->dev.kc_max = kc; c->dev.rg_eq = re; c->dev.rg_flux = rf;
+    if (hipMemcpyAsync(th, h, fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(tb, b, fb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(tW, W, wb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(tq, q, qb, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipEventRecord(e0, st) != hipSuccess) { rc = fail(UGKS_E_DEVICE, "autotune copy"); return -1.0; }
+    rc = run_inner(c, dt, n_inner, th, tb, (double*)tW, Wn, (double*)tq, Sh, Sb, Fn, nullptr, st, nullptr);
+    if (rc) return -1.0;
+    float ms = 0.f;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = fail(UGKS_E_DEVICE, "autotune timing"); return -1.0; }
+    return ms;
+  };
+  // the three shapes act on different kernels (micro sweep, face-moment
+  // march, flux march): one coordinate at a time, the others at their best
+  auto consider = [&](int kc, int re, int rf) {
+    const double ms = trial(kc, re, rf);
+    if (ms >= 0.0 && ms < best) { best = ms; bk = kc; be = re; bf = rf; }
+  };
+  consider(16, 8, 8);
+  consider(8, 8, 8);
+  const int kc1 = bk;
+  for (int re : {10, 6}) consider(kc1, re, 8);
+  const int re1 = be;
+  for (int rf : {10, 6}) consider(kc1, re1, rf);
   c->dev = saved;
   if (!rc) {
     c->dev.kc_max = bk; c->dev.rg_eq = be; c->dev.rg_flux = bf;

@@ -583,8 +583,31 @@ __device__ __forceinline__ Side<C> side_ghost(const Dev& g, const LD6<C>& L, int
 __device__ __forceinline__ double rec_at(double v, int l) { return lane_read(v, l); }
 __device__ __forceinline__ int rec_int(double v, int l) { return (int)lane_read(v, l); }
 
-// one staged face: its record (NREC entries) then its packed geometry
-constexpr int kStg = NREC + kFpN;
+// scalar-cache prefetch of the records of two faces: one word of each
+// 64-byte line of the face record (NREC doubles, 64-byte aligned) and of its
+// packed geometry (kFpN doubles, 32-byte aligned: two lines).  The words are
+// only kept alive (sgpr_keep) so that the loads are issued; a missing face
+// (-1) touches face 0.
+constexpr int kTouch = 7;
+__device__ __forceinline__ void face_touch(const double* __restrict__ rec, const double* __restrict__ fpl,
+                                           int f0, int f1, int (&t)[2 * kTouch]) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int fq = __builtin_amdgcn_readfirstlane(q == 0 ? f0 : f1);
+    const int fs = (fq < 0) ? 0 : fq;
+    const int* rr = (const int*)(rec + (size_t)fs * NREC);
+    const int* pp = (const int*)(fpl + (size_t)fs * kFpN);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) t[kTouch * q + m] = rr[16 * m];
+    t[kTouch * q + 5] = pp[0];
+    t[kTouch * q + 6] = pp[2 * kFpN - 1];
+  }
+}
+__device__ __forceinline__ void sgpr_keep(const int (&t)[2 * kTouch]) {
+  asm volatile("" ::"s"(t[0]), "s"(t[1]), "s"(t[2]), "s"(t[3]), "s"(t[4]), "s"(t[5]), "s"(t[6]), "s"(t[7]),
+               "s"(t[8]), "s"(t[9]), "s"(t[10]), "s"(t[11]), "s"(t[12]), "s"(t[13]));
+}
+static_assert(NREC * 8 == 5 * 64 && kFpN * 8 <= 96, "face_touch covers the record in 5 lines, geometry in 2");
 
 template <int RG, class T, class C, int MODE>
 __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __restrict__ binfo, int nchunk,
@@ -594,18 +617,13 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
                                                          double* __restrict__ part, T* __restrict__ Dh,
                                                          T* __restrict__ Db) {
   constexpr int NW = RG + 2;
-  // FP64 flux pass: face records and geometry read through the scalar cache
-  // (uniform addresses, read-only), which frees the registers and LDS of
-  // staging them; elsewhere they are staged in LDS one column ahead
-  constexpr bool SREC = (MODE == 1) && (sizeof(C) == 8);
-  constexpr int SG = SREC ? 1 : 2, SQ = SREC ? 1 : 2, SN = SREC ? 1 : kStg;
   // reconstructions of three columns, raw values of one column per row for
-  // the j-neighbours, j-face fluxes of two columns (flux pass), the face
-  // records of two columns (staged one column ahead)
+  // the j-neighbours, j-face fluxes of two columns (flux pass).  Face records
+  // and geometry are read through the scalar cache (uniform addresses,
+  // read-only), prefetched one column ahead.
   __shared__ LD6<C> lds[3][NW][64];
   __shared__ C pub[2][NW][2][64];
   __shared__ C jfl[(MODE == 1) ? 2 : 1][NW][2][64];
-  __shared__ double stg[SG][NW][SQ][SN];
   const int* bi = binfo + 8 * blockIdx.z;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], per_i = bi[3], per_j = bi[4];
   const int j0 = blockIdx.y * RG;
@@ -669,11 +687,7 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
       fi = (x >= 0) ? rec_int(cpx, kCpFace + 1) : rec_int(cp0, kCpFace + 0);
     if (jface && x >= 0 && x < ni) fj = (jr >= 0) ? rec_int(cpx, kCpFace + 3) : rec_int(cpx, kCpFace + 2);
   };
-  // lane l: entry l of the staged record of face f (record, then geometry)
-  auto face_load = [&](int f) -> double {
-    if (f < 0 || lane >= kStg) return 0.0;
-    return (lane < NREC) ? rec[(size_t)f * NREC + lane] : g.fplan[(size_t)f * kFpN + (lane - NREC)];
-  };
+
   // side data at a face from the reconstruction of a cell and the offset
   // from its centroid to the face centre
   auto side_at = [](const LD6<C>& L, double dx, double dy) -> Side<C> {
@@ -831,7 +845,7 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   // column x (i-face (x|x+1), j-face above x) and, in flux mode, gathers the
   // divergence of column x - 1 from the faces of the previous step.  Ahead
   // of use, in registers: raw values (two columns), packed cell records
-  // (three columns), face records (two columns, then staged in LDS).
+  // (three columns); in the scalar cache: face records (one column).
   raw(jr, -2, a0h, a0b);
   raw(jr, -1, a1h, a1b);
   raw(jr, 0, a2h, a2b);
@@ -844,16 +858,12 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   double cpm1 = cplan_load(-3), cp0c = cplan_load(-2), cp1 = cplan_load(-1), cp2 = cplan_load(0),
          cp3 = cplan_load(1);
   const double cpz = cplan_load(0);
-  // face records of column -1 in registers (staged during the first step)
-  double fn_i = 0.0, fn_j = 0.0;
-  if constexpr (!SREC) {
-    int fi, fj;
-    face_ids(-1, cp1, cpz, fi, fj);
-    fn_i = face_load(fi);
-    fn_j = face_load(fj);
-  }
   lds_barrier();
   double fi_m2[2] = {0.0, 0.0}, fi_m1[2] = {0.0, 0.0}, fj_m1[2] = {0.0, 0.0};
+  // the records of the next column's faces are requested after this
+  // column's faces and waited for before the next column's: one round trip
+  // per column instead of several dependent ones per face
+  int touched[2 * kTouch] = {};
   auto divergence = [&](int x, double cp) {
     // divergence of cell (x, jr) of a core row from the i-faces (x-1|x) and
     // (x|x+1), the j-face above (this row) and below (the row beneath)
@@ -873,7 +883,7 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   };
   for (int x = -2; x < ni; ++x) {
     // registers: cell records cpm1 .. cp3 of columns x-1 .. x+3 (cp3 in
-    // flight); face records fn of column x + 1
+    // flight)
     recon(x + 1, cp1);
     // publish column x + 2 of this row, advance the windows
     pub[x & 1][w][0][lane] = a2h;
@@ -882,25 +892,11 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     raw(jr, x + 4, p_h, p_b);
     oc_h = on_h; oc_b = on_b;
     raw(jo, x + 3, on_h, on_b);
-    // face records of column x + 2 (ids from the record of column x + 2)
-    double f2_i = 0.0, f2_j = 0.0;
-    if constexpr (!SREC) {
-      int fi2, fj2;
-      face_ids(x + 2, cp2, cpz, fi2, fj2);
-      f2_i = face_load(fi2);
-      f2_j = face_load(fj2);
-    }
     const double cdiv = cpm1;  // column x - 1
     const double cfac = cp0c;  // column x
     cpm1 = cp0c; cp0c = cp1; cp1 = cp2; cp2 = cp3;
     cp3 = cplan_load(x + 4);
     lds_barrier();
-    // stage the face records of column x + 1 (the buffer was last read at
-    // column x - 1, before this barrier)
-    if constexpr (!SREC) {
-      if (lane < kStg) { stg[(x + 1) & 1][w][0][lane] = fn_i; stg[(x + 1) & 1][w][1][lane] = fn_j; }
-      fn_i = f2_i; fn_j = f2_j;
-    }
     if (MODE == 1) {
       divergence(x - 1, cdiv);
       fi_m2[0] = fi_m1[0]; fi_m2[1] = fi_m1[1];
@@ -915,21 +911,15 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
       int fiw = -1, fjw = -1;
       int fid[2];
       face_ids(x, cfac, cpz, fid[0], fid[1]);
+      sgpr_keep(touched);
       // the two faces of this column: q = 0 the i-face (x|x+1) of a core
       // row, q = 1 the j-face above (x, jr) for the bottom halo and core rows
       auto face_q = [&](int q) {
         const int f = (q == 0) ? fid[0] : fid[1];
         if (f < 0) return;
-        const double* r;
-        const double* fp;
-        if constexpr (SREC) {
-          const int fu = __builtin_amdgcn_readfirstlane(f);
-          r = rec + (size_t)fu * NREC;
-          fp = fpl + (size_t)fu * kFpN;
-        } else {
-          r = &stg[x & 1][w][q][0];
-          fp = r + NREC;
-        }
+        const int fu = __builtin_amdgcn_readfirstlane(f);
+        const double* r = rec + (size_t)fu * NREC;
+        const double* fp = fpl + (size_t)fu * kFpN;
         if (__builtin_amdgcn_readfirstlane((int)fp[kFpAct]) == 0) return;
         const int L = __builtin_amdgcn_readfirstlane((int)fp[kFpL]);
         const int R = __builtin_amdgcn_readfirstlane((int)fp[kFpR]);
@@ -953,15 +943,15 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
         if (MODE == 1) write_flux(owner ? f : -1, mom);
         if (q == 0) {
           fi_cur[0] = fc[0]; fi_cur[1] = fc[1];
-          if (owner) fiw = f;
-          if (MODE == 0) {
+          if constexpr (MODE == 0) {
+            if (owner) fiw = f;
 #pragma unroll
             for (int m = 0; m < NM; ++m) mi[m] = mom[m];
           }
         } else {
           fj_cur[0] = fc[0]; fj_cur[1] = fc[1];
-          if (owner) fjw = f;
-          if (MODE == 0) {
+          if constexpr (MODE == 0) {
+            if (owner) fjw = f;
 #pragma unroll
             for (int m = 0; m < NM; ++m) mj[m] = mom[m];
           }
@@ -983,6 +973,9 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
       if (MODE == 0) write_partials(fiw, mi, fjw, mj);
       fi_m1[0] = fi_cur[0]; fi_m1[1] = fi_cur[1];
       fj_m1[0] = fj_cur[0]; fj_m1[1] = fj_cur[1];
+      int nid[2];
+      face_ids(x + 1, cp0c, cpz, nid[0], nid[1]);  // cp0c: column x + 1
+      face_touch(rec, fpl, nid[0], nid[1], touched);
     }
   }
   if (MODE == 1) {
@@ -1950,12 +1943,9 @@ template <class T, class C, int MODE>
 static void march_rg(int rg, const Dev& g, const int* binfo, int max_nj, int nchunk, const void* h,
                      const void* b, const double* W, const double* rec, double* part, void* Dh, void* Db,
                      hipStream_t st) {
+  // 10 core rows: 12 wavefronts, 3 per SIMD, one workgroup per CU in FP64
   if (rg == 6) { march_pass<6, T, C, MODE>(g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st); return; }
-  // 10 core rows (12 wavefronts, 3 per SIMD) fit the registers and LDS only
-  // where face records are not staged: the FP64 flux pass; elsewhere 10 runs 8
-  if constexpr (MODE == 1 && sizeof(C) == 8) {
-    if (rg == 10) { march_pass<10, T, C, MODE>(g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st); return; }
-  }
+  if (rg == 10) { march_pass<10, T, C, MODE>(g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st); return; }
   march_pass<8, T, C, MODE>(g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st);
 }
 

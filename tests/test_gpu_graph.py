@@ -122,7 +122,7 @@ def test_tuning_does_not_change_results(prec):
     dt, st0 = _state(s, case, prec)
     out = None
     for kc in (16, 8, 4):
-        for re_ in (8, 6):
+        for re_ in (10, 8, 6):
             for rf in (10, 8, 6):
                 s.set_tuning(kc, re_, rf)
                 assert s.tuning() == (kc, re_, rf)
@@ -135,12 +135,13 @@ def test_tuning_does_not_change_results(prec):
     with pytest.raises(ugks.UgksError):
         s.set_tuning(32, 8, 8)
     with pytest.raises(ugks.UgksError):
-        s.set_tuning(16, 10, 8)  # 10 rows: the flux pass only
+        s.set_tuning(16, 12, 8)
+    with pytest.raises(ugks.UgksError):
+        s.set_tuning(16, 8, 4)
     st = _clone(st0)
     choice, ms = s.autotune(dt, 2, *st[:3], st[3], st[4], *st[5:])
     say("autotune", choice, ms)
-    assert choice[0] in (16, 8) and choice[1] in (8, 6) and ms > 0
-    assert choice[2] in ((10, 8, 6) if prec == ugks.F64 else (8, 6))
+    assert choice[0] in (16, 8) and choice[1] in (10, 8, 6) and choice[2] in (10, 8, 6) and ms > 0
     assert s.tuning() == choice
     assert _equal(st, st0)  # the caller's state is not written
     s.close()
