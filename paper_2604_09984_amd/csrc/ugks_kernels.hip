@@ -919,7 +919,11 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
         if (f < 0) return;
         const int fu = __builtin_amdgcn_readfirstlane(f);
         const double* r = rec + (size_t)fu * NREC;
-        const double* fp = fpl + (size_t)fu * kFpN;
+        // the face geometry in one batch of scalar loads (its fields are
+        // tested one after another below)
+        double fp[kFpN];
+#pragma unroll
+        for (int m = 0; m < kFpN; ++m) fp[m] = fpl[(size_t)fu * kFpN + m];
         if (__builtin_amdgcn_readfirstlane((int)fp[kFpAct]) == 0) return;
         const int L = __builtin_amdgcn_readfirstlane((int)fp[kFpL]);
         const int R = __builtin_amdgcn_readfirstlane((int)fp[kFpR]);
