@@ -1723,8 +1723,21 @@ __global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const doubl
 // row hand-off buffer has a zero slot below row 0 and above the last row,
 // so the couplings need no row tests; results are stored only for cells of
 // the block.
+//
+// Synchronisation per hyperplane: with one row per thread and no periodic
+// seam along j, a row's neighbours are the rows next to it, so a wavefront
+// depends only on the two wavefronts beside it (their edge rows feed its edge
+// rows, and they reuse its hand-off slots two hyperplanes later), while rows
+// inside a wavefront hand off in the wavefront's own LDS order.  Each
+// wavefront then publishes its count of finished hyperplanes in LDS and
+// waits for its two neighbours to have finished the previous one, instead of
+// a workgroup barrier: the wavefront with the least progress can always go
+// on, and the wait is bounded (kMicroSpin sleeps) so that the kernel ends in
+// any case.  Two rows per thread or a periodic j seam use the barrier.
 constexpr int kMicroRec = 14;   // C_GEO (12), C_D0, C_FLD
 constexpr int kMicroRecLds = 16;
+constexpr int kMicroProg = 8;   // doubles of LDS for the 16 progress counters
+constexpr int kMicroSpin = 1 << 20;
 
 // 1/d for d > 0 of moderate size: hardware estimate and two Newton steps
 __device__ __forceinline__ double recip_pos(double d) {
@@ -1769,14 +1782,39 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
     jl[q] = row[q] ? jr[q] : nj - 1;  // rows beyond the block read (not write) the last row's slots
     cbase[q] = c0 + ni * jl[q];       // cell (0, j)
   }
-  // LDS: hand[2][nslot + 2][KC][2] (slot s + 1 holds row s), cells[2][nslot][16],
-  // pj[ni][KC][2]
-  double* hand = smem;
-  double* cells = smem + 4 * (nslot + 2) * KC;
+  // LDS: progress counters (16 ints), hand[2][nslot + 2][KC][2] (slot s + 1
+  // holds row s), cells[2][nslot][16], pj[ni][KC][2]
+  int* prog = (int*)smem;
+  double* hand = smem + kMicroProg;
+  double* cells = hand + 4 * (nslot + 2) * KC;
   double* pjb = cells + 2 * nslot * kMicroRecLds;
   auto HND = [&](int p, int s) -> double* { return hand + ((size_t)(p * (nslot + 2) + s) * KC + lk) * 2; };
   auto CEL = [&](int p, int q) -> double* { return cells + (size_t)(p * nslot + jl[q]) * kMicroRecLds; };
   for (int e = t; e < 4 * (nslot + 2) * KC; e += blockDim.x) hand[e] = 0.0;
+  if (t < 2 * kMicroProg) prog[t] = 0;
+  const bool p2p = (R == 1) && !(D == 2 && pj);
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int nwv = (int)(blockDim.x + 63) >> 6;
+  int done = 0;  // hyperplanes finished by this wavefront (both sweeps)
+  auto prog_of = [&](int v) -> int {
+    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(&prog[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+  };
+  // before a hyperplane: both neighbour wavefronts have finished `done`
+  auto wait_neighbours = [&]() {
+    for (int spin = 0; spin < kMicroSpin; ++spin) {
+      const bool lo = (wv == 0) || prog_of(wv - 1) >= done;
+      const bool hi = (wv + 1 >= nwv) || prog_of(wv + 1) >= done;
+      if (lo && hi) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  };
+  // after a hyperplane's hand-off writes
+  auto publish = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    ++done;
+    if ((t & 63) == 0) __hip_atomic_store(&prog[wv], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
   const double vx = g.vx[kk], vy = (D == 2) ? g.vy[kk] : 0.0;
   const int HH = ni + nj - 1;
 
@@ -1881,11 +1919,13 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
       // and loads share one in-order counter)
 #pragma unroll
       for (int q = 0; q < R; ++q) stage(q, (u + 1) % P, (hp + 1) & 1);
+      if (p2p) wait_neighbours();
 #pragma unroll
       for (int q = 0; q < R; ++q) cell(q, hp, hp & 1, false, ra[q][u], rb_[q][u], 0.0, 0.0);
+      if (p2p) publish();
 #pragma unroll
       for (int q = 0; q < R; ++q) issue(q, u, hp + P, false);
-      lds_barrier();
+      if (!p2p) lds_barrier();
     }
   }
   // ---------------- backward sweep: (D + U) dF = D dF* ----------------
@@ -1904,11 +1944,13 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
       const int hp = h0 - u;
 #pragma unroll
       for (int q = 0; q < R; ++q) stage(q, (u + 1) % P, (hp - 1) & 1);
+      if (p2p) wait_neighbours();
 #pragma unroll
       for (int q = 0; q < R; ++q) cell(q, hp, hp & 1, true, ra[q][u], rb_[q][u], rf0[q][u], rf1[q][u]);
+      if (p2p) publish();
 #pragma unroll
       for (int q = 0; q < R; ++q) issue(q, u, hp - P, true);
-      lds_barrier();
+      if (!p2p) lds_barrier();
     }
   }
 }
@@ -2046,7 +2088,8 @@ void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int an
 #endif
 static size_t micro_lds_of(int dim, int max_ni, int max_nj, int any_pj, int kc) {
   const int nslot = (dim == 1) ? 1 : max_nj;
-  return sizeof(double) * (size_t)(4 * (nslot + 2) * kc + 2 * nslot * kMicroRecLds + (any_pj ? 2 * max_ni * kc : 0));
+  return sizeof(double) *
+         (size_t)(kMicroProg + 4 * (nslot + 2) * kc + 2 * nslot * kMicroRecLds + (any_pj ? 2 * max_ni * kc : 0));
 }
 
 // velocity-chunk width KC and rows per thread R of the micro sweep: the
