@@ -26,12 +26,26 @@ HBM_PEAK_GBS = 8000.0
 #   flux         flux march: read h, b; write D_h, D_b
 #   micro_rhs    micro residual: read S, f, D; write r over D
 #   micro_sweep  forward: read r, write dF*; backward: read dF*, f, write f
+#                (residual fused into the forward sweep: read D, S, f instead
+#                of r, and no micro_rhs pass)
 #   step7        Step-7 moments: read h, b
 KERNEL_VALUES = {"face_eq": 2, "flux": 4, "micro_rhs": 8, "micro_sweep": 10, "step7": 2}
+FUSED_SWEEP_VALUES = 14
 KERNEL_NAMES = {"face_eq": "k_march (face-moment pass, MODE 0)", "flux": "k_march (flux pass, MODE 1)",
                 "micro_rhs": "k_micro_rhs", "micro_sweep": "k_micro", "step7": "k_step7"}
 KERNEL_KEYS = {"face_eq": "k_march<{re}, {t}, {t}, 0>", "flux": "k_march<{rf}, {t}, {t}, 1>",
-               "micro_rhs": "k_micro_rhs<{t}>", "micro_sweep": "k_micro<2, {t}, {kc}, 3, 1>", "step7": "k_step7<{t}>"}
+               "micro_rhs": "k_micro_rhs<{t}>", "micro_sweep": "k_micro<2, {t}, {kc}, {mp}, {mr}>",
+               "step7": "k_step7<{t}>"}
+
+
+def kernel_values(micro):
+    """Algorithmic values per pair of the kernels that run for this micro
+    sweep shape (kc, rows, depth, fused)."""
+    kv = dict(KERNEL_VALUES)
+    if micro[3]:
+        del kv["micro_rhs"]
+        kv["micro_sweep"] = FUSED_SWEEP_VALUES
+    return kv
 
 
 def parse():
@@ -121,7 +135,7 @@ def run_gpu(case, prec_name, steps, warmup, adjoint_calls=0):
         adj_ms = 1e3 * (time.perf_counter() - t2) / adjoint_calls
     pairs = int((s.types() == 1).sum()) * s.nv
     out = dict(prec=prec_name, pairs=pairs, wall_s=wall_s, eager_ms=eager_ms, steps=steps, stages=prof,
-               tuning=dict(zip(("kc_max", "rg_eq", "rg_flux"), tuning)),
+               tuning=dict(zip(("kc_max", "rg_eq", "rg_flux"), tuning)), micro=s.micro_shape(),
                finite=bool(torch.isfinite(h).all().item() and torch.isfinite(W).all().item()), adjoint_ms=adj_ms)
     out["h"] = h.to(torch.float64).cpu()
     s.close()
@@ -248,16 +262,17 @@ def cpu_baseline(case, nsteps):
                       f"{pairs} pairs, {sec:.1f} s"}
 
 
-def roofline(stages, pairs, prec, tuning):
+def roofline(stages, pairs, prec, tuning, micro):
     """Dominant measured kernel: algorithmic bytes per launch over its mean
     launch time (HIP events), against the HBM peak."""
-    dom = max(KERNEL_VALUES, key=lambda k: stages[k])
+    kv = kernel_values(micro)
+    dom = max(kv, key=lambda k: stages[k])
     nbytes = 8 if prec == "f64" else 4
-    algo = KERNEL_VALUES[dom] * nbytes * pairs
+    algo = kv[dom] * nbytes * pairs
     t = stages[dom] * 1e-3
     achieved = algo / t / 1e9
     key = KERNEL_KEYS[dom].format(t="double" if prec == "f64" else "float", re=tuning["rg_eq"],
-                                  rf=tuning["rg_flux"], kc=tuning["kc_max"])
+                                  rf=tuning["rg_flux"], kc=micro[0], mp=micro[2], mr=micro[1])
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(key, prec),
             "kernel": KERNEL_NAMES[dom], "kernel_instance": key, "kernel_ms": round(stages[dom], 4), "algorithmic_bytes_per_launch": algo}
@@ -288,10 +303,11 @@ def main():
     value = r64["pairs"] * args.steps / r64["wall_s"]
     st = r64["stages"]
     per_kernel = {}
-    for k, nv in KERNEL_VALUES.items():
+    kv64 = kernel_values(r64["micro"])
+    for k, nv in kv64.items():
         gbs = nv * 8 * r64["pairs"] / (st[k] * 1e-3) / 1e9
         per_kernel[k] = {"ms": round(st[k], 4), "algorithmic_GBs": round(gbs, 1)}
-    total_values = sum(KERNEL_VALUES.values())
+    total_values = sum(kv64.values())
     line = {
         "metric": "(cell x velocity) updates/s per pseudo-step",
         "value": value,
@@ -308,11 +324,12 @@ def main():
         "config": {"workload": f"Ma5 cylinder, O-mesh 128x64 cells, {args.nvx}x{args.nvx} velocities on "
                                f"[-15,15]^2, Kn 0.01 hard sphere, isothermal wall, dt = 20 dt_s",
                    "pairs": r64["pairs"], "pseudo_steps": args.steps, "launch": "hipGraph replay, 10 per replay"},
-        "roofline": roofline(st, r64["pairs"], "f64", r64["tuning"]),
+        "roofline": roofline(st, r64["pairs"], "f64", r64["tuning"], r64["micro"]),
         "kernels_f64": per_kernel,
         "stages_ms_f64": {k: round(v, 4) for k, v in st.items()},
         "eager_ms_per_step_f64": round(r64["eager_ms"], 4),
-        "launch_shapes_f64": r64["tuning"],
+        "launch_shapes_f64": dict(r64["tuning"], micro_kc=r64["micro"][0], micro_rows=r64["micro"][1],
+                                  micro_fused_residual=bool(r64["micro"][3])),
         "hbm_algorithmic_GBs_f64": round(total_values * 8 * r64["pairs"] / (ms64 * 1e-3) / 1e9, 1),
     }
     if r32 is not None:
@@ -324,7 +341,7 @@ def main():
         line["f32"] = {"value": r32["pairs"] * args.steps / r32["wall_s"], "ms_per_step": ms32,
                        "speedup_vs_f64": ms64 / ms32,
                        "rel_l2_h_vs_f64_after_run": rel,
-                       "roofline": roofline(r32["stages"], r32["pairs"], "f32", r32["tuning"]),
+                       "roofline": roofline(r32["stages"], r32["pairs"], "f32", r32["tuning"], r32["micro"]),
                        "launch_shapes": r32["tuning"],
                        "stages_ms": {k: round(v, 4) for k, v in r32["stages"].items()}}
     if r64["adjoint_ms"] is not None:

@@ -285,6 +285,15 @@ int ugks_batch_destroy(ugks_batch* batch);
  */
 int ugks_set_tuning(ugks_ctx* ctx, int32_t kc_max, int32_t rg_eq, int32_t rg_flux);
 int ugks_get_tuning(const ugks_ctx* ctx, int32_t* kc_max, int32_t* rg_eq, int32_t* rg_flux);
+/*
+ * The micro sweep's launch under the current kc_max (host outputs, any may
+ * be NULL): velocity-chunk width, rows per thread, depth of the register ring
+ * of prefetched hyperplanes, and 1 when the micro residual (Eq.
+ * residual_micro_n+1,s) is formed inside the forward sweep instead of by a
+ * separate pass (one row per thread and chunks of 8 or more velocities).
+ * Results do not depend on it.  Returns UGKS_E_ARG for a NULL context.
+ */
+int ugks_micro_shape(const ugks_ctx* ctx, int32_t* kc, int32_t* rows, int32_t* depth, int32_t* fused);
 int ugks_autotune(ugks_ctx* ctx, double dt, int32_t n_inner, const void* h, const void* b, const double* W,
                   const double* Wn, const double* q, const void* Sh, const void* Sb, const double* Fn,
                   int32_t* choice, double* best_ms, void* stream);

@@ -1168,6 +1168,17 @@ int ugks_get_tuning(const ugks_ctx* c, int32_t* kc_max, int32_t* rg_eq, int32_t*
   return UGKS_OK;
 }
 
+int ugks_micro_shape(const ugks_ctx* c, int32_t* kc, int32_t* rows, int32_t* depth, int32_t* fused) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  int k, r, p, f;
+  micro_launch_shape(c->dim, c->prec, c->max_ni, c->max_nj, c->any_pj, c->dev.kc_max, k, r, p, f);
+  if (kc) *kc = k;
+  if (rows) *rows = r;
+  if (depth) *depth = p;
+  if (fused) *fused = f;
+  return UGKS_OK;
+}
+
 int ugks_autotune(ugks_ctx* c, double dt, int32_t n_inner, const void* h, const void* b, const double* W,
                   const double* Wn, const double* q, const void* Sh, const void* Sb, const double* Fn,
                   int32_t* choice, double* best_ms, void* stream) {

@@ -7,6 +7,11 @@ namespace ugks {
 // sets the kernels' dynamic LDS limits on the current device; 0 on success
 int init_kernel_attributes();
 void micro_shape(int dim, int max_ni, int max_nj, int any_pj, int kc_max, int& kc, int& rows);
+// the micro sweep's launch for these limits: chunk width, rows per thread,
+// register-ring depth and whether the residual is fused into the forward
+// sweep (kc = 0 when no shape fits)
+void micro_launch_shape(int dim, int prec, int max_ni, int max_nj, int any_pj, int kc_max, int& kc, int& rows,
+                        int& depth, int& fused);
 size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj, int kc_max);
 size_t macro_lds(int nt, int max_ni, int max_nj, int any_pi, int any_pj);
 

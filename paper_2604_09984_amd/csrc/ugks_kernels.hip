@@ -1674,9 +1674,33 @@ __global__ void k_resid(int nblock, int nw, const double* __restrict__ rpart, do
   out[m] = sqrt(s);
 }
 
-// micro residual r = S - f^s/dt + (D + (f+' - f^s)/tau')/2 of every field
-// pair (Eq. residual_micro_n+1,s with the stored level-n part S), written over
-// D: fully parallel, one wavefront per cell, the cell record is wave-uniform
+// micro residual r = S - f^s/dt + (D + (f+' - f^s)/tau')/2 of one pair
+// (Eq. residual_micro_n+1,s with the stored level-n part S) from the cell's
+// equilibrium and rate fields (record r), rounded to the storage type; no
+// contraction, so that the residual pass and the forward sweep that forms it
+// itself give the same bits
+template <class T>
+__device__ __forceinline__ void micro_residual(int dim, const double* r, double vx, double vy, double idt,
+                                               double f0, double f1, double s0, double s1, double d0,
+                                               double d1, double& r0, double& r1) {
+#pragma clang fp contract(off)
+  const double ux = r[C_UX], uy = r[C_UY], lam = r[C_LAM], qx = r[C_QX], qy = r[C_QY];
+  const double hn = r[C_HN], sh = r[C_SH], it = r[C_ITAU];
+  const double rt = 0.5 / lam;
+  const double cx = vx - ux, cy = (dim == 2) ? vy - uy : 0.0;
+  const double c2 = cx * cx + cy * cy;
+  const double H = hn * exp(-lam * c2);
+  const double B = (double)(3 - dim) * rt * H;
+  const double sq = sh * (cx * qx + cy * qy);
+  const double tl = 2.0 * lam * c2;
+  const double hpl = H + sq * (tl - 2.0 - dim) * H;
+  const double bpl = B + sq * (tl - dim) * (double)(3 - dim) * rt * H;
+  r0 = (double)(T)(s0 - f0 * idt + 0.5 * (d0 + (hpl - f0) * it));
+  r1 = (double)(T)(s1 - f1 * idt + 0.5 * (d1 + (bpl - f1) * it));
+}
+
+// the residual pass, written over D: fully parallel, one wavefront per cell,
+// the cell record is wave-uniform
 template <class T>
 __global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const double* __restrict__ crec,
                                                    const T* __restrict__ h, const T* __restrict__ b,
@@ -1686,24 +1710,14 @@ __global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const doubl
   const int lane = threadIdx.x & 63;
   if (c >= g.ncell || g.type[c] != 1) return;
   const double* r = crec + (size_t)c * NCREC;
-  const double ux = r[C_UX], uy = r[C_UY], lam = r[C_LAM], qx = r[C_QX], qy = r[C_QY];
-  const double hn = r[C_HN], sh = r[C_SH], it = r[C_ITAU];
   const double idt = 1.0 / dt;
-  const double rt = 0.5 / lam;
-  const int D = g.dim;
   for (int k = lane; k < g.nv; k += 64) {
     const size_t o = (size_t)c * g.nv + k;
-    const double cx = g.vx[k] - ux, cy = (D == 2) ? g.vy[k] - uy : 0.0;
-    const double c2 = cx * cx + cy * cy;
-    const double H = hn * exp(-lam * c2);
-    const double B = (double)(3 - D) * rt * H;
-    const double sq = sh * (cx * qx + cy * qy);
-    const double tl = 2.0 * lam * c2;
-    const double hpl = H + sq * (tl - 2.0 - D) * H;
-    const double bpl = B + sq * (tl - D) * (double)(3 - D) * rt * H;
-    const double f0 = (double)h[o], f1 = (double)b[o];
-    Dh[o] = (T)((double)Sh[o] - f0 * idt + 0.5 * ((double)Dh[o] + (hpl - f0) * it));
-    Db[o] = (T)((double)Sb[o] - f1 * idt + 0.5 * ((double)Db[o] + (bpl - f1) * it));
+    double r0, r1;
+    micro_residual<T>(g.dim, r, g.vx[k], (g.dim == 2) ? g.vy[k] : 0.0, idt, (double)h[o], (double)b[o],
+                      (double)Sh[o], (double)Sb[o], (double)Dh[o], (double)Db[o], r0, r1);
+    Dh[o] = (T)r0;
+    Db[o] = (T)r1;
   }
 }
 
@@ -1734,8 +1748,16 @@ __global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const doubl
 // a workgroup barrier: the wavefront with the least progress can always go
 // on, and the wait is bounded (kMicroSpin sleeps) so that the kernel ends in
 // any case.  Two rows per thread or a periodic j seam use the barrier.
-constexpr int kMicroRec = 14;   // C_GEO (12), C_D0, C_FLD
-constexpr int kMicroRecLds = 16;
+//
+// With one row per thread and chunks of 8 or more velocities the residual is
+// fused into the forward sweep: instead of reading r, written over D by
+// k_micro_rhs, it reads D, S and f^s, and the cell's equilibrium and rate
+// fields are staged with its record (the residual needs no hand-off value,
+// so it is formed before the wait for the neighbour rows).
+//
+// staged record per row: C_UX .. C_FLD (fused residual) or C_GEO .. C_FLD
+constexpr bool micro_fused(int kc, int rows) { return rows == 1 && kc >= 8; }
+constexpr int micro_rec_lds(int kc) { return kc >= 8 ? 24 : 16; }
 constexpr int kMicroProg = 8;   // doubles of LDS for the 16 progress counters
 constexpr int kMicroSpin = 1 << 20;
 
@@ -1750,9 +1772,16 @@ __device__ __forceinline__ double recip_pos(double d) {
 template <int D, class T, int KC, int P, int R>
 __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ binfo, int nslot,
                                                 const double* __restrict__ crec, T* __restrict__ h,
-                                                T* __restrict__ b, T* __restrict__ Dh, T* __restrict__ Db) {
+                                                T* __restrict__ b, T* __restrict__ Dh, T* __restrict__ Db,
+                                                const T* __restrict__ Sh, const T* __restrict__ Sb, double dt) {
   extern __shared__ double smem[];
-  constexpr int NS = (kMicroRec + KC - 1) / KC;  // record entries per lane
+  constexpr bool FUSE = micro_fused(KC, R);
+  constexpr int RB = FUSE ? C_UX : C_GEO;       // first staged record entry
+  constexpr int NRM = C_FLD + 1 - RB;           // staged entries
+  constexpr int RLD = micro_rec_lds(KC);        // LDS stride of a staged record
+  static_assert(NRM <= RLD, "staged record fits its LDS slot");
+  constexpr int NS = (NRM + KC - 1) / KC;       // record entries per lane
+  constexpr int OG = C_GEO - RB, OD = C_D0 - RB, OF = C_FLD - RB;
   const int* bi = binfo + 8 * blockIdx.y;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], pi = bi[3], pj = bi[4];
   const int t = threadIdx.x;
@@ -1787,9 +1816,9 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   int* prog = (int*)smem;
   double* hand = smem + kMicroProg;
   double* cells = hand + 4 * (nslot + 2) * KC;
-  double* pjb = cells + 2 * nslot * kMicroRecLds;
+  double* pjb = cells + 2 * nslot * RLD;
   auto HND = [&](int p, int s) -> double* { return hand + ((size_t)(p * (nslot + 2) + s) * KC + lk) * 2; };
-  auto CEL = [&](int p, int q) -> double* { return cells + (size_t)(p * nslot + jl[q]) * kMicroRecLds; };
+  auto CEL = [&](int p, int q) -> double* { return cells + (size_t)(p * nslot + jl[q]) * RLD; };
   for (int e = t; e < 4 * (nslot + 2) * KC; e += blockDim.x) hand[e] = 0.0;
   if (t < 2 * kMicroProg) prog[t] = 0;
   const bool p2p = (R == 1) && !(D == 2 && pj);
@@ -1818,24 +1847,35 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   const double vx = g.vx[kk], vy = (D == 2) ? g.vy[kk] : 0.0;
   const int HH = ni + nj - 1;
 
-  double ra[R][P], rb_[R][P], rf0[R][P], rf1[R][P];
+  // ring: r (or D when fused) for both components, f^s (backward sweep, and
+  // the fused forward sweep), S (fused forward sweep), record entries
+  double ra[R][P], rb_[R][P], rf0[R][P], rf1[R][P], rs0[R][P], rs1[R][P];
   double rr[R][P][NS];
   auto issue = [&](int q, int u, int hp, bool bwd) {
     const int i = min(max(hp - jr[q], 0), ni - 1);
     const size_t o = (size_t)(cbase[q] + i) * nv + kk;
     ra[q][u] = (double)Dh[o];
     rb_[q][u] = (double)Db[o];
-    if (bwd) { rf0[q][u] = (double)h[o]; rf1[q][u] = (double)b[o]; }
-    const double* r = crec + (size_t)(cbase[q] + i) * NCREC + C_GEO;
+    if (bwd || FUSE) { rf0[q][u] = (double)h[o]; rf1[q][u] = (double)b[o]; }
+    if (FUSE && !bwd) { rs0[q][u] = (double)Sh[o]; rs1[q][u] = (double)Sb[o]; }
+    const double* r = crec + (size_t)(cbase[q] + i) * NCREC + RB;
 #pragma unroll
-    for (int m = 0; m < NS; ++m) rr[q][u][m] = r[min(lk + KC * m, kMicroRec - 1)];  // unpredicated
+    for (int m = 0; m < NS; ++m) rr[q][u][m] = r[min(lk + KC * m, NRM - 1)];  // unpredicated
   };
   auto stage = [&](int q, int u, int p) {
     if (!row[q]) return;
     double* d = CEL(p, q);
 #pragma unroll
     for (int m = 0; m < NS; ++m)
-      if (lk + KC * m < kMicroRec) d[lk + KC * m] = rr[q][u][m];
+      if (lk + KC * m < NRM) d[lk + KC * m] = rr[q][u][m];
+  };
+  // fused forward sweep: the micro residual of the pair from D, S, f^s and
+  // the cell's staged fields, as k_micro_rhs forms it
+  const double idt = 1.0 / dt;
+  auto resid = [&](int q, int u, int p, double& a0, double& a1) {
+    // the staged record starts at entry RB of the cell record
+    micro_residual<T>(D, CEL(p, q) - RB, vx, vy, idt, rf0[q][u], rf1[q][u], rs0[q][u], rs1[q][u], ra[q][u],
+                      rb_[q][u], a0, a1);
   };
   // one cell of a sweep (nothing is written when (i, j) is outside the block)
   double ph[R], pb[R], chh[R], cbb[R];
@@ -1847,13 +1887,13 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
     const bool act = row[q] && i >= 0 && i < ni;
     const double* r = CEL(p, q);
     double ts[4];
-    double d = r[12];
+    double d = r[OD];
 #pragma unroll
     for (int s = 0; s < 2 * D; ++s) {
-      ts[s] = r[3 * s] * vx + r[3 * s + 1] * vy - r[3 * s + 2];
+      ts[s] = r[OG + 3 * s] * vx + r[OG + 3 * s + 1] * vy - r[OG + 3 * s + 2];
       d += fmax(ts[s], 0.0);
     }
-    const bool fld = act && r[13] != 0.0;
+    const bool fld = act && r[OF] != 0.0;
     // couplings: along i from the row's previous cell (zero before the first
     // cell of the sweep), along j through the hand-off buffer, and across
     // periodic seams
@@ -1919,9 +1959,15 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
       // and loads share one in-order counter)
 #pragma unroll
       for (int q = 0; q < R; ++q) stage(q, (u + 1) % P, (hp + 1) & 1);
+      double a0[R], a1[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        if constexpr (FUSE) resid(q, u, hp & 1, a0[q], a1[q]);
+        else { a0[q] = ra[q][u]; a1[q] = rb_[q][u]; }
+      }
       if (p2p) wait_neighbours();
 #pragma unroll
-      for (int q = 0; q < R; ++q) cell(q, hp, hp & 1, false, ra[q][u], rb_[q][u], 0.0, 0.0);
+      for (int q = 0; q < R; ++q) cell(q, hp, hp & 1, false, a0[q], a1[q], 0.0, 0.0);
       if (p2p) publish();
 #pragma unroll
       for (int q = 0; q < R; ++q) issue(q, u, hp + P, false);
@@ -2089,7 +2135,7 @@ void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int an
 static size_t micro_lds_of(int dim, int max_ni, int max_nj, int any_pj, int kc) {
   const int nslot = (dim == 1) ? 1 : max_nj;
   return sizeof(double) *
-         (size_t)(kMicroProg + 4 * (nslot + 2) * kc + 2 * nslot * kMicroRecLds + (any_pj ? 2 * max_ni * kc : 0));
+         (size_t)(kMicroProg + 4 * (nslot + 2) * kc + 2 * nslot * micro_rec_lds(kc) + (any_pj ? 2 * max_ni * kc : 0));
 }
 
 // velocity-chunk width KC and rows per thread R of the micro sweep: the
@@ -2115,52 +2161,71 @@ size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj, int kc_max) {
 }
 
 // ring depth of the sweep: two rows per thread (of FP64 values, or with
-// records spread over few lanes) take the registers a third slot would need
+// records spread over few lanes) and the fused residual (six values per
+// pair) take the registers a third slot would need
 template <class T, int KC, int R>
-constexpr int micro_depth() { return (R == 2 && (sizeof(T) == 8 || KC <= 4)) ? 2 : UGKS_MICRO_DEPTH; }
+constexpr int micro_depth() {
+  return ((R == 2 && (sizeof(T) == 8 || KC <= 4)) || micro_fused(KC, R)) ? 2 : UGKS_MICRO_DEPTH;
+}
+
+void micro_launch_shape(int dim, int prec, int max_ni, int max_nj, int any_pj, int kc_max, int& kc, int& rows,
+                        int& depth, int& fused) {
+  micro_shape(dim, max_ni, max_nj, any_pj, kc_max, kc, rows);
+  if (dim == 1) { kc = 64; rows = 1; }
+  fused = micro_fused(kc, rows) ? 1 : 0;
+  depth = (prec == 0) ? ((rows == 2 || fused) ? 2 : UGKS_MICRO_DEPTH)
+                      : (((rows == 2 && kc <= 4) || fused) ? 2 : UGKS_MICRO_DEPTH);
+  if (kc == 0) depth = fused = 0;
+}
 
 template <int D, class T, int KC, int R>
-static void micro_t(const Dev& g, const int* binfo, int nslot, size_t lds, const double* crec, void* h, void* b,
+static void micro_t(const Dev& g, const int* binfo, int nslot, size_t lds, double dt, const double* crec, void* h,
+                    void* b, const void* Sh, const void* Sb,
                     void* Dh, void* Db, hipStream_t st) {
   constexpr int P = micro_depth<T, KC, R>();
   dim3 grid((unsigned)((g.nv + KC - 1) / KC), (unsigned)g.nblock);
   int threads = ((((nslot + R - 1) / R) * KC + 63) / 64) * 64;
-  k_micro<D, T, KC, P, R><<<grid, threads, lds, st>>>(g, binfo, nslot, crec, (T*)h, (T*)b, (T*)Dh, (T*)Db);
+  k_micro<D, T, KC, P, R><<<grid, threads, lds, st>>>(g, binfo, nslot, crec, (T*)h, (T*)b, (T*)Dh, (T*)Db,
+                                                       (const T*)Sh, (const T*)Sb, dt);
 }
 
 template <class T>
-static void micro_prec(const Dev& g, const int* binfo, int KC, int R, int nslot, size_t lds, const double* crec,
+static void micro_prec(const Dev& g, const int* binfo, int KC, int R, int nslot, size_t lds, double dt,
+                       const double* crec, const void* Sh, const void* Sb,
                        void* h, void* b, void* Dh, void* Db, hipStream_t st) {
-  if (g.dim == 1) { micro_t<1, T, 64, 1>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); return; }
+  if (g.dim == 1) { micro_t<1, T, 64, 1>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); return; }
   switch (KC * 4 + R) {
-    case 16 * 4 + 1: micro_t<2, T, 16, 1>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
-    case 16 * 4 + 2: micro_t<2, T, 16, 2>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
-    case 8 * 4 + 1: micro_t<2, T, 8, 1>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
-    case 8 * 4 + 2: micro_t<2, T, 8, 2>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
-    case 4 * 4 + 1: micro_t<2, T, 4, 1>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
-    case 4 * 4 + 2: micro_t<2, T, 4, 2>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
-    case 2 * 4 + 1: micro_t<2, T, 2, 1>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
-    default: micro_t<2, T, 2, 2>(g, binfo, nslot, lds, crec, h, b, Dh, Db, st); break;
+    case 16 * 4 + 1: micro_t<2, T, 16, 1>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); break;
+    case 16 * 4 + 2: micro_t<2, T, 16, 2>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); break;
+    case 8 * 4 + 1: micro_t<2, T, 8, 1>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); break;
+    case 8 * 4 + 2: micro_t<2, T, 8, 2>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); break;
+    case 4 * 4 + 1: micro_t<2, T, 4, 1>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); break;
+    case 4 * 4 + 2: micro_t<2, T, 4, 2>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); break;
+    case 2 * 4 + 1: micro_t<2, T, 2, 1>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); break;
+    default: micro_t<2, T, 2, 2>(g, binfo, nslot, lds, dt, crec, h, b, Sh, Sb, Dh, Db, st); break;
   }
 }
 
 void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_nj, int any_pj, double dt,
                   const double* crec, void* h, void* b, const void* Sh, const void* Sb, void* Dh, void* Db,
                   hipStream_t st, hipEvent_t* ev) {
-  if (prec == 0)
-    k_micro_rhs<double><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const double*)h, (const double*)b,
-                                                      (const double*)Sh, (const double*)Sb, (double*)Dh,
-                                                      (double*)Db);
-  else
-    k_micro_rhs<float><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const float*)h, (const float*)b,
-                                                     (const float*)Sh, (const float*)Sb, (float*)Dh, (float*)Db);
-  if (ev) (void)hipEventRecord(ev[0], st);
   int KC, R;
   micro_shape(g.dim, max_ni, max_nj, any_pj, g.kc_max, KC, R);
+  // the residual pass, unless the forward sweep of this shape forms it
+  if (!micro_fused(KC, R)) {
+    if (prec == 0)
+      k_micro_rhs<double><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const double*)h, (const double*)b,
+                                                        (const double*)Sh, (const double*)Sb, (double*)Dh,
+                                                        (double*)Db);
+    else
+      k_micro_rhs<float><<<nb4(g.ncell), 256, 0, st>>>(g, dt, crec, (const float*)h, (const float*)b,
+                                                       (const float*)Sh, (const float*)Sb, (float*)Dh, (float*)Db);
+  }
+  if (ev) (void)hipEventRecord(ev[0], st);
   const int nslot = (g.dim == 1) ? 1 : max_nj;
   const size_t lds = micro_lds_of(g.dim, max_ni, max_nj, any_pj, KC);
-  if (prec == 0) micro_prec<double>(g, binfo, KC, R, nslot, lds, crec, h, b, Dh, Db, st);
-  else micro_prec<float>(g, binfo, KC, R, nslot, lds, crec, h, b, Dh, Db, st);
+  if (prec == 0) micro_prec<double>(g, binfo, KC, R, nslot, lds, dt, crec, Sh, Sb, h, b, Dh, Db, st);
+  else micro_prec<float>(g, binfo, KC, R, nslot, lds, dt, crec, Sh, Sb, h, b, Dh, Db, st);
 }
 
 // dynamic LDS limits of the sweep kernels, set once per device before any

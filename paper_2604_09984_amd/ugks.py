@@ -70,6 +70,7 @@ def lib():
         L.ugks_batch_step.argtypes = [vp, C.POINTER(d), i32, pa, pa, pa, pa, pa, pa, pa, pa, pa, vp]
         L.ugks_set_tuning.argtypes = [vp, i32, i32, i32]
         L.ugks_get_tuning.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.ugks_micro_shape.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.ugks_autotune.argtypes = [vp, d, i32, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), C.POINTER(d), vp]
         L.ugks_set_wall_rt.argtypes = [vp, i32, i32, d]
         L.ugks_set_block_velocity.argtypes = [vp, i32, d, d, d]
@@ -88,7 +89,7 @@ def exported_symbols():
             "ugks_get_types", "ugks_set_overset", "overset_assemble", "ugks_get_overset", "ugks_maxwellian",
             "ugks_moments", "ugks_heatflux", "ugks_flux", "overset_interp", "ugks_begin_step", "ugks_step",
             "ugks_timesteps", "ugks_step_profile", "ugks_step_graph", "ugks_batch_create", "ugks_batch_step",
-            "ugks_batch_destroy", "ugks_set_tuning", "ugks_get_tuning", "ugks_autotune", "ugks_set_wall_rt",
+            "ugks_batch_destroy", "ugks_set_tuning", "ugks_get_tuning", "ugks_micro_shape", "ugks_autotune", "ugks_set_wall_rt",
             "ugks_last_flux", "ugks_set_block_velocity", "ugks_face_geometry", "ugks_overset_rows",
             "ugks_flux_adjoint", "ugks_step_adjoint", "ugks_begin_step_adjoint",
             "ugks_last_error"]
@@ -266,6 +267,13 @@ class Solver:
     def tuning(self):
         v = [C.c_int32() for _ in range(3)]
         _check(lib().ugks_get_tuning(self.ctx, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def micro_shape(self):
+        """(chunk width, rows per thread, ring depth, fused residual) of the
+        micro sweep under the current tuning."""
+        v = [C.c_int32() for _ in range(4)]
+        _check(lib().ugks_micro_shape(self.ctx, *[C.byref(x) for x in v]))
         return tuple(x.value for x in v)
 
     def autotune(self, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, stream=None):

@@ -126,6 +126,9 @@ def test_tuning_does_not_change_results(prec):
             for rf in (10, 8, 6):
                 s.set_tuning(kc, re_, rf)
                 assert s.tuning() == (kc, re_, rf)
+                # 128 x 64 cells: one row per thread; chunks of 8 or more
+                # velocities form the residual inside the forward sweep
+                assert s.micro_shape() == ((kc, 1, 2, 1) if kc >= 8 else (kc, 1, 3, 0))
                 st = _clone(st0)
                 s.step(dt, 2, *st[:3], st[3], st[4], *st[5:])
                 if out is None:
