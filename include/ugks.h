@@ -278,7 +278,7 @@ int ugks_batch_destroy(ugks_batch* batch);
  * and flux march kernels (10, 8 or 6 each).  ugks_autotune times n_inner
  * pseudo-iterations run on device copies of the given state (the caller's
  * arrays are not written; scratch is allocated for the call) for kc_max
- * {16, 8}, then rg_eq {8, 10, 6} and then rg_flux {8, 10, 6}, each with the
+ * {16, 8, 4}, then rg_eq {8, 10, 6} and then rg_flux {8, 10, 6}, each with the
  * others at their best so far (the three act on different kernels), keeps
  * the fastest and reports it in host choice[3] and its mean milliseconds per
  * pseudo-iteration in *best_ms.  Synchronous.
@@ -290,7 +290,7 @@ int ugks_get_tuning(const ugks_ctx* ctx, int32_t* kc_max, int32_t* rg_eq, int32_
  * be NULL): velocity-chunk width, rows per thread, depth of the register ring
  * of prefetched hyperplanes, and 1 when the micro residual (Eq.
  * residual_micro_n+1,s) is formed inside the forward sweep instead of by a
- * separate pass (one row per thread and chunks of 8 or more velocities).
+ * separate pass (2D, one row per thread and chunks of 8 or 16 velocities).
  * Results do not depend on it.  Returns UGKS_E_ARG for a NULL context.
  */
 int ugks_micro_shape(const ugks_ctx* ctx, int32_t* kc, int32_t* rows, int32_t* depth, int32_t* fused);

@@ -1223,6 +1223,7 @@ int ugks_autotune(ugks_ctx* c, double dt, int32_t n_inner, const void* h, const 
   };
   consider(16, 8, 8);
   consider(8, 8, 8);
+  consider(4, 8, 8);
   const int kc1 = bk;
   for (int re : {10, 6}) consider(kc1, re, 8);
   const int re1 = be;

@@ -1749,15 +1749,17 @@ __global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const doubl
 // on, and the wait is bounded (kMicroSpin sleeps) so that the kernel ends in
 // any case.  Two rows per thread or a periodic j seam use the barrier.
 //
-// With one row per thread and chunks of 8 or more velocities the residual is
-// fused into the forward sweep: instead of reading r, written over D by
+// With one row per thread and chunks of 8 or 16 velocities (2D) the residual
+// is fused into the forward sweep: instead of reading r, written over D by
 // k_micro_rhs, it reads D, S and f^s, and the cell's equilibrium and rate
 // fields are staged with its record (the residual needs no hand-off value,
-// so it is formed before the wait for the neighbour rows).
+// so it is formed before the wait for the neighbour rows).  The 1D sweep (one
+// wavefront per chunk) keeps the separate, fully parallel residual pass,
+// which would otherwise lengthen its sequential chain.
 //
 // staged record per row: C_UX .. C_FLD (fused residual) or C_GEO .. C_FLD
-constexpr bool micro_fused(int kc, int rows) { return rows == 1 && kc >= 8; }
-constexpr int micro_rec_lds(int kc) { return kc >= 8 ? 24 : 16; }
+constexpr bool micro_fused(int kc, int rows) { return rows == 1 && kc >= 8 && kc <= 16; }
+constexpr int micro_rec_lds(int kc, int rows) { return micro_fused(kc, rows) ? 24 : 16; }
 constexpr int kMicroProg = 8;   // doubles of LDS for the 16 progress counters
 constexpr int kMicroSpin = 1 << 20;
 
@@ -1778,7 +1780,7 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   constexpr bool FUSE = micro_fused(KC, R);
   constexpr int RB = FUSE ? C_UX : C_GEO;       // first staged record entry
   constexpr int NRM = C_FLD + 1 - RB;           // staged entries
-  constexpr int RLD = micro_rec_lds(KC);        // LDS stride of a staged record
+  constexpr int RLD = micro_rec_lds(KC, R);     // LDS stride of a staged record
   static_assert(NRM <= RLD, "staged record fits its LDS slot");
   constexpr int NS = (NRM + KC - 1) / KC;       // record entries per lane
   constexpr int OG = C_GEO - RB, OD = C_D0 - RB, OF = C_FLD - RB;
@@ -2132,23 +2134,24 @@ void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int an
 #ifndef UGKS_MICRO_DEPTH
 #define UGKS_MICRO_DEPTH 3
 #endif
-static size_t micro_lds_of(int dim, int max_ni, int max_nj, int any_pj, int kc) {
+static size_t micro_lds_of(int dim, int max_ni, int max_nj, int any_pj, int kc, int rows) {
   const int nslot = (dim == 1) ? 1 : max_nj;
-  return sizeof(double) *
-         (size_t)(kMicroProg + 4 * (nslot + 2) * kc + 2 * nslot * micro_rec_lds(kc) + (any_pj ? 2 * max_ni * kc : 0));
+  return sizeof(double) * (size_t)(kMicroProg + 4 * (nslot + 2) * kc + 2 * nslot * micro_rec_lds(kc, rows) +
+                                   (any_pj ? 2 * max_ni * kc : 0));
 }
 
 // velocity-chunk width KC and rows per thread R of the micro sweep: the
-// widest chunk up to kc_max whose LDS fits 160 KiB, one row per thread
-// before two, with KC * ceil(nj / R) <= 1024 threads; kc = 0 when none fits
+// widest chunk up to kc_max, one row per thread before two, with
+// KC * ceil(nj / R) <= 1024 threads and LDS within 160 KiB; kc = 0 when none
+// fits
 void micro_shape(int dim, int max_ni, int max_nj, int any_pj, int kc_max, int& kc, int& rows) {
   rows = 1;
   if (dim == 1) { kc = 64; return; }
-  for (kc = kc_max; kc >= 2; kc >>= 1) {
-    if (micro_lds_of(dim, max_ni, max_nj, any_pj, kc) > 160 * 1024) continue;
+  for (kc = kc_max; kc >= 2; kc >>= 1)
     for (rows = 1; rows <= 2; ++rows)
-      if (kc * ((max_nj + rows - 1) / rows) <= 1024) return;
-  }
+      if (kc * ((max_nj + rows - 1) / rows) <= 1024 &&
+          micro_lds_of(dim, max_ni, max_nj, any_pj, kc, rows) <= 160 * 1024)
+        return;
   kc = 0;
   rows = 1;
 }
@@ -2157,7 +2160,7 @@ size_t micro_lds(int dim, int max_ni, int max_nj, int any_pj, int kc_max) {
   int kc, rows;
   micro_shape(dim, max_ni, max_nj, any_pj, kc_max, kc, rows);
   if (kc == 0) return (size_t)1 << 40;  // no shape fits
-  return micro_lds_of(dim, max_ni, max_nj, any_pj, kc);
+  return micro_lds_of(dim, max_ni, max_nj, any_pj, kc, rows);
 }
 
 // ring depth of the sweep: two rows per thread (of FP64 values, or with
@@ -2223,7 +2226,7 @@ void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_
   }
   if (ev) (void)hipEventRecord(ev[0], st);
   const int nslot = (g.dim == 1) ? 1 : max_nj;
-  const size_t lds = micro_lds_of(g.dim, max_ni, max_nj, any_pj, KC);
+  const size_t lds = micro_lds_of(g.dim, max_ni, max_nj, any_pj, KC, R);
   if (prec == 0) micro_prec<double>(g, binfo, KC, R, nslot, lds, dt, crec, Sh, Sb, h, b, Dh, Db, st);
   else micro_prec<float>(g, binfo, KC, R, nslot, lds, dt, crec, Sh, Sb, h, b, Dh, Db, st);
 }
