@@ -1738,16 +1738,20 @@ __global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const doubl
 // so the couplings need no row tests; results are stored only for cells of
 // the block.
 //
-// Synchronisation per hyperplane: with one row per thread and no periodic
-// seam along j, a row's neighbours are the rows next to it, so a wavefront
-// depends only on the two wavefronts beside it (their edge rows feed its edge
-// rows, and they reuse its hand-off slots two hyperplanes later), while rows
-// inside a wavefront hand off in the wavefront's own LDS order.  Each
-// wavefront then publishes its count of finished hyperplanes in LDS and
-// waits for its two neighbours to have finished the previous one, instead of
-// a workgroup barrier: the wavefront with the least progress can always go
-// on, and the wait is bounded (kMicroSpin sleeps) so that the kernel ends in
-// any case.  Two rows per thread or a periodic j seam use the barrier.
+// Synchronisation per hyperplane: without a periodic seam along j a row's
+// neighbours are the rows next to it, so a wavefront depends only on the two
+// wavefronts beside it (their edge rows feed its edge rows, and they reuse
+// its hand-off slots two hyperplanes later), while rows inside a wavefront
+// hand off in the wavefront's own LDS order.  With two rows per thread (rows
+// jt and jt + NTR) the first wavefront's second rows and the last
+// wavefront's first rows are neighbours too, so the wavefronts form a ring;
+// this needs every thread to own distinct rows (NTR * KC a whole number of
+// wavefronts).  Each wavefront then publishes its count of finished
+// hyperplanes in LDS and waits for its two neighbours to have finished the
+// previous one, instead of a workgroup barrier: the wavefront with the least
+// progress can always go on, and the wait is bounded (kMicroSpin sleeps) so
+// that the kernel ends in any case.  A periodic j seam, or threads beyond
+// NTR * KC, use the barrier.
 //
 // With one row per thread and chunks of 8 or 16 velocities (2D) the residual
 // is fused into the forward sweep: instead of reading r, written over D by
@@ -1823,9 +1827,12 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   auto CEL = [&](int p, int q) -> double* { return cells + (size_t)(p * nslot + jl[q]) * RLD; };
   for (int e = t; e < 4 * (nslot + 2) * KC; e += blockDim.x) hand[e] = 0.0;
   if (t < 2 * kMicroProg) prog[t] = 0;
-  const bool p2p = (R == 1) && !(D == 2 && pj);
+  const bool p2p = !(D == 2 && pj) && (R == 1 || NTR * KC == (int)blockDim.x);
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int nwv = (int)(blockDim.x + 63) >> 6;
+  // neighbour wavefronts (-1: none); a ring for two rows per thread
+  const int lo_wv = (R == 1) ? wv - 1 : (wv + nwv - 1) % nwv;
+  const int hi_wv = (R == 1) ? ((wv + 1 < nwv) ? wv + 1 : -1) : (wv + 1) % nwv;
   int done = 0;  // hyperplanes finished by this wavefront (both sweeps)
   auto prog_of = [&](int v) -> int {
     return __builtin_amdgcn_readfirstlane(__hip_atomic_load(&prog[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
@@ -1833,8 +1840,8 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   // before a hyperplane: both neighbour wavefronts have finished `done`
   auto wait_neighbours = [&]() {
     for (int spin = 0; spin < kMicroSpin; ++spin) {
-      const bool lo = (wv == 0) || prog_of(wv - 1) >= done;
-      const bool hi = (wv + 1 >= nwv) || prog_of(wv + 1) >= done;
+      const bool lo = (lo_wv < 0) || (lo_wv == wv) || prog_of(lo_wv) >= done;
+      const bool hi = (hi_wv < 0) || (hi_wv == wv) || prog_of(hi_wv) >= done;
       if (lo && hi) break;
       __builtin_amdgcn_s_sleep(1);
     }
