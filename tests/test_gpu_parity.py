@@ -39,11 +39,14 @@ def small_cases():
     dense = wl.periodic_box(2, 8, 6, 10, kn=1e-5)
     dense.name = "continuum_box"
     # blocks of 70, 130 and 300 rows: the sweep's two-rows-per-thread shapes
-    # (16 x 2, 8 x 2 and 4 x 2 velocities x rows)
+    # (16 x 2, 8 x 2 and 4 x 2 velocities x rows) with threads beyond the
+    # rows (workgroup barrier); 96 and 128 rows: 16 x 2 filling 12 and 16
+    # whole wavefronts (the wavefronts' ring of neighbour waits)
     return [wl.sod_1d(ncell=40, nv=33), wl.periodic_box(1, 12, 1, 17), wl.periodic_box(2, 8, 6, 10),
             ffbox, mixbox, free, dense,
             wl.cylinder(ni=16, nj=8, nvx=16), wl.cavity(8, 12), wl.cavity(6, 10, periodic_x=True),
-            mov, wallmov, wl.channel(6, 70, 8), wl.channel(5, 130, 6), wl.channel(4, 300, 6)]
+            mov, wallmov, wl.channel(6, 70, 8), wl.channel(5, 130, 6), wl.channel(4, 300, 6),
+            wl.channel(4, 96, 6), wl.channel(3, 128, 6)]
 
 
 CASES = small_cases()
