@@ -1487,6 +1487,11 @@ size_t macro_lds(int nt, int max_ni, int max_nj, int any_pi, int any_pj) {
                                    (any_pi ? 2 * kMacSlot * max_nj : 0));
 }
 
+// rows of records in flight in the one-wavefront macro sweep
+#ifndef UGKS_MACRO_RING
+#define UGKS_MACRO_RING 3
+#endif
+
 // NTB: the launch's thread bound (64 for blocks up to 64 cells tall: one
 // wavefront, whose ring of prefetched rows then has the register file to
 // itself; 512 otherwise)
@@ -1572,32 +1577,17 @@ __global__ __launch_bounds__(NTB) void k_macro_sweep(Dev g, const int* __restric
   };
   // ring of three rows for a one-wavefront launch; of two (prefetch one
   // hyperplane ahead) for the wide launch, whose registers it would exceed
-  constexpr int RING = (NTB == 64) ? 3 : 2;
-  MacroRow ra, rb, rc;
-  macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, 0, ra);
-  if constexpr (RING == 3) {
-    macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, 1, rb);
-    for (int h = 0; h < H; h += 3) {
-      macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + 2, rc);
-      fwd_step(h, ra);
-      lds_barrier();
-      if (h + 1 >= H) break;
-      macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + 3, ra);
-      fwd_step(h + 1, rb);
-      lds_barrier();
-      if (h + 2 >= H) break;
-      macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + 4, rb);
-      fwd_step(h + 2, rc);
-      lds_barrier();
-    }
-  } else {
-    for (int h = 0; h < H; h += 2) {
-      macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + 1, rb);
-      fwd_step(h, ra);
-      lds_barrier();
-      if (h + 1 >= H) break;
-      macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + 2, ra);
-      fwd_step(h + 1, rb);
+  constexpr int RING = (NTB == 64) ? UGKS_MACRO_RING : 2;
+  MacroRow ring[RING];
+#pragma unroll
+  for (int u = 0; u < RING - 1; ++u) macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, u, ring[u]);
+  for (int h0 = 0; h0 < H; h0 += RING) {
+#pragma unroll
+    for (int u = 0; u < RING; ++u) {
+      const int h = h0 + u;
+      if (h >= H) break;
+      macro_row_load<D>(mac, dWs, 0, ni, nj, c0, j, h + RING - 1, ring[(u + RING - 1) % RING]);
+      fwd_step(h, ring[u]);
       lds_barrier();
     }
   }
@@ -1636,30 +1626,15 @@ __global__ __launch_bounds__(NTB) void k_macro_sweep(Dev g, const int* __restric
       if (pj && j == nj - 1) pjb[4 * i + m] = x[m];
     }
   };
-  macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, H - 1, ra);
-  if constexpr (RING == 3) {
-    macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, H - 2, rb);
-    for (int h = H - 1; h >= 0; h -= 3) {
-      macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 2, rc);
-      bwd_step(h, ra);
-      lds_barrier();
-      if (h - 1 < 0) break;
-      macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 3, ra);
-      bwd_step(h - 1, rb);
-      lds_barrier();
-      if (h - 2 < 0) break;
-      macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 4, rb);
-      bwd_step(h - 2, rc);
-      lds_barrier();
-    }
-  } else {
-    for (int h = H - 1; h >= 0; h -= 2) {
-      macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 1, rb);
-      bwd_step(h, ra);
-      lds_barrier();
-      if (h - 1 < 0) break;
-      macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - 2, ra);
-      bwd_step(h - 1, rb);
+#pragma unroll
+  for (int u = 0; u < RING - 1; ++u) macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, H - 1 - u, ring[u]);
+  for (int h0 = H - 1; h0 >= 0; h0 -= RING) {
+#pragma unroll
+    for (int u = 0; u < RING; ++u) {
+      const int h = h0 - u;
+      if (h < 0) break;
+      macro_row_load<D>(mac, dWs, 1, ni, nj, c0, j, h - (RING - 1), ring[(u + RING - 1) % RING]);
+      bwd_step(h, ring[u]);
       lds_barrier();
     }
   }
