@@ -1550,9 +1550,9 @@ __global__ __launch_bounds__(NTB) void k_macro_sweep(Dev g, const int* __restric
   __syncthreads();
   const int H = ni + nj - 1;
   double prev[4] = {0, 0, 0, 0}, cw[4] = {0, 0, 0, 0};
-  // forward sweep: (D + L) dW* = R.  The records of hyperplane h + 2 are
-  // loaded while h is solved (a ring of three rows in registers): the sweep
-  // is one wavefront per block, so each hyperplane's latency is exposed
+  // forward sweep: (D + L) dW* = R.  The records of hyperplane h + RING - 1
+  // are loaded while h is solved (a ring of rows in registers): the sweep is
+  // one wavefront per block, so each hyperplane's latency is exposed
   auto fwd_step = [&](int h, const MacroRow& cur) __attribute__((always_inline)) {
     if (!cur.ok) return;
     const int i = h - j, c = cur.c;
@@ -1575,8 +1575,9 @@ __global__ __launch_bounds__(NTB) void k_macro_sweep(Dev g, const int* __restric
       if (pj && j == 0) pjb[4 * i + m] = x[m];
     }
   };
-  // ring of three rows for a one-wavefront launch; of two (prefetch one
-  // hyperplane ahead) for the wide launch, whose registers it would exceed
+  // ring of UGKS_MACRO_RING rows for a one-wavefront launch; of two
+  // (prefetch one hyperplane ahead) for the wide launch, whose registers a
+  // deeper ring would exceed
   constexpr int RING = (NTB == 64) ? UGKS_MACRO_RING : 2;
   MacroRow ring[RING];
 #pragma unroll
