@@ -2154,14 +2154,28 @@ constexpr int micro_depth() {
   return ((R == 2 && (sizeof(T) == 8 || KC <= 4)) || micro_fused(KC, R)) ? 2 : UGKS_MICRO_DEPTH;
 }
 
+// ring depth of the launched instance (the kernels' own rule)
+template <class T>
+static int micro_depth_of(int kc, int rows) {
+  switch (kc * 4 + rows) {
+    case 64 * 4 + 1: return micro_depth<T, 64, 1>();
+    case 16 * 4 + 1: return micro_depth<T, 16, 1>();
+    case 16 * 4 + 2: return micro_depth<T, 16, 2>();
+    case 8 * 4 + 1: return micro_depth<T, 8, 1>();
+    case 8 * 4 + 2: return micro_depth<T, 8, 2>();
+    case 4 * 4 + 1: return micro_depth<T, 4, 1>();
+    case 4 * 4 + 2: return micro_depth<T, 4, 2>();
+    case 2 * 4 + 1: return micro_depth<T, 2, 1>();
+    case 2 * 4 + 2: return micro_depth<T, 2, 2>();
+    default: return 0;
+  }
+}
+
 void micro_launch_shape(int dim, int prec, int max_ni, int max_nj, int any_pj, int kc_max, int& kc, int& rows,
                         int& depth, int& fused) {
   micro_shape(dim, max_ni, max_nj, any_pj, kc_max, kc, rows);
-  if (dim == 1) { kc = 64; rows = 1; }
-  fused = micro_fused(kc, rows) ? 1 : 0;
-  depth = (prec == 0) ? ((rows == 2 || fused) ? 2 : UGKS_MICRO_DEPTH)
-                      : (((rows == 2 && kc <= 4) || fused) ? 2 : UGKS_MICRO_DEPTH);
-  if (kc == 0) depth = fused = 0;
+  fused = (kc > 0 && micro_fused(kc, rows)) ? 1 : 0;
+  depth = (prec == 0) ? micro_depth_of<double>(kc, rows) : micro_depth_of<float>(kc, rows);
 }
 
 template <int D, class T, int KC, int R>
