@@ -509,6 +509,8 @@ __global__ __launch_bounds__(256) void k_flux(Dev g, const T* __restrict__ h, co
 // flux mode the core rows then gather the divergence of cell x.  Face
 // moments (MODE 0) and macro fluxes (MODE 1) are written as per-chunk
 // partial sums, reduced over chunks by the finalize kernels in a fixed order.
+// Face records are wave-uniform and come through the scalar cache, their
+// lines requested one column ahead.
 // ------------------------------------------------------------------------
 constexpr int kMomP = 9;   // partial values per face and chunk, MODE 0
 constexpr int kFluxP = 4;  // MODE 1
@@ -1700,9 +1702,9 @@ __global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const doubl
 // micro LU-SGS (Eq. dualTimeStepping_micro): forward and backward sweep of
 // one velocity chunk (KC lanes) of one block, R rows per thread slot (rows
 // j, j + ceil(nj/R), ...: cells of one hyperplane in different rows are
-// independent), in hyperplane order.  Dh/Db hold the residual r on entry and
-// dF* after the forward sweep; h, b are updated to f^{s+1} by the backward
-// sweep.
+// independent), in hyperplane order.  Dh/Db hold the residual r on entry (D
+// when the forward sweep forms the residual itself, below) and dF* after the
+// forward sweep; h, b are updated to f^{s+1} by the backward sweep.
 //
 // Latency and issue: everything a hyperplane needs from global memory (its
 // residual or dF*, h, b, and the cell's coefficient record: face geometry,
