@@ -387,13 +387,13 @@ int upload_plans(ugks_ctx* c) {
   c->cplan.assign((size_t)kCpN * c->ncell, 0.0);
   for (int n = 0; n < c->ncell; ++n) {
     double* P = &c->cplan[(size_t)kCpN * n];
-    P[kCpType] = c->type[n];
+    P[kCpType] = cp_int_entry(c->type[n]);
     for (int s = 0; s < 4; ++s) {
       const int f = c->cf[4 * (size_t)n + s];
-      P[kCpNb + s] = c->nb[4 * (size_t)n + s];
+      P[kCpNb + s] = cp_int_entry(c->nb[4 * (size_t)n + s]);
       P[kCpG + s] = c->G[4 * (size_t)n + s];
       P[kCpS + s] = (f >= 0) ? c->fgeo[8 * (size_t)f + 2] : 0.0;
-      P[kCpFace + s] = f;
+      P[kCpFace + s] = cp_int_entry(f);
     }
     P[kCpIvol] = 1.0 / c->vol[n];
   }

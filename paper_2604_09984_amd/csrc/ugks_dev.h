@@ -45,10 +45,18 @@ __device__ __forceinline__ void record_derived(double* r) {
   r[R_SQY] = r[R_SH] * r[R_QY];
 }
 
-// packed per-cell table of the march kernels (double, exact small integers
-// for kinds and indices): kind, neighbour codes per slot, J^{-T}, face area
-// per slot (0 without a face), 1/|Omega|, face id per slot (-1 none)
+// packed per-cell table of the march kernels (one double per entry; kinds
+// and indices as int32 in the low word, high word zero, so that a lane read
+// of the low word gives the integer): kind, neighbour codes per slot,
+// J^{-T}, face area per slot (0 without a face), 1/|Omega|, face id per slot
+// (-1 none)
 enum : int { kCpType = 0, kCpNb = 1, kCpG = 5, kCpS = 9, kCpIvol = 13, kCpFace = 14, kCpN = 20 };
+inline double cp_int_entry(int v) {
+  const unsigned long long u = (unsigned long long)(unsigned int)v;
+  double d;
+  __builtin_memcpy(&d, &u, sizeof d);
+  return d;
+}
 // packed per-face table: unit normal, area, grid velocity, offsets from the
 // centroids of the low and high cells to the face centre (zero on a ghost or
 // wall side), low and high cell or ghost code, 1 if the face carries flux

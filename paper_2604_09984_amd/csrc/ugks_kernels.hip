@@ -581,9 +581,10 @@ __device__ __forceinline__ Side<C> side_ghost(const Dev& g, const LD6<C>& L, int
 }
 
 // lane-held tables: lane l of a wavefront holds entry l of a record; a
-// wave-uniform entry is read back with two lane reads
+// wave-uniform entry is read back with two lane reads, an int32 entry (low
+// word) with one
 __device__ __forceinline__ double rec_at(double v, int l) { return lane_read(v, l); }
-__device__ __forceinline__ int rec_int(double v, int l) { return (int)lane_read(v, l); }
+__device__ __forceinline__ int rec_int(double v, int l) { return __builtin_amdgcn_readlane(__double2loint(v), l); }
 
 // scalar-cache prefetch of the records of two faces: one word of each
 // 64-byte line of the face record (NREC doubles, 64-byte aligned) and of its
@@ -678,7 +679,7 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   // outside the block
   auto cplan_load = [&](int x) -> double {
     const int xw = col(x);
-    if (prow < 0 || xw < 0) return (lane == kCpType) ? 0.0 : -1.0;
+    if (prow < 0 || xw < 0) return __hiloint2double(0, (lane == kCpType) ? 0 : -1);
     return (lane < kCpN) ? g.cplan[(size_t)cell(xw, prow) * kCpN + lane] : 0.0;
   };
   // the two faces of column x from the cell records of columns x (and 0 for
