@@ -354,7 +354,7 @@ __device__ inline void side_rev(const Dev& g, const double* f, const double* fin
 // side data of face f at velocity k: cell code, centroid-to-face offset
 __device__ inline void face_side(const Dev& g, const double* fp, int s, int& code, int& inner, double& dx,
                                  double& dy) {
-  int L = (int)fp[kFpL], R = (int)fp[kFpR];
+  int L = tab_int(fp[kFpL]), R = tab_int(fp[kFpR]);
   code = s ? R : L;
   inner = (L >= 0) ? L : R;
   dx = fp[s ? kFpDR : kFpDL];
@@ -435,7 +435,7 @@ __device__ __forceinline__ void side_rev_d(const Dev& g, const SideD& s, int cod
 // divergence bars of its field cells and the face macro-flux bar
 __device__ inline void flux_bar_k(const Dev& g, const double* fp, const double* Dbh, const double* Dbb,
                                   const double* Fbf, int k, double& Fhb, double& Fbb) {
-  int L = (int)fp[kFpL], R = (int)fp[kFpR];
+  int L = tab_int(fp[kFpL]), R = tab_int(fp[kFpR]);
   double S = fp[kFpS];
   double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
   Fhb = w * (Fbf[0] + Fbf[1] * vx + ((kD == 2) ? Fbf[2] * vy : 0.0) + Fbf[kD + 1] * 0.5 * (vx * vx + vy * vy));
@@ -484,8 +484,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_face(Dev g, double dts, const do
   if (f >= g.nface) return;
   Rec& e = srec[threadIdx.x >> 6];
   const double* fp = g.fplan + (size_t)f * kFpN;
-  if (fp[kFpAct] == 0.0) return;
-  const int L = (int)fp[kFpL], R = (int)fp[kFpR];
+  if (tab_int(fp[kFpAct]) == 0) return;
+  const int L = tab_int(fp[kFpL]), R = tab_int(fp[kFpR]);
   if (L == kNbWall || R == kNbWall) return;
   const int D = kD, nv = g.nv;
   const double nx = fp[kFpN0], ny = fp[kFpN0 + 1], ufx = fp[kFpU], ufy = fp[kFpU + 1];

@@ -387,13 +387,13 @@ int upload_plans(ugks_ctx* c) {
   c->cplan.assign((size_t)kCpN * c->ncell, 0.0);
   for (int n = 0; n < c->ncell; ++n) {
     double* P = &c->cplan[(size_t)kCpN * n];
-    P[kCpType] = cp_int_entry(c->type[n]);
+    P[kCpType] = tab_int_entry(c->type[n]);
     for (int s = 0; s < 4; ++s) {
       const int f = c->cf[4 * (size_t)n + s];
-      P[kCpNb + s] = cp_int_entry(c->nb[4 * (size_t)n + s]);
+      P[kCpNb + s] = tab_int_entry(c->nb[4 * (size_t)n + s]);
       P[kCpG + s] = c->G[4 * (size_t)n + s];
       P[kCpS + s] = (f >= 0) ? c->fgeo[8 * (size_t)f + 2] : 0.0;
-      P[kCpFace + s] = cp_int_entry(f);
+      P[kCpFace + s] = tab_int_entry(f);
     }
     P[kCpIvol] = 1.0 / c->vol[n];
   }
@@ -403,7 +403,7 @@ int upload_plans(ugks_ctx* c) {
     const double* fg = &c->fgeo[8 * (size_t)f];
     P[kFpN0] = fg[0]; P[kFpN0 + 1] = fg[1]; P[kFpS] = fg[2]; P[kFpU] = fg[3]; P[kFpU + 1] = fg[4];
     const int L = c->fcell[2 * (size_t)f], R = c->fcell[2 * (size_t)f + 1];
-    P[kFpL] = L; P[kFpR] = R; P[kFpAct] = c->fact[f];
+    P[kFpL] = tab_int_entry(L); P[kFpR] = tab_int_entry(R); P[kFpAct] = tab_int_entry(c->fact[f]);
     for (int side = 0; side < 2; ++side) {
       const int cell = side ? R : L;
       if (cell < 0) continue;

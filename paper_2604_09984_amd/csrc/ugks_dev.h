@@ -51,15 +51,23 @@ __device__ __forceinline__ void record_derived(double* r) {
 // J^{-T}, face area per slot (0 without a face), 1/|Omega|, face id per slot
 // (-1 none)
 enum : int { kCpType = 0, kCpNb = 1, kCpG = 5, kCpS = 9, kCpIvol = 13, kCpFace = 14, kCpN = 20 };
-inline double cp_int_entry(int v) {
+// an int32 entry of the packed march tables (low word, high word zero) and
+// its read-back
+inline double tab_int_entry(int v) {
   const unsigned long long u = (unsigned long long)(unsigned int)v;
   double d;
   __builtin_memcpy(&d, &u, sizeof d);
   return d;
 }
+__host__ __device__ __forceinline__ int tab_int(double v) {
+  unsigned long long u;
+  __builtin_memcpy(&u, &v, sizeof u);
+  return (int)(unsigned int)(u & 0xffffffffull);
+}
 // packed per-face table: unit normal, area, grid velocity, offsets from the
 // centroids of the low and high cells to the face centre (zero on a ghost or
 // wall side), low and high cell or ghost code, 1 if the face carries flux
+// (the last three int32 entries, read with tab_int)
 enum : int { kFpN0 = 0, kFpS = 2, kFpU = 3, kFpDL = 5, kFpDR = 7, kFpL = 9, kFpR = 10, kFpAct = 11, kFpN = 12 };
 
 // per-cell record (double): state of the Shakhov source, the micro LU-SGS

@@ -927,9 +927,9 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
         double fp[kFpN];
 #pragma unroll
         for (int m = 0; m < kFpN; ++m) fp[m] = fpl[(size_t)fu * kFpN + m];
-        if (__builtin_amdgcn_readfirstlane((int)fp[kFpAct]) == 0) return;
-        const int L = __builtin_amdgcn_readfirstlane((int)fp[kFpL]);
-        const int R = __builtin_amdgcn_readfirstlane((int)fp[kFpR]);
+        if (__builtin_amdgcn_readfirstlane(tab_int(fp[kFpAct])) == 0) return;
+        const int L = __builtin_amdgcn_readfirstlane(tab_int(fp[kFpL]));
+        const int R = __builtin_amdgcn_readfirstlane(tab_int(fp[kFpR]));
         // owner: the low cell, or the cell of a boundary face; a periodic
         // seam i-face (x = -1) is written by the high end of the row; the
         // bottom halo writes only the block's lower boundary j-face
