@@ -1000,8 +1000,11 @@ __global__ void k_face_fin(Dev g, double dts, int nchunk, const double* __restri
   const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
   double m[kMomP];
   for (int q = 0; q < kMomP; ++q) m[q] = 0.0;
+  // chunk order kept; unrolled so that several chunks' loads are in flight
+#pragma unroll 8
   for (int ch = 0; ch < nchunk; ++ch) {
     const double* p = part + ((size_t)ch * g.nface + f) * kMomP;
+#pragma unroll
     for (int q = 0; q < kMomP; ++q) m[q] += p[q];
   }
   double* r = rec + (size_t)f * NREC;
@@ -1044,8 +1047,11 @@ __global__ void k_flux_fin(Dev g, int nchunk, const double* __restrict__ part, c
   int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= g.nface || !g.fact[f]) return;
   double m[kFluxP] = {0, 0, 0, 0};
+  // chunk order kept; unrolled so that several chunks' loads are in flight
+#pragma unroll 8
   for (int ch = 0; ch < nchunk; ++ch) {
     const double* p = part + ((size_t)ch * g.nface + f) * kFluxP;
+#pragma unroll
     for (int q = 0; q < kFluxP; ++q) m[q] += p[q];
   }
   if (F) for (int q = 0; q < kFluxP; ++q) F[(size_t)f * 4 + q] = m[q];
@@ -1999,8 +2005,8 @@ template <int D, class T, class C>
 void launch_flux_t(const Dev& g, double dts, const void* h, const void* b, const double* W, const double* q,
                    double* gW, double* rec, void* Dh, void* Db, double* F, double* wall, hipStream_t st,
                    hipEvent_t* ev) {
-  k_gradW<<<nbl(g.ncell, 256), 256, 0, st>>>(g, W, gW);
-  k_wallprep<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, W, q, gW, rec);
+  k_gradW<<<nbl(g.ncell, 64), 64, 0, st>>>(g, W, gW);
+  k_wallprep<<<nbl(g.nface, 64), 64, 0, st>>>(g, dts, W, q, gW, rec);
   if (ev) (void)hipEventRecord(ev[0], st);
   k_face_eq<D, T><<<nb4(g.ncell), 256, 0, st>>>(g, dts, (const T*)h, (const T*)b, W, gW, rec);
   if (ev) { (void)hipEventRecord(ev[1], st); (void)hipEventRecord(ev[2], st); }
@@ -2034,16 +2040,16 @@ void launch_march_t(const Dev& g, const int* binfo, int max_nj, double dts, cons
                     const double* W, const double* q, double* gW, double* rec, double* part, void* Dh, void* Db,
                     double* F, double* wall, hipStream_t st, hipEvent_t* ev) {
   const int nchunk = (g.nv + 63) / 64;
-  k_gradW<<<nbl(g.ncell, 256), 256, 0, st>>>(g, W, gW);
-  k_wallprep<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, W, q, gW, rec);
+  k_gradW<<<nbl(g.ncell, 64), 64, 0, st>>>(g, W, gW);
+  k_wallprep<<<nbl(g.nface, 64), 64, 0, st>>>(g, dts, W, q, gW, rec);
   if (ev) (void)hipEventRecord(ev[0], st);
   march_rg<T, C, 0>(g.rg_eq, g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st);
   if (ev) (void)hipEventRecord(ev[1], st);
-  k_face_fin<<<nbl(g.nface, 256), 256, 0, st>>>(g, dts, nchunk, part, W, gW, rec);
+  k_face_fin<<<nbl(g.nface, 64), 64, 0, st>>>(g, dts, nchunk, part, W, gW, rec);
   if (ev) (void)hipEventRecord(ev[2], st);
   march_rg<T, C, 1>(g.rg_flux, g, binfo, max_nj, nchunk, h, b, W, rec, part, Dh, Db, st);
   if (ev) (void)hipEventRecord(ev[3], st);
-  k_flux_fin<<<nbl(g.nface, 256), 256, 0, st>>>(g, nchunk, part, rec, F, wall);
+  k_flux_fin<<<nbl(g.nface, 64), 64, 0, st>>>(g, nchunk, part, rec, F, wall);
 }
 
 void launch_flux(const Dev& g, int prec, const int* binfo, int max_nj, double dts, const void* h, const void* b,
@@ -2078,7 +2084,7 @@ void launch_interp(const Dev& g, int prec, int nrec, const int* rec, const int* 
 
 void launch_cellrec(const Dev& g, double dt, const double* W, const double* q, const double* mrec, double* crec,
                     hipStream_t st) {
-  k_cellrec<<<nbl(g.ncell, 256), 256, 0, st>>>(g, dt, W, q, mrec, crec);
+  k_cellrec<<<nbl(g.ncell, 64), 64, 0, st>>>(g, dt, W, q, mrec, crec);
 }
 
 void launch_source(const Dev& g, int prec, double dt, const void* h, const void* b, const double* crec,
@@ -2098,8 +2104,8 @@ void launch_macro(const Dev& g, const int* binfo, int max_ni, int max_nj, int an
                   const double* W, const double* Wn, const double* F, const double* Fn, double* gam, double* R,
                   double* Dg, double* dWs, double* dW, double* Wp, double* rpart, double* resid, hipStream_t st) {
   (void)Dg;
-  k_gamma<<<nbl(g.nface, 256), 256, 0, st>>>(g, W, gam);
-  k_macro_prep<<<nbl(g.ncell, 256), 256, 0, st>>>(g, dt, W, Wn, F, Fn, gam, R);
+  k_gamma<<<nbl(g.nface, 64), 64, 0, st>>>(g, W, gam);
+  k_macro_prep<<<nbl(g.ncell, 64), 64, 0, st>>>(g, dt, W, Wn, F, Fn, gam, R);
   const int nt = ((max_nj + 63) / 64) * 64;
   const size_t lds = macro_lds(nt, max_ni, max_nj, any_pi, any_pj);
   if (g.dim == 2) {
