@@ -285,10 +285,24 @@ def test_free_transport_linear_data_exact(oracle_lib):
     W = np.tile(wl.cons(1, 1.0, [0.0], 0.5), (o.ncell, 1))
     q = np.zeros((o.ncell, 1))
     dts, _ = o.timesteps()
-    Dh, _, _, _ = o.flux(dts, h, b, W, q)
+    Dh, Db, F, _ = o.flux(dts, h, b, W, q)
     inner = slice(2, o.ncell - 2)
     # linear profile transported at speed v: cell divergence is -v * slope
     assert np.allclose(Dh[inner], -(vx * beta)[None, :], rtol=0, atol=1e-12)
+    assert np.allclose(Db[inner], -(2 * vx * beta)[None, :], rtol=0, atol=2e-12)
+    # face flux: the time average over dt_s of v f(x_f - v t) is
+    # v (f(x_f) - beta v dt_s / 2), for h and for b = 2 h, summed into the
+    # mass and energy fluxes with the velocity weights
+    g = o.geometry()
+    _, _, wk = o.dvs()
+    for f in range(o.nface):
+        if g["fl"][f] < 2 or g["fr"][f] < 0 or g["fr"][f] >= o.ncell - 2:
+            continue
+        hf = alpha + beta * g["fx"][f, 0] - beta * vx * dts / 2
+        fm = vx * hf
+        assert abs(F[f, 0] - wk @ fm) <= 1e-13 * np.abs(wk @ np.abs(fm))
+        fe = 0.5 * (vx * vx * fm + 2 * fm)
+        assert abs(F[f, 2] - wk @ fe) <= 1e-13 * np.abs(wk @ np.abs(fe))
 
 
 def _bump_errors(oracle_lib, cfl_s, sizes=(32, 64, 128), inner=30):
