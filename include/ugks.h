@@ -12,7 +12,9 @@
  *    No C++ exception crosses this interface.
  *  - Device arrays are caller-owned HIP device pointers; the library never
  *    frees them.  Host arrays are marked "host".  The context owns its own
- *    device copies of the geometry and its scratch buffers.
+ *    device copies of the geometry; its scratch (and the reverse mode's
+ *    workspace) is its own allocation or a caller's workspace
+ *    (ugks_workspace_size, ugks_create_with_workspace).
  *  - Every compute call is asynchronous on `stream` (a hipStream_t passed as
  *    void*, NULL = the null stream).  Calls on one context must not overlap.
  *  - Layouts.  nv = nvx*nvy discrete velocities, k = ix + nvx*iy.  The reduced
@@ -111,6 +113,29 @@ typedef struct ugks_ctx ugks_ctx;
    block within 160 KiB (else UGKS_E_UNSUPPORTED, with the reason in
    ugks_last_error). */
 int ugks_create(const ugks_problem* p, int device, ugks_ctx** out);
+/*
+ * Device memory a problem needs beyond the caller's state arrays (host
+ * outputs, either may be NULL): *scratch receives the bytes of the
+ * context's scratch (face and cell records, W gradients, chunk partial
+ * sums of the face moments and macro fluxes, the macro and micro LU-SGS
+ * intermediates: Secs. 2.1-2.2), *adjoint the bytes of the reverse-mode
+ * workspace (about 14 FP64 arrays of [ncell][nv]).  The geometry and table
+ * copies a context keeps (O(ncell + nface)) are not included.  UGKS_E_ARG
+ * or UGKS_E_SHAPE for a problem ugks_create would reject on those grounds.
+ */
+int ugks_workspace_size(const ugks_problem* p, size_t* scratch, size_t* adjoint);
+
+/*
+ * ugks_create with a caller-owned device workspace `work` of work_bytes
+ * (256-byte aligned; at least the scratch bytes of ugks_workspace_size):
+ * the context's scratch lives there instead of in its own allocation, and
+ * when work_bytes also covers the adjoint bytes (scratch + adjoint) the
+ * reverse-mode workspace follows the scratch in it, so that neither the
+ * step nor the adjoint allocates device memory.  The workspace must outlive
+ * the context; the library never frees it.  UGKS_E_SHAPE if it is too small.
+ */
+int ugks_create_with_workspace(const ugks_problem* p, int device, void* work, size_t work_bytes, ugks_ctx** out);
+
 /* Release the context and its device memory.  NULL is accepted. */
 int ugks_destroy(ugks_ctx* ctx);
 /* Sizes: cells, faces, velocities, storage precision (any pointer may be NULL). */
@@ -218,6 +243,8 @@ int ugks_begin_step(ugks_ctx* ctx, double dt, void* h, void* b, double* W, doubl
  * (Eq. dualTimeStepping_micro) by LU-SGS per velocity and correct W
  * (Step 7).  Wn is W at level n.  resid (device, may be NULL) receives
  * [n_inner][dim+2] L2 norms of the macro residual over field cells.
+ * Failures found on the device (see ugks_status) are returned here only in
+ * the synchronising check mode of ugks_set_checks.
  */
 int ugks_step(ugks_ctx* ctx, double dt, int32_t n_inner, void* h, void* b, double* W,
               const double* Wn, double* q, const void* Sh, const void* Sb, const double* Fn,
@@ -277,11 +304,13 @@ int ugks_batch_destroy(ugks_batch* batch);
  * and rg_eq, rg_flux, the core rows per workgroup of the face-equilibrium
  * and flux march kernels (10, 8 or 6 each).  ugks_autotune times n_inner
  * pseudo-iterations run on device copies of the given state (the caller's
- * arrays are not written; scratch is allocated for the call) for kc_max
+ * arrays are not written) for kc_max
  * {16, 8, 4}, then rg_eq {8, 10, 6} and then rg_flux {8, 10, 6}, each with the
  * others at their best so far (the three act on different kernels), keeps
  * the fastest and reports it in host choice[3] and its mean milliseconds per
- * pseudo-iteration in *best_ms.  Synchronous.
+ * pseudo-iteration in *best_ms.  The state copies live in the reverse-mode
+ * workspace when the context has one, else they are allocated for the call.
+ * Synchronous.
  */
 int ugks_set_tuning(ugks_ctx* ctx, int32_t kc_max, int32_t rg_eq, int32_t rg_flux);
 int ugks_get_tuning(const ugks_ctx* ctx, int32_t* kc_max, int32_t* rg_eq, int32_t* rg_flux);
@@ -343,8 +372,9 @@ int ugks_last_flux(const ugks_ctx* ctx, double* F, void* stream);
  * switches, upwind sign, positivity fallbacks, |.| of the spectral radius)
  * the derivative of the branch the forward pass takes is returned.  Each
  * call recomputes the forward quantities it needs from the given inputs
- * (the inputs are not modified) and allocates its FP64 workspace (about 14
- * arrays of [ncell][nv]) on first use; the context's scratch is overwritten.
+ * (the inputs are not modified) in its FP64 workspace (about 14 arrays of
+ * [ncell][nv]: the caller's, see ugks_create_with_workspace, or allocated
+ * on first use); the context's scratch is overwritten.
  * The cotangent of a hole cell's value is not defined.  Asynchronous on
  * `stream`.
  *
@@ -383,6 +413,73 @@ int ugks_begin_step_adjoint(ugks_ctx* ctx, double dt, const void* h, const void*
                             const double* W1_bar, const double* q1_bar, const double* Sh_bar,
                             const double* Sb_bar, const double* Fn_bar, double* h_bar, double* b_bar,
                             double* W_bar, double* q_bar, double* face_bar, void* stream);
+
+/*
+ * Device-side checks.  Kernels record failures in the context's status
+ * word: the micro LU-SGS sweep (Eq. dualTimeStepping_micro) when its bounded
+ * wait for a neighbouring wavefront runs out (it then goes on, so the kernel
+ * ends, but the f it writes is not valid), and Step 7 (Sec. 2.2) when the
+ * corrected W of a field cell has a non-positive density or temperature or
+ * a non-finite entry.  ugks_status waits for `stream`, reads and clears the
+ * word and returns UGKS_E_DEVICE (wait ran out; checked first),
+ * UGKS_E_NONPHYS, or UGKS_OK.
+ */
+int ugks_status(ugks_ctx* ctx, void* stream);
+/*
+ * sync != 0: ugks_begin_step, ugks_step and ugks_step_graph wait for their
+ * stream at the end and return ugks_status (default 0: asynchronous, the
+ * status is read by an explicit ugks_status).  wait_limit >= 0 sets the
+ * bound of the micro sweep's neighbour wait in sleeps (default 2^20, also
+ * for a negative value); a small bound lets a test force the failure path.
+ */
+int ugks_set_checks(ugks_ctx* ctx, int32_t sync, int32_t wait_limit);
+
+/*
+ * Wall loads (Sec. 2.1: the macro flux into an isothermal wall, Eq.
+ * maxWalldes; the load and heat flux on a body) from a face macro flux F
+ * [nface][dim+2] (ugks_flux, ugks_last_flux).  face_loads [nface][dim+3]
+ * (device, may be NULL): per wall face the momentum flux into the wall per
+ * unit area (dim components: the load on the body per area), its component
+ * along the normal pointing into the wall (pressure p_w) and along that
+ * normal turned by +90 degrees (shear sigma_w; 0 in 1D), and the energy flux
+ * into the wall q_w; zero on faces that are not walls.  side_loads
+ * [nblock][4][4] (device, may be NULL): per block side (0 i-min, 1 i-max,
+ * 2 j-min, 3 j-max) the area integrals of the force on the body (x, y), of
+ * its moment about the block's moved rotation centre (z) and of q_w; zero
+ * on sides that are not walls.  Sums run in face order (reproducible).
+ */
+int ugks_wall_loads(ugks_ctx* ctx, const double* F, double* face_loads, double* side_loads, void* stream);
+/* Reverse of ugks_wall_loads with respect to F: F_bar [nface][dim+2]
+   (written; zero off the walls) from the cotangents face_loads_bar and
+   side_loads_bar (layouts as above; either may be NULL = zero). */
+int ugks_wall_loads_adjoint(ugks_ctx* ctx, const double* face_loads_bar, const double* side_loads_bar,
+                            double* F_bar, void* stream);
+/* Cotangents of the prescribed motion and wall temperatures from the
+   per-face cotangents face_bar [nface][5] of the reverse-mode entry points
+   below: U_bar [nblock][2] = sum over the block's faces of the face grid
+   velocity and wall velocity entries (the rigid block velocity moves both),
+   rtw_bar [nblock][4] = sum of the wall RT entries over each side's faces.
+   Sums in a fixed order. */
+int ugks_param_bars(ugks_ctx* ctx, const double* face_bar, double* U_bar, double* rtw_bar, void* stream);
+
+/*
+ * Newton-Euler (3-DOF) rigid motion of block `blk` (Sec. 3, Step 1: a body
+ * moves by the Newton-Euler equations driven by the gas, or by a given
+ * motion), loosely coupled: the force and moment on the body at level n are
+ * the area integrals of the macro flux into the block's wall sides from the
+ * face macro flux F (device [nface][dim+2]; e.g. ugks_last_flux after the
+ * last inner iteration of step n), the moment about the block's moved
+ * rotation centre (the centre of mass), plus the constant external load of
+ * body (host [5]: mass, moment of inertia, Fx, Fy, Mz).  pose (host [6], in
+ * and out: dx, dy, th, ux, uy, om, as ugks_set_poses takes them) advances
+ * by dt: u' = u + dt F/m, om' = om + dt M/I, then the position and angle by
+ * the trapezoidal rule of the old and new velocities (exact for constant
+ * loads).  The caller installs the new poses with ugks_set_poses.  Waits for
+ * `stream`.  UGKS_E_UNSUPPORTED in 1D; UGKS_E_ARG for a bad block, a
+ * non-positive mass, inertia or dt.
+ */
+int ugks_newton_euler(ugks_ctx* ctx, int32_t blk, const double* body, double dt, const double* F, double* pose,
+                      void* stream);
 
 /* Thread-local message of the last failure ("" if none). */
 const char* ugks_last_error(void);

@@ -59,6 +59,8 @@ def _bind(L, S):
     L.or_shakhov.argtypes = [C.c_int, S, S, D, S, D, D, D, D]
     L.or_flux.argtypes = [C.c_void_p, S, D, D, D, D, D, D, D, D]
     L.or_interp.argtypes = [C.c_void_p, D, D, D, D]
+    L.or_wall_loads.argtypes = [C.c_void_p, D, D, D]
+    L.or_newton_euler.argtypes = [C.c_void_p, C.c_int, D, S, D, D]
     L.or_begin_step.argtypes = [C.c_void_p, S, S, D, D, D, D, D, D, D]
     L.or_begin_step_cells.argtypes = [C.c_void_p, S, S, D, D, D, D, C.c_int, I, D, D, D]
     L.or_pseudo_step.argtypes = [C.c_void_p, S, S, D, D, D, D, D, D, D, D, D, D, D]
@@ -313,6 +315,24 @@ class Oracle:
         F = z(max(self.nface, 1), self.nw); wall = z(max(self.nface, 1), 1 + self.nw)
         self.L.or_flux(self.ptr, self._s(dts), _d(h), _d(b), _d(W), _d(q), _d(Dh), _d(Db), _d(F), _d(wall))
         return Dh, Db, F, wall
+
+    def wall_loads(self, F):
+        """(face_out [nface][dim+3], side_out [nblock][4][4]) from a face
+        macro flux F [nface][nw] (oracle face order)."""
+        fo = self._z(max(self.nface, 1), self.dim + 3)
+        so = self._z(len(self.case.blocks), 4, 4)
+        self.L.or_wall_loads(self.ptr, _d(np.ascontiguousarray(F)), _d(fo), _d(so))
+        return fo[:self.nface], so
+
+    def newton_euler(self, blk, body, dt, F, pose):
+        """The block's pose [6] advanced by one Newton-Euler step from the
+        wall loads of F (oracle face order) and the external load in body =
+        (m, I, Fx_ext, Fy_ext, M_ext); returns the new pose."""
+        assert not self.tangent
+        p = np.array(pose, dtype=np.float64)
+        bd = np.array(body, dtype=np.float64)
+        self.L.or_newton_euler(self.ptr, int(blk), _d(bd), float(dt), _d(np.ascontiguousarray(F)), _d(p))
+        return p
 
     def interp(self, h, b, W, q):
         self.L.or_interp(self.ptr, _d(h), _d(b), _d(W), _d(q))

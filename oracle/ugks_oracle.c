@@ -1162,6 +1162,79 @@ void or_flux(const or_case* c, real dts, const real* h, const real* b,
   free(X.rec);
 }
 
+/* Wall loads (Sec. 2.1: the macro flux into an isothermal wall gives the
+   load and the heat flux on the body).  Per wall face the flux into the wall
+   per unit area: momentum (the load on the body), its component along the
+   normal pointing into the wall (pressure) and along that normal turned by
+   +90 degrees (shear), and energy; per block side the area integrals of the
+   force, of its moment about the block's moved rotation centre and of the
+   energy flux, summed in face order. */
+void or_wall_loads(const or_case* c, const real* F, real* face_out, real* side_out) {
+  int d = c->dim, nw = c->nw;
+  if (face_out)
+    for (size_t i = 0; i < (size_t)c->nface * (d + 3); i++) face_out[i] = 0.0;
+  if (side_out)
+    for (int i = 0; i < 16 * c->nblock; i++) side_out[i] = 0.0;
+  for (int f = 0; f < c->nface; f++) {
+    const face_t* Fc = &c->face[f];
+    if (Fc->kind != F_WALL) continue;
+    real sg = (Fc->R < 0) ? 1.0 : -1.0;  /* wall on the R side: the normal points into it */
+    real nix = sg * Fc->nx, niy = sg * Fc->ny;
+    real mx = sg * F[(size_t)f * nw + 1];
+    real my = (d == 2) ? sg * F[(size_t)f * nw + 2] : 0.0;
+    real en = sg * F[(size_t)f * nw + d + 1];
+    if (face_out) {
+      real* o = face_out + (size_t)f * (d + 3);
+      o[0] = mx;
+      if (d == 2) o[1] = my;
+      o[d] = mx * nix + my * niy;
+      o[d + 1] = -mx * niy + my * nix;
+      o[d + 2] = en;
+    }
+    if (side_out) {
+      const blk_t* B = &c->blk[Fc->blk];
+      real rx = Fc->xf - (B->xc0 + B->dx), ry = Fc->yf - (B->yc0 + B->dy);
+      real* o = side_out + 4 * (4 * Fc->blk + Fc->side);
+      o[0] += Fc->S * mx;
+      o[1] += Fc->S * my;
+      o[2] += Fc->S * (rx * my - ry * mx);
+      o[3] += Fc->S * en;
+    }
+  }
+}
+
+/* Newton-Euler (3-DOF) motion of block b (Sec. 3, Step 1: a body moves by
+   the Newton-Euler equations or by a given motion).  Reading (loose
+   coupling, the paper gives no integrator): the force and moment on the body
+   at level n are the area integrals of the macro flux into the block's walls
+   from the face macro flux F of the last flux evaluation (moment about the
+   block's rotation centre, taken as the centre of mass), plus a constant
+   external force and moment; the velocities take an explicit step and the
+   pose the trapezoidal rule, exact for constant loads:
+     u' = u + dt (F + F_ext) / m,   om' = om + dt (M + M_ext) / I,
+     d' = d + dt (u + u') / 2,      th' = th + dt (om + om') / 2.
+   body = {m, I, Fx_ext, Fy_ext, M_ext}; pose = {dx, dy, th, ux, uy, om} of
+   the block, advanced in place (the caller sets the new pose). */
+void or_newton_euler(const or_case* c, int b, const real* body, real dt, const real* F, real* pose) {
+  real* side = (real*)malloc(sizeof(real) * 16 * c->nblock);
+  or_wall_loads(c, F, NULL, side);
+  real fx = body[2], fy = body[3], mz = body[4];
+  for (int s = 0; s < 4; s++) {
+    if (c->blk[b].bc[s] != OR_WALL) continue;
+    fx += side[16 * b + 4 * s + 0];
+    fy += side[16 * b + 4 * s + 1];
+    mz += side[16 * b + 4 * s + 2];
+  }
+  free(side);
+  real ux = pose[3] + dt * fx / body[0];
+  real uy = pose[4] + dt * fy / body[0];
+  real om = pose[5] + dt * mz / body[1];
+  pose[0] += 0.5 * dt * (pose[3] + ux);
+  pose[1] += 0.5 * dt * (pose[4] + uy);
+  pose[2] += 0.5 * dt * (pose[5] + om);
+  pose[3] = ux; pose[4] = uy; pose[5] = om;
+}
+
 /* ------------------------------------------------------------------------ */
 /* overset interpolation (Sec. 3.2) -- weights supplied by the assembly      */
 /* ------------------------------------------------------------------------ */

@@ -125,6 +125,19 @@ void or_flux(const or_case* c, real dts, const real* h, const real* b,
              const real* W, const real* q, real* Dh, real* Db,
              real* F, real* wall);
 
+/* wall loads from a face macro flux F [nface][nw]: face_out [nface][dim+3]
+   (per wall face and unit area: momentum flux into the wall, its pressure
+   and shear components, energy flux; zero elsewhere), side_out
+   [nblock][4][4] (per block side: force x, y, its moment about the block's
+   moved rotation centre, energy flux); either may be NULL */
+void or_wall_loads(const or_case* c, const real* F, real* face_out, real* side_out);
+
+/* Newton-Euler (3-DOF) step of block b's rigid motion driven by its wall
+   loads from F [nface][nw] plus a constant external load:
+   body = {mass, moment of inertia, Fx_ext, Fy_ext, M_ext}; pose [6] =
+   {dx, dy, th, ux, uy, om} advanced by dt in place */
+void or_newton_euler(const or_case* c, int b, const real* body, real dt, const real* F, real* pose);
+
 /* overset interpolation of f, W, q into receptors */
 void or_interp(const or_case* c, real* h, real* b, real* W, real* q);
 

@@ -17,8 +17,8 @@ parameters of the prescribed motion and boundaries:
 
 U and rtw are float64 tensors on any device; their gradients come back on the
 same device.  Objectives are functions of the returned states and of F, the
-face macro flux of the last inner iteration (wall force and heat flux:
-wall_weights()).
+face macro flux of the last inner iteration (wall force, moment and heat
+flux per block side: wall_loads(), computed by the library).
 
 Checkpointing: physical_step() stores only its inputs; its backward re-runs
 the step's forward (Steps 1-2 and the n_inner inner iterations, keeping the
@@ -39,76 +39,38 @@ from __future__ import annotations
 
 import inspect
 
-import numpy as np
 import torch
 
 from . import ugks
 
 
 # --------------------------------------------------------------------------
-# face bookkeeping (product face numbering of include/ugks.h)
+# wall loads (computed by the library) as a differentiable function of F
 # --------------------------------------------------------------------------
-def face_blocks(case):
-    """Block and boundary side (-1: none) of every face."""
-    blk, side = [], []
-    for b, B in enumerate(case.blocks):
-        ni, nj = B.ni, B.nj
-        if case.dim == 1:
-            for i in range(ni + 1):
-                blk.append(b)
-                side.append(0 if i == 0 else (1 if i == ni else -1))
-            continue
-        for j in range(nj):
-            for i in range(ni + 1):
-                blk.append(b)
-                side.append(0 if i == 0 else (1 if i == ni else -1))
-        for j in range(nj + 1):
-            for i in range(ni):
-                blk.append(b)
-                side.append(2 if j == 0 else (3 if j == nj else -1))
-    return np.asarray(blk, np.int64), np.asarray(side, np.int64)
+class WallLoads(torch.autograd.Function):
+    """F [nface][dim+2] -> side loads [nblock][4][4] (force x, y, moment,
+    energy flux into the walls of each block side; ugks_wall_loads)."""
+
+    @staticmethod
+    def forward(ctx, solver, F):
+        _, side = solver.wall_loads(F)
+        ctx.solver = solver
+        return side
+
+    @staticmethod
+    def backward(ctx, g):
+        return None, ctx.solver.wall_loads_adjoint(side_bar=g.contiguous())
 
 
-def wall_weights(solver, blk, sides=(0, 1, 2, 3)):
-    """Weights w [nface] with sum_f w_f F[f, m] = the flux of component m into
-    the walls of block `blk` on `sides` (area times +-1 for the orientation of
-    the face normal): m = 1, 2 give the force on the body, m = dim+1 the
-    energy flux into it."""
-    fb, fs = face_blocks(solver.case)
-    g = solver.face_geometry()
-    B = solver.case.blocks[blk]
-    w = np.zeros(solver.nface)
-    for s in sides:
-        if B.bc[s] != 3:  # not a wall
-            continue
-        sel = (fb == blk) & (fs == s)
-        sgn = 1.0 if s in (1, 3) else -1.0  # normal points into the wall on high sides
-        w[sel] = sgn * g[sel, 2]
-    return torch.tensor(w, dtype=torch.float64, device=solver.device)
+def wall_loads(solver, F):
+    """Differentiable side loads of a face macro flux (see WallLoads)."""
+    return WallLoads.apply(solver, F)
 
 
-class _Faces:
-    def __init__(self, solver):
-        b, s = face_blocks(solver.case)
-        self.blk = torch.tensor(b, device=solver.device)
-        self.side = torch.tensor(s, device=solver.device)
-        self.nblock = len(solver.case.blocks)
-
-    def param_grads(self, face_bar):
-        """Block velocity and wall-RT gradients from per-face bars."""
-        gU = torch.zeros((self.nblock, 2), dtype=torch.float64, device=face_bar.device)
-        gU.index_add_(0, self.blk, torch.stack([face_bar[:, 0] + face_bar[:, 2], face_bar[:, 1] + face_bar[:, 3]], 1))
-        gR = torch.zeros((self.nblock * 4,), dtype=torch.float64, device=face_bar.device)
-        ok = self.side >= 0
-        gR.index_add_(0, (self.blk * 4 + self.side)[ok], face_bar[ok, 4])
-        return gU, gR.reshape(self.nblock, 4)
-
-
-def _faces(solver):
-    f = getattr(solver, "_adj_faces", None)
-    if f is None:
-        f = solver._adj_faces = _Faces(solver)
-    return f
+def _param_grads(solver, face_bar):
+    """Block velocity and wall-RT cotangents from per-face cotangents
+    (ugks_param_bars)."""
+    return solver.param_bars(face_bar)
 
 
 def apply_params(solver, U, rtw):
@@ -213,7 +175,7 @@ class PseudoStep(torch.autograd.Function):
         hb, bb, Wb, Wnb, qb, Shb, Sbb, Fnb, fb = t.step_adjoint(ctx.dt, _f64(h), _f64(b), W, Wn, q, _f64(Sh),
                                                                  _f64(Sb), Fn, _f64(gh), _f64(gb), _c(gW),
                                                                  _c(gq), _c(gF))
-        gU, gR = _faces(t).param_grads(fb)
+        gU, gR = _param_grads(t, fb)
         return (None, None, None, _as(hb, h), _as(bb, b), Wb, qb, Wnb, _as(Shb, Sh), _as(Sbb, Sb), Fnb,
                 _out_grad(U, gU), _out_grad(rtw, gR))
 
@@ -246,7 +208,7 @@ class BeginStep(torch.autograd.Function):
         apply_params(t, U, rtw)
         hb, bb, Wb, qb, fb = t.begin_step_adjoint(ctx.dt, _f64(h), _f64(b), W, q, _f64(gh), _f64(gb), _c(gW),
                                                   _c(gq), _f64(gSh), _f64(gSb), _c(gFn), refill=ctx.refill)
-        gU, gR = _faces(t).param_grads(fb)
+        gU, gR = _param_grads(t, fb)
         return None, None, None, _as(hb, h), _as(bb, b), Wb, qb, _out_grad(U, gU), _out_grad(rtw, gR)
 
 
@@ -319,7 +281,7 @@ class PhysicalStep(torch.autograd.Function):
                                                   refill=ctx.refill)
         faces += fb
         Wb = Wb + gWn
-        gU, gR = _faces(s).param_grads(faces)
+        gU, gR = _param_grads(s, faces)
         return None, None, None, None, _as(hb, h_in), _as(bb, b_in), Wb, qb, _out_grad(U, gU), _out_grad(rtw, gR)
 
 

@@ -90,13 +90,26 @@ struct ugks_ctx {
   void *d_rec = nullptr, *d_ptr = nullptr, *d_don = nullptr, *d_w = nullptr;
   std::vector<int> h_rec, h_ptr, h_don;
   std::vector<double> h_w;
-  // workspace of the reverse-mode entry points (allocated on first use)
+  // workspace of the reverse-mode entry points (allocated on first use, or
+  // carved from a caller's workspace)
   std::vector<void*> adj;
+  // scratch: one block, owned (allocated at creation) or the caller's
+  void* scratch = nullptr;
+  bool own_scratch = true;
+  bool own_adj = true;
+  // device status word (kStatus* bits) and the synchronising check mode
+  unsigned* d_status = nullptr;
+  int sync_check = 0;
+  // wall table (kWt* entries per wall face, grouped by block side) and the
+  // face range of each block
+  std::vector<double> wtab;
+  std::vector<int> wptr, bface;
+  void *d_wtab = nullptr, *d_wptr = nullptr, *d_bface = nullptr;
+  void* d_side = nullptr;  // [nblock][4][4] side loads of the body motion
 };
 
 namespace {
 
-size_t tsize(const ugks_ctx* c) { return c->prec == UGKS_F64 ? sizeof(double) : sizeof(float); }
 
 // composite closed Newton-Cotes weights on n uniform points of [a, b]
 // (Boole if (n-1) % 4 == 0; Simpson for odd n; Simpson | 3/8 | Simpson for
@@ -294,8 +307,10 @@ void compute_geometry(ugks_ctx* c) {
     double fy[4] = {0.5 * (py[0] + py[3]), 0.5 * (py[1] + py[2]), 0.5 * (py[0] + py[1]), 0.5 * (py[3] + py[2])};
     for (int q = 0; q < 4; ++q) { D[2 * q] = fx[q] - xc; D[2 * q + 1] = fy[q] - yc; }
   }
-  // faces
+  // faces; wall faces are listed per block side for the wall loads
   c->fgeo.assign(8 * (size_t)c->nface, 0.0);
+  const size_t nside = 4 * c->blk.size();
+  std::vector<std::vector<double>> wall_of(nside);
   for (int b = 0; b < (int)c->blk.size(); ++b) {
     const Block& B = c->blk[b];
     double cxm = B.xc0 + B.pose[0], cym = B.yc0 + B.pose[1];
@@ -331,9 +346,22 @@ void compute_geometry(ugks_ctx* c) {
             g[5] = g[3] + B.vwx[side];
             g[6] = (d == 2) ? g[4] + B.vwy[side] : 0.0;
             g[7] = B.rtw[side];
+            const double sg = (R == kNbWall) ? 1.0 : -1.0;
+            double e[kWtN] = {0.0};
+            e[kWtFace] = tab_int_entry(f);
+            e[kWtS] = g[2]; e[kWtSgn] = sg; e[kWtNx] = sg * g[0]; e[kWtNy] = sg * g[1];
+            e[kWtRx] = rx; e[kWtRy] = ry;
+            auto& v = wall_of[4 * (size_t)b + side];
+            v.insert(v.end(), e, e + kWtN);
           }
         }
     }
+  }
+  c->wtab.clear();
+  c->wptr.assign(nside + 1, 0);
+  for (size_t q = 0; q < nside; ++q) {
+    c->wtab.insert(c->wtab.end(), wall_of[q].begin(), wall_of[q].end());
+    c->wptr[q + 1] = (int)(c->wtab.size() / kWtN);
   }
   // time steps: max_k |(v_k - U_f).n| is reached at a corner of the velocity box
   std::vector<double> smax(c->nface, 0.0);
@@ -427,6 +455,8 @@ int upload_geometry(ugks_ctx* c) {
   if ((rc = upload(c->d_dtp, c->dtp))) return rc;
   if ((rc = upload(c->d_fgeo, c->fgeo))) return rc;
   if ((rc = upload(c->d_mgeo, c->mgeo))) return rc;
+  if ((rc = upload(c->d_wptr, c->wptr))) return rc;
+  if ((rc = upload(c->d_wtab, c->wtab))) return rc;
   return upload_plans(c);
 }
 
@@ -456,14 +486,93 @@ void fill_dev(ugks_ctx* c) {
 
 void free_all(ugks_ctx* c) {
   void* ps[] = {c->d_vx, c->d_vy, c->d_wk, c->d_vol, c->d_G, c->d_cdx, c->d_dtp, c->d_type, c->d_nb, c->d_cf,
-                c->d_fcell, c->d_fgeo, c->d_fact, c->d_finf_h, c->d_finf_b, c->d_binfo, c->d_mgeo, c->s_gW, c->s_rec,
-                c->s_gam, c->s_R, c->s_Dg, c->s_dWs, c->s_dW, c->s_Wp, c->s_rpart, c->s_crec, c->s_mrec,
-                c->s_Dh, c->s_Db, c->s_F, c->s_part, c->d_rec, c->d_ptr, c->d_don, c->d_w, c->d_cplan, c->d_fplan};
+                c->d_fcell, c->d_fgeo, c->d_fact, c->d_finf_h, c->d_finf_b, c->d_binfo, c->d_mgeo, c->d_rec,
+                c->d_ptr, c->d_don, c->d_w, c->d_cplan, c->d_fplan, c->d_status, c->d_wtab, c->d_wptr,
+                c->d_bface, c->d_side};
   for (void* p : ps)
     if (p) (void)hipFree(p);
-  for (void* p : c->adj)
-    if (p) (void)hipFree(p);
+  if (c->own_scratch && c->scratch) (void)hipFree(c->scratch);
+  c->scratch = nullptr;
+  if (c->own_adj && !c->adj.empty() && c->adj[0]) (void)hipFree(c->adj[0]);
   c->adj.clear();
+}
+
+// ---------------------------------------------------------------------------
+// scratch layout: every buffer of the context's scratch at a 256-byte aligned
+// offset of one block; the adjoint workspace likewise
+// ---------------------------------------------------------------------------
+struct Sizes {
+  int dim, nw, ncell, nface, nv, nvx, nvy, nblock, prec;
+};
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// byte sizes of the scratch buffers, in the order of scratch_slots
+std::vector<size_t> scratch_sizes(const Sizes& z) {
+  const size_t N = (size_t)z.ncell * z.nv, ts = z.prec == UGKS_F64 ? 8 : 4;
+  return {sizeof(double) * 8 * (size_t)z.ncell,            // gW
+          sizeof(double) * NREC * (size_t)z.nface,         // face records
+          sizeof(double) * z.nface,                        // Gamma
+          sizeof(double) * 64 * (size_t)z.ncell,           // macro record
+          sizeof(double) * z.ncell,                        // macro diagonal
+          sizeof(double) * z.nw * (size_t)z.ncell,         // dW*
+          sizeof(double) * z.nw * (size_t)z.ncell,         // dW
+          sizeof(double) * z.nw * (size_t)z.ncell,         // W'
+          sizeof(double) * 4 * (size_t)z.nblock,           // residual partials
+          sizeof(double) * NCREC * (size_t)z.ncell,        // cell records
+          sizeof(double) * NMREC * (size_t)z.ncell,        // moment records
+          ts * N, ts * N,                                  // D / r / dF* (h, b)
+          sizeof(double) * z.nw * (size_t)z.nface,         // face macro flux
+          sizeof(double) * flux_part_doubles(z.nv, z.nface)};  // chunk partials
+}
+
+std::vector<void**> scratch_slots(ugks_ctx* c) {
+  return {&c->s_gW, &c->s_rec, &c->s_gam, &c->s_R, &c->s_Dg, &c->s_dWs, &c->s_dW, &c->s_Wp, &c->s_rpart,
+          &c->s_crec, &c->s_mrec, &c->s_Dh, &c->s_Db, &c->s_F, &c->s_part};
+}
+
+size_t scratch_bytes(const Sizes& z) {
+  size_t t = 0;
+  for (size_t b : scratch_sizes(z)) t += align256(std::max<size_t>(b, 256));
+  return t;
+}
+
+// doubles of each adjoint buffer (enum AdjBuf order, defined below)
+std::vector<size_t> adjoint_counts(const Sizes& z);
+
+size_t adjoint_bytes(const Sizes& z) {
+  size_t t = 0;
+  for (size_t n : adjoint_counts(z)) t += align256(sizeof(double) * std::max<size_t>(n, 1));
+  return t;
+}
+
+// carve the adjoint buffers from one block
+void carve_adjoint(ugks_ctx* c, const Sizes& z, char* base) {
+  std::vector<size_t> n = adjoint_counts(z);
+  c->adj.assign(n.size(), nullptr);
+  size_t off = 0;
+  for (size_t i = 0; i < n.size(); ++i) {
+    c->adj[i] = base + off;
+    off += align256(sizeof(double) * std::max<size_t>(n[i], 1));
+  }
+}
+
+// sizes of a problem (validated by the caller)
+Sizes sizes_of(const ugks_problem* p) {
+  Sizes z{};
+  z.dim = p->dim; z.nw = p->dim + 2; z.nv = p->nvx * ((p->dim == 2) ? p->nvy : 1);
+  z.nvx = p->nvx; z.nvy = (p->dim == 2) ? p->nvy : 1;
+  z.nblock = p->nblock; z.prec = p->prec;
+  for (int b = 0; b < p->nblock; ++b) {
+    const int ni = p->bint[6 * b], nj = (p->dim == 2) ? p->bint[6 * b + 1] : 1;
+    z.ncell += ni * nj;
+    z.nface += (ni + 1) * nj + ((p->dim == 2) ? ni * (nj + 1) : 0);
+  }
+  return z;
+}
+
+Sizes sizes_of(const ugks_ctx* c) {
+  return Sizes{c->dim, c->nw, c->ncell, c->nface, c->nv, c->nvx, c->nvy, (int)c->blk.size(), c->prec};
 }
 
 }  // namespace
@@ -475,16 +584,49 @@ extern "C" {
 
 const char* ugks_last_error(void) { return g_err.c_str(); }
 
+static int create_ctx(const ugks_problem* p, int device, void* work, size_t work_bytes, ugks_ctx** out);
+
 int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
-  g_err.clear();
-  if (!p || !out) return fail(UGKS_E_ARG, "null argument");
-  *out = nullptr;
+  return create_ctx(p, device, nullptr, 0, out);
+}
+
+int ugks_create_with_workspace(const ugks_problem* p, int device, void* work, size_t work_bytes, ugks_ctx** out) {
+  if (!work) return fail(UGKS_E_ARG, "null workspace");
+  if ((uintptr_t)work % 256 != 0) return fail(UGKS_E_ARG, "workspace must be 256-byte aligned");
+  return create_ctx(p, device, work, work_bytes, out);
+}
+
+static int check_problem(const ugks_problem* p) {
   if (p->dim != 1 && p->dim != 2) return fail(UGKS_E_ARG, "dim must be 1 or 2");
   if (p->prec != UGKS_F64 && p->prec != UGKS_F32) return fail(UGKS_E_ARG, "prec must be UGKS_F64 or UGKS_F32");
   if (p->nvx < 2 || (p->dim == 2 && p->nvy < 2) || (p->dim == 1 && p->nvy != 1))
     return fail(UGKS_E_SHAPE, "bad velocity grid size");
   if (!p->vx || !p->vy || !p->bint || !p->bdbl || !p->nodes || p->nblock < 1)
     return fail(UGKS_E_ARG, "null array or no block");
+  for (int b = 0; b < p->nblock; ++b)
+    if (p->bint[6 * b] < 2 || (p->dim == 2 && p->bint[6 * b + 1] < 2)) return fail(UGKS_E_ARG, "bad block size");
+  return UGKS_OK;
+}
+
+int ugks_workspace_size(const ugks_problem* p, size_t* scratch, size_t* adjoint) {
+  g_err.clear();
+  if (!p) return fail(UGKS_E_ARG, "null problem");
+  if (int rc = check_problem(p)) return rc;
+  const Sizes z = sizes_of(p);
+  if (scratch) *scratch = scratch_bytes(z);
+  if (adjoint) *adjoint = adjoint_bytes(z);
+  return UGKS_OK;
+}
+
+static int create_ctx(const ugks_problem* p, int device, void* work, size_t work_bytes, ugks_ctx** out) {
+  g_err.clear();
+  if (!p || !out) return fail(UGKS_E_ARG, "null argument");
+  *out = nullptr;
+  if (int rc = check_problem(p)) return rc;
+  if (work) {
+    const size_t need = scratch_bytes(sizes_of(p));
+    if (work_bytes < need) return fail(UGKS_E_SHAPE, "workspace smaller than ugks_workspace_size's scratch bytes");
+  }
   if (!(p->cfl_s > 0) || !(p->cfl_p > 0) || !(p->pr > 0)) return fail(UGKS_E_ARG, "bad CFL or Prandtl number");
   auto* c = new ugks_ctx();
   c->device = device;
@@ -612,22 +754,44 @@ int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
   }
   if (!rc) rc = upload_geometry(c);
   if (!rc) rc = upload_tables(c);
-  size_t N = (size_t)c->ncell * c->nv;
-  if (!rc) rc = alloc(c->s_gW, sizeof(double) * 8 * c->ncell);
-  if (!rc) rc = alloc(c->s_rec, sizeof(double) * NREC * (size_t)c->nface);
-  if (!rc) rc = alloc(c->s_gam, sizeof(double) * c->nface);
-  if (!rc) rc = alloc(c->s_R, sizeof(double) * 64 * (size_t)c->ncell);  // macro record
-  if (!rc) rc = alloc(c->s_Dg, sizeof(double) * c->ncell);
-  if (!rc) rc = alloc(c->s_dWs, sizeof(double) * c->nw * (size_t)c->ncell);
-  if (!rc) rc = alloc(c->s_dW, sizeof(double) * c->nw * (size_t)c->ncell);
-  if (!rc) rc = alloc(c->s_Wp, sizeof(double) * c->nw * (size_t)c->ncell);
-  if (!rc) rc = alloc(c->s_rpart, sizeof(double) * 4 * c->blk.size());
-  if (!rc) rc = alloc(c->s_crec, sizeof(double) * NCREC * (size_t)c->ncell);
-  if (!rc) rc = alloc(c->s_mrec, sizeof(double) * NMREC * (size_t)c->ncell);
-  if (!rc) rc = alloc(c->s_Dh, tsize(c) * N);
-  if (!rc) rc = alloc(c->s_Db, tsize(c) * N);
-  if (!rc) rc = alloc(c->s_F, sizeof(double) * c->nw * (size_t)c->nface);
-  if (!rc) rc = alloc(c->s_part, sizeof(double) * flux_part_doubles(c->nv, c->nface));
+  // face range of each block (faces are numbered block by block)
+  c->bface.assign(c->blk.size() + 1, 0);
+  for (size_t b = 0; b < c->blk.size(); ++b)
+    c->bface[b + 1] = (b + 1 < c->blk.size()) ? c->blk[b + 1].face_i0 : c->nface;
+  if (!rc) rc = upload(c->d_bface, c->bface);
+  if (!rc) rc = alloc(c->d_side, sizeof(double) * 16 * c->blk.size());
+  if (!rc) {
+    void* st = nullptr;
+    rc = alloc(st, sizeof(unsigned));
+    c->d_status = (unsigned*)st;
+  }
+  if (!rc && hipMemset(c->d_status, 0, sizeof(unsigned)) != hipSuccess) rc = fail(UGKS_E_DEVICE, "hipMemset failed");
+  // scratch: the caller's workspace or one allocation; with a workspace
+  // large enough, the adjoint workspace follows the scratch in it
+  const Sizes z = sizes_of(c);
+  const size_t sbytes = scratch_bytes(z);
+  if (!rc) {
+    if (work) {
+      c->scratch = work;
+      c->own_scratch = false;
+      if (work_bytes >= sbytes + adjoint_bytes(z)) {
+        carve_adjoint(c, z, (char*)work + sbytes);
+        c->own_adj = false;
+      }
+    } else if (hipMalloc(&c->scratch, sbytes) != hipSuccess) {
+      c->scratch = nullptr;
+      rc = fail(UGKS_E_DEVICE, "scratch allocation");
+    }
+  }
+  if (!rc) {
+    std::vector<size_t> sz = scratch_sizes(z);
+    std::vector<void**> slot = scratch_slots(c);
+    size_t off = 0;
+    for (size_t i = 0; i < sz.size(); ++i) {
+      *slot[i] = (char*)c->scratch + off;
+      off += align256(std::max<size_t>(sz[i], 256));
+    }
+  }
   if (rc) { free_all(c); delete c; return rc; }
   // scratch that kernels read before writing everywhere starts at zero
   if (hipMemset(c->s_rec, 0, sizeof(double) * NREC * (size_t)c->nface) != hipSuccess ||
@@ -636,6 +800,7 @@ int ugks_create(const ugks_problem* p, int device, ugks_ctx** out) {
     free_all(c); delete c; return fail(UGKS_E_DEVICE, "hipMemset failed");
   }
   fill_dev(c);
+  c->dev.status = c->d_status;
   // default launch shapes (measured on the cylinder workload; ugks_autotune
   // refines them per case): the FP64 flux pass keeps more registers per
   // wavefront with six core rows per workgroup
@@ -880,9 +1045,9 @@ int ugks_flux(ugks_ctx* c, double dts, const void* h, const void* b, const doubl
   if (int rc = check_dev(c, {h, b, W, q, Dh, Db})) return rc;
   if (!(dts > 0) || !std::isfinite(dts)) return fail(UGKS_E_ARG, "dts must be positive");
   hipStream_t st = (hipStream_t)stream;
-  if (wall) HIPCHK(hipMemsetAsync(wall, 0, sizeof(double) * (c->nw + 1) * (size_t)c->nface, st));
+  if (wall) launch_fill(wall, (c->nw + 1) * (size_t)c->nface, 0.0, st);
   double* Fo = F ? F : (double*)c->s_F;
-  HIPCHK(hipMemsetAsync(Fo, 0, sizeof(double) * c->nw * (size_t)c->nface, st));
+  launch_fill(Fo, c->nw * (size_t)c->nface, 0.0, st);
   launch_flux(c->dev, c->prec, (const int*)c->d_binfo, c->max_nj, dts, h, b, W, q, (double*)c->s_gW,
               (double*)c->s_rec, (double*)c->s_part, Dh, Db, Fo, wall, st);
   HIPCHK(hipGetLastError());
@@ -911,14 +1076,14 @@ int ugks_begin_step(ugks_ctx* c, double dt, void* h, void* b, double* W, double*
   c->nref = 0;
   launch_interp(c->dev, c->prec, c->nrec, (const int*)c->d_rec, (const int*)c->d_ptr, (const int*)c->d_don,
                 (const double*)c->d_w, h, b, W, q, st);
-  HIPCHK(hipMemsetAsync(Fn, 0, sizeof(double) * c->nw * (size_t)c->nface, st));
+  launch_fill(Fn, c->nw * (size_t)c->nface, 0.0, st);
   // the level-n divergence is staged in Sh, Sb
   launch_flux(c->dev, c->prec, (const int*)c->d_binfo, c->max_nj, c->dts, h, b, W, q, (double*)c->s_gW,
               (double*)c->s_rec, (double*)c->s_part, Sh, Sb, Fn, nullptr, st);
   launch_cellrec(c->dev, dt, W, q, nullptr, (double*)c->s_crec, st);
   launch_source(c->dev, c->prec, dt, h, b, (const double*)c->s_crec, Sh, Sb, st);
   HIPCHK(hipGetLastError());
-  return UGKS_OK;
+  return c->sync_check ? ugks_status(c, stream) : UGKS_OK;
 }
 
 // the pseudo-iteration loop; with ev (9 events per inner iteration) the
@@ -963,7 +1128,9 @@ int ugks_step(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, double*
   if (int rc = check_dev(c, {h, b, W, Wn, q, Sh, Sb, Fn})) return rc;
   if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
   if (n_inner < 0) return fail(UGKS_E_ARG, "n_inner must be >= 0");
-  return run_inner(c, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, resid, (hipStream_t)stream, nullptr);
+  int rc = run_inner(c, dt, n_inner, h, b, W, Wn, q, Sh, Sb, Fn, resid, (hipStream_t)stream, nullptr);
+  if (!rc && c->sync_check) rc = ugks_status(c, stream);
+  return rc;
 }
 
 int ugks_step_profile(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, double* W, const double* Wn,
@@ -1069,7 +1236,7 @@ int ugks_step_graph(ugks_ctx* c, double dt, int32_t n_inner, void* h, void* b, d
     c->gkey = key;
   }
   HIPCHK(hipGraphLaunch(c->gexec, (hipStream_t)stream));
-  return UGKS_OK;
+  return c->sync_check ? ugks_status(c, stream) : UGKS_OK;
 }
 
 int ugks_batch_create(int32_t ncase, ugks_ctx* const* ctxs, ugks_batch** out) {
@@ -1191,9 +1358,18 @@ int ugks_autotune(ugks_ctx* c, double dt, int32_t n_inner, const void* h, const 
   void *th = nullptr, *tb = nullptr, *tW = nullptr, *tq = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = UGKS_OK;
-  if (hipMalloc(&th, fb) != hipSuccess || hipMalloc(&tb, fb) != hipSuccess || hipMalloc(&tW, wb) != hipSuccess ||
-      hipMalloc(&tq, qb) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+  // state copies: in the adjoint workspace when the context has one (its
+  // first buffers are [ncell][nv] doubles, [ncell][nw] and [ncell][dim]),
+  // else allocated for the call
+  const bool in_adj = !c->adj.empty();
+  if (in_adj) {
+    th = c->adj[0]; tb = c->adj[1]; tW = c->adj[14]; tq = c->adj[16];
+  } else if (hipMalloc(&th, fb) != hipSuccess || hipMalloc(&tb, fb) != hipSuccess ||
+             hipMalloc(&tW, wb) != hipSuccess || hipMalloc(&tq, qb) != hipSuccess) {
     rc = fail(UGKS_E_DEVICE, "autotune scratch");
+  }
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = fail(UGKS_E_DEVICE, "autotune events");
   const Dev saved = c->dev;
   double best = 1e300;
   int bk = saved.kc_max, be = saved.rg_eq, bf = saved.rg_flux;
@@ -1235,7 +1411,8 @@ int ugks_autotune(ugks_ctx* c, double dt, int32_t n_inner, const void* h, const 
     if (choice) { choice[0] = bk; choice[1] = be; choice[2] = bf; }
     if (best_ms) *best_ms = best / n_inner;
   }
-  for (void* p : {th, tb, tW, tq}) if (p) (void)hipFree(p);
+  if (!in_adj)
+    for (void* p : {th, tb, tW, tq}) if (p) (void)hipFree(p);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   return rc;
@@ -1258,26 +1435,33 @@ enum AdjBuf {
   A_DGB, A_GWB, A_GAMB, A_FB, A_FBAR, A_NBUF
 };
 
-int adj_alloc(ugks_ctx* c) {
-  if (!c->adj.empty()) return UGKS_OK;
-  c->adj.assign(A_NBUF, nullptr);
-  const size_t N = (size_t)c->ncell * c->nv, NW = (size_t)c->ncell * c->nw, NQ = (size_t)c->ncell * c->dim;
+std::vector<size_t> adjoint_counts(const Sizes& z) {
+  const size_t N = (size_t)z.ncell * z.nv, NW = (size_t)z.ncell * z.nw, NQ = (size_t)z.ncell * z.dim;
+  std::vector<size_t> out(A_NBUF);
   for (int i = 0; i < A_NBUF; ++i) {
     size_t n;
     if (i <= A_BB) n = N;
     else if (i == A_Q0 || i == A_Q1 || i == A_QB) n = NQ;
     else if (i <= A_WB) n = NW;
-    else if (i == A_DGB) n = c->ncell;
-    else if (i == A_GWB) n = 8 * (size_t)c->ncell;
-    else if (i == A_GAMB) n = c->nface;
-    else if (i == A_FB) n = (size_t)c->nface * c->nw;
-    else n = (size_t)c->nface * 5;
-    if (hipMalloc(&c->adj[i], sizeof(double) * std::max<size_t>(n, 1)) != hipSuccess) {
-      for (void*& p : c->adj) { if (p) (void)hipFree(p); p = nullptr; }
-      c->adj.clear();
-      return fail(UGKS_E_DEVICE, "adjoint workspace allocation");
-    }
+    else if (i == A_DGB) n = z.ncell;
+    else if (i == A_GWB) n = 8 * (size_t)z.ncell;
+    else if (i == A_GAMB) n = z.nface;
+    else if (i == A_FB) n = (size_t)z.nface * z.nw;
+    else n = (size_t)z.nface * 5;
+    out[i] = n;
   }
+  return out;
+}
+
+// the adjoint workspace: the caller's (carved at creation) or one
+// allocation on first use
+int adj_alloc(ugks_ctx* c) {
+  if (!c->adj.empty()) return UGKS_OK;
+  const Sizes z = sizes_of(c);
+  void* base = nullptr;
+  if (hipMalloc(&base, adjoint_bytes(z)) != hipSuccess) return fail(UGKS_E_DEVICE, "adjoint workspace allocation");
+  carve_adjoint(c, z, (char*)base);
+  c->own_adj = true;
   return UGKS_OK;
 }
 
@@ -1486,6 +1670,95 @@ int ugks_begin_step_adjoint(ugks_ctx* c, double dt, const void* h, const void* b
   if (!rc) rc = interp_rows_rev(c, c->nrec, nref, st);
   if (!rc) rc = store_bars(c, h_bar, b_bar, W_bar, q_bar, face_bar, st);
   return rc;
+}
+
+
+// ---------------------------------------------------------------------------
+// status of the device-side checks, wall loads, parameter cotangents
+// ---------------------------------------------------------------------------
+int ugks_status(ugks_ctx* c, void* stream) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  unsigned st = 0;
+  HIPCHK(hipMemcpy(&st, c->d_status, sizeof st, hipMemcpyDeviceToHost));
+  if (st == 0) return UGKS_OK;
+  const unsigned zero = 0;
+  HIPCHK(hipMemcpy(c->d_status, &zero, sizeof zero, hipMemcpyHostToDevice));
+  if (st & kStatusWait)
+    return fail(UGKS_E_DEVICE, "a micro sweep's wait for its neighbour wavefronts ran out; its results are not valid");
+  return fail(UGKS_E_NONPHYS, "Step 7 produced a non-positive density or temperature, or a non-finite state");
+}
+
+int ugks_set_checks(ugks_ctx* c, int32_t sync, int32_t wait_limit) {
+  if (!c) return fail(UGKS_E_ARG, "null context");
+  c->sync_check = sync ? 1 : 0;
+  const int lim = (wait_limit < 0) ? (1 << 20) : wait_limit;
+  if (lim != c->dev.micro_spin) {
+    c->dev.micro_spin = lim;
+    ++c->version;  // captured graphs hold the kernels' arguments
+  }
+  return UGKS_OK;
+}
+
+int ugks_wall_loads(ugks_ctx* c, const double* F, double* face_loads, double* side_loads, void* stream) {
+  if (int rc = check_dev(c, {F})) return rc;
+  launch_wall_loads(c->dev, 4 * (int)c->blk.size(), (const int*)c->d_wptr, (const double*)c->d_wtab, F, face_loads,
+                    side_loads, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+int ugks_wall_loads_adjoint(ugks_ctx* c, const double* face_loads_bar, const double* side_loads_bar, double* F_bar,
+                            void* stream) {
+  if (int rc = check_dev(c, {F_bar})) return rc;
+  launch_wall_loads_adj(c->dev, 4 * (int)c->blk.size(), (const int*)c->d_wptr, (const double*)c->d_wtab,
+                        face_loads_bar, side_loads_bar, F_bar, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+int ugks_param_bars(ugks_ctx* c, const double* face_bar, double* U_bar, double* rtw_bar, void* stream) {
+  if (int rc = check_dev(c, {face_bar, U_bar, rtw_bar})) return rc;
+  launch_param_bars((int)c->blk.size(), (const int*)c->d_bface, (const int*)c->d_wptr, (const double*)c->d_wtab,
+                    face_bar, U_bar, rtw_bar, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+int ugks_newton_euler(ugks_ctx* c, int32_t blk, const double* body, double dt, const double* F, double* pose,
+                      void* stream) {
+  if (int rc = check_dev(c, {F})) return rc;
+  if (!body || !pose) return fail(UGKS_E_ARG, "null host array");
+  if (c->dim != 2) return fail(UGKS_E_UNSUPPORTED, "rigid-body motion is built for 2D cases");
+  if (blk < 0 || blk >= (int)c->blk.size()) return fail(UGKS_E_ARG, "bad block");
+  if (!(body[0] > 0) || !(body[1] > 0) || !std::isfinite(body[0]) || !std::isfinite(body[1]))
+    return fail(UGKS_E_ARG, "mass and moment of inertia must be positive");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(UGKS_E_ARG, "dt must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  launch_wall_loads(c->dev, 4 * (int)c->blk.size(), (const int*)c->d_wptr, (const double*)c->d_wtab, F, nullptr,
+                    (double*)c->d_side, st);
+  HIPCHK(hipGetLastError());
+  std::vector<double> side(16 * c->blk.size());
+  HIPCHK(hipMemcpyAsync(side.data(), c->d_side, sizeof(double) * side.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // force and moment on the body: its walls' loads plus the external load;
+  // velocities by an explicit step, the pose by the trapezoidal rule (exact
+  // for constant loads)
+  double fx = body[2], fy = body[3], mz = body[4];
+  for (int sd = 0; sd < 4; ++sd) {
+    if (c->blk[blk].bc[sd] != UGKS_BC_WALL) continue;
+    fx += side[16 * (size_t)blk + 4 * sd + 0];
+    fy += side[16 * (size_t)blk + 4 * sd + 1];
+    mz += side[16 * (size_t)blk + 4 * sd + 2];
+  }
+  const double ux = pose[3] + dt * fx / body[0];
+  const double uy = pose[4] + dt * fy / body[0];
+  const double om = pose[5] + dt * mz / body[1];
+  pose[0] += 0.5 * dt * (pose[3] + ux);
+  pose[1] += 0.5 * dt * (pose[4] + uy);
+  pose[2] += 0.5 * dt * (pose[5] + om);
+  pose[3] = ux; pose[4] = uy; pose[5] = om;
+  return UGKS_OK;
 }
 
 }  // extern "C"

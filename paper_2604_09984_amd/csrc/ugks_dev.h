@@ -70,6 +70,11 @@ __host__ __device__ __forceinline__ int tab_int(double v) {
 // (the last three int32 entries, read with tab_int)
 enum : int { kFpN0 = 0, kFpS = 2, kFpU = 3, kFpDL = 5, kFpDR = 7, kFpL = 9, kFpR = 10, kFpAct = 11, kFpN = 12 };
 
+// wall table entry (double; the face id as an int32 entry): face id, area,
+// sign turning the face normal into the normal pointing into the wall, that
+// inward normal, face centre relative to the block's moved rotation centre
+enum : int { kWtFace = 0, kWtS, kWtSgn, kWtNx, kWtNy, kWtRx, kWtRy, kWtN = 8 };
+
 // per-cell record (double): state of the Shakhov source, the micro LU-SGS
 // diagonal base 1/dt' + 1/dt + 1/(2 tau) and, per slot s, the face
 // coefficients (A, B, C) with S/(2|Omega|) * w.n_out = A vx + B vy - C
@@ -110,7 +115,21 @@ struct Dev {
   // on them): widest velocity chunk of the micro sweep, core rows per
   // workgroup of the face-equilibrium and flux march kernels
   int kc_max = 16, rg_eq = 8, rg_flux = 8;
+  // device status word of the context (bits kStatus*), set by the kernels
+  // that detect a failure and read by the host at a synchronisation
+  unsigned* status = nullptr;
+  // bound of the micro sweep's wait for its neighbour wavefronts (sleeps)
+  int micro_spin = 1 << 20;
 };
+
+// bits of the device status word
+constexpr unsigned kStatusWait = 1u;     // a sweep's neighbour wait ran out
+constexpr unsigned kStatusNonPhys = 2u;  // Step 7 produced rho <= 0, T <= 0 or a non-finite W
+
+// sets bits of the status word (one vector atomic per calling lane)
+__device__ __forceinline__ void raise_status(unsigned* st, unsigned bits) {
+  if (st) __hip_atomic_fetch_or(st, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ------------------------------------------------------------------------
 // gas relations

@@ -39,4 +39,17 @@ void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_
                   const double* crec, void* h, void* b, const void* Sh, const void* Sb, void* Dh, void* Db,
                   hipStream_t st, hipEvent_t* ev = nullptr);
 
+// fills n doubles with v (a kernel, so that captured graphs hold no memset)
+void launch_fill(double* a, size_t n, double v, hipStream_t st);
+// wall loads from a face macro flux F: face_out [nface][dim+3] (zero off the
+// walls), side_out [nside][4]; either may be null
+void launch_wall_loads(const Dev& g, int nside, const int* wptr, const double* wtab, const double* F,
+                       double* face_out, double* side_out, hipStream_t st);
+// F_bar [nface][nw] (written) from the cotangents of the wall loads
+void launch_wall_loads_adj(const Dev& g, int nside, const int* wptr, const double* wtab, const double* face_bar,
+                           const double* side_bar, double* F_bar, hipStream_t st);
+// U_bar [nblock][2], rtw_bar [nblock][4] from per-face cotangents [nface][5]
+void launch_param_bars(int nblock, const int* bface, const int* wptr, const double* wtab, const double* face_bar,
+                       double* U_bar, double* rtw_bar, hipStream_t st);
+
 }  // namespace ugks

@@ -1187,7 +1187,13 @@ __global__ __launch_bounds__(256) void k_step7(Dev g, int mode, const T* __restr
   const double* wp = Wp + (size_t)c * g.nw;
   double fm[4] = {fm0, fm1, fm2, fmE}, gm[4] = {g0, g1, g2, g3};
   if (g.dim == 1) { fm[2] = fmE; gm[2] = g3; }
-  for (int m = 0; m < g.nw; ++m) w[m] = wp[m] + (fm[m] - gm[m]);
+  bool finite = true;
+  for (int m = 0; m < g.nw; ++m) {
+    w[m] = wp[m] + (fm[m] - gm[m]);
+    finite = finite && isfinite(w[m]);
+  }
+  // a non-physical or non-finite state is reported through the status word
+  if (!finite || !physical_state(g.dim, w)) raise_status(g.status, kStatusNonPhys);
   double r2, ux, uy, l2;
   prim_of(g, w, r2, ux, uy, l2);
   double qx, qy;
@@ -1734,7 +1740,7 @@ __global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const doubl
 // wavefronts).  Each wavefront then publishes its count of finished
 // hyperplanes in LDS and waits for its two neighbours to have finished the
 // previous one, instead of a workgroup barrier: the wavefront with the least
-// progress can always go on, and the wait is bounded (kMicroSpin sleeps) so
+// progress can always go on, and the wait is bounded (Dev::micro_spin sleeps) so
 // that the kernel ends in any case.  A periodic j seam, or threads beyond
 // NTR * KC, use the barrier.
 //
@@ -1750,7 +1756,6 @@ __global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const doubl
 constexpr bool micro_fused(int kc, int rows) { return rows == 1 && kc >= 8 && kc <= 16; }
 constexpr int micro_rec_lds(int kc, int rows) { return micro_fused(kc, rows) ? 24 : 16; }
 constexpr int kMicroProg = 8;   // doubles of LDS for the 16 progress counters
-constexpr int kMicroSpin = 1 << 20;
 
 // 1/d for d > 0 of moderate size: hardware estimate and two Newton steps
 __device__ __forceinline__ double recip_pos(double d) {
@@ -1823,13 +1828,20 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
     return __builtin_amdgcn_readfirstlane(__hip_atomic_load(&prog[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
   };
   // before a hyperplane: both neighbour wavefronts have finished `done`
+  // If the bound runs out the wavefront goes on (so the kernel always ends)
+  // and sets the context's status bit: its results are then not valid and
+  // the host reports the failure at its next status check.
+  const int spin_limit = g.micro_spin;
   auto wait_neighbours = [&]() {
-    for (int spin = 0; spin < kMicroSpin; ++spin) {
+    bool ready = false;
+    for (int spin = 0;; ++spin) {
       const bool lo = (lo_wv < 0) || (lo_wv == wv) || prog_of(lo_wv) >= done;
       const bool hi = (hi_wv < 0) || (hi_wv == wv) || prog_of(hi_wv) >= done;
-      if (lo && hi) break;
+      ready = lo && hi;
+      if (ready || spin >= spin_limit) break;
       __builtin_amdgcn_s_sleep(1);
     }
+    if (!ready && (t & 63) == 0) raise_status(g.status, kStatusWait);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
   };
   // after a hyperplane's hand-off writes
@@ -2262,6 +2274,144 @@ int init_kernel_attributes() {
                         (const void*)k_macro_sweep<2, 512>})
     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess) return -1;
   return 0;
+}
+
+}  // namespace ugks
+
+namespace ugks {
+
+// ------------------------------------------------------------------------
+// wall loads (Sec. 2.1: the macro flux into an isothermal wall gives the
+// pressure and shear load and the heat flux on the body).  The wall table
+// lists the wall faces of each (block, side) in face order; entry e holds
+// kWt* fields: face id, area, the sign that turns the face normal into the
+// normal pointing into the wall, that inward normal, and the face centre
+// relative to the block's moved rotation centre.  One thread per (block,
+// side) walks its faces in order, so the sums are reproducible.
+// ------------------------------------------------------------------------
+__global__ void k_fill(double* __restrict__ a, size_t n, double v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_wall_loads(Dev g, int nside, const int* __restrict__ wptr, const double* __restrict__ wtab,
+                             const double* __restrict__ F, double* __restrict__ face_out,
+                             double* __restrict__ side_out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nside) return;
+  const int D = g.dim, nw = g.nw;
+  double fx = 0.0, fy = 0.0, mz = 0.0, qe = 0.0;
+  for (int e = wptr[s]; e < wptr[s + 1]; ++e) {
+    const double* t = wtab + (size_t)e * kWtN;
+    const int f = tab_int(t[kWtFace]);
+    const double S = t[kWtS], sg = t[kWtSgn], nix = t[kWtNx], niy = t[kWtNy];
+    const double* Ff = F + (size_t)f * nw;
+    // flux into the wall per unit area: momentum (the load on the body)
+    // and energy
+    const double mx = sg * Ff[1], my = (D == 2) ? sg * Ff[2] : 0.0, en = sg * Ff[D + 1];
+    if (face_out) {
+      double* o = face_out + (size_t)f * (D + 3);
+      o[0] = mx;
+      if (D == 2) o[1] = my;
+      o[D] = mx * nix + my * niy;        // pressure load p_w
+      o[D + 1] = -mx * niy + my * nix;   // shear load sigma_w along (-n_y, n_x)
+      o[D + 2] = en;                     // heat flux q_w
+    }
+    fx += S * mx;
+    fy += S * my;
+    mz += S * (t[kWtRx] * my - t[kWtRy] * mx);
+    qe += S * en;
+  }
+  if (side_out) {
+    double* o = side_out + (size_t)s * 4;
+    o[0] = fx; o[1] = fy; o[2] = mz; o[3] = qe;
+  }
+}
+
+// transpose of k_wall_loads with respect to F (F_bar of non-wall faces is
+// zeroed before)
+__global__ void k_wall_loads_adj(Dev g, int nside, const int* __restrict__ wptr, const double* __restrict__ wtab,
+                                 const double* __restrict__ face_bar, const double* __restrict__ side_bar,
+                                 double* __restrict__ F_bar) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nside) return;
+  const int D = g.dim, nw = g.nw;
+  const double* sb = side_bar ? side_bar + (size_t)s * 4 : nullptr;
+  for (int e = wptr[s]; e < wptr[s + 1]; ++e) {
+    const double* t = wtab + (size_t)e * kWtN;
+    const int f = tab_int(t[kWtFace]);
+    const double S = t[kWtS], sg = t[kWtSgn], nix = t[kWtNx], niy = t[kWtNy];
+    double bmx = 0.0, bmy = 0.0, ben = 0.0;
+    if (face_bar) {
+      const double* o = face_bar + (size_t)f * (D + 3);
+      bmx = o[0] + o[D] * nix - o[D + 1] * niy;
+      if (D == 2) bmy = o[1] + o[D] * niy + o[D + 1] * nix;
+      ben = o[D + 2];
+    }
+    if (sb) {
+      bmx += S * (sb[0] - t[kWtRy] * sb[2]);
+      bmy += S * (sb[1] + t[kWtRx] * sb[2]);
+      ben += S * sb[3];
+    }
+    double* Fb = F_bar + (size_t)f * nw;
+    Fb[1] = sg * bmx;
+    if (D == 2) Fb[2] = sg * bmy;
+    Fb[D + 1] = sg * ben;
+  }
+}
+
+// rigid-velocity and wall-RT cotangents of each block from the per-face
+// cotangents [nface][5] (face grid velocity x, y; wall velocity x, y; wall
+// RT): one workgroup of 256 threads per block sums its faces (strided, then
+// a fixed tree), and four threads sum the wall RT entries of its sides
+__global__ __launch_bounds__(256) void k_param_bars(int nblock, const int* __restrict__ bface,
+                                                    const int* __restrict__ wptr, const double* __restrict__ wtab,
+                                                    const double* __restrict__ face_bar, double* __restrict__ U_bar,
+                                                    double* __restrict__ rtw_bar) {
+  __shared__ double red[2][256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  if (b >= nblock) return;
+  double sx = 0.0, sy = 0.0;
+  for (int f = bface[b] + t; f < bface[b + 1]; f += 256) {
+    const double* fb = face_bar + (size_t)f * 5;
+    sx += fb[0] + fb[2];
+    sy += fb[1] + fb[3];
+  }
+  red[0][t] = sx;
+  red[1][t] = sy;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) { red[0][t] += red[0][t + w]; red[1][t] += red[1][t + w]; }
+    __syncthreads();
+  }
+  if (t == 0) { U_bar[2 * b] = red[0][0]; U_bar[2 * b + 1] = red[1][0]; }
+  if (t < 4) {
+    const int s = 4 * b + t;
+    double r = 0.0;
+    for (int e = wptr[s]; e < wptr[s + 1]; ++e) r += face_bar[(size_t)tab_int(wtab[(size_t)e * kWtN + kWtFace]) * 5 + 4];
+    rtw_bar[s] = r;
+  }
+}
+
+void launch_fill(double* a, size_t n, double v, hipStream_t st) {
+  if (n > 0) k_fill<<<nbl(n, 256), 256, 0, st>>>(a, n, v);
+}
+
+void launch_wall_loads(const Dev& g, int nside, const int* wptr, const double* wtab, const double* F,
+                       double* face_out, double* side_out, hipStream_t st) {
+  if (face_out) launch_fill(face_out, (size_t)g.nface * (g.dim + 3), 0.0, st);
+  k_wall_loads<<<nbl(nside, 64), 64, 0, st>>>(g, nside, wptr, wtab, F, face_out, side_out);
+}
+
+void launch_wall_loads_adj(const Dev& g, int nside, const int* wptr, const double* wtab, const double* face_bar,
+                           const double* side_bar, double* F_bar, hipStream_t st) {
+  launch_fill(F_bar, (size_t)g.nface * g.nw, 0.0, st);
+  k_wall_loads_adj<<<nbl(nside, 64), 64, 0, st>>>(g, nside, wptr, wtab, face_bar, side_bar, F_bar);
+}
+
+void launch_param_bars(int nblock, const int* bface, const int* wptr, const double* wtab, const double* face_bar,
+                       double* U_bar, double* rtw_bar, hipStream_t st) {
+  k_param_bars<<<nblock, 256, 0, st>>>(nblock, bface, wptr, wtab, face_bar, U_bar, rtw_bar);
 }
 
 }  // namespace ugks

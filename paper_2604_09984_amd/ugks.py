@@ -80,6 +80,14 @@ def lib():
         L.ugks_flux_adjoint.argtypes = [vp] + [vp] * 12 + [vp]
         L.ugks_step_adjoint.argtypes = [vp, d] + [vp] * 22 + [vp]
         L.ugks_begin_step_adjoint.argtypes = [vp, d, vp, vp, vp, vp, i32] + [vp] * 12 + [vp]
+        L.ugks_workspace_size.argtypes = [C.POINTER(_Problem), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+        L.ugks_create_with_workspace.argtypes = [C.POINTER(_Problem), C.c_int, vp, C.c_size_t, C.POINTER(vp)]
+        L.ugks_status.argtypes = [vp, vp]
+        L.ugks_set_checks.argtypes = [vp, i32, i32]
+        L.ugks_wall_loads.argtypes = [vp, vp, vp, vp, vp]
+        L.ugks_wall_loads_adjoint.argtypes = [vp, vp, vp, vp, vp]
+        L.ugks_param_bars.argtypes = [vp, vp, vp, vp, vp]
+        L.ugks_newton_euler.argtypes = [vp, i32, C.POINTER(d), d, vp, C.POINTER(d), vp]
         _lib = L
     return _lib
 
@@ -92,6 +100,8 @@ def exported_symbols():
             "ugks_batch_destroy", "ugks_set_tuning", "ugks_get_tuning", "ugks_micro_shape", "ugks_autotune", "ugks_set_wall_rt",
             "ugks_last_flux", "ugks_set_block_velocity", "ugks_face_geometry", "ugks_overset_rows",
             "ugks_flux_adjoint", "ugks_step_adjoint", "ugks_begin_step_adjoint",
+            "ugks_workspace_size", "ugks_create_with_workspace", "ugks_status", "ugks_set_checks",
+            "ugks_wall_loads", "ugks_wall_loads_adjoint", "ugks_param_bars", "ugks_newton_euler",
             "ugks_last_error"]
 
 
@@ -112,37 +122,63 @@ def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-class Solver:
-    """A libugks context for one case (see workloads.Case)."""
+def _problem(case, prec):
+    """The ugks_problem of a case and the host arrays it points to."""
+    vx = np.ascontiguousarray(case.vx, dtype=np.float64)
+    vy = np.ascontiguousarray(case.vy, dtype=np.float64)
+    bint = case.block_ints()
+    bdbl = case.block_dbls()
+    nodes = case.node_array()
+    p = _Problem()
+    p.dim = case.dim
+    p.pr, p.omega, p.mu_ref, p.rt_ref = case.pr, case.omega, case.mu_ref, case.rt_ref
+    p.nvx, p.nvy = case.nvx, case.nvy
+    p.vx, p.vy = _dp(vx), _dp(vy)
+    for m in range(4):
+        p.vrange[m] = float(case.vrange[m])
+        p.winf[m] = float(case.winf[m]) if m < case.nw else 0.0
+    p.cfl_s, p.cfl_p = case.cfl_s, case.cfl_p
+    p.nblock = len(case.blocks)
+    p.bint = bint.ctypes.data_as(C.POINTER(C.c_int32))
+    p.bdbl = _dp(bdbl)
+    p.nodes = _dp(nodes)
+    p.prec = prec
+    return p, (vx, vy, bint, bdbl, nodes)
 
-    def __init__(self, case, prec: int = F64, device: int = 0):
+
+def workspace_size(case, prec: int = F64):
+    """(scratch bytes, adjoint workspace bytes) of a case (ugks_workspace_size)."""
+    p, keep = _problem(case, prec)
+    a, b = C.c_size_t(), C.c_size_t()
+    _check(lib().ugks_workspace_size(C.byref(p), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+class Solver:
+    """A libugks context for one case (see workloads.Case).  With
+    workspace="scratch" or "all" the context's scratch (and with "all" also
+    the reverse-mode workspace) lives in a torch-allocated device buffer
+    (ugks_create_with_workspace) that the Solver keeps."""
+
+    def __init__(self, case, prec: int = F64, device: int = 0, workspace: Optional[str] = None):
         L = lib()
         self.case = case
         self.prec = prec
         self.device = torch.device("cuda", device)
         self.dtype = torch.float64 if prec == F64 else torch.float32
-        vx = np.ascontiguousarray(case.vx, dtype=np.float64)
-        vy = np.ascontiguousarray(case.vy, dtype=np.float64)
-        bint = case.block_ints()
-        bdbl = case.block_dbls()
-        nodes = case.node_array()
-        self._keep = (vx, vy, bint, bdbl, nodes)
-        p = _Problem()
-        p.dim = case.dim
-        p.pr, p.omega, p.mu_ref, p.rt_ref = case.pr, case.omega, case.mu_ref, case.rt_ref
-        p.nvx, p.nvy = case.nvx, case.nvy
-        p.vx, p.vy = _dp(vx), _dp(vy)
-        for m in range(4):
-            p.vrange[m] = float(case.vrange[m])
-            p.winf[m] = float(case.winf[m]) if m < case.nw else 0.0
-        p.cfl_s, p.cfl_p = case.cfl_s, case.cfl_p
-        p.nblock = len(case.blocks)
-        p.bint = bint.ctypes.data_as(C.POINTER(C.c_int32))
-        p.bdbl = _dp(bdbl)
-        p.nodes = _dp(nodes)
-        p.prec = prec
+        p, self._keep = _problem(case, prec)
         ctx = C.c_void_p()
-        _check(L.ugks_create(C.byref(p), device, C.byref(ctx)))
+        if workspace is None:
+            _check(L.ugks_create(C.byref(p), device, C.byref(ctx)))
+            self.workspace = None
+        else:
+            sb, ab = workspace_size(case, prec)
+            nbytes = sb + (ab if workspace == "all" else 0)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            off = (-base) % 256
+            _check(L.ugks_create_with_workspace(C.byref(p), device, C.c_void_p(base + off), C.c_size_t(nbytes),
+                                                C.byref(ctx)))
         self.ctx = ctx
         n = [C.c_int32() for _ in range(4)]
         _check(L.ugks_sizes(ctx, *[C.byref(x) for x in n]))
@@ -305,6 +341,56 @@ class Solver:
         v = [C.c_int32() for _ in range(3)]
         _check(lib().ugks_overset_rows(self.ctx, *[C.byref(x) for x in v]))
         return tuple(x.value for x in v)
+
+    def status(self, stream=None):
+        """Waits for the stream and raises UgksError if a device-side check
+        failed (ugks_status: -3 a sweep's wait ran out, -4 a non-physical
+        state)."""
+        _check(lib().ugks_status(self.ctx, self._stream(stream)))
+
+    def status_code(self, stream=None) -> int:
+        """ugks_status's return code (0 when no check failed)."""
+        return int(lib().ugks_status(self.ctx, self._stream(stream)))
+
+    def set_checks(self, sync=False, wait_limit=-1):
+        """ugks_set_checks: synchronising status checks; bound of the micro
+        sweep's neighbour wait (negative: default)."""
+        _check(lib().ugks_set_checks(self.ctx, int(bool(sync)), int(wait_limit)))
+
+    def wall_loads(self, F, stream=None):
+        """(face loads [nface][dim+3], side loads [nblock][4][4]) of a face
+        macro flux F (ugks_wall_loads)."""
+        fo = self.zeros_face(self.dim + 3)
+        so = torch.zeros((len(self.case.blocks), 4, 4), dtype=torch.float64, device=self.device)
+        _check(lib().ugks_wall_loads(self.ctx, _p(F.contiguous()), _p(fo), _p(so), self._stream(stream)))
+        return fo, so
+
+    def wall_loads_adjoint(self, face_bar=None, side_bar=None, stream=None):
+        """F_bar [nface][nw] from cotangents of the wall loads."""
+        Fb = self.zeros_face(self.nw)
+        _check(lib().ugks_wall_loads_adjoint(self.ctx, _p(None if face_bar is None else face_bar.contiguous()),
+                                             _p(None if side_bar is None else side_bar.contiguous()), _p(Fb),
+                                             self._stream(stream)))
+        return Fb
+
+    def param_bars(self, face_bar, stream=None):
+        """(U_bar [nblock][2], rtw_bar [nblock][4]) from per-face
+        cotangents [nface][5] (ugks_param_bars)."""
+        nb = len(self.case.blocks)
+        U = torch.zeros((nb, 2), dtype=torch.float64, device=self.device)
+        R = torch.zeros((nb, 4), dtype=torch.float64, device=self.device)
+        _check(lib().ugks_param_bars(self.ctx, _p(face_bar.contiguous()), _p(U), _p(R), self._stream(stream)))
+        return U, R
+
+    def newton_euler(self, blk, body, dt, F, pose, stream=None):
+        """The block's pose [6] after one Newton-Euler step driven by the wall
+        loads of F and the external load in body = (m, I, Fx, Fy, Mz)
+        (ugks_newton_euler); returns the new pose (host)."""
+        p = np.ascontiguousarray(np.array(pose, dtype=np.float64))
+        bd = np.ascontiguousarray(np.array(body, dtype=np.float64))
+        _check(lib().ugks_newton_euler(self.ctx, int(blk), _dp(bd), float(dt), _p(F.contiguous()), _dp(p),
+                                       self._stream(stream)))
+        return p
 
     def last_flux(self, stream=None):
         """Face macro flux [nface][nw] of the last flux evaluation."""

@@ -63,3 +63,33 @@ def test_null_context_is_an_argument_error():
     L = ugks.lib()
     assert L.ugks_flux(None, 1.0, None, None, None, None, None, None, None, None, None) == -1
     assert L.ugks_destroy(None) == 0
+
+
+def test_workspace_size_without_device():
+    """ugks_workspace_size is host arithmetic on the problem: the scratch
+    holds at least the two [ncell][nv] divergence / residual arrays and the
+    adjoint workspace at least its 14 FP64 [ncell][nv] arrays; bad problems
+    are rejected as by ugks_create."""
+    from paper_2604_09984_amd import ugks, workloads as wl
+    case = wl.cylinder(ni=16, nj=8, nvx=12)
+    n = case.ncell * case.nv
+    s64, a64 = ugks.workspace_size(case, ugks.F64)
+    s32, a32 = ugks.workspace_size(case, ugks.F32)
+    assert s64 >= 2 * 8 * n and s32 >= 2 * 4 * n and s32 < s64
+    assert a64 == a32 >= 14 * 8 * n
+    p, keep = _problem(ugks, case, dim=3)
+    a, b = C.c_size_t(), C.c_size_t()
+    assert ugks.lib().ugks_workspace_size(C.byref(p), C.byref(a), C.byref(b)) == -1
+
+
+def test_create_with_workspace_rejects_bad_buffers_without_device():
+    from paper_2604_09984_amd import ugks, workloads as wl
+    case = wl.sod_1d(20, 9)
+    p, keep = _problem(ugks, case)
+    ctx = C.c_void_p()
+    L = ugks.lib()
+    assert L.ugks_create_with_workspace(C.byref(p), 0, None, 1 << 20, C.byref(ctx)) == -1
+    assert L.ugks_create_with_workspace(C.byref(p), 0, C.c_void_p(4096 + 8), 1 << 20, C.byref(ctx)) == -1
+    s, _ = ugks.workspace_size(case, ugks.F64)
+    assert L.ugks_create_with_workspace(C.byref(p), 0, C.c_void_p(4096), s - 1, C.byref(ctx)) == -2
+    assert not ctx.value

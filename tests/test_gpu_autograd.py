@@ -4,9 +4,10 @@ oracle's reference gradient (the dual-number tangent build run through the
 same physical steps) and against central differences of the HIP forward
 path.
 
-Objective: wall heat flux and force on a body (the face macro flux of the last
-inner iteration of each physical step, weighted by wall_weights) plus a
-random linear functional of the final distribution.  Parameters: the rigid
+Objective: wall heat flux and force on a body (the side loads the library
+forms from the face macro flux of the last inner iteration of each physical
+step, ugks_wall_loads; the oracle's or_wall_loads on its side) plus a random
+linear functional of the final distribution.  Parameters: the rigid
 velocity of a block (dt_s and dt' held at the pose's values) and the wall
 temperature; and the initial distribution.
 """
@@ -78,7 +79,7 @@ class Run:
         h = dev(self.h0, s.dtype) if h0 is None else h0
         b, W, q = dev(self.b0, s.dtype), dev(self.W0), dev(self.q0)
         J = 0.0
-        self.dts, self.dtps, self.ws, self.dtk = [], [], [], []
+        self.dts, self.dtps, self.dtk = [], [], []
         for k in range(self.n_phys):
             setup = self.setup_fn(k, s.types())
             if setup is not None:
@@ -86,12 +87,10 @@ class Run:
             dts, dtp = s.timesteps()
             dt = self.dt_over * dts
             self.dts.append(dts); self.dtps.append(dtp); self.dtk.append(dt)
-            wts = adjoint.wall_weights(s, self.body, self.sides)
-            self.ws.append(host(wts))
             h, b, W, q, F = adjoint.physical_step(s, dt, self.n_inner, h, b, W, q, U, rtw, setup=setup,
                                                   checkpoint=checkpoint)
-            D = case.dim
-            J = J + (wts * (self.c[0] * F[:, D + 1] + self.c[1] * F[:, 1] + self.c[2] * F[:, 2])).sum()
+            L = adjoint.wall_loads(s, F)[self.body, list(self.sides)]
+            J = J + (self.c[0] * L[:, 3] + self.c[1] * L[:, 0] + self.c[2] * L[:, 1]).sum()
         J = J + (dev(self.yh) * h).sum()
         return J
 
@@ -131,10 +130,10 @@ class Run:
             F = ot._z(max(ot.nface, 1), case.nw)
             for _ in range(self.n_inner):
                 ot.pseudo_step((dt, 0.0), (dts, 0.0), dual(self.dtps[k]), h, b, W, Wn, q, Sh, Sb, Fn, F)
-            w = self.ws[k][self.idx]
-            D = case.dim
-            G = self.c[0] * F[:ot.nface, D + 1] + self.c[1] * F[:ot.nface, 1] + self.c[2] * F[:ot.nface, 2]
-            Jv += float(np.sum(w * G[:, 0])); Jd += float(np.sum(w * G[:, 1]))
+            _, side = ot.wall_loads(F[:ot.nface])
+            L = side[self.body, list(self.sides)]
+            G = self.c[0] * L[:, 3] + self.c[1] * L[:, 0] + self.c[2] * L[:, 1]
+            Jv += float(np.sum(G[..., 0])); Jd += float(np.sum(G[..., 1]))
         Jv += float(np.sum(self.yh * h[..., 0])); Jd += float(np.sum(self.yh * h[..., 1]))
         return Jv, Jd
 

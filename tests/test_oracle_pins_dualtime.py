@@ -502,3 +502,38 @@ def test_sod_euler_limit(oracle_lib):
     ref = exact_riemann_density(xc, t, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
     l1 = np.abs(W[:, 0] - ref).mean()
     assert l1 <= 2e-2, l1
+
+
+# --------------------------------------------------------------------------
+# wall loads (Sec. 2.1: the macro flux into an isothermal wall)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kn", [0.1, 0.0])
+def test_wall_loads_of_resting_gas(oracle_lib, kn):
+    """A resting uniform gas at the walls' temperature in the closed unit box
+    presses on each wall with p = rho RT along the normal into the wall, with
+    no shear and no heat flux: side forces p (-1, 0), p (1, 0), p (0, -1),
+    p (0, 1) and moments about the origin p/2, -p/2, -p/2, p/2 (integrals of
+    r x p n over each unit side); kn = 0 is collisionless."""
+    rho, rt = 1.3, 0.5
+    case = wl.cavity(6, 8, kn=max(kn, 0.1), lid=0.0)
+    if kn == 0.0:
+        case.mu_ref = 0.0
+    case.vx = wl.uniform_points(39, -6.0, 6.0)
+    case.vy = case.vx.copy()
+    case.vrange = (-6.0, 6.0, -6.0, 6.0)
+    case.w_init = np.tile(wl.cons(2, rho, [0.0, 0.0], rt), (case.ncell, 1))
+    o = Oracle(case)
+    h, b, W, q = o.init_state()
+    dts, _ = o.timesteps()
+    _, _, F, _ = o.flux(dts, h, b, W, q)
+    face, side = o.wall_loads(F)
+    p = rho * rt
+    want = np.array([[-p, 0.0, p / 2, 0.0], [p, 0.0, -p / 2, 0.0],
+                     [0.0, -p, -p / 2, 0.0], [0.0, p, p / 2, 0.0]])
+    assert np.allclose(side[0], want, rtol=0, atol=1e-9 * p), side[0] - want
+    g = o.geometry()
+    walls = (g["fl"] < 0) | (g["fr"] < 0)
+    assert np.allclose(face[walls, 2], p, rtol=1e-9)      # pressure
+    assert np.abs(face[walls, 3]).max() < 1e-12 * p       # shear
+    assert np.abs(face[walls, 4]).max() < 1e-12 * p       # heat flux
+    assert np.all(face[~walls] == 0.0)
