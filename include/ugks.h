@@ -219,6 +219,23 @@ int ugks_heatflux(ugks_ctx* ctx, const void* h, const void* b, const double* W, 
 int ugks_flux(ugks_ctx* ctx, double dts, const void* h, const void* b, const double* W,
               const double* q, void* Dh, void* Db, double* F, double* wall, void* stream);
 
+/*
+ * ugks_flux for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same operation and results as ugks_flux, with its scratch (W
+ * gradients, face records, per-chunk partial sums, and the face macro flux
+ * when F is NULL) in the library's file-scope static device array of
+ * 128 MiB instead of the context's buffers.  Calls no allocating routine.
+ * UGKS_E_SHAPE (nothing launched) when the case needs more than the array:
+ * 8 ncell + 40 nface + 9 nface ceil(nv/64) (+ (dim+2) nface with F NULL)
+ * doubles, each part rounded up to 256 bytes.  Every call on a device
+ * shares that device's array, which keeps the last call's contents (the
+ * face records are cleared on entry): calls that overlap on one device,
+ * on any stream or context, race.
+ */
+int ugks_flux_noalloc(ugks_ctx* ctx, double dts, const void* h, const void* b, const double* W, const double* q,
+                      void* Dh, void* Db, double* F, double* wall, void* stream);
+
 /* Overset interpolation (Sec. 3.2) of h, b, W and q into the receptor rows,
    in place. */
 int overset_interp(ugks_ctx* ctx, void* h, void* b, double* W, double* q, void* stream);

@@ -106,6 +106,10 @@ struct ugks_ctx {
   std::vector<int> wptr, bface;
   void *d_wtab = nullptr, *d_wptr = nullptr, *d_bface = nullptr;
   void* d_side = nullptr;  // [nblock][4][4] side loads of the body motion
+  // this device's address of the library's static scratch array (entry
+  // points that allocate nothing), looked up at creation; null if the
+  // lookup failed
+  void* sscratch = nullptr;
 };
 
 namespace {
@@ -719,6 +723,8 @@ static int create_ctx(const ugks_problem* p, int device, void* work, size_t work
       ready.push_back(device);
     }
   }
+  // the static scratch of ugks_flux_noalloc: its address on this device
+  if (static_scratch(device, &c->sscratch)) c->sscratch = nullptr;
   int rc = UGKS_OK;
   std::vector<int> binfo(8 * c->blk.size(), 0);
   for (size_t b = 0; b < c->blk.size(); ++b) {
@@ -1050,6 +1056,38 @@ int ugks_flux(ugks_ctx* c, double dts, const void* h, const void* b, const doubl
   launch_fill(Fo, c->nw * (size_t)c->nface, 0.0, st);
   launch_flux(c->dev, c->prec, (const int*)c->d_binfo, c->max_nj, dts, h, b, W, q, (double*)c->s_gW,
               (double*)c->s_rec, (double*)c->s_part, Dh, Db, Fo, wall, st);
+  HIPCHK(hipGetLastError());
+  return UGKS_OK;
+}
+
+int ugks_flux_noalloc(ugks_ctx* c, double dts, const void* h, const void* b, const double* W, const double* q,
+                      void* Dh, void* Db, double* F, double* wall, void* stream) {
+  if (int rc = check_dev(c, {h, b, W, q, Dh, Db})) return rc;
+  if (!(dts > 0) || !std::isfinite(dts)) return fail(UGKS_E_ARG, "dts must be positive");
+  if (!c->sscratch) return fail(UGKS_E_DEVICE, "the static scratch array has no address on this device");
+  // the flux's scratch carved from the static array: W gradients, face
+  // records, chunk partial sums, and the face macro flux when F is NULL
+  const size_t sz[4] = {sizeof(double) * 8 * (size_t)c->ncell, sizeof(double) * NREC * (size_t)c->nface,
+                        sizeof(double) * flux_part_doubles(c->nv, c->nface),
+                        F ? 0 : sizeof(double) * c->nw * (size_t)c->nface};
+  size_t off[4], total = 0;
+  for (int i = 0; i < 4; ++i) { off[i] = total; total += (sz[i] + 255) & ~(size_t)255; }
+  if (total > kStaticScratchBytes)
+    return fail(UGKS_E_SHAPE, "ugks_flux_noalloc needs " + std::to_string(total) + " bytes of scratch, above its " +
+                                  std::to_string(kStaticScratchBytes) + "-byte static array");
+  char* base = (char*)c->sscratch;
+  double* gW = (double*)(base + off[0]);
+  double* rec = (double*)(base + off[1]);
+  double* part = (double*)(base + off[2]);
+  double* Fo = F ? F : (double*)(base + off[3]);
+  hipStream_t st = (hipStream_t)stream;
+  // the array keeps the last call's contents: the face records start at zero
+  // like the context's (fill kernels, no memset)
+  launch_fill(rec, NREC * (size_t)c->nface, 0.0, st);
+  if (wall) launch_fill(wall, (c->nw + 1) * (size_t)c->nface, 0.0, st);
+  launch_fill(Fo, c->nw * (size_t)c->nface, 0.0, st);
+  launch_flux(c->dev, c->prec, (const int*)c->d_binfo, c->max_nj, dts, h, b, W, q, gW, rec, part, Dh, Db, Fo, wall,
+              st);
   HIPCHK(hipGetLastError());
   return UGKS_OK;
 }

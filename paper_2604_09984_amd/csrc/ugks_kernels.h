@@ -52,4 +52,11 @@ void launch_wall_loads_adj(const Dev& g, int nside, const int* wptr, const doubl
 void launch_param_bars(int nblock, const int* bface, const int* wptr, const double* wtab, const double* face_bar,
                        double* U_bar, double* rtw_bar, hipStream_t st);
 
+// The scratch array of the entry points that allocate nothing: a file-scope
+// device array of kStaticScratchBytes, one per device.  Sets *ptr to this
+// device's address of it (looked up once per device, with that device
+// current, then cached); 0 on success.
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+int static_scratch(int device, void** ptr);
+
 }  // namespace ugks

@@ -6,6 +6,9 @@
 // Velocity reductions are wavefront shuffles accumulated in double.
 #include "ugks_kernels.h"
 
+#include <mutex>
+#include <vector>
+
 namespace ugks {
 
 // ------------------------------------------------------------------------
@@ -2412,6 +2415,40 @@ void launch_wall_loads_adj(const Dev& g, int nside, const int* wptr, const doubl
 void launch_param_bars(int nblock, const int* bface, const int* wptr, const double* wtab, const double* face_bar,
                        double* U_bar, double* rtw_bar, hipStream_t st) {
   k_param_bars<<<nblock, 256, 0, st>>>(nblock, bface, wptr, wtab, face_bar, U_bar, rtw_bar);
+}
+
+}  // namespace ugks
+
+// ------------------------------------------------------------------------
+// scratch of the entry points that allocate nothing: one file-scope device
+// array, each device holding its own copy (at its own address) while the
+// process lives.  Its host-side name is not a device address: the address
+// is looked up once per device, with that device current, and cached.
+// ------------------------------------------------------------------------
+namespace {
+static __device__ __align__(256) char scratch[ugks::kStaticScratchBytes];
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device
+}  // namespace
+
+namespace ugks {
+
+int static_scratch(int device, void** ptr) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0) return -1;
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return -1;
+    if (cur != device && hipSetDevice(device) != hipSuccess) return -1;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) return -1;
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return 0;
 }
 
 }  // namespace ugks

@@ -88,6 +88,7 @@ def lib():
         L.ugks_wall_loads_adjoint.argtypes = [vp, vp, vp, vp, vp]
         L.ugks_param_bars.argtypes = [vp, vp, vp, vp, vp]
         L.ugks_newton_euler.argtypes = [vp, i32, C.POINTER(d), d, vp, C.POINTER(d), vp]
+        L.ugks_flux_noalloc.argtypes = [vp, d, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -102,7 +103,7 @@ def exported_symbols():
             "ugks_flux_adjoint", "ugks_step_adjoint", "ugks_begin_step_adjoint",
             "ugks_workspace_size", "ugks_create_with_workspace", "ugks_status", "ugks_set_checks",
             "ugks_wall_loads", "ugks_wall_loads_adjoint", "ugks_param_bars", "ugks_newton_euler",
-            "ugks_last_error"]
+            "ugks_flux_noalloc", "ugks_last_error"]
 
 
 def _check(rc):
