@@ -35,14 +35,84 @@ enum : int {
   R_RT = 32,   // 1/(2 lam)
   R_SQX, R_SQY,  // R_SH * q
   R_SX, R_SY,  // moment shift of the face (mean velocity of its two sides)
-  NREC = 40
+  // 2D: the interface distribution as polynomials in c = v - U (below)
+  R_PH = 40,   // cubic Q_h: c00 c01 c02 c03 c10 c11 c12 c20 c21 c30 (10)
+  R_LB = 50,   // linear part of Q_b: l0 lx ly (3)
+  R_KB = 53,   // Q_b = R_KB Q_h + L_b
+  NREC = 56
 };
 
-// derived fields of a face record used per velocity
-__device__ __forceinline__ void record_derived(double* r) {
+// cubic polynomials in two variables: c[i][j] multiplies X^i Y^j, i + j <= 3
+struct Poly3 {
+  double c[4][4];
+};
+__device__ inline Poly3 poly_lin(double a0, double ax, double ay) {
+  Poly3 p = {};
+  p.c[0][0] = a0; p.c[1][0] = ax; p.c[0][1] = ay;
+  return p;
+}
+__device__ inline Poly3 poly_axpy(double s, const Poly3& a, const Poly3& b) {  // s a + b
+  Poly3 p;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) p.c[i][j] = s * a.c[i][j] + b.c[i][j];
+  return p;
+}
+__device__ inline Poly3 poly_mul(const Poly3& a, const Poly3& b) {  // degrees add up to at most 3 here
+  Poly3 p = {};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; i + j < 4; ++j)
+      for (int k = 0; i + k < 4; ++k)
+        for (int l = 0; j + l < 4 && i + k + j + l < 4; ++l) p.c[i + k][j + l] += a.c[i][j] * b.c[k][l];
+  return p;
+}
+
+// derived fields of a face record used per velocity.  In 2D the interface
+// distribution of Eq. fullSolution integrated over dt_s (face state U, lam,
+// q; slopes a_x, a_y; time coefficient A; integrals q1..q5; face grid
+// velocity Uf, w = v - Uf) is
+//   I_h = q1 f_h + q2 w.grad f_h + exp(-lam |c|^2) Q_h(c),
+//   I_b = q1 f_b + q2 w.grad f_b + exp(-lam |c|^2) (K_b Q_h(c) + L_b(c)),
+// c = v - U: the Maxwellian's prefactor, the Shakhov factor, (w.a) and A.psi
+// collected into one cubic Q_h and a linear L_b, once per face instead of
+// once per velocity
+__device__ inline void record_derived(double* r, int dim, int nxi, double ufx, double ufy) {
   r[R_RT] = 0.5 / r[R_LAM];
   r[R_SQX] = r[R_SH] * r[R_QX];
   r[R_SQY] = r[R_SH] * r[R_QY];
+  if (dim != 2) return;
+  const double lam = r[R_LAM], rt = r[R_RT], hn = r[R_HN], ux = r[R_UX], uy = r[R_UY];
+  const double sqx = r[R_SQX], sqy = r[R_SQY];
+  const double* ax = r + R_AX;
+  const double* ay = r + R_AY;
+  const double* at = r + R_AT;
+  const double* t = r + R_T1;
+  const double dx = ux - ufx, dy = uy - ufy;  // w = c + (U - Uf)
+  const Poly3 X = poly_lin(0.0, 1.0, 0.0), Y = poly_lin(0.0, 0.0, 1.0);
+  const Poly3 one = poly_lin(1.0, 0.0, 0.0);
+  const Poly3 s = poly_lin(0.0, sqx, sqy);                                   // c.(Shakhov q)
+  const Poly3 c2 = poly_axpy(1.0, poly_mul(X, X), poly_mul(Y, Y));
+  // 1 + s (2 lam |c|^2 - 2 - D): Maxwellian plus its Shakhov part for h
+  const Poly3 shk = poly_axpy(1.0, one, poly_mul(s, poly_axpy(2.0 * lam, c2, poly_lin(-2.0 - dim, 0.0, 0.0))));
+  // energy factor of (a.psi) for h: (|v|^2 + nxi rt) / 2
+  const Poly3 vx = poly_lin(ux, 1.0, 0.0), vy = poly_lin(uy, 0.0, 1.0);
+  const Poly3 eh = poly_axpy(0.5, poly_axpy(1.0, poly_mul(vx, vx), poly_mul(vy, vy)),
+                             poly_lin(0.5 * nxi * rt, 0.0, 0.0));
+  const Poly3 pax = poly_lin(ax[0] + ax[1] * ux + ax[2] * uy, ax[1], ax[2]);
+  const Poly3 pay = poly_lin(ay[0] + ay[1] * ux + ay[2] * uy, ay[1], ay[2]);
+  const Poly3 pat = poly_lin(at[0] + at[1] * ux + at[2] * uy, at[1], at[2]);
+  const Poly3 wx = poly_lin(dx, 1.0, 0.0), wy = poly_lin(dy, 0.0, 1.0);
+  const Poly3 wah = poly_axpy(1.0, poly_mul(wx, poly_axpy(ax[3], eh, pax)), poly_mul(wy, poly_axpy(ay[3], eh, pay)));
+  const Poly3 ath = poly_axpy(at[3], eh, pat);
+  const Poly3 ph = poly_axpy(t[2], shk, poly_axpy(t[3], wah, poly_axpy(t[4], ath, Poly3{})));
+  const double q[10] = {ph.c[0][0], ph.c[0][1], ph.c[0][2], ph.c[0][3], ph.c[1][0],
+                        ph.c[1][1], ph.c[1][2], ph.c[2][0], ph.c[2][1], ph.c[3][0]};
+  for (int m = 0; m < 10; ++m) r[R_PH + m] = hn * q[m];
+  // Q_b = nxi rt hn (P_h + 2 q3 s + rt (q4 (w_x a_x3 + w_y a_y3) + q5 A_3))
+  const double kb = nxi * rt, hb = hn * kb;
+  r[R_KB] = kb;
+  r[R_LB] = hb * rt * (t[3] * (ax[3] * dx + ay[3] * dy) + t[4] * at[3]);
+  r[R_LB + 1] = hb * (2.0 * t[2] * sqx + rt * t[3] * ax[3]);
+  r[R_LB + 2] = hb * (2.0 * t[2] * sqy + rt * t[3] * ay[3]);
 }
 
 // packed per-cell table of the march kernels (one double per entry; kinds
@@ -314,8 +384,11 @@ __device__ __forceinline__ void lds_barrier() {
 template <int CTRL>
 __device__ __forceinline__ double dpp_perm(double v) {
   int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  // every control used here (quad permutes, row mirrors) reads a lane of
+  // the same row, so no lane keeps an old value: the plain DPP move needs
+  // no zeroed destination
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
 

@@ -68,6 +68,23 @@ __device__ inline void interface_avg(const FaceEq<C>& e, int dim, int nxi, C vx,
   Ib = e.t[0] * fb + e.t[1] * (wx * gbx + wy * gby) + e.t[2] * (B + Bp) + e.t[3] * wab * B + e.t[4] * atb * B;
 }
 
+// 2D form of interface_avg from the per-face polynomials of the record
+// (record_derived): c = v - U, w = v - Uf
+template <class C>
+__device__ __forceinline__ void interface_poly(const double* r, C cx, C cy, C wx, C wy, C fh, C fb, C ghx, C ghy,
+                                               C gbx, C gby, C& Ih, C& Ib) {
+  const C E = expo<C>(-(C)r[R_LAM] * (cx * cx + cy * cy));
+  const double* p = r + R_PH;
+  const C p0 = (C)p[0] + cy * ((C)p[1] + cy * ((C)p[2] + cy * (C)p[3]));
+  const C p1 = (C)p[4] + cy * ((C)p[5] + cy * (C)p[6]);
+  const C p2 = (C)p[7] + cy * (C)p[8];
+  const C Qh = p0 + cx * (p1 + cx * (p2 + cx * (C)p[9]));
+  const C Qb = (C)r[R_KB] * Qh + ((C)r[R_LB] + cx * (C)r[R_LB + 1] + cy * (C)r[R_LB + 2]);
+  const C t0 = (C)r[R_T1], t1 = (C)r[R_T1 + 1];
+  Ih = t0 * fh + t1 * (wx * ghx + wy * ghy) + E * Qh;
+  Ib = t0 * fb + t1 * (wx * gbx + wy * gby) + E * Qb;
+}
+
 // ------------------------------------------------------------------------
 // cell gradients of W (limited, physical): gW[cell][2][nw]
 // ------------------------------------------------------------------------
@@ -154,7 +171,7 @@ __global__ void k_wallprep(Dev g, double dts, const double* __restrict__ W, cons
   time_integrals(dts, inv_tau_of(g, rho, lam), tq);
   for (int m = 0; m < 5; ++m) r[R_T1 + m] = tq[m] / dts;
   r[R_ACT] = 1.0;
-  record_derived(r);
+  record_derived(r, g.dim, g.nxi, fg[3], fg[4]);
   r[R_LAMW] = 0.5 / fg[7];
   r[R_HWN] = pow(r[R_LAMW] / kPi, 0.5 * g.dim);
   r[R_VWX] = fg[5];
@@ -372,7 +389,7 @@ __global__ __launch_bounds__(256) void k_face_eq(Dev g, double dts, const T* __r
     time_integrals(dts, inv_tau_of(g, rho, lam), tq);
     for (int m = 0; m < 5; ++m) r[R_T1 + m] = tq[m] / dts;
     r[R_ACT] = 1.0;
-    record_derived(r);
+    record_derived(r, g.dim, g.nxi, ufx, ufy);
   }
 }
 
@@ -531,15 +548,35 @@ __device__ __forceinline__ C cfetch(const T* __restrict__ f, const T* __restrict
   return self;
 }
 
+// reciprocal of a nonzero value of normal range: the hardware estimate, in
+// double refined by two Newton steps (relative error near 1 ulp)
+template <class C>
+__device__ __forceinline__ C recip_nr(C d);
+template <>
+__device__ __forceinline__ double recip_nr<double>(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
+template <>
+__device__ __forceinline__ float recip_nr<float>(float d) { return __builtin_amdgcn_rcpf(d); }
+
+// van Leer slope (s1 |s2| + |s1| s2) / (|s1| + |s2|), which is
+// 2 s1 s2 / (s1 + s2) where the one-sided slopes agree in sign and 0 where
+// they do not; slopes whose sum is below the normal range (f in the far
+// tails) also give 0, so the reciprocal never overflows
 template <class C>
 __device__ __forceinline__ C climit(int lo, int hi, C vlo, C v0, C vhi) {
   if (lo == kNbMiss || hi == kNbMiss) return C(0);
   if (lo == kNbWall && hi == kNbWall) return C(0);
   if (lo == kNbWall) return vhi - v0;
   if (hi == kNbWall) return v0 - vlo;
-  C s1 = v0 - vlo, s2 = vhi - v0;
-  C vl = (s1 * fabs(s2) + fabs(s1) * s2) / (fabs(s1) + fabs(s2));
-  return (s1 * s2 <= C(0)) ? C(0) : vl;
+  const C s1 = v0 - vlo, s2 = vhi - v0;
+  const C sum = s1 + s2;
+  const C tiny = (sizeof(C) == 8) ? C(1e-300) : C(1e-36);
+  const C vl = C(2) * s1 * s2 * recip_nr<C>(sum);
+  return (s1 * s2 <= C(0) || !(fabs(sum) >= tiny)) ? C(0) : vl;
 }
 
 // value and physical gradient of one component at cell c (codes nbc)
@@ -590,11 +627,16 @@ __device__ __forceinline__ double rec_at(double v, int l) { return lane_read(v, 
 __device__ __forceinline__ int rec_int(double v, int l) { return __builtin_amdgcn_readlane(__double2loint(v), l); }
 
 // scalar-cache prefetch of the records of two faces: one word of each
-// 64-byte line of the face record (NREC doubles, 64-byte aligned) and of its
+// 64-byte line of the face record (NREC doubles, 64-byte aligned) that the
+// march reads per velocity (lines 0, 2-6: state, time integrals, wall
+// fields, moment shift, interface polynomials; line 1 holds the slope and
+// time coefficients, which enter only through the polynomials) and of its
 // packed geometry (kFpN doubles, 32-byte aligned: two lines).  The words are
 // only kept alive (sgpr_keep) so that the loads are issued; a missing face
 // (-1) touches face 0.
-constexpr int kTouch = 7;
+constexpr int kRecLines = 6;
+constexpr int kRecLine[kRecLines] = {0, 2, 3, 4, 5, 6};
+constexpr int kTouch = kRecLines + 2;
 __device__ __forceinline__ void face_touch(const double* __restrict__ rec, const double* __restrict__ fpl,
                                            int f0, int f1, int (&t)[2 * kTouch]) {
 #pragma unroll
@@ -604,16 +646,18 @@ __device__ __forceinline__ void face_touch(const double* __restrict__ rec, const
     const int* rr = (const int*)(rec + (size_t)fs * NREC);
     const int* pp = (const int*)(fpl + (size_t)fs * kFpN);
 #pragma unroll
-    for (int m = 0; m < 5; ++m) t[kTouch * q + m] = rr[16 * m];
-    t[kTouch * q + 5] = pp[0];
-    t[kTouch * q + 6] = pp[2 * kFpN - 1];
+    for (int m = 0; m < kRecLines; ++m) t[kTouch * q + m] = rr[16 * kRecLine[m]];
+    t[kTouch * q + kRecLines] = pp[0];
+    t[kTouch * q + kRecLines + 1] = pp[2 * kFpN - 1];
   }
 }
 __device__ __forceinline__ void sgpr_keep(const int (&t)[2 * kTouch]) {
   asm volatile("" ::"s"(t[0]), "s"(t[1]), "s"(t[2]), "s"(t[3]), "s"(t[4]), "s"(t[5]), "s"(t[6]), "s"(t[7]),
-               "s"(t[8]), "s"(t[9]), "s"(t[10]), "s"(t[11]), "s"(t[12]), "s"(t[13]));
+               "s"(t[8]), "s"(t[9]), "s"(t[10]), "s"(t[11]), "s"(t[12]), "s"(t[13]), "s"(t[14]), "s"(t[15]));
 }
-static_assert(NREC * 8 == 5 * 64 && kFpN * 8 <= 96, "face_touch covers the record in 5 lines, geometry in 2");
+static_assert(NREC * 8 == 7 * 64 && R_PH / 8 == 5 && (R_KB + 1) <= 56 && R_SX / 8 == 4 && R_T1 / 8 == 2 &&
+                  R_SGN / 8 == 3 && R_RHOW / 8 == 3 && kFpN * 8 <= 96,
+              "face_touch covers the record lines read per velocity, geometry in 2");
 
 template <int RG, class T, class C, int MODE>
 __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __restrict__ binfo, int nchunk,
@@ -769,12 +813,11 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
       mom[5] = wh * cx * cy; mom[6] = wh * cy * cy; mom[7] = we * cx; mom[8] = we * cy;
       return;
     }
-    FaceEq<C> e;
-    e.load(r);
     const bool up_low = wn > 0.0;
     const Side<C>& u = up_low ? sl : sh;
     C Ih, Ib;
-    interface_avg<C>(e, 2, 1, (C)vx, (C)vy, (C)(vx - ux), (C)(vy - uy), u.hv, u.bv, u.hx, u.hy, u.bx, u.by, Ih, Ib);
+    interface_poly<C>(r, (C)(vx - r[R_UX]), (C)(vy - r[R_UY]), (C)(vx - ux), (C)(vy - uy), u.hv, u.bv, u.hx, u.hy,
+                      u.bx, u.by, Ih, Ib);
     double fh = (wn != 0.0) ? wn * (double)Ih : 0.0;
     double fb = (wn != 0.0) ? wn * (double)Ib : 0.0;
     fh = kin ? fh : 0.0;
@@ -792,11 +835,9 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     const double fg[5] = {fp[kFpN0], fp[kFpN0 + 1], fp[kFpS], fp[kFpU], fp[kFpU + 1]};
     const double wn = exact_wn(vx, vy, fg[3], fg[4], sg * fg[0], sg * fg[1]);
     const Side<C> S = side_at(L, low ? fp[kFpDL] : fp[kFpDR], low ? fp[kFpDL + 1] : fp[kFpDR + 1]);
-    FaceEq<C> e;
-    e.load(r);
     C Ih, Ib;
-    interface_avg<C>(e, 2, 1, (C)vx, (C)vy, (C)(vx - fg[3]), (C)(vy - fg[4]), S.hv, S.bv, S.hx, S.hy, S.bx, S.by,
-                     Ih, Ib);
+    interface_poly<C>(r, (C)(vx - r[R_UX]), (C)(vy - r[R_UY]), (C)(vx - fg[3]), (C)(vy - fg[4]), S.hv, S.bv, S.hx,
+                      S.hy, S.bx, S.by, Ih, Ib);
     if (MODE == 0) {
       const double cx = vx - r[R_VWX], cy = vy - r[R_VWY];
       const double hw = r[R_HWN] * exp(-r[R_LAMW] * (cx * cx + cy * cy));
@@ -1041,7 +1082,7 @@ __global__ void k_face_fin(Dev g, double dts, int nchunk, const double* __restri
   time_integrals(dts, inv_tau_of(g, rho, lam), tq);
   for (int q = 0; q < 5; ++q) r[R_T1 + q] = tq[q] / dts;
   r[R_ACT] = 1.0;
-  record_derived(r);
+  record_derived(r, 2, g.nxi, fg[3], fg[4]);
 }
 
 // macro flux per face (and the wall output) from the chunk partials
