@@ -201,13 +201,20 @@ def time_batch(count, prec_name, iters):
         s.autotune(dt, 1, h, b, W, Wn, q, Sh, Sb, Fn)
         dts.append(dt)
         states.append([h, b, W, Wn, q, Sh, Sb, Fn])
-    batch = ugks.Batch(solvers)
-    batch.step(dts, iters, states)  # capture, warm
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.step(dts, iters, states)
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / iters
+    def timed(mode):
+        batch = ugks.Batch(solvers, mode=mode)
+        batch.step(dts, iters, states)  # capture, warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.step(dts, iters, states)
+        torch.cuda.synchronize()
+        out = 1e3 * (time.perf_counter() - t0) / iters
+        batch.close()
+        return out
+    # one launch per stage (persistent march and micro grids), then the
+    # cases' own chains on concurrent branches
+    ms = timed(1)
+    ms_branches = timed(0)
     for s, st, dt in zip(solvers, states, dts):
         s.step_graph(dt, iters, *st)
     torch.cuda.synchronize()
@@ -217,13 +224,14 @@ def time_batch(count, prec_name, iters):
     torch.cuda.synchronize()
     ms_seq = 1e3 * (time.perf_counter() - t0) / iters
     pairs = sum(int((s.types() == 1).sum()) * s.nv for s in solvers)
-    batch.close()
     for s in solvers:
         s.close()
     del states
     torch.cuda.empty_cache()
     return {"prec": prec_name, "cases": count, "pairs": pairs, "pseudo_steps": iters,
             "ms_per_pseudo_step": round(ms, 4), "value": pairs / (ms * 1e-3),
+            "launch": "one launch per stage (persistent march and micro-sweep grids over work items)",
+            "branches_ms_per_pseudo_step": round(ms_branches, 4),
             "sequential_ms_per_pseudo_step": round(ms_seq, 4)}
 
 

@@ -301,18 +301,33 @@ int ugks_step_graph(ugks_ctx* ctx, double dt, int32_t n_inner, void* h, void* b,
 
 /*
  * Batches of independent cases (ragged sizes, one context each, all on one
- * device): ugks_batch_step runs n_inner pseudo-iterations of every case
- * from one graph whose branches (up to four, round robin over the cases)
- * run concurrently, launched on `stream`.  Array arguments are host arrays
- * of ncase device pointers in case order (resid may be NULL, or hold NULL
- * entries).  Cached like ugks_step_graph; results are identical to ugks_step
- * per case.  The batch keeps the context pointers: destroy it before them.
+ * device): ugks_batch_step runs n_inner pseudo-iterations (Sec. 2.2,
+ * Steps 3-7) of every case from one captured graph launched on `stream`.
+ * Array arguments are host arrays of ncase device pointers in case order
+ * (resid may be NULL, or hold NULL entries).  Cached like ugks_step_graph
+ * (the first call after a change of the arguments, the cases' geometry or
+ * donor tables waits for the device and rebuilds the graph); results are
+ * identical to ugks_step per case, bit for bit.  The batch keeps the
+ * context pointers: destroy it before them.
+ *
+ * Mode 1 (the default where it applies: 2D cases of one storage type): one
+ * launch per stage of the pseudo-iteration for all cases; the per-cell and
+ * per-face stages run one grid over every case's cells or faces, and the
+ * two march passes and the micro LU-SGS sweep run persistent grids that
+ * stride over (case, velocity chunk, row group or block) work items, the
+ * costliest first.  Mode 0: each case's own kernel chain, the chains on up
+ * to four concurrent branches (round robin over the cases).
+ * ugks_batch_set_mode returns UGKS_E_UNSUPPORTED for mode 1 on other
+ * batches, UGKS_E_ARG for another mode; ugks_batch_get_mode gives the mode
+ * in effect.
  */
 typedef struct ugks_batch ugks_batch;
 int ugks_batch_create(int32_t ncase, ugks_ctx* const* ctxs, ugks_batch** out);
 int ugks_batch_step(ugks_batch* batch, const double* dt, int32_t n_inner, void* const* h, void* const* b,
                     double* const* W, const double* const* Wn, double* const* q, const void* const* Sh,
                     const void* const* Sb, const double* const* Fn, double* const* resid, void* stream);
+int ugks_batch_set_mode(ugks_batch* batch, int32_t mode);
+int ugks_batch_get_mode(const ugks_batch* batch, int32_t* mode);
 int ugks_batch_destroy(ugks_batch* batch);
 
 /*

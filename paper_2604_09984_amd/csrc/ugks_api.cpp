@@ -1251,7 +1251,181 @@ struct ugks_batch {
   std::vector<hipEvent_t> ev;   // fork and join events
   hipGraphExec_t gexec = nullptr;
   std::vector<uint64_t> gkey;
+  // 1: one launch per stage for all cases (BatchPlan); 0: each case's own
+  // kernel chain, the chains on concurrent branches
+  int mode = 1;
+  // mode 1: the cases in groups of like block height (one group per
+  // branch), each group one chain of batched launches with its own plan
+  std::vector<BatchPlan> plan;
+  std::vector<void*> d_plan;  // device tables of each group's plan
+  std::vector<size_t> plan_bytes;
 };
+
+namespace {
+
+// one launch per stage applies to 2D cases of one storage type
+bool batch_fusable(const ugks_batch* B) {
+  for (const ugks_ctx* c : B->ctx)
+    if (c->dim != 2 || c->prec != B->ctx[0]->prec) return false;
+  return true;
+}
+
+// builds the launch plan of a batch (case table, workgroup prefix tables,
+// work items sorted by decreasing cost) and uploads it; the caller has
+// waited for the device
+int batch_build_plan(ugks_batch* B, int grp, const std::vector<int>& members, const double* dt, void* const* h,
+                     void* const* b, double* const* W, const double* const* Wn, double* const* q,
+                     const void* const* Sh, const void* const* Sb, const double* const* Fn, double* const* resid) {
+  const int n = (int)members.size();
+  BatchPlan& P = B->plan[grp];
+  P = BatchPlan{};
+  P.ncase = n;
+  P.prec = B->ctx[0]->prec;
+  std::vector<BatchCase> cs(n);
+  std::vector<int> off[5];
+  for (auto& o : off) o.assign(n + 1, 0);
+  // the widest micro-sweep chunk that the batch's tallest block allows (the
+  // cases' own tuned chunk widths are for their own launches)
+  const int kc_max = 16;
+  for (int i = 0; i < n; ++i) {
+    const ugks_ctx* c = B->ctx[members[i]];
+    P.max_ni = std::max(P.max_ni, c->max_ni);
+    P.max_nj = std::max(P.max_nj, c->max_nj);
+    P.any_pi |= c->any_pi;
+    P.any_pj |= c->any_pj;
+  }
+  micro_shape(2, P.max_ni, P.max_nj, P.any_pj, kc_max, P.micro_kc, P.micro_rows);
+  if (P.micro_kc <= 0) return fail(UGKS_E_UNSUPPORTED, "no micro sweep shape fits the batch's largest block");
+  P.micro_nslot = P.max_nj;
+  P.micro_lds = micro_lds(2, P.max_ni, P.max_nj, P.any_pj, kc_max);
+  P.macro_nt = ((P.max_nj + 63) / 64) * 64;
+  P.macro_lds = macro_lds(P.macro_nt, P.max_ni, P.max_nj, P.any_pi, P.any_pj);
+  // march rows per workgroup: the value most of the group's pairs were
+  // tuned for (ugks_autotune on each case), per pass
+  for (int m = 0; m < 2; ++m) {
+    double votes[3] = {0, 0, 0};  // 6, 8, 10
+    for (int i = 0; i < n; ++i) {
+      const ugks_ctx* c = B->ctx[members[i]];
+      const int r = m ? c->dev.rg_flux : c->dev.rg_eq;
+      votes[(r == 6) ? 0 : (r == 10) ? 2 : 1] += (double)c->ncell * c->nv;
+    }
+    P.rg[m] = (votes[0] > votes[1] && votes[0] >= votes[2]) ? 6 : (votes[2] > votes[1]) ? 10 : 8;
+  }
+  std::vector<std::pair<long long, BatchItem>> mi[2], ui;
+  for (int i = 0; i < n; ++i) {
+    const int u = members[i];
+    ugks_ctx* c = B->ctx[u];
+    BatchCase& a = cs[i];
+    a.g = c->dev;
+    a.binfo = (const int*)c->d_binfo;
+    a.nchunk = (c->nv + 63) / 64;
+    a.nrec = c->nrec;
+    a.dt = dt[u];
+    a.dts = c->dts;
+    a.h = h[u]; a.b = b[u]; a.Dh = c->s_Dh; a.Db = c->s_Db; a.Sh = Sh[u]; a.Sb = Sb[u];
+    a.W = W[u]; a.q = q[u]; a.resid = resid ? resid[u] : nullptr; a.Wn = Wn[u]; a.Fn = Fn[u];
+    a.gW = (double*)c->s_gW; a.rec = (double*)c->s_rec; a.part = (double*)c->s_part; a.F = (double*)c->s_F;
+    a.gam = (double*)c->s_gam; a.mac = (double*)c->s_R; a.dWs = (double*)c->s_dWs; a.dW = (double*)c->s_dW;
+    a.Wp = (double*)c->s_Wp; a.rpart = (double*)c->s_rpart; a.crec = (double*)c->s_crec;
+    a.mrec = (double*)c->s_mrec;
+    a.orec = (const int*)c->d_rec; a.optr = (const int*)c->d_ptr; a.odon = (const int*)c->d_don;
+    a.ow = (const double*)c->d_w;
+    if (a.resid) P.want_resid = 1;
+    const int cnt[5] = {(c->ncell + 63) / 64, (c->nface + 63) / 64, (c->ncell + 3) / 4, (c->nrec + 3) / 4,
+                        (int)c->blk.size()};
+    for (int k = 0; k < 5; ++k) off[k][i + 1] = off[k][i] + cnt[k];
+    const int nchu = (c->nv + P.micro_kc - 1) / P.micro_kc;
+    for (int z = 0; z < (int)c->blk.size(); ++z) {
+      const Block& bl = c->blk[z];
+      for (int m = 0; m < 2; ++m)
+        for (int y = 0; y * P.rg[m] < bl.nj; ++y) {
+          const long long cost = (long long)bl.ni * std::min(P.rg[m], bl.nj - y * P.rg[m]);
+          for (int x = 0; x < a.nchunk; ++x) mi[m].push_back({cost, BatchItem{i, x, y, z}});
+        }
+      const long long ucost = (long long)(bl.ni + bl.nj) * 1024 + bl.nj;
+      for (int x = 0; x < nchu; ++x) ui.push_back({ucost, BatchItem{i, x, z, 0}});
+    }
+  }
+  auto by_cost = [](const std::pair<long long, BatchItem>& l, const std::pair<long long, BatchItem>& r) {
+    return l.first > r.first;
+  };
+  for (auto& v : mi) std::stable_sort(v.begin(), v.end(), by_cost);
+  std::stable_sort(ui.begin(), ui.end(), by_cost);
+  P.n_cell64 = off[0][n]; P.n_face64 = off[1][n]; P.n_cell4 = off[2][n]; P.n_rec4 = off[3][n];
+  P.n_block = off[4][n];
+  P.n_micro = (int)ui.size();
+  for (int m = 0; m < 2; ++m) {
+    P.n_march[m] = (int)mi[m].size();
+    if (batch_march_grid(P.prec, P.rg[m], m, P.grid_march[m])) return fail(UGKS_E_DEVICE, "occupancy query failed");
+    P.grid_march[m] = std::min(P.grid_march[m], std::max(P.n_march[m], 1));
+  }
+  if (batch_micro_grid(P.micro_lds, P.grid_micro)) return fail(UGKS_E_DEVICE, "occupancy query failed");
+  P.grid_micro = std::min(P.grid_micro, std::max(P.n_micro, 1));
+  // one device block: cases, five prefix tables, the items of both march
+  // passes and of the micro sweep
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t s_cs = al(sizeof(BatchCase) * n), s_off = al(sizeof(int) * (n + 1));
+  const size_t s_it[3] = {al(sizeof(BatchItem) * std::max<size_t>(mi[0].size(), 1)),
+                          al(sizeof(BatchItem) * std::max<size_t>(mi[1].size(), 1)),
+                          al(sizeof(BatchItem) * std::max<size_t>(ui.size(), 1))};
+  const size_t total = s_cs + 5 * s_off + s_it[0] + s_it[1] + s_it[2];
+  if (total > B->plan_bytes[grp]) {
+    if (B->d_plan[grp]) (void)hipFree(B->d_plan[grp]);
+    B->d_plan[grp] = nullptr;
+    B->plan_bytes[grp] = 0;
+    if (hipMalloc(&B->d_plan[grp], total) != hipSuccess)
+      return fail(UGKS_E_DEVICE, "hipMalloc of the batch plan failed");
+    B->plan_bytes[grp] = total;
+  }
+  std::vector<char> host(total, 0);
+  char* base = (char*)B->d_plan[grp];
+  std::memcpy(host.data(), cs.data(), sizeof(BatchCase) * n);
+  const int** offp[5] = {&P.off_cell64, &P.off_face64, &P.off_cell4, &P.off_rec4, &P.off_block};
+  for (int k = 0; k < 5; ++k) {
+    std::memcpy(host.data() + s_cs + k * s_off, off[k].data(), sizeof(int) * (n + 1));
+    *offp[k] = (const int*)(base + s_cs + k * s_off);
+  }
+  size_t o = s_cs + 5 * s_off;
+  const std::vector<std::pair<long long, BatchItem>>* lists[3] = {&mi[0], &mi[1], &ui};
+  const BatchItem** dst[3] = {&P.march_items[0], &P.march_items[1], &P.micro_items};
+  for (int k = 0; k < 3; ++k) {
+    for (size_t e = 0; e < lists[k]->size(); ++e)
+      std::memcpy(host.data() + o + e * sizeof(BatchItem), &(*lists[k])[e].second, sizeof(BatchItem));
+    *dst[k] = (const BatchItem*)(base + o);
+    o += s_it[k];
+  }
+  P.cases = (const BatchCase*)base;
+  if (hipMemcpy(B->d_plan[grp], host.data(), total, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(UGKS_E_DEVICE, "upload of the batch plan failed");
+  return UGKS_OK;
+}
+
+// groups of the batch (one per branch): the cases ordered by tallest block,
+// then velocity count, cut into runs of about equal (cell, velocity) pairs,
+// so that each group's common launch shapes fit its cases closely
+std::vector<std::vector<int>> batch_groups(const ugks_batch* B, int ngroup) {
+  const int n = (int)B->ctx.size();
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const ugks_ctx *a = B->ctx[x], *b = B->ctx[y];
+    return a->max_nj != b->max_nj ? a->max_nj < b->max_nj : a->nv < b->nv;
+  });
+  double total = 0.0;
+  for (const ugks_ctx* c : B->ctx) total += (double)c->ncell * c->nv;
+  std::vector<std::vector<int>> g(1);
+  double acc = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const ugks_ctx* c = B->ctx[order[k]];
+    if (!g.back().empty() && (int)g.size() < ngroup && acc >= total * (double)g.size() / ngroup)
+      g.emplace_back();
+    g.back().push_back(order[k]);
+    acc += (double)c->ncell * c->nv;
+  }
+  return g;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1304,6 +1478,7 @@ int ugks_batch_destroy(ugks_batch* B) {
   if (!B) return UGKS_OK;
   (void)hipDeviceSynchronize();
   if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+  for (void* p : B->d_plan) if (p) (void)hipFree(p);
   for (auto s : B->st) if (s) (void)hipStreamDestroy(s);
   for (auto e : B->ev) if (e) (void)hipEventDestroy(e);
   delete B;
@@ -1324,6 +1499,40 @@ int ugks_batch_step(ugks_batch* B, const double* dt, int32_t n_inner, void* cons
     if (!(dt[i] > 0) || !std::isfinite(dt[i])) return fail(UGKS_E_ARG, "dt must be positive");
     auto k = step_key(c, dt[i], n_inner, {h[i], b[i], W[i], Wn[i], q[i], Sh[i], Sb[i], Fn[i], r});
     key.insert(key.end(), k.begin(), k.end());
+  }
+  const bool fused = B->mode == 1 && batch_fusable(B);
+  key.push_back(fused ? 1 : 0);
+  if ((!B->gexec || key != B->gkey) && fused) {
+    // one launch per stage for all cases: the plan's tables are rewritten,
+    // so no earlier replay may still read them
+    HIPCHK(hipDeviceSynchronize());
+    const auto groups = batch_groups(B, (int)B->st.size());
+    const int ng = (int)groups.size();
+    B->plan.resize(ng);
+    B->d_plan.resize(ng, nullptr);
+    B->plan_bytes.resize(ng, 0);
+    for (int k = 0; k < ng; ++k)
+      if (int rc = batch_build_plan(B, k, groups[k], dt, h, b, W, Wn, q, Sh, Sb, Fn, resid)) {
+        B->gkey.clear();
+        return rc;
+      }
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(B->st[0], hipStreamCaptureModeThreadLocal));
+    int rc = UGKS_OK;
+    if (hipEventRecord(B->ev[0], B->st[0]) != hipSuccess) rc = fail(UGKS_E_DEVICE, "fork");
+    for (int k = 1; k < ng && !rc; ++k)
+      if (hipStreamWaitEvent(B->st[k], B->ev[0], 0) != hipSuccess) rc = fail(UGKS_E_DEVICE, "fork");
+    for (int k = 0; k < ng && !rc; ++k) launch_batch_inner(B->plan[k], n_inner, B->st[k]);
+    if (!rc && hipGetLastError() != hipSuccess) rc = fail(UGKS_E_DEVICE, "batched launch failed");
+    for (int k = 1; k < ng && !rc; ++k)
+      if (hipEventRecord(B->ev[k], B->st[k]) != hipSuccess || hipStreamWaitEvent(B->st[0], B->ev[k], 0) != hipSuccess)
+        rc = fail(UGKS_E_DEVICE, "join");
+    hipError_t e = hipStreamEndCapture(B->st[0], &graph);
+    if (!rc && e != hipSuccess) rc = fail(UGKS_E_DEVICE, "stream capture failed");
+    if (!rc) rc = graph_to_exec(graph, &B->gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) { B->gkey.clear(); return rc; }
+    B->gkey = key;
   }
   if (!B->gexec || key != B->gkey) {
     // one graph: the cases on parallel branches (round robin over the
@@ -1350,6 +1559,23 @@ int ugks_batch_step(ugks_batch* B, const double* dt, int32_t n_inner, void* cons
     B->gkey = key;
   }
   HIPCHK(hipGraphLaunch(B->gexec, (hipStream_t)stream));
+  return UGKS_OK;
+}
+
+int ugks_batch_set_mode(ugks_batch* B, int32_t mode) {
+  if (!B || (mode != 0 && mode != 1)) return fail(UGKS_E_ARG, "mode must be 0 or 1");
+  if (mode == 1 && !batch_fusable(B))
+    return fail(UGKS_E_UNSUPPORTED, "one launch per stage needs 2D cases of one storage type");
+  if (B->mode != mode) {
+    B->mode = mode;
+    B->gkey.clear();
+  }
+  return UGKS_OK;
+}
+
+int ugks_batch_get_mode(const ugks_batch* B, int32_t* mode) {
+  if (!B || !mode) return fail(UGKS_E_ARG, "null argument");
+  *mode = (B->mode == 1 && batch_fusable(B)) ? 1 : 0;
   return UGKS_OK;
 }
 

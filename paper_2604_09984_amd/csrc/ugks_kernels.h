@@ -39,6 +39,59 @@ void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_
                   const double* crec, void* h, void* b, const void* Sh, const void* Sb, void* Dh, void* Db,
                   hipStream_t st, hipEvent_t* ev = nullptr);
 
+// ---------------------------------------------------------------------------
+// Batched pseudo-iteration: many cases advanced by one launch per stage.
+// Each case's arguments live in a device table; the per-cell and per-face
+// stages run one flat grid whose workgroups find their case in a prefix
+// table of per-case workgroup counts; the march passes and the micro sweep
+// are persistent grids striding over (case, velocity chunk, row group,
+// block) work items, ordered by decreasing cost.  Every work item runs the
+// same code as the case's own launch, so each case's results are those of
+// its own pseudo-iteration, bit for bit.
+struct BatchCase {
+  Dev g;
+  const int* binfo;
+  int nchunk, nrec;
+  double dt, dts;
+  void *h, *b, *Dh, *Db;
+  const void *Sh, *Sb;
+  double *W, *q, *resid;
+  const double *Wn, *Fn;
+  double *gW, *rec, *part, *F, *gam, *mac, *dWs, *dW, *Wp, *rpart, *crec, *mrec;
+  const int *orec, *optr, *odon;
+  const double* ow;
+};
+struct BatchItem {
+  int cs, x, y, z;  // case; chunk; row group (march) or block (micro); block (march)
+};
+struct BatchPlan {
+  int ncase = 0, prec = 0;
+  const BatchCase* cases = nullptr;  // device [ncase]
+  // device prefix tables [ncase + 1] of per-case workgroup counts and their
+  // totals: 64-thread workgroups over cells and faces, 4 cells or receptors
+  // per 256-thread workgroup, one per block, one per case
+  const int *off_cell64 = nullptr, *off_face64 = nullptr, *off_cell4 = nullptr, *off_rec4 = nullptr,
+            *off_block = nullptr;
+  int n_cell64 = 0, n_face64 = 0, n_cell4 = 0, n_rec4 = 0, n_block = 0;
+  // work items of the face-moment [0] and flux [1] march passes (rg[m] core
+  // rows per workgroup) and of the micro sweep (device)
+  const BatchItem* march_items[2] = {nullptr, nullptr};
+  const BatchItem* micro_items = nullptr;
+  int n_march[2] = {0, 0}, grid_march[2] = {0, 0}, rg[2] = {8, 8};
+  int n_micro = 0, grid_micro = 0;
+  // launch shapes common to the batch
+  int micro_kc = 0, micro_rows = 1, micro_nslot = 0, macro_nt = 64;
+  size_t micro_lds = 0, macro_lds = 0;
+  int max_ni = 0, max_nj = 0, any_pi = 0, any_pj = 0;
+  int want_resid = 0;
+};
+// persistent grid sizes (host): of a march pass (mode 0 face moments, 1
+// flux) with rg core rows per workgroup, and of the micro sweep with its LDS
+int batch_march_grid(int prec, int rg, int mode, int& grid);
+int batch_micro_grid(size_t micro_lds, int& grid);
+// the pseudo-iterations of a batch (2D, one storage type) on stream st
+void launch_batch_inner(const BatchPlan& p, int n_inner, hipStream_t st);
+
 // fills n doubles with v (a kernel, so that captured graphs hold no memset)
 void launch_fill(double* a, size_t n, double v, hipStream_t st);
 // wall loads from a face macro flux F: face_out [nface][dim+3] (zero off the

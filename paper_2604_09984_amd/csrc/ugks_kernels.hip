@@ -68,13 +68,20 @@ __device__ inline void interface_avg(const FaceEq<C>& e, int dim, int nxi, C vx,
   Ib = e.t[0] * fb + e.t[1] * (wx * gbx + wy * gby) + e.t[2] * (B + Bp) + e.t[3] * wab * B + e.t[4] * atb * B;
 }
 
+// read-only tables of a launch (face records, packed face geometry, block
+// table) addressed in the constant address space: wave-uniform entries are
+// scalar loads wherever the table pointer comes from (a kernel argument or
+// the case table of a batched launch)
+typedef const double __attribute__((address_space(4))) cdouble;
+typedef const int __attribute__((address_space(4))) cint;
+
 // 2D form of interface_avg from the per-face polynomials of the record
 // (record_derived): c = v - U, w = v - Uf
-template <class C>
-__device__ __forceinline__ void interface_poly(const double* r, C cx, C cy, C wx, C wy, C fh, C fb, C ghx, C ghy,
+template <class C, class RP>
+__device__ __forceinline__ void interface_poly(RP r, C cx, C cy, C wx, C wy, C fh, C fb, C ghx, C ghy,
                                                C gbx, C gby, C& Ih, C& Ib) {
   const C E = expo<C>(-(C)r[R_LAM] * (cx * cx + cy * cy));
-  const double* p = r + R_PH;
+  const auto p = r + R_PH;
   const C p0 = (C)p[0] + cy * ((C)p[1] + cy * ((C)p[2] + cy * (C)p[3]));
   const C p1 = (C)p[4] + cy * ((C)p[5] + cy * (C)p[6]);
   const C p2 = (C)p[7] + cy * (C)p[8];
@@ -88,8 +95,8 @@ __device__ __forceinline__ void interface_poly(const double* r, C cx, C cy, C wx
 // ------------------------------------------------------------------------
 // cell gradients of W (limited, physical): gW[cell][2][nw]
 // ------------------------------------------------------------------------
-__global__ void k_gradW(Dev g, const double* __restrict__ W, double* __restrict__ gW) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gradW_body(int BX, const Dev& g, const double* __restrict__ W, double* __restrict__ gW) {
+  int c = BX * blockDim.x + threadIdx.x;
   if (c >= g.ncell) return;
   double* o = gW + (size_t)c * 8;
   for (int m = 0; m < 8; ++m) o[m] = 0.0;
@@ -116,14 +123,18 @@ __global__ void k_gradW(Dev g, const double* __restrict__ W, double* __restrict_
     o[g.nw + m] = (g.dim == 2) ? G[2] * s[0] + G[3] * s[1] : 0.0;
   }
 }
+__global__ void k_gradW(Dev g, const double* __restrict__ W, double* __restrict__ gW) {
+  gradW_body(blockIdx.x, g, W, gW);
+}
 
 // ------------------------------------------------------------------------
 // wall incident state of every active wall face (one-sided data of the
 // interior cell): record fields R_RHO..R_T1, wall parameters, sign
 // ------------------------------------------------------------------------
-__global__ void k_wallprep(Dev g, double dts, const double* __restrict__ W, const double* __restrict__ q,
-                           const double* __restrict__ gW, double* __restrict__ rec) {
-  int f = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void wallprep_body(int BX, const Dev& g, double dts, const double* __restrict__ W,
+                                              const double* __restrict__ q, const double* __restrict__ gW,
+                                              double* __restrict__ rec) {
+  int f = BX * blockDim.x + threadIdx.x;
   if (f >= g.nface) return;
   int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
   double* r = rec + (size_t)f * NREC;
@@ -177,6 +188,10 @@ __global__ void k_wallprep(Dev g, double dts, const double* __restrict__ W, cons
   r[R_VWX] = fg[5];
   r[R_VWY] = fg[6];
   r[R_SGN] = (R == kNbWall) ? 1.0 : -1.0;
+}
+__global__ void k_wallprep(Dev g, double dts, const double* __restrict__ W, const double* __restrict__ q,
+                           const double* __restrict__ gW, double* __restrict__ rec) {
+  wallprep_body(blockIdx.x, g, dts, W, q, gW, rec);
 }
 
 // ------------------------------------------------------------------------
@@ -637,14 +652,14 @@ __device__ __forceinline__ int rec_int(double v, int l) { return __builtin_amdgc
 constexpr int kRecLines = 6;
 constexpr int kRecLine[kRecLines] = {0, 2, 3, 4, 5, 6};
 constexpr int kTouch = kRecLines + 2;
-__device__ __forceinline__ void face_touch(const double* __restrict__ rec, const double* __restrict__ fpl,
+__device__ __forceinline__ void face_touch(cdouble* rec, cdouble* fpl,
                                            int f0, int f1, int (&t)[2 * kTouch]) {
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int fq = __builtin_amdgcn_readfirstlane(q == 0 ? f0 : f1);
     const int fs = (fq < 0) ? 0 : fq;
-    const int* rr = (const int*)(rec + (size_t)fs * NREC);
-    const int* pp = (const int*)(fpl + (size_t)fs * kFpN);
+    cint* rr = (cint*)(rec + (size_t)fs * NREC);
+    cint* pp = (cint*)(fpl + (size_t)fs * kFpN);
 #pragma unroll
     for (int m = 0; m < kRecLines; ++m) t[kTouch * q + m] = rr[16 * kRecLine[m]];
     t[kTouch * q + kRecLines] = pp[0];
@@ -660,12 +675,10 @@ static_assert(NREC * 8 == 7 * 64 && R_PH / 8 == 5 && (R_KB + 1) <= 56 && R_SX / 
               "face_touch covers the record lines read per velocity, geometry in 2");
 
 template <int RG, class T, class C, int MODE>
-__global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __restrict__ binfo, int nchunk,
-                                                         const T* __restrict__ h, const T* __restrict__ b,
-                                                         const double* __restrict__ rec,
-                                                         const double* __restrict__ fpl,
-                                                         double* __restrict__ part, T* __restrict__ Dh,
-                                                         T* __restrict__ Db) {
+__device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g, cint* binfo, int nchunk,
+                                           const T* __restrict__ h, const T* __restrict__ b, cdouble* rec,
+                                           cdouble* fpl, double* __restrict__ part, T* __restrict__ Dh,
+                                           T* __restrict__ Db) {
   constexpr int NW = RG + 2;
   // reconstructions of three columns, raw values of one column per row for
   // the j-neighbours, j-face fluxes of two columns (flux pass).  Face records
@@ -674,13 +687,13 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   __shared__ LD6<C> lds[3][NW][64];
   __shared__ C pub[2][NW][2][64];
   __shared__ C jfl[(MODE == 1) ? 2 : 1][NW][2][64];
-  const int* bi = binfo + 8 * blockIdx.z;
+  cint* bi = binfo + 8 * BZ;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], per_i = bi[3], per_j = bi[4];
-  const int j0 = blockIdx.y * RG;
+  const int j0 = BY * RG;
   if (j0 >= nj) return;  // whole workgroup
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int chunk = blockIdx.x;
+  const int chunk = BX;
   const int k = chunk * 64 + lane;
   const bool kin = k < g.nv;
   const int kk = kin ? k : g.nv - 1;
@@ -797,7 +810,7 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   };
   // upwind interface data of a face between sides sl (low) and sh (high)
   // with normal (nx, ny) and mesh velocity (ux, uy)
-  auto face_eval = [&](const double* r, const double* fp, const Side<C>& sl, const Side<C>& sh, double* facc,
+  auto face_eval = [&](auto r, const double* fp, const Side<C>& sl, const Side<C>& sh, double* facc,
                        double* mom) -> void {
     const double nx = fp[kFpN0], ny = fp[kFpN0 + 1], ux = fp[kFpU], uy = fp[kFpU + 1];
     const double wn = exact_wn(vx, vy, ux, uy, nx, ny);
@@ -829,7 +842,7 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
   };
   // wall face seen from the interior cell c (slot s) with data L: MODE 0
   // gives the numerator and denominator of the wall density (Eq. rhow)
-  auto wall_eval = [&](const double* r, const double* fp, bool low, const LD6<C>& L, double* facc,
+  auto wall_eval = [&](auto r, const double* fp, bool low, const LD6<C>& L, double* facc,
                        double* mom) -> void {
     const double sg = r[R_SGN];
     const double fg[5] = {fp[kFpN0], fp[kFpN0 + 1], fp[kFpS], fp[kFpU], fp[kFpU + 1]};
@@ -965,7 +978,7 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
         const int f = (q == 0) ? fid[0] : fid[1];
         if (f < 0) return;
         const int fu = __builtin_amdgcn_readfirstlane(f);
-        const double* r = rec + (size_t)fu * NREC;
+        cdouble* r = rec + (size_t)fu * NREC;
         // the face geometry in one batch of scalar loads (its fields are
         // tested one after another below)
         double fp[kFpN];
@@ -1034,12 +1047,23 @@ __global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __res
     divergence(ni - 1, cpm1);
   }
 }
+template <int RG, class T, class C, int MODE>
+__global__ __launch_bounds__(64 * (RG + 2)) void k_march(Dev g, const int* __restrict__ binfo, int nchunk,
+                                                         const T* __restrict__ h, const T* __restrict__ b,
+                                                         const double* __restrict__ rec,
+                                                         const double* __restrict__ fpl,
+                                                         double* __restrict__ part, T* __restrict__ Dh,
+                                                         T* __restrict__ Db) {
+  march_body<RG, T, C, MODE>(blockIdx.x, blockIdx.y, blockIdx.z, g, (cint*)binfo, nchunk, h, b, (cdouble*)rec,
+                             (cdouble*)fpl, part, Dh, Db);
+}
 
 // face records from the chunk partials of the face moments (interior and
 // ghost faces) and the wall density (wall faces)
-__global__ void k_face_fin(Dev g, double dts, int nchunk, const double* __restrict__ part,
-                           const double* __restrict__ W, const double* __restrict__ gW, double* __restrict__ rec) {
-  int f = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void face_fin_body(int BX, const Dev& g, double dts, int nchunk,
+                                              const double* __restrict__ part, const double* __restrict__ W,
+                                              const double* __restrict__ gW, double* __restrict__ rec) {
+  int f = BX * blockDim.x + threadIdx.x;
   if (f >= g.nface || !g.fact[f]) return;
   const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
   double m[kMomP];
@@ -1084,11 +1108,16 @@ __global__ void k_face_fin(Dev g, double dts, int nchunk, const double* __restri
   r[R_ACT] = 1.0;
   record_derived(r, 2, g.nxi, fg[3], fg[4]);
 }
+__global__ void k_face_fin(Dev g, double dts, int nchunk, const double* __restrict__ part,
+                           const double* __restrict__ W, const double* __restrict__ gW, double* __restrict__ rec) {
+  face_fin_body(blockIdx.x, g, dts, nchunk, part, W, gW, rec);
+}
 
 // macro flux per face (and the wall output) from the chunk partials
-__global__ void k_flux_fin(Dev g, int nchunk, const double* __restrict__ part, const double* __restrict__ rec,
-                           double* __restrict__ F, double* __restrict__ wall) {
-  int f = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void flux_fin_body(int BX, const Dev& g, int nchunk, const double* __restrict__ part,
+                                              const double* __restrict__ rec, double* __restrict__ F,
+                                              double* __restrict__ wall) {
+  int f = BX * blockDim.x + threadIdx.x;
   if (f >= g.nface || !g.fact[f]) return;
   double m[kFluxP] = {0, 0, 0, 0};
   // chunk order kept; unrolled so that several chunks' loads are in flight
@@ -1106,6 +1135,10 @@ __global__ void k_flux_fin(Dev g, int nchunk, const double* __restrict__ part, c
     o[0] = r[R_RHOW];
     for (int q = 0; q < 4; ++q) o[1 + q] = r[R_SGN] * m[q];
   }
+}
+__global__ void k_flux_fin(Dev g, int nchunk, const double* __restrict__ part, const double* __restrict__ rec,
+                           double* __restrict__ F, double* __restrict__ wall) {
+  flux_fin_body(blockIdx.x, g, nchunk, part, rec, F, wall);
 }
 
 // ------------------------------------------------------------------------
@@ -1167,11 +1200,11 @@ __device__ inline void heat_from_record(const double* M, double Vx, double Vy, i
 // about the shift V' (mode 1); mode 0 only writes the record (shift: V of W);
 // mode 2 writes the record and the heat flux about V of W
 template <class T>
-__global__ __launch_bounds__(256) void k_step7(Dev g, int mode, const T* __restrict__ h,
-                                               const T* __restrict__ b, const double* __restrict__ crec,
-                                               const double* __restrict__ Wp, double* __restrict__ W,
-                                               double* __restrict__ q, double* __restrict__ mrec) {
-  int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void step7_body(int BX, const Dev& g, int mode, const T* __restrict__ h,
+                                           const T* __restrict__ b, const double* __restrict__ crec,
+                                           const double* __restrict__ Wp, double* __restrict__ W,
+                                           double* __restrict__ q, double* __restrict__ mrec) {
+  int c = BX * 4 + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (c >= g.ncell || g.type[c] == 0) return;
   double sx, sy, rho = 0, lam = 0, hn = 0;
@@ -1245,13 +1278,21 @@ __global__ __launch_bounds__(256) void k_step7(Dev g, int mode, const T* __restr
   q[(size_t)c * g.dim] = qx;
   if (g.dim == 2) q[(size_t)c * g.dim + 1] = qy;
 }
+template <class T>
+__global__ __launch_bounds__(256) void k_step7(Dev g, int mode, const T* __restrict__ h,
+                                               const T* __restrict__ b, const double* __restrict__ crec,
+                                               const double* __restrict__ Wp, double* __restrict__ W,
+                                               double* __restrict__ q, double* __restrict__ mrec) {
+  step7_body<T>(blockIdx.x, g, mode, h, b, crec, Wp, W, q, mrec);
+}
 
 // per-cell record from W (or W') and the heat flux (given, or from a moment
 // record shifted to the velocity of W), the micro diagonal base for the
 // physical step dt, and the micro face coefficients
-__global__ void k_cellrec(Dev g, double dt, const double* __restrict__ W, const double* __restrict__ q,
-                          const double* __restrict__ mrec, double* __restrict__ crec) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void cellrec_body(int BX, const Dev& g, double dt, const double* __restrict__ W,
+                                             const double* __restrict__ q, const double* __restrict__ mrec,
+                                             double* __restrict__ crec) {
+  int c = BX * blockDim.x + threadIdx.x;
   if (c >= g.ncell) return;
   crec[(size_t)c * NCREC + C_FLD] = (g.type[c] == 1) ? 1.0 : 0.0;
   if (g.type[c] == 0) return;
@@ -1268,6 +1309,10 @@ __global__ void k_cellrec(Dev g, double dt, const double* __restrict__ W, const 
   r[C_ITAU] = it;
   r[C_D0] = 1.0 / g.dtp[c] + 1.0 / dt + 0.5 * it;
   for (int m = 0; m < 12; ++m) r[C_GEO + m] = g.mgeo[(size_t)c * 12 + m];
+}
+__global__ void k_cellrec(Dev g, double dt, const double* __restrict__ W, const double* __restrict__ q,
+                          const double* __restrict__ mrec, double* __restrict__ crec) {
+  cellrec_body(blockIdx.x, g, dt, W, q, mrec, crec);
 }
 
 // Shakhov equilibrium h+, b+ of a cell record at velocity (vx, vy)
@@ -1320,12 +1365,11 @@ __global__ void k_maxwellian(Dev g, const double* __restrict__ W, T* __restrict_
 
 // overset interpolation: one wavefront per receptor
 template <class T>
-__global__ __launch_bounds__(256) void k_interp(Dev g, int nrec, const int* __restrict__ rec,
-                                                const int* __restrict__ ptr, const int* __restrict__ don,
-                                                const double* __restrict__ wt, T* __restrict__ h,
-                                                T* __restrict__ b, double* __restrict__ W,
-                                                double* __restrict__ q) {
-  int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void interp_body(int BX, const Dev& g, int nrec, const int* __restrict__ rec,
+                                            const int* __restrict__ ptr, const int* __restrict__ don,
+                                            const double* __restrict__ wt, T* __restrict__ h, T* __restrict__ b,
+                                            double* __restrict__ W, double* __restrict__ q) {
+  int r = BX * 4 + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (r >= nrec) return;
   int c = rec[r], p0 = ptr[r], p1 = ptr[r + 1];
@@ -1350,13 +1394,22 @@ __global__ __launch_bounds__(256) void k_interp(Dev g, int nrec, const int* __re
     q[(size_t)c * g.dim + m] = s;
   }
 }
+template <class T>
+__global__ __launch_bounds__(256) void k_interp(Dev g, int nrec, const int* __restrict__ rec,
+                                                const int* __restrict__ ptr, const int* __restrict__ don,
+                                                const double* __restrict__ wt, T* __restrict__ h,
+                                                T* __restrict__ b, double* __restrict__ W,
+                                                double* __restrict__ q) {
+  interp_body<T>(blockIdx.x, g, nrec, rec, ptr, don, wt, h, b, W, q);
+}
 
 // ------------------------------------------------------------------------
 // macro LU-SGS (Eq. dualTimeStepping_macro)
 // ------------------------------------------------------------------------
 // spectral radius per face from W^s
-__global__ void k_gamma(Dev g, const double* __restrict__ W, double* __restrict__ gam) {
-  int f = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gamma_body(int BX, const Dev& g, const double* __restrict__ W,
+                                           double* __restrict__ gam) {
+  int f = BX * blockDim.x + threadIdx.x;
   if (f >= g.nface) return;
   int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
   const double* fg = g.fgeo + (size_t)f * 8;
@@ -1386,6 +1439,9 @@ __global__ void k_gamma(Dev g, const double* __restrict__ W, double* __restrict_
   double mx = 0.5 * (u1 + u2), my = 0.5 * (v1 + v2);
   gam[f] = fabs((mx - fg[3]) * fg[0] + (my - fg[4]) * fg[1]) + 0.5 * (a1 + a2);
 }
+__global__ void k_gamma(Dev g, const double* __restrict__ W, double* __restrict__ gam) {
+  gamma_body(blockIdx.x, g, W, gam);
+}
 
 // macro record per cell (computed in parallel before the sweep):
 //   [0..3] residual R, [4] 1/D (LU-SGS diagonal), [5] 1/(4|Omega|),
@@ -1396,10 +1452,11 @@ constexpr int kMacSlot = 14;
 
 __device__ __forceinline__ void euler_flux_n(int dim, const double* w, double nx, double ny, double un, double* o);
 
-__global__ void k_macro_prep(Dev g, double dt, const double* __restrict__ W, const double* __restrict__ Wn,
-                             const double* __restrict__ F, const double* __restrict__ Fn,
-                             const double* __restrict__ gam, double* __restrict__ mac) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void macro_prep_body(int BX, const Dev& g, double dt, const double* __restrict__ W,
+                                                const double* __restrict__ Wn, const double* __restrict__ F,
+                                                const double* __restrict__ Fn, const double* __restrict__ gam,
+                                                double* __restrict__ mac) {
+  int c = BX * blockDim.x + threadIdx.x;
   if (c >= g.ncell) return;
   const int nw = g.nw;
   double* M = mac + (size_t)c * kMacRec;
@@ -1438,6 +1495,11 @@ __global__ void k_macro_prep(Dev g, double dt, const double* __restrict__ W, con
   M[5] = 0.25 * ivol;
   M[6] = Dg;
   M[7] = 0.0;
+}
+__global__ void k_macro_prep(Dev g, double dt, const double* __restrict__ W, const double* __restrict__ Wn,
+                             const double* __restrict__ F, const double* __restrict__ Fn,
+                             const double* __restrict__ gam, double* __restrict__ mac) {
+  macro_prep_body(blockIdx.x, g, dt, W, Wn, F, Fn, gam, mac);
 }
 
 // ALE Euler flux difference F_E(W + dW) - F_E(W) along n with mesh velocity U
@@ -1555,14 +1617,13 @@ size_t macro_lds(int nt, int max_ni, int max_nj, int any_pi, int any_pj) {
 // wavefront, whose ring of prefetched rows then has the register file to
 // itself; 512 otherwise)
 template <int D, int NTB>
-__global__ __launch_bounds__(NTB) void k_macro_sweep(Dev g, const int* __restrict__ binfo,
-                                                     const double* __restrict__ W,
-                                                     const double* __restrict__ mac,
-                                                     double* __restrict__ dWs, double* __restrict__ dW,
-                                                     double* __restrict__ Wp, double* __restrict__ rpart,
-                                                     int max_ni, int max_nj, int any_pi, int any_pj) {
+__device__ __forceinline__ void macro_sweep_body(int BX, const Dev& g, const int* __restrict__ binfo,
+                                                 const double* __restrict__ W, const double* __restrict__ mac,
+                                                 double* __restrict__ dWs, double* __restrict__ dW,
+                                                 double* __restrict__ Wp, double* __restrict__ rpart, int max_ni,
+                                                 int max_nj, int any_pi, int any_pj) {
   extern __shared__ double msm[];
-  const int* bi = binfo + 8 * blockIdx.x;
+  const int* bi = binfo + 8 * BX;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], pi = bi[3], pj = bi[4];
   const int j = threadIdx.x;
   const int NT = blockDim.x;
@@ -1603,7 +1664,7 @@ __global__ __launch_bounds__(NTB) void k_macro_sweep(Dev g, const int* __restric
     for (int m = 0; m < nw; ++m) {
       double t = 0.0;
       for (int w = 0; w < (NT + 63) / 64; ++w) t += hand[w * 4 + m];
-      rpart[(size_t)blockIdx.x * 4 + m] = t;
+      rpart[(size_t)BX * 4 + m] = t;
     }
   }
   __syncthreads();
@@ -1699,14 +1760,27 @@ __global__ __launch_bounds__(NTB) void k_macro_sweep(Dev g, const int* __restric
     }
   }
 }
+template <int D, int NTB>
+__global__ __launch_bounds__(NTB) void k_macro_sweep(Dev g, const int* __restrict__ binfo,
+                                                     const double* __restrict__ W,
+                                                     const double* __restrict__ mac,
+                                                     double* __restrict__ dWs, double* __restrict__ dW,
+                                                     double* __restrict__ Wp, double* __restrict__ rpart,
+                                                     int max_ni, int max_nj, int any_pi, int any_pj) {
+  macro_sweep_body<D, NTB>(blockIdx.x, g, binfo, W, mac, dWs, dW, Wp, rpart, max_ni, max_nj, any_pi, any_pj);
+}
 
 // L2 norms of the residual: sum the per-block partial sums
-__global__ void k_resid(int nblock, int nw, const double* __restrict__ rpart, double* __restrict__ out) {
+__device__ __forceinline__ void resid_body(int nblock, int nw, const double* __restrict__ rpart,
+                                           double* __restrict__ out) {
   int m = threadIdx.x;
   if (m >= nw) return;
   double s = 0.0;
   for (int b = 0; b < nblock; ++b) s += rpart[(size_t)b * 4 + m];
   out[m] = sqrt(s);
+}
+__global__ void k_resid(int nblock, int nw, const double* __restrict__ rpart, double* __restrict__ out) {
+  resid_body(nblock, nw, rpart, out);
 }
 
 // micro residual r = S - f^s/dt + (D + (f+' - f^s)/tau')/2 of one pair
@@ -1737,11 +1811,11 @@ __device__ __forceinline__ void micro_residual(int dim, const double* r, double 
 // the residual pass, written over D: fully parallel, one wavefront per cell,
 // the cell record is wave-uniform
 template <class T>
-__global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const double* __restrict__ crec,
-                                                   const T* __restrict__ h, const T* __restrict__ b,
-                                                   const T* __restrict__ Sh, const T* __restrict__ Sb,
-                                                   T* __restrict__ Dh, T* __restrict__ Db) {
-  const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+__device__ __forceinline__ void micro_rhs_body(int BX, const Dev& g, double dt, const double* __restrict__ crec,
+                                               const T* __restrict__ h, const T* __restrict__ b,
+                                               const T* __restrict__ Sh, const T* __restrict__ Sb, T* __restrict__ Dh,
+                                               T* __restrict__ Db) {
+  const int c = __builtin_amdgcn_readfirstlane(BX * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (c >= g.ncell || g.type[c] != 1) return;
   const double* r = crec + (size_t)c * NCREC;
@@ -1754,6 +1828,13 @@ __global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const doubl
     Dh[o] = (T)r0;
     Db[o] = (T)r1;
   }
+}
+template <class T>
+__global__ __launch_bounds__(256) void k_micro_rhs(Dev g, double dt, const double* __restrict__ crec,
+                                                   const T* __restrict__ h, const T* __restrict__ b,
+                                                   const T* __restrict__ Sh, const T* __restrict__ Sb,
+                                                   T* __restrict__ Dh, T* __restrict__ Db) {
+  micro_rhs_body<T>(blockIdx.x, g, dt, crec, h, b, Sh, Sb, Dh, Db);
 }
 
 // micro LU-SGS (Eq. dualTimeStepping_micro): forward and backward sweep of
@@ -1810,10 +1891,10 @@ __device__ __forceinline__ double recip_pos(double d) {
 }
 
 template <int D, class T, int KC, int P, int R>
-__global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ binfo, int nslot,
-                                                const double* __restrict__ crec, T* __restrict__ h,
-                                                T* __restrict__ b, T* __restrict__ Dh, T* __restrict__ Db,
-                                                const T* __restrict__ Sh, const T* __restrict__ Sb, double dt) {
+__device__ __forceinline__ void micro_body(int BX, int NBX, int BY, const Dev& g, const int* __restrict__ binfo,
+                                           int nslot, const double* __restrict__ crec, T* __restrict__ h,
+                                           T* __restrict__ b, T* __restrict__ Dh, T* __restrict__ Db,
+                                           const T* __restrict__ Sh, const T* __restrict__ Sb, double dt) {
   extern __shared__ double smem[];
   constexpr bool FUSE = micro_fused(KC, R);
   constexpr int RB = FUSE ? C_UX : C_GEO;       // first staged record entry
@@ -1822,7 +1903,7 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   static_assert(NRM <= RLD, "staged record fits its LDS slot");
   constexpr int NS = (NRM + KC - 1) / KC;       // record entries per lane
   constexpr int OG = C_GEO - RB, OD = C_D0 - RB, OF = C_FLD - RB;
-  const int* bi = binfo + 8 * blockIdx.y;
+  const int* bi = binfo + 8 * BY;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], pi = bi[3], pj = bi[4];
   const int t = threadIdx.x;
   const int lk = t % KC, jt = t / KC;
@@ -1834,10 +1915,10 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
   // that the round-robin dispatch places on the same XCD (every 8th
   // workgroup), so each line is fetched once into that XCD's L2
   constexpr int G = (128 / (KC * (int)sizeof(T)) > 1) ? 128 / (KC * (int)sizeof(T)) : 1;
-  int chunk = blockIdx.x;
+  int chunk = BX;
   if constexpr (G > 1) {
     const int span = 8 * G, base = (chunk / span) * span;
-    if (base + span <= (int)gridDim.x) chunk = base + G * (chunk % 8) + (chunk / 8) % G;
+    if (base + span <= NBX) chunk = base + G * (chunk % 8) + (chunk / 8) % G;
   }
   const int k = chunk * KC + lk;
   const bool kin = k < nv;
@@ -2049,6 +2130,13 @@ __global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ b
       if (!p2p) lds_barrier();
     }
   }
+}
+template <int D, class T, int KC, int P, int R>
+__global__ __launch_bounds__(1024) void k_micro(Dev g, const int* __restrict__ binfo, int nslot,
+                                                const double* __restrict__ crec, T* __restrict__ h,
+                                                T* __restrict__ b, T* __restrict__ Dh, T* __restrict__ Db,
+                                                const T* __restrict__ Sh, const T* __restrict__ Sb, double dt) {
+  micro_body<D, T, KC, P, R>(blockIdx.x, (int)gridDim.x, blockIdx.y, g, binfo, nslot, crec, h, b, Dh, Db, Sh, Sb, dt);
 }
 
 // ------------------------------------------------------------------------
@@ -2293,6 +2381,235 @@ void launch_micro(const Dev& g, int prec, const int* binfo, int max_ni, int max_
   else micro_prec<float>(g, binfo, KC, R, nslot, lds, dt, crec, Sh, Sb, h, b, Dh, Db, st);
 }
 
+// ------------------------------------------------------------------------
+// batched pseudo-iteration (BatchPlan): one launch per stage for all cases
+// ------------------------------------------------------------------------
+// case of flat workgroup `bid`: off[c] <= bid < off[c + 1] (binary search
+// over the prefix table; wave-uniform, so scalar loads)
+__device__ __forceinline__ int case_of(const int* __restrict__ off, int ncase, int bid) {
+  typedef const int __attribute__((address_space(4))) CInt;
+  const CInt* o = (const CInt*)off;
+  int lo = 0, hi = ncase;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (o[mid] <= bid) lo = mid; else hi = mid;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// the case table is read through the constant address space: read-only
+// for the whole launch, so its loads are scalar and free to repeat, as for a
+// per-case kernel's own argument block
+typedef const BatchCase __attribute__((address_space(4))) ConstCase;
+__device__ __forceinline__ const BatchCase& const_case(const BatchCase* cs, int i) {
+  return *(const BatchCase*)&((ConstCase*)cs)[__builtin_amdgcn_readfirstlane(i)];
+}
+// a work item (wave-uniform), read through the constant address space
+__device__ __forceinline__ BatchItem const_item(const BatchItem* items, int it) {
+  typedef const int __attribute__((address_space(4))) CInt;
+  const CInt* p = (const CInt*)(items + __builtin_amdgcn_readfirstlane(it));
+  return BatchItem{__builtin_amdgcn_readfirstlane(p[0]), __builtin_amdgcn_readfirstlane(p[1]),
+                   __builtin_amdgcn_readfirstlane(p[2]), __builtin_amdgcn_readfirstlane(p[3])};
+}
+
+#define UGKS_BATCH_CASE(off)                                   \
+  const int bc_ = case_of(off, ncase, (int)blockIdx.x);         \
+  const BatchCase& a = const_case(cs, bc_);                     \
+  const int bx = (int)blockIdx.x - ((const int __attribute__((address_space(4)))*)off)[bc_];
+
+__global__ void kb_gradW(const BatchCase* __restrict__ cs, const int* __restrict__ off, int ncase) {
+  UGKS_BATCH_CASE(off)
+  gradW_body(bx, a.g, a.W, a.gW);
+}
+__global__ void kb_wallprep(const BatchCase* __restrict__ cs, const int* __restrict__ off, int ncase) {
+  UGKS_BATCH_CASE(off)
+  wallprep_body(bx, a.g, a.dts, a.W, a.q, a.gW, a.rec);
+}
+__global__ void kb_face_fin(const BatchCase* __restrict__ cs, const int* __restrict__ off, int ncase) {
+  UGKS_BATCH_CASE(off)
+  face_fin_body(bx, a.g, a.dts, a.nchunk, a.part, a.W, a.gW, a.rec);
+}
+__global__ void kb_flux_fin(const BatchCase* __restrict__ cs, const int* __restrict__ off, int ncase) {
+  UGKS_BATCH_CASE(off)
+  flux_fin_body(bx, a.g, a.nchunk, a.part, a.rec, a.F, nullptr);
+}
+__global__ void kb_gamma(const BatchCase* __restrict__ cs, const int* __restrict__ off, int ncase) {
+  UGKS_BATCH_CASE(off)
+  gamma_body(bx, a.g, a.W, a.gam);
+}
+__global__ void kb_macro_prep(const BatchCase* __restrict__ cs, const int* __restrict__ off, int ncase) {
+  UGKS_BATCH_CASE(off)
+  macro_prep_body(bx, a.g, a.dt, a.W, a.Wn, a.F, a.Fn, a.gam, a.mac);
+}
+__global__ void kb_cellrec(const BatchCase* __restrict__ cs, const int* __restrict__ off, int ncase) {
+  UGKS_BATCH_CASE(off)
+  cellrec_body(bx, a.g, a.dt, a.Wp, nullptr, a.mrec, a.crec);
+}
+template <class T>
+__global__ __launch_bounds__(256) void kb_interp(const BatchCase* __restrict__ cs, const int* __restrict__ off,
+                                                 int ncase) {
+  UGKS_BATCH_CASE(off)
+  interp_body<T>(bx, a.g, a.nrec, a.orec, a.optr, a.odon, a.ow, (T*)a.h, (T*)a.b, a.W, a.q);
+}
+template <class T>
+__global__ __launch_bounds__(256) void kb_step7(const BatchCase* __restrict__ cs, const int* __restrict__ off,
+                                                int ncase, int mode) {
+  UGKS_BATCH_CASE(off)
+  step7_body<T>(bx, a.g, mode, (const T*)a.h, (const T*)a.b, mode ? a.crec : nullptr, mode ? a.Wp : nullptr, a.W,
+                a.q, a.mrec);
+}
+template <class T>
+__global__ __launch_bounds__(256) void kb_micro_rhs(const BatchCase* __restrict__ cs, const int* __restrict__ off,
+                                                    int ncase) {
+  UGKS_BATCH_CASE(off)
+  micro_rhs_body<T>(bx, a.g, a.dt, a.crec, (const T*)a.h, (const T*)a.b, (const T*)a.Sh, (const T*)a.Sb,
+                    (T*)a.Dh, (T*)a.Db);
+}
+template <int NTB>
+__global__ __launch_bounds__(NTB) void kb_macro_sweep(const BatchCase* __restrict__ cs, const int* __restrict__ off,
+                                                      int ncase, int max_ni, int max_nj, int any_pi, int any_pj) {
+  UGKS_BATCH_CASE(off)
+  macro_sweep_body<2, NTB>(bx, a.g, a.binfo, a.W, a.mac, a.dWs, a.dW, a.Wp, a.rpart, max_ni, max_nj, any_pi,
+                           any_pj);
+}
+// residual norms of inner iteration s: one workgroup per case
+__global__ void kb_resid(const BatchCase* __restrict__ cs, int s) {
+  const BatchCase& a = const_case(cs, blockIdx.x);
+  if (a.resid) resid_body(a.g.nblock, a.g.nw, a.rpart, a.resid + (size_t)s * a.g.nw);
+}
+// persistent march: each workgroup takes every gridDim.x-th work item
+template <int RG, class T, int MODE>
+__global__ __launch_bounds__(64 * (RG + 2)) void kb_march(const BatchCase* __restrict__ cs,
+                                                          const BatchItem* __restrict__ items, int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BatchItem w = const_item(items, it);
+    const BatchCase& a = const_case(cs, w.cs);
+    march_body<RG, T, T, MODE>(w.x, w.y, w.z, a.g, (cint*)a.binfo, a.nchunk, (const T*)a.h, (const T*)a.b,
+                               (cdouble*)a.rec, (cdouble*)a.g.fplan, a.part, (T*)a.Dh, (T*)a.Db);
+    __syncthreads();  // the next item reuses the LDS
+  }
+}
+// persistent micro sweep (no chunk-to-XCD remapping: the items are dealt
+// round robin already)
+template <class T, int KC, int P, int R>
+__global__ __launch_bounds__(1024) void kb_micro(const BatchCase* __restrict__ cs,
+                                                 const BatchItem* __restrict__ items, int nitems, int nslot) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BatchItem w = const_item(items, it);
+    const BatchCase& a = const_case(cs, w.cs);
+    micro_body<2, T, KC, P, R>(w.x, 0, w.y, a.g, a.binfo, nslot, a.crec, (T*)a.h, (T*)a.b, (T*)a.Dh, (T*)a.Db,
+                               (const T*)a.Sh, (const T*)a.Sb, a.dt);
+    __syncthreads();
+  }
+}
+#undef UGKS_BATCH_CASE
+
+template <class T, int KC, int R>
+static const void* kb_micro_fn() {
+  return (const void*)kb_micro<T, KC, micro_depth<T, KC, R>(), R>;
+}
+template <class T>
+static const void* kb_micro_sel(int KC, int R) {
+  switch (KC * 4 + R) {
+    case 16 * 4 + 1: return kb_micro_fn<T, 16, 1>();
+    case 16 * 4 + 2: return kb_micro_fn<T, 16, 2>();
+    case 8 * 4 + 1: return kb_micro_fn<T, 8, 1>();
+    case 8 * 4 + 2: return kb_micro_fn<T, 8, 2>();
+    case 4 * 4 + 1: return kb_micro_fn<T, 4, 1>();
+    case 4 * 4 + 2: return kb_micro_fn<T, 4, 2>();
+    case 2 * 4 + 1: return kb_micro_fn<T, 2, 1>();
+    default: return kb_micro_fn<T, 2, 2>();
+  }
+}
+template <class T>
+static const void* kb_march_sel(int rg, int mode) {
+  if (rg == 6) return mode ? (const void*)kb_march<6, T, 1> : (const void*)kb_march<6, T, 0>;
+  if (rg == 10) return mode ? (const void*)kb_march<10, T, 1> : (const void*)kb_march<10, T, 0>;
+  return mode ? (const void*)kb_march<8, T, 1> : (const void*)kb_march<8, T, 0>;
+}
+
+static int micro_threads(int nslot, int KC, int R) { return ((((nslot + R - 1) / R) * KC + 63) / 64) * 64; }
+
+static int cu_count(int& ncu) {
+  int dev = 0;
+  return (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+             ? -1
+             : 0;
+}
+
+int batch_march_grid(int prec, int rg, int mode, int& grid) {
+  int ncu = 0, a = 0;
+  if (cu_count(ncu)) return -1;
+  const void* fm = prec ? kb_march_sel<float>(rg, mode) : kb_march_sel<double>(rg, mode);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, fm, 64 * (rg + 2), 0) != hipSuccess) return -1;
+  grid = ncu * (a > 0 ? a : 1);
+  return 0;
+}
+
+int batch_micro_grid(size_t micro_lds, int& grid) {
+  int ncu = 0;
+  if (cu_count(ncu)) return -1;
+  // the sweep's occupancy follows from its LDS (one workgroup holds the
+  // hand-off and record slots of its block), at most two 1024-thread
+  // workgroups per CU
+  const int m = (int)((160 * 1024) / (micro_lds > 0 ? micro_lds : 1));
+  grid = ncu * (m > 0 ? (m < 2 ? m : 2) : 1);
+  return 0;
+}
+
+template <class T>
+static void batch_inner_t(const BatchPlan& p, int n_inner, hipStream_t st) {
+  const BatchCase* cs = p.cases;
+  const int nc = p.ncase;
+  kb_step7<T><<<p.n_cell4, 256, 0, st>>>(cs, p.off_cell4, nc, 0);
+  const int KC = p.micro_kc, R = p.micro_rows;
+  const int mthreads = micro_threads(p.micro_nslot, KC, R);
+  for (int s = 0; s < n_inner; ++s) {
+    if (p.n_rec4 > 0) kb_interp<T><<<p.n_rec4, 256, 0, st>>>(cs, p.off_rec4, nc);
+    kb_gradW<<<p.n_cell64, 64, 0, st>>>(cs, p.off_cell64, nc);
+    kb_wallprep<<<p.n_face64, 64, 0, st>>>(cs, p.off_face64, nc);
+    for (int mode = 0; mode < 2; ++mode) {
+      const int rg = p.rg[mode], gm = p.grid_march[mode], nm = p.n_march[mode];
+      const BatchItem* it = p.march_items[mode];
+      if (rg == 6) {
+        if (mode) kb_march<6, T, 1><<<gm, 64 * 8, 0, st>>>(cs, it, nm);
+        else kb_march<6, T, 0><<<gm, 64 * 8, 0, st>>>(cs, it, nm);
+      } else if (rg == 10) {
+        if (mode) kb_march<10, T, 1><<<gm, 64 * 12, 0, st>>>(cs, it, nm);
+        else kb_march<10, T, 0><<<gm, 64 * 12, 0, st>>>(cs, it, nm);
+      } else {
+        if (mode) kb_march<8, T, 1><<<gm, 64 * 10, 0, st>>>(cs, it, nm);
+        else kb_march<8, T, 0><<<gm, 64 * 10, 0, st>>>(cs, it, nm);
+      }
+      if (mode == 0) kb_face_fin<<<p.n_face64, 64, 0, st>>>(cs, p.off_face64, nc);
+    }
+    kb_flux_fin<<<p.n_face64, 64, 0, st>>>(cs, p.off_face64, nc);
+    kb_gamma<<<p.n_face64, 64, 0, st>>>(cs, p.off_face64, nc);
+    kb_macro_prep<<<p.n_cell64, 64, 0, st>>>(cs, p.off_cell64, nc);
+    if (p.macro_nt == 64)
+      kb_macro_sweep<64><<<p.n_block, 64, p.macro_lds, st>>>(cs, p.off_block, nc, p.max_ni, p.max_nj, p.any_pi,
+                                                            p.any_pj);
+    else
+      kb_macro_sweep<512><<<p.n_block, p.macro_nt, p.macro_lds, st>>>(cs, p.off_block, nc, p.max_ni, p.max_nj,
+                                                                      p.any_pi, p.any_pj);
+    if (p.want_resid) kb_resid<<<nc, 64, 0, st>>>(cs, s);
+    kb_cellrec<<<p.n_cell64, 64, 0, st>>>(cs, p.off_cell64, nc);
+    if (!micro_fused(KC, R)) kb_micro_rhs<T><<<p.n_cell4, 256, 0, st>>>(cs, p.off_cell4, nc);
+    const void* fn = kb_micro_sel<T>(KC, R);
+    const BatchItem* mi = p.micro_items;
+    int nmi = p.n_micro, nslot = p.micro_nslot;
+    void* args[] = {(void*)&cs, (void*)&mi, (void*)&nmi, (void*)&nslot};
+    (void)hipLaunchKernel(fn, dim3((unsigned)p.grid_micro), dim3((unsigned)mthreads), args, p.micro_lds, st);
+    kb_step7<T><<<p.n_cell4, 256, 0, st>>>(cs, p.off_cell4, nc, 1);
+  }
+}
+
+void launch_batch_inner(const BatchPlan& p, int n_inner, hipStream_t st) {
+  if (p.prec == 0) batch_inner_t<double>(p, n_inner, st);
+  else batch_inner_t<float>(p, n_inner, st);
+}
+
 // dynamic LDS limits of the sweep kernels, set once per device before any
 // launch (kernel attributes are not stream work, so a captured graph never
 // depends on them)
@@ -2315,8 +2632,13 @@ static int micro_attrs() {
 int init_kernel_attributes() {
   if (micro_attrs<double>() || micro_attrs<float>()) return -1;
   for (const void* k : {(const void*)k_macro_sweep<1, 64>, (const void*)k_macro_sweep<2, 64>,
-                        (const void*)k_macro_sweep<2, 512>})
+                        (const void*)k_macro_sweep<2, 512>, (const void*)kb_macro_sweep<64>,
+                        (const void*)kb_macro_sweep<512>})
     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess) return -1;
+  for (int kc : {16, 8, 4, 2})
+    for (int r : {1, 2})
+      for (const void* k : {kb_micro_sel<double>(kc, r), kb_micro_sel<float>(kc, r)})
+        if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess) return -1;
   return 0;
 }
 

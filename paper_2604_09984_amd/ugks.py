@@ -68,6 +68,8 @@ def lib():
         L.ugks_batch_create.argtypes = [i32, pa, C.POINTER(vp)]
         L.ugks_batch_destroy.argtypes = [vp]
         L.ugks_batch_step.argtypes = [vp, C.POINTER(d), i32, pa, pa, pa, pa, pa, pa, pa, pa, pa, vp]
+        L.ugks_batch_set_mode.argtypes = [vp, i32]
+        L.ugks_batch_get_mode.argtypes = [vp, C.POINTER(i32)]
         L.ugks_set_tuning.argtypes = [vp, i32, i32, i32]
         L.ugks_get_tuning.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.ugks_micro_shape.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
@@ -98,7 +100,7 @@ def exported_symbols():
             "ugks_get_types", "ugks_set_overset", "overset_assemble", "ugks_get_overset", "ugks_maxwellian",
             "ugks_moments", "ugks_heatflux", "ugks_flux", "overset_interp", "ugks_begin_step", "ugks_step",
             "ugks_timesteps", "ugks_step_profile", "ugks_step_graph", "ugks_batch_create", "ugks_batch_step",
-            "ugks_batch_destroy", "ugks_set_tuning", "ugks_get_tuning", "ugks_micro_shape", "ugks_autotune", "ugks_set_wall_rt",
+            "ugks_batch_destroy", "ugks_batch_set_mode", "ugks_batch_get_mode", "ugks_set_tuning", "ugks_get_tuning", "ugks_micro_shape", "ugks_autotune", "ugks_set_wall_rt",
             "ugks_last_flux", "ugks_set_block_velocity", "ugks_face_geometry", "ugks_overset_rows",
             "ugks_flux_adjoint", "ugks_step_adjoint", "ugks_begin_step_adjoint",
             "ugks_workspace_size", "ugks_create_with_workspace", "ugks_status", "ugks_set_checks",
@@ -480,14 +482,27 @@ class Solver:
 
 class Batch:
     """Independent cases (one Solver each, ragged sizes) advanced together
-    from one captured graph with concurrent branches."""
+    from one captured graph: mode 1, one launch per stage for all cases
+    (persistent march and micro-sweep grids over work items); mode 0, each
+    case's own kernel chain on concurrent branches."""
 
-    def __init__(self, solvers):
+    def __init__(self, solvers, mode=None):
         self.solvers = list(solvers)
         arr = (C.c_void_p * len(self.solvers))(*[s.ctx for s in self.solvers])
         h = C.c_void_p()
         _check(lib().ugks_batch_create(len(self.solvers), arr, C.byref(h)))
         self.handle = h
+        if mode is not None:
+            self.set_mode(mode)
+
+    def set_mode(self, mode):
+        _check(lib().ugks_batch_set_mode(self.handle, int(mode)))
+
+    @property
+    def mode(self):
+        m = C.c_int32()
+        _check(lib().ugks_batch_get_mode(self.handle, C.byref(m)))
+        return int(m.value)
 
     def close(self):
         if getattr(self, "handle", None):

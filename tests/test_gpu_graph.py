@@ -89,17 +89,23 @@ def test_graph_after_motion_and_assembly():
     s.close()
 
 
-def test_batch_matches_individual_steps():
+@pytest.mark.parametrize("mode,prec", [(1, ugks.F64), (1, ugks.F32), (0, ugks.F64)],
+                         ids=["one_launch_per_stage_f64", "one_launch_per_stage_f32", "branches_f64"])
+def test_batch_matches_individual_steps(mode, prec):
+    """Ragged cases (cylinder, cavities, a box periodic in both directions,
+    a 70-row channel) advanced by the batch graph equal each case's own
+    pseudo-iterations bit for bit, over two replays."""
     cases = [_cyl(), wl.cavity(8, 12), wl.periodic_box(2, 8, 6, 10),
              wl.cavity(6, 10, periodic_x=True), wl.channel(6, 70, 8)]
-    solvers = [ugks.Solver(c, ugks.F64) for c in cases]
+    solvers = [ugks.Solver(c, prec) for c in cases]
     states, dts, ref = [], [], []
     for c, s in zip(cases, solvers):
-        dt, st = _state(s, c, ugks.F64)
+        dt, st = _state(s, c, prec)
         dts.append(dt)
         states.append(_clone(st))
         ref.append(_clone(st))
-    batch = ugks.Batch(solvers)
+    batch = ugks.Batch(solvers, mode=mode)
+    assert batch.mode == mode
     resid = [torch.zeros((3, c.nw), dtype=torch.float64, device="cuda") for c in cases]
     rref = [torch.zeros_like(r) for r in resid]
     for rep in range(2):
@@ -148,3 +154,21 @@ def test_tuning_does_not_change_results(prec):
     assert s.tuning() == choice
     assert _equal(st, st0)  # the caller's state is not written
     s.close()
+
+
+def test_batch_mode_rules():
+    """One launch per stage needs 2D cases of one storage type; a batch with
+    a 1D case keeps the branch graph."""
+    s1 = ugks.Solver(wl.sod_1d(ncell=20, nv=13), ugks.F64)
+    s2 = ugks.Solver(wl.cavity(6, 8), ugks.F64)
+    s3 = ugks.Solver(wl.cavity(6, 8), ugks.F32)
+    for group in ([s1, s2], [s2, s3]):
+        b = ugks.Batch(group)
+        assert b.mode == 0
+        with pytest.raises(ugks.UgksError):
+            b.set_mode(1)
+        with pytest.raises(ugks.UgksError):
+            b.set_mode(2)
+        b.close()
+    for s in (s1, s2, s3):
+        s.close()
