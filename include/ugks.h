@@ -184,6 +184,16 @@ int ugks_set_overset(ugks_ctx* ctx, int32_t nrec, const int32_t* rec, const int3
  * in 1D; nothing is installed on error.  Synchronous.
  */
 int overset_assemble(ugks_ctx* ctx, int32_t wrule, int32_t overlap, int32_t* nrec);
+/*
+ * overset_assemble on the context's GPU (Secs. 3.1-3.2): bins of each zone's
+ * cells, node classes one thread per node, cell kinds and receptor layers
+ * one thread per cell, donors and weights one thread per receptor, rows
+ * compacted by scans; the same predicates and arithmetic without
+ * contraction, so kinds, receptors, donors and weights equal
+ * overset_assemble's bit for bit.  Same arguments, errors and installation;
+ * uses temporary device memory and a stream of its own; synchronous.
+ */
+int overset_assemble_device(ugks_ctx* ctx, int32_t wrule, int32_t overlap, int32_t* nrec);
 
 /* The installed donor table (host copies): *nrec receptors, *ndon donor
    entries; rec[nrec], ptr[nrec+1], don[ndon], w[ndon] are filled when not

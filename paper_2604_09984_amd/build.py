@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libugks.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["ugks_kernels.hip", "ugks_adjoint.hip", "ugks_api.cpp", "ugks_overset.cpp"]
+SOURCES = ["ugks_kernels.hip", "ugks_adjoint.hip", "ugks_api.cpp", "ugks_overset.cpp", "ugks_overset_dev.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -23,6 +23,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 # the per-case kernel and into the batched one rounds the same (results are
 # bit-identical per case whatever the launch)
 EXTRA = {"ugks_api.cpp": ["-ffp-contract=off"], "ugks_overset.cpp": ["-ffp-contract=off"],
+         "ugks_overset_dev.hip": ["-ffp-contract=off"],
          "ugks_kernels.hip": ["-ffp-contract=on"]}
 
 

@@ -985,7 +985,17 @@ int ugks_get_overset(const ugks_ctx* c, int32_t* nrec, int32_t* ndon, int32_t* r
   return UGKS_OK;
 }
 
+static int assemble_impl(ugks_ctx* c, int32_t wrule, int32_t overlap, int32_t* nrec, bool device);
+
 int overset_assemble(ugks_ctx* c, int32_t wrule, int32_t overlap, int32_t* nrec) {
+  return assemble_impl(c, wrule, overlap, nrec, false);
+}
+
+int overset_assemble_device(ugks_ctx* c, int32_t wrule, int32_t overlap, int32_t* nrec) {
+  return assemble_impl(c, wrule, overlap, nrec, true);
+}
+
+static int assemble_impl(ugks_ctx* c, int32_t wrule, int32_t overlap, int32_t* nrec, bool device) {
   if (!c) return fail(UGKS_E_ARG, "null context");
   ++c->version;
   if (wrule != 0 && wrule != 1) return fail(UGKS_E_ARG, "wrule must be 0 or 1");
@@ -1002,7 +1012,13 @@ int overset_assemble(ugks_ctx* c, int32_t wrule, int32_t overlap, int32_t* nrec)
   in.old_type = &c->type;
   OversetOutput res;
   std::string msg;
-  int rc = overset_build(in, wrule, overlap, res, msg);
+  int rc = UGKS_OK;
+  if (device) {
+    if (hipSetDevice(c->device) != hipSuccess) return fail(UGKS_E_DEVICE, "hipSetDevice failed");
+    rc = overset_build_device(in, wrule, overlap, res, msg);
+  } else {
+    rc = overset_build(in, wrule, overlap, res, msg);
+  }
   if (rc) return fail(rc, msg);
   c->type = res.type;
   build_tables(c);

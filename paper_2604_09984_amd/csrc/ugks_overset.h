@@ -31,5 +31,8 @@ struct OversetOutput {
 // returns 0 or a negative UGKS_E_* code with a message; on error `out` is
 // left unspecified and nothing should be installed
 int overset_build(const OversetInput& in, int wrule, int overlap, OversetOutput& out, std::string& msg);
+// the same assembly on the current HIP device (ugks_overset_dev.hip), with
+// identical results
+int overset_build_device(const OversetInput& in, int wrule, int overlap, OversetOutput& out, std::string& msg);
 
 }  // namespace ugks

@@ -52,6 +52,7 @@ def lib():
         L.ugks_get_types.argtypes = [vp, C.POINTER(C.c_int8)]
         L.ugks_set_overset.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(d)]
         L.overset_assemble.argtypes = [vp, i32, i32, C.POINTER(i32)]
+        L.overset_assemble_device.argtypes = [vp, i32, i32, C.POINTER(i32)]
         L.ugks_get_overset.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
                                        C.POINTER(i32), C.POINTER(d)]
         L.ugks_maxwellian.argtypes = [vp, vp, vp, vp, vp]
@@ -97,7 +98,7 @@ def lib():
 
 def exported_symbols():
     return ["ugks_create", "ugks_destroy", "ugks_sizes", "ugks_set_poses", "ugks_set_types",
-            "ugks_get_types", "ugks_set_overset", "overset_assemble", "ugks_get_overset", "ugks_maxwellian",
+            "ugks_get_types", "ugks_set_overset", "overset_assemble", "overset_assemble_device", "ugks_get_overset", "ugks_maxwellian",
             "ugks_moments", "ugks_heatflux", "ugks_flux", "overset_interp", "ugks_begin_step", "ugks_step",
             "ugks_timesteps", "ugks_step_profile", "ugks_step_graph", "ugks_batch_create", "ugks_batch_step",
             "ugks_batch_destroy", "ugks_batch_set_mode", "ugks_batch_get_mode", "ugks_set_tuning", "ugks_get_tuning", "ugks_micro_shape", "ugks_autotune", "ugks_set_wall_rt",
@@ -228,9 +229,12 @@ class Solver:
         ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
         _check(lib().ugks_set_overset(self.ctx, len(rec), ip(rec), ip(ptr), ip(don), _dp(w)))
 
-    def assemble(self, wrule=0, overlap=2) -> int:
+    def assemble(self, wrule=0, overlap=2, device=False) -> int:
+        """Overset assembly at the installed poses (on the GPU with
+        device=True; identical results); returns the receptor count."""
         n = C.c_int32()
-        _check(lib().overset_assemble(self.ctx, int(wrule), int(overlap), C.byref(n)))
+        fn = lib().overset_assemble_device if device else lib().overset_assemble
+        _check(fn(self.ctx, int(wrule), int(overlap), C.byref(n)))
         return n.value
 
     def overset(self):

@@ -66,7 +66,7 @@ def test_assembly_errors():
     s.close()
 
 
-def _moving_steps(case, prec, nsteps=2, n_inner=3, jump=None):
+def _moving_steps(case, prec, nsteps=2, n_inner=3, jump=None, device=False):
     o, s = both(case, prec=prec)
     h, b, W = wl.synthetic_f(case, amp=0.02)
     q = o.heatflux(h, b, W)
@@ -82,7 +82,7 @@ def _moving_steps(case, prec, nsteps=2, n_inner=3, jump=None):
             o.set_poses(poses)
             s.set_poses(poses)
         assert o.assemble(wr, ov)[0] == 0
-        s.assemble(wr, ov)
+        s.assemble(wr, ov, device=device)
         _same_tables(o, s)
         dts, dtp = o.timesteps()
         dt = case.dt if case.dt is not None else case.dt_over_dts * dts
@@ -133,3 +133,79 @@ def test_moving_overset_steps_f32(name, mk):
     e = _moving_steps(case, ugks.F32)
     say("f32 moving overset", name, e)
     assert max(e) <= 1e-5
+
+
+# ----------------------------------------------------------------------------
+# The assembly on the GPU (overset_assemble_device): the same tables as the
+# oracle and, weights included, bit for bit as the host assembly.
+
+def _tables(s):
+    return (s.types(), *s.overset())
+
+
+@pytest.mark.parametrize("name,mk", OV_CASES, ids=[c[0] for c in OV_CASES])
+def test_device_assembly_parity(name, mk):
+    case = mk()
+    o, s = both(case)
+    h = ugks.Solver(case, ugks.F64)
+    for t in (0.0, 0.37, 1.3):
+        poses = case.poses(t)
+        for x in (o, s, h):
+            x.set_poses(poses)
+        rc, n_o = o.assemble(case.overset["wrule"], case.overset["overlap"])
+        assert rc == 0
+        n_d = s.assemble(case.overset["wrule"], case.overset["overlap"], device=True)
+        n_h = h.assemble(case.overset["wrule"], case.overset["overlap"])
+        assert n_d == n_o == n_h
+        _same_tables(o, s)
+        td, th = _tables(s), _tables(h)
+        assert all(np.array_equal(a, b) for a, b in zip(td, th))
+    s.close()
+    h.close()
+
+
+def test_device_assembly_orphan():
+    case = wl.overset_patch(ni_bg=16, npatch=14, half=0.55, nv=4)
+    s = ugks.Solver(case, ugks.F64)
+    assert s.assemble(0, 2, device=True) > 0
+    before = s.types()
+    s.set_poses([(0.0,) * 6, (5.0, 0.0, 0.0, 0.0, 0.0, 0.0)])
+    with pytest.raises(ugks.UgksError, match="-5"):
+        s.assemble(0, 2, device=True)
+    assert np.array_equal(s.types(), before)
+    with pytest.raises(ugks.UgksError):
+        s.assemble(2, 2, device=True)
+    s.close()
+
+
+def test_device_assembly_refill_steps():
+    """A jump uncovers hole cells: the device assembly's refill rows drive
+    the same moving steps as the oracle's."""
+    case = wl.overset_patch(ni_bg=16, npatch=14, half=0.55, nv=8)
+    jump = [(0.0,) * 6, (0.18, 0.3, 0.09, 0.0, 0.0, 0.0)]
+    e = _moving_steps(case, ugks.F64, nsteps=2, jump=jump, device=True)
+    say("device assembly, refill h b W", e)
+    assert max(e) <= 1e-10
+
+
+@pytest.mark.parametrize("mk", [lambda: wl.mems_plate(kn=0.1), lambda: wl.two_body(nv=4)], ids=["mems_plate", "two_body"])
+def test_device_assembly_full_size(mk):
+    """Full-size meshes (256^2 + 128 x 64; 512 x 256 + 2 x 128 x 96) at a
+    moving pose: device tables equal the host's bit for bit; both timed."""
+    import time
+    case = mk()
+    s, h = ugks.Solver(case, ugks.F32), ugks.Solver(case, ugks.F32)
+    for t in (0.025, 0.3):
+        for x in (s, h):
+            x.set_poses(case.poses(t))
+        t1 = time.perf_counter()
+        n_h = h.assemble(case.overset["wrule"], case.overset["overlap"])
+        t2 = time.perf_counter()
+        n_d = s.assemble(case.overset["wrule"], case.overset["overlap"], device=True)
+        t0 = t1 - (time.perf_counter() - t2)
+        td, th = _tables(s), _tables(h)
+        say(f"  {case.name} t={t}: {n_d} receptors; device {1e3 * (t1 - t0):.1f} ms, host {1e3 * (t2 - t1):.1f} ms")
+        assert n_d == n_h
+        assert all(np.array_equal(a, b) for a, b in zip(td, th))
+    s.close()
+    h.close()
