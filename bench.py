@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--workload-steps", type=int, default=5,
                     help="pseudo-iterations timed on each of the other workloads (0: skip)")
     ap.add_argument("--nvx", type=int, default=64)
+    ap.add_argument("--workload", default=None,
+                    help="run only this workload (sod, plate, two_body, batch) and print its line")
     ap.add_argument("--adjoint-calls", type=int, default=3,
                     help="timed reverse passes of one pseudo-iteration (FP64; 0: skip)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
@@ -173,9 +175,29 @@ def time_workload(case, prec_name, iters, t_pose=0.0):
     s.step_graph(dt, iters, h, b, W, Wn, q, Sh, Sb, Fn)
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / iters
-    pairs = int((s.types() == 1).sum()) * s.nv
+    finite = bool(torch.isfinite(h).all().item() and torch.isfinite(W).all().item())
+    live = s.types() == 1
+    rho_min = float(W[torch.as_tensor(live, device=W.device), 0].min().item()) if case.dim == 2 else None
+    pairs = int(live.sum()) * s.nv
+    tuning_d = dict(zip(("kc_max", "rg_eq", "rg_flux"), tuning))
+    micro = s.micro_shape()
+    # per-kernel times (HIP events on the library's stream), the dominant
+    # kernel's roofline and the whole iteration's algorithmic HBM rate
+    prof = s.step_profile(dt, 2, h, b, W, Wn, q, Sh, Sb, Fn)
+    torch.cuda.synchronize()
+    kv = kernel_values(micro)
+    nbytes = 8 if prec_name == "f64" else 4
+    step_bytes = sum(kv.values()) * nbytes * pairs
     out.update(pairs=pairs, pseudo_steps=iters, ms_per_pseudo_step=round(ms, 4), value=pairs / (ms * 1e-3),
-               launch_shapes=dict(zip(("kc_max", "rg_eq", "rg_flux"), tuning)))
+               launch_shapes=tuning_d, finite=finite, rho_min=rho_min,
+               stages_ms={k: round(v, 4) for k, v in prof.items()},
+               hbm_algorithmic_frac=round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               roofline=roofline(prof, pairs, prec_name, tuning_d, micro) if case.dim == 2 else None)
+    if case.overset is not None:
+        # the same assembly on the GPU (identical tables)
+        t0 = time.perf_counter()
+        s.assemble(case.overset["wrule"], case.overset["overlap"], device=True)
+        out["assembly_device_ms"] = round(1e3 * (time.perf_counter() - t0), 2)
     s.close()
     del h, b, W, Wn, q, Sh, Sb, Fn
     torch.cuda.empty_cache()
@@ -248,7 +270,7 @@ def copy_calibration(gib):
     print(json.dumps({"copy_calibration_bytes": 8 * n, "launches": 3}), flush=True)
 
 
-def cpu_baseline(case, nsteps):
+def cpu_baseline(case, nsteps, one_thread=True):
     """The FP64 oracle, as it stands, on the host cores: Steps 1-2 untimed,
     then `nsteps` pseudo-iterations timed on the full workload."""
     import numpy as np
@@ -265,9 +287,34 @@ def cpu_baseline(case, nsteps):
     sec = time.perf_counter() - t0
     pairs = o.ncell * o.nv
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": pairs * nsteps / sec, "unit": "pair-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{nsteps} pseudo-iterations (after Steps 1-2) of the full workload, "
-                      f"{pairs} pairs, {sec:.1f} s"}
+    out = {"value": pairs * nsteps / sec, "unit": "pair-updates/s", "cores": cores, "kind": "oracle",
+           "sample": f"{nsteps} pseudo-iterations (after Steps 1-2) of the full workload, "
+                     f"{pairs} pairs, {sec:.1f} s", "cpu_model": cpu_model()}
+    if one_thread:
+        # the same oracle on one thread (its OpenMP loops run over independent
+        # velocities or cells, so the results are the same), one iteration
+        import ctypes
+        omp = ctypes.CDLL("libgomp.so.1")
+        omp.omp_set_num_threads(1)
+        try:
+            t0 = time.perf_counter()
+            o.pseudo_step(dt, dts, dtp, h, b, W, Wn, q, Sh, Sb, Fn)
+            sec1 = time.perf_counter() - t0
+        finally:
+            omp.omp_set_num_threads(cores)
+        out["one_thread"] = {"value": pairs / sec1, "sample": f"1 pseudo-iteration, {sec1:.1f} s"}
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def roofline(stages, pairs, prec, tuning, micro):
@@ -303,6 +350,22 @@ def main():
         sys.exit(3)
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
+        return
+    if args.workload is not None:
+        k = max(args.workload_steps, 1)
+        if args.workload == "sod":
+            r = time_workload(wl.sod_1d(), "f64", 10 * k)
+        elif args.workload == "plate":
+            plate = wl.mems_plate(kn=0.1)
+            r = {p: time_workload(plate, p, k, t_pose=plate.dt) for p in ("f32", "f64")}
+        elif args.workload == "two_body":
+            r = {p: time_workload(wl.two_body(), p, k, t_pose=0.25) for p in ("f32", "f64")}
+        elif args.workload == "batch":
+            r = time_batch(64, "f32", k)
+        else:
+            print(f"unknown workload {args.workload}", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({"workload": args.workload, "result": r}), flush=True)
         return
     case = wl.cylinder(nvx=args.nvx)
     r64 = run_gpu(case, "f64", args.steps, args.warmup, adjoint_calls=args.adjoint_calls)
