@@ -86,6 +86,13 @@ extern "C" {
  *   nodes          per block the reference node coordinates, x then y, each
  *                  (ni+1)*(nj+1) values with index i + (ni+1)*j (1D: x only).
  *   prec           UGKS_F64 or UGKS_F32.
+ *   nvu, vu, wu    optional unstructured velocity mesh (2D; nvu = 0: the
+ *                  uniform grid above).  nvu > 0 replaces it by nvu points
+ *                  vu (x components, then y components) with weights wu,
+ *                  the areas of their velocity cells (Sec. 2.1: V_k is the
+ *                  volume of the k-th velocity cell); nvx, nvy, vx, vy and
+ *                  vrange are then ignored.  UGKS_E_ARG for a non-positive
+ *                  weight or a null array, UGKS_E_UNSUPPORTED in 1D.
  */
 typedef struct {
   int32_t dim;
@@ -101,6 +108,9 @@ typedef struct {
   const double* bdbl;
   const double* nodes;
   int32_t prec;
+  int32_t nvu;
+  const double* vu;
+  const double* wu;
 } ugks_problem;
 
 typedef struct ugks_ctx ugks_ctx;

@@ -29,6 +29,8 @@ def _bind(L, S):
     L.or_create.restype = C.c_void_p
     L.or_create.argtypes = [C.c_int, D, I, D, D, D, D, D, C.c_int, I, D, D]
     L.or_free.argtypes = [C.c_void_p]
+    L.or_set_dvs.argtypes = [C.c_void_p, C.c_int, D, D, D]
+    L.or_set_dvs.restype = C.c_int
     for n in ("or_ncell", "or_nface", "or_nv"):
         getattr(L, n).argtypes = [C.c_void_p]
         getattr(L, n).restype = C.c_int
@@ -168,6 +170,10 @@ class Oracle:
                                _d(cfl), len(case.blocks), _i(bint), _d(bdbl), _d(nodes))
         if not self.ptr:
             raise ValueError("oracle rejected the case")
+        if getattr(case, "dvs", None) is not None:
+            dx, dy, dw = (self._in(np.ascontiguousarray(a, dtype=np.float64)) for a in case.dvs)
+            if L.or_set_dvs(self.ptr, len(case.dvs[0]), _d(dx), _d(dy), _d(dw)) != 0:
+                raise ValueError("oracle rejected the velocity mesh")
         self.ncell = L.or_ncell(self.ptr)
         self.nface = L.or_nface(self.ptr)
         self.nv = L.or_nv(self.ptr)

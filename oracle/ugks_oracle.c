@@ -669,6 +669,27 @@ void or_free(or_case* c) {
   free(c);
 }
 
+/* Unstructured discrete velocity space (Sec. 2.1: V_k is the volume of the
+   k-th cell of the velocity mesh): the points and their cell areas replace
+   the uniform grid; the far-field Maxwellian follows.  2D only. */
+int or_set_dvs(or_case* c, int nv, const real* vx, const real* vy, const real* wk) {
+  if (c->dim != 2 || nv < 1) return -1;
+  for (int k = 0; k < nv; k++)
+    if (!(wk[k] > 0.0)) return -1;
+  free(c->vk_x); free(c->vk_y); free(c->wk); free(c->finf_h); free(c->finf_b);
+  c->nv = nv; c->nvx = nv; c->nvy = 1;
+  c->vk_x = (real*)malloc(sizeof(real) * nv);
+  c->vk_y = (real*)malloc(sizeof(real) * nv);
+  c->wk = (real*)malloc(sizeof(real) * nv);
+  c->finf_h = (real*)malloc(sizeof(real) * nv);
+  c->finf_b = (real*)malloc(sizeof(real) * nv);
+  for (int k = 0; k < nv; k++) { c->vk_x[k] = vx[k]; c->vk_y[k] = vy[k]; c->wk[k] = wk[k]; }
+  real rho, u[2], lam;
+  prim(c, c->winf, &rho, u, &lam);
+  for (int k = 0; k < nv; k++) maxw(c, rho, u, lam, c->vk_x[k], c->vk_y[k], &c->finf_h[k], &c->finf_b[k]);
+  return 0;
+}
+
 void or_dvs(const or_case* c, real* vx, real* vy, real* wk) {
   for (int k = 0; k < c->nv; k++) { vx[k] = c->vk_x[k]; vy[k] = c->vk_y[k]; wk[k] = c->wk[k]; }
 }

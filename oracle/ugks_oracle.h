@@ -80,6 +80,10 @@ void or_set_wall_rt(or_case* c, int blk, int side, real rtw);
    poses. */
 void or_update_geometry(or_case* c);
 
+/* replaces the uniform velocity grid by nv points (vx, vy) with cell
+   volumes wk > 0 (an unstructured velocity mesh, 2D); call right after
+   or_create.  0, or -1 on bad input (nothing changed). */
+int or_set_dvs(or_case* c, int nv, const real* vx, const real* vy, const real* wk);
 /* velocity points and quadrature weights V_k (k = ix + nvx*iy) */
 void or_dvs(const or_case* c, real* vx, real* vy, real* wk);
 /* one-axis composite Newton-Cotes weights (reading of the velocity grid) */

@@ -260,6 +260,41 @@ void build_faces(ugks_ctx* c) {
 }
 
 // node positions, cell and face geometry, time steps at the current poses
+// vertices of the convex hull of the velocity points: the four corners of a
+// uniform grid (in the order x-min/max by y-min/max), Andrew's monotone
+// chain for an unstructured mesh
+static std::vector<std::pair<double, double>> velocity_hull(const ugks_ctx* c) {
+  std::vector<std::pair<double, double>> h;
+  if (c->nvy > 1 || c->dim == 1) {
+    const double vxs[2] = {c->vx[0], c->vx[c->nv - 1]};
+    const double vys[2] = {c->vy[0], c->vy[c->nv - 1]};
+    for (int a = 0; a < 2; ++a)
+      for (int e = 0; e < 2; ++e) h.push_back({vxs[a], vys[e]});
+    return h;
+  }
+  std::vector<std::pair<double, double>> p(c->nv);
+  for (int k = 0; k < c->nv; ++k) p[k] = {c->vx[k], c->vy[k]};
+  std::sort(p.begin(), p.end());
+  p.erase(std::unique(p.begin(), p.end()), p.end());
+  if (p.size() < 3) return p;
+  auto cross = [](const std::pair<double, double>& o, const std::pair<double, double>& a,
+                  const std::pair<double, double>& b) {
+    return (a.first - o.first) * (b.second - o.second) - (a.second - o.second) * (b.first - o.first);
+  };
+  std::vector<std::pair<double, double>> H(2 * p.size());
+  size_t k = 0;
+  for (size_t i = 0; i < p.size(); ++i) {
+    while (k >= 2 && cross(H[k - 2], H[k - 1], p[i]) <= 0) --k;
+    H[k++] = p[i];
+  }
+  for (size_t i = p.size() - 1, t = k + 1; i > 0; --i) {
+    while (k >= t && cross(H[k - 2], H[k - 1], p[i - 1]) <= 0) --k;
+    H[k++] = p[i - 1];
+  }
+  H.resize(k - 1);
+  return H;
+}
+
 void compute_geometry(ugks_ctx* c) {
   int d = c->dim;
   for (int b = 0; b < (int)c->blk.size(); ++b) {
@@ -367,18 +402,18 @@ void compute_geometry(ugks_ctx* c) {
     c->wtab.insert(c->wtab.end(), wall_of[q].begin(), wall_of[q].end());
     c->wptr[q + 1] = (int)(c->wtab.size() / kWtN);
   }
-  // time steps: max_k |(v_k - U_f).n| is reached at a corner of the velocity box
+  // time steps: max_k |(v_k - U_f).n| (a convex function of v) is reached
+  // at a vertex of the velocity points' convex hull: the corners of a
+  // uniform grid's box, the hull of an unstructured mesh
   std::vector<double> smax(c->nface, 0.0);
-  double vxs[2] = {c->vx[0], c->vx[c->nv - 1]};
-  double vys[2] = {c->vy[0], c->vy[c->nv - 1]};
+  const std::vector<std::pair<double, double>> hull = velocity_hull(c);
   for (int f = 0; f < c->nface; ++f) {
     const double* g = &c->fgeo[8 * (size_t)f];
     double m = 0.0;
-    for (int a = 0; a < 2; ++a)
-      for (int e = 0; e < 2; ++e) {
-        double w = std::fabs((vxs[a] - g[3]) * g[0] + (vys[e] - g[4]) * g[1]);
-        m = std::max(m, w);
-      }
+    for (const auto& v : hull) {
+      double w = std::fabs((v.first - g[3]) * g[0] + (v.second - g[4]) * g[1]);
+      m = std::max(m, w);
+    }
     smax[f] = m;
   }
   double dts = INFINITY;
@@ -566,6 +601,7 @@ Sizes sizes_of(const ugks_problem* p) {
   Sizes z{};
   z.dim = p->dim; z.nw = p->dim + 2; z.nv = p->nvx * ((p->dim == 2) ? p->nvy : 1);
   z.nvx = p->nvx; z.nvy = (p->dim == 2) ? p->nvy : 1;
+  if (p->nvu > 0) { z.nv = p->nvu; z.nvx = p->nvu; z.nvy = 1; }
   z.nblock = p->nblock; z.prec = p->prec;
   for (int b = 0; b < p->nblock; ++b) {
     const int ni = p->bint[6 * b], nj = (p->dim == 2) ? p->bint[6 * b + 1] : 1;
@@ -603,10 +639,18 @@ int ugks_create_with_workspace(const ugks_problem* p, int device, void* work, si
 static int check_problem(const ugks_problem* p) {
   if (p->dim != 1 && p->dim != 2) return fail(UGKS_E_ARG, "dim must be 1 or 2");
   if (p->prec != UGKS_F64 && p->prec != UGKS_F32) return fail(UGKS_E_ARG, "prec must be UGKS_F64 or UGKS_F32");
-  if (p->nvx < 2 || (p->dim == 2 && p->nvy < 2) || (p->dim == 1 && p->nvy != 1))
-    return fail(UGKS_E_SHAPE, "bad velocity grid size");
-  if (!p->vx || !p->vy || !p->bint || !p->bdbl || !p->nodes || p->nblock < 1)
-    return fail(UGKS_E_ARG, "null array or no block");
+  if (p->nvu < 0) return fail(UGKS_E_ARG, "negative nvu");
+  if (p->nvu > 0) {
+    if (p->dim != 2) return fail(UGKS_E_UNSUPPORTED, "an unstructured velocity mesh is 2D");
+    if (!p->vu || !p->wu) return fail(UGKS_E_ARG, "null velocity mesh");
+    for (int k = 0; k < p->nvu; ++k)
+      if (!(p->wu[k] > 0.0)) return fail(UGKS_E_ARG, "non-positive velocity cell area");
+  } else {
+    if (p->nvx < 2 || (p->dim == 2 && p->nvy < 2) || (p->dim == 1 && p->nvy != 1))
+      return fail(UGKS_E_SHAPE, "bad velocity grid size");
+    if (!p->vx || !p->vy) return fail(UGKS_E_ARG, "null velocity points");
+  }
+  if (!p->bint || !p->bdbl || !p->nodes || p->nblock < 1) return fail(UGKS_E_ARG, "null array or no block");
   for (int b = 0; b < p->nblock; ++b)
     if (p->bint[6 * b] < 2 || (p->dim == 2 && p->bint[6 * b + 1] < 2)) return fail(UGKS_E_ARG, "bad block size");
   return UGKS_OK;
@@ -637,19 +681,27 @@ static int create_ctx(const ugks_problem* p, int device, void* work, size_t work
   c->dim = p->dim; c->nxi = 3 - p->dim; c->nw = p->dim + 2; c->prec = p->prec;
   c->pr = p->pr; c->omega = p->omega; c->mu_ref = p->mu_ref; c->rt_ref = p->rt_ref;
   c->cfl_s = p->cfl_s; c->cfl_p = p->cfl_p;
-  c->nvx = p->nvx; c->nvy = p->nvy; c->nv = p->nvx * p->nvy;
   for (int m = 0; m < 4; ++m) c->vrange[m] = p->vrange[m];
   for (int m = 0; m < c->nw; ++m) c->winf[m] = p->winf[m];
-  std::vector<double> wx = nc_weights(c->nvx, p->vrange[0], p->vrange[1]);
-  std::vector<double> wy = (c->dim == 2) ? nc_weights(c->nvy, p->vrange[2], p->vrange[3]) : std::vector<double>{1.0};
-  c->vx.resize(c->nv); c->vy.resize(c->nv); c->wk.resize(c->nv);
-  for (int iy = 0; iy < c->nvy; ++iy)
-    for (int ix = 0; ix < c->nvx; ++ix) {
-      int k = ix + c->nvx * iy;
-      c->vx[k] = p->vx[ix];
-      c->vy[k] = (c->dim == 2) ? p->vy[iy] : 0.0;
-      c->wk[k] = wx[ix] * wy[iy];
-    }
+  if (p->nvu > 0) {
+    // unstructured velocity mesh: the given points and cell areas
+    c->nvx = p->nvu; c->nvy = 1; c->nv = p->nvu;
+    c->vx.assign(p->vu, p->vu + p->nvu);
+    c->vy.assign(p->vu + p->nvu, p->vu + 2 * (size_t)p->nvu);
+    c->wk.assign(p->wu, p->wu + p->nvu);
+  } else {
+    c->nvx = p->nvx; c->nvy = p->nvy; c->nv = p->nvx * p->nvy;
+    std::vector<double> wx = nc_weights(c->nvx, p->vrange[0], p->vrange[1]);
+    std::vector<double> wy = (c->dim == 2) ? nc_weights(c->nvy, p->vrange[2], p->vrange[3]) : std::vector<double>{1.0};
+    c->vx.resize(c->nv); c->vy.resize(c->nv); c->wk.resize(c->nv);
+    for (int iy = 0; iy < c->nvy; ++iy)
+      for (int ix = 0; ix < c->nvx; ++ix) {
+        int k = ix + c->nvx * iy;
+        c->vx[k] = p->vx[ix];
+        c->vy[k] = (c->dim == 2) ? p->vy[iy] : 0.0;
+        c->wk[k] = wx[ix] * wy[iy];
+      }
+  }
   const double* np = p->nodes;
   int ncell = 0;
   size_t nnode = 0;

@@ -27,7 +27,8 @@ class _Problem(C.Structure):
                 ("vx", C.POINTER(C.c_double)), ("vy", C.POINTER(C.c_double)),
                 ("vrange", C.c_double * 4), ("winf", C.c_double * 4), ("cfl_s", C.c_double),
                 ("cfl_p", C.c_double), ("nblock", C.c_int32), ("bint", C.POINTER(C.c_int32)),
-                ("bdbl", C.POINTER(C.c_double)), ("nodes", C.POINTER(C.c_double)), ("prec", C.c_int32)]
+                ("bdbl", C.POINTER(C.c_double)), ("nodes", C.POINTER(C.c_double)), ("prec", C.c_int32),
+                ("nvu", C.c_int32), ("vu", C.POINTER(C.c_double)), ("wu", C.POINTER(C.c_double))]
 
 
 class UgksError(RuntimeError):
@@ -147,7 +148,15 @@ def _problem(case, prec):
     p.bdbl = _dp(bdbl)
     p.nodes = _dp(nodes)
     p.prec = prec
-    return p, (vx, vy, bint, bdbl, nodes)
+    keep = (vx, vy, bint, bdbl, nodes)
+    dvs = getattr(case, "dvs", None)
+    if dvs is not None:
+        # unstructured velocity mesh: points (x then y) and cell areas
+        vu = np.ascontiguousarray(np.concatenate([dvs[0], dvs[1]]), dtype=np.float64)
+        wu = np.ascontiguousarray(dvs[2], dtype=np.float64)
+        p.nvu, p.vu, p.wu = len(dvs[0]), _dp(vu), _dp(wu)
+        keep = keep + (vu, wu)
+    return p, keep
 
 
 def workspace_size(case, prec: int = F64):

@@ -70,6 +70,9 @@ class Case:
     motion: Optional[Callable[[float], list]] = None  # t -> [(dx,dy,th,ux,uy,om)] per block
     overset: Optional[dict] = None      # {"wrule": 0|1, "overlap": int}
     notes: str = ""
+    # unstructured velocity mesh (2D): (vx_k, vy_k, area_k) of every point;
+    # vx then holds vx_k and vy = [0] so that nvx = nv, nvy = 1
+    dvs: Optional[tuple] = None
 
     @property
     def nvx(self) -> int:
@@ -129,6 +132,33 @@ class Case:
 # --------------------------------------------------------------------------
 # helpers (problem statement only)
 # --------------------------------------------------------------------------
+def polar_dvs(nr: int, nth: int, vmax: float, twist: float = 0.5):
+    """Polar velocity mesh on the disk |v| <= vmax: nr rings of width
+    vmax/nr, nth sectors, a point at the centre of each annular sector
+    (radius (m + 1/2) dr; the sectors of ring m turned by twist * m * dth so
+    that rings do not line up), its area r dr dth as the weight.  Points in
+    ring-major order."""
+    dr, dth = vmax / nr, 2.0 * math.pi / nth
+    vx, vy, w = [], [], []
+    for m in range(nr):
+        r = (m + 0.5) * dr
+        for n in range(nth):
+            th = (n + 0.5 + twist * m) * dth
+            vx.append(r * math.cos(th))
+            vy.append(r * math.sin(th))
+            w.append(r * dr * dth)
+    return np.array(vx), np.array(vy), np.array(w)
+
+
+def with_dvs(case: "Case", dvs) -> "Case":
+    """The case on an unstructured velocity mesh dvs = (vx_k, vy_k, area_k)."""
+    case.dvs = tuple(np.asarray(a, dtype=np.float64) for a in dvs)
+    case.vx = case.dvs[0].copy()
+    case.vy = np.zeros(1)
+    case.name = case.name + f"_dvs{len(case.dvs[0])}"
+    return case
+
+
 def uniform_points(n: int, a: float, b: float) -> np.ndarray:
     if n == 1:
         return np.zeros(1)
@@ -229,9 +259,12 @@ def synthetic_f(case: Case, seed: int = SEED, amp: float = 0.05):
     u = np.zeros((case.ncell, 2))
     u[:, :case.dim] = W[:, 1:1 + case.dim] / rho[:, None]
     rt = (W[:, -1] - 0.5 * rho * np.sum(u ** 2, 1)) / (1.5 * rho)
-    VX, VY = np.meshgrid(case.vx, case.vy if case.dim == 2 else np.zeros(1))
-    vx = VX.ravel()[None, :]
-    vy = VY.ravel()[None, :]
+    if case.dvs is not None:
+        vx, vy = case.dvs[0][None, :], case.dvs[1][None, :]
+    else:
+        VX, VY = np.meshgrid(case.vx, case.vy if case.dim == 2 else np.zeros(1))
+        vx = VX.ravel()[None, :]
+        vy = VY.ravel()[None, :]
     a1 = rng.uniform(-1, 1, size=(case.ncell, 1))
     a2 = rng.uniform(-1, 1, size=(case.ncell, 1))
     nxi = 3 - case.dim
