@@ -65,7 +65,14 @@ using ::pow;
 // ------------------------------------------------------------------------
 // small helpers
 // ------------------------------------------------------------------------
-__device__ __forceinline__ void atomic_add(double* p, double v) {
+// scatter update.  The kernels that scatter run over one colour of a
+// write-disjoint colouring of their items at a time (faces, cells or donor
+// rows), so no two threads of a launch update one address, and one thread's
+// updates of an address take effect in program order: every sum is formed
+// in an order fixed by the colouring, independent of scheduling.  The
+// update is issued as an atomic add without return only so that the thread
+// does not wait for the old value.
+__device__ __forceinline__ void acc_add(double* p, double v) {
   if (v != 0.0) unsafeAtomicAdd(p, v);
 }
 
@@ -299,7 +306,7 @@ __device__ __forceinline__ double nbval(const double* f, const double* finf, int
 
 // reconstructed value and physical slope of f at velocity k on the side of
 // cell c whose face offset is (dx, dy); with bars (vb, gxb, gyb) the
-// reverse is scattered into fb (atomic)
+// reverse is scattered into fb
 struct SideK {
   double v, gx, gy;
 };
@@ -324,8 +331,8 @@ __device__ inline SideK side_val(const Dev& g, const double* f, const double* fi
 }
 
 __device__ __forceinline__ void scatter_code(double* fb, int code, int c, int nv, int k, double v) {
-  if (code >= 0) atomic_add(fb + (size_t)code * nv + k, v);
-  else if (code == kNbCopy) atomic_add(fb + (size_t)c * nv + k, v);
+  if (code >= 0) acc_add(fb + (size_t)code * nv + k, v);
+  else if (code == kNbCopy) acc_add(fb + (size_t)c * nv + k, v);
 }
 
 __device__ inline void side_rev(const Dev& g, const double* f, const double* finf, int c, double dx, double dy,
@@ -348,7 +355,7 @@ __device__ inline void side_rev(const Dev& g, const double* f, const double* fin
     scatter_code(fbar, lo, c, g.nv, k, sb * dl);
     scatter_code(fbar, hi, c, g.nv, k, sb * dh);
   }
-  atomic_add(fbar + (size_t)c * g.nv + k, own);
+  acc_add(fbar + (size_t)c * g.nv + k, own);
 }
 
 // side data of face f at velocity k: cell code, centroid-to-face offset
@@ -375,7 +382,7 @@ __device__ inline SideK side_any(const Dev& g, const double* f, const double* fi
 __device__ inline void side_any_rev(const Dev& g, const double* f, const double* finf, int code, int inner,
                                     double dx, double dy, int k, double vb, double gxb, double gyb, double* fbar) {
   if (code >= 0) side_rev(g, f, finf, code, dx, dy, k, vb, gxb, gyb, fbar);
-  else if (code == kNbCopy) atomic_add(fbar + (size_t)inner * g.nv + k, vb);
+  else if (code == kNbCopy) acc_add(fbar + (size_t)inner * g.nv + k, vb);
 }
 
 // reconstruction with the partials of its two limited index slopes kept,
@@ -410,7 +417,7 @@ __device__ __forceinline__ SideD side_val_d(const Dev& g, const double* f, const
 __device__ __forceinline__ void side_rev_d(const Dev& g, const SideD& s, int code, int inner, double dx, double dy,
                                            int k, double vb, double gxb, double gyb, double* fbar) {
   if (code < 0) {
-    if (code == kNbCopy) atomic_add(fbar + (size_t)inner * g.nv + k, vb);
+    if (code == kNbCopy) acc_add(fbar + (size_t)inner * g.nv + k, vb);
     return;
   }
   const int* nb = g.nb + 4 * code;
@@ -423,12 +430,12 @@ __device__ __forceinline__ void side_rev_d(const Dev& g, const SideD& s, int cod
     own += sb[d] * s.p[d][1];
     const int lo = nb[2 * d], hi = nb[2 * d + 1];
     const double a = sb[d] * s.p[d][0], c = sb[d] * s.p[d][2];
-    if (lo >= 0) atomic_add(fbar + (size_t)lo * g.nv + k, a);
+    if (lo >= 0) acc_add(fbar + (size_t)lo * g.nv + k, a);
     else if (lo == kNbCopy) own += a;
-    if (hi >= 0) atomic_add(fbar + (size_t)hi * g.nv + k, c);
+    if (hi >= 0) acc_add(fbar + (size_t)hi * g.nv + k, c);
     else if (hi == kNbCopy) own += c;
   }
-  atomic_add(fbar + (size_t)code * g.nv + k, own);
+  acc_add(fbar + (size_t)code * g.nv + k, own);
 }
 
 // cotangent of the flux F_k (along the face normal) of face f from the
@@ -453,12 +460,39 @@ __device__ inline void flux_bar_k(const Dev& g, const double* fp, const double* 
 }
 
 // ------------------------------------------------------------------------
-// flux reverse, faces between cells (interior and ghost faces): one
-// wavefront per face, lanes over velocities.  The face record lives in LDS
-// (every lane writes the same values and reads back its own writes).
-// Pass 1: W0; pass 2: q0 and the sums of its U-derivative; pass 3: the flux
-// reversed per velocity (its bars of the upwind data scattered at once) with
-// the record bars accumulated; the record Jacobian, one input per lane;
+// the face reverses run one face per block of up to kFaceWaves wavefronts,
+// threads over velocities
+// ------------------------------------------------------------------------
+constexpr int kFaceWaves = 8;
+
+// sum over the block of each thread's v[0..N-1], returned to every thread:
+// the wavefront sums, then those in wavefront order (a fixed order).  Every
+// thread of the block must call it; red holds kFaceWaves * N doubles.
+template <int N>
+__device__ __forceinline__ void block_sum(double* v, double* red) {
+  for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
+  const int nwv = blockDim.x >> 6;
+  if (nwv == 1) return;
+  const int wv = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+    for (int i = 0; i < N; ++i) red[wv * N + i] = v[i];
+  __syncthreads();
+  for (int i = 0; i < N; ++i) {
+    double t = red[i];
+    for (int w = 1; w < nwv; ++w) t += red[w * N + i];
+    v[i] = t;
+  }
+}
+
+// ------------------------------------------------------------------------
+// flux reverse, faces between cells (interior and ghost faces): one block
+// per face, threads over velocities.  The face record lives in LDS (the
+// first wavefront computes it from the block sums).  Pass 1: W0; pass 2:
+// q0 and the sums of its U-derivative; pass 3: the flux reversed per
+// velocity (its bars of the upwind data scattered at once) with the record
+// bars accumulated; the record Jacobian in the first wavefront, one input
+// per lane;
 // pass 4: the moment bars (W0, q0) scattered to both sides.
 // ------------------------------------------------------------------------
 __device__ __forceinline__ void store_rec(Rec& e, double rho, double ux, double uy, double lam, double qx, double qy,
@@ -471,18 +505,20 @@ __device__ __forceinline__ void rec_values(const Dev& g, double dts, const doubl
   face_coeffs(g, dts, x, c);
 }
 
-__global__ __launch_bounds__(256, 2) void k_adj_face(Dev g, double dts, const double* __restrict__ h,
+__global__ __launch_bounds__(64 * kFaceWaves) void k_adj_face(Dev g, const int* __restrict__ items, int nitems, double dts,
+                                                  const double* __restrict__ h,
                                                   const double* __restrict__ b, const double* __restrict__ gW,
                                                   const double* __restrict__ rec,
                                                   const double* __restrict__ Dbh, const double* __restrict__ Dbb,
                                                   const double* __restrict__ Fb, double* __restrict__ hbar,
                                                   double* __restrict__ bbar, double* __restrict__ gWbar,
                                                   double* __restrict__ fbar) {
-  __shared__ Rec srec[4];
-  const int f = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (f >= g.nface) return;
-  Rec& e = srec[threadIdx.x >> 6];
+  __shared__ Rec e;
+  __shared__ double sred[kFaceWaves * kRecBar];
+  __shared__ double sxb[kRecIn];
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  if ((int)blockIdx.x >= nitems) return;
+  const int f = items[blockIdx.x];
   const double* fp = g.fplan + (size_t)f * kFpN;
   if (tab_int(fp[kFpAct]) == 0) return;
   const int L = tab_int(fp[kFpL]), R = tab_int(fp[kFpR]);
@@ -527,7 +563,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_face(Dev g, double dts, const do
     const double sx = fr[R_SX], sy = fr[R_SY];
     double m[13];
     for (int i = 0; i < 13; ++i) m[i] = 0.0;
-    for (int k = lane; k < nv; k += 64) {
+    for (int k = tid; k < nv; k += nt) {
       double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
       double fh, fb;
       upwind(k, wn_exact(vx, vy, ufx, ufy, nx, ny), fh, fb);
@@ -539,7 +575,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_face(Dev g, double dts, const do
       const double b0 = w * fb;
       m[10] += b0; m[11] += b0 * cx; m[12] += b0 * cy;
     }
-    for (int i = 0; i < 13; ++i) m[i] = wave_sum(m[i]);
+    block_sum<13>(m, sred);
     const double M0 = m[0], M1x = m[1], M1y = m[2], Mxx = m[3], Mxy = m[4], Myy = m[5];
     const double Mxxx = m[6], Mxxy = m[7], Mxyy = m[8], Myyy = m[9], B0 = m[10], B1x = m[11], B1y = m[12];
     W0[0] = M0;
@@ -562,8 +598,11 @@ __global__ __launch_bounds__(256, 2) void k_adj_face(Dev g, double dts, const do
     double x[kRecIn], c[kRecOut];
     x[0] = rho; x[1] = ux; x[2] = uy; x[3] = lam;
     grad_in(x);
-    rec_values(g, dts, x, c);
-    store_rec(e, rho, ux, uy, lam, q0x, q0y, c);
+    if (tid < 64) {
+      rec_values(g, dts, x, c);
+      store_rec(e, rho, ux, uy, lam, q0x, q0y, c);
+    }
+    __syncthreads();
   }
   // pass 3: reverse of the flux at every velocity; the bars of the upwind
   // data go to the cells at once, the record bars are accumulated
@@ -571,7 +610,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_face(Dev g, double dts, const do
   for (int i = 0; i < kRecBar; ++i) acc[i] = 0.0;
   double ufb_x = 0.0, ufb_y = 0.0;
   const double* Fbf = Fb + (size_t)f * kNw;
-  for (int k = lane; k < nv; k += 64) {
+  for (int k = tid; k < nv; k += nt) {
     double vx = g.vx[k], vy = g.vy[k];
     double wn = wn_exact(vx, vy, ufx, ufy, nx, ny);
     if (wn == 0.0) continue;
@@ -590,20 +629,26 @@ __global__ __launch_bounds__(256, 2) void k_adj_face(Dev g, double dts, const do
     side_rev_d(g, sh, up, inner, ox, oy, k, fhb, ghb[0], ghb[1], hbar);
     side_rev_d(g, sb, up, inner, ox, oy, k, fbb, gbb[0], gbb[1], bbar);
   }
-  for (int i = 0; i < kRecBar; ++i) acc[i] = wave_sum(acc[i]);
-  ufb_x = wave_sum(ufb_x) - acc[23];
-  ufb_y = wave_sum(ufb_y) - acc[24];
+  block_sum<kRecBar>(acc, sred);
+  {
+    double v[2] = {ufb_x, ufb_y};
+    block_sum<2>(v, sred);
+    ufb_x = v[0] - acc[23];
+    ufb_y = v[1] - acc[24];
+  }
   // contraction with the record Jacobian: lane j < kRecIn holds input j's bar
   double xb[kRecIn];
-  {
+  if (tid < 64) {
     double x[kRecIn], val[kRecOut], col[kRecOut];
     x[0] = e.rho; x[1] = e.ux; x[2] = e.uy; x[3] = e.lam;
     grad_in(x);
     face_coeffs_lanes(g, dts, x, lane, val, col);
     double inb = 0.0;
     for (int i = 0; i < kRecOut; ++i) inb += acc[6 + i] * col[i];
-    for (int j = 0; j < kRecIn; ++j) xb[j] = lane_read(inb, j);
+    if (lane < kRecIn) sxb[lane] = inb;
   }
+  __syncthreads();
+  for (int j = 0; j < kRecIn; ++j) xb[j] = sxb[j];
   double uxb = acc[1] + xb[1], uyb = acc[2] + xb[2];
   const double qxb = acc[4], qyb = acc[5];
   ufb_x += xb[12];
@@ -614,18 +659,18 @@ __global__ __launch_bounds__(256, 2) void k_adj_face(Dev g, double dts, const do
   double W0b[4] = {0, 0, 0, 0};
   prim_rev(D, kNxi, W0, acc[0] + xb[0], uxb, uyb, acc[3] + xb[3], W0b);
   // gradient bars of the two cells (the face slope is their mean)
-  if (lane < 8) {
+  if (tid < 8) {
     double v = 0.5 * xb[4 + lane];
-    if (L >= 0) atomic_add(gWbar + (size_t)L * 8 + lane, v);
-    if (R >= 0) atomic_add(gWbar + (size_t)R * 8 + lane, v);
+    if (L >= 0) acc_add(gWbar + (size_t)L * 8 + lane, v);
+    if (R >= 0) acc_add(gWbar + (size_t)R * 8 + lane, v);
   }
-  if (lane == 0) {
+  if (tid == 0) {
     fbar[(size_t)f * 5 + 0] += ufb_x;
     fbar[(size_t)f * 5 + 1] += ufb_y;
   }
   // pass 4: the moment bars of the upwind data (W0, q0), to both sides
   const double ux0 = e.ux, uy0 = e.uy;
-  for (int k = lane; k < nv; k += 64) {
+  for (int k = tid; k < nv; k += nt) {
     double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
     double wn = wn_exact(vx, vy, ufx, ufy, nx, ny);
     double cx = vx - ux0, cy = (D == 2) ? vy - uy0 : 0.0;
@@ -655,7 +700,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_face(Dev g, double dts, const do
 // incident part reversed, its bars scattered at once, record bars
 // accumulated; then the record Jacobian and the incident state.
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const double* __restrict__ h,
+__global__ __launch_bounds__(64 * kFaceWaves) void k_adj_wall(Dev g, const int* __restrict__ items, int nitems, double dts,
+                                                  const double* __restrict__ h,
                                                   const double* __restrict__ b, const double* __restrict__ W,
                                                   const double* __restrict__ q, const double* __restrict__ gW,
                                                   const double* __restrict__ Dbh, const double* __restrict__ Dbb,
@@ -663,23 +709,24 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
                                                   double* __restrict__ bbar, double* __restrict__ Wbar,
                                                   double* __restrict__ qbar, double* __restrict__ gWbar,
                                                   double* __restrict__ fbar) {
-  __shared__ Rec srec[4];
-  const int f = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (f >= g.nface) return;
-  Rec& e = srec[threadIdx.x >> 6];
+  __shared__ Rec e;
+  __shared__ double sred[kFaceWaves * kRecBar];
+  __shared__ double sxb[kRecIn];
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  if ((int)blockIdx.x >= nitems) return;
+  const int f = items[blockIdx.x];
   const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
   if (L != kNbWall && R != kNbWall) return;
   const int c = (L == kNbWall) ? R : L;
   if (c < 0 || g.type[c] != 1) return;
   const int D = kD, nw = kNw, nv = g.nv, nxi = kNxi;
-  int slot = 0;
-  for (int s = 0; s < 4; ++s) if (g.cf[4 * c + s] == f) slot = s;
+  int fs = 0;
+  for (int s = 0; s < 4; ++s) if (g.cf[4 * c + s] == f) fs = s;
   const double* fg = g.fgeo + (size_t)f * 8;
   const double sgn = (R == kNbWall) ? 1.0 : -1.0;
   const double nwx = sgn * fg[0], nwy = sgn * fg[1], ufx = fg[3], ufy = fg[4];
   const double vwx = fg[5], vwy = fg[6], rtw = fg[7];
-  const double dx = g.cdx[8 * c + 2 * slot], dy = g.cdx[8 * c + 2 * slot + 1];
+  const double dx = g.cdx[8 * c + 2 * fs], dy = g.cdx[8 * c + 2 * fs + 1];
   const double* hinf = (const double*)g.finf_h;
   const double* binf = (const double*)g.finf_b;
   // incident state: one-sided extrapolation of W, cell state if unphysical
@@ -697,15 +744,18 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
   {
     double x[kRecIn], cc[kRecOut];
     rec_in(x);
-    rec_values(g, dts, x, cc);
-    store_rec(e, x[0], x[1], x[2], x[3], q[(size_t)c * D], (D == 2) ? q[(size_t)c * D + 1] : 0.0, cc);
+    if (tid < 64) {
+      rec_values(g, dts, x, cc);
+      store_rec(e, x[0], x[1], x[2], x[3], q[(size_t)c * D], (D == 2) ? q[(size_t)c * D + 1] : 0.0, cc);
+    }
+    __syncthreads();
   }
   const double lamw = 0.5 / rtw;
   const double nrm = pow(lamw / kPi, 0.5 * D);
   const double betaw = (double)nxi / (2.0 * lamw);
   // pass 1: incident mass flux and the wall normaliser
   double num = 0.0, den = 0.0;
-  for (int k = lane; k < nv; k += 64) {
+  for (int k = tid; k < nv; k += nt) {
     double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
     double wn = wn_exact(vx, vy, ufx, ufy, nwx, nwy);
     if (wn > 0.0) {
@@ -719,15 +769,19 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
       den += w * wn * nrm * exp(-lamw * (cx * cx + cy * cy));
     }
   }
-  num = wave_sum(num);
-  den = wave_sum(den);
+  {
+    double v[2] = {num, den};
+    block_sum<2>(v, sred);
+    num = v[0];
+    den = v[1];
+  }
   const double rhow = -num / (dts * den);
   const double* Fbf = Fb + (size_t)f * nw;
   const double* fpw = g.fplan + (size_t)f * kFpN;
   // pass 2: the reflected part (wn < 0) and the normaliser's derivatives
   double rhowb = 0, lamwb = 0, vwbx = 0, vwby = 0, ufbx = 0, ufby = 0;
   double dden_l = 0, dden_vx = 0, dden_vy = 0, dden_u = 0;
-  for (int k = lane; k < nv; k += 64) {
+  for (int k = tid; k < nv; k += nt) {
     double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
     double wn = wn_exact(vx, vy, ufx, ufy, nwx, nwy);
     if (!(wn < 0.0)) continue;
@@ -750,10 +804,14 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
     dden_vy += w * wn * Ek * 2.0 * lamw * cy;
     dden_u += w * Ek;
   }
-  rhowb = wave_sum(rhowb); lamwb = wave_sum(lamwb);
-  vwbx = wave_sum(vwbx); vwby = wave_sum(vwby);
-  ufbx = wave_sum(ufbx); ufby = wave_sum(ufby);
-  dden_l = wave_sum(dden_l); dden_vx = wave_sum(dden_vx); dden_vy = wave_sum(dden_vy); dden_u = wave_sum(dden_u);
+  {
+    double v[10] = {rhowb, lamwb, vwbx, vwby, ufbx, ufby, dden_l, dden_vx, dden_vy, dden_u};
+    block_sum<10>(v, sred);
+    rhowb = v[0]; lamwb = v[1];
+    vwbx = v[2]; vwby = v[3];
+    ufbx = v[4]; ufby = v[5];
+    dden_l = v[6]; dden_vx = v[7]; dden_vy = v[8]; dden_u = v[9];
+  }
   const double numb = -rhowb / (dts * den);
   const double denb = -rhowb * rhow / den;
   lamwb += denb * dden_l;
@@ -766,7 +824,7 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
   double acc[kRecBar];
   for (int i = 0; i < kRecBar; ++i) acc[i] = 0.0;
   double ufb2x = 0, ufb2y = 0;
-  for (int k = lane; k < nv; k += 64) {
+  for (int k = tid; k < nv; k += nt) {
     double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
     double wn = wn_exact(vx, vy, ufx, ufy, nwx, nwy);
     if (!(wn > 0.0)) continue;
@@ -784,39 +842,45 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
     side_rev_d(g, sh, c, c, dx, dy, k, fhb, ghb[0], ghb[1], hbar);
     side_rev_d(g, sb, c, c, dx, dy, k, fbb, gbb[0], gbb[1], bbar);
   }
-  for (int i = 0; i < kRecBar; ++i) acc[i] = wave_sum(acc[i]);
-  ufbx += wave_sum(ufb2x) - acc[23];
-  ufby += wave_sum(ufb2y) - acc[24];
-  double xb[kRecIn];
+  block_sum<kRecBar>(acc, sred);
   {
+    double v[2] = {ufb2x, ufb2y};
+    block_sum<2>(v, sred);
+    ufbx += v[0] - acc[23];
+    ufby += v[1] - acc[24];
+  }
+  double xb[kRecIn];
+  if (tid < 64) {
     double x[kRecIn], val[kRecOut], col[kRecOut];
     rec_in(x);
     face_coeffs_lanes(g, dts, x, lane, val, col);
     double inb = 0.0;
     for (int i = 0; i < kRecOut; ++i) inb += acc[6 + i] * col[i];
-    for (int j = 0; j < kRecIn; ++j) xb[j] = lane_read(inb, j);
+    if (lane < kRecIn) sxb[lane] = inb;
   }
+  __syncthreads();
+  for (int j = 0; j < kRecIn; ++j) xb[j] = sxb[j];
   ufbx += xb[12];
   ufby += xb[13];
   double Winb[4] = {0, 0, 0, 0};
   prim_rev(D, nxi, Win, acc[0] + xb[0], acc[1] + xb[1], acc[2] + xb[2], acc[3] + xb[3], Winb);
-  if (lane == 0) {
-    atomic_add(qbar + (size_t)c * D, acc[4]);
-    if (D == 2) atomic_add(qbar + (size_t)c * D + 1, acc[5]);
-    for (int m = 0; m < nw; ++m) atomic_add(Wbar + (size_t)c * nw + m, Winb[m]);
+  if (tid == 0) {
+    acc_add(qbar + (size_t)c * D, acc[4]);
+    if (D == 2) acc_add(qbar + (size_t)c * D + 1, acc[5]);
+    for (int m = 0; m < nw; ++m) acc_add(Wbar + (size_t)c * nw + m, Winb[m]);
     double* o = fbar + (size_t)f * 5;
     o[0] += ufbx; o[1] += ufby;
     o[2] += vwbx; o[3] += vwby;
     o[4] += -lamwb * 2.0 * lamw * lamw;  // lam_w = 1/(2 RT_w)
   }
-  if (lane < 8) {
+  if (tid < 8) {
     // the slope input and, through the extrapolation, the incident state
     double v = xb[4 + lane];
     if (extrap) {
       if (lane < nw) v += Winb[lane] * dx;
       else if (lane >= nw && lane < 2 * nw) v += Winb[lane - nw] * dy;
     }
-    atomic_add(gWbar + (size_t)c * 8 + lane, v);
+    acc_add(gWbar + (size_t)c * 8 + lane, v);
   }
 }
 
@@ -824,10 +888,12 @@ __global__ __launch_bounds__(256) void k_adj_wall(Dev g, double dts, const doubl
 // limited W gradients (reconstruction of W for the slopes and the wall
 // incident state): gW bars to W bars, one thread per cell
 // ------------------------------------------------------------------------
-__global__ void k_adj_gradW(Dev g, const double* __restrict__ W, const double* __restrict__ gWbar,
-                            double* __restrict__ Wbar) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.ncell || g.type[c] == 0) return;
+__global__ void k_adj_gradW(Dev g, const int* __restrict__ items, int nitems, const double* __restrict__ W,
+                            const double* __restrict__ gWbar, double* __restrict__ Wbar) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nitems) return;
+  const int c = items[slot];
+  if (g.type[c] == 0) return;
   const int nw = kNw;
   const double* gb = gWbar + (size_t)c * 8;
   const double* G = g.G + 4 * c;
@@ -850,12 +916,12 @@ __global__ void k_adj_gradW(Dev g, const double* __restrict__ W, const double* _
       double dl, d0, dh;
       lim_d(lo, hi, val(lo), v0, val(hi), dl, d0, dh);
       own += sb * d0;
-      if (lo >= 0) atomic_add(Wbar + (size_t)lo * nw + m, sb * dl);
+      if (lo >= 0) acc_add(Wbar + (size_t)lo * nw + m, sb * dl);
       else if (lo == kNbCopy) own += sb * dl;
-      if (hi >= 0) atomic_add(Wbar + (size_t)hi * nw + m, sb * dh);
+      if (hi >= 0) acc_add(Wbar + (size_t)hi * nw + m, sb * dh);
       else if (hi == kNbCopy) own += sb * dh;
     }
-    atomic_add(Wbar + (size_t)c * nw + m, own);
+    acc_add(Wbar + (size_t)c * nw + m, own);
   }
 }
 
@@ -995,7 +1061,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_micro_coef(
     const double* __restrict__ yh, const double* __restrict__ yb, const double* __restrict__ rh,
     const double* __restrict__ rb, const double* __restrict__ xbh, const double* __restrict__ xbb,
     double* __restrict__ hbar, double* __restrict__ bbar, double* __restrict__ Shb, double* __restrict__ Sbb,
-    double* __restrict__ Dbh, double* __restrict__ Dbb, double* __restrict__ Wpb, double* __restrict__ fbar) {
+    double* __restrict__ Dbh, double* __restrict__ Dbb, double* __restrict__ Wpb, double* __restrict__ sbar) {
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= g.ncell) return;
@@ -1081,15 +1147,33 @@ __global__ __launch_bounds__(256, 2) void k_adj_micro_coef(
   prim_rev(D, kNxi, Wp + (size_t)c * nw, a[0], uxb, uyb, a[3], Wl);
   if (lane < nw) Wpb[(size_t)c * nw + lane] += Wl[lane];
   // face coefficient a = S/(2|Omega|) (v - U_f).n_out = A vx + B vy - C:
-  // its U_f bar is -(A, B) a_bar
+  // its U_f bar is -(A, B) a_bar, kept per (cell, slot) and added to the
+  // faces by k_adj_slot_fold
   if (lane < ns) {
     const int s = lane;
-    const int f = g.cf[4 * c + s];
-    if (f >= 0) {
-      atomic_add(fbar + (size_t)f * 5 + 0, -mg[3 * s] * ab[s]);
-      atomic_add(fbar + (size_t)f * 5 + 1, -mg[3 * s + 1] * ab[s]);
-    }
+    sbar[(size_t)(4 * c + s) * 2 + 0] = -mg[3 * s] * ab[s];
+    sbar[(size_t)(4 * c + s) * 2 + 1] = -mg[3 * s + 1] * ab[s];
   }
+}
+
+// per face: the U_f bars of the micro coefficients of its field cells, the
+// left cell's before the right one's
+__global__ void k_adj_slot_fold(Dev g, const double* __restrict__ sbar, double* __restrict__ fbar) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= g.nface) return;
+  const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
+  double ax = 0.0, ay = 0.0;
+  for (int side = 0; side < 2; ++side) {
+    const int c = side ? R : L;
+    if (c < 0 || (side == 1 && R == L) || g.type[c] != 1) continue;
+    for (int s = 0; s < 2 * kD; ++s)
+      if (g.cf[4 * c + s] == f) {
+        ax += sbar[(size_t)(4 * c + s) * 2 + 0];
+        ay += sbar[(size_t)(4 * c + s) * 2 + 1];
+      }
+  }
+  fbar[(size_t)f * 5 + 0] += ax;
+  fbar[(size_t)f * 5 + 1] += ay;
 }
 
 // ------------------------------------------------------------------------
@@ -1244,39 +1328,52 @@ __global__ __launch_bounds__(512) void k_adj_macro_sweep(
   }
 }
 
-// residual and diagonal bars to W, Wn, F, Fn and Gamma; one thread per cell
-__global__ void k_adj_macro_post(Dev g, double dt, const double* __restrict__ Rb, const double* __restrict__ Dgb,
-                                 double* __restrict__ Wbar, double* __restrict__ Wnb, double* __restrict__ Fbar,
-                                 double* __restrict__ Fnb, double* __restrict__ gamb) {
+// residual bars to W and Wn; one thread per cell
+__global__ void k_adj_macro_post(Dev g, double dt, const double* __restrict__ Rb, double* __restrict__ Wbar,
+                                 double* __restrict__ Wnb) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.ncell) return;
   const int nw = kNw;
   if (g.type[c] != 1) return;
-  const double ivol = 1.0 / g.vol[c];
   for (int m = 0; m < nw; ++m) {
     double r = Rb[(size_t)c * nw + m];
     Wbar[(size_t)c * nw + m] -= r / dt;
     Wnb[(size_t)c * nw + m] += r / dt;
   }
-  for (int s = 0; s < 2 * kD; ++s) {
-    int f = g.cf[4 * c + s];
-    if (f < 0) continue;
-    const double S = g.fgeo[(size_t)f * 8 + 2];
-    const double sig = (s & 1) ? 1.0 : -1.0;
-    for (int m = 0; m < nw; ++m) {
-      double v = -0.5 * ivol * sig * S * Rb[(size_t)c * nw + m];
-      atomic_add(Fbar + (size_t)f * nw + m, v);
-      atomic_add(Fnb + (size_t)f * nw + m, v);
+}
+
+// residual and diagonal bars to the faces' F, Fn and Gamma: one thread per
+// face, its field cells in the order left, right
+__global__ void k_adj_macro_face(Dev g, const double* __restrict__ Rb, const double* __restrict__ Dgb,
+                                 double* __restrict__ Fbar, double* __restrict__ Fnb, double* __restrict__ gamb) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= g.nface) return;
+  const int nw = kNw;
+  const int L = g.fcell[2 * f], R = g.fcell[2 * f + 1];
+  const double S = g.fgeo[(size_t)f * 8 + 2];
+  for (int side = 0; side < 2; ++side) {
+    const int c = side ? R : L;
+    if (c < 0 || (side == 1 && R == L) || g.type[c] != 1) continue;
+    const double ivol = 1.0 / g.vol[c];
+    for (int s = 0; s < 2 * kD; ++s) {
+      if (g.cf[4 * c + s] != f) continue;
+      const double sig = (s & 1) ? 1.0 : -1.0;
+      for (int m = 0; m < nw; ++m) {
+        const double v = -0.5 * ivol * sig * S * Rb[(size_t)c * nw + m];
+        acc_add(Fbar + (size_t)f * nw + m, v);
+        acc_add(Fnb + (size_t)f * nw + m, v);
+      }
+      acc_add(gamb + f, 0.25 * ivol * S * Dgb[c]);
     }
-    atomic_add(gamb + f, 0.25 * ivol * S * Dgb[c]);
   }
 }
 
 // spectral radius Gamma of a face reversed: one thread per face
-__global__ void k_adj_gamma(Dev g, const double* __restrict__ W, const double* __restrict__ gamb,
-                            double* __restrict__ Wbar, double* __restrict__ fbar) {
-  int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= g.nface) return;
+__global__ void k_adj_gamma(Dev g, const int* __restrict__ items, int nitems, const double* __restrict__ W,
+                            const double* __restrict__ gamb, double* __restrict__ Wbar, double* __restrict__ fbar) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nitems) return;
+  const int f = items[slot];
   const double gb = gamb[f];
   if (gb == 0.0) return;
   const int D = kD, nw = kNw;
@@ -1296,7 +1393,7 @@ __global__ void k_adj_gamma(Dev g, const double* __restrict__ W, const double* _
     double lb = -wgt_a * gb * a / (2.0 * lam);
     double Wl[4] = {0, 0, 0, 0};
     prim_rev(D, kNxi, w, 0.0, wgt_u * thb * nx, wgt_u * thb * ny, lb, Wl);
-    for (int m = 0; m < nw; ++m) atomic_add(Wbar + (size_t)tgt * nw + m, Wl[m]);
+    for (int m = 0; m < nw; ++m) acc_add(Wbar + (size_t)tgt * nw + m, Wl[m]);
   };
   double thv;
   if (L == kNbWall || R == kNbWall) {
@@ -1380,10 +1477,10 @@ __global__ __launch_bounds__(256) void k_adj_source(Dev g, double dt, const doub
   if (g.mu_ref > 0.0) { a[0] += itb * dr; a[3] += itb * dl; }
   double Wl[4] = {0, 0, 0, 0};
   prim_rev(D, kNxi, W + (size_t)c * nw, a[0], a[1], a[2], a[3], Wl);
-  if (lane < nw) atomic_add(Wbar + (size_t)c * nw + lane, Wl[lane]);
+  if (lane < nw) acc_add(Wbar + (size_t)c * nw + lane, Wl[lane]);
   if (lane == 0) {
-    atomic_add(qbar + (size_t)c * D, a[4]);
-    if (D == 2) atomic_add(qbar + (size_t)c * D + 1, a[5]);
+    acc_add(qbar + (size_t)c * D, a[4]);
+    if (D == 2) acc_add(qbar + (size_t)c * D + 1, a[5]);
   }
 }
 
@@ -1392,34 +1489,35 @@ __global__ __launch_bounds__(256) void k_adj_source(Dev g, double dt, const doub
 // cells move to their donors and the targets' bars become zero; one
 // wavefront per row (donors are never targets of the same call)
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_adj_interp(Dev g, int nrow, const int* __restrict__ rec,
-                                                    const int* __restrict__ ptr, const int* __restrict__ don,
-                                                    const double* __restrict__ wt, double* __restrict__ hbar,
-                                                    double* __restrict__ bbar, double* __restrict__ Wbar,
-                                                    double* __restrict__ qbar) {
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ __launch_bounds__(256) void k_adj_interp(Dev g, const int* __restrict__ items, int nitems,
+                                                    const int* __restrict__ rec, const int* __restrict__ ptr,
+                                                    const int* __restrict__ don, const double* __restrict__ wt,
+                                                    double* __restrict__ hbar, double* __restrict__ bbar,
+                                                    double* __restrict__ Wbar, double* __restrict__ qbar) {
+  const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (r >= nrow) return;
+  if (slot >= nitems) return;
+  const int r = items[slot];
   const int c = rec[r], p0 = ptr[r], p1 = ptr[r + 1];
   for (int k = lane; k < g.nv; k += 64) {
     const size_t o = (size_t)c * g.nv + k;
     const double vh = hbar[o], vb = bbar[o];
     for (int p = p0; p < p1; ++p) {
-      atomic_add(hbar + (size_t)don[p] * g.nv + k, wt[p] * vh);
-      atomic_add(bbar + (size_t)don[p] * g.nv + k, wt[p] * vb);
+      acc_add(hbar + (size_t)don[p] * g.nv + k, wt[p] * vh);
+      acc_add(bbar + (size_t)don[p] * g.nv + k, wt[p] * vb);
     }
     hbar[o] = 0.0;
     bbar[o] = 0.0;
   }
   if (lane < kNw) {
     const double v = Wbar[(size_t)c * kNw + lane];
-    for (int p = p0; p < p1; ++p) atomic_add(Wbar + (size_t)don[p] * kNw + lane, wt[p] * v);
+    for (int p = p0; p < p1; ++p) acc_add(Wbar + (size_t)don[p] * kNw + lane, wt[p] * v);
     Wbar[(size_t)c * kNw + lane] = 0.0;
   }
   if (lane >= 8 && lane < 8 + kD) {
     const int m = lane - 8;
     const double v = qbar[(size_t)c * kD + m];
-    for (int p = p0; p < p1; ++p) atomic_add(qbar + (size_t)don[p] * kD + m, wt[p] * v);
+    for (int p = p0; p < p1; ++p) acc_add(qbar + (size_t)don[p] * kD + m, wt[p] * v);
     qbar[(size_t)c * kD + m] = 0.0;
   }
 }
@@ -1429,16 +1527,38 @@ __global__ __launch_bounds__(256) void k_adj_interp(Dev g, int nrow, const int* 
 // ------------------------------------------------------------------------
 static inline unsigned nblk(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
-void adj_flux(const Dev& g, double dts, const double* h, const double* b, const double* W, const double* q,
-              const double* gW, const double* rec, const double* Dbh, const double* Dbb, const double* Fb,
-              double* hbar, double* bbar, double* Wbar, double* qbar, double* gWbar, double* fbar, hipStream_t st) {
-  if (g.nface > 0) {
-    hipLaunchKernelGGL(k_adj_face, dim3(nblk(g.nface, 4)), dim3(256), 0, st, g, dts, h, b, gW, rec, Dbh, Dbb, Fb,
-                       hbar, bbar, gWbar, fbar);
-    hipLaunchKernelGGL(k_adj_wall, dim3(nblk(g.nface, 4)), dim3(256), 0, st, g, dts, h, b, W, q, gW, Dbh, Dbb, Fb,
-                       hbar, bbar, Wbar, qbar, gWbar, fbar);
+// one launch per colour of an order; `wave` items per block of `threads`
+template <typename F>
+static void per_colour(const Order& o, int wave, unsigned threads, F launch) {
+  for (int i = 0; i < o.ncolour; ++i) {
+    const int n = o.off[i + 1] - o.off[i];
+    if (n > 0) launch(dim3(nblk(n, wave)), dim3(threads), o.items + o.off[i], n);
   }
-  hipLaunchKernelGGL(k_adj_gradW, dim3(nblk(g.ncell, 128)), dim3(128), 0, st, g, W, gWbar, Wbar);
+}
+
+// threads of a face block: a wavefront per 512 velocities, at most
+// kFaceWaves
+static unsigned face_threads(int nv) {
+  const int w = std::min(kFaceWaves, std::max(1, (nv + 511) / 512));
+  return 64u * (unsigned)w;
+}
+
+void adj_flux(const Dev& g, const Order& faces, const Order& walls, const Order& cells, double dts,
+              const double* h, const double* b, const double* W, const double* q, const double* gW,
+              const double* rec, const double* Dbh, const double* Dbb, const double* Fb, double* hbar, double* bbar,
+              double* Wbar, double* qbar, double* gWbar, double* fbar, hipStream_t st) {
+  const unsigned nt = face_threads(g.nv);
+  per_colour(faces, 1, nt, [&](dim3 gr, dim3 bl, const int* it, int n) {
+    hipLaunchKernelGGL(k_adj_face, gr, bl, 0, st, g, it, n, dts, h, b, gW, rec, Dbh, Dbb, Fb, hbar, bbar, gWbar,
+                       fbar);
+  });
+  per_colour(walls, 1, nt, [&](dim3 gr, dim3 bl, const int* it, int n) {
+    hipLaunchKernelGGL(k_adj_wall, gr, bl, 0, st, g, it, n, dts, h, b, W, q, gW, Dbh, Dbb, Fb, hbar, bbar, Wbar,
+                       qbar, gWbar, fbar);
+  });
+  per_colour(cells, 128, 128, [&](dim3 gr, dim3 bl, const int* it, int n) {
+    hipLaunchKernelGGL(k_adj_gradW, gr, bl, 0, st, g, it, n, W, gWbar, Wbar);
+  });
 }
 
 void adj_step7(const Dev& g, const double* h1, const double* b1, const double* W1, const double* Wp,
@@ -1451,28 +1571,34 @@ void adj_micro(const Dev& g, const int* binfo, int nblock, double dt, const doub
                const double* h0, const double* b0, const double* h1, const double* b1, const double* xsh,
                const double* xsb, const double* xbh, const double* xbb, double* yh, double* yb, double* rh,
                double* rb, double* hbar, double* bbar, double* Shb, double* Sbb, double* Dbh, double* Dbb,
-               double* Wpb, double* fbar, hipStream_t st) {
+               double* Wpb, double* sbar, double* fbar, hipStream_t st) {
   dim3 grid(nblock, nblk(g.nv, 16));
   hipLaunchKernelGGL(k_adj_micro_sweep<0>, grid, dim3(1024), 0, st, g, binfo, crec, xbh, xbb, yh, yb);
   hipLaunchKernelGGL(k_adj_micro_sweep<1>, grid, dim3(1024), 0, st, g, binfo, crec, (const double*)yh,
                      (const double*)yb, rh, rb);
   hipLaunchKernelGGL(k_adj_micro_coef, dim3(nblk(g.ncell, 4)), dim3(256), 0, st, g, dt, crec, Wp, h0, b0, h1, b1,
                      xsh, xsb, (const double*)yh, (const double*)yb, (const double*)rh, (const double*)rb, xbh, xbb,
-                     hbar, bbar, Shb, Sbb, Dbh, Dbb, Wpb, fbar);
+                     hbar, bbar, Shb, Sbb, Dbh, Dbb, Wpb, sbar);
+  if (g.nface > 0)
+    hipLaunchKernelGGL(k_adj_slot_fold, dim3(nblk(g.nface, 128)), dim3(128), 0, st, g, (const double*)sbar, fbar);
 }
 
-void adj_macro(const Dev& g, const int* binfo, int nblock, double dt, const double* W, const double* dWs,
-               const double* dW, const double* gam, const double* Wpb, double* dWb, double* abar, double* bbarm,
-               double* dWsb, double* Rb, double* Dgb, double* gamb, double* Wbar, double* Wnb, double* Fbar,
-               double* Fnb, double* fbar, hipStream_t st) {
+void adj_macro(const Dev& g, const Order& faces, const Order& walls, const int* binfo, int nblock, double dt,
+               const double* W, const double* dWs, const double* dW, const double* gam, const double* Wpb,
+               double* dWb, double* abar, double* bbarm, double* dWsb, double* Rb, double* Dgb, double* gamb,
+               double* Wbar, double* Wnb, double* Fbar, double* Fnb, double* fbar, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_macro_init, dim3(nblk(g.ncell, 128)), dim3(128), 0, st, g, W, dW, Wpb, Wbar, dWb);
   hipLaunchKernelGGL(k_adj_macro_sweep, dim3(nblock), dim3(512), 0, st, g, binfo, dt, W, dWs, dW, gam,
                      (const double*)dWb, abar, bbarm, dWsb, Rb, Dgb, gamb, Wbar, fbar);
-  hipLaunchKernelGGL(k_adj_macro_post, dim3(nblk(g.ncell, 128)), dim3(128), 0, st, g, dt, (const double*)Rb,
-                     (const double*)Dgb, Wbar, Wnb, Fbar, Fnb, gamb);
+  hipLaunchKernelGGL(k_adj_macro_post, dim3(nblk(g.ncell, 128)), dim3(128), 0, st, g, dt, (const double*)Rb, Wbar,
+                     Wnb);
   if (g.nface > 0)
-    hipLaunchKernelGGL(k_adj_gamma, dim3(nblk(g.nface, 128)), dim3(128), 0, st, g, W, (const double*)gamb, Wbar,
-                       fbar);
+    hipLaunchKernelGGL(k_adj_macro_face, dim3(nblk(g.nface, 128)), dim3(128), 0, st, g, (const double*)Rb,
+                       (const double*)Dgb, Fbar, Fnb, gamb);
+  for (const Order* o : {&faces, &walls})
+    per_colour(*o, 128, 128, [&](dim3 gr, dim3 bl, const int* it, int n) {
+      hipLaunchKernelGGL(k_adj_gamma, gr, bl, 0, st, g, it, n, W, (const double*)gamb, Wbar, fbar);
+    });
 }
 
 void adj_source(const Dev& g, double dt, const double* crec, const double* W, const double* h, const double* b,
@@ -1482,11 +1608,11 @@ void adj_source(const Dev& g, double dt, const double* crec, const double* W, co
                      bbar, Dbh, Dbb, Wbar, qbar);
 }
 
-void adj_interp(const Dev& g, int nrow, const int* rec, const int* ptr, const int* don, const double* w,
+void adj_interp(const Dev& g, const Order& rows, const int* rec, const int* ptr, const int* don, const double* w,
                 double* hbar, double* bbar, double* Wbar, double* qbar, hipStream_t st) {
-  if (nrow <= 0) return;
-  hipLaunchKernelGGL(k_adj_interp, dim3(nblk(nrow, 4)), dim3(256), 0, st, g, nrow, rec, ptr, don, w, hbar, bbar,
-                     Wbar, qbar);
+  per_colour(rows, 4, 256, [&](dim3 gr, dim3 bl, const int* it, int n) {
+    hipLaunchKernelGGL(k_adj_interp, gr, bl, 0, st, g, it, n, rec, ptr, don, w, hbar, bbar, Wbar, qbar);
+  });
 }
 
 }  // namespace ugks

@@ -93,6 +93,12 @@ struct ugks_ctx {
   // workspace of the reverse-mode entry points (allocated on first use, or
   // carved from a caller's workspace)
   std::vector<void*> adj;
+  // write-disjoint colourings of the reverse-mode scatters: faces other than
+  // wall faces, cells, receptor rows, refill rows, wall faces (items in that
+  // order in the workspace buffer A_ORD, colour offsets on the host), for
+  // the tables of version `ord_version`
+  long long ord_version = -1;
+  std::vector<int> ord_off[5];
   // scratch: one block, owned (allocated at creation) or the caller's
   void* scratch = nullptr;
   bool own_scratch = true;
@@ -1764,7 +1770,12 @@ enum AdjBuf {
   // [ncell][nw], [ncell][dim]
   A_W0, A_W1, A_Q0, A_Q1, A_WPB, A_DWB, A_ABAR, A_BBAR, A_DWSB, A_RBAR, A_WB, A_QB,
   // others
-  A_DGB, A_GWB, A_GAMB, A_FB, A_FBAR, A_NBUF
+  A_DGB, A_GWB, A_GAMB, A_FB, A_FBAR,
+  // [ncell][4][2]: face-velocity bars of the micro coefficients per cell side
+  A_SLOT,
+  // int32 items of the scatter colourings: every face, every cell, and up
+  // to 2 ncell donor rows (receptor rows and refill rows are cells)
+  A_ORD, A_NBUF
 };
 
 std::vector<size_t> adjoint_counts(const Sizes& z) {
@@ -1779,6 +1790,8 @@ std::vector<size_t> adjoint_counts(const Sizes& z) {
     else if (i == A_GWB) n = 8 * (size_t)z.ncell;
     else if (i == A_GAMB) n = z.nface;
     else if (i == A_FB) n = (size_t)z.nface * z.nw;
+    else if (i == A_SLOT) n = 8 * (size_t)z.ncell;
+    else if (i == A_ORD) n = ((size_t)z.nface + 3 * (size_t)z.ncell + 1) / 2;
     else n = (size_t)z.nface * 5;
     out[i] = n;
   }
@@ -1799,11 +1812,118 @@ int adj_alloc(ugks_ctx* c) {
 
 double* A(ugks_ctx* c, int i) { return (double*)c->adj[i]; }
 
+// Greedy colouring of items by their write sets: the items, in the order
+// given, each take the lowest colour that no earlier item sharing a
+// resource holds.  `res(id, out)` lists an item's resources (ids below
+// nres).  Appends the item ids sorted by colour (in the given order within
+// a colour) to `order` and returns the colour offsets relative to its first
+// entry.
+template <typename R>
+int colour_items(const std::vector<int>& ids, int nres, R res, std::vector<int>& order, std::vector<int>& off) {
+  constexpr int kW = 4;  // up to 256 colours
+  const int n = (int)ids.size();
+  std::vector<uint64_t> used((size_t)nres * kW, 0);
+  std::vector<int> col(n), set;
+  int ncol = 0;
+  for (int i = 0; i < n; ++i) {
+    set.clear();
+    res(ids[i], set);
+    uint64_t busy[kW] = {0, 0, 0, 0};
+    for (int r : set)
+      for (int w = 0; w < kW; ++w) busy[w] |= used[(size_t)r * kW + w];
+    int k = 0;
+    while (k < 64 * kW && ((busy[k >> 6] >> (k & 63)) & 1)) ++k;
+    if (k == 64 * kW) return fail(UGKS_E_UNSUPPORTED, "scatter colouring needs more than 256 colours");
+    col[i] = k;
+    ncol = std::max(ncol, k + 1);
+    for (int r : set) used[(size_t)r * kW + (k >> 6)] |= uint64_t(1) << (k & 63);
+  }
+  off.assign(ncol + 1, 0);
+  for (int i = 0; i < n; ++i) ++off[col[i] + 1];
+  for (int k = 0; k < ncol; ++k) off[k + 1] += off[k];
+  const size_t base = order.size();
+  order.resize(base + n);
+  std::vector<int> pos(off.begin(), off.end() - 1);
+  for (int i = 0; i < n; ++i) order[base + pos[col[i]]++] = ids[i];
+  return UGKS_OK;
+}
+
+std::vector<int> iota_ids(int n) {
+  std::vector<int> v(std::max(n, 0));
+  for (int i = 0; i < n; ++i) v[i] = i;
+  return v;
+}
+
+// the colourings of the reverse-mode scatters for the current tables
+int adj_orders(ugks_ctx* c) {
+  if (c->ord_version == (long long)c->version) return UGKS_OK;
+  const int nc = c->ncell;
+  auto cell_nb = [&](int x, std::vector<int>& out) {
+    out.push_back(x);
+    for (int s = 0; s < 4; ++s)
+      if (c->nb[4 * (size_t)x + s] >= 0) out.push_back(c->nb[4 * (size_t)x + s]);
+  };
+  std::vector<int> order, inner_faces, wall_faces;
+  for (int f = 0; f < c->nface; ++f) {
+    const bool wall = c->fcell[2 * (size_t)f] == kNbWall || c->fcell[2 * (size_t)f + 1] == kNbWall;
+    (wall ? wall_faces : inner_faces).push_back(f);
+  }
+  // faces: the cells whose bars the face reverse (reconstruction of either
+  // side, wall incident state, spectral radius) can update
+  auto face_res = [&](int f, std::vector<int>& out) {
+    const int L = c->fcell[2 * (size_t)f], R = c->fcell[2 * (size_t)f + 1];
+    if (L == kNbWall || R == kNbWall) {
+      const int x = (L == kNbWall) ? R : L;
+      if (x >= 0) cell_nb(x, out);
+      return;
+    }
+    const int inner = (L >= 0) ? L : R;
+    for (int x : {L, R}) {
+      if (x >= 0) cell_nb(x, out);
+      else if (inner >= 0) out.push_back(inner);
+    }
+  };
+  int rc = colour_items(inner_faces, nc, face_res, order, c->ord_off[0]);
+  // cells: the limited W gradients reversed write c and its neighbours
+  if (!rc) rc = colour_items(iota_ids(nc), nc, cell_nb, order, c->ord_off[1]);
+  // donor rows: the target and its donors, receptor rows and refill rows
+  // apart (they are reversed by separate launches)
+  const int nrow = (int)c->h_rec.size();
+  for (int part = 0; part < 2 && !rc; ++part) {
+    const int r0 = part ? c->nrec : 0, n = part ? nrow - c->nrec : c->nrec;
+    rc = colour_items(iota_ids(n), nc, [&](int r, std::vector<int>& out) {
+      out.push_back(c->h_rec[r0 + r]);
+      for (int p = c->h_ptr[r0 + r]; p < c->h_ptr[r0 + r + 1]; ++p) out.push_back(c->h_don[p]);
+    }, order, c->ord_off[2 + part]);
+  }
+  if (!rc) rc = colour_items(wall_faces, nc, face_res, order, c->ord_off[4]);
+  if (rc) return rc;
+  if (order.size() > (size_t)c->nface + 3 * (size_t)c->ncell) return fail(UGKS_E_SHAPE, "donor table larger than 2 ncell rows");
+  // earlier reverse calls, on any stream, may still read the old orders
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(A(c, A_ORD), order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice));
+  c->ord_version = (long long)c->version;
+  return UGKS_OK;
+}
+
+// colouring `k` (0 faces other than wall faces, 1 cells, 2 receptor rows,
+// 3 refill rows, 4 wall faces) as a launch order
+Order order_of(ugks_ctx* c, int k) {
+  size_t base = 0;
+  for (int i = 0; i < k; ++i) base += c->ord_off[i].back();
+  Order o;
+  o.items = (const int*)A(c, A_ORD) + base;
+  o.off = c->ord_off[k].data();
+  o.ncolour = (int)c->ord_off[k].size() - 1;
+  return o;
+}
+
 int adj_check(ugks_ctx* c) {
   if (!c) return fail(UGKS_E_ARG, "null context");
   if (c->prec != UGKS_F64) return fail(UGKS_E_UNSUPPORTED, "the adjoint needs FP64 storage");
   if (c->dim != 2) return fail(UGKS_E_UNSUPPORTED, "the adjoint is built for 2D cases");
-  return adj_alloc(c);
+  if (int rc = adj_alloc(c)) return rc;
+  return adj_orders(c);
 }
 
 int dcopy(void* dst, const void* src, size_t n, hipStream_t st) {
@@ -1826,7 +1946,8 @@ int dcopy_or_zero(void* dst, const void* src, size_t n, hipStream_t st) {
 // (s_gW and s_rec must hold the forward gradients of W0 and face records)
 int flux_reverse(ugks_ctx* c, hipStream_t st) {
   if (int rc = dzero(A(c, A_GWB), 8 * (size_t)c->ncell, st)) return rc;
-  adj_flux(c->dev, c->dts, A(c, A_H0), A(c, A_B0), A(c, A_W0), A(c, A_Q0), (const double*)c->s_gW,
+  adj_flux(c->dev, order_of(c, 0), order_of(c, 4), order_of(c, 1), c->dts, A(c, A_H0), A(c, A_B0), A(c, A_W0), A(c, A_Q0),
+           (const double*)c->s_gW,
            (const double*)c->s_rec, A(c, A_DBH),
            A(c, A_DBB), A(c, A_FB), A(c, A_HB), A(c, A_BB), A(c, A_WB), A(c, A_QB), A(c, A_GWB), A(c, A_FBAR), st);
   HIPCHK(hipGetLastError());
@@ -1841,9 +1962,11 @@ int interp_rows(ugks_ctx* c, int r0, int nrow, double* h, double* b, double* W, 
   return UGKS_OK;
 }
 
-int interp_rows_rev(ugks_ctx* c, int r0, int nrow, hipStream_t st) {
+// rows r0 .. r0 + nrow - 1 reversed: the receptor rows (refill false, r0 =
+// 0) or the refill rows after them
+int interp_rows_rev(ugks_ctx* c, bool refill, int r0, int nrow, hipStream_t st) {
   if (nrow <= 0) return UGKS_OK;
-  adj_interp(c->dev, nrow, (const int*)c->d_rec + r0, (const int*)c->d_ptr + r0, (const int*)c->d_don,
+  adj_interp(c->dev, order_of(c, refill ? 3 : 2), (const int*)c->d_rec + r0, (const int*)c->d_ptr + r0, (const int*)c->d_don,
              (const double*)c->d_w, A(c, A_HB), A(c, A_BB), A(c, A_WB), A(c, A_QB), st);
   HIPCHK(hipGetLastError());
   return UGKS_OK;
@@ -1942,7 +2065,7 @@ int ugks_step_adjoint(ugks_ctx* c, double dt, const void* h, const void* b, cons
   adj_micro(g, (const int*)c->d_binfo, nblock, dt, (const double*)c->s_crec, (const double*)c->s_Wp, A(c, A_H0),
             A(c, A_B0), A(c, A_H1), A(c, A_B1), (const double*)c->s_Dh, (const double*)c->s_Db, A(c, A_XBH),
             A(c, A_XBB), A(c, A_YH), A(c, A_YB), A(c, A_RH), A(c, A_RB), A(c, A_HB), A(c, A_BB), Sh_bar, Sb_bar,
-            A(c, A_DBH), A(c, A_DBB), A(c, A_WPB), A(c, A_FBAR), st);
+            A(c, A_DBH), A(c, A_DBB), A(c, A_WPB), A(c, A_SLOT), A(c, A_FBAR), st);
   HIPCHK(hipGetLastError());
   // macro LU-SGS (Step 4)
   rc = dzero(A(c, A_WB), NW, st);
@@ -1952,14 +2075,14 @@ int ugks_step_adjoint(ugks_ctx* c, double dt, const void* h, const void* b, cons
   if (!rc) rc = dzero(A(c, A_DGB), c->ncell, st);
   if (!rc) rc = dzero(A(c, A_GAMB), c->nface, st);
   if (rc) return rc;
-  adj_macro(g, (const int*)c->d_binfo, nblock, dt, A(c, A_W0), (const double*)c->s_dWs, (const double*)c->s_dW,
+  adj_macro(g, order_of(c, 0), order_of(c, 4), (const int*)c->d_binfo, nblock, dt, A(c, A_W0), (const double*)c->s_dWs, (const double*)c->s_dW,
             (const double*)c->s_gam, A(c, A_WPB), A(c, A_DWB), A(c, A_ABAR), A(c, A_BBAR), A(c, A_DWSB),
             A(c, A_RBAR), A(c, A_DGB), A(c, A_GAMB), A(c, A_WB), Wn_bar, A(c, A_FB), Fn_bar, A(c, A_FBAR), st);
   HIPCHK(hipGetLastError());
   // flux (Step 3) at the interpolated state, then the interpolation
   rc = dzero(A(c, A_QB), NQ, st);
   if (!rc) rc = flux_reverse(c, st);
-  if (!rc) rc = interp_rows_rev(c, 0, c->nrec, st);
+  if (!rc) rc = interp_rows_rev(c, false, 0, c->nrec, st);
   if (!rc) rc = store_bars(c, h_bar, b_bar, W_bar, q_bar, face_bar, st);
   return rc;
 }
@@ -1998,8 +2121,8 @@ int ugks_begin_step_adjoint(ugks_ctx* c, double dt, const void* h, const void* b
              A(c, A_BB), A(c, A_DBH), A(c, A_DBB), A(c, A_WB), A(c, A_QB), st);
   HIPCHK(hipGetLastError());
   rc = flux_reverse(c, st);
-  if (!rc) rc = interp_rows_rev(c, 0, c->nrec, st);
-  if (!rc) rc = interp_rows_rev(c, c->nrec, nref, st);
+  if (!rc) rc = interp_rows_rev(c, false, 0, c->nrec, st);
+  if (!rc) rc = interp_rows_rev(c, true, c->nrec, nref, st);
   if (!rc) rc = store_bars(c, h_bar, b_bar, W_bar, q_bar, face_bar, st);
   return rc;
 }
