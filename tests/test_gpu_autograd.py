@@ -87,12 +87,42 @@ class Run:
             dts, dtp = s.timesteps()
             dt = self.dt_over * dts
             self.dts.append(dts); self.dtps.append(dtp); self.dtk.append(dt)
-            h, b, W, q, F = adjoint.physical_step(s, dt, self.n_inner, h, b, W, q, U, rtw, setup=setup,
-                                                  checkpoint=checkpoint)
-            L = adjoint.wall_loads(s, F)[self.body, list(self.sides)]
+            h, b, W, q, F, L = adjoint.physical_step(s, dt, self.n_inner, h, b, W, q, U, rtw, setup=setup,
+                                                     checkpoint=checkpoint, loads=True)
+            L = L[self.body, list(self.sides)]
             J = J + (self.c[0] * L[:, 3] + self.c[1] * L[:, 0] + self.c[2] * L[:, 1]).sum()
         J = J + (dev(self.yh) * h).sum()
         return J
+
+    def gpu_rollout(self, U, rtw, snapshots, inner_snapshots=None, h0=None, stats=None):
+        """The same objective through one adjoint.rollout node (binomial
+        checkpointing over the physical steps)."""
+        s, case = self.s, self.case
+        s.set_types(np.ones(case.ncell, np.int8))
+        s.set_poses(case.poses(0.0))
+        if case.overset is not None:
+            s.assemble(case.overset["wrule"], case.overset["overlap"])
+        h = dev(self.h0, s.dtype) if h0 is None else h0
+        b, W, q = dev(self.b0, s.dtype), dev(self.W0), dev(self.q0)
+
+        def setup_at(k):
+            if case.motion is None:
+                return None
+
+            def setup(solver):
+                solver.set_poses(case.poses(self.times[k]))
+                if case.overset is not None:
+                    solver.assemble(case.overset["wrule"], case.overset["overlap"])
+            return setup
+        dt_of = lambda solver: self.dt_over * solver.timesteps()[0]
+        steps = [(dt_of, self.n_inner, setup_at(k)) for k in range(self.n_phys)]
+        h, b, W, q, F, Ls = adjoint.rollout(s, steps, h, b, W, q, U, rtw, snapshots=snapshots,
+                                            inner_snapshots=inner_snapshots, stats=stats)
+        J = 0.0
+        for k in range(self.n_phys):
+            L = Ls[k][self.body, list(self.sides)]
+            J = J + (self.c[0] * L[:, 3] + self.c[1] * L[:, 0] + self.c[2] * L[:, 1]).sum()
+        return J + (dev(self.yh) * h).sum()
 
     def oracle(self, U, rtw, dU=None, drt=None, dh0=None):
         """J and its directional derivative from the tangent build, with the
@@ -330,3 +360,58 @@ def test_fp32_storage_gradient(make, body, sides):
     dU = np.zeros((len(case.blocks), 2)); dU[body, 0] = 1.0
     _, Jd = R64.oracle(U, rt, dU=dU)
     _close(Jd, float(g32[0][body, 0]), 1e-4, f"dJ/dU[{body},0] FP32 vs oracle")
+
+
+@pytest.mark.timeout(300)
+def test_rollout_binomial_checkpointing_same_bits():
+    """Six physical steps of the moving overset cylinder (re-assembly at each
+    step) as one rollout node: for every number of kept states (1: each step
+    re-run from the input; 2, 3; 5: each state computed once) and with the
+    inner iterations of a step re-run from Steps 1-2's output (inner
+    snapshots 1), the gradients equal, bit for bit, those of the chain of
+    checkpointed physical steps, and the re-run steps number
+    revolve_cost(6, snapshots)."""
+    case = moving_overset()
+    R = Run(case, n_phys=6, n_inner=2, body=1, sides=(2,))
+    U, rt = _params(R)
+
+    def grads(fn):
+        Ug = U.clone().requires_grad_(True)
+        rtg = rt.clone().requires_grad_(True)
+        h0 = dev(R.h0).requires_grad_(True)
+        J = fn(Ug, rtg, h0)
+        return [float(J)] + [t.detach().clone() for t in torch.autograd.grad(J, [Ug, rtg, h0])]
+
+    ref = grads(lambda u, r, h0: R.gpu(u, r, h0=h0))
+    for snaps, inner in ((1, None), (2, None), (3, 1), (5, None)):
+        stats = {}
+        got = grads(lambda u, r, h0: R.gpu_rollout(u, r, snaps, inner, h0=h0, stats=stats))
+        say("rollout", "snapshots", snaps, "inner", inner, "re-run steps", stats["recomputed_steps"],
+            "J", got[0], "|dJ/dU|", float(got[1].abs().max()))
+        for name, a, b in zip(("U", "RTw", "h0"), ref[1:], got[1:]):
+            d = (a - b).abs().max().item()
+            say("  ", name, "max |difference|", d, "max |gradient|", a.abs().max().item(),
+                "equal" if torch.equal(a, b) else "differ")
+        assert got[0] == ref[0]
+        for a, b in zip(ref[1:], got[1:]):
+            assert torch.equal(a, b)
+        assert stats["recomputed_steps"] == adjoint.revolve_cost(6, snaps)
+
+
+def test_wall_loads_reverse_refuses_another_pose():
+    """adjoint.wall_loads reverses at the solver's current geometry, so it
+    refuses to run after the pose moved (the loads of a moving step come
+    from physical_step(loads=True) or rollout instead)."""
+    case = moving_overset()
+    s = ugks.Solver(case, ugks.F64)
+    s.set_poses(case.poses(0.1))
+    F = torch.ones((s.nface, case.nw), dtype=torch.float64, device="cuda", requires_grad=True)
+    L = adjoint.wall_loads(s, F)
+    s.set_poses(case.poses(0.2))
+    with pytest.raises(ValueError, match="another pose"):
+        L.sum().backward()
+    s.set_poses(case.poses(0.1))
+    L = adjoint.wall_loads(s, F)
+    L.sum().backward()
+    assert float(F.grad.abs().sum()) > 0
+    s.close()
