@@ -387,6 +387,16 @@ int ugks_autotune(ugks_ctx* ctx, double dt, int32_t n_inner, const void* h, cons
 int ugks_set_wall_rt(ugks_ctx* ctx, int32_t blk, int32_t side, double rtw);
 
 /*
+ * Far-field state (Sec. 2.1: far-field sides take the Maxwellian of a given
+ * state as their ghost distribution): winf (host, D + 2 conservative
+ * values rho, rho u, [rho v,] rho E) replaces the state of ugks_problem and
+ * its Maxwellian from the next call on, e.g. to ramp an inflow.  Waits for
+ * the device first.  UGKS_E_ARG for a null pointer, a non-finite value or
+ * a non-positive density or internal energy.
+ */
+int ugks_set_farfield(ugks_ctx* ctx, const double* winf);
+
+/*
  * Rigid velocity (ux, uy) and angular velocity om of block `blk` at the
  * current node positions (the prescribed body motion of Sec. 3): face grid
  * velocities U_f and wall velocities are recomputed; node positions, dt_s and

@@ -36,6 +36,7 @@ def _bind(L, S):
         getattr(L, n).restype = C.c_int
     L.or_set_pose.argtypes = [C.c_void_p, C.c_int] + [S] * 6
     L.or_set_wall_rt.argtypes = [C.c_void_p, C.c_int, C.c_int, S]
+    L.or_set_farfield.argtypes = [C.c_void_p, D]
     L.or_update_geometry.argtypes = [C.c_void_p]
     L.or_dvs.argtypes = [C.c_void_p, D, D, D]
     L.or_nc_weights.argtypes = [C.c_int, S, S, D]
@@ -212,6 +213,13 @@ class Oracle:
     def set_wall_rt(self, blk, side, rtw):
         """RT of the isothermal wall on one block side (scalar or (v, t))."""
         self.L.or_set_wall_rt(self.ptr, int(blk), int(side), self._s(rtw))
+
+    def set_farfield(self, winf):
+        """Far-field conservative state (nw values; held fixed in the tangent
+        build) and its Maxwellian."""
+        w = self._in(np.asarray(winf, dtype=np.float64).reshape(-1)[:self.case.nw].copy())
+        self._keep_farfield = w
+        self.L.or_set_farfield(self.ptr, _d(w))
 
     def dvs(self):
         vx = self._z(self.nv); vy = self._z(self.nv); w = self._z(self.nv)

@@ -474,6 +474,15 @@ void or_set_wall_rt(or_case* c, int b, int side, real rtw) {
   }
 }
 
+/* far-field state W_inf and its Maxwellian (the ghost value of far-field
+   sides, Sec. 2.1) */
+void or_set_farfield(or_case* c, const real* winf) {
+  for (int i = 0; i < c->nw; i++) c->winf[i] = winf[i];
+  real rho, u[2], lam;
+  prim(c, c->winf, &rho, u, &lam);
+  for (int k = 0; k < c->nv; k++) maxw(c, rho, u, lam, c->vk_x[k], c->vk_y[k], &c->finf_h[k], &c->finf_b[k]);
+}
+
 /* rigid motion: x = xc0 + d + R(th)(x0 - xc0); U = u + om x (x - xc0 - d) */
 void or_update_geometry(or_case* c) {
   for (int b = 0; b < c->nblock; b++) {

@@ -76,6 +76,9 @@ void or_set_pose(or_case* c, int blk, real dx, real dy, real th,
 /* wall RT of side `side` (0 i-min, 1 i-max, 2 j-min, 3 j-max) of a wall
    block side, for the faces already built */
 void or_set_wall_rt(or_case* c, int blk, int side, real rtw);
+/* far-field conservative state (nw entries) and its Maxwellian, the value
+   of far-field ghosts from the next step on */
+void or_set_farfield(or_case* c, const real* winf);
 /* node positions, cell and face geometry, face grid velocity at the current
    poses. */
 void or_update_geometry(or_case* c);

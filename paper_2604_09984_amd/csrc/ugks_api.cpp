@@ -529,6 +529,27 @@ void fill_dev(ugks_ctx* c) {
   g.fplan = (const double*)c->d_fplan;
 }
 
+// the far-field Maxwellian of c->winf (ghost value of far-field sides) in
+// storage precision, to the device
+int upload_farfield(ugks_ctx* c) {
+  std::vector<double> fh(c->nv), fb(c->nv);
+  double rho, ux, uy, lam;
+  prim(c, c->winf, rho, ux, uy, lam);
+  double nrm = rho * std::pow(lam / kPi, 0.5 * c->dim);
+  for (int k = 0; k < c->nv; ++k) {
+    double cx = c->vx[k] - ux, cy = (c->dim == 2) ? c->vy[k] - uy : 0.0;
+    fh[k] = nrm * std::exp(-lam * (cx * cx + cy * cy));
+    fb[k] = (double)c->nxi * 0.5 / lam * fh[k];
+  }
+  if (c->prec == UGKS_F64) {
+    int rc = upload(c->d_finf_h, fh);
+    return rc ? rc : upload(c->d_finf_b, fb);
+  }
+  std::vector<float> a(fh.begin(), fh.end()), e(fb.begin(), fb.end());
+  int rc = upload(c->d_finf_h, a);
+  return rc ? rc : upload(c->d_finf_b, e);
+}
+
 void free_all(ugks_ctx* c) {
   void* ps[] = {c->d_vx, c->d_vy, c->d_wk, c->d_vol, c->d_G, c->d_cdx, c->d_dtp, c->d_type, c->d_nb, c->d_cf,
                 c->d_fcell, c->d_fgeo, c->d_fact, c->d_finf_h, c->d_finf_b, c->d_binfo, c->d_mgeo, c->d_rec,
@@ -790,32 +811,13 @@ static int create_ctx(const ugks_problem* p, int device, void* work, size_t work
     binfo[8 * b] = B.ni; binfo[8 * b + 1] = B.nj; binfo[8 * b + 2] = B.cell0;
     binfo[8 * b + 3] = B.bc[0] == UGKS_BC_PERIODIC; binfo[8 * b + 4] = B.bc[2] == UGKS_BC_PERIODIC;
   }
-  // far-field Maxwellian in storage precision
-  std::vector<double> fh(c->nv), fb(c->nv);
-  {
-    double rho, ux, uy, lam;
-    prim(c, c->winf, rho, ux, uy, lam);
-    double nrm = rho * std::pow(lam / kPi, 0.5 * c->dim);
-    for (int k = 0; k < c->nv; ++k) {
-      double cx = c->vx[k] - ux, cy = (c->dim == 2) ? c->vy[k] - uy : 0.0;
-      fh[k] = nrm * std::exp(-lam * (cx * cx + cy * cy));
-      fb[k] = (double)c->nxi * 0.5 / lam * fh[k];
-    }
-  }
   if (!rc) rc = upload(c->d_vx, c->vx);
   if (!rc) rc = upload(c->d_vy, c->vy);
   if (!rc) rc = upload(c->d_wk, c->wk);
   if (!rc) rc = upload(c->d_cf, c->cf);
   if (!rc) rc = upload(c->d_fcell, c->fcell);
   if (!rc) rc = upload(c->d_binfo, binfo);
-  if (!rc) {
-    if (c->prec == UGKS_F64) { rc = upload(c->d_finf_h, fh); if (!rc) rc = upload(c->d_finf_b, fb); }
-    else {
-      std::vector<float> a(fh.begin(), fh.end()), e(fb.begin(), fb.end());
-      rc = upload(c->d_finf_h, a);
-      if (!rc) rc = upload(c->d_finf_b, e);
-    }
-  }
+  if (!rc) rc = upload_farfield(c);
   if (!rc) rc = upload_geometry(c);
   if (!rc) rc = upload_tables(c);
   // face range of each block (faces are numbered block by block)
@@ -928,6 +930,24 @@ int ugks_set_wall_rt(ugks_ctx* c, int32_t blk, int32_t side, double rtw) {
   ++c->version;
   c->blk[blk].rtw[side] = rtw;
   return refresh_frozen_steps(c);
+}
+
+int ugks_set_farfield(ugks_ctx* c, const double* winf) {
+  if (!c || !winf) return fail(UGKS_E_ARG, "null argument");
+  double w[4] = {0, 0, 0, 0};
+  for (int m = 0; m < c->nw; ++m) {
+    if (!std::isfinite(winf[m])) return fail(UGKS_E_ARG, "non-finite far-field state");
+    w[m] = winf[m];
+  }
+  double ke = 0.0;
+  for (int d = 0; d < c->dim; ++d) ke += 0.5 * w[1 + d] * w[1 + d] / w[0];
+  if (!(w[0] > 0.0) || !(w[c->dim + 1] - ke > 0.0)) return fail(UGKS_E_ARG, "far-field density and internal energy must be positive");
+  HIPCHK(hipDeviceSynchronize());  // kernels in flight read the old Maxwellian
+  for (int m = 0; m < 4; ++m) c->winf[m] = w[m];
+  ++c->version;  // captured graphs hold the far-field state
+  int rc = upload_farfield(c);
+  if (!rc) fill_dev(c);
+  return rc;
 }
 
 int ugks_set_block_velocity(ugks_ctx* c, int32_t blk, double ux, double uy, double om) {

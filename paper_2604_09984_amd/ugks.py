@@ -50,6 +50,7 @@ def lib():
         L.ugks_sizes.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.ugks_set_poses.argtypes = [vp, C.POINTER(d), C.POINTER(d)]
         L.ugks_set_types.argtypes = [vp, C.POINTER(C.c_int8)]
+        L.ugks_set_farfield.argtypes = [vp, C.POINTER(d)]
         L.ugks_get_types.argtypes = [vp, C.POINTER(C.c_int8)]
         L.ugks_set_overset.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(d)]
         L.overset_assemble.argtypes = [vp, i32, i32, C.POINTER(i32)]
@@ -103,7 +104,7 @@ def exported_symbols():
             "ugks_moments", "ugks_heatflux", "ugks_flux", "overset_interp", "ugks_begin_step", "ugks_step",
             "ugks_timesteps", "ugks_step_profile", "ugks_step_graph", "ugks_batch_create", "ugks_batch_step",
             "ugks_batch_destroy", "ugks_batch_set_mode", "ugks_batch_get_mode", "ugks_set_tuning", "ugks_get_tuning", "ugks_micro_shape", "ugks_autotune", "ugks_set_wall_rt",
-            "ugks_last_flux", "ugks_set_block_velocity", "ugks_face_geometry", "ugks_overset_rows",
+            "ugks_last_flux", "ugks_set_block_velocity", "ugks_set_farfield", "ugks_face_geometry", "ugks_overset_rows",
             "ugks_flux_adjoint", "ugks_step_adjoint", "ugks_begin_step_adjoint",
             "ugks_workspace_size", "ugks_create_with_workspace", "ugks_status", "ugks_set_checks",
             "ugks_wall_loads", "ugks_wall_loads_adjoint", "ugks_param_bars", "ugks_newton_euler",
@@ -340,6 +341,13 @@ class Solver:
     def set_wall_rt(self, blk, side, rtw):
         """RT of the isothermal wall on one side of a block."""
         _check(lib().ugks_set_wall_rt(self.ctx, int(blk), int(side), float(rtw)))
+
+    def set_farfield(self, winf):
+        """Far-field conservative state (nw values) and its Maxwellian
+        (ugks_set_farfield)."""
+        a = np.zeros(4)
+        a[:self.nw] = np.asarray(winf, dtype=np.float64).reshape(-1)[:self.nw]
+        _check(lib().ugks_set_farfield(self.ctx, _dp(a)))
 
     def set_block_velocity(self, blk, ux, uy, om=0.0):
         """Rigid velocity of a block; geometry, dt_s and dt' stay fixed."""

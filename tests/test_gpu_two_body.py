@@ -23,8 +23,8 @@ import numpy as np
 import pytest
 import torch
 
-from oracle.oracle import Oracle
-from paper_2604_09984_amd import ugks, workloads as wl
+from oracle.oracle import Oracle, dual
+from paper_2604_09984_amd import adjoint, ugks, workloads as wl
 from tests.parity import dev, host, rel_l2, say
 
 pytestmark = pytest.mark.gpu
@@ -202,4 +202,140 @@ def test_two_body_full_shape_whole_step(prec, tol):
     err.append(rel_l2(host(Wd)[live], W[live]))
     say("  rel L2 h b W", err)
     assert max(err) <= tol
+    s.close()
+
+
+# --------------------------------------------------------------------------
+# the adjoint at Ma 6, Kn 1e-3 after a ramped inflow
+# --------------------------------------------------------------------------
+NRAMP, NDIFF, NIN = 20, 20, 2
+
+
+def _winf(mach, rt=0.5):
+    return wl.cons(2, 1.0, [mach * np.sqrt(5.0 / 3.0 * rt), 0.0], rt)
+
+
+@pytest.mark.timeout(900)
+def test_ma6_adjoint_after_ramped_inflow():
+    """The separation's gradient at Ma 6 and Kn 1e-3: a 96 x 48 background
+    with two 24 x 10 O-meshes and 24 x 24 velocities on [-10, 10]^2 (a
+    range that still resolves the Ma 6 Maxwellian), started at rest and
+    brought to Ma 6 by 20 non-differentiated steps of the oracle with the
+    far-field Mach number raised by 0.3 per step (an impulsive Ma 6 start
+    empties the lee-side wall cells at this resolution); from that state,
+    20 differentiated physical steps (two inner iterations each, the small
+    body moving as dy = t^2 / 2, dtheta = t / 5 with re-assembly at every
+    step, through adjoint.rollout with 3 kept states) of the small body's
+    lift summed over the steps, with respect to its (constant) block
+    velocity and wall temperature: against the oracle's tangent build run
+    through the same 20 steps (its own assembly and time steps at each
+    pose) and central differences of the HIP forward path."""
+    case = wl.two_body(nx=96, ny=48, ni=24, nj=10, nv=24, vmax=10.0, mach=6.0, kn=1e-3)
+    o = Oracle(case)
+    o.set_poses(case.poses(0.0))
+    assert o.assemble(0, 2)[0] == 0
+    W = np.tile(_winf(0.0), (case.ncell, 1))
+    h, b = o.maxwellian(W)
+    q = o.heatflux(h, b, W)
+    for k in range(NRAMP):
+        o.set_farfield(_winf(6.0 * (k + 1) / NRAMP))
+        dts, dtp = o.timesteps()
+        dt = case.dt_over_dts * dts
+        Wn = W.copy()
+        Sh, Sb, Fn = o.begin_step(dt, dts, h, b, W, q)
+        for _ in range(NIN):
+            o.pseudo_step(dt, dts, dtp, h, b, W, Wn, q, Sh, Sb, Fn)
+    field = o.types() == 1
+    say("Ma 6 ramp: field rho min", float(W[field, 0].min()), "max", float(W[field, 0].max()))
+    assert np.isfinite(h).all() and W[field, 0].min() > 0.3
+    times = [0.02 * (k + 1) for k in range(NDIFF)]
+    body, side = 2, 2  # the small body's wall (its O-mesh's j-min side)
+
+    s = ugks.Solver(case, ugks.F64)
+    s.set_farfield(_winf(6.0))
+    U, R = adjoint.default_params(s)
+    U[body, 1] = 0.4
+
+    def J_gpu(Ug, Rg, stats=None):
+        s.set_types(np.ones(case.ncell, np.int8))
+        s.set_poses(case.poses(0.0))
+        s.assemble(0, 2)
+
+        def setup_at(t):
+            def setup(solver):
+                solver.set_poses(case.poses(t))
+                solver.assemble(0, 2)
+            return setup
+        dt_of = lambda solver: case.dt_over_dts * solver.timesteps()[0]
+        steps = [(dt_of, NIN, setup_at(t)) for t in times]
+        hN, bN, WN, qN, F, L = adjoint.rollout(s, steps, dev(h), dev(b), dev(W), dev(q), Ug, Rg, snapshots=3,
+                                               stats=stats)
+        assert bool(torch.isfinite(WN).all())
+        return L[:, body, side, 1].sum()
+
+    Ug = U.clone().requires_grad_(True)
+    Rg = R.clone().requires_grad_(True)
+    stats = {}
+    J = J_gpu(Ug, Rg, stats)
+    gU, gR = torch.autograd.grad(J, [Ug, Rg])
+    assert stats["recomputed_steps"] == adjoint.revolve_cost(NDIFF, 3)
+
+    # the oracle's tangent build along the small body's y velocity
+    ot = Oracle(case, tangent=True)
+    ot.set_farfield(_winf(6.0))
+
+    def pose(t):
+        out = []
+        for bi, p in enumerate(case.poses(t)):
+            row = [(x, 0.0) for x in p]
+            row[3] = (float(U[bi, 0]), 0.0)
+            row[4] = (float(U[bi, 1]), 1.0 if bi == body else 0.0)
+            out.append(row)
+        return out
+    ot.set_poses(pose(0.0))
+    assert ot.assemble(0, 2)[0] == 0
+    hd, bd, Wd, qd = dual(h), dual(b), dual(W), dual(q)
+    Jv = Jd = 0.0
+    for t in times:
+        # as the library: the pose's geometry, assembly and time steps,
+        # then the block velocity parameter on the faces (dt_s, dt' kept)
+        ot.set_poses([[(x, 0.0) for x in p] for p in case.poses(t)])
+        assert ot.assemble(0, 2)[0] == 0
+        dts, dtp = ot.timesteps()
+        ot.set_poses(pose(t))
+        dt = case.dt_over_dts * dts[0]
+        Wn = Wd.copy()
+        Sh, Sb, Fn = ot.begin_step((dt, 0.0), (dts[0], 0.0), hd, bd, Wd, qd)
+        F = ot._z(max(ot.nface, 1), case.nw)
+        for _ in range(NIN):
+            ot.pseudo_step((dt, 0.0), (dts[0], 0.0), dtp, hd, bd, Wd, Wn, qd, Sh, Sb, Fn, F)
+        _, sl = ot.wall_loads(F[:ot.nface])
+        Jv += float(sl[body, side, 1, 0])
+        Jd += float(sl[body, side, 1, 1])
+
+    def close(ref, got, tol, what):
+        rel = abs(ref - got) / max(abs(ref), abs(got), 1e-300)
+        say(f"  {what}: reference {ref:.15e} gpu {got:.15e} rel {rel:.2e}")
+        assert rel <= tol, (what, ref, got, rel)
+    close(Jv, float(J), 1e-9, "lift over 20 steps")
+    close(Jd, float(gU[body, 1]), 1e-8, "dlift/dU_y (oracle tangent)")
+    eps = 1e-6
+    with torch.no_grad():
+        Up, Um = U.clone(), U.clone()
+        Up[body, 1] += eps; Um[body, 1] -= eps
+        fd = (float(J_gpu(Up, R)) - float(J_gpu(Um, R))) / (2 * eps)
+        close(fd, float(gU[body, 1]), 1e-6, "dlift/dU_y (central differences)")
+        Rp, Rm = R.clone(), R.clone()
+        Rp[body, side] += eps; Rm[body, side] -= eps
+        fd = (float(J_gpu(U, Rp)) - float(J_gpu(U, Rm))) / (2 * eps)
+        close(fd, float(gR[body, side]), 1e-6, "dlift/dRTw (central differences)")
+    s.close()
+
+
+def test_set_farfield_rejects_a_bad_state():
+    s = ugks.Solver(wl.cavity(4, 4), ugks.F64)
+    for bad in ([0.0, 0.0, 0.0, 1.0], [1.0, 2.0, 0.0, 1.0], [1.0, float("nan"), 0.0, 1.0]):
+        with pytest.raises(ugks.UgksError):
+            s.set_farfield(bad)
+    s.set_farfield(_winf(0.5))
     s.close()
