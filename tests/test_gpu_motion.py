@@ -9,7 +9,7 @@ import pytest
 
 from oracle.oracle import Oracle
 from paper_2604_09984_amd import ugks, workloads as wl
-from tests.parity import dev, host, rel_l2, say
+from tests.parity import cell_max_rel, dev, host, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -96,6 +96,9 @@ def test_free_body_trajectory_and_field(make):
     live = to != wl.HOLE
     assert rel_l2(hg[live], ho[live]) <= 1e-10 and rel_l2(bg[live], bo[live]) <= 1e-10
     assert rel_l2(Wg[live], Wo[live]) <= 1e-10
+    c = max(cell_max_rel(hg, ho, live), cell_max_rel(bg, bo, live), cell_max_rel(Wg, Wo, live))
+    say("  per-cell max rel", c)
+    assert c <= 1e-12
 
 
 def test_newton_euler_rejects_bad_arguments():
