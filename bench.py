@@ -67,16 +67,16 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_from_profiles(kernel, prec):
-    """HBM bytes per launch from the committed counter summary, if it still
-    matches the kernel source."""
+def traffic_from_profiles(kernel, prec, workload):
+    """HBM bytes per launch from the committed counter summary, if it was
+    measured on this workload and still matches the kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         data = json.load(open(path))
         ent = data.get(f"{kernel}:{prec}")
-        if not ent:
+        if not ent or ent.get("workload") != workload:
             return None
         import hashlib
         src = open(os.path.join(ROOT, "paper_2604_09984_amd", "csrc", "ugks_kernels.hip"), "rb").read()
@@ -192,7 +192,7 @@ def time_workload(case, prec_name, iters, t_pose=0.0):
                launch_shapes=tuning_d, finite=finite, rho_min=rho_min,
                stages_ms={k: round(v, 4) for k, v in prof.items()},
                hbm_algorithmic_frac=round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-               roofline=roofline(prof, pairs, prec_name, tuning_d, micro) if case.dim == 2 else None)
+               roofline=roofline(prof, pairs, prec_name, tuning_d, micro, case.name) if case.dim == 2 else None)
     if case.overset is not None:
         # the same assembly on the GPU (identical tables)
         t0 = time.perf_counter()
@@ -317,7 +317,7 @@ def cpu_model():
     return "unknown"
 
 
-def roofline(stages, pairs, prec, tuning, micro):
+def roofline(stages, pairs, prec, tuning, micro, workload):
     """Dominant measured kernel: algorithmic bytes per launch over its mean
     launch time (HIP events), against the HBM peak."""
     kv = kernel_values(micro)
@@ -329,7 +329,7 @@ def roofline(stages, pairs, prec, tuning, micro):
     key = KERNEL_KEYS[dom].format(t="double" if prec == "f64" else "float", re=tuning["rg_eq"],
                                   rf=tuning["rg_flux"], kc=micro[0], mp=micro[2], mr=micro[1])
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(key, prec),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(key, prec, workload),
             "kernel": KERNEL_NAMES[dom], "kernel_instance": key, "kernel_ms": round(stages[dom], 4), "algorithmic_bytes_per_launch": algo}
 
 
@@ -368,6 +368,7 @@ def main():
         print(json.dumps({"workload": args.workload, "result": r}), flush=True)
         return
     case = wl.cylinder(nvx=args.nvx)
+    cyl_key = f"cylinder_128x64_v{args.nvx}x{args.nvx}"  # workload key of profiles/traffic.json
     r64 = run_gpu(case, "f64", args.steps, args.warmup, adjoint_calls=args.adjoint_calls)
     r32 = None if args.no_f32 else run_gpu(case, "f32", args.steps, args.warmup)
     ms64 = 1e3 * r64["wall_s"] / args.steps
@@ -395,7 +396,7 @@ def main():
         "config": {"workload": f"Ma5 cylinder, O-mesh 128x64 cells, {args.nvx}x{args.nvx} velocities on "
                                f"[-15,15]^2, Kn 0.01 hard sphere, isothermal wall, dt = 20 dt_s",
                    "pairs": r64["pairs"], "pseudo_steps": args.steps, "launch": "hipGraph replay, 10 per replay"},
-        "roofline": roofline(st, r64["pairs"], "f64", r64["tuning"], r64["micro"]),
+        "roofline": roofline(st, r64["pairs"], "f64", r64["tuning"], r64["micro"], cyl_key),
         "kernels_f64": per_kernel,
         "stages_ms_f64": {k: round(v, 4) for k, v in st.items()},
         "eager_ms_per_step_f64": round(r64["eager_ms"], 4),
@@ -412,7 +413,7 @@ def main():
         line["f32"] = {"value": r32["pairs"] * args.steps / r32["wall_s"], "ms_per_step": ms32,
                        "speedup_vs_f64": ms64 / ms32,
                        "rel_l2_h_vs_f64_after_run": rel,
-                       "roofline": roofline(r32["stages"], r32["pairs"], "f32", r32["tuning"], r32["micro"]),
+                       "roofline": roofline(r32["stages"], r32["pairs"], "f32", r32["tuning"], r32["micro"], cyl_key),
                        "launch_shapes": r32["tuning"],
                        "stages_ms": {k: round(v, 4) for k, v in r32["stages"].items()}}
     if r64["adjoint_ms"] is not None:
