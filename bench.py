@@ -121,7 +121,7 @@ def run_gpu(case, prec_name, steps, warmup, adjoint_calls=0):
     # per-kernel timing: HIP events on the library's stream, separate run
     prof = s.step_profile(dt, chunk, h, b, W, Wn, q, Sh, Sb, Fn)
     torch.cuda.synchronize()
-    adj_ms = None
+    adj_ms = adj_finite = None
     if adjoint_calls > 0 and prec == ugks.F64:
         # reverse pass of one pseudo-iteration at the current state with random
         # cotangents (one call = the iteration's forward recomputation plus the
@@ -135,10 +135,14 @@ def run_gpu(case, prec_name, steps, warmup, adjoint_calls=0):
             s.step_adjoint(dt, h, b, W, Wn, q, Sh, Sb, Fn, *ys)
         torch.cuda.synchronize()
         adj_ms = 1e3 * (time.perf_counter() - t2) / adjoint_calls
+        bars = s.step_adjoint(dt, h, b, W, Wn, q, Sh, Sb, Fn, *ys)
+        adj_finite = all(bool(torch.isfinite(t).all().item()) for t in bars)
+        del bars
     pairs = int((s.types() == 1).sum()) * s.nv
     out = dict(prec=prec_name, pairs=pairs, wall_s=wall_s, eager_ms=eager_ms, steps=steps, stages=prof,
                tuning=dict(zip(("kc_max", "rg_eq", "rg_flux"), tuning)), micro=s.micro_shape(),
-               finite=bool(torch.isfinite(h).all().item() and torch.isfinite(W).all().item()), adjoint_ms=adj_ms)
+               finite=bool(torch.isfinite(h).all().item() and torch.isfinite(W).all().item()), adjoint_ms=adj_ms,
+               adjoint_finite=adj_finite)
     out["h"] = h.to(torch.float64).cpu()
     s.close()
     return out
@@ -419,6 +423,7 @@ def main():
     if r64["adjoint_ms"] is not None:
         line["adjoint_f64"] = {"ms_per_pseudo_step": round(r64["adjoint_ms"], 3),
                                "ratio_to_forward_eager": round(r64["adjoint_ms"] / r64["eager_ms"], 2),
+                               "finite": r64["adjoint_finite"],
                                "what": "ugks_step_adjoint: recomputation of one pseudo-iteration and its "
                                        "reverse pass (vector-Jacobian product w.r.t. f, W, q, S, Fn, block "
                                        "velocity and wall temperature)"}

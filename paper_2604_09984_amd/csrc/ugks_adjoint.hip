@@ -289,13 +289,18 @@ __device__ inline double lim_d(int lo, int hi, double vlo, double v0, double vhi
   if (lo == kNbWall && hi == kNbWall) return 0.0;
   if (lo == kNbWall) { dhi = 1.0; d0 = -1.0; return vhi - v0; }
   if (hi == kNbWall) { d0 = 1.0; dlo = -1.0; return v0 - vlo; }
-  double s1 = v0 - vlo, s2 = vhi - v0;
-  if (s1 * s2 <= 0.0) return 0.0;
-  double vl = (s1 * fabs(s2) + fabs(s1) * s2) / (fabs(s1) + fabs(s2));
-  double sm = s1 + s2;
-  double p1 = 2.0 * s2 * s2 / (sm * sm), p2 = 2.0 * s1 * s1 / (sm * sm);
+  const double s1 = v0 - vlo, s2 = vhi - v0;
+  const double sm = s1 + s2;
+  // one-sided slopes of one sign: the van Leer slope is 2 s1 s2 / (s1 + s2)
+  // (|s1| + |s2| = |s1 + s2|), its partials 2 (s2 / sm)^2 and 2 (s1 / sm)^2
+  // (ratios in [0, 1], so no square underflows); as in the forward pass, a
+  // sum below the normal range (far tails of f) gives a zero slope
+  if (s1 * s2 <= 0.0 || !(fabs(sm) >= 1e-300)) return 0.0;
+  const double r = 1.0 / sm;
+  const double t1 = s1 * r, t2 = s2 * r;
+  const double p1 = 2.0 * t2 * t2, p2 = 2.0 * t1 * t1;
   d0 = p1 - p2; dlo = -p1; dhi = p2;
-  return vl;
+  return 2.0 * s1 * t2;
 }
 
 __device__ __forceinline__ double nbval(const double* f, const double* finf, int code, double self, int nv, int k) {
