@@ -20,6 +20,10 @@ struct Order {
   int ncolour = 0;
 };
 
+// workgroups of the face reverse (each strides over its colour's faces and
+// stages one face's per-velocity bars in its own [6][nv] slice of fsc)
+constexpr int kFaceBlocks = 512;
+
 // UGKS flux (Sec. 2.1) reversed at the state (h, b, W, q) with the cell
 // gradients gW of W and the forward face records rec (their moment shifts
 // are used): divergence bars Dbh, Dbb [ncell][nv] and face macro flux bar
@@ -28,11 +32,12 @@ struct Order {
 // wall faces, coloured so that a colour's faces touch disjoint cells (both
 // sides and the index neighbours of each side); `walls`: the wall faces, a
 // colour's faces with disjoint cells and cell neighbours; `cells`: every
-// cell, a colour's cells with disjoint sets {c} + nb(c).
+// cell, a colour's cells with disjoint sets {c} + nb(c).  fsc: scratch of
+// kFaceBlocks x 6 x nv doubles.
 void adj_flux(const Dev& g, const Order& faces, const Order& walls, const Order& cells, double dts,
               const double* h, const double* b, const double* W, const double* q, const double* gW,
               const double* rec, const double* Dbh, const double* Dbb, const double* Fb, double* hbar, double* bbar,
-              double* Wbar, double* qbar, double* gWbar, double* fbar, hipStream_t st);
+              double* Wbar, double* qbar, double* gWbar, double* fbar, double* fsc, hipStream_t st);
 
 // Step 7 and the heat flux of the new state reversed: hb, bb (bars of f')
 // updated in place, Wpb = bar of the macro predictor (written)

@@ -510,20 +510,17 @@ __device__ __forceinline__ void rec_values(const Dev& g, double dts, const doubl
   face_coeffs(g, dts, x, c);
 }
 
-__global__ __launch_bounds__(64 * kFaceWaves) void k_adj_face(Dev g, const int* __restrict__ items, int nitems, double dts,
-                                                  const double* __restrict__ h,
-                                                  const double* __restrict__ b, const double* __restrict__ gW,
-                                                  const double* __restrict__ rec,
-                                                  const double* __restrict__ Dbh, const double* __restrict__ Dbb,
-                                                  const double* __restrict__ Fb, double* __restrict__ hbar,
-                                                  double* __restrict__ bbar, double* __restrict__ gWbar,
-                                                  double* __restrict__ fbar) {
-  __shared__ Rec e;
-  __shared__ double sred[kFaceWaves * kRecBar];
-  __shared__ double sxb[kRecIn];
+// sc: this workgroup's [6][nv] staging of the pass-3 bars of the upwind
+// reconstructions (value, physical slopes; h then b), completed by the
+// moment bars in pass 4 and scattered once
+__device__ __forceinline__ void adj_face_body(const Dev& g, int f, double dts, const double* __restrict__ h,
+                                              const double* __restrict__ b, const double* __restrict__ gW,
+                                              const double* __restrict__ rec, const double* __restrict__ Dbh,
+                                              const double* __restrict__ Dbb, const double* __restrict__ Fb,
+                                              double* __restrict__ hbar, double* __restrict__ bbar,
+                                              double* __restrict__ gWbar, double* __restrict__ fbar,
+                                              double* __restrict__ sc, Rec& e, double* sred, double* sxb) {
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
-  if ((int)blockIdx.x >= nitems) return;
-  const int f = items[blockIdx.x];
   const double* fp = g.fplan + (size_t)f * kFpN;
   if (tab_int(fp[kFpAct]) == 0) return;
   const int L = tab_int(fp[kFpL]), R = tab_int(fp[kFpR]);
@@ -631,8 +628,8 @@ __global__ __launch_bounds__(64 * kFaceWaves) void k_adj_face(Dev g, const int* 
     double wnb = (Fhb * Ih + Fbb * Ib) / dts;
     ufb_x -= wnb * nx;
     ufb_y -= wnb * ny;
-    side_rev_d(g, sh, up, inner, ox, oy, k, fhb, ghb[0], ghb[1], hbar);
-    side_rev_d(g, sb, up, inner, ox, oy, k, fbb, gbb[0], gbb[1], bbar);
+    sc[k] = fhb; sc[nv + k] = ghb[0]; sc[2 * nv + k] = ghb[1];
+    sc[3 * nv + k] = fbb; sc[4 * nv + k] = gbb[0]; sc[5 * nv + k] = gbb[1];
   }
   block_sum<kRecBar>(acc, sred);
   {
@@ -673,7 +670,9 @@ __global__ __launch_bounds__(64 * kFaceWaves) void k_adj_face(Dev g, const int* 
     fbar[(size_t)f * 5 + 0] += ufb_x;
     fbar[(size_t)f * 5 + 1] += ufb_y;
   }
-  // pass 4: the moment bars of the upwind data (W0, q0), to both sides
+  // pass 4: the moment bars of the upwind data (W0, q0) added to the staged
+  // pass-3 bars, one scatter of the upwind reconstruction per velocity (on a
+  // tie, which pass 3 skips: half to each side)
   const double ux0 = e.ux, uy0 = e.uy;
   for (int k = tid; k < nv; k += nt) {
     double vx = g.vx[k], vy = g.vy[k], w = g.wk[k];
@@ -683,19 +682,42 @@ __global__ __launch_bounds__(64 * kFaceWaves) void k_adj_face(Dev g, const int* 
     double mh = w * (W0b[0] + W0b[1] * vx + ((D == 2) ? W0b[2] * vy : 0.0) +
                      W0b[D + 1] * 0.5 * (vx * vx + vy * vy)) + w * 0.5 * cqb * (cx * cx + cy * cy);
     double mb = w * 0.5 * W0b[D + 1] + w * 0.5 * cqb;
-    // the upwind side (on a tie: half to each side), chosen per lane
-    const bool tie = (wn == 0.0);
-    const double sl = tie ? 0.5 : 1.0;
+    // the upwind side, chosen per lane
     const bool lft = wn > 0.0;
     const int up = lft ? cL : cR;
     const double ox = lft ? dLx : dRx, oy = lft ? dLy : dRy;
-    side_any_rev(g, h, hinf, up, inner, ox, oy, k, sl * mh, 0.0, 0.0, hbar);
-    side_any_rev(g, b, binf, up, inner, ox, oy, k, sl * mb, 0.0, 0.0, bbar);
-    if (tie) {
+    if (wn == 0.0) {
+      side_any_rev(g, h, hinf, up, inner, ox, oy, k, 0.5 * mh, 0.0, 0.0, hbar);
+      side_any_rev(g, b, binf, up, inner, ox, oy, k, 0.5 * mb, 0.0, 0.0, bbar);
       side_any_rev(g, h, hinf, cL, inner, dLx, dLy, k, 0.5 * mh, 0.0, 0.0, hbar);
       side_any_rev(g, b, binf, cL, inner, dLx, dLy, k, 0.5 * mb, 0.0, 0.0, bbar);
+    } else {
+      const SideD sh = side_val_d(g, h, hinf, up, inner, ox, oy, k);
+      side_rev_d(g, sh, up, inner, ox, oy, k, sc[k] + mh, sc[nv + k], sc[2 * nv + k], hbar);
+      const SideD sb = side_val_d(g, b, binf, up, inner, ox, oy, k);
+      side_rev_d(g, sb, up, inner, ox, oy, k, sc[3 * nv + k] + mb, sc[4 * nv + k], sc[5 * nv + k], bbar);
     }
   }
+}
+
+// one face per workgroup (sc: kFaceBlocks x [6][nv]; at most kFaceBlocks
+// workgroups per launch)
+__global__ __launch_bounds__(64 * kFaceWaves) void k_adj_face(Dev g, const int* __restrict__ items, int nitems,
+                                                              double dts, const double* __restrict__ h,
+                                                              const double* __restrict__ b,
+                                                              const double* __restrict__ gW,
+                                                              const double* __restrict__ rec,
+                                                              const double* __restrict__ Dbh,
+                                                              const double* __restrict__ Dbb,
+                                                              const double* __restrict__ Fb, double* __restrict__ hbar,
+                                                              double* __restrict__ bbar, double* __restrict__ gWbar,
+                                                              double* __restrict__ fbar, double* __restrict__ fsc) {
+  __shared__ Rec e;
+  __shared__ double sred[kFaceWaves * kRecBar];
+  __shared__ double sxb[kRecIn];
+  if ((int)blockIdx.x >= nitems) return;
+  adj_face_body(g, items[blockIdx.x], dts, h, b, gW, rec, Dbh, Dbb, Fb, hbar, bbar, gWbar, fbar,
+                fsc + (size_t)blockIdx.x * 6 * g.nv, e, sred, sxb);
 }
 
 // ------------------------------------------------------------------------
@@ -1551,11 +1573,14 @@ static unsigned face_threads(int nv) {
 void adj_flux(const Dev& g, const Order& faces, const Order& walls, const Order& cells, double dts,
               const double* h, const double* b, const double* W, const double* q, const double* gW,
               const double* rec, const double* Dbh, const double* Dbb, const double* Fb, double* hbar, double* bbar,
-              double* Wbar, double* qbar, double* gWbar, double* fbar, hipStream_t st) {
+              double* Wbar, double* qbar, double* gWbar, double* fbar, double* fsc, hipStream_t st) {
   const unsigned nt = face_threads(g.nv);
-  per_colour(faces, 1, nt, [&](dim3 gr, dim3 bl, const int* it, int n) {
-    hipLaunchKernelGGL(k_adj_face, gr, bl, 0, st, g, it, n, dts, h, b, gW, rec, Dbh, Dbb, Fb, hbar, bbar, gWbar,
-                       fbar);
+  per_colour(faces, 1, nt, [&](dim3, dim3 bl, const int* it, int n) {
+    for (int o = 0; o < n; o += kFaceBlocks) {
+      const int m = std::min(n - o, kFaceBlocks);
+      hipLaunchKernelGGL(k_adj_face, dim3((unsigned)m), bl, 0, st, g, it + o, m, dts, h, b, gW, rec, Dbh, Dbb, Fb,
+                         hbar, bbar, gWbar, fbar, fsc);
+    }
   });
   per_colour(walls, 1, nt, [&](dim3 gr, dim3 bl, const int* it, int n) {
     hipLaunchKernelGGL(k_adj_wall, gr, bl, 0, st, g, it, n, dts, h, b, W, q, gW, Dbh, Dbb, Fb, hbar, bbar, Wbar,

@@ -1795,7 +1795,9 @@ enum AdjBuf {
   A_SLOT,
   // int32 items of the scatter colourings: every face, every cell, and up
   // to 2 ncell donor rows (receptor rows and refill rows are cells)
-  A_ORD, A_NBUF
+  A_ORD,
+  // [kFaceBlocks][6][nv]: per-velocity bars staged by the face reverse
+  A_FSC, A_NBUF
 };
 
 std::vector<size_t> adjoint_counts(const Sizes& z) {
@@ -1812,6 +1814,7 @@ std::vector<size_t> adjoint_counts(const Sizes& z) {
     else if (i == A_FB) n = (size_t)z.nface * z.nw;
     else if (i == A_SLOT) n = 8 * (size_t)z.ncell;
     else if (i == A_ORD) n = ((size_t)z.nface + 3 * (size_t)z.ncell + 1) / 2;
+    else if (i == A_FSC) n = (size_t)kFaceBlocks * 6 * z.nv;
     else n = (size_t)z.nface * 5;
     out[i] = n;
   }
@@ -1969,7 +1972,8 @@ int flux_reverse(ugks_ctx* c, hipStream_t st) {
   adj_flux(c->dev, order_of(c, 0), order_of(c, 4), order_of(c, 1), c->dts, A(c, A_H0), A(c, A_B0), A(c, A_W0), A(c, A_Q0),
            (const double*)c->s_gW,
            (const double*)c->s_rec, A(c, A_DBH),
-           A(c, A_DBB), A(c, A_FB), A(c, A_HB), A(c, A_BB), A(c, A_WB), A(c, A_QB), A(c, A_GWB), A(c, A_FBAR), st);
+           A(c, A_DBB), A(c, A_FB), A(c, A_HB), A(c, A_BB), A(c, A_WB), A(c, A_QB), A(c, A_GWB), A(c, A_FBAR),
+           A(c, A_FSC), st);
   HIPCHK(hipGetLastError());
   return UGKS_OK;
 }
