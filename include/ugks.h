@@ -120,8 +120,8 @@ typedef struct ugks_ctx ugks_ctx;
    *out receives the context.  Block sizes the sweeps accept (one workgroup
    per block and velocity chunk, state in LDS): nj <= 512 in 2D; ni <= 256
    when a block is periodic in j; the LU-SGS sweeps' LDS of the largest
-   block within 160 KiB (else UGKS_E_UNSUPPORTED, with the reason in
-   ugks_last_error). */
+   block within 160 KiB, which bounds nj to 511 (else UGKS_E_UNSUPPORTED,
+   with the reason in ugks_last_error). */
 int ugks_create(const ugks_problem* p, int device, ugks_ctx** out);
 /*
  * Device memory a problem needs beyond the caller's state arrays (host
