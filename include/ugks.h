@@ -436,7 +436,11 @@ int ugks_last_flux(const ugks_ctx* ctx, double* F, void* stream);
  * call recomputes the forward quantities it needs from the given inputs
  * (the inputs are not modified) in its FP64 workspace (about 14 arrays of
  * [ncell][nv]: the caller's, see ugks_create_with_workspace, or allocated
- * on first use); the context's scratch is overwritten.
+ * on first use); the context's scratch is overwritten.  Every bar is summed
+ * in an order fixed by the mesh (the scatters run over write-disjoint
+ * colourings of faces, cells and donor rows, computed on the host when the
+ * tables change and kept in the workspace), so the results are bitwise
+ * reproducible from call to call and across contexts.
  * The cotangent of a hole cell's value is not defined.  Asynchronous on
  * `stream`.
  *

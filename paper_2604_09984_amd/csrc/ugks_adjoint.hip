@@ -6,13 +6,16 @@
 // (checkpointed recomputation): the stages run backwards, Step 7 and the
 // heat flux first, then the micro LU-SGS sweeps (transposed sweeps in
 // reversed hyperplane order), the macro LU-SGS (reverse of the two nonlinear
-// sweeps), the UGKS interface flux (per face, lanes over velocities) and the
-// overset interpolation.  Small dense per-face maps (the equilibrium
+// sweeps), the UGKS interface flux (per face, threads over velocities) and
+// the overset interpolation.  Small dense per-face maps (the equilibrium
 // expansion coefficients and the time integrals of Eq. fullSolution) are
 // differentiated in forward mode, one input direction per lane, and the
 // resulting Jacobian columns are contracted with the cotangent in the same
-// lanes.  Contributions that several threads add to one cell or face use
-// device-scope atomic additions (the sums are exact up to their order).
+// lanes.  Contributions that several items (faces, cells, donor rows) add
+// to one cell run over a write-disjoint colouring of the items, one launch
+// per colour, and contributions of a cell to its own faces are gathered per
+// face: every sum has a fixed order and the results are bitwise
+// reproducible.
 //
 // Differentiated quantities: the distribution (h, b), W, q and the dual-time
 // sources of a step; the face grid velocity U_f (Eq. BGK, w = v - U), the
