@@ -415,3 +415,40 @@ def test_wall_loads_reverse_refuses_another_pose():
     L.sum().backward()
     assert float(F.grad.abs().sum()) > 0
     s.close()
+
+
+@pytest.mark.timeout(900)
+def test_batch_all_cases_heat_flux_gradient_fd():
+    """All 64 cases of the seeded batch (cavities and plates, 32^2 to 128^2
+    cells, 24^2 to 64^2 velocities, Kn 1e-4 to 10): the energy flux into the
+    moving top wall through one checkpointed physical step of two inner
+    iterations, differentiated with respect to that wall's temperature by the
+    library's adjoint, against central differences of the HIP forward path
+    (FP64 storage; relative 1e-6)."""
+    cases = wl.batch_cases(64)
+    worst = 0.0
+    for case in cases:
+        s = ugks.Solver(case, ugks.F64)
+        h0, b0, W0 = wl.synthetic_f(case, seed=5, amp=0.02)
+        hd, bd, Wd = dev(h0), dev(b0), dev(W0)
+        qd = s.heatflux(hd, bd, Wd)
+        dts, _ = s.timesteps()
+        dt = case.dt if case.dt is not None else case.dt_over_dts * dts
+        U, R = adjoint.default_params(s)
+
+        def J(rt):
+            _, _, _, _, _, L = adjoint.physical_step(s, dt, 2, hd, bd, Wd, qd, U, rt, loads=True)
+            return L[0, 3, 3]
+        Rg = R.clone().requires_grad_(True)
+        g = torch.autograd.grad(J(Rg), [Rg])[0][0, 3].item()
+        eps = 1e-6 * float(R[0, 3])
+        with torch.no_grad():
+            Rp, Rm = R.clone(), R.clone()
+            Rp[0, 3] += eps; Rm[0, 3] -= eps
+            fd = (float(J(Rp)) - float(J(Rm))) / (2 * eps)
+        rel = abs(fd - g) / max(abs(fd), abs(g), 1e-300)
+        worst = max(worst, rel)
+        say(f"  {case.name}: dq/dRTw adjoint {g:.12e} central differences {fd:.12e} rel {rel:.2e}")
+        assert abs(g) > 0 and rel <= 1e-6, (case.name, g, fd, rel)
+        s.close()
+    say("worst relative difference over the 64 cases", worst)
