@@ -261,6 +261,53 @@ def time_batch(count, prec_name, iters):
             "sequential_ms_per_pseudo_step": round(ms_seq, 4)}
 
 
+def time_batch_adjoint(count, group=8):
+    """The reverse pass of one pseudo-iteration (ugks_step_adjoint, FP64
+    contexts) of every case of the seeded batch at its state after Steps
+    1-2, with random cotangents: the cases one after another, and `group`
+    cases at a time on their own streams (default priority).  Contexts are
+    made `group` at a time so that the reverse workspaces fit."""
+    import torch
+    from paper_2604_09984_amd import ugks, workloads as wl
+    cases = wl.batch_cases(count)
+    seq_ms = par_ms = 0.0
+    for g0 in range(0, count, group):
+        solvers, runs = [], []
+        for c in cases[g0:g0 + group]:
+            s = ugks.Solver(c, ugks.F64)
+            d, _ = s.timesteps()
+            dt = c.dt_over_dts * d
+            h, b, W, q = s.init_state()
+            Wn = W.clone()
+            Sh, Sb, Fn = s.begin_step(dt, h, b, W, q)
+            gen = torch.Generator(device=h.device).manual_seed(len(runs))
+            ys = [torch.randn(t.shape, dtype=torch.float64, device=h.device, generator=gen) for t in (h, b, W, q)]
+            solvers.append(s)
+            runs.append((dt, (h, b, W, Wn, q, Sh, Sb, Fn), ys))
+        streams = [torch.cuda.Stream() for _ in solvers]
+        for s, (dt, x, ys), st in zip(solvers, runs, streams):  # first calls: workspaces and colourings
+            with torch.cuda.stream(st):
+                s.step_adjoint(dt, *x, *ys)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s, (dt, x, ys) in zip(solvers, runs):
+            s.step_adjoint(dt, *x, *ys)
+        torch.cuda.synchronize()
+        seq_ms += 1e3 * (time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        for s, (dt, x, ys), st in zip(solvers, runs, streams):
+            with torch.cuda.stream(st):
+                s.step_adjoint(dt, *x, *ys)
+        torch.cuda.synchronize()
+        par_ms += 1e3 * (time.perf_counter() - t0)
+        for s in solvers:
+            s.close()
+        del solvers, runs, streams
+        torch.cuda.empty_cache()
+    return {"what": "ugks_step_adjoint of one pseudo-iteration for every case (FP64 contexts)",
+            "sequential_ms": round(seq_ms, 3), "streams_ms": round(par_ms, 3), "streams": group}
+
+
 def copy_calibration(gib):
     """A plain device-to-device copy of known size (read n bytes, write n
     bytes), the reference of the HBM counters."""
@@ -366,6 +413,7 @@ def main():
             r = {p: time_workload(wl.two_body(), p, k, t_pose=0.25) for p in ("f32", "f64")}
         elif args.workload == "batch":
             r = time_batch(64, "f32", k)
+            r["adjoint_f64"] = time_batch_adjoint(64)
         else:
             print(f"unknown workload {args.workload}", file=sys.stderr)
             sys.exit(2)
@@ -441,6 +489,7 @@ def main():
         for p in ("f32", "f64"):
             wk[f"two_body_{p}"] = time_workload(tb, p, k, t_pose=0.25)
         wk["batch64_f32"] = time_batch(64, "f32", k)
+        wk["batch64_f32"]["adjoint_f64"] = time_batch_adjoint(64)
         line["workloads"] = wk
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
