@@ -680,13 +680,16 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
                                            cdouble* fpl, double* __restrict__ part, T* __restrict__ Dh,
                                            T* __restrict__ Db) {
   constexpr int NW = RG + 2;
-  // reconstructions of three columns, raw values of one column per row for
-  // the j-neighbours, j-face fluxes of two columns (flux pass).  Face records
-  // and geometry are read through the scalar cache (uniform addresses,
-  // read-only), prefetched one column ahead.
-  __shared__ LD6<C> lds[3][NW][64];
+  // reconstructions of two columns, raw values of one column per row for
+  // the j-neighbours, j-face fluxes of two columns (flux pass; rows 0..RG
+  // evaluate j-faces).  Face records and geometry are read through the
+  // scalar cache (uniform addresses, read-only), prefetched one column ahead.
+  // Two reconstruction slots suffice with one barrier per column because the
+  // only reconstruction a wavefront reads from another row is the one written
+  // in the same column step (the j-face of the column just reconstructed).
+  __shared__ LD6<C> lds[2][NW][64];
   __shared__ C pub[2][NW][2][64];
-  __shared__ C jfl[(MODE == 1) ? 2 : 1][NW][2][64];
+  __shared__ C jfl[(MODE == 1) ? 2 : 1][RG + 1][2][64];
   cint* bi = binfo + 8 * BZ;
   const int ni = bi[0], nj = bi[1], c0 = bi[2], per_i = bi[3], per_j = bi[4];
   const int j0 = BY * RG;
@@ -727,28 +730,43 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
   const bool jface = (w <= RG) && (j0 - 1 + w < nj);  // evaluates the j-face above its row
   const int prow = (jr >= 0) ? jr : jh;              // row of the packed cell records it reads
   auto cell = [&](int x, int j) -> int { return c0 + x + ni * j; };
-  auto raw = [&](int row, int x, C& vh, C& vb) {
-    const int xw = col(x);
-    if (row < 0 || xw < 0) { vh = C(0); vb = C(0); return; }
-    const size_t o = (size_t)cell(xw, row) * g.nv + kk;
-    vh = (C)h[o];
-    vb = (C)b[o];
+  // this lane's entry in column 0 of the rows it reads (a column xw is
+  // xw * nv further on); per-lane offsets keep the scalar registers for the
+  // face records
+  const size_t nv = (size_t)g.nv;
+  const size_t o_r = (size_t)cell(0, jr < 0 ? 0 : jr) * nv + kk;
+  const size_t o_o = (size_t)cell(0, jo < 0 ? 0 : jo) * nv + kk;
+  const size_t o_p = (size_t)cell(0, prow < 0 ? 0 : prow) * kCpN + ((lane < kCpN) ? lane : 0);
+  // raw values of wrapped column xw (-1: outside the block) of this row or of
+  // the row beyond it
+  auto raw_r = [&](int xw, C& vh, C& vb) {
+    if (jr < 0 || xw < 0) { vh = C(0); vb = C(0); return; }
+    vh = (C)h[o_r + (size_t)xw * nv];
+    vb = (C)b[o_r + (size_t)xw * nv];
   };
-  auto slot = [](int x) -> int { return (x + 6) % 3; };  // x >= -6, constant divisor
-  // packed cell record of column x of row prow (lane l: entry l), zeros
-  // outside the block
-  auto cplan_load = [&](int x) -> double {
-    const int xw = col(x);
+  auto raw_o = [&](int xw, C& vh, C& vb) {
+    if (jo < 0 || xw < 0) { vh = C(0); vb = C(0); return; }
+    vh = (C)h[o_o + (size_t)xw * nv];
+    vb = (C)b[o_o + (size_t)xw * nv];
+  };
+  auto slot = [](int x) -> int { return x & 1; };
+  // packed cell record of wrapped column xw of row prow (lane l: entry l),
+  // zeros outside the block
+  auto cplan_at = [&](int xw) -> double {
     if (prow < 0 || xw < 0) return __hiloint2double(0, (lane == kCpType) ? 0 : -1);
-    return (lane < kCpN) ? g.cplan[(size_t)cell(xw, prow) * kCpN + lane] : 0.0;
+    return (lane < kCpN) ? g.cplan[o_p + (size_t)(xw * kCpN)] : 0.0;
   };
-  // the two faces of column x from the cell records of columns x (and 0 for
-  // the seam face x = -1): i-face (x|x+1) of a core row, j-face above (x, jr)
-  auto face_ids = [&](int x, double cpx, double cp0, int& fi, int& fj) {
-    fi = -1; fj = -1;
-    if (core && jr >= 0 && x >= -1 && x < ni)
-      fi = (x >= 0) ? rec_int(cpx, kCpFace + 1) : rec_int(cp0, kCpFace + 0);
-    if (jface && x >= 0 && x < ni) fj = (jr >= 0) ? rec_int(cpx, kCpFace + 3) : rec_int(cpx, kCpFace + 2);
+  // i-face (x|x+1) of a core row from the cell record of column x (of
+  // column 0 for the seam face x = -1), and j-face above (x, jr) from the
+  // record of column x; -1 where there is none
+  const bool icore = core && jr >= 0;
+  auto iface_id = [&](int x, double cpx, double cp0) -> int {
+    if (icore && x >= -1 && x < ni) return (x >= 0) ? rec_int(cpx, kCpFace + 1) : rec_int(cp0, kCpFace + 0);
+    return -1;
+  };
+  auto jface_id = [&](int x, double cpx) -> int {
+    if (jface && x >= 0 && x < ni) return (jr >= 0) ? rec_int(cpx, kCpFace + 3) : rec_int(cpx, kCpFace + 2);
+    return -1;
   };
 
   // side data at a face from the reconstruction of a cell and the offset
@@ -764,9 +782,9 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
   // flight; the outer row of a halo wavefront at x+1 and x+2
   C a0h, a0b, a1h, a1b, a2h, a2b, p_h, p_b, oc_h, oc_b, on_h, on_b;
   // reconstruction of column x + 1 (window centre) into LDS
-  auto recon = [&](int x1, double cp) {
+  auto recon = [&](int x1, int xw1, double cp) {
     if (jr < 0) return;
-    if (col(x1) < 0) return;
+    if (xw1 < 0) return;
     if (rec_int(cp, kCpType) == 0) return;
     int nbc[4];
 #pragma unroll
@@ -810,7 +828,7 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
   };
   // upwind interface data of a face between sides sl (low) and sh (high)
   // with normal (nx, ny) and mesh velocity (ux, uy)
-  auto face_eval = [&](auto r, const double* fp, const Side<C>& sl, const Side<C>& sh, double* facc,
+  auto face_eval = [&](auto r, auto fp, const Side<C>& sl, const Side<C>& sh, double* facc,
                        double* mom) -> void {
     const double nx = fp[kFpN0], ny = fp[kFpN0 + 1], ux = fp[kFpU], uy = fp[kFpU + 1];
     const double wn = exact_wn(vx, vy, ux, uy, nx, ny);
@@ -842,7 +860,7 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
   };
   // wall face seen from the interior cell c (slot s) with data L: MODE 0
   // gives the numerator and denominator of the wall density (Eq. rhow)
-  auto wall_eval = [&](auto r, const double* fp, bool low, const LD6<C>& L, double* facc,
+  auto wall_eval = [&](auto r, auto fp, bool low, const LD6<C>& L, double* facc,
                        double* mom) -> void {
     const double sg = r[R_SGN];
     const double fg[5] = {fp[kFpN0], fp[kFpN0 + 1], fp[kFpS], fp[kFpU], fp[kFpU + 1]};
@@ -901,32 +919,35 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
     multi_sum<4>(m, lane);
     if ((lane & 15) == 0) part[((size_t)chunk * g.nface + fw) * kFluxP + (lane >> 4)] = m[0];
   };
-  // march: step x reconstructs column x + 1, then evaluates the faces of
-  // column x (i-face (x|x+1), j-face above x) and, in flux mode, gathers the
-  // divergence of column x - 1 from the faces of the previous step.  Ahead
+  // march: step x reconstructs column x + 1, then evaluates the i-face
+  // (x|x+1) and the j-face above column x + 1 and, in flux mode, gathers the
+  // divergence of column x (its j-faces come from the previous step).  Ahead
   // of use, in registers: raw values (two columns), packed cell records
   // (three columns); in the scalar cache: face records (one column).
-  raw(jr, -2, a0h, a0b);
-  raw(jr, -1, a1h, a1b);
-  raw(jr, 0, a2h, a2b);
-  raw(jr, 1, p_h, p_b);
-  raw(jo, -1, oc_h, oc_b);
-  raw(jo, 0, on_h, on_b);
+  // wrapped columns x + 1, x + 3 and x + 4 of the march step x, advanced
+  // by one column per step
+  int c1 = col(-1), c2 = col(0), c3 = col(1), c4 = col(2);
+  raw_r(col(-2), a0h, a0b);
+  raw_r(c1, a1h, a1b);
+  raw_r(c2, a2h, a2b);
+  raw_r(c3, p_h, p_b);
+  raw_o(c1, oc_h, oc_b);
+  raw_o(c2, on_h, on_b);
   pub[1][w][0][lane] = a1h;  // column -1
   pub[1][w][1][lane] = a1b;
-  // cell records of columns -3 .. 1 and 0
-  double cpm1 = cplan_load(-3), cp0c = cplan_load(-2), cp1 = cplan_load(-1), cp2 = cplan_load(0),
-         cp3 = cplan_load(1);
-  const double cpz = cplan_load(0);
+  // cell records of columns -2 .. 1 and 0
+  double cp0c = cplan_at(col(-2)), cp1 = cplan_at(c1), cp2 = cplan_at(c2), cp3 = cplan_at(c3);
+  const double cpz = cp2;
   lds_barrier();
-  double fi_m2[2] = {0.0, 0.0}, fi_m1[2] = {0.0, 0.0}, fj_m1[2] = {0.0, 0.0};
+  double fi_m1[2] = {0.0, 0.0}, fj_m1[2] = {0.0, 0.0};
   // the records of the next column's faces are requested after this
   // column's faces and waited for before the next column's: one round trip
   // per column instead of several dependent ones per face
   int touched[2 * kTouch] = {};
-  auto divergence = [&](int x, double cp) {
-    // divergence of cell (x, jr) of a core row from the i-faces (x-1|x) and
-    // (x|x+1), the j-face above (this row) and below (the row beneath)
+  // divergence of cell (x, jr) of a core row from the i-faces (x-1|x) and
+  // (x|x+1), the j-face above (this row, evaluated one column step earlier)
+  // and the j-face below (evaluated by the row beneath, handed over in LDS)
+  auto divergence = [&](int x, double cp, const double* fi_lo, const double* fi_hi, const double* fj_up) {
     if (!(core && jr >= 0 && x >= 0 && kin)) return;
     const int c = cell(x, jr);
     double dh = 0.0, db = 0.0;
@@ -935,32 +956,33 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
       const double S0 = rec_at(cp, kCpS), S1 = rec_at(cp, kCpS + 1), S2 = rec_at(cp, kCpS + 2),
                    S3 = rec_at(cp, kCpS + 3);
       const double bh = (double)jfl[x & 1][w - 1][0][lane], bb = (double)jfl[x & 1][w - 1][1][lane];
-      dh = -ivol * (-S0 * fi_m2[0] + S1 * fi_m1[0] - S2 * bh + S3 * fj_m1[0]);
-      db = -ivol * (-S0 * fi_m2[1] + S1 * fi_m1[1] - S2 * bb + S3 * fj_m1[1]);
+      dh = -ivol * (-S0 * fi_lo[0] + S1 * fi_hi[0] - S2 * bh + S3 * fj_up[0]);
+      db = -ivol * (-S0 * fi_lo[1] + S1 * fi_hi[1] - S2 * bb + S3 * fj_up[1]);
     }
     Dh[(size_t)c * g.nv + k] = (T)dh;
     Db[(size_t)c * g.nv + k] = (T)db;
   };
   for (int x = -2; x < ni; ++x) {
-    // registers: cell records cpm1 .. cp3 of columns x-1 .. x+3 (cp3 in
-    // flight)
-    recon(x + 1, cp1);
+    // registers: cell records cp0c .. cp3 of columns x .. x+3 (cp3 in flight)
+    recon(x + 1, c1, cp1);
     // publish column x + 2 of this row, advance the windows
     pub[x & 1][w][0][lane] = a2h;
     pub[x & 1][w][1][lane] = a2b;
     a0h = a1h; a0b = a1b; a1h = a2h; a1b = a2b; a2h = p_h; a2b = p_b;
-    raw(jr, x + 4, p_h, p_b);
+    raw_r(c4, p_h, p_b);
     oc_h = on_h; oc_b = on_b;
-    raw(jo, x + 3, on_h, on_b);
-    const double cdiv = cpm1;  // column x - 1
+    raw_o(c3, on_h, on_b);
     const double cfac = cp0c;  // column x
-    cpm1 = cp0c; cp0c = cp1; cp1 = cp2; cp2 = cp3;
-    cp3 = cplan_load(x + 4);
-    lds_barrier();
-    if (MODE == 1) {
-      divergence(x - 1, cdiv);
-      fi_m2[0] = fi_m1[0]; fi_m2[1] = fi_m1[1];
+    cp0c = cp1; cp1 = cp2; cp2 = cp3;
+    cp3 = cplan_at(c4);
+    {
+      // column x + 5: the next in the block, or wrapped (periodic), or -1
+      int cn = c4 + 1;
+      cn = (cn >= ni) ? 0 : cn;
+      cn = per_i ? cn : ((x + 5 < ni) ? x + 5 : -1);
+      c1 = c2; c2 = c3; c3 = c4; c4 = cn;
     }
+    lds_barrier();
     if (x >= -1) {
       const int sx0 = slot(x), sx1 = slot(x + 1);
       double fi_cur[2] = {0.0, 0.0}, fj_cur[2] = {0.0, 0.0};
@@ -969,21 +991,22 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
 #pragma unroll
       for (int q = 0; q < NM; ++q) { mi[q] = 0.0; mj[q] = 0.0; }
       int fiw = -1, fjw = -1;
+      // the i-face (x|x+1) and the j-face above column x + 1, whose
+      // reconstructions were written in this column step
       int fid[2];
-      face_ids(x, cfac, cpz, fid[0], fid[1]);
+      fid[0] = iface_id(x, cfac, cpz);
+      fid[1] = jface_id(x + 1, cp0c);  // cp0c: column x + 1
       sgpr_keep(touched);
-      // the two faces of this column: q = 0 the i-face (x|x+1) of a core
-      // row, q = 1 the j-face above (x, jr) for the bottom halo and core rows
+      // q = 0 the i-face (x|x+1) of a core row, q = 1 the j-face above
+      // (x + 1, jr) for the bottom halo and core rows
       auto face_q = [&](int q) {
         const int f = (q == 0) ? fid[0] : fid[1];
         if (f < 0) return;
         const int fu = __builtin_amdgcn_readfirstlane(f);
         cdouble* r = rec + (size_t)fu * NREC;
-        // the face geometry in one batch of scalar loads (its fields are
-        // tested one after another below)
-        double fp[kFpN];
-#pragma unroll
-        for (int m = 0; m < kFpN; ++m) fp[m] = fpl[(size_t)fu * kFpN + m];
+        // the face geometry, read field by field where it is used (its lines
+        // were requested one column ahead)
+        cdouble* fp = fpl + (size_t)fu * kFpN;
         if (__builtin_amdgcn_readfirstlane(tab_int(fp[kFpAct])) == 0) return;
         const int L = __builtin_amdgcn_readfirstlane(tab_int(fp[kFpL]));
         const int R = __builtin_amdgcn_readfirstlane(tab_int(fp[kFpR]));
@@ -991,8 +1014,8 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
         // seam i-face (x = -1) is written by the high end of the row; the
         // bottom halo writes only the block's lower boundary j-face
         const bool owner = ((q == 0) ? (x >= 0) : (w >= 1)) || (L < 0);
-        const LD6<C>& lo = lds[sx0][w][lane];
-        const LD6<C>& hi = (q == 0) ? lds[sx1][w][lane] : lds[sx0][w + 1][lane];
+        const LD6<C>& lo = lds[(q == 0) ? sx0 : sx1][w][lane];
+        const LD6<C>& hi = lds[sx1][(q == 0) ? w : w + 1][lane];
         double fc[2] = {0.0, 0.0}, mom[NM];
 #pragma unroll
         for (int m = 0; m < NM; ++m) mom[m] = 0.0;
@@ -1021,30 +1044,18 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
           }
         }
       };
-      if constexpr (MODE == 0) {
-        face_q(0);
-        face_q(1);
-      } else {
-        // one evaluation path for both faces (not unrolled), so that only one
-        // face's data is live: the flux pass is register bound
-#pragma clang loop unroll(disable)
-        for (int q = 0; q < 2; ++q) face_q(q);
-      }
-      if (MODE == 1 && x >= 0 && jface) {
-        jfl[x & 1][w][0][lane] = (C)fj_cur[0];
-        jfl[x & 1][w][1][lane] = (C)fj_cur[1];
+      face_q(0);
+      face_q(1);
+      if (MODE == 1 && x + 1 < ni && jface) {
+        jfl[(x + 1) & 1][w][0][lane] = (C)fj_cur[0];
+        jfl[(x + 1) & 1][w][1][lane] = (C)fj_cur[1];
       }
       if (MODE == 0) write_partials(fiw, mi, fjw, mj);
+      if (MODE == 1) divergence(x, cfac, fi_m1, fi_cur, fj_m1);
       fi_m1[0] = fi_cur[0]; fi_m1[1] = fi_cur[1];
       fj_m1[0] = fj_cur[0]; fj_m1[1] = fj_cur[1];
-      int nid[2];
-      face_ids(x + 1, cp0c, cpz, nid[0], nid[1]);  // cp0c: column x + 1
-      face_touch(rec, fpl, nid[0], nid[1], touched);
+      face_touch(rec, fpl, iface_id(x + 1, cp0c, cpz), jface_id(x + 2, cp1), touched);  // cp1: column x + 2
     }
-  }
-  if (MODE == 1) {
-    lds_barrier();
-    divergence(ni - 1, cpm1);
   }
 }
 template <int RG, class T, class C, int MODE>
