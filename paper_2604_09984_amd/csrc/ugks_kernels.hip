@@ -582,16 +582,23 @@ __device__ __forceinline__ float recip_nr<float>(float d) { return __builtin_amd
 // they do not; slopes whose sum is below the normal range (f in the far
 // tails) also give 0, so the reciprocal never overflows
 template <class C>
-__device__ __forceinline__ C climit(int lo, int hi, C vlo, C v0, C vhi) {
-  if (lo == kNbMiss || hi == kNbMiss) return C(0);
-  if (lo == kNbWall && hi == kNbWall) return C(0);
-  if (lo == kNbWall) return vhi - v0;
-  if (hi == kNbWall) return v0 - vlo;
+__device__ __forceinline__ C vanleer(C vlo, C v0, C vhi) {
   const C s1 = v0 - vlo, s2 = vhi - v0;
   const C sum = s1 + s2;
   const C tiny = (sizeof(C) == 8) ? C(1e-300) : C(1e-36);
   const C vl = C(2) * s1 * s2 * recip_nr<C>(sum);
   return (s1 * s2 <= C(0) || !(fabs(sum) >= tiny)) ? C(0) : vl;
+}
+// slope of a cell between neighbours of codes lo and hi: none across a
+// missing neighbour or between two walls, one-sided next to a wall, else
+// van Leer
+template <class C>
+__device__ __forceinline__ C climit(int lo, int hi, C vlo, C v0, C vhi) {
+  if (lo == kNbMiss || hi == kNbMiss) return C(0);
+  if (lo == kNbWall && hi == kNbWall) return C(0);
+  if (lo == kNbWall) return vhi - v0;
+  if (hi == kNbWall) return v0 - vlo;
+  return vanleer<C>(vlo, v0, vhi);
 }
 
 // value and physical gradient of one component at cell c (codes nbc)
@@ -800,23 +807,27 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
     const C lo_b = (w == 0) ? oc_b : pub[pp][(w == 0) ? 0 : w - 1][1][lane];
     const C hi_h = (w == RG + 1) ? oc_h : pub[pp][(w == RG + 1) ? RG + 1 : w + 1][0][lane];
     const C hi_b = (w == RG + 1) ? oc_b : pub[pp][(w == RG + 1) ? RG + 1 : w + 1][1][lane];
+    C sih, sjh, sib, sjb;
+    if ((nbc[0] | nbc[1] | nbc[2] | nbc[3]) >= 0) {
+      // four neighbouring cells (most of the field): van Leer in both
+      // directions, no boundary codes to test
+      sih = vanleer<C>(a0h, a1h, a2h);
+      sjh = vanleer<C>(lo_h, a1h, hi_h);
+      sib = vanleer<C>(a0b, a1b, a2b);
+      sjb = vanleer<C>(lo_b, a1b, hi_b);
+    } else {
+      sih = climit<C>(nbc[0], nbc[1], nbv(nbc[0], a0h, finh, a1h), a1h, nbv(nbc[1], a2h, finh, a1h));
+      sjh = climit<C>(nbc[2], nbc[3], nbv(nbc[2], lo_h, finh, a1h), a1h, nbv(nbc[3], hi_h, finh, a1h));
+      sib = climit<C>(nbc[0], nbc[1], nbv(nbc[0], a0b, finb, a1b), a1b, nbv(nbc[1], a2b, finb, a1b));
+      sjb = climit<C>(nbc[2], nbc[3], nbv(nbc[2], lo_b, finb, a1b), a1b, nbv(nbc[3], hi_b, finb, a1b));
+    }
     LD6<C> L;
-    {
-      const C v = a1h;
-      const C si = climit<C>(nbc[0], nbc[1], nbv(nbc[0], a0h, finh, v), v, nbv(nbc[1], a2h, finh, v));
-      const C sj = climit<C>(nbc[2], nbc[3], nbv(nbc[2], lo_h, finh, v), v, nbv(nbc[3], hi_h, finh, v));
-      L.hv = v;
-      L.hx = (C)G[0] * si + (C)G[1] * sj;
-      L.hy = (C)G[2] * si + (C)G[3] * sj;
-    }
-    {
-      const C v = a1b;
-      const C si = climit<C>(nbc[0], nbc[1], nbv(nbc[0], a0b, finb, v), v, nbv(nbc[1], a2b, finb, v));
-      const C sj = climit<C>(nbc[2], nbc[3], nbv(nbc[2], lo_b, finb, v), v, nbv(nbc[3], hi_b, finb, v));
-      L.bv = v;
-      L.bx = (C)G[0] * si + (C)G[1] * sj;
-      L.by = (C)G[2] * si + (C)G[3] * sj;
-    }
+    L.hv = a1h;
+    L.hx = (C)G[0] * sih + (C)G[1] * sjh;
+    L.hy = (C)G[2] * sih + (C)G[3] * sjh;
+    L.bv = a1b;
+    L.bx = (C)G[0] * sib + (C)G[1] * sjb;
+    L.by = (C)G[2] * sib + (C)G[3] * sjb;
     lds[slot(x1)][w][lane] = L;
   };
   auto ghost = [&](const LD6<C>& L, int code) -> Side<C> {
@@ -1023,8 +1034,15 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
           wall_eval(r, fp, L != kNbWall, (L == kNbWall) ? hi : lo, fc, mom);
         } else {
           // the low side of the seam face (x = -1) is cell ni-1, staged as column -1
-          const Side<C> sl = (L >= 0) ? side_at(lo, fp[kFpDL], fp[kFpDL + 1]) : ghost(hi, L);
-          const Side<C> sh = (R >= 0) ? side_at(hi, fp[kFpDR], fp[kFpDR + 1]) : ghost(lo, R);
+          Side<C> sl, sh;
+          if ((L | R) >= 0) {
+            // interior face (most faces): both sides reconstructed
+            sl = side_at(lo, fp[kFpDL], fp[kFpDL + 1]);
+            sh = side_at(hi, fp[kFpDR], fp[kFpDR + 1]);
+          } else {
+            sl = (L >= 0) ? side_at(lo, fp[kFpDL], fp[kFpDL + 1]) : ghost(hi, L);
+            sh = (R >= 0) ? side_at(hi, fp[kFpDR], fp[kFpDR + 1]) : ghost(lo, R);
+          }
           face_eval(r, fp, sl, sh, fc, mom);
         }
         if (MODE == 1) write_flux(owner ? f : -1, mom);
