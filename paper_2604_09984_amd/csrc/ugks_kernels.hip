@@ -973,7 +973,11 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
     Dh[(size_t)c * g.nv + k] = (T)dh;
     Db[(size_t)c * g.nv + k] = (T)db;
   };
-  for (int x = -2; x < ni; ++x) {
+  // one column step; for a column of known parity P (0 or 1) the LDS slot,
+  // hand-over and publication indices become constants
+  auto column = [&](int xin, auto par) __attribute__((always_inline)) {
+    constexpr int P = decltype(par)::value;
+    const int x = (P < 0) ? xin : ((xin & ~1) | P);
     // registers: cell records cp0c .. cp3 of columns x .. x+3 (cp3 in flight)
     recon(x + 1, c1, cp1);
     // publish column x + 2 of this row, advance the windows
@@ -1074,6 +1078,18 @@ __device__ __forceinline__ void march_body(int BX, int BY, int BZ, const Dev& g,
       fj_m1[0] = fj_cur[0]; fj_m1[1] = fj_cur[1];
       face_touch(rec, fpl, iface_id(x + 1, cp0c, cpz), jface_id(x + 2, cp1), touched);  // cp1: column x + 2
     }
+  };
+  if constexpr (sizeof(C) == 8) {
+    // two columns per iteration: the loop-carried windows rotate by two
+    // and the parities are constants (2-3 % on the FP64 passes)
+    for (int x = -2; x < ni; x += 2) {
+      column(x, std::integral_constant<int, 0>{});
+      if (x + 1 < ni) column(x + 1, std::integral_constant<int, 1>{});
+    }
+  } else {
+    // one column per iteration: the FP32 passes stay within 128 VGPRs, so
+    // that two 6-row workgroups share a CU
+    for (int x = -2; x < ni; ++x) column(x, std::integral_constant<int, -1>{});
   }
 }
 template <int RG, class T, class C, int MODE>
