@@ -285,13 +285,9 @@ __device__ __forceinline__ void iint_rev(const Dev& g, const Rec& e, double vx, 
 // direction) and its reverse
 // ------------------------------------------------------------------------
 // limited index slope and its partials with respect to (low, centre, high)
-__device__ inline double lim_d(int lo, int hi, double vlo, double v0, double vhi, double& dlo, double& d0,
-                               double& dhi) {
+// van Leer slope between two neighbouring cells and its partials
+__device__ __forceinline__ double lim_vl(double vlo, double v0, double vhi, double& dlo, double& d0, double& dhi) {
   dlo = d0 = dhi = 0.0;
-  if (lo == kNbMiss || hi == kNbMiss) return 0.0;
-  if (lo == kNbWall && hi == kNbWall) return 0.0;
-  if (lo == kNbWall) { dhi = 1.0; d0 = -1.0; return vhi - v0; }
-  if (hi == kNbWall) { d0 = 1.0; dlo = -1.0; return v0 - vlo; }
   const double s1 = v0 - vlo, s2 = vhi - v0;
   const double sm = s1 + s2;
   // one-sided slopes of one sign: the van Leer slope is 2 s1 s2 / (s1 + s2)
@@ -304,6 +300,15 @@ __device__ inline double lim_d(int lo, int hi, double vlo, double v0, double vhi
   const double p1 = 2.0 * t2 * t2, p2 = 2.0 * t1 * t1;
   d0 = p1 - p2; dlo = -p1; dhi = p2;
   return 2.0 * s1 * t2;
+}
+__device__ inline double lim_d(int lo, int hi, double vlo, double v0, double vhi, double& dlo, double& d0,
+                               double& dhi) {
+  dlo = d0 = dhi = 0.0;
+  if (lo == kNbMiss || hi == kNbMiss) return 0.0;
+  if (lo == kNbWall && hi == kNbWall) return 0.0;
+  if (lo == kNbWall) { dhi = 1.0; d0 = -1.0; return vhi - v0; }
+  if (hi == kNbWall) { d0 = 1.0; dlo = -1.0; return v0 - vlo; }
+  return lim_vl(vlo, v0, vhi, dlo, d0, dhi);
 }
 
 __device__ __forceinline__ double nbval(const double* f, const double* finf, int code, double self, int nv, int k) {
@@ -410,11 +415,20 @@ __device__ __forceinline__ SideD side_val_d(const Dev& g, const double* f, const
     return s;
   }
   const int* nb = g.nb + 4 * code;
+  const int n0 = nb[0], n1 = nb[1], n2 = nb[2], n3 = nb[3];
   const double v0 = f[(size_t)code * g.nv + k];
-  const double si = lim_d(nb[0], nb[1], nbval(f, finf, nb[0], v0, g.nv, k), v0, nbval(f, finf, nb[1], v0, g.nv, k),
-                          s.p[0][0], s.p[0][1], s.p[0][2]);
-  const double sj = lim_d(nb[2], nb[3], nbval(f, finf, nb[2], v0, g.nv, k), v0, nbval(f, finf, nb[3], v0, g.nv, k),
-                          s.p[1][0], s.p[1][1], s.p[1][2]);
+  double si, sj;
+  if ((n0 | n1 | n2 | n3) >= 0) {
+    // four neighbouring cells (most of the field): no boundary codes to test
+    const size_t nv = (size_t)g.nv;
+    si = lim_vl(f[n0 * nv + k], v0, f[n1 * nv + k], s.p[0][0], s.p[0][1], s.p[0][2]);
+    sj = lim_vl(f[n2 * nv + k], v0, f[n3 * nv + k], s.p[1][0], s.p[1][1], s.p[1][2]);
+  } else {
+    si = lim_d(n0, n1, nbval(f, finf, n0, v0, g.nv, k), v0, nbval(f, finf, n1, v0, g.nv, k), s.p[0][0], s.p[0][1],
+               s.p[0][2]);
+    sj = lim_d(n2, n3, nbval(f, finf, n2, v0, g.nv, k), v0, nbval(f, finf, n3, v0, g.nv, k), s.p[1][0], s.p[1][1],
+               s.p[1][2]);
+  }
   const double* G = g.G + 4 * code;
   s.gx = G[0] * si + G[1] * sj;
   s.gy = G[2] * si + G[3] * sj;
